@@ -1,0 +1,294 @@
+/*
+ * maskgs.h -- C ABI of the MI355X (gfx950) masked Gaussian rasterizer.
+ *
+ * Masked rasterization of 3D Gaussians, forward and backward, after
+ * MaskGaussian (Liu et al., arXiv 2412.20522):
+ *   - every Gaussian is splatted to a 2D Gaussian with a colour from
+ *     view-dependent spherical harmonics and alpha_i = o_i * G2D_i(x)
+ *     (Sec. 3.1), unaffected by its mask (Sec. 3.2-3.3);
+ *   - per pixel, the Gaussians that intersect the pixel's tile and pass the
+ *     alpha filter are composited front to back in depth order with the mask
+ *     gating both colour accumulation and transmittance attenuation,
+ *     Eq. (3)-(4), plus the final transmittance times the background colour
+ *     (supplementary derivation of the mask gradient);
+ *   - the backward pass returns dL/dM_i for every Gaussian that passed the
+ *     alpha filter, whether its mask is 0 or 1, Eq. (6) with the colour
+ *     behind read relative to T_{i+1} and the background term of the
+ *     supplementary material, and the usual gradients of centres, conics,
+ *     opacities and colours, which are zero for masked entries (Fig. 1).
+ *   - masks come from two scores per Gaussian through a straight-through
+ *     Gumbel-Softmax (Sec. 3.3); the mask-count loss is Eq. (7)-(8).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller unless the
+ *     parameter says "host".  The library never frees caller memory.
+ *   - Every call is asynchronous on the caller's stream unless its comment
+ *     says it synchronises.  A NULL stream is the null stream.
+ *   - Arrays are dense, row-major, float32 unless stated; N = number of
+ *     Gaussians, V = number of views, R = V * N projected records
+ *     (record r = view * N + gaussian), K = number of (tile, Gaussian)
+ *     instances, P = total pixels over all views.
+ *   - Images are packed view after view, each view as [3, H_v, W_v];
+ *     per-pixel arrays are packed view after view as [H_v, W_v].
+ *   - Arguments are validated on the host.  A failing call returns a status
+ *     other than MGS_OK, launches nothing, and sets the message returned by
+ *     mgs_last_error.  No C++ exception crosses this boundary.
+ *   - Conditions found on the device (capacity overflow, non-finite values)
+ *     set device flags reported as MGS_ERR_CAPACITY / MGS_ERR_NONFINITE by the
+ *     next call that synchronises (mgs_forward reads them when it reads K).
+ */
+#ifndef MASKGS_H
+#define MASKGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGS_API __attribute__((visibility("default")))
+#define MGS_MAX_VIEWS 16
+
+typedef struct ihipStream_t* mgs_stream; /* hipStream_t */
+
+typedef enum {
+    MGS_OK = 0,
+    MGS_ERR_INVALID_ARG = 1,
+    MGS_ERR_OOM = 2,
+    MGS_ERR_CAPACITY = 3,
+    MGS_ERR_NONFINITE = 4,
+    MGS_ERR_HIP = 5,
+    MGS_ERR_UNSUPPORTED = 6,
+    MGS_ERR_STATE = 7
+} mgs_status;
+
+/* Pinhole camera.  viewmat maps world to camera, row-major 4x4, camera +z
+ * forward, +y down, +x right; fx, fy, cx, cy in pixels; pixel (x, y) has its
+ * centre at (x + 0.5, y + 0.5). */
+typedef struct {
+    float viewmat[16];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} mgs_camera;
+
+/* Rasterization constants (defaults from mgs_default_settings). */
+typedef struct {
+    int32_t tile_w, tile_h;  /* 8x8, 16x8, 16x16 or 32x8 pixels (16x16, Sec. 3.1) */
+    int32_t batch_depth;     /* entries staged in LDS per batch: 32, 64, 128 or 256,
+                                at most tile_w * tile_h */
+    int32_t sh_degree;       /* 0..3 */
+    float alpha_min;         /* alpha filter, 1/255 ("alpha > 0", Sec. 3.1) */
+    float alpha_max;         /* alpha clamp, 0.99 */
+    float t_min;             /* early termination: stop before T drops below 1e-4 */
+    float q_max;             /* per-pixel cut on the Mahalanobis form, 9 (3 sigma) */
+    float near_plane;        /* cull depth <= 0.2 */
+    float dilation;          /* added to the 2D covariance diagonal, 0.3 */
+    float jac_clamp;         /* lateral clamp of the EWA Jacobian, 1.3 * tan(fov/2) */
+    float lambda_floor;      /* floor of the eigenvalue discriminant, 0.1 */
+    float bg[3];             /* background colour */
+    int32_t exact_mode;      /* 1: alpha_min = 0, t_min = 0, no Q cut, every valid
+                                Gaussian in every tile (for calculus tests) */
+    int32_t persistent;      /* 1: compositing pops tiles from a device queue */
+    int32_t fwd_ppt;         /* pixels per thread in forward compositing: 1, 2 or 4
+                                (tile_w * tile_h / ppt threads per workgroup, a
+                                multiple of 64) */
+    int32_t bwd_ppt;         /* pixels per thread in backward compositing */
+} mgs_settings;
+
+/* Gaussian parameters (device pointers, float32). */
+typedef struct {
+    const float* means;          /* [N, 3] */
+    const float* log_scales;     /* [N, 3] */
+    const float* quats;          /* [N, 4] (w, x, y, z), need not be unit */
+    const float* opacity_logits; /* [N], opacity = sigmoid(logit) */
+    const float* sh;             /* [N, (d+1)^2, 3], index l*l + l + m */
+    const float* masks;          /* [N], sampled mask M_i, normally 0 or 1;
+                                    any value in [0, 1] is well defined */
+    int64_t n;
+} mgs_gaussians;
+
+/* Gradient outputs (device pointers, float32, overwritten, not accumulated).
+ * Any pointer may be NULL to skip that output. */
+typedef struct {
+    float* d_means;          /* [N, 3] */
+    float* d_log_scales;     /* [N, 3] */
+    float* d_quats;          /* [N, 4] */
+    float* d_opacity_logits; /* [N] */
+    float* d_sh;             /* [N, (d+1)^2, 3] */
+    float* d_masks;          /* [N], dL/dM_i, Eq. (6) plus background term */
+} mgs_gradients;
+
+typedef struct {
+    int64_t n_gaussians, n_views, n_records, n_pixels;
+    int64_t n_instances;     /* K of the last forward */
+    int64_t total_tiles;
+    int64_t instance_capacity;
+    int32_t sort_passes;
+    int32_t tile_bits;
+} mgs_frame_stats;
+
+typedef struct mgs_ctx mgs_ctx;
+typedef struct mgs_frame mgs_frame;
+typedef struct mgs_graph mgs_graph;
+
+/* ---------------------------------------------------------------------- */
+/* lifecycle                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+MGS_API int mgs_version(void);
+
+/* Fills *out with the defaults listed on mgs_settings. */
+MGS_API mgs_status mgs_default_settings(mgs_settings* out);
+
+/* Creates a context on HIP device `device` (checks it is a gfx950).  *out
+ * (host) receives the handle; free it with mgs_destroy. */
+MGS_API mgs_status mgs_create(int device, mgs_ctx** out);
+MGS_API mgs_status mgs_destroy(mgs_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of the last failed mgs_create
+ * when ctx is NULL).  The string belongs to the library and stays valid
+ * until the next call on the same context. */
+MGS_API const char* mgs_last_error(const mgs_ctx* ctx);
+
+/* A frame holds what one forward saves for its backward (projected records,
+ * sorted instance lists, tile ranges, per-pixel final transmittance and last
+ * blended entry).  Its device buffers grow on demand and are reused by later
+ * forwards.  One forward, then at most one backward, per frame at a time. */
+MGS_API mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out);
+MGS_API mgs_status mgs_frame_destroy(mgs_frame* frame);
+MGS_API mgs_status mgs_frame_get_stats(const mgs_frame* frame, mgs_frame_stats* out);
+
+/* ---------------------------------------------------------------------- */
+/* whole path                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Masked forward rendering of n_views cameras (host array cams[n_views],
+ * 1 <= n_views <= MGS_MAX_VIEWS): projection, tile counts, scan, key
+ * duplication, radix sort, tile ranges, masked compositing (Eq. 3-4 with the
+ * background term).  images [3 * P] receives the rendering; t_final [P]
+ * (optional, may be NULL) the final transmittance.  Synchronises the stream
+ * once, to read K and size the sort. */
+MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
+                               int n_views, const mgs_settings* st, float* images, float* t_final);
+
+/* Backward of the last mgs_forward on this frame.  dl_dimages [3 * P] is the
+ * gradient of the loss w.r.t. the rendered images.  Writes every non-NULL
+ * field of *grads (host struct of device pointers).  The Gaussian
+ * parameters passed to the forward must be unchanged.  Asynchronous. */
+MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float* dl_dimages,
+                                const mgs_gradients* grads);
+
+/* Number of list entries examined per pixel in the last forward, up to and
+ * including each pixel's stop entry (the Gaussian-pixel evaluations of the
+ * forward pass).  Writes the sum to *total (host).  Synchronises. */
+MGS_API mgs_status mgs_frame_count_evals(mgs_frame* frame, mgs_stream stream, int64_t* total);
+
+/* ---------------------------------------------------------------------- */
+/* stages, for stage-wise checking; all buffers caller-owned               */
+/* ---------------------------------------------------------------------- */
+
+/* EWA projection and SH colour (Sec. 3.1) of every Gaussian for every view.
+ * rec [R, 12]: u, v, conic a, conic b, conic c, opacity, mask, 0, r, g, b, 0
+ *   (conic (a, b, c) is the inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2);
+ * depth [R]: view-space z rounded to float32 from a double-precision
+ *   transform (the sort key); radius [R]: ceil(3 sqrt(lambda_max));
+ * tiles [R] (u32): number of tiles of the record's square footprint.
+ * Culled records (depth <= near, singular covariance) have tiles = 0. */
+MGS_API mgs_status mgs_project(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
+                               int n_views, const mgs_settings* st, float* rec, float* depth, float* radius,
+                               uint32_t* tiles);
+
+/* Exclusive prefix sum of n u32 values; total_dev (device, one u64) gets
+ * the sum.  scratch must hold mgs_scan_scratch_bytes(n) bytes. */
+MGS_API size_t mgs_scan_scratch_bytes(int64_t n);
+MGS_API mgs_status mgs_scan(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
+                            uint64_t* total_dev, void* scratch);
+
+/* Writes, for every record r with tiles > 0 and every tile t of its
+ * footprint, key = (global tile id << 32) | float bits of depth and
+ * value = r, starting at offsets[r].  Global tile ids number the tiles of
+ * view 0 first, row-major.  Entries at or beyond capacity are not written
+ * and raise the capacity flag. */
+MGS_API mgs_status mgs_duplicate(mgs_ctx* ctx, mgs_stream stream, const float* rec, const float* depth,
+                                 const float* radius, const uint32_t* tiles, const uint32_t* offsets, int64_t n,
+                                 const mgs_camera* cams, int n_views, const mgs_settings* st, uint64_t* keys,
+                                 uint32_t* vals, int64_t capacity);
+
+/* Stable LSD radix sort of K (key, value) pairs on the low key_bits bits of
+ * the key (8 bits per pass).  Sorted pairs end in keys/vals; keys_alt and
+ * vals_alt (K entries each) are scratch; scratch holds
+ * mgs_sort_scratch_bytes(K) bytes. */
+MGS_API size_t mgs_sort_scratch_bytes(int64_t K);
+MGS_API mgs_status mgs_sort(mgs_ctx* ctx, mgs_stream stream, uint64_t* keys, uint32_t* vals, int64_t K,
+                            int key_bits, uint64_t* keys_alt, uint32_t* vals_alt, void* scratch);
+
+/* [start, end) of every global tile in the sorted keys; tiles without
+ * entries get [0, 0).  ranges [total_tiles, 2] (u32). */
+MGS_API mgs_status mgs_tile_ranges(mgs_ctx* ctx, mgs_stream stream, const uint64_t* keys, int64_t K,
+                                   int64_t total_tiles, uint32_t* ranges);
+
+/* Masked forward compositing, Eq. (3)-(4) plus background, per pixel over
+ * its tile's sorted entries.  last [P] (i32): list position of the last
+ * blended entry (-1 if none); examined [P] (i32, optional): entries
+ * examined up to and including the stop entry. */
+MGS_API mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
+                                         const uint32_t* ranges, const mgs_camera* cams, int n_views,
+                                         const mgs_settings* st, float* images, float* t_final, int32_t* last,
+                                         int32_t* examined);
+
+/* Masked backward compositing in reverse order, recovering transmittance
+ * by division.  d_rec [R, 9] (zeroed here, then accumulated): dL/du, dL/dv,
+ * dL/d(conic a, b, c), dL/dopacity, dL/d(r, g, b); d_masks [n] (zeroed
+ * here): dL/dM_i summed over views. */
+MGS_API mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
+                                          const uint32_t* ranges, const mgs_camera* cams, int n_views,
+                                          const mgs_settings* st, const float* t_final, const int32_t* last,
+                                          const float* dl_dimages, int64_t n, float* d_rec, float* d_masks);
+
+/* Chain rule from d_rec [R, 9] to the Gaussian parameters, summed over
+ * views (no atomics: one thread per Gaussian).  grads->d_masks is ignored. */
+MGS_API mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g,
+                                        const mgs_camera* cams, int n_views, const mgs_settings* st,
+                                        const float* d_rec, const mgs_gradients* grads);
+
+/* ---------------------------------------------------------------------- */
+/* masks, loss, optimiser                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Straight-through Gumbel-Softmax over two scores per Gaussian (Sec. 3.3).
+ * scores [n, 2] (column 0 = exists).  Philox4x32-10 with counter
+ * (i lo, i hi, step lo, step hi) and key (seed lo, seed hi) gives uniforms
+ * u = (bits >> 8 + 0.5) 2^-24 for the two scores, g = -log(-log u), computed
+ * in double.  m_hard [n] = [s0 + g0 > s1 + g1]; y_soft [n] =
+ * sigmoid((s0 + g0 - s1 - g1) / tau). */
+MGS_API mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float tau,
+                                    uint64_t seed, uint64_t step, float* m_hard, float* y_soft);
+
+/* Gradient to the scores through the straight-through mask, adding the
+ * mask-count loss L_m = (mean M)^2 weighted by lambda_m (Eq. 7-8):
+ * d_scores[i, 0] = (d_masks[i] + lambda_m 2 sum(M) / n^2) y (1 - y) / tau,
+ * d_scores[i, 1] = -d_scores[i, 0].  loss_m (device, one float, optional)
+ * receives L_m.  scratch holds mgs_reduce_scratch_bytes(n) bytes. */
+MGS_API size_t mgs_reduce_scratch_bytes(int64_t n);
+MGS_API mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
+                                 const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores,
+                                 float* loss_m, void* scratch);
+
+/* L1 rendering loss over m elements (mean |image - target|, sign(0) = 0):
+ * d_images [m] = sign(image - target) / m; loss (device, one float,
+ * optional).  scratch holds mgs_reduce_scratch_bytes(m) bytes. */
+MGS_API mgs_status mgs_l1_loss_grad(mgs_ctx* ctx, mgs_stream stream, const float* images, const float* targets,
+                                    int64_t m, float* d_images, float* loss, void* scratch);
+
+/* One Adam step (Kingma and Ba) over n float32 parameters, in place on
+ * params, m and v; step >= 1 is the bias-correction step count. */
+MGS_API mgs_status mgs_adam_step(mgs_ctx* ctx, mgs_stream stream, float* params, const float* grads, float* m,
+                                 float* v, int64_t n, float lr, float beta1, float beta2, float eps, int64_t step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MASKGS_H */

@@ -41,7 +41,7 @@ class Settings(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("sh_degree", C.c_int32), ("exact_mode", C.c_int32),
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float), ("q_max", C.c_float),
                 ("near_plane", C.c_float), ("dilation", C.c_float), ("jac_clamp", C.c_float),
-                ("lambda_floor", C.c_float), ("bg", C.c_float * 3), ("margin", C.c_float)]
+                ("lambda_floor", C.c_float), ("bg", C.c_float * 3), ("margin", C.c_float), ("margin_t", C.c_float)]
 
 
 @dataclass
@@ -64,6 +64,7 @@ class RasterSettings:
     lambda_floor: float = 0.1
     bg: tuple = (0.0, 0.0, 0.0)
     margin: float = 1e-5
+    margin_t: float = 2e-4
 
     def c(self) -> Settings:
         s = Settings()
@@ -74,6 +75,7 @@ class RasterSettings:
         for i in range(3):
             s.bg[i] = self.bg[i]
         s.margin = self.margin
+        s.margin_t = self.margin_t
         return s
 
 

@@ -76,7 +76,10 @@ typedef struct {
     float jac_clamp;     /* 1.3   */
     float lambda_floor;  /* 0.1   */
     float bg[3];
-    float margin;        /* relative margin for decision flags, 1e-5 */
+    float margin;        /* relative margin for the Q / alpha decision flags, 1e-5 */
+    float margin_t;      /* relative margin for the transmittance stop flag, 2e-4
+                            (an FP32 transmittance carries a relative rounding
+                            error that grows with the number of blended entries) */
 } orc_settings;
 
 /* flag bits per pixel */
@@ -547,7 +550,7 @@ static void composite_pixel(const orc_splats* sp, const uint32_t* vals, int64_t 
         if (alpha < amin) continue;
         const double M = sp->mask[g];
         const double test = T * (1.0 - M * alpha);
-        if (tmin > 0.0 && fabs(test - tmin) <= mg * tmin) px->flags |= ORC_FLAG_TMIN;
+        if (tmin > 0.0 && fabs(test - tmin) <= (double)st->margin_t * tmin) px->flags |= ORC_FLAG_TMIN;
         if (test < tmin) {
             px->stopped = 1;
             px->stop_pos = k;

@@ -1,0 +1,646 @@
+// Host side of the C ABI declared in include/maskgs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "maskgs.h"
+
+using namespace mgs;
+
+struct mgs_ctx {
+    int device = 0;
+    int num_cus = 256;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+mgs_status fail(mgs_ctx* ctx, mgs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_error = buf;
+    return s;
+}
+
+#define MGS_HIP(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail((ctx), MGS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define MGS_CHECK_LAUNCH(ctx)                                                                          \
+    do {                                                                                              \
+        hipError_t e_ = hipGetLastError();                                                            \
+        if (e_ != hipSuccess) return fail((ctx), MGS_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// Grows a device buffer (contents are not preserved).
+mgs_status grow(mgs_ctx* ctx, DevBuf& b, size_t need) {
+    if (need <= b.bytes && b.p) return MGS_OK;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = need + need / 4 + 256;
+    want = (want + 255) & ~(size_t)255;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, MGS_ERR_OOM, "hipMalloc of %zu bytes failed", want);
+    }
+    b.bytes = want;
+    return MGS_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+bool valid_tile(int w, int h) {
+    return (w == 8 && h == 8) || (w == 16 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8);
+}
+
+mgs_status check_settings(mgs_ctx* ctx, const mgs_settings* st) {
+    if (!st) return fail(ctx, MGS_ERR_INVALID_ARG, "settings is NULL");
+    if (!valid_tile(st->tile_w, st->tile_h))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "tile %dx%d not one of 8x8, 16x8, 16x16, 32x8", st->tile_w, st->tile_h);
+    const int bd = st->batch_depth;
+    if (!(bd == 32 || bd == 64 || bd == 128 || bd == 256) || bd > st->tile_w * st->tile_h * 4)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "batch_depth %d not one of 32, 64, 128, 256", bd);
+    if (st->sh_degree < 0 || st->sh_degree > 3) return fail(ctx, MGS_ERR_INVALID_ARG, "sh_degree %d", st->sh_degree);
+    const CompositeConfig cf{st->tile_w, st->tile_h, st->fwd_ppt}, cb{st->tile_w, st->tile_h, st->bwd_ppt};
+    if (!composite_config_supported(cf) || !composite_config_supported(cb))
+        return fail(ctx, MGS_ERR_UNSUPPORTED, "pixels per thread %d/%d unsupported for tile %dx%d", st->fwd_ppt,
+                    st->bwd_ppt, st->tile_w, st->tile_h);
+    if (!(st->alpha_max > 0.f && st->alpha_max < 1.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "alpha_max in (0, 1)");
+    if (!(st->near_plane > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "near_plane must be > 0");
+    return MGS_OK;
+}
+
+mgs_status check_cameras(mgs_ctx* ctx, const mgs_camera* cams, int n_views) {
+    if (n_views < 1 || n_views > MGS_MAX_VIEWS)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "n_views %d not in [1, %d]", n_views, MGS_MAX_VIEWS);
+    if (!cams) return fail(ctx, MGS_ERR_INVALID_ARG, "cams is NULL");
+    for (int v = 0; v < n_views; ++v) {
+        const mgs_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
+            return fail(ctx, MGS_ERR_INVALID_ARG, "view %d: size %dx%d", v, c.width, c.height);
+        if (!(c.fx > 0.f && c.fy > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "view %d: focal lengths", v);
+    }
+    return MGS_OK;
+}
+
+mgs_status check_gaussians(mgs_ctx* ctx, const mgs_gaussians* g, bool need_masks) {
+    if (!g) return fail(ctx, MGS_ERR_INVALID_ARG, "gaussians is NULL");
+    if (g->n < 0 || g->n > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_INVALID_ARG, "n = %lld", (long long)g->n);
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh ||
+                     (need_masks && !g->masks)))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "a Gaussian parameter pointer is NULL");
+    if (g->n > 0 && (((uintptr_t)g->quats & 15) != 0))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "quats must be 16-byte aligned");
+    return MGS_OK;
+}
+
+// Host-side construction of the per-view device constants.
+ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t* total_px) {
+    ViewSet vs;
+    memset(&vs, 0, sizeof vs);
+    vs.n_views = n_views;
+    uint32_t toff = 0, poff = 0;
+    for (int i = 0; i < n_views; ++i) {
+        const mgs_camera& c = cams[i];
+        DevView& d = vs.v[i];
+        for (int r = 0; r < 3; ++r) {
+            for (int k = 0; k < 3; ++k) d.W[3 * r + k] = c.viewmat[4 * r + k];
+            d.t[r] = c.viewmat[4 * r + 3];
+        }
+        d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int r = 0; r < 3; ++r) s += (double)c.viewmat[4 * r + k] * (double)c.viewmat[4 * r + 3];
+            d.campos[k] = (float)(-s);
+        }
+        d.width = c.width;
+        d.height = c.height;
+        d.grid_w = (c.width + tw - 1) / tw;
+        d.grid_h = (c.height + th - 1) / th;
+        d.tile_off = toff;
+        d.px_off = poff;
+        toff += (uint32_t)(d.grid_w * d.grid_h);
+        poff += (uint32_t)(c.width * c.height);
+    }
+    vs.total_tiles = toff;
+    if (total_px) *total_px = poff;
+    return vs;
+}
+
+void set_limits(ViewSet& vs, const mgs_camera* cams, float jac_clamp) {
+    for (int i = 0; i < vs.n_views; ++i) {
+        vs.v[i].limx = (float)((double)jac_clamp * 0.5 * cams[i].width / cams[i].fx);
+        vs.v[i].limy = (float)((double)jac_clamp * 0.5 * cams[i].height / cams[i].fy);
+    }
+}
+
+DevSettings make_settings(const mgs_settings* s) {
+    DevSettings d;
+    d.tile_w = s->tile_w;
+    d.tile_h = s->tile_h;
+    d.batch = s->batch_depth;
+    d.sh_degree = s->sh_degree;
+    d.alpha_max = s->alpha_max;
+    d.near_plane = s->near_plane;
+    d.dilation = s->dilation;
+    d.lambda_floor = s->lambda_floor;
+    d.bg[0] = s->bg[0]; d.bg[1] = s->bg[1]; d.bg[2] = s->bg[2];
+    if (s->exact_mode) {
+        d.alpha_min = 0.f;
+        d.t_min = 0.f;
+        d.q_max = INFINITY;
+        d.full_rect = 1;
+    } else {
+        d.alpha_min = s->alpha_min;
+        d.t_min = s->t_min;
+        d.q_max = s->q_max;
+        d.full_rect = 0;
+    }
+    return d;
+}
+
+int bits_for(uint64_t v) {  // bits needed to hold values < v
+    int b = 0;
+    while (b < 64 && (1ull << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+struct mgs_frame {
+    mgs_ctx* ctx = nullptr;
+    // state of the last forward
+    bool have_forward = false;
+    mgs_gaussians g{};
+    ViewSet views{};
+    DevSettings st{};
+    CompositeConfig cfg_fwd{}, cfg_bwd{};
+    int persistent = 0;
+    int n_views = 0;
+    int64_t n = 0, R = 0, P = 0, K = 0, total_tiles = 0, capacity = 0;
+    int sort_passes = 0, tile_bits = 0;
+    bool sorted_in_alt = false;
+    // device buffers
+    DevBuf rec, depth, radius, tiles, offsets, keys, vals, keys_alt, vals_alt, ranges, t_final, last, examined;
+    DevBuf d_rec, d_masks_tmp, scan_tmp, sort_tmp, misc, queue, sum_tmp;
+    uint64_t* h_pinned = nullptr;  // K, flags read-back
+    uint64_t* keys_sorted() { return (uint64_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
+    uint32_t* vals_sorted() { return (uint32_t*)(sorted_in_alt ? vals_alt.p : vals.p); }
+    uint32_t* flags() { return (uint32_t*)misc.p; }
+    uint64_t* total() { return (uint64_t*)((char*)misc.p + 8); }
+};
+
+extern "C" {
+
+int mgs_version(void) { return 100; }
+
+mgs_status mgs_default_settings(mgs_settings* out) {
+    if (!out) return MGS_ERR_INVALID_ARG;
+    memset(out, 0, sizeof *out);
+    out->tile_w = 16;
+    out->tile_h = 16;
+    out->batch_depth = 256;
+    out->sh_degree = 3;
+    out->alpha_min = 1.f / 255.f;
+    out->alpha_max = 0.99f;
+    out->t_min = 1e-4f;
+    out->q_max = 9.f;
+    out->near_plane = 0.2f;
+    out->dilation = 0.3f;
+    out->jac_clamp = 1.3f;
+    out->lambda_floor = 0.1f;
+    out->exact_mode = 0;
+    out->persistent = 0;
+    out->fwd_ppt = 1;
+    out->bwd_ppt = 4;
+    return MGS_OK;
+}
+
+mgs_status mgs_create(int device, mgs_ctx** out) {
+    if (!out) return fail(nullptr, MGS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(nullptr, MGS_ERR_HIP, "no HIP device available");
+    if (device < 0 || device >= count) return fail(nullptr, MGS_ERR_INVALID_ARG, "device %d of %d", device, count);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(nullptr, MGS_ERR_HIP, "device properties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, MGS_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
+                    prop.gcnArchName);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, MGS_ERR_HIP, "hipSetDevice(%d)", device);
+    mgs_ctx* c = new (std::nothrow) mgs_ctx();
+    if (!c) return fail(nullptr, MGS_ERR_OOM, "context allocation");
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    *out = c;
+    return MGS_OK;
+}
+
+mgs_status mgs_destroy(mgs_ctx* ctx) {
+    delete ctx;
+    return MGS_OK;
+}
+
+const char* mgs_last_error(const mgs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
+    if (!ctx || !out) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    mgs_frame* f = new (std::nothrow) mgs_frame();
+    if (!f) return fail(ctx, MGS_ERR_OOM, "frame allocation");
+    f->ctx = ctx;
+    if (hipHostMalloc((void**)&f->h_pinned, 64, hipHostMallocDefault) != hipSuccess) {
+        delete f;
+        return fail(ctx, MGS_ERR_OOM, "pinned host allocation");
+    }
+    if (grow(ctx, f->misc, 256) != MGS_OK) {
+        (void)hipHostFree(f->h_pinned);
+        delete f;
+        return MGS_ERR_OOM;
+    }
+    *out = f;
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_destroy(mgs_frame* f) {
+    if (!f) return MGS_OK;
+    (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&f->rec, &f->depth, &f->radius, &f->tiles, &f->offsets, &f->keys, &f->vals, &f->keys_alt,
+                      &f->vals_alt, &f->ranges, &f->t_final, &f->last, &f->examined, &f->d_rec, &f->d_masks_tmp,
+                      &f->scan_tmp, &f->sort_tmp, &f->misc, &f->queue, &f->sum_tmp};
+    for (DevBuf* b : bufs) release(*b);
+    if (f->h_pinned) (void)hipHostFree(f->h_pinned);
+    delete f;
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_get_stats(const mgs_frame* f, mgs_frame_stats* out) {
+    if (!f || !out) return MGS_ERR_INVALID_ARG;
+    out->n_gaussians = f->n;
+    out->n_views = f->n_views;
+    out->n_records = f->R;
+    out->n_pixels = f->P;
+    out->n_instances = f->K;
+    out->total_tiles = f->total_tiles;
+    out->instance_capacity = f->capacity;
+    out->sort_passes = f->sort_passes;
+    out->tile_bits = f->tile_bits;
+    return MGS_OK;
+}
+
+mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g, const mgs_camera* cams, int n_views,
+                       const mgs_settings* st, float* images, float* t_final_out) {
+    if (!f) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    mgs_status s;
+    if ((s = check_gaussians(ctx, g, true)) != MGS_OK) return s;
+    if ((s = check_cameras(ctx, cams, n_views)) != MGS_OK) return s;
+    if ((s = check_settings(ctx, st)) != MGS_OK) return s;
+    if (!images) return fail(ctx, MGS_ERR_INVALID_ARG, "images is NULL");
+    f->have_forward = false;
+    f->g = *g;
+    f->n = g->n;
+    f->n_views = n_views;
+    f->R = g->n * n_views;
+    f->views = make_views(cams, n_views, st->tile_w, st->tile_h, &f->P);
+    set_limits(f->views, cams, st->jac_clamp);
+    f->st = make_settings(st);
+    f->cfg_fwd = CompositeConfig{st->tile_w, st->tile_h, st->fwd_ppt};
+    f->cfg_bwd = CompositeConfig{st->tile_w, st->tile_h, st->bwd_ppt};
+    f->persistent = st->persistent;
+    f->total_tiles = f->views.total_tiles;
+    f->tile_bits = bits_for((uint64_t)f->total_tiles);
+    const int64_t R = f->R, P = f->P;
+    if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) || (s = grow(ctx, f->ranges, (size_t)f->total_tiles * 8)) ||
+        (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
+        (s = grow(ctx, f->examined, (size_t)P * 4)) || (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(R))) ||
+        (s = grow(ctx, f->queue, 256)))
+        return s;
+    launch_fill_u32(stream, f->flags(), 2, 0u);
+    launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
+                       (uint32_t*)f->tiles.p, f->flags());
+    launch_scan_u32(stream, (const uint32_t*)f->tiles.p, R, (uint32_t*)f->offsets.p, f->total(), f->scan_tmp.p);
+    MGS_CHECK_LAUNCH(ctx);
+    // the one synchronisation of the plain path: K sizes the sort
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 16, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipStreamSynchronize(stream));
+    const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
+    const uint64_t K = f->h_pinned[1];
+    if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
+    if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu instances exceed 2^31 - 1",
+                                                (unsigned long long)K);
+    f->K = (int64_t)K;
+    if ((s = grow(ctx, f->keys, (size_t)K * 8 + 8)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 4)) ||
+        (s = grow(ctx, f->keys_alt, (size_t)K * 8 + 8)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 4)) ||
+        (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))))
+        return s;
+    f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 8, f->vals.bytes / 4);
+    launch_duplicate(stream, (const float*)f->rec.p, (const float*)f->radius.p, (const float*)f->depth.p,
+                     (const uint32_t*)f->tiles.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
+                     (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
+    const int key_bits = 32 + f->tile_bits;
+    f->sort_passes = (key_bits + 7) / 8;
+    bool in_alt = false;
+    launch_radix_sort(stream, (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, (uint64_t*)f->keys_alt.p,
+                      (uint32_t*)f->vals_alt.p, f->K, nullptr, key_bits, f->sort_tmp.p, &in_alt);
+    f->sorted_in_alt = in_alt;
+    launch_tile_ranges(stream, f->keys_sorted(), f->K, nullptr, f->total_tiles, (uint32_t*)f->ranges.p);
+    uint32_t* queue = nullptr;
+    int grid = 0;
+    if (f->persistent) {
+        queue = (uint32_t*)f->queue.p;
+        launch_fill_u32(stream, queue, 1, 0u);
+        grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
+    }
+    launch_composite_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->vals_sorted(), (const uint32_t*)f->ranges.p,
+                         f->views, f->st, images, (float*)f->t_final.p, (int32_t*)f->last.p,
+                         (int32_t*)f->examined.p, queue, grid);
+    MGS_CHECK_LAUNCH(ctx);
+    if (t_final_out)
+        MGS_HIP(ctx, hipMemcpyAsync(t_final_out, f->t_final.p, (size_t)P * 4, hipMemcpyDeviceToDevice, stream));
+    f->have_forward = true;
+    return MGS_OK;
+}
+
+mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimages, const mgs_gradients* grads) {
+    if (!f) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "mgs_backward without a preceding mgs_forward");
+    if (!dl_dimages || !grads) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    mgs_status s;
+    if ((s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 4 + 4))) return s;
+    float* d_masks = grads->d_masks;
+    if (!d_masks) {
+        if ((s = grow(ctx, f->d_masks_tmp, (size_t)f->n * 4 + 4))) return s;
+        d_masks = (float*)f->d_masks_tmp.p;
+    }
+    launch_fill_f32(stream, (float*)f->d_rec.p, f->R * DREC, 0.f);
+    launch_fill_f32(stream, d_masks, f->n, 0.f);
+    uint32_t* queue = nullptr;
+    int grid = 0;
+    if (f->persistent) {
+        queue = (uint32_t*)f->queue.p;
+        launch_fill_u32(stream, queue, 1, 0u);
+        grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
+    }
+    launch_composite_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->vals_sorted(), (const uint32_t*)f->ranges.p,
+                         f->views, f->st, (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
+                         (float*)f->d_rec.p, d_masks, queue, grid);
+    launch_project_bwd(stream, f->g, f->views, f->st, (const float*)f->d_rec.p, *grads);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_count_evals(mgs_frame* f, mgs_stream stream_, int64_t* total) {
+    if (!f || !total) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "no forward on this frame");
+    mgs_status s;
+    if ((s = grow(ctx, f->sum_tmp, scan_scratch_bytes(f->P) + 64))) return s;
+    uint64_t* out = (uint64_t*)((char*)f->sum_tmp.p + scan_scratch_bytes(f->P));
+    launch_sum_i32(stream, (const int32_t*)f->examined.p, f->P, out, f->sum_tmp.p);
+    MGS_CHECK_LAUNCH(ctx);
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned + 2, out, 8, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipStreamSynchronize(stream));
+    *total = (int64_t)f->h_pinned[2];
+    return MGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+
+mgs_status mgs_project(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams, int n_views,
+                       const mgs_settings* st, float* rec, float* depth, float* radius, uint32_t* tiles) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    mgs_status s;
+    if ((s = check_gaussians(ctx, g, true)) || (s = check_cameras(ctx, cams, n_views)) ||
+        (s = check_settings(ctx, st)))
+        return s;
+    if (g->n > 0 && (!rec || !depth || !radius || !tiles)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL output");
+    if (((uintptr_t)rec & 15) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "rec must be 16-byte aligned");
+    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
+    set_limits(vs, cams, st->jac_clamp);
+    DevSettings ds = make_settings(st);
+    uint32_t* flags = nullptr;
+    if (hipMallocAsync((void**)&flags, 16, (hipStream_t)stream) != hipSuccess)
+        return fail(ctx, MGS_ERR_OOM, "flag buffer");
+    launch_fill_u32((hipStream_t)stream, flags, 4, 0u);
+    launch_project_fwd((hipStream_t)stream, *g, vs, ds, rec, depth, radius, tiles, flags);
+    (void)hipFreeAsync(flags, (hipStream_t)stream);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+size_t mgs_scan_scratch_bytes(int64_t n) { return scan_scratch_bytes(n < 0 ? 0 : n); }
+
+mgs_status mgs_scan(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
+                    uint64_t* total_dev, void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && (!in || !out || !scratch)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (!scratch) return fail(ctx, MGS_ERR_INVALID_ARG, "scratch is NULL");
+    launch_scan_u32((hipStream_t)stream, in, n, out, total_dev, scratch);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_duplicate(mgs_ctx* ctx, mgs_stream stream, const float* rec, const float* depth, const float* radius,
+                         const uint32_t* tiles, const uint32_t* offsets, int64_t n, const mgs_camera* cams,
+                         int n_views, const mgs_settings* st, uint64_t* keys, uint32_t* vals, int64_t capacity) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    mgs_status s;
+    if ((s = check_cameras(ctx, cams, n_views)) || (s = check_settings(ctx, st))) return s;
+    if (n < 0 || capacity < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "negative size");
+    if (n > 0 && (!rec || !depth || !radius || !tiles || !offsets || (capacity > 0 && (!keys || !vals))))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
+    DevSettings ds = make_settings(st);
+    uint32_t* flags = nullptr;
+    if (hipMallocAsync((void**)&flags, 16, (hipStream_t)stream) != hipSuccess)
+        return fail(ctx, MGS_ERR_OOM, "flag buffer");
+    launch_fill_u32((hipStream_t)stream, flags, 4, 0u);
+    launch_duplicate((hipStream_t)stream, rec, radius, depth, tiles, offsets, n * n_views, n, vs, ds, keys, vals,
+                     capacity, flags);
+    uint32_t hf = 0;
+    MGS_HIP(ctx, hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    MGS_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    (void)hipFreeAsync(flags, (hipStream_t)stream);
+    MGS_CHECK_LAUNCH(ctx);
+    if (hf & FLAG_CAPACITY) return fail(ctx, MGS_ERR_CAPACITY, "instances exceed capacity %lld", (long long)capacity);
+    return MGS_OK;
+}
+
+size_t mgs_sort_scratch_bytes(int64_t K) { return sort_scratch_bytes(K < 0 ? 0 : K); }
+
+mgs_status mgs_sort(mgs_ctx* ctx, mgs_stream stream, uint64_t* keys, uint32_t* vals, int64_t K, int key_bits,
+                    uint64_t* keys_alt, uint32_t* vals_alt, void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (K < 0 || K > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_INVALID_ARG, "K = %lld", (long long)K);
+    if (key_bits < 0 || key_bits > 64) return fail(ctx, MGS_ERR_INVALID_ARG, "key_bits %d", key_bits);
+    if (K > 0 && (!keys || !vals || !keys_alt || !vals_alt || !scratch))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (K <= 1) return MGS_OK;
+    bool in_alt = false;
+    launch_radix_sort((hipStream_t)stream, keys, vals, keys_alt, vals_alt, K, nullptr, key_bits, scratch, &in_alt);
+    if (in_alt) {
+        MGS_HIP(ctx, hipMemcpyAsync(keys, keys_alt, (size_t)K * 8, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+        MGS_HIP(ctx, hipMemcpyAsync(vals, vals_alt, (size_t)K * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    }
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_tile_ranges(mgs_ctx* ctx, mgs_stream stream, const uint64_t* keys, int64_t K, int64_t total_tiles,
+                           uint32_t* ranges) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (K < 0 || total_tiles < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "negative size");
+    if ((K > 0 && !keys) || (total_tiles > 0 && !ranges)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    launch_tile_ranges((hipStream_t)stream, keys, K, nullptr, total_tiles, ranges);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
+                                 const uint32_t* ranges, const mgs_camera* cams, int n_views, const mgs_settings* st,
+                                 float* images, float* t_final, int32_t* last, int32_t* examined) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    mgs_status s;
+    if ((s = check_cameras(ctx, cams, n_views)) || (s = check_settings(ctx, st))) return s;
+    if (!rec || !vals || !ranges || !images) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
+    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
+    DevSettings ds = make_settings(st);
+    launch_composite_fwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->fwd_ppt}, rec, vals,
+                         ranges, vs, ds, images, t_final, last, examined, nullptr, 0);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
+                                  const uint32_t* ranges, const mgs_camera* cams, int n_views,
+                                  const mgs_settings* st, const float* t_final, const int32_t* last,
+                                  const float* dl_dimages, int64_t n, float* d_rec, float* d_masks) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    mgs_status s;
+    if ((s = check_cameras(ctx, cams, n_views)) || (s = check_settings(ctx, st))) return s;
+    if (!rec || !vals || !ranges || !t_final || !last || !dl_dimages || !d_rec || !d_masks)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
+    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
+    DevSettings ds = make_settings(st);
+    launch_fill_f32((hipStream_t)stream, d_rec, n * n_views * DREC, 0.f);
+    launch_fill_f32((hipStream_t)stream, d_masks, n, 0.f);
+    launch_composite_bwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->bwd_ppt}, rec, vals, ranges,
+                         vs, ds, t_final, last, dl_dimages, n, d_rec, d_masks, nullptr, 0);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
+                                int n_views, const mgs_settings* st, const float* d_rec, const mgs_gradients* grads) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    mgs_status s;
+    if ((s = check_gaussians(ctx, g, false)) || (s = check_cameras(ctx, cams, n_views)) ||
+        (s = check_settings(ctx, st)))
+        return s;
+    if (!grads || (g->n > 0 && !d_rec)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "d_quats must be 16-byte aligned");
+    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
+    set_limits(vs, cams, st->jac_clamp);
+    DevSettings ds = make_settings(st);
+    launch_project_bwd((hipStream_t)stream, *g, vs, ds, d_rec, *grads);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// masks, loss, optimiser
+// ---------------------------------------------------------------------------
+
+mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float tau, uint64_t seed,
+                            uint64_t step, float* m_hard, float* y_soft) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (!(tau > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "tau must be > 0");
+    if (n > 0 && (!scores || !m_hard || !y_soft)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "scores must be 8-byte aligned");
+    launch_sample_masks((hipStream_t)stream, scores, n, tau, seed, step, m_hard, y_soft);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+size_t mgs_reduce_scratch_bytes(int64_t n) { return reduce_scratch_bytes(n); }
+
+mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
+                         const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores, float* loss_m,
+                         void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (!(tau > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "tau must be > 0");
+    if (n > 0 && (!d_masks || !m_hard || !y_soft || !d_scores || !scratch))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)d_scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "d_scores must be 8-byte aligned");
+    launch_mask_grad((hipStream_t)stream, d_masks, m_hard, y_soft, n, tau, lambda_m, d_scores, loss_m, scratch);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_l1_loss_grad(mgs_ctx* ctx, mgs_stream stream, const float* images, const float* targets, int64_t m,
+                            float* d_images, float* loss, void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (m < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "m < 0");
+    if (m > 0 && (!images || !targets || !d_images || !scratch))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    launch_l1_loss_grad((hipStream_t)stream, images, targets, m, d_images, loss, scratch);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_adam_step(mgs_ctx* ctx, mgs_stream stream, float* params, const float* grads, float* m, float* v,
+                         int64_t n, float lr, float beta1, float beta2, float eps, int64_t step) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0 || step < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0 or step < 1");
+    if (n > 0 && (!params || !grads || !m || !v)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    launch_adam((hipStream_t)stream, params, grads, m, v, n, lr, beta1, beta2, eps, step);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+}  // extern "C"

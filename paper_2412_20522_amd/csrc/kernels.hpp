@@ -1,0 +1,66 @@
+// Host-side launchers of the gfx950 kernels (one translation unit each).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace mgs {
+
+// projection
+void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags);
+void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                        const float* d_rec, const mgs_gradients& out);
+
+// scan / binning / sort / ranges
+size_t scan_scratch_bytes(int64_t n);
+// Exclusive scan of n u32; total (u64) to total_dev.  count_dev (optional)
+// holds the live element count on the device (<= n); elements at or past it
+// are treated as zero.
+void launch_scan_u32(hipStream_t stream, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total_dev,
+                     void* scratch);
+void launch_duplicate(hipStream_t stream, const float* rec, const float* radius, const float* depth,
+                      const uint32_t* tiles, const uint32_t* offsets, int64_t n_records, int64_t n_per_view,
+                      const ViewSet& views, const DevSettings& st, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                      uint32_t* flags);
+size_t sort_scratch_bytes(int64_t K);
+// Sorts (keys, vals) by the low key_bits bits; K_dev (optional) is the live
+// count on the device (<= K).  Returns through *out_in_alt whether the
+// result ended in the alternate buffers.
+void launch_radix_sort(hipStream_t stream, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                       int64_t K, const uint64_t* K_dev, int key_bits, void* scratch, bool* out_in_alt);
+void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, const uint64_t* K_dev,
+                        int64_t total_tiles, uint32_t* ranges);
+void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value);
+void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value);
+// Sum of n int32 values into a device u64 (deterministic).
+void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);
+
+// compositing
+struct CompositeConfig {
+    int tile_w, tile_h, ppt;  // pixels per thread; threads per block = tile_w * tile_h / ppt
+};
+bool composite_config_supported(const CompositeConfig& c);
+void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
+                          const uint32_t* ranges, const ViewSet& views, const DevSettings& st, float* images,
+                          float* t_final, int32_t* last, int32_t* examined, uint32_t* queue, int grid_override);
+void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
+                          const uint32_t* ranges, const ViewSet& views, const DevSettings& st, const float* t_final,
+                          const int32_t* last, const float* dl_dimages, int64_t n, float* d_rec, float* d_masks,
+                          uint32_t* queue, int grid_override);
+
+// masks, loss, optimiser
+size_t reduce_scratch_bytes(int64_t n);
+void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, float tau, uint64_t seed, uint64_t step,
+                         float* m_hard, float* y_soft);
+void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
+                      float tau, float lambda_m, float* d_scores, float* loss_m, void* scratch);
+void launch_l1_loss_grad(hipStream_t stream, const float* images, const float* targets, int64_t m, float* d_images,
+                         float* loss, void* scratch);
+void launch_adam(hipStream_t stream, float* params, const float* grads, float* m, float* v, int64_t n, float lr,
+                 float b1, float b2, float eps, int64_t step);
+
+}  // namespace mgs

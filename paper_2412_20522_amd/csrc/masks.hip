@@ -1,0 +1,169 @@
+// Mask sampling and mask gradient (Sec. 3.3, Eq. 7-8), L1 rendering loss
+// and Adam on gfx950.
+//
+// Masks: two scores per Gaussian, Gumbel-Softmax with a hard forward value
+// and the soft sample's derivative in the backward (straight-through).  The
+// Gumbel noise is a function of (seed, step, Gaussian id) through
+// Philox4x32-10 (Salmon et al., SC'11), so a step can be replayed.  The noise
+// and the hard decision are computed in double precision.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mgs {
+namespace {
+
+constexpr int RNT = 256;
+
+// Philox4x32-10: ten rounds of two 32x32->64 multiplies with the Weyl key
+// schedule, written from the generator's published definition.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
+                                              uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+__device__ __forceinline__ double gumbel_from_bits(uint32_t x) {
+    const double u = ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+    return -log(-log(u));
+}
+
+__global__ void __launch_bounds__(RNT) sample_masks_kernel(const float* __restrict__ scores, int64_t n, float tau,
+                                                            uint64_t seed, uint64_t step, float* __restrict__ m_hard,
+                                                            float* __restrict__ y_soft) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32), c2 = (uint32_t)step, c3 = (uint32_t)(step >> 32);
+    philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float2 s = reinterpret_cast<const float2*>(scores)[i];
+    const double z0 = (double)s.x + gumbel_from_bits(c0);
+    const double z1 = (double)s.y + gumbel_from_bits(c1);
+    m_hard[i] = z0 > z1 ? 1.f : 0.f;
+    y_soft[i] = (float)(1.0 / (1.0 + exp(-(z0 - z1) / (double)tau)));
+}
+
+// Deterministic two-level sums in double.
+__global__ void __launch_bounds__(RNT) partial_sum_kernel(const float* __restrict__ a, int64_t n,
+                                                           double* __restrict__ partial) {
+    __shared__ double sh[RNT / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RNT) s += (double)a[i];
+    s = block_sum_double(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(RNT) partial_abs_diff_kernel(const float* __restrict__ a,
+                                                                const float* __restrict__ b, int64_t n,
+                                                                float inv_m, float* __restrict__ d,
+                                                                double* __restrict__ partial) {
+    __shared__ double sh[RNT / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RNT) {
+        const float x = a[i] - b[i];
+        s += fabs((double)a[i] - (double)b[i]);
+        d[i] = x > 0.f ? inv_m : (x < 0.f ? -inv_m : 0.f);
+    }
+    s = block_sum_double(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(RNT) finish_sum_kernel(const double* __restrict__ partial, int nb, double scale,
+                                                          double* __restrict__ total, float* __restrict__ out_f,
+                                                          int square) {
+    __shared__ double sh[RNT / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += RNT) s += partial[i];
+    s = block_sum_double(s, sh);
+    if (threadIdx.x == 0) {
+        *total = s;
+        if (out_f) {
+            const double m = s * scale;
+            *out_f = (float)(square ? m * m : m);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(RNT) mask_grad_kernel(const float* __restrict__ d_masks,
+                                                         const float* __restrict__ y_soft, int64_t n, float tau,
+                                                         float lambda_m, const double* __restrict__ sum_m,
+                                                         float* __restrict__ d_scores) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // d L_m / d M_i = 2 mean(M) / n
+    const float dlm = (float)(2.0 * (*sum_m) / ((double)n * (double)n));
+    const float y = y_soft[i];
+    const float g = (d_masks[i] + lambda_m * dlm) * y * (1.f - y) / tau;
+    reinterpret_cast<float2*>(d_scores)[i] = make_float2(g, -g);
+}
+
+__global__ void __launch_bounds__(RNT) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                    float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                                    float b1, float b2, float eps, float inv_c1, float inv_c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
+}
+
+constexpr int REDUCE_BLOCKS = 1024;
+
+}  // namespace
+
+size_t reduce_scratch_bytes(int64_t) { return (REDUCE_BLOCKS + 8) * sizeof(double); }
+
+void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, float tau, uint64_t seed, uint64_t step,
+                         float* m_hard, float* y_soft) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(sample_masks_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores, n,
+                       tau, seed, step, m_hard, y_soft);
+}
+
+void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
+                      float tau, float lambda_m, float* d_scores, float* loss_m, void* scratch) {
+    if (n == 0) return;
+    double* partial = reinterpret_cast<double*>(scratch);
+    double* total = partial + REDUCE_BLOCKS;
+    const int nb = (int)std::min<int64_t>(REDUCE_BLOCKS, (n + RNT - 1) / RNT);
+    hipLaunchKernelGGL(partial_sum_kernel, dim3(nb), dim3(RNT), 0, stream, m_hard, n, partial);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RNT), 0, stream, (const double*)partial, nb, 1.0 / (double)n,
+                       total, loss_m, 1);
+    hipLaunchKernelGGL(mask_grad_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, d_masks, y_soft,
+                       n, tau, lambda_m, (const double*)total, d_scores);
+}
+
+void launch_l1_loss_grad(hipStream_t stream, const float* images, const float* targets, int64_t m, float* d_images,
+                         float* loss, void* scratch) {
+    if (m == 0) return;
+    double* partial = reinterpret_cast<double*>(scratch);
+    double* total = partial + REDUCE_BLOCKS;
+    const int nb = (int)std::min<int64_t>(REDUCE_BLOCKS, (m + RNT - 1) / RNT);
+    hipLaunchKernelGGL(partial_abs_diff_kernel, dim3(nb), dim3(RNT), 0, stream, images, targets, m,
+                       (float)(1.0 / (double)m), d_images, partial);
+    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RNT), 0, stream, (const double*)partial, nb, 1.0 / (double)m,
+                       total, loss, 0);
+}
+
+void launch_adam(hipStream_t stream, float* params, const float* grads, float* m, float* v, int64_t n, float lr,
+                 float b1, float b2, float eps, int64_t step) {
+    if (n == 0) return;
+    const double c1 = 1.0 - pow((double)b1, (double)step), c2 = 1.0 - pow((double)b2, (double)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, params, grads, m, v,
+                       n, lr, b1, b2, eps, (float)(1.0 / c1), (float)(1.0 / c2));
+}
+
+}  // namespace mgs

@@ -1,0 +1,497 @@
+// EWA projection of 3D Gaussians and its backward pass (gfx950).
+//
+// Forward (Sec. 3.1): scale/quaternion -> 3D covariance, view transform,
+// perspective Jacobian -> 2D covariance (+ dilation) -> conic, radius, tile
+// footprint, and the view-dependent SH colour.  Masks are not applied here;
+// they only travel in the record to the compositing kernels (Sec. 3.2-3.3).
+//
+// One thread per Gaussian loops over all views, so the 3D covariance and
+// the SH coefficients (up to 192 B) are read from HBM once per Gaussian
+// rather than once per view.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mgs {
+namespace {
+
+// Real spherical harmonics (no Condon-Shortley phase) in Cartesian form.
+constexpr float SH0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+constexpr float SH1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
+constexpr float SH2a = 1.0925484305920792f;   // sqrt(15 / pi) / 2
+constexpr float SH2b = 0.31539156525252005f;  // sqrt(5 / pi) / 4
+constexpr float SH2c = 0.54627421529603959f;  // sqrt(15 / pi) / 4
+constexpr float SH3a = 0.59004358992664352f;  // sqrt(35 / (2 pi)) / 4
+constexpr float SH3b = 2.8906114426405538f;   // sqrt(105 / pi) / 2
+constexpr float SH3c = 0.45704579946446572f;  // sqrt(21 / (2 pi)) / 4
+constexpr float SH3d = 0.37317633259011540f;  // sqrt(7 / pi) / 4
+constexpr float SH3e = 1.4453057213202769f;   // sqrt(105 / pi) / 4
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+    Y[0] = SH0;
+    if (DEG >= 1) {
+        Y[1] = SH1 * y;
+        Y[2] = SH1 * z;
+        Y[3] = SH1 * x;
+    }
+    if (DEG >= 2) {
+        Y[4] = SH2a * x * y;
+        Y[5] = SH2a * y * z;
+        Y[6] = SH2b * (3.f * z * z - 1.f);
+        Y[7] = SH2a * x * z;
+        Y[8] = SH2c * (x * x - y * y);
+    }
+    if (DEG >= 3) {
+        Y[9] = SH3a * y * (3.f * x * x - y * y);
+        Y[10] = SH3b * x * y * z;
+        Y[11] = SH3c * y * (5.f * z * z - 1.f);
+        Y[12] = SH3d * z * (5.f * z * z - 3.f);
+        Y[13] = SH3c * x * (5.f * z * z - 1.f);
+        Y[14] = SH3e * z * (x * x - y * y);
+        Y[15] = SH3a * x * (x * x - 3.f * y * y);
+    }
+}
+
+// Partial derivatives of the polynomials above in (x, y, z).
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float (*D)[3]) {
+    D[0][0] = D[0][1] = D[0][2] = 0.f;
+    if (DEG >= 1) {
+        D[1][0] = 0.f;  D[1][1] = SH1;  D[1][2] = 0.f;
+        D[2][0] = 0.f;  D[2][1] = 0.f;  D[2][2] = SH1;
+        D[3][0] = SH1;  D[3][1] = 0.f;  D[3][2] = 0.f;
+    }
+    if (DEG >= 2) {
+        D[4][0] = SH2a * y;        D[4][1] = SH2a * x;         D[4][2] = 0.f;
+        D[5][0] = 0.f;             D[5][1] = SH2a * z;         D[5][2] = SH2a * y;
+        D[6][0] = 0.f;             D[6][1] = 0.f;              D[6][2] = SH2b * 6.f * z;
+        D[7][0] = SH2a * z;        D[7][1] = 0.f;              D[7][2] = SH2a * x;
+        D[8][0] = SH2c * 2.f * x;  D[8][1] = -SH2c * 2.f * y;  D[8][2] = 0.f;
+    }
+    if (DEG >= 3) {
+        D[9][0] = SH3a * 6.f * x * y;
+        D[9][1] = SH3a * 3.f * (x * x - y * y);
+        D[9][2] = 0.f;
+        D[10][0] = SH3b * y * z;
+        D[10][1] = SH3b * x * z;
+        D[10][2] = SH3b * x * y;
+        D[11][0] = 0.f;
+        D[11][1] = SH3c * (5.f * z * z - 1.f);
+        D[11][2] = SH3c * 10.f * y * z;
+        D[12][0] = 0.f;
+        D[12][1] = 0.f;
+        D[12][2] = SH3d * (15.f * z * z - 3.f);
+        D[13][0] = SH3c * (5.f * z * z - 1.f);
+        D[13][1] = 0.f;
+        D[13][2] = SH3c * 10.f * x * z;
+        D[14][0] = SH3e * 2.f * x * z;
+        D[14][1] = -SH3e * 2.f * y * z;
+        D[14][2] = SH3e * (x * x - y * y);
+        D[15][0] = SH3a * 3.f * (x * x - y * y);
+        D[15][1] = -SH3a * 6.f * x * y;
+        D[15][2] = 0.f;
+    }
+}
+
+template <int DEG>
+__device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t g, float* c) {
+    constexpr int K3 = 3 * (DEG + 1) * (DEG + 1);
+    const float* p = sh + g * K3;
+    if constexpr (K3 % 4 == 0) {
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int i = 0; i < K3 / 4; ++i) {
+            const float4 q = p4[i];
+            c[4 * i] = q.x; c[4 * i + 1] = q.y; c[4 * i + 2] = q.z; c[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K3; ++i) c[i] = p[i];
+    }
+}
+
+// Rotation matrix of the normalised quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+struct ViewGeom {
+    bool valid;
+    float tx, ty, tz;     // view-space centre (float32 of the double transform)
+    float u, v;
+    float sx, sy;         // lateral ratios after clamping
+    bool clx, cly;
+    float T0[3], T1[3];   // J W
+    float a, b, c;        // 2D covariance incl. dilation
+    float ca, cb, cc;     // conic
+    float radius;
+};
+
+// Per-view geometry of one Gaussian; Sig = 3D covariance (00,01,02,11,12,22).
+__device__ __forceinline__ ViewGeom view_geom(const DevView& cam, const DevSettings& st, float px, float py, float pz,
+                                              const float* Sig) {
+    ViewGeom o;
+    // view transform in double: products of two floats are exact, so the
+    // association ((W0 x + W1 y) + W2 z) + t fixes the result bit for bit
+    const double xd = px, yd = py, zd = pz;
+    const double txd = (((double)cam.W[0] * xd + (double)cam.W[1] * yd) + (double)cam.W[2] * zd) + (double)cam.t[0];
+    const double tyd = (((double)cam.W[3] * xd + (double)cam.W[4] * yd) + (double)cam.W[5] * zd) + (double)cam.t[1];
+    const double tzd = (((double)cam.W[6] * xd + (double)cam.W[7] * yd) + (double)cam.W[8] * zd) + (double)cam.t[2];
+    o.tz = (float)tzd;
+    o.valid = o.tz > st.near_plane;
+    if (!o.valid) return o;
+    o.tx = (float)txd;
+    o.ty = (float)tyd;
+    o.u = (float)((double)cam.fx * txd / tzd + (double)cam.cx);
+    o.v = (float)((double)cam.fy * tyd / tzd + (double)cam.cy);
+    const float iz = 1.f / o.tz;
+    const float rx = o.tx * iz, ry = o.ty * iz;
+    o.clx = rx < -cam.limx || rx > cam.limx;
+    o.cly = ry < -cam.limy || ry > cam.limy;
+    o.sx = fminf(fmaxf(rx, -cam.limx), cam.limx);
+    o.sy = fminf(fmaxf(ry, -cam.limy), cam.limy);
+    const float J00 = cam.fx * iz, J02 = -cam.fx * o.sx * iz;
+    const float J11 = cam.fy * iz, J12 = -cam.fy * o.sy * iz;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        o.T0[j] = J00 * cam.W[j] + J02 * cam.W[6 + j];
+        o.T1[j] = J11 * cam.W[3 + j] + J12 * cam.W[6 + j];
+    }
+    // U = T Sigma (2x3)
+    const float S00 = Sig[0], S01 = Sig[1], S02 = Sig[2], S11 = Sig[3], S12 = Sig[4], S22 = Sig[5];
+    const float U00 = o.T0[0] * S00 + o.T0[1] * S01 + o.T0[2] * S02;
+    const float U01 = o.T0[0] * S01 + o.T0[1] * S11 + o.T0[2] * S12;
+    const float U02 = o.T0[0] * S02 + o.T0[1] * S12 + o.T0[2] * S22;
+    const float U10 = o.T1[0] * S00 + o.T1[1] * S01 + o.T1[2] * S02;
+    const float U11 = o.T1[0] * S01 + o.T1[1] * S11 + o.T1[2] * S12;
+    const float U12 = o.T1[0] * S02 + o.T1[1] * S12 + o.T1[2] * S22;
+    o.a = U00 * o.T0[0] + U01 * o.T0[1] + U02 * o.T0[2] + st.dilation;
+    o.b = U00 * o.T1[0] + U01 * o.T1[1] + U02 * o.T1[2];
+    o.c = U10 * o.T1[0] + U11 * o.T1[1] + U12 * o.T1[2] + st.dilation;
+    // determinant in double: one rounding instead of a float cancellation
+    const double det = (double)o.a * (double)o.c - (double)o.b * (double)o.b;
+    if (!(det > 0.0)) { o.valid = false; return o; }
+    const float idet = (float)(1.0 / det);
+    o.ca = o.c * idet;
+    o.cb = -o.b * idet;
+    o.cc = o.a * idet;
+    const float mid = 0.5f * (o.a + o.c);
+    const float disc = fmaxf(st.lambda_floor, mid * mid - (float)det);
+    o.radius = ceilf(3.f * sqrtf(mid + sqrtf(disc)));
+    if (!(isfinite(o.u) && isfinite(o.v) && isfinite(o.ca) && isfinite(o.cb) && isfinite(o.cc) &&
+          isfinite(o.radius) && o.radius > 0.f))
+        o.valid = false;
+    return o;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) project_fwd_kernel(
+    const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh, const float* __restrict__ masks,
+    int64_t n, ViewSet views, DevSettings st, float4* __restrict__ rec, float* __restrict__ depth_out,
+    float* __restrict__ radius_out, uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ flags) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
+    const float s0 = __expf(log_scales[3 * g]), s1 = __expf(log_scales[3 * g + 1]), s2 = __expf(log_scales[3 * g + 2]);
+    const float4 q = reinterpret_cast<const float4*>(quats)[g];
+    const float qinv = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    float R[9];
+    quat_to_rot(q.x * qinv, q.y * qinv, q.z * qinv, q.w * qinv, R);
+    // Sigma = (R S)(R S)^T
+    float Sig[6];
+    {
+        const float M00 = R[0] * s0, M01 = R[1] * s1, M02 = R[2] * s2;
+        const float M10 = R[3] * s0, M11 = R[4] * s1, M12 = R[5] * s2;
+        const float M20 = R[6] * s0, M21 = R[7] * s1, M22 = R[8] * s2;
+        Sig[0] = M00 * M00 + M01 * M01 + M02 * M02;
+        Sig[1] = M00 * M10 + M01 * M11 + M02 * M12;
+        Sig[2] = M00 * M20 + M01 * M21 + M02 * M22;
+        Sig[3] = M10 * M10 + M11 * M11 + M12 * M12;
+        Sig[4] = M10 * M20 + M11 * M21 + M12 * M22;
+        Sig[5] = M20 * M20 + M21 * M21 + M22 * M22;
+    }
+    const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
+    const float mval = masks[g];
+    float coef[3 * K];
+    load_sh<DEG>(sh, g, coef);
+    bool bad = false;
+    for (int vi = 0; vi < views.n_views; ++vi) {
+        const DevView& cam = views.v[vi];
+        const int64_t r = (int64_t)vi * n + g;
+        const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
+        if (!o.valid) {
+            // culled, or non-finite geometry (flagged unless simply behind the near plane)
+            if (o.tz > st.near_plane) bad = true;
+            rec[3 * r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[3 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec[3 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            depth_out[r] = o.tz;
+            radius_out[r] = 0.f;
+            tiles_out[r] = 0;
+            continue;
+        }
+        // colour in the viewing direction
+        float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
+        const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= dinv; dy *= dinv; dz *= dinv;
+        float Y[K];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
+            col[ch] = fmaxf(acc, 0.f);
+        }
+        // square footprint in tiles, in double so the bounds are exact
+        uint32_t count;
+        if (st.full_rect) {
+            count = (uint32_t)(cam.grid_w * cam.grid_h);
+        } else {
+            const double ud = o.u, vd = o.v, rd = o.radius;
+            double x0 = floor((ud - rd) / st.tile_w), x1 = floor((ud + rd) / st.tile_w);
+            double y0 = floor((vd - rd) / st.tile_h), y1 = floor((vd + rd) / st.tile_h);
+            x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+            x1 = fmin(x1, (double)(cam.grid_w - 1)); y1 = fmin(y1, (double)(cam.grid_h - 1));
+            count = (x0 <= x1 && y0 <= y1) ? (uint32_t)((x1 - x0 + 1.0) * (y1 - y0 + 1.0)) : 0u;
+        }
+        rec[3 * r] = make_float4(o.u, o.v, o.ca, o.cb);
+        rec[3 * r + 1] = make_float4(o.cc, opac, mval, 0.f);
+        rec[3 * r + 2] = make_float4(col[0], col[1], col[2], 0.f);
+        depth_out[r] = o.tz;
+        radius_out[r] = o.radius;
+        tiles_out[r] = count;
+    }
+    if (bad) atomicOr(flags, FLAG_NONFINITE);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) project_bwd_kernel(
+    const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh, int64_t n, ViewSet views,
+    DevSettings st, const float* __restrict__ d_rec, float* __restrict__ d_means, float* __restrict__ d_log_scales,
+    float* __restrict__ d_quats, float* __restrict__ d_opacity_logits, float* __restrict__ d_sh) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
+    const float s[3] = {__expf(log_scales[3 * g]), __expf(log_scales[3 * g + 1]), __expf(log_scales[3 * g + 2])};
+    const float4 q = reinterpret_cast<const float4*>(quats)[g];
+    const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+    const float qinv = rsqrtf(qn2);
+    const float qw = q.x * qinv, qx = q.y * qinv, qy = q.z * qinv, qz = q.w * qinv;
+    float R[9];
+    quat_to_rot(qw, qx, qy, qz, R);
+    float Sig[6];
+    {
+        const float M00 = R[0] * s[0], M01 = R[1] * s[1], M02 = R[2] * s[2];
+        const float M10 = R[3] * s[0], M11 = R[4] * s[1], M12 = R[5] * s[2];
+        const float M20 = R[6] * s[0], M21 = R[7] * s[1], M22 = R[8] * s[2];
+        Sig[0] = M00 * M00 + M01 * M01 + M02 * M02;
+        Sig[1] = M00 * M10 + M01 * M11 + M02 * M12;
+        Sig[2] = M00 * M20 + M01 * M21 + M02 * M22;
+        Sig[3] = M10 * M10 + M11 * M11 + M12 * M12;
+        Sig[4] = M10 * M20 + M11 * M21 + M12 * M22;
+        Sig[5] = M20 * M20 + M21 * M21 + M22 * M22;
+    }
+    const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
+    float coef[3 * K];
+    load_sh<DEG>(sh, g, coef);
+
+    float gS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // dL/dSigma (full-matrix gradient, symmetric entries)
+    float gp[3] = {0.f, 0.f, 0.f};
+    float gop = 0.f;
+    float gsh[3 * K];
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) gsh[i] = 0.f;
+
+    for (int vi = 0; vi < views.n_views; ++vi) {
+        const DevView& cam = views.v[vi];
+        const int64_t r = (int64_t)vi * n + g;
+        const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
+        if (!o.valid) continue;
+        const float* dr = d_rec + r * DREC;
+        const float du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
+        gop += dr[5];
+        // colour: SH coefficients and viewing direction
+        float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
+        const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= dinv; dy *= dinv; dz *= dinv;
+        float Y[K];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float dcol[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
+            dcol[ch] = acc < 0.f ? 0.f : dr[6 + ch];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            gsh[3 * k] += dcol[0] * Y[k];
+            gsh[3 * k + 1] += dcol[1] * Y[k];
+            gsh[3 * k + 2] += dcol[2] * Y[k];
+        }
+        if (DEG > 0) {
+            float D[K][3];
+            sh_basis_grad<DEG>(dx, dy, dz, D);
+            float dd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 1; k < K; ++k) {
+                const float w = dcol[0] * coef[3 * k] + dcol[1] * coef[3 * k + 1] + dcol[2] * coef[3 * k + 2];
+                dd[0] += w * D[k][0];
+                dd[1] += w * D[k][1];
+                dd[2] += w * D[k][2];
+            }
+            const float proj = dd[0] * dx + dd[1] * dy + dd[2] * dz;
+            gp[0] += (dd[0] - proj * dx) * dinv;
+            gp[1] += (dd[1] - proj * dy) * dinv;
+            gp[2] += (dd[2] - proj * dz) * dinv;
+        }
+        // conic -> 2D covariance: H = -Conic Gc Conic, Gc = [[dca, dcb/2], [dcb/2, dcc]]
+        const float hb = 0.5f * dcb;
+        const float X00 = o.ca * dca + o.cb * hb, X01 = o.ca * hb + o.cb * dcc;
+        const float X10 = o.cb * dca + o.cc * hb, X11 = o.cb * hb + o.cc * dcc;
+        const float H00 = -(X00 * o.ca + X01 * o.cb);
+        const float H01 = -(X00 * o.cb + X01 * o.cc);
+        const float H11 = -(X10 * o.cb + X11 * o.cc);
+        // dSigma += T^T H T ; dT = 2 H T Sigma
+        float HT0[3], HT1[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            HT0[j] = H00 * o.T0[j] + H01 * o.T1[j];
+            HT1[j] = H01 * o.T0[j] + H11 * o.T1[j];
+        }
+        gS[0] += o.T0[0] * HT0[0] + o.T1[0] * HT1[0];
+        gS[1] += o.T0[0] * HT0[1] + o.T1[0] * HT1[1];
+        gS[2] += o.T0[0] * HT0[2] + o.T1[0] * HT1[2];
+        gS[3] += o.T0[1] * HT0[1] + o.T1[1] * HT1[1];
+        gS[4] += o.T0[1] * HT0[2] + o.T1[1] * HT1[2];
+        gS[5] += o.T0[2] * HT0[2] + o.T1[2] * HT1[2];
+        float dT0[3], dT1[3];
+        dT0[0] = 2.f * (HT0[0] * Sig[0] + HT0[1] * Sig[1] + HT0[2] * Sig[2]);
+        dT0[1] = 2.f * (HT0[0] * Sig[1] + HT0[1] * Sig[3] + HT0[2] * Sig[4]);
+        dT0[2] = 2.f * (HT0[0] * Sig[2] + HT0[1] * Sig[4] + HT0[2] * Sig[5]);
+        dT1[0] = 2.f * (HT1[0] * Sig[0] + HT1[1] * Sig[1] + HT1[2] * Sig[2]);
+        dT1[1] = 2.f * (HT1[0] * Sig[1] + HT1[1] * Sig[3] + HT1[2] * Sig[4]);
+        dT1[2] = 2.f * (HT1[0] * Sig[2] + HT1[1] * Sig[4] + HT1[2] * Sig[5]);
+        // T = J W  ->  dJ = dT W^T (only J00, J02, J11, J12 are variables)
+        const float dJ00 = dT0[0] * cam.W[0] + dT0[1] * cam.W[1] + dT0[2] * cam.W[2];
+        const float dJ02 = dT0[0] * cam.W[6] + dT0[1] * cam.W[7] + dT0[2] * cam.W[8];
+        const float dJ11 = dT1[0] * cam.W[3] + dT1[1] * cam.W[4] + dT1[2] * cam.W[5];
+        const float dJ12 = dT1[0] * cam.W[6] + dT1[1] * cam.W[7] + dT1[2] * cam.W[8];
+        // view-space centre
+        const float iz = 1.f / o.tz, iz2 = iz * iz;
+        float dtx = du * cam.fx * iz;
+        float dty = dv * cam.fy * iz;
+        float dtz = -(du * cam.fx * o.tx + dv * cam.fy * o.ty) * iz2;
+        dtz += -(dJ00 * cam.fx + dJ11 * cam.fy) * iz2;
+        if (!o.clx) {
+            dtx += -dJ02 * cam.fx * iz2;
+            dtz += dJ02 * 2.f * cam.fx * o.tx * iz2 * iz;
+        } else {
+            dtz += dJ02 * cam.fx * o.sx * iz2;
+        }
+        if (!o.cly) {
+            dty += -dJ12 * cam.fy * iz2;
+            dtz += dJ12 * 2.f * cam.fy * o.ty * iz2 * iz;
+        } else {
+            dtz += dJ12 * cam.fy * o.sy * iz2;
+        }
+        // t = W p + t  ->  dp = W^T dt
+        gp[0] += cam.W[0] * dtx + cam.W[3] * dty + cam.W[6] * dtz;
+        gp[1] += cam.W[1] * dtx + cam.W[4] * dty + cam.W[7] * dtz;
+        gp[2] += cam.W[2] * dtx + cam.W[5] * dty + cam.W[8] * dtz;
+    }
+
+    // Sigma = R diag(s^2) R^T with G = dL/dSigma (symmetric)
+    const float G[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+    float GR[9];  // G R
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) GR[3 * i + k] = G[3 * i] * R[k] + G[3 * i + 1] * R[3 + k] + G[3 * i + 2] * R[6 + k];
+    float dR[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dR[3 * i + k] = 2.f * GR[3 * i + k] * s[k] * s[k];
+    float dls[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float rgr = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];  // (R^T G R)_kk
+        dls[k] = 2.f * s[k] * s[k] * rgr;
+    }
+    // rotation matrix -> normalised quaternion
+    const float gw = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    const float gx = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                            qw * dR[7] - 2.f * qx * dR[8]);
+    const float gy = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                            qz * dR[7] - 2.f * qy * dR[8]);
+    const float gz = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] +
+                            qy * dR[5] + qx * dR[6] + qy * dR[7]);
+    const float dotq = qw * gw + qx * gx + qy * gy + qz * gz;
+    if (d_quats)
+        reinterpret_cast<float4*>(d_quats)[g] = make_float4((gw - qw * dotq) * qinv, (gx - qx * dotq) * qinv,
+                                                            (gy - qy * dotq) * qinv, (gz - qz * dotq) * qinv);
+    if (d_means) {
+        d_means[3 * g] = gp[0];
+        d_means[3 * g + 1] = gp[1];
+        d_means[3 * g + 2] = gp[2];
+    }
+    if (d_log_scales) {
+        d_log_scales[3 * g] = dls[0];
+        d_log_scales[3 * g + 1] = dls[1];
+        d_log_scales[3 * g + 2] = dls[2];
+    }
+    if (d_opacity_logits) d_opacity_logits[g] = gop * opac * (1.f - opac);
+    if (d_sh) {
+        float* o = d_sh + g * 3 * K;
+#pragma unroll
+        for (int i = 0; i < 3 * K; ++i) o[i] = gsh[i];
+    }
+}
+
+}  // namespace
+
+void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags) {
+    if (g.n == 0) return;
+    const dim3 grid((unsigned)((g.n + 255) / 256));
+    float4* rec4 = reinterpret_cast<float4*>(rec);
+    switch (st.sh_degree) {
+        case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
+                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
+        case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
+                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
+        case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
+                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
+        default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
+                                    g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
+    }
+}
+
+void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                        const float* d_rec, const mgs_gradients& out) {
+    if (g.n == 0) return;
+    const dim3 grid((unsigned)((g.n + 255) / 256));
+#define MGS_PBWD(D)                                                                                                \
+    hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,          \
+                       g.opacity_logits, g.sh, g.n, views, st, d_rec, out.d_means, out.d_log_scales, out.d_quats,  \
+                       out.d_opacity_logits, out.d_sh)
+    switch (st.sh_degree) {
+        case 0: MGS_PBWD(0); break;
+        case 1: MGS_PBWD(1); break;
+        case 2: MGS_PBWD(2); break;
+        default: MGS_PBWD(3); break;
+    }
+#undef MGS_PBWD
+}
+
+}  // namespace mgs

@@ -1,0 +1,429 @@
+// Binning and ordering of (tile, Gaussian) instances on gfx950:
+// exclusive scan of tile counts, key duplication, a stable LSD radix sort
+// of (tile << 32 | depth bits) keys, and per-tile ranges (Sec. 3.1: only
+// Gaussians that intersect a tile take part in that tile, in depth order).
+//
+// The sort is reduce-then-scan (per-block digit histograms, a device-wide
+// scan of the digit-major histogram, then a stable scatter); it has no
+// inter-block spin waits, so it needs no forward-progress guarantee between
+// workgroups.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mgs {
+namespace {
+
+constexpr int NT = 256;
+constexpr int IPT = 16;
+constexpr int TILE = NT * IPT;  // 4096 elements per block
+constexpr int RADIX = 256;
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over a 256-thread block; *total gets the block sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
+    const T inc = wave_inclusive_scan(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) sh[w] = inc;
+    __syncthreads();
+    T wo = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        if (i < w) wo += sh[i];
+        tot += sh[i];
+    }
+    *total = tot;
+    __syncthreads();
+    return wo + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// scan of u32 counts (reduce, scan of block sums, downsweep)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(NT) scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                          uint64_t* __restrict__ partial) {
+    __shared__ uint64_t sh[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    s = wave_inclusive_scan(s);
+    if (lane_id() == 63) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < NT / 64; ++i) t += sh[i];
+        partial[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(NT) scan_partials_kernel(uint64_t* __restrict__ partial, int64_t nb,
+                                                            uint64_t* __restrict__ total_dev) {
+    __shared__ uint64_t sh[NT / 64];
+    uint64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += NT) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = i < nb ? partial[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) partial[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_dev) *total_dev = carry;
+}
+
+__global__ void __launch_bounds__(NT) scan_down_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                        const uint64_t* __restrict__ partial,
+                                                        uint32_t* __restrict__ out) {
+    __shared__ uint32_t tile[TILE];
+    __shared__ uint32_t sh[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    // coalesced load, then each thread takes 16 consecutive elements
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        tile[j * NT + threadIdx.x] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[IPT];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        v[j] = tile[threadIdx.x * IPT + j];
+        s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, sh, &tot) + (uint32_t)partial[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        tile[threadIdx.x * IPT + j] = run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) out[i] = tile[j * NT + threadIdx.x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// key duplication: one thread per record walks its tile rectangle
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) duplicate_kernel(
+    const float4* __restrict__ rec, const float* __restrict__ radius, const float* __restrict__ depth,
+    const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ offsets, int64_t n_records, int64_t n_per_view,
+    ViewSet views, DevSettings st, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
+    uint32_t* __restrict__ flags) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_records) return;
+    const uint32_t cnt = tiles[r];
+    if (cnt == 0) return;
+    const int vi = (int)(r / n_per_view);
+    const DevView& cam = views.v[vi];
+    int x0, x1, y0, y1;
+    if (st.full_rect) {
+        x0 = 0; y0 = 0; x1 = cam.grid_w - 1; y1 = cam.grid_h - 1;
+    } else {
+        const float4 A = rec[3 * r];
+        const double ud = A.x, vd = A.y, rd = radius[r];
+        double fx0 = floor((ud - rd) / st.tile_w), fx1 = floor((ud + rd) / st.tile_w);
+        double fy0 = floor((vd - rd) / st.tile_h), fy1 = floor((vd + rd) / st.tile_h);
+        // clamp into the grid before converting (values can be far outside it)
+        x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.grid_w);
+        y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.grid_h);
+        x1 = (int)fmax(fmin(fx1, (double)(cam.grid_w - 1)), -1.0);
+        y1 = (int)fmax(fmin(fy1, (double)(cam.grid_h - 1)), -1.0);
+    }
+    const uint64_t dbits = (uint64_t)__float_as_uint(depth[r]);
+    int64_t off = offsets[r];
+    bool overflow = false;
+    for (int ty = y0; ty <= y1; ++ty) {
+        const uint64_t row = (uint64_t)cam.tile_off + (uint64_t)ty * cam.grid_w;
+        for (int tx = x0; tx <= x1; ++tx) {
+            if (off < capacity) {
+                keys[off] = ((row + tx) << 32) | dbits;
+                vals[off] = (uint32_t)r;
+            } else {
+                overflow = true;
+            }
+            ++off;
+        }
+    }
+    if (overflow) atomicOr(flags, FLAG_CAPACITY);
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8 bits per pass
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t live_count(int64_t K, const uint64_t* K_dev) {
+    if (!K_dev) return K;
+    const uint64_t k = *K_dev;
+    return (int64_t)(k < (uint64_t)K ? k : (uint64_t)K);
+}
+
+__global__ void __launch_bounds__(NT) radix_upsweep_kernel(const uint64_t* __restrict__ keys, int64_t Kcap,
+                                                            const uint64_t* __restrict__ K_dev, int shift,
+                                                            uint32_t* __restrict__ hist, int64_t nb) {
+    __shared__ uint32_t h[NT / 64][RADIX];
+    const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&h[0][0])[i] = 0u;
+    __syncthreads();
+    const int64_t K = live_count(Kcap, K_dev);
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+#pragma unroll 4
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        if (i < K) {
+            const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
+            atomicAdd(&h[w][d], 1u);
+        }
+    }
+    __syncthreads();
+    const int d = threadIdx.x;  // NT == RADIX
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += h[i][d];
+    hist[(int64_t)d * nb + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(NT) radix_downsweep_kernel(
+    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint64_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
+    const uint32_t* __restrict__ hist_scan, int64_t nb) {
+    __shared__ uint64_t sk[TILE];
+    __shared__ uint32_t sv[TILE];
+    __shared__ uint32_t wcnt[NT / 64][RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t gstart[RADIX];
+    __shared__ uint32_t scan_sh[NT / 64];
+
+    const int64_t K = live_count(Kcap, K_dev);
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    if (base >= K) return;  // uniform over the block
+    const int nvalid = (int)min((int64_t)TILE, K - base);
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
+    __syncthreads();
+
+    // wave w owns the contiguous span [w * 1024, (w + 1) * 1024) of the block;
+    // round j covers 64 consecutive items, lane l the (j * 64 + l)-th
+    uint64_t key[IPT];
+    uint32_t val[IPT];
+    uint32_t rank[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const int li = w * (IPT * 64) + j * 64 + lane;
+        if (li < nvalid) {
+            key[j] = keys_in[base + li];
+            val[j] = vals_in[base + li];
+        } else {
+            key[j] = ~0ull;  // digit 255 at every shift, ranked after every valid item
+            val[j] = 0u;
+        }
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (RADIX - 1);
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t before = wcnt[w][d];
+        rank[j] = before + (uint32_t)__popcll(peers & lt);
+        const int leader = __ffsll((long long)peers) - 1;
+        if (lane == leader) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of each wave, block total, then block-wide digit starts
+    {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            const uint32_t c = wcnt[i][d];
+            wcnt[i][d] = run;
+            run += c;
+        }
+        uint32_t tot;
+        dstart[d] = block_exclusive_scan(run, scan_sh, &tot);
+        gstart[d] = hist_scan[(int64_t)d * nb + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) {
+        const uint32_t d = (uint32_t)(key[j] >> shift) & (RADIX - 1);
+        const uint32_t pos = dstart[d] + wcnt[w][d] + rank[j];
+        sk[pos] = key[j];
+        sv[pos] = val[j];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nvalid; i += NT) {
+        const uint64_t k = sk[i];
+        const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
+        const uint32_t o = gstart[d] + (uint32_t)i - dstart[d];
+        keys_out[o] = k;
+        vals_out[o] = sv[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile ranges, fills, sums
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t* __restrict__ keys, int64_t Kcap,
+                                                           const uint64_t* __restrict__ K_dev,
+                                                           uint2* __restrict__ ranges) {
+    const int64_t K = live_count(Kcap, K_dev);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t t = (uint32_t)(keys[k] >> 32);
+    if (k == 0) {
+        ranges[t].x = 0;
+    } else {
+        const uint32_t p = (uint32_t)(keys[k - 1] >> 32);
+        if (p != t) {
+            ranges[p].y = (uint32_t)k;
+            ranges[t].x = (uint32_t)k;
+        }
+    }
+    if (k == K - 1) ranges[t].y = (uint32_t)K;
+}
+
+__global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) fill_f32_kernel(float* __restrict__ p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(NT) sum_i32_partial_kernel(const int32_t* __restrict__ in, int64_t n,
+                                                              uint64_t* __restrict__ partial) {
+    __shared__ uint64_t sh[NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    uint64_t s = 0;
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) s += (uint64_t)(int64_t)in[i];
+    }
+    s = wave_inclusive_scan(s);
+    if (lane_id() == 63) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < NT / 64; ++i) t += sh[i];
+        partial[blockIdx.x] = t;
+    }
+}
+
+inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n) { return (size_t)(nblocks(n) + 1) * sizeof(uint64_t) + 256; }
+
+void launch_scan_u32(hipStream_t stream, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total_dev,
+                     void* scratch) {
+    const int64_t nb = nblocks(n);
+    uint64_t* partial = reinterpret_cast<uint64_t*>(scratch);
+    if (n == 0) {
+        if (total_dev) hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial, (int64_t)0,
+                                          total_dev);
+        return;
+    }
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, in, n, partial);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial, nb, total_dev);
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, in, n,
+                       (const uint64_t*)partial, out);
+}
+
+void launch_duplicate(hipStream_t stream, const float* rec, const float* radius, const float* depth,
+                      const uint32_t* tiles, const uint32_t* offsets, int64_t n_records, int64_t n_per_view,
+                      const ViewSet& views, const DevSettings& st, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                      uint32_t* flags) {
+    if (n_records == 0) return;
+    hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n_records + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const float4*>(rec), radius, depth, tiles, offsets, n_records, n_per_view,
+                       views, st, keys, vals, capacity, flags);
+}
+
+size_t sort_scratch_bytes(int64_t K) {
+    const int64_t nb = nblocks(K > 0 ? K : 1);
+    const int64_t hist = nb * RADIX;
+    return (size_t)hist * sizeof(uint32_t) * 2 + scan_scratch_bytes(hist) + 1024;
+}
+
+void launch_radix_sort(hipStream_t stream, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                       int64_t K, const uint64_t* K_dev, int key_bits, void* scratch, bool* out_in_alt) {
+    *out_in_alt = false;
+    if (K <= 1 && !K_dev) return;
+    const int64_t nb = nblocks(K > 0 ? K : 1);
+    const int64_t hn = nb * RADIX;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
+    uint32_t* hist_scan = hist + hn;
+    char* scan_tmp = reinterpret_cast<char*>(hist_scan + hn);
+    scan_tmp = reinterpret_cast<char*>(((uintptr_t)scan_tmp + 255) & ~(uintptr_t)255);
+    uint64_t* kin = keys;
+    uint32_t* vin = vals;
+    uint64_t* kout = keys_alt;
+    uint32_t* vout = vals_alt;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(radix_upsweep_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift, hist,
+                           nb);
+        launch_scan_u32(stream, hist, hn, hist_scan, nullptr, scan_tmp);
+        hipLaunchKernelGGL(radix_downsweep_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout, K,
+                           K_dev, shift, (const uint32_t*)hist_scan, nb);
+        uint64_t* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+        *out_in_alt = !*out_in_alt;
+    }
+}
+
+void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, const uint64_t* K_dev,
+                        int64_t total_tiles, uint32_t* ranges) {
+    launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
+    if (K == 0) return;
+    hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K, K_dev,
+                       reinterpret_cast<uint2*>(ranges));
+}
+
+void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+}
+
+void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+}
+
+void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch) {
+    const int64_t nb = nblocks(n > 0 ? n : 1);
+    uint64_t* partial = reinterpret_cast<uint64_t*>(scratch);
+    hipLaunchKernelGGL(sum_i32_partial_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, in, n, partial);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial, nb, out_dev);
+}
+
+}  // namespace mgs

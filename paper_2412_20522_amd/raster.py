@@ -1,0 +1,160 @@
+"""Rasterizer objects and the differentiable masked rasterization op.
+
+``MaskedRasterize`` is the torch.autograd.Function of MaskGaussian's
+training step (Sec. 3.3-3.5): it samples hard masks from two scores per
+Gaussian with a straight-through Gumbel-Softmax, renders with masked
+compositing (Eq. 3-4), and in backward returns gradients for every Gaussian
+parameter and for the scores, through dL/dM (Eq. 6) and the mask-count loss
+(Eq. 7-8).  Transmittance is recomputed in reverse inside the backward
+kernel; nothing per pixel beyond the final transmittance and the last
+blended entry is kept.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import maskgs as M
+
+PARAM_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def image_sizes(cams: Sequence[dict]):
+    return [(int(c["height"]), int(c["width"])) for c in cams]
+
+
+def total_pixels(cams: Sequence[dict]) -> int:
+    return sum(h * w for h, w in image_sizes(cams))
+
+
+def split_views(flat: torch.Tensor, cams: Sequence[dict]):
+    """Packed [3 * P] images -> list of [3, H, W] views (views, no copy)."""
+    out, off = [], 0
+    for h, w in image_sizes(cams):
+        out.append(flat[off:off + 3 * h * w].view(3, h, w))
+        off += 3 * h * w
+    return out
+
+
+@dataclass
+class Grads:
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logits: torch.Tensor
+    sh: torch.Tensor
+    masks: torch.Tensor
+
+
+class Rasterizer:
+    """A library context plus a pool of frames on one device."""
+
+    def __init__(self, device: int = 0, **settings):
+        self.device = device
+        self.ctx = M.mgs_create(device)
+        self.settings = M.settings_struct(**settings)
+        self._free_frames = []
+
+    def __del__(self):
+        try:
+            for f in self._free_frames:
+                M.mgs_frame_destroy(f)
+            M.mgs_destroy(self.ctx)
+        except Exception:
+            pass
+
+    def set(self, **settings) -> None:
+        for k, v in settings.items():
+            if k == "bg":
+                for i in range(3):
+                    self.settings.bg[i] = float(v[i])
+            else:
+                setattr(self.settings, k, type(getattr(self.settings, k))(v))
+
+    def acquire_frame(self):
+        return self._free_frames.pop() if self._free_frames else M.mgs_frame_create(self.ctx)
+
+    def release_frame(self, frame) -> None:
+        self._free_frames.append(frame)
+
+    # -- plain calls -------------------------------------------------------
+    def forward(self, frame, params: dict, masks: torch.Tensor, cams: Sequence[dict],
+                images: Optional[torch.Tensor] = None, t_final: Optional[torch.Tensor] = None) -> torch.Tensor:
+        dev = params["means"].device
+        if images is None:
+            images = torch.empty(3 * total_pixels(cams), dtype=torch.float32, device=dev)
+        g = M.gaussians_struct(*(params[k] for k in PARAM_KEYS), masks)
+        M.mgs_forward(self.ctx, frame, g, cams, self.settings, images, t_final)
+        return images
+
+    def backward(self, frame, params: dict, dl_dimages: torch.Tensor, out: Optional[Grads] = None) -> Grads:
+        if out is None:
+            out = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS),
+                        torch.empty(params["means"].shape[0], dtype=torch.float32, device=params["means"].device))
+        gr = M.gradients_struct(out.means, out.log_scales, out.quats, out.opacity_logits, out.sh, out.masks)
+        M.mgs_backward(self.ctx, frame, dl_dimages.contiguous(), gr)
+        return out
+
+    def count_evals(self, frame) -> int:
+        return M.mgs_frame_count_evals(self.ctx, frame)
+
+    def stats(self, frame) -> dict:
+        return M.mgs_frame_get_stats(frame)
+
+    def sample_masks(self, scores: torch.Tensor, tau: float, seed: int, step: int):
+        n = scores.shape[0]
+        m = torch.empty(n, dtype=torch.float32, device=scores.device)
+        y = torch.empty_like(m)
+        M.mgs_sample_masks(self.ctx, scores.contiguous(), tau, seed, step, m, y)
+        return m, y
+
+
+class MaskedRasterize(torch.autograd.Function):
+    """images, mask_loss = MaskedRasterize.apply(means, log_scales, quats,
+    opacity_logits, sh, mask_scores, rasterizer, cams, tau, seed, step)
+
+    images is the packed [3 * P] rendering of all views; mask_loss is
+    (mean M)^2 (Eq. 7) so a caller forms L = L_render + lambda_m * mask_loss
+    (Eq. 8).  The hard masks are available as ``rasterizer.last_masks``.
+    """
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, mask_scores, rasterizer: Rasterizer,
+                cams, tau: float, seed: int, step: int):
+        params = {"means": means.detach().contiguous(), "log_scales": log_scales.detach().contiguous(),
+                  "quats": quats.detach().contiguous(), "opacity_logits": opacity_logits.detach().contiguous(),
+                  "sh": sh.detach().contiguous()}
+        m_hard, y_soft = rasterizer.sample_masks(mask_scores.detach(), tau, seed, step)
+        frame = rasterizer.acquire_frame()
+        images = rasterizer.forward(frame, params, m_hard, cams)
+        mask_loss = (m_hard.sum(dtype=torch.float64) / max(m_hard.numel(), 1)).square().to(torch.float32)
+        ctx.rasterizer = rasterizer
+        ctx.frame = frame
+        ctx.params = params
+        ctx.tau = tau
+        ctx.save_for_backward(m_hard, y_soft)
+        rasterizer.last_masks = m_hard
+        return images, mask_loss
+
+    @staticmethod
+    def backward(ctx, dl_dimages, dl_dmask_loss):
+        m_hard, y_soft = ctx.saved_tensors
+        r: Rasterizer = ctx.rasterizer
+        if dl_dimages is None:
+            n_px = M.mgs_frame_get_stats(ctx.frame)["n_pixels"]
+            dl_dimages = torch.zeros(3 * n_px, dtype=torch.float32, device=m_hard.device)
+        g = r.backward(ctx.frame, ctx.params, dl_dimages.contiguous())
+        r.release_frame(ctx.frame)
+        ctx.frame = None
+        lam = float(dl_dmask_loss) if dl_dmask_loss is not None else 0.0
+        d_scores = torch.empty(m_hard.shape[0], 2, dtype=torch.float32, device=m_hard.device)
+        M.mgs_mask_grad(r.ctx, g.masks, m_hard, y_soft, ctx.tau, lam, d_scores)
+        return g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, d_scores, None, None, None, None, None
+
+
+def masked_rasterize(params: dict, mask_scores: torch.Tensor, rasterizer: Rasterizer, cams, tau: float = 0.5,
+                     seed: int = 0, step: int = 0):
+    return MaskedRasterize.apply(params["means"], params["log_scales"], params["quats"], params["opacity_logits"],
+                                 params["sh"], mask_scores, rasterizer, cams, tau, seed, step)

@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point the header declares, and rejects bad arguments on the host before
+touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "maskgs.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"MGS_API\s+[\w\s\*]+?\b(mgs_\w+)\s*\(", txt)))
+
+
+def _lib():
+    from paper_2412_20522_amd import maskgs
+    return maskgs
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("mgs_create", "mgs_forward", "mgs_backward", "mgs_project", "mgs_sort", "mgs_composite_forward",
+                 "mgs_composite_backward", "mgs_project_backward", "mgs_sample_masks", "mgs_mask_grad",
+                 "mgs_adam_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    M = _lib()
+    raw = C.CDLL(M.LIB_PATH)
+    for name in _declared():
+        assert hasattr(raw, name), name
+    # and the binding wraps every declared symbol under the same name
+    assert set(_declared()) == set(M.EXPORTED)
+
+
+def test_default_settings_and_version():
+    M = _lib()
+    s = M.mgs_default_settings()
+    assert (s.tile_w, s.tile_h, s.batch_depth) == (16, 16, 256)
+    assert abs(s.alpha_min - 1 / 255) < 1e-9 and abs(s.alpha_max - 0.99) < 1e-7
+    assert abs(s.t_min - 1e-4) < 1e-10 and s.q_max == 9.0
+    assert M.mgs_version() >= 100
+
+
+def test_struct_layouts_match_header():
+    M = _lib()
+    assert C.sizeof(M.mgs_camera) == 16 * 4 + 4 * 4 + 2 * 4
+    assert C.sizeof(M.mgs_settings) == 4 * 4 + 8 * 4 + 3 * 4 + 4 * 4
+    assert C.sizeof(M.mgs_gaussians) == 6 * 8 + 8
+
+
+def test_host_validation_without_device():
+    M = _lib()
+    L = M.lib()
+    # NULL context / NULL outputs are rejected before any device call
+    assert L.mgs_create(0, None) == 1
+    assert L.mgs_frame_create(None, None) == 1
+    assert L.mgs_scan(None, None, None, 0, None, None, None) == 1
+    assert L.mgs_sort(None, None, None, None, 0, 40, None, None, None) == 1
+    assert L.mgs_sample_masks(None, None, None, 0, 0.5, 0, 0, None, None) == 1
+    assert L.mgs_default_settings(None) == 1
+    assert L.mgs_scan_scratch_bytes(10_000) > 0
+    assert L.mgs_sort_scratch_bytes(1_000_000) > L.mgs_sort_scratch_bytes(1000)
+
+
+def test_create_fails_cleanly_without_gfx950():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    M = _lib()
+    with pytest.raises(M.MaskGSError):
+        M.mgs_create(0)
+    assert M.mgs_last_error(None)

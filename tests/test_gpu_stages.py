@@ -1,0 +1,302 @@
+"""Stage-wise parity of the HIP path with the FP64 oracle.
+
+Each stage runs on the GPU through its C-ABI entry point; the oracle stage
+runs on the GPU's own upstream outputs widened exactly to FP64.  Integer
+stages (tile counts, scan, keys, sort order, ranges, last blended entry,
+entries examined) must match bit for bit; compositing within 1e-5 of the
+image scale; gradients within 2e-3 relative.  Pixels whose discrete
+decisions the oracle flags as within a relative margin of a threshold are
+left out of element-wise checks (and the Gaussians they touch out of the
+element-wise gradient checks); norm-wise checks include everything.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    M = U.M()
+    c = M.mgs_create(0)
+    yield c
+    M.mgs_destroy(c)
+
+
+def _scene(kind):
+    if kind == "tiny":
+        return scenegen.tiny_scene()
+    if kind == "ragged_sh3":
+        return scenegen.small_scene(3000, 150, 90, seed=101, sh_degree=3, log_scale_mean=-2.6)
+    if kind == "ragged_sh1":
+        return scenegen.small_scene(2500, 97, 61, seed=102, sh_degree=1, log_scale_mean=-2.4)
+    if kind == "multiview":
+        s = scenegen.small_scene(2000, 80, 60, seed=103, sh_degree=2, log_scale_mean=-2.5, n_views=3)
+        s["cameras"][1] = scenegen.orbit_camera(4.0, 35.0, 8.0, 50, 72)
+        s["cameras"][2] = scenegen.orbit_camera(3.5, -60.0, -12.0, 33, 29)
+        return s
+    raise KeyError(kind)
+
+
+def _run_stages(ctx, scene, cams, bg=(0.0, 0.0, 0.0), **kw):
+    deg = scene["sh_degree"]
+    ost, gst = U.settings_pair(sh_degree=deg, bg=bg, **kw)
+    dev = U.to_device(scene)
+    n = scene["means"].shape[0]
+    rec, depth, radius, tiles = U.gpu_project(ctx, dev, cams, gst)
+    offsets, K, keys, vals, ranges = U.gpu_lists(ctx, rec, depth, radius, tiles, n, cams, gst)
+    oi = U.oracle_inputs_from_rec(rec)
+    widths = [c["width"] for c in cams]
+    heights = [c["height"] for c in cams]
+    valid = (radius.cpu().numpy() > 0).astype(np.uint8)
+    olists = oracle.build_lists(widths, heights, n, oi["mean2d"], radius.cpu().numpy().astype(np.float64),
+                                U.u32(depth), valid, ost)
+    return dict(ost=ost, gst=gst, dev=dev, n=n, rec=rec, depth=depth, radius=radius, tiles=tiles, offsets=offsets,
+                K=K, keys=keys, vals=vals, ranges=ranges, oi=oi, olists=olists, widths=widths, heights=heights,
+                masks=scene["masks"].astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+def test_project_matches_oracle(ctx, kind):
+    s = _scene(kind)
+    cams = s["cameras"]
+    ost, gst = U.settings_pair(sh_degree=s["sh_degree"])
+    dev = U.to_device(s)
+    rec, depth, radius, tiles = U.gpu_project(ctx, dev, cams, gst)
+    n = s["means"].shape[0]
+    rec = rec.cpu().numpy().astype(np.float64)
+    for v, cam in enumerate(cams):
+        pr = oracle.project(s, cam, ost)
+        sl = slice(v * n, (v + 1) * n)
+        gvalid = radius.cpu().numpy()[sl] > 0
+        assert np.array_equal(gvalid, pr.valid.astype(bool))
+        # depth keys agree bit for bit end to end
+        assert np.array_equal(U.u32(depth)[sl][gvalid], pr.depth_bits[gvalid])
+        r = rec[sl][gvalid]
+        np.testing.assert_allclose(r[:, 0:2], pr.mean2d[gvalid], rtol=0, atol=2e-4 * max(cam["width"], 1) / 100)
+        scale = np.abs(pr.conic[gvalid]).max(axis=1, keepdims=True)
+        np.testing.assert_allclose(r[:, 2:5] / scale, pr.conic[gvalid] / scale, rtol=0, atol=5e-5)
+        np.testing.assert_allclose(r[:, 5], pr.opacity[gvalid], rtol=2e-6)
+        np.testing.assert_allclose(r[:, 8:11], pr.color[gvalid], rtol=0, atol=5e-6)
+        np.testing.assert_array_equal(r[:, 6], s["masks"][gvalid])
+        # integer radii: FP32 and FP64 ceil may differ only when 3 sqrt(lambda) is within rounding of an integer
+        mism = np.count_nonzero(radius.cpu().numpy()[sl][gvalid] != pr.radius[gvalid])
+        assert mism <= max(1, gvalid.sum() // 10000), mism
+
+
+def test_tiles_and_lists_match_oracle_bitwise(ctx):
+    for kind in ["tiny", "ragged_sh3", "multiview"]:
+        s = _scene(kind)
+        for tw, th in [(16, 16), (8, 8), (32, 8)]:
+            r = _run_stages(ctx, s, s["cameras"], tile_w=tw, tile_h=th)
+            ol = r["olists"]
+            assert np.array_equal(U.u32(r["tiles"]).astype(np.int64), ol.tiles_touched)
+            assert r["K"] == ol.keys.size
+            assert np.array_equal(U.u64(r["keys"]), ol.keys)
+            assert np.array_equal(U.u32(r["vals"]), ol.vals)
+            assert np.array_equal(U.u32(r["ranges"]).reshape(-1, 2), ol.ranges)
+
+
+# ---------------------------------------------------------------------------
+# scan and sort on synthetic inputs (bit-exact against the definitions)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [0, 1, 7, 4095, 4096, 4097, 123457])
+def test_scan_matches_cumsum(ctx, n):
+    rng = np.random.default_rng(n)
+    a = rng.integers(0, 300, n).astype(np.uint32)
+    inp = torch.from_numpy(a.view(np.int32)).cuda()
+    out = torch.full((max(n, 1),), -1, dtype=torch.int32, device="cuda")
+    total = torch.zeros(1, dtype=torch.int64, device="cuda")
+    U.M().mgs_scan(ctx, inp, out[:n], total)
+    torch.cuda.synchronize()
+    want = np.concatenate([[0], np.cumsum(a.astype(np.uint64))[:-1]]) if n else np.zeros(0)
+    assert np.array_equal(U.u32(out[:n]).astype(np.uint64), want.astype(np.uint64))
+    assert int(total.item()) == int(a.astype(np.uint64).sum())
+
+
+@pytest.mark.parametrize("K,bits", [(2, 40), (4096, 38), (4097, 46), (100_001, 47), (300_000, 64)])
+def test_sort_is_stable_and_matches_lexsort(ctx, K, bits):
+    rng = np.random.default_rng(K)
+    tiles = rng.integers(0, 1 << max(bits - 32, 0), K, dtype=np.uint64) if bits > 32 else np.zeros(K, np.uint64)
+    depth = rng.integers(0, 1 << 31, K, dtype=np.uint64)
+    depth[::7] = depth[0]  # many equal keys: order must follow the input
+    keys = (tiles << np.uint64(32)) | depth
+    if bits == 64:
+        keys = rng.integers(0, 2 ** 63, K, dtype=np.uint64) * np.uint64(2) + (keys & np.uint64(1))
+        keys[::5] = keys[1]
+    vals = np.arange(K, dtype=np.uint32)
+    kt = torch.from_numpy(keys.view(np.int64)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    U.M().mgs_sort(ctx, kt, vt, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(U.u64(kt), keys[order])
+    assert np.array_equal(U.u32(vt), vals[order])
+
+
+# ---------------------------------------------------------------------------
+# compositing, stage-wise
+# ---------------------------------------------------------------------------
+
+SHAPES = [(16, 16, 1, 1, 256), (16, 16, 2, 4, 128), (16, 16, 4, 4, 64), (8, 8, 1, 1, 32), (16, 8, 2, 1, 256),
+          (32, 8, 4, 2, 128)]
+
+
+def _oracle_fwd(r):
+    oi = r["oi"]
+    return oracle.render_fwd(r["widths"], r["heights"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
+                             r["masks"], r["olists"], r["ost"])
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_composite_forward_matches_oracle(ctx, kind, shape):
+    tw, th, fppt, bppt, batch = shape
+    s = _scene(kind)
+    bg = (0.0, 0.0, 0.0) if kind == "tiny" else (0.3, 0.5, 0.7)
+    r = _run_stages(ctx, s, s["cameras"], bg=bg, tile_w=tw, tile_h=th, fwd_ppt=fppt, bwd_ppt=bppt,
+                    batch_depth=batch)
+    img, tfin, last, exam = U.gpu_composite_fwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"])
+    of = _oracle_fwd(r)
+    ok = of.flags == 0
+    P = ok.size
+    assert ok.mean() > 0.99
+    gi = img.cpu().numpy().astype(np.float64).reshape(-1)
+    scale = max(np.abs(of.image).max(), 1.0)
+    # images: per pixel, 3 channels (channel planes are per view; compare through a pixel mask)
+    pix_mask = np.zeros(3 * P, bool)
+    off = 0
+    for w, h in zip(r["widths"], r["heights"]):
+        p = w * h
+        m = ok[off:off + p]
+        pix_mask[3 * off:3 * off + 3 * p] = np.tile(m, 3)
+        off += p
+    err = np.abs(gi - of.image)[pix_mask].max()
+    assert err <= 1e-5 * scale, err
+    assert np.abs(tfin.cpu().numpy() - of.t_final)[ok].max() <= 1e-5
+    assert np.array_equal(last.cpu().numpy()[ok], of.last[ok])
+    assert np.array_equal(exam.cpu().numpy()[ok], of.examined[ok])
+    assert U.rel_err(gi, of.image) <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_composite_backward_matches_oracle(ctx, kind, shape):
+    tw, th, fppt, bppt, batch = shape
+    s = _scene(kind)
+    bg = (0.0, 0.0, 0.0) if kind == "tiny" else (0.3, 0.5, 0.7)
+    r = _run_stages(ctx, s, s["cameras"], bg=bg, tile_w=tw, tile_h=th, fwd_ppt=fppt, bwd_ppt=bppt,
+                    batch_depth=batch)
+    img, tfin, last, exam = U.gpu_composite_fwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"])
+    P = tfin.numel()
+    rng = np.random.default_rng(7)
+    dl = rng.normal(size=3 * P).astype(np.float32)
+    dl_t = torch.from_numpy(dl).cuda()
+    d_rec, d_masks = U.gpu_composite_bwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"], tfin, last,
+                                         dl_t, r["n"])
+    oi = r["oi"]
+    ob = oracle.render_bwd(r["widths"], r["heights"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
+                           r["masks"], r["olists"], dl.astype(np.float64), r["ost"])
+    g = d_rec.cpu().numpy().astype(np.float64)
+    ex = ob.touched_flagged.astype(bool)
+    U.assert_grad_close(g[:, 0:2], ob.d_mean2d, ex, name="mean2d")
+    U.assert_grad_close(g[:, 2:5], ob.d_conic, ex, name="conic")
+    U.assert_grad_close(g[:, 5], ob.d_opacity, ex, name="opacity")
+    U.assert_grad_close(g[:, 6:9], ob.d_color, ex, name="color")
+    n = r["n"]
+    exg = ex.reshape(-1, n).any(axis=0)
+    U.assert_grad_close(d_masks.cpu().numpy(), ob.d_mask, exg, name="mask")
+    # masked Gaussians receive a mask gradient and nothing else
+    masked = r["masks"] == 0
+    gm = g.reshape(-1, n, 9)[:, masked, :]
+    assert np.all(gm == 0.0)
+    assert np.count_nonzero(d_masks.cpu().numpy()[masked]) > 0
+
+
+def test_project_backward_matches_oracle(ctx):
+    for kind in ["tiny", "ragged_sh3", "multiview"]:
+        s = _scene(kind)
+        cams = s["cameras"]
+        ost, gst = U.settings_pair(sh_degree=s["sh_degree"])
+        dev = U.to_device(s)
+        n = s["means"].shape[0]
+        R = n * len(cams)
+        rng = np.random.default_rng(11)
+        d_rec = rng.normal(size=(R, 9)) * np.array([1.0, 1.0, 50.0, 50.0, 50.0, 0.5, 0.3, 0.3, 0.3])
+        d_rec_t = torch.from_numpy(d_rec.astype(np.float32)).cuda()
+        out = {k: torch.full_like(dev[k], 9.0) for k in U.PARAM_KEYS}
+        gr = U.M().gradients_struct(out["means"], out["log_scales"], out["quats"], out["opacity_logits"], out["sh"])
+        U.M().mgs_project_backward(ctx, U.gstruct(dev), cams, gst, d_rec_t, gr)
+        torch.cuda.synchronize()
+        dr = d_rec.astype(np.float32).astype(np.float64)
+        og = oracle.project_bwd(s, cams, ost, dr[:, 0:2], dr[:, 2:5], dr[:, 5], dr[:, 6:9])
+        for k, o in [("means", og.means), ("log_scales", og.log_scales), ("quats", og.quats),
+                     ("opacity_logits", og.opacity_logits), ("sh", og.sh)]:
+            U.assert_grad_close(out[k].cpu().numpy().astype(np.float64), o, name=f"{kind}:{k}")
+
+
+# ---------------------------------------------------------------------------
+# masks, loss, optimiser
+# ---------------------------------------------------------------------------
+
+def test_sample_masks_match_oracle(ctx):
+    rng = np.random.default_rng(3)
+    n = 200_003
+    scores = rng.normal(size=(n, 2)).astype(np.float32)
+    st = torch.from_numpy(scores).cuda()
+    m = torch.empty(n, device="cuda")
+    y = torch.empty(n, device="cuda")
+    for seed, step in [(0, 0), (2412, 17), (2 ** 40 + 5, 2 ** 33 + 1)]:
+        U.M().mgs_sample_masks(ctx, st, 0.5, seed, step, m, y)
+        torch.cuda.synchronize()
+        om, oy = oracle.sample_masks(scores, 0.5, seed, step)
+        assert np.array_equal(m.cpu().numpy().astype(np.float64), om)
+        np.testing.assert_allclose(y.cpu().numpy(), oy, rtol=0, atol=1e-7)
+
+
+def test_mask_grad_l1_and_adam_match_oracle(ctx):
+    rng = np.random.default_rng(4)
+    n = 50_001
+    dM = rng.normal(size=n).astype(np.float32)
+    mh = (rng.uniform(size=n) < 0.7).astype(np.float32)
+    y = rng.uniform(0.01, 0.99, n).astype(np.float32)
+    d = torch.empty(n, 2, device="cuda")
+    lm = torch.zeros(1, device="cuda")
+    U.M().mgs_mask_grad(ctx, torch.from_numpy(dM).cuda(), torch.from_numpy(mh).cuda(), torch.from_numpy(y).cuda(),
+                        0.5, 0.1, d, lm)
+    torch.cuda.synchronize()
+    od, olm = oracle.mask_grad(dM, mh, y, 0.5, 0.1)
+    np.testing.assert_allclose(d.cpu().numpy(), od, rtol=2e-6, atol=1e-9)
+    assert abs(lm.item() - olm) <= 1e-6 * olm
+    img = rng.uniform(size=30_000).astype(np.float32)
+    tgt = rng.uniform(size=30_000).astype(np.float32)
+    tgt[:10] = img[:10]
+    di = torch.empty(30_000, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    U.M().mgs_l1_loss_grad(ctx, torch.from_numpy(img).cuda(), torch.from_numpy(tgt).cuda(), di, loss)
+    torch.cuda.synchronize()
+    ol, od = oracle.l1_loss(img.astype(np.float64), tgt)
+    assert np.array_equal(di.cpu().numpy().astype(np.float64), od.astype(np.float32).astype(np.float64))
+    assert abs(loss.item() - ol) <= 1e-6 * ol
+    p = rng.normal(size=1000).astype(np.float32)
+    pt = torch.from_numpy(p.copy()).cuda()
+    mt = torch.zeros(1000, device="cuda")
+    vt = torch.zeros(1000, device="cuda")
+    po = p.astype(np.float64)
+    m1, m2 = np.zeros(1000), np.zeros(1000)
+    for step in range(1, 4):
+        g = rng.normal(size=1000).astype(np.float32)
+        U.M().mgs_adam_step(ctx, pt, torch.from_numpy(g).cuda(), mt, vt, 1e-2, 0.9, 0.999, 1e-15, step)
+        oracle.adam(po, g.astype(np.float64), m1, m2, 1e-2, 0.9, 0.999, 1e-15, step)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(pt.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
