@@ -1,0 +1,295 @@
+#!/usr/bin/env python
+"""Throughput of masked forward + backward rasterization on one MI355X.
+
+A step is one pass of the hot path over one batch of synthetic input:
+straight-through Gumbel mask sampling, projection, tile counts, scan, key
+duplication, radix sort, tile ranges, masked compositing, L1 loss gradient,
+masked backward compositing, projection backward and the mask-score
+gradient.  The default workload is the batched multi-view case: a
+1M-Gaussian unbounded scene (SH degree 3, heavy-tailed scales) rendered for
+8 views of uneven size in one call ("batched"), compared with 8 single-view
+calls ("plain").
+
+metric: Gaussian-pixel evaluations per second, counting for every pixel the
+sorted entries its 16x16 tile list presents up to and including its stop
+entry (the forward evaluations; each has a backward counterpart).
+
+Prints one JSON line.  --gpus N > 1 is rejected: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU lane-slots per Gaussian-pixel evaluation, counted from the formulas
+# (each add, multiply, fused multiply-add, compare or select is one slot; exp
+# and reciprocal are quarter rate and count four).
+SLOTS_FILTER = 16      # dx, dy, Q, cut, exp, o*G, clamp, alpha filter
+SLOTS_BLEND = 9        # M*a, test, stop compare, weight, 3 colour FMAs, T
+SLOTS_BWD_VISIBLE = 44  # T recovery (rcp), X, dL/dM, dL/dc, dL/do, dL/dQ, dL/du,dv, conic, b update
+SLOTS_BWD_MASKED = 11   # X with T unchanged, dL/dM
+PEAK_SLOTS = 256 * 64 * 2.4e9   # 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_workload(name: str):
+    import scenegen
+    if name == "batched":
+        s = scenegen.batched_scene()
+        desc = "batched: 1M-Gaussian unbounded scene (SH3, heavy-tailed scales), 8 uneven views in one call"
+    elif name == "unbounded":
+        s = scenegen.unbounded_scene()
+        desc = "unbounded: 1.5M Gaussians (SH3, heavy-tailed scales), one 1264x832 view"
+    elif name == "object":
+        s = scenegen.object_scene()
+        desc = "object: 200k Gaussians in 64 clusters (SH3), one 800x800 view"
+    elif name == "tiny":
+        s = scenegen.tiny_scene()
+        desc = "tiny: 4096 Gaussians (SH0), one 128x128 view"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return s, desc
+
+
+def stage_roofline(stage: str, ms_per_launch: float, counts: dict, frame_stats: dict, n: int, views: int,
+                   sh_deg: int):
+    """Algorithmic work of one launch of `stage` and its roofline."""
+    t = ms_per_launch * 1e-3
+    K = frame_stats["n_instances"]
+    R = frame_stats["n_records"]
+    P = frame_stats["n_pixels"]
+    k3 = 3 * (sh_deg + 1) ** 2
+    if stage == "composite_bwd":
+        vis = counts["blended"] - counts["blended_masked"]
+        work = SLOTS_FILTER * counts["bwd_examined"] + SLOTS_BWD_VISIBLE * vis + SLOTS_BWD_MASKED * counts[
+            "blended_masked"]
+        return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                    frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
+    if stage == "composite_fwd":
+        work = SLOTS_FILTER * counts["examined"] + SLOTS_BLEND * counts["blended"]
+        return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                    frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
+    if stage == "sort":
+        passes = frame_stats["sort_passes"]
+        byt = 24 * K * passes
+    elif stage == "project":
+        byt = n * 4 * (11 + k3 + 1) + R * (48 + 12)
+    elif stage == "project_bwd":
+        byt = n * 4 * (11 + k3) + R * 36 + n * 4 * (10 + k3)
+    elif stage == "duplicate":
+        byt = R * 16 + K * 12
+    elif stage == "scan":
+        byt = R * 8
+    else:
+        byt = P * 16
+    return dict(bound="hbm", achieved=byt / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=byt / t / PEAK_HBM,
+                algorithmic=byt, algorithmic_unit="bytes")
+
+
+def cpu_baseline(scene: dict, cam_index: int, tau: float, seed: int, step: int) -> dict:
+    """The FP64 oracle on one view of the same workload (bounded sample)."""
+    import oracle
+    oracle.lib()
+    cam = scene["cameras"][cam_index]
+    ost = oracle.RasterSettings(sh_degree=scene["sh_degree"])
+    m, _ = oracle.sample_masks(scene["mask_scores"], tau, seed, step)
+    tgt = [scene["targets"][cam_index]]
+    t0 = time.perf_counter()
+    out = oracle.run_pipeline(scene, [cam], m, ost, targets=tgt)
+    dt = time.perf_counter() - t0
+    evals = int(out.fwd.examined.sum())
+    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"view {cam_index} ({cam['width']}x{cam['height']}) of the same scene, full masked "
+                      f"fwd+bwd through projection backward, FP64, {evals} evals in {dt:.1f} s",
+            "views_per_s": 1.0 / dt, "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched", choices=["batched", "unbounded", "object", "tiny"])
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--batch-depth", type=int, default=256)
+    ap.add_argument("--fwd-ppt", type=int, default=1)
+    ap.add_argument("--bwd-ppt", type=int, default=4)
+    ap.add_argument("--persistent", type=int, default=1)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    from paper_2412_20522_amd import maskgs as M
+    from paper_2412_20522_amd.raster import PARAM_KEYS, Grads, Rasterizer
+
+    t_gen = time.perf_counter()
+    scene, desc = build_workload(args.workload)
+    log(f"[bench] generated {scene['name']} in {time.perf_counter() - t_gen:.1f} s")
+    cams = scene["cameras"]
+    V = len(cams)
+    n = scene["means"].shape[0]
+    deg = scene["sh_degree"]
+    tau = float(scene.get("gumbel_tau", 0.5))
+    lambda_m, seed, step_id = 0.1, 2412, 0
+    dev = torch.device("cuda:0")
+    params = {k: torch.from_numpy(np.ascontiguousarray(scene[k], np.float32)).to(dev) for k in PARAM_KEYS}
+    scores = torch.from_numpy(scene["mask_scores"]).to(dev)
+    P = sum(c["width"] * c["height"] for c in cams)
+    targets = torch.cat([torch.from_numpy(t.reshape(-1)) for t in scene["targets"]]).to(dev)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    rast = Rasterizer(0, sh_degree=deg, tile_w=tw, tile_h=th, batch_depth=args.batch_depth, fwd_ppt=args.fwd_ppt,
+                      bwd_ppt=args.bwd_ppt, persistent=args.persistent)
+    ctx = rast.ctx
+    frame = rast.acquire_frame()
+    images = torch.empty(3 * P, device=dev)
+    d_img = torch.empty_like(images)
+    loss = torch.zeros(1, device=dev)
+    loss_m = torch.zeros(1, device=dev)
+    grads = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS), torch.empty(n, device=dev))
+    d_scores = torch.empty(n, 2, device=dev)
+    m_hard = torch.empty(n, device=dev)
+    y_soft = torch.empty(n, device=dev)
+    red_scratch = torch.empty(int(M.lib().mgs_reduce_scratch_bytes(3 * P)), dtype=torch.uint8, device=dev)
+
+    def batched_step():
+        M.mgs_sample_masks(ctx, scores, tau, seed, step_id, m_hard, y_soft)
+        rast.forward(frame, params, m_hard, cams, images=images)
+        M.mgs_l1_loss_grad(ctx, images, targets, d_img, loss, red_scratch)
+        rast.backward(frame, params, d_img, out=grads)
+        M.mgs_mask_grad(ctx, grads.masks, m_hard, y_soft, tau, lambda_m, d_scores, loss_m, red_scratch)
+
+    # the evaluation count at 16x16 tiles (the numerator), untimed
+    rast.set(tile_w=16, tile_h=16, fwd_ppt=1, bwd_ppt=4, persistent=0)
+    M.mgs_sample_masks(ctx, scores, tau, seed, step_id, m_hard, y_soft)
+    rast.forward(frame, params, m_hard, cams, images=images)
+    counts16 = rast.count_evals(frame)
+    E16 = counts16["examined"]
+    rast.set(tile_w=tw, tile_h=th, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt, persistent=args.persistent)
+    log(f"[bench] E16 = {E16:.4e} evals per step ({V} views, {P} pixels, {n} Gaussians)")
+
+    for _ in range(args.warmup):
+        batched_step()
+    torch.cuda.synchronize()
+    counts = rast.count_evals(frame)
+    fstats = rast.stats(frame)
+    M.mgs_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched_step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    prof = M.mgs_profile_read(ctx)
+    M.mgs_profile_enable(ctx, False)
+    log(f"[bench] batched: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}")
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    for k, v in prof.items():
+        if v[1]:
+            log(f"[bench]   {k:14s} {v[0] / v[1]:9.3f} ms/launch x {v[1] // args.steps}")
+    dom = max(stage_ms, key=lambda k: prof[k][0])
+    roof = stage_roofline(dom, stage_ms[dom], counts, fstats, n, V, deg)
+    roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof, "traffic": None}
+
+    plain = None
+    if not args.no_plain and V > 1:
+        rast_p = Rasterizer(0, sh_degree=deg, tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=1, bwd_ppt=4,
+                            persistent=0)
+        fr = rast_p.acquire_frame()
+        offs = np.cumsum([0] + [3 * c["width"] * c["height"] for c in cams])
+
+        def plain_step():
+            M.mgs_sample_masks(rast_p.ctx, scores, tau, seed, step_id, m_hard, y_soft)
+            for v, c in enumerate(cams):
+                im = images[offs[v]:offs[v + 1]]
+                dv = d_img[offs[v]:offs[v + 1]]
+                rast_p.forward(fr, params, m_hard, [c], images=im)
+                M.mgs_l1_loss_grad(rast_p.ctx, im, targets[offs[v]:offs[v + 1]], dv, loss, red_scratch)
+                rast_p.backward(fr, params, dv, out=grads)
+            M.mgs_mask_grad(rast_p.ctx, grads.masks, m_hard, y_soft, tau, lambda_m, d_scores, loss_m, red_scratch)
+
+        for _ in range(max(1, args.warmup // 2)):
+            plain_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.plain_steps):
+            plain_step()
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / args.plain_steps
+        plain = {"ms_per_step": pms, "evals_per_s": E16 / (pms * 1e-3), "views_per_s": V / (pms * 1e-3)}
+        log(f"[bench] plain: {pms:.3f} ms/step")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on one view ...")
+        cpu = cpu_baseline(scene, 0, tau, seed, step_id)
+        log(f"[bench] oracle: {cpu['seconds']:.1f} s for one view on {cpu['cores']} threads")
+
+    value = E16 / (ms_step * 1e-3)
+    out = {
+        "metric": "masked fwd+bwd Gaussian-pixel evals/s and views/s, batched vs plain, at oracle tol",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "gaussians": n,
+            "views": V,
+            "pixels": P,
+            "evals_per_step_16x16": E16,
+            "instances": fstats["n_instances"],
+            "views_per_s": V / (ms_step * 1e-3),
+            "tile": args.tile,
+            "batch_depth": args.batch_depth,
+            "fwd_ppt": args.fwd_ppt,
+            "bwd_ppt": args.bwd_ppt,
+            "persistent": bool(args.persistent),
+            "plain": plain,
+            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if prof[k][1]},
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

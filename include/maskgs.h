@@ -180,10 +180,48 @@ MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_ga
 MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float* dl_dimages,
                                 const mgs_gradients* grads);
 
-/* Number of list entries examined per pixel in the last forward, up to and
- * including each pixel's stop entry (the Gaussian-pixel evaluations of the
- * forward pass).  Writes the sum to *total (host).  Synchronises. */
-MGS_API mgs_status mgs_frame_count_evals(mgs_frame* frame, mgs_stream stream, int64_t* total);
+/* Gaussian-pixel work of the last forward on a frame, summed over pixels. */
+typedef struct {
+    int64_t examined;        /* entries examined in the forward, up to and including
+                                each pixel's stop entry (the forward evaluations) */
+    int64_t blended;         /* entries that passed the filters and were blended */
+    int64_t blended_masked;  /* ... of which with mask 0 */
+    int64_t bwd_examined;    /* entries the backward revisits: from the range start
+                                to each pixel's last blended entry */
+} mgs_eval_counts;
+
+/* Sums the per-pixel counts of the last forward into *out (host).
+ * Synchronises. */
+MGS_API mgs_status mgs_frame_count_evals(mgs_frame* frame, mgs_stream stream, mgs_eval_counts* out);
+
+/* ---------------------------------------------------------------------- */
+/* per-stage timing with HIP events on the caller's stream                 */
+/* ---------------------------------------------------------------------- */
+
+typedef enum {
+    MGS_STAGE_PROJECT = 0,
+    MGS_STAGE_SCAN,
+    MGS_STAGE_DUPLICATE,
+    MGS_STAGE_SORT,
+    MGS_STAGE_RANGES,
+    MGS_STAGE_COMPOSITE_FWD,
+    MGS_STAGE_COMPOSITE_BWD,
+    MGS_STAGE_PROJECT_BWD,
+    MGS_STAGE_SAMPLE_MASKS,
+    MGS_STAGE_MASK_GRAD,
+    MGS_STAGE_LOSS,
+    MGS_STAGE_ADAM,
+    MGS_NUM_STAGES
+} mgs_stage;
+
+/* While enabled, every launch of a stage on ctx is bracketed by two HIP
+ * events recorded on the launch stream.  Enabling clears earlier records. */
+MGS_API mgs_status mgs_profile_enable(mgs_ctx* ctx, int on);
+
+/* Waits for the recorded events, writes per stage the summed elapsed
+ * milliseconds ms[MGS_NUM_STAGES] and launch counts launches[MGS_NUM_STAGES]
+ * (host arrays), and clears the records.  Synchronises on the events. */
+MGS_API mgs_status mgs_profile_read(mgs_ctx* ctx, double* ms, int64_t* launches);
 
 /* ---------------------------------------------------------------------- */
 /* stages, for stage-wise checking; all buffers caller-owned               */

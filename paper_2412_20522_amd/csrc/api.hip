@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -19,9 +20,58 @@ struct mgs_ctx {
     int device = 0;
     int num_cus = 256;
     std::string err;
+    // per-stage timing
+    bool prof_on = false;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> prof;
+    std::vector<hipEvent_t> pool;
+    ~mgs_ctx() {
+        for (auto& r : prof) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t take_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
 };
 
 namespace {
+
+// Brackets the launches of one stage with two events while profiling is on.
+struct StageTimer {
+    mgs_ctx* ctx;
+    hipStream_t stream;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageTimer(mgs_ctx* c, hipStream_t s, int st) : ctx(c), stream(s), stage(st) {
+        if (ctx && ctx->prof_on) {
+            a = ctx->take_event();
+            if (a) (void)hipEventRecord(a, stream);
+        }
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = ctx->take_event();
+        if (!b) {
+            ctx->pool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, stream);
+        ctx->prof.push_back({stage, a, b});
+    }
+};
 
 thread_local std::string g_create_error;
 
@@ -210,7 +260,7 @@ struct mgs_frame {
     int sort_passes = 0, tile_bits = 0;
     bool sorted_in_alt = false;
     // device buffers
-    DevBuf rec, depth, radius, tiles, offsets, keys, vals, keys_alt, vals_alt, ranges, t_final, last, examined;
+    DevBuf rec, depth, radius, tiles, offsets, keys, vals, keys_alt, vals_alt, ranges, t_final, last, stats;
     DevBuf d_rec, d_masks_tmp, scan_tmp, sort_tmp, misc, queue, sum_tmp;
     uint64_t* h_pinned = nullptr;  // K, flags read-back
     uint64_t* keys_sorted() { return (uint64_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
@@ -295,7 +345,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&f->rec, &f->depth, &f->radius, &f->tiles, &f->offsets, &f->keys, &f->vals, &f->keys_alt,
-                      &f->vals_alt, &f->ranges, &f->t_final, &f->last, &f->examined, &f->d_rec, &f->d_masks_tmp,
+                      &f->vals_alt, &f->ranges, &f->t_final, &f->last, &f->stats, &f->d_rec, &f->d_masks_tmp,
                       &f->scan_tmp, &f->sort_tmp, &f->misc, &f->queue, &f->sum_tmp};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
@@ -345,13 +395,19 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) || (s = grow(ctx, f->ranges, (size_t)f->total_tiles * 8)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
-        (s = grow(ctx, f->examined, (size_t)P * 4)) || (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(R))) ||
+        (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(R))) ||
         (s = grow(ctx, f->queue, 256)))
         return s;
     launch_fill_u32(stream, f->flags(), 2, 0u);
-    launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
-                       (uint32_t*)f->tiles.p, f->flags());
-    launch_scan_u32(stream, (const uint32_t*)f->tiles.p, R, (uint32_t*)f->offsets.p, f->total(), f->scan_tmp.p);
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_PROJECT);
+        launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
+                           (uint32_t*)f->tiles.p, f->flags());
+    }
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_SCAN);
+        launch_scan_u32(stream, (const uint32_t*)f->tiles.p, R, (uint32_t*)f->offsets.p, f->total(), f->scan_tmp.p);
+    }
     MGS_CHECK_LAUNCH(ctx);
     // the one synchronisation of the plain path: K sizes the sort
     MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 16, hipMemcpyDeviceToHost, stream));
@@ -367,16 +423,25 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))))
         return s;
     f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 8, f->vals.bytes / 4);
-    launch_duplicate(stream, (const float*)f->rec.p, (const float*)f->radius.p, (const float*)f->depth.p,
-                     (const uint32_t*)f->tiles.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
-                     (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
+        launch_duplicate(stream, (const float*)f->rec.p, (const float*)f->radius.p, (const float*)f->depth.p,
+                         (const uint32_t*)f->tiles.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
+                         (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
+    }
     const int key_bits = 32 + f->tile_bits;
-    f->sort_passes = (key_bits + 7) / 8;
+    f->sort_passes = f->K > 1 ? (key_bits + 7) / 8 : 0;
     bool in_alt = false;
-    launch_radix_sort(stream, (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, (uint64_t*)f->keys_alt.p,
-                      (uint32_t*)f->vals_alt.p, f->K, nullptr, key_bits, f->sort_tmp.p, &in_alt);
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_SORT);
+        launch_radix_sort(stream, (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, (uint64_t*)f->keys_alt.p,
+                          (uint32_t*)f->vals_alt.p, f->K, nullptr, key_bits, f->sort_tmp.p, &in_alt);
+    }
     f->sorted_in_alt = in_alt;
-    launch_tile_ranges(stream, f->keys_sorted(), f->K, nullptr, f->total_tiles, (uint32_t*)f->ranges.p);
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_RANGES);
+        launch_tile_ranges(stream, f->keys_sorted(), f->K, nullptr, f->total_tiles, (uint32_t*)f->ranges.p);
+    }
     uint32_t* queue = nullptr;
     int grid = 0;
     if (f->persistent) {
@@ -384,9 +449,12 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         launch_fill_u32(stream, queue, 1, 0u);
         grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
     }
-    launch_composite_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->vals_sorted(), (const uint32_t*)f->ranges.p,
-                         f->views, f->st, images, (float*)f->t_final.p, (int32_t*)f->last.p,
-                         (int32_t*)f->examined.p, queue, grid);
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
+        launch_composite_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->vals_sorted(),
+                             (const uint32_t*)f->ranges.p, f->views, f->st, images, (float*)f->t_final.p,
+                             (int32_t*)f->last.p, nullptr, (int32_t*)f->stats.p, queue, grid);
+    }
     MGS_CHECK_LAUNCH(ctx);
     if (t_final_out)
         MGS_HIP(ctx, hipMemcpyAsync(t_final_out, f->t_final.p, (size_t)P * 4, hipMemcpyDeviceToDevice, stream));
@@ -400,6 +468,8 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     hipStream_t stream = (hipStream_t)stream_;
     if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "mgs_backward without a preceding mgs_forward");
     if (!dl_dimages || !grads) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "d_quats must be 16-byte aligned");
     mgs_status s;
     if ((s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 4 + 4))) return s;
     float* d_masks = grads->d_masks;
@@ -407,36 +477,77 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         if ((s = grow(ctx, f->d_masks_tmp, (size_t)f->n * 4 + 4))) return s;
         d_masks = (float*)f->d_masks_tmp.p;
     }
-    launch_fill_f32(stream, (float*)f->d_rec.p, f->R * DREC, 0.f);
-    launch_fill_f32(stream, d_masks, f->n, 0.f);
     uint32_t* queue = nullptr;
     int grid = 0;
+    launch_fill_f32(stream, (float*)f->d_rec.p, f->R * DREC, 0.f);
+    launch_fill_f32(stream, d_masks, f->n, 0.f);
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
         grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
     }
-    launch_composite_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->vals_sorted(), (const uint32_t*)f->ranges.p,
-                         f->views, f->st, (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
-                         (float*)f->d_rec.p, d_masks, queue, grid);
-    launch_project_bwd(stream, f->g, f->views, f->st, (const float*)f->d_rec.p, *grads);
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_BWD);
+        launch_composite_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->vals_sorted(),
+                             (const uint32_t*)f->ranges.p, f->views, f->st, (const float*)f->t_final.p,
+                             (const int32_t*)f->last.p, dl_dimages, f->n, (float*)f->d_rec.p, d_masks, queue, grid);
+    }
+    {
+        StageTimer t(ctx, stream, MGS_STAGE_PROJECT_BWD);
+        launch_project_bwd(stream, f->g, f->views, f->st, (const float*)f->d_rec.p, *grads);
+    }
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }
 
-mgs_status mgs_frame_count_evals(mgs_frame* f, mgs_stream stream_, int64_t* total) {
-    if (!f || !total) return MGS_ERR_INVALID_ARG;
+mgs_status mgs_frame_count_evals(mgs_frame* f, mgs_stream stream_, mgs_eval_counts* out) {
+    if (!f || !out) return MGS_ERR_INVALID_ARG;
     mgs_ctx* ctx = f->ctx;
     hipStream_t stream = (hipStream_t)stream_;
     if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "no forward on this frame");
     mgs_status s;
-    if ((s = grow(ctx, f->sum_tmp, scan_scratch_bytes(f->P) + 64))) return s;
-    uint64_t* out = (uint64_t*)((char*)f->sum_tmp.p + scan_scratch_bytes(f->P));
-    launch_sum_i32(stream, (const int32_t*)f->examined.p, f->P, out, f->sum_tmp.p);
+    const size_t part = 4 * scan_scratch_bytes(f->P);
+    if ((s = grow(ctx, f->sum_tmp, part + 64))) return s;
+    uint64_t* dev = (uint64_t*)((char*)f->sum_tmp.p + part);
+    launch_sum_i32x4(stream, (const int32_t*)f->stats.p, f->P, dev, f->sum_tmp.p);
     MGS_CHECK_LAUNCH(ctx);
-    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned + 2, out, 8, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned + 2, dev, 32, hipMemcpyDeviceToHost, stream));
     MGS_HIP(ctx, hipStreamSynchronize(stream));
-    *total = (int64_t)f->h_pinned[2];
+    out->examined = (int64_t)f->h_pinned[2];
+    out->blended = (int64_t)f->h_pinned[3];
+    out->blended_masked = (int64_t)f->h_pinned[4];
+    out->bwd_examined = (int64_t)f->h_pinned[5];
+    return MGS_OK;
+}
+
+mgs_status mgs_profile_enable(mgs_ctx* ctx, int on) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    for (auto& r : ctx->prof) {
+        (void)hipEventSynchronize(r.b);
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->prof.clear();
+    ctx->prof_on = on != 0;
+    return MGS_OK;
+}
+
+mgs_status mgs_profile_read(mgs_ctx* ctx, double* ms, int64_t* launches) {
+    if (!ctx || !ms || !launches) return MGS_ERR_INVALID_ARG;
+    for (int i = 0; i < MGS_NUM_STAGES; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto& r : ctx->prof) {
+        MGS_HIP(ctx, hipEventSynchronize(r.b));
+        float e = 0.f;
+        MGS_HIP(ctx, hipEventElapsedTime(&e, r.a, r.b));
+        ms[r.stage] += e;
+        launches[r.stage] += 1;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->prof.clear();
     return MGS_OK;
 }
 
@@ -545,8 +656,9 @@ mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const float* r
     if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
     ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
     DevSettings ds = make_settings(st);
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_COMPOSITE_FWD);
     launch_composite_fwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->fwd_ppt}, rec, vals,
-                         ranges, vs, ds, images, t_final, last, examined, nullptr, 0);
+                         ranges, vs, ds, images, t_final, last, examined, nullptr, nullptr, 0);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }
@@ -564,6 +676,7 @@ mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* 
     if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
     ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
     DevSettings ds = make_settings(st);
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_COMPOSITE_BWD);
     launch_fill_f32((hipStream_t)stream, d_rec, n * n_views * DREC, 0.f);
     launch_fill_f32((hipStream_t)stream, d_masks, n, 0.f);
     launch_composite_bwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->bwd_ppt}, rec, vals, ranges,
@@ -601,6 +714,7 @@ mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores
     if (!(tau > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "tau must be > 0");
     if (n > 0 && (!scores || !m_hard || !y_soft)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (((uintptr_t)scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "scores must be 8-byte aligned");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_SAMPLE_MASKS);
     launch_sample_masks((hipStream_t)stream, scores, n, tau, seed, step, m_hard, y_soft);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
@@ -617,6 +731,7 @@ mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, 
     if (n > 0 && (!d_masks || !m_hard || !y_soft || !d_scores || !scratch))
         return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (((uintptr_t)d_scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "d_scores must be 8-byte aligned");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_MASK_GRAD);
     launch_mask_grad((hipStream_t)stream, d_masks, m_hard, y_soft, n, tau, lambda_m, d_scores, loss_m, scratch);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
@@ -628,6 +743,7 @@ mgs_status mgs_l1_loss_grad(mgs_ctx* ctx, mgs_stream stream, const float* images
     if (m < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "m < 0");
     if (m > 0 && (!images || !targets || !d_images || !scratch))
         return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_LOSS);
     launch_l1_loss_grad((hipStream_t)stream, images, targets, m, d_images, loss, scratch);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
@@ -638,6 +754,7 @@ mgs_status mgs_adam_step(mgs_ctx* ctx, mgs_stream stream, float* params, const f
     if (!ctx) return MGS_ERR_INVALID_ARG;
     if (n < 0 || step < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0 or step < 1");
     if (n > 0 && (!params || !grads || !m || !v)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_ADAM);
     launch_adam((hipStream_t)stream, params, grads, m, v, n, lr, beta1, beta2, eps, step);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;

@@ -78,7 +78,8 @@ template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
     const float4* __restrict__ rec, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
     ViewSet views, DevSettings st, float* __restrict__ images, float* __restrict__ t_final,
-    int32_t* __restrict__ last_out, int32_t* __restrict__ examined_out, uint32_t* __restrict__ queue) {
+    int32_t* __restrict__ last_out, int32_t* __restrict__ examined_out, int4* __restrict__ stats_out,
+    uint32_t* __restrict__ queue) {
     constexpr int NT = TW * TH / PPT;
     __shared__ float4 sA[MAXB], sB[MAXB], sC[MAXB];
     __shared__ uint32_t s_tile;
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
-        int last[PPT], stopk[PPT];
+        int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT];
         bool done[PPT], inside[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -103,6 +104,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
             C0[i] = C1[i] = C2[i] = 0.f;
             last[i] = -1;
             stopk[i] = -1;
+            nblend[i] = nmasked[i] = 0;
             done[i] = !inside[i];
         }
         const uint2 rg = ranges[tile];
@@ -144,6 +146,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
                     C2[i] += wgt * Cc.z;
                     T[i] = test;
                     last[i] = base + j;
+                    ++nblend[i];
+                    nmasked[i] += B.z == 0.f;
                 }
                 active = false;
 #pragma unroll
@@ -164,7 +168,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
             const int64_t p = (int64_t)cam.px_off + loc;
             if (t_final) t_final[p] = T[i];
             if (last_out) last_out[p] = last[i];
-            if (examined_out) examined_out[p] = stopk[i] >= 0 ? stopk[i] - start + 1 : end - start;
+            const int exam = stopk[i] >= 0 ? stopk[i] - start + 1 : end - start;
+            if (examined_out) examined_out[p] = exam;
+            if (stats_out) stats_out[p] = make_int4(exam, nblend[i], nmasked[i], last[i] >= 0 ? last[i] - start + 1 : 0);
         }
         if (!queue) break;
     }
@@ -305,10 +311,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
 template <int TW, int TH, int PPT>
 void launch_fwd_t(hipStream_t s, int grid, const float* rec, const uint32_t* vals, const uint32_t* ranges,
                   const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
-                  int32_t* examined, uint32_t* queue) {
+                  int32_t* examined, int32_t* stats, uint32_t* queue) {
     hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
                        reinterpret_cast<const float4*>(rec), vals, reinterpret_cast<const uint2*>(ranges), views, st,
-                       images, t_final, last, examined, queue);
+                       images, t_final, last, examined, reinterpret_cast<int4*>(stats), queue);
 }
 
 template <int TW, int TH, int PPT>
@@ -344,12 +350,14 @@ bool composite_config_supported(const CompositeConfig& c) {
 
 void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
                           const uint32_t* ranges, const ViewSet& views, const DevSettings& st, float* images,
-                          float* t_final, int32_t* last, int32_t* examined, uint32_t* queue, int grid_override) {
+                          float* t_final, int32_t* last, int32_t* examined, int32_t* stats, uint32_t* queue,
+                          int grid_override) {
     const int grid = grid_override > 0 ? grid_override : (int)views.total_tiles;
     if (grid == 0) return;
 #define MGS_FWD(A, B, P)                                                                                     \
     if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                \
-        launch_fwd_t<A, B, P>(stream, grid, rec, vals, ranges, views, st, images, t_final, last, examined, queue); \
+        launch_fwd_t<A, B, P>(stream, grid, rec, vals, ranges, views, st, images, t_final, last, examined, stats, \
+                              queue);                                                                        \
         return;                                                                                              \
     }
     MGS_COMPOSITE_SHAPES(MGS_FWD)

@@ -38,15 +38,21 @@ void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value)
 void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value);
 // Sum of n int32 values into a device u64 (deterministic).
 void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);
+// Column sums of an [n, 4] int32 array into out_dev[4] (u64); scratch holds
+// 4 * scan_scratch_bytes(n) bytes.
+void launch_sum_i32x4(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);
 
 // compositing
 struct CompositeConfig {
     int tile_w, tile_h, ppt;  // pixels per thread; threads per block = tile_w * tile_h / ppt
 };
 bool composite_config_supported(const CompositeConfig& c);
+// stats (optional) [P, 4] i32 per pixel: examined, blended, blended with mask
+// 0, entries up to the last blended one.
 void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
                           const uint32_t* ranges, const ViewSet& views, const DevSettings& st, float* images,
-                          float* t_final, int32_t* last, int32_t* examined, uint32_t* queue, int grid_override);
+                          float* t_final, int32_t* last, int32_t* examined, int32_t* stats, uint32_t* queue,
+                          int grid_override);
 void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
                           const uint32_t* ranges, const ViewSet& views, const DevSettings& st, const float* t_final,
                           const int32_t* last, const float* dl_dimages, int64_t n, float* d_rec, float* d_masks,

@@ -8,6 +8,13 @@
 // One thread per Gaussian loops over all views, so the 3D covariance and
 // the SH coefficients (up to 192 B) are read from HBM once per Gaussian
 // rather than once per view.
+//
+// The covariance chain (3D covariance, Jacobian, 2D covariance, its inverse,
+// and their derivatives) runs in double precision: needle-shaped Gaussians
+// (scale ratios of 1e4 and more) lose their thin direction in FP32 and can
+// produce a negative 2D determinant.  Vector FP64 runs at the lane rate of
+// non-packed FP32 on this chip, and these kernels are bound by HBM traffic.
+// Colours (SH) are FP32.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -110,78 +117,108 @@ __device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t g,
     }
 }
 
-// Rotation matrix of the normalised quaternion (w, x, y, z), row-major.
-__device__ __forceinline__ void quat_to_rot(float w, float x, float y, float z, float* R) {
-    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z);       R[2] = 2.f * (x * z + w * y);
-    R[3] = 2.f * (x * y + w * z);       R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
-    R[6] = 2.f * (x * z - w * y);       R[7] = 2.f * (y * z + w * x);       R[8] = 1.f - 2.f * (x * x + y * y);
+// Scale, rotation and 3D covariance of one Gaussian, in double.
+struct Cov3 {
+    double s[3];
+    double q[4];     // normalised (w, x, y, z)
+    double qinv;     // 1 / |q|
+    double R[9];     // rotation, row-major
+    double S[6];     // covariance entries 00, 01, 02, 11, 12, 22
+};
+
+__device__ __forceinline__ Cov3 cov3(const float* __restrict__ log_scales, const float* __restrict__ quats,
+                                     int64_t g) {
+    Cov3 c;
+    c.s[0] = exp((double)log_scales[3 * g]);
+    c.s[1] = exp((double)log_scales[3 * g + 1]);
+    c.s[2] = exp((double)log_scales[3 * g + 2]);
+    const float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+    const double qw = q4.x, qx = q4.y, qy = q4.z, qz = q4.w;
+    c.qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw * c.qinv, x = qx * c.qinv, y = qy * c.qinv, z = qz * c.qinv;
+    c.q[0] = w; c.q[1] = x; c.q[2] = y; c.q[3] = z;
+    c.R[0] = 1.0 - 2.0 * (y * y + z * z); c.R[1] = 2.0 * (x * y - w * z);       c.R[2] = 2.0 * (x * z + w * y);
+    c.R[3] = 2.0 * (x * y + w * z);       c.R[4] = 1.0 - 2.0 * (x * x + z * z); c.R[5] = 2.0 * (y * z - w * x);
+    c.R[6] = 2.0 * (x * z - w * y);       c.R[7] = 2.0 * (y * z + w * x);       c.R[8] = 1.0 - 2.0 * (x * x + y * y);
+    double M[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) M[3 * i + k] = c.R[3 * i + k] * c.s[k];
+    c.S[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    c.S[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    c.S[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    c.S[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    c.S[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    c.S[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+    return c;
 }
 
 struct ViewGeom {
     bool valid;
-    float tx, ty, tz;     // view-space centre (float32 of the double transform)
+    float depth;          // float32 of the double view-space z (sort key, cull test)
+    double tx, ty, tz;    // view-space centre
     float u, v;
-    float sx, sy;         // lateral ratios after clamping
+    double sx, sy;        // lateral ratios after clamping
     bool clx, cly;
-    float T0[3], T1[3];   // J W
-    float a, b, c;        // 2D covariance incl. dilation
-    float ca, cb, cc;     // conic
+    double T0[3], T1[3];  // J W
+    double a, b, c;       // 2D covariance incl. dilation
+    double ca, cb, cc;    // conic
     float radius;
 };
 
-// Per-view geometry of one Gaussian; Sig = 3D covariance (00,01,02,11,12,22).
+// Per-view geometry of one Gaussian.
 __device__ __forceinline__ ViewGeom view_geom(const DevView& cam, const DevSettings& st, float px, float py, float pz,
-                                              const float* Sig) {
+                                              const double* Sig) {
     ViewGeom o;
-    // view transform in double: products of two floats are exact, so the
-    // association ((W0 x + W1 y) + W2 z) + t fixes the result bit for bit
+    // products of two floats are exact in double, so the association
+    // ((W0 x + W1 y) + W2 z) + t fixes the depth key bit for bit
     const double xd = px, yd = py, zd = pz;
-    const double txd = (((double)cam.W[0] * xd + (double)cam.W[1] * yd) + (double)cam.W[2] * zd) + (double)cam.t[0];
-    const double tyd = (((double)cam.W[3] * xd + (double)cam.W[4] * yd) + (double)cam.W[5] * zd) + (double)cam.t[1];
-    const double tzd = (((double)cam.W[6] * xd + (double)cam.W[7] * yd) + (double)cam.W[8] * zd) + (double)cam.t[2];
-    o.tz = (float)tzd;
-    o.valid = o.tz > st.near_plane;
+    o.tx = (((double)cam.W[0] * xd + (double)cam.W[1] * yd) + (double)cam.W[2] * zd) + (double)cam.t[0];
+    o.ty = (((double)cam.W[3] * xd + (double)cam.W[4] * yd) + (double)cam.W[5] * zd) + (double)cam.t[1];
+    o.tz = (((double)cam.W[6] * xd + (double)cam.W[7] * yd) + (double)cam.W[8] * zd) + (double)cam.t[2];
+    o.depth = (float)o.tz;
+    o.valid = o.depth > st.near_plane;
     if (!o.valid) return o;
-    o.tx = (float)txd;
-    o.ty = (float)tyd;
-    o.u = (float)((double)cam.fx * txd / tzd + (double)cam.cx);
-    o.v = (float)((double)cam.fy * tyd / tzd + (double)cam.cy);
-    const float iz = 1.f / o.tz;
-    const float rx = o.tx * iz, ry = o.ty * iz;
-    o.clx = rx < -cam.limx || rx > cam.limx;
-    o.cly = ry < -cam.limy || ry > cam.limy;
-    o.sx = fminf(fmaxf(rx, -cam.limx), cam.limx);
-    o.sy = fminf(fmaxf(ry, -cam.limy), cam.limy);
-    const float J00 = cam.fx * iz, J02 = -cam.fx * o.sx * iz;
-    const float J11 = cam.fy * iz, J12 = -cam.fy * o.sy * iz;
+    const double fx = cam.fx, fy = cam.fy;
+    const double iz = 1.0 / o.tz;
+    o.u = (float)(fx * o.tx * iz + (double)cam.cx);
+    o.v = (float)(fy * o.ty * iz + (double)cam.cy);
+    const double limx = cam.limx, limy = cam.limy;
+    const double rx = o.tx * iz, ry = o.ty * iz;
+    o.clx = rx < -limx || rx > limx;
+    o.cly = ry < -limy || ry > limy;
+    o.sx = fmin(fmax(rx, -limx), limx);
+    o.sy = fmin(fmax(ry, -limy), limy);
+    const double J00 = fx * iz, J02 = -fx * o.sx * iz;
+    const double J11 = fy * iz, J12 = -fy * o.sy * iz;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        o.T0[j] = J00 * cam.W[j] + J02 * cam.W[6 + j];
-        o.T1[j] = J11 * cam.W[3 + j] + J12 * cam.W[6 + j];
+        o.T0[j] = J00 * (double)cam.W[j] + J02 * (double)cam.W[6 + j];
+        o.T1[j] = J11 * (double)cam.W[3 + j] + J12 * (double)cam.W[6 + j];
     }
-    // U = T Sigma (2x3)
-    const float S00 = Sig[0], S01 = Sig[1], S02 = Sig[2], S11 = Sig[3], S12 = Sig[4], S22 = Sig[5];
-    const float U00 = o.T0[0] * S00 + o.T0[1] * S01 + o.T0[2] * S02;
-    const float U01 = o.T0[0] * S01 + o.T0[1] * S11 + o.T0[2] * S12;
-    const float U02 = o.T0[0] * S02 + o.T0[1] * S12 + o.T0[2] * S22;
-    const float U10 = o.T1[0] * S00 + o.T1[1] * S01 + o.T1[2] * S02;
-    const float U11 = o.T1[0] * S01 + o.T1[1] * S11 + o.T1[2] * S12;
-    const float U12 = o.T1[0] * S02 + o.T1[1] * S12 + o.T1[2] * S22;
-    o.a = U00 * o.T0[0] + U01 * o.T0[1] + U02 * o.T0[2] + st.dilation;
+    const double S00 = Sig[0], S01 = Sig[1], S02 = Sig[2], S11 = Sig[3], S12 = Sig[4], S22 = Sig[5];
+    const double U00 = o.T0[0] * S00 + o.T0[1] * S01 + o.T0[2] * S02;
+    const double U01 = o.T0[0] * S01 + o.T0[1] * S11 + o.T0[2] * S12;
+    const double U02 = o.T0[0] * S02 + o.T0[1] * S12 + o.T0[2] * S22;
+    const double U10 = o.T1[0] * S00 + o.T1[1] * S01 + o.T1[2] * S02;
+    const double U11 = o.T1[0] * S01 + o.T1[1] * S11 + o.T1[2] * S12;
+    const double U12 = o.T1[0] * S02 + o.T1[1] * S12 + o.T1[2] * S22;
+    const double dil = st.dilation;
+    o.a = U00 * o.T0[0] + U01 * o.T0[1] + U02 * o.T0[2] + dil;
     o.b = U00 * o.T1[0] + U01 * o.T1[1] + U02 * o.T1[2];
-    o.c = U10 * o.T1[0] + U11 * o.T1[1] + U12 * o.T1[2] + st.dilation;
-    // determinant in double: one rounding instead of a float cancellation
-    const double det = (double)o.a * (double)o.c - (double)o.b * (double)o.b;
+    o.c = U10 * o.T1[0] + U11 * o.T1[1] + U12 * o.T1[2] + dil;
+    const double det = o.a * o.c - o.b * o.b;
     if (!(det > 0.0)) { o.valid = false; return o; }
-    const float idet = (float)(1.0 / det);
+    const double idet = 1.0 / det;
     o.ca = o.c * idet;
     o.cb = -o.b * idet;
     o.cc = o.a * idet;
-    const float mid = 0.5f * (o.a + o.c);
-    const float disc = fmaxf(st.lambda_floor, mid * mid - (float)det);
-    o.radius = ceilf(3.f * sqrtf(mid + sqrtf(disc)));
-    if (!(isfinite(o.u) && isfinite(o.v) && isfinite(o.ca) && isfinite(o.cb) && isfinite(o.cc) &&
-          isfinite(o.radius) && o.radius > 0.f))
+    const double mid = 0.5 * (o.a + o.c);
+    const double disc = fmax((double)st.lambda_floor, mid * mid - det);
+    o.radius = (float)ceil(3.0 * sqrt(mid + sqrt(disc)));
+    if (!(isfinite(o.u) && isfinite(o.v) && isfinite((float)o.ca) && isfinite((float)o.cb) &&
+          isfinite((float)o.cc) && isfinite(o.radius) && o.radius > 0.f))
         o.valid = false;
     return o;
 }
@@ -196,24 +233,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
-    const float s0 = __expf(log_scales[3 * g]), s1 = __expf(log_scales[3 * g + 1]), s2 = __expf(log_scales[3 * g + 2]);
-    const float4 q = reinterpret_cast<const float4*>(quats)[g];
-    const float qinv = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
-    float R[9];
-    quat_to_rot(q.x * qinv, q.y * qinv, q.z * qinv, q.w * qinv, R);
-    // Sigma = (R S)(R S)^T
-    float Sig[6];
-    {
-        const float M00 = R[0] * s0, M01 = R[1] * s1, M02 = R[2] * s2;
-        const float M10 = R[3] * s0, M11 = R[4] * s1, M12 = R[5] * s2;
-        const float M20 = R[6] * s0, M21 = R[7] * s1, M22 = R[8] * s2;
-        Sig[0] = M00 * M00 + M01 * M01 + M02 * M02;
-        Sig[1] = M00 * M10 + M01 * M11 + M02 * M12;
-        Sig[2] = M00 * M20 + M01 * M21 + M02 * M22;
-        Sig[3] = M10 * M10 + M11 * M11 + M12 * M12;
-        Sig[4] = M10 * M20 + M11 * M21 + M12 * M22;
-        Sig[5] = M20 * M20 + M21 * M21 + M22 * M22;
-    }
+    const Cov3 cv = cov3(log_scales, quats, g);
     const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
     const float mval = masks[g];
     float coef[3 * K];
@@ -222,14 +242,14 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     for (int vi = 0; vi < views.n_views; ++vi) {
         const DevView& cam = views.v[vi];
         const int64_t r = (int64_t)vi * n + g;
-        const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
+        const ViewGeom o = view_geom(cam, st, px, py, pz, cv.S);
         if (!o.valid) {
-            // culled, or non-finite geometry (flagged unless simply behind the near plane)
-            if (o.tz > st.near_plane) bad = true;
+            // culled; flagged as non-finite unless simply behind the near plane
+            if (o.depth > st.near_plane) bad = true;
             rec[3 * r] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[3 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[3 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
-            depth_out[r] = o.tz;
+            depth_out[r] = o.depth;
             radius_out[r] = 0.f;
             tiles_out[r] = 0;
             continue;
@@ -260,10 +280,10 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             x1 = fmin(x1, (double)(cam.grid_w - 1)); y1 = fmin(y1, (double)(cam.grid_h - 1));
             count = (x0 <= x1 && y0 <= y1) ? (uint32_t)((x1 - x0 + 1.0) * (y1 - y0 + 1.0)) : 0u;
         }
-        rec[3 * r] = make_float4(o.u, o.v, o.ca, o.cb);
-        rec[3 * r + 1] = make_float4(o.cc, opac, mval, 0.f);
+        rec[3 * r] = make_float4(o.u, o.v, (float)o.ca, (float)o.cb);
+        rec[3 * r + 1] = make_float4((float)o.cc, opac, mval, 0.f);
         rec[3 * r + 2] = make_float4(col[0], col[1], col[2], 0.f);
-        depth_out[r] = o.tz;
+        depth_out[r] = o.depth;
         radius_out[r] = o.radius;
         tiles_out[r] = count;
     }
@@ -280,31 +300,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
-    const float s[3] = {__expf(log_scales[3 * g]), __expf(log_scales[3 * g + 1]), __expf(log_scales[3 * g + 2])};
-    const float4 q = reinterpret_cast<const float4*>(quats)[g];
-    const float qn2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
-    const float qinv = rsqrtf(qn2);
-    const float qw = q.x * qinv, qx = q.y * qinv, qy = q.z * qinv, qz = q.w * qinv;
-    float R[9];
-    quat_to_rot(qw, qx, qy, qz, R);
-    float Sig[6];
-    {
-        const float M00 = R[0] * s[0], M01 = R[1] * s[1], M02 = R[2] * s[2];
-        const float M10 = R[3] * s[0], M11 = R[4] * s[1], M12 = R[5] * s[2];
-        const float M20 = R[6] * s[0], M21 = R[7] * s[1], M22 = R[8] * s[2];
-        Sig[0] = M00 * M00 + M01 * M01 + M02 * M02;
-        Sig[1] = M00 * M10 + M01 * M11 + M02 * M12;
-        Sig[2] = M00 * M20 + M01 * M21 + M02 * M22;
-        Sig[3] = M10 * M10 + M11 * M11 + M12 * M12;
-        Sig[4] = M10 * M20 + M11 * M21 + M12 * M22;
-        Sig[5] = M20 * M20 + M21 * M21 + M22 * M22;
-    }
+    const Cov3 cv = cov3(log_scales, quats, g);
     const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
     float coef[3 * K];
     load_sh<DEG>(sh, g, coef);
 
-    float gS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // dL/dSigma (full-matrix gradient, symmetric entries)
-    float gp[3] = {0.f, 0.f, 0.f};
+    double gS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma3 (symmetric full-matrix gradient)
+    double gp[3] = {0.0, 0.0, 0.0};
     float gop = 0.f;
     float gsh[3 * K];
 #pragma unroll
@@ -313,10 +315,10 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     for (int vi = 0; vi < views.n_views; ++vi) {
         const DevView& cam = views.v[vi];
         const int64_t r = (int64_t)vi * n + g;
-        const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
+        const ViewGeom o = view_geom(cam, st, px, py, pz, cv.S);
         if (!o.valid) continue;
         const float* dr = d_rec + r * DREC;
-        const float du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
+        const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
         gop += dr[5];
         // colour: SH coefficients and viewing direction
         float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
@@ -355,14 +357,14 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             gp[2] += (dd[2] - proj * dz) * dinv;
         }
         // conic -> 2D covariance: H = -Conic Gc Conic, Gc = [[dca, dcb/2], [dcb/2, dcc]]
-        const float hb = 0.5f * dcb;
-        const float X00 = o.ca * dca + o.cb * hb, X01 = o.ca * hb + o.cb * dcc;
-        const float X10 = o.cb * dca + o.cc * hb, X11 = o.cb * hb + o.cc * dcc;
-        const float H00 = -(X00 * o.ca + X01 * o.cb);
-        const float H01 = -(X00 * o.cb + X01 * o.cc);
-        const float H11 = -(X10 * o.cb + X11 * o.cc);
-        // dSigma += T^T H T ; dT = 2 H T Sigma
-        float HT0[3], HT1[3];
+        const double hb = 0.5 * dcb;
+        const double X00 = o.ca * dca + o.cb * hb, X01 = o.ca * hb + o.cb * dcc;
+        const double X10 = o.cb * dca + o.cc * hb, X11 = o.cb * hb + o.cc * dcc;
+        const double H00 = -(X00 * o.ca + X01 * o.cb);
+        const double H01 = -(X00 * o.cb + X01 * o.cc);
+        const double H11 = -(X10 * o.cb + X11 * o.cc);
+        // dSigma3 += T^T H T ; dT = 2 H T Sigma3
+        double HT0[3], HT1[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             HT0[j] = H00 * o.T0[j] + H01 * o.T1[j];
@@ -374,81 +376,88 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         gS[3] += o.T0[1] * HT0[1] + o.T1[1] * HT1[1];
         gS[4] += o.T0[1] * HT0[2] + o.T1[1] * HT1[2];
         gS[5] += o.T0[2] * HT0[2] + o.T1[2] * HT1[2];
-        float dT0[3], dT1[3];
-        dT0[0] = 2.f * (HT0[0] * Sig[0] + HT0[1] * Sig[1] + HT0[2] * Sig[2]);
-        dT0[1] = 2.f * (HT0[0] * Sig[1] + HT0[1] * Sig[3] + HT0[2] * Sig[4]);
-        dT0[2] = 2.f * (HT0[0] * Sig[2] + HT0[1] * Sig[4] + HT0[2] * Sig[5]);
-        dT1[0] = 2.f * (HT1[0] * Sig[0] + HT1[1] * Sig[1] + HT1[2] * Sig[2]);
-        dT1[1] = 2.f * (HT1[0] * Sig[1] + HT1[1] * Sig[3] + HT1[2] * Sig[4]);
-        dT1[2] = 2.f * (HT1[0] * Sig[2] + HT1[1] * Sig[4] + HT1[2] * Sig[5]);
+        const double* S = cv.S;
+        double dT0[3], dT1[3];
+        dT0[0] = 2.0 * (HT0[0] * S[0] + HT0[1] * S[1] + HT0[2] * S[2]);
+        dT0[1] = 2.0 * (HT0[0] * S[1] + HT0[1] * S[3] + HT0[2] * S[4]);
+        dT0[2] = 2.0 * (HT0[0] * S[2] + HT0[1] * S[4] + HT0[2] * S[5]);
+        dT1[0] = 2.0 * (HT1[0] * S[0] + HT1[1] * S[1] + HT1[2] * S[2]);
+        dT1[1] = 2.0 * (HT1[0] * S[1] + HT1[1] * S[3] + HT1[2] * S[4]);
+        dT1[2] = 2.0 * (HT1[0] * S[2] + HT1[1] * S[4] + HT1[2] * S[5]);
         // T = J W  ->  dJ = dT W^T (only J00, J02, J11, J12 are variables)
-        const float dJ00 = dT0[0] * cam.W[0] + dT0[1] * cam.W[1] + dT0[2] * cam.W[2];
-        const float dJ02 = dT0[0] * cam.W[6] + dT0[1] * cam.W[7] + dT0[2] * cam.W[8];
-        const float dJ11 = dT1[0] * cam.W[3] + dT1[1] * cam.W[4] + dT1[2] * cam.W[5];
-        const float dJ12 = dT1[0] * cam.W[6] + dT1[1] * cam.W[7] + dT1[2] * cam.W[8];
+        const double W0 = cam.W[0], W1 = cam.W[1], W2 = cam.W[2], W3 = cam.W[3], W4 = cam.W[4], W5 = cam.W[5];
+        const double W6 = cam.W[6], W7 = cam.W[7], W8 = cam.W[8];
+        const double dJ00 = dT0[0] * W0 + dT0[1] * W1 + dT0[2] * W2;
+        const double dJ02 = dT0[0] * W6 + dT0[1] * W7 + dT0[2] * W8;
+        const double dJ11 = dT1[0] * W3 + dT1[1] * W4 + dT1[2] * W5;
+        const double dJ12 = dT1[0] * W6 + dT1[1] * W7 + dT1[2] * W8;
         // view-space centre
-        const float iz = 1.f / o.tz, iz2 = iz * iz;
-        float dtx = du * cam.fx * iz;
-        float dty = dv * cam.fy * iz;
-        float dtz = -(du * cam.fx * o.tx + dv * cam.fy * o.ty) * iz2;
-        dtz += -(dJ00 * cam.fx + dJ11 * cam.fy) * iz2;
+        const double fx = cam.fx, fy = cam.fy;
+        const double iz = 1.0 / o.tz, iz2 = iz * iz;
+        double dtx = du * fx * iz;
+        double dty = dv * fy * iz;
+        double dtz = -(du * fx * o.tx + dv * fy * o.ty) * iz2;
+        dtz += -(dJ00 * fx + dJ11 * fy) * iz2;
         if (!o.clx) {
-            dtx += -dJ02 * cam.fx * iz2;
-            dtz += dJ02 * 2.f * cam.fx * o.tx * iz2 * iz;
+            dtx += -dJ02 * fx * iz2;
+            dtz += dJ02 * 2.0 * fx * o.tx * iz2 * iz;
         } else {
-            dtz += dJ02 * cam.fx * o.sx * iz2;
+            dtz += dJ02 * fx * o.sx * iz2;
         }
         if (!o.cly) {
-            dty += -dJ12 * cam.fy * iz2;
-            dtz += dJ12 * 2.f * cam.fy * o.ty * iz2 * iz;
+            dty += -dJ12 * fy * iz2;
+            dtz += dJ12 * 2.0 * fy * o.ty * iz2 * iz;
         } else {
-            dtz += dJ12 * cam.fy * o.sy * iz2;
+            dtz += dJ12 * fy * o.sy * iz2;
         }
         // t = W p + t  ->  dp = W^T dt
-        gp[0] += cam.W[0] * dtx + cam.W[3] * dty + cam.W[6] * dtz;
-        gp[1] += cam.W[1] * dtx + cam.W[4] * dty + cam.W[7] * dtz;
-        gp[2] += cam.W[2] * dtx + cam.W[5] * dty + cam.W[8] * dtz;
+        gp[0] += W0 * dtx + W3 * dty + W6 * dtz;
+        gp[1] += W1 * dtx + W4 * dty + W7 * dtz;
+        gp[2] += W2 * dtx + W5 * dty + W8 * dtz;
     }
 
-    // Sigma = R diag(s^2) R^T with G = dL/dSigma (symmetric)
-    const float G[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
-    float GR[9];  // G R
+    // Sigma3 = R diag(s^2) R^T with G = dL/dSigma3 (symmetric)
+    const double G[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+    const double* R = cv.R;
+    double GR[9];  // G R
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) GR[3 * i + k] = G[3 * i] * R[k] + G[3 * i + 1] * R[3 + k] + G[3 * i + 2] * R[6 + k];
-    float dR[9];
+    double dR[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dR[3 * i + k] = 2.f * GR[3 * i + k] * s[k] * s[k];
-    float dls[3];
+        for (int k = 0; k < 3; ++k) dR[3 * i + k] = 2.0 * GR[3 * i + k] * cv.s[k] * cv.s[k];
+    double dls[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float rgr = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];  // (R^T G R)_kk
-        dls[k] = 2.f * s[k] * s[k] * rgr;
+        const double rgr = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];  // (R^T G R)_kk
+        dls[k] = 2.0 * cv.s[k] * cv.s[k] * rgr;
     }
-    // rotation matrix -> normalised quaternion
-    const float gw = 2.f * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-    const float gx = 2.f * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.f * qx * dR[4] - qw * dR[5] + qz * dR[6] +
-                            qw * dR[7] - 2.f * qx * dR[8]);
-    const float gy = 2.f * (-2.f * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
-                            qz * dR[7] - 2.f * qy * dR[8]);
-    const float gz = 2.f * (-2.f * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.f * qz * dR[4] +
-                            qy * dR[5] + qx * dR[6] + qy * dR[7]);
-    const float dotq = qw * gw + qx * gx + qy * gy + qz * gz;
+    // rotation matrix -> normalised quaternion -> raw quaternion
+    const double qw = cv.q[0], qx = cv.q[1], qy = cv.q[2], qz = cv.q[3];
+    const double gw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+    const double gx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                             qw * dR[7] - 2.0 * qx * dR[8]);
+    const double gy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                             qz * dR[7] - 2.0 * qy * dR[8]);
+    const double gz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
+                             qy * dR[5] + qx * dR[6] + qy * dR[7]);
+    const double dotq = qw * gw + qx * gx + qy * gy + qz * gz;
     if (d_quats)
-        reinterpret_cast<float4*>(d_quats)[g] = make_float4((gw - qw * dotq) * qinv, (gx - qx * dotq) * qinv,
-                                                            (gy - qy * dotq) * qinv, (gz - qz * dotq) * qinv);
+        reinterpret_cast<float4*>(d_quats)[g] =
+            make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
+                        (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
     if (d_means) {
-        d_means[3 * g] = gp[0];
-        d_means[3 * g + 1] = gp[1];
-        d_means[3 * g + 2] = gp[2];
+        d_means[3 * g] = (float)gp[0];
+        d_means[3 * g + 1] = (float)gp[1];
+        d_means[3 * g + 2] = (float)gp[2];
     }
     if (d_log_scales) {
-        d_log_scales[3 * g] = dls[0];
-        d_log_scales[3 * g + 1] = dls[1];
-        d_log_scales[3 * g + 2] = dls[2];
+        d_log_scales[3 * g] = (float)dls[0];
+        d_log_scales[3 * g + 1] = (float)dls[1];
+        d_log_scales[3 * g + 2] = (float)dls[2];
     }
     if (d_opacity_logits) d_opacity_logits[g] = gop * opac * (1.f - opac);
     if (d_sh) {
@@ -465,16 +474,16 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     float4* rec4 = reinterpret_cast<float4*>(rec);
+#define MGS_PFWD(D)                                                                                                \
+    hipLaunchKernelGGL(project_fwd_kernel<D>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,          \
+                       g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags)
     switch (st.sh_degree) {
-        case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
-                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
-        case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
-                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
-        case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
-                                   g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
-        default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,
-                                    g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags); break;
+        case 0: MGS_PFWD(0); break;
+        case 1: MGS_PFWD(1); break;
+        case 2: MGS_PFWD(2); break;
+        default: MGS_PFWD(3); break;
     }
+#undef MGS_PFWD
 }
 
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,

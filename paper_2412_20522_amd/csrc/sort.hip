@@ -338,6 +338,34 @@ __global__ void __launch_bounds__(NT) sum_i32_partial_kernel(const int32_t* __re
     }
 }
 
+__global__ void __launch_bounds__(NT) sum_i32x4_partial_kernel(const int4* __restrict__ in, int64_t n,
+                                                                uint64_t* __restrict__ partial, int64_t nb) {
+    __shared__ uint64_t sh[4][NT / 64];
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    uint64_t s[4] = {0, 0, 0, 0};
+    for (int j = 0; j < IPT; ++j) {
+        const int64_t i = base + j * NT + threadIdx.x;
+        if (i < n) {
+            const int4 v = in[i];
+            s[0] += (uint64_t)(int64_t)v.x;
+            s[1] += (uint64_t)(int64_t)v.y;
+            s[2] += (uint64_t)(int64_t)v.z;
+            s[3] += (uint64_t)(int64_t)v.w;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t x = wave_inclusive_scan(s[c]);
+        if (lane_id() == 63) sh[c][threadIdx.x >> 6] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint64_t t = 0;
+        for (int i = 0; i < NT / 64; ++i) t += sh[threadIdx.x][i];
+        partial[threadIdx.x * nb + blockIdx.x] = t;
+    }
+}
+
 inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
 
 }  // namespace
@@ -417,6 +445,15 @@ void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value)
 void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value) {
     if (n <= 0) return;
     hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+}
+
+void launch_sum_i32x4(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch) {
+    const int64_t nb = nblocks(n > 0 ? n : 1);
+    uint64_t* partial = reinterpret_cast<uint64_t*>(scratch);
+    hipLaunchKernelGGL(sum_i32x4_partial_kernel, dim3((unsigned)nb), dim3(NT), 0, stream,
+                       reinterpret_cast<const int4*>(in), n, partial, nb);
+    for (int c = 0; c < 4; ++c)
+        hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial + c * nb, nb, out_dev + c);
 }
 
 void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch) {

@@ -53,6 +53,16 @@ class mgs_gradients(C.Structure):
                 ("d_opacity_logits", C.c_void_p), ("d_sh", C.c_void_p), ("d_masks", C.c_void_p)]
 
 
+class mgs_eval_counts(C.Structure):
+    _fields_ = [("examined", C.c_int64), ("blended", C.c_int64), ("blended_masked", C.c_int64),
+                ("bwd_examined", C.c_int64)]
+
+
+STAGES = ("project", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd", "project_bwd",
+          "sample_masks", "mask_grad", "loss", "adam")
+MGS_NUM_STAGES = len(STAGES)
+
+
 class mgs_frame_stats(C.Structure):
     _fields_ = [("n_gaussians", C.c_int64), ("n_views", C.c_int64), ("n_records", C.c_int64),
                 ("n_pixels", C.c_int64), ("n_instances", C.c_int64), ("total_tiles", C.c_int64),
@@ -73,7 +83,9 @@ _SIGS = {
     "mgs_forward": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                               C.POINTER(mgs_settings), _VP, _VP]),
     "mgs_backward": (C.c_int, [_VP, _VP, _VP, C.POINTER(mgs_gradients)]),
-    "mgs_frame_count_evals": (C.c_int, [_VP, _VP, C.POINTER(C.c_int64)]),
+    "mgs_frame_count_evals": (C.c_int, [_VP, _VP, C.POINTER(mgs_eval_counts)]),
+    "mgs_profile_enable": (C.c_int, [_VP, C.c_int]),
+    "mgs_profile_read": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mgs_project": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                               C.POINTER(mgs_settings), _VP, _VP, _VP, _VP]),
     "mgs_scan_scratch_bytes": (_SZ, [_I64]),
@@ -253,10 +265,22 @@ def mgs_backward(ctx, frame, dl_dimages: torch.Tensor, grads: mgs_gradients, str
     _check(ctx, _lib.mgs_backward(frame, _stream(stream), _ptr(dl_dimages, name="dl_dimages"), C.byref(grads)))
 
 
-def mgs_frame_count_evals(ctx, frame, stream=None) -> int:
-    out = C.c_int64()
+def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:
+    out = mgs_eval_counts()
     _check(ctx, _lib.mgs_frame_count_evals(frame, _stream(stream), C.byref(out)))
-    return int(out.value)
+    return {k: int(getattr(out, k)) for k, _ in mgs_eval_counts._fields_}
+
+
+def mgs_profile_enable(ctx, on: bool = True) -> None:
+    _check(ctx, _lib.mgs_profile_enable(ctx, 1 if on else 0))
+
+
+def mgs_profile_read(ctx) -> dict:
+    """{stage name: (total ms, launches)} since the last enable/read."""
+    ms = (C.c_double * MGS_NUM_STAGES)()
+    n = (C.c_int64 * MGS_NUM_STAGES)()
+    _check(ctx, _lib.mgs_profile_read(ctx, ms, n))
+    return {STAGES[i]: (float(ms[i]), int(n[i])) for i in range(MGS_NUM_STAGES)}
 
 
 def mgs_project(ctx, g: mgs_gaussians, cams, st, rec, depth, radius, tiles, stream=None) -> None:

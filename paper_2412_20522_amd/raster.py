@@ -97,7 +97,8 @@ class Rasterizer:
         M.mgs_backward(self.ctx, frame, dl_dimages.contiguous(), gr)
         return out
 
-    def count_evals(self, frame) -> int:
+    def count_evals(self, frame) -> dict:
+        """examined / blended / blended_masked / bwd_examined of the last forward."""
         return M.mgs_frame_count_evals(self.ctx, frame)
 
     def stats(self, frame) -> dict:

@@ -64,7 +64,10 @@ def test_full_path_matches_oracle(rast, kind):
     assert U.rel_err(img, op.fwd.image) <= 2e-4
     assert np.abs(img - op.fwd.image).max() <= 2e-2
     assert stats["n_instances"] == pytest.approx(op.lists.keys.size, rel=1e-3)
-    assert evals == pytest.approx(int(op.fwd.examined.sum()), rel=1e-3)
+    assert evals["examined"] == pytest.approx(int(op.fwd.examined.sum()), rel=1e-3)
+    assert evals["blended"] == pytest.approx(int(op.fwd.n_blend.sum()), rel=1e-3)
+    assert 0 < evals["blended_masked"] < evals["blended"]
+    assert evals["examined"] >= evals["bwd_examined"] >= evals["blended"]
     for name, a, b in [("means", g.means, op.grads.means), ("log_scales", g.log_scales, op.grads.log_scales),
                        ("quats", g.quats, op.grads.quats), ("opacity_logits", g.opacity_logits,
                                                              op.grads.opacity_logits),
