@@ -84,8 +84,11 @@ def stage_roofline(stage: str, ms_per_launch: float, counts: dict, frame_stats: 
         return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
     if stage == "sort":
+        # stable pass over 32-bit tile keys and 32-bit values: read and write both
         passes = frame_stats["sort_passes"]
-        byt = 24 * K * passes
+        byt = 16 * K * passes
+    elif stage == "depth_sort":
+        byt = 16 * R * 4 + R * 12
     elif stage == "project":
         byt = n * 4 * (11 + k3 + 1) + R * (48 + 12)
     elif stage == "project_bwd":
@@ -132,6 +135,10 @@ def main() -> int:
     ap.add_argument("--fwd-ppt", type=int, default=1)
     ap.add_argument("--bwd-ppt", type=int, default=4)
     ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--wide-tiles", type=int, default=0,
+                    help="hybrid binning threshold in tiles (0: automatic, -1: every record duplicated)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,6 +152,17 @@ def main() -> int:
         return 2
     from paper_2412_20522_amd import maskgs as M
     from paper_2412_20522_amd.raster import PARAM_KEYS, Grads, Rasterizer
+
+    if args.copy_calibration_mib > 0:
+        # a plain copy of known size: reads and writes exactly this many bytes
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
 
     t_gen = time.perf_counter()
     scene, desc = build_workload(args.workload)
@@ -162,7 +180,7 @@ def main() -> int:
     targets = torch.cat([torch.from_numpy(t.reshape(-1)) for t in scene["targets"]]).to(dev)
     tw, th = (int(x) for x in args.tile.split("x"))
     rast = Rasterizer(0, sh_degree=deg, tile_w=tw, tile_h=th, batch_depth=args.batch_depth, fwd_ppt=args.fwd_ppt,
-                      bwd_ppt=args.bwd_ppt, persistent=args.persistent)
+                      bwd_ppt=args.bwd_ppt, persistent=args.persistent, wide_tiles=args.wide_tiles)
     ctx = rast.ctx
     frame = rast.acquire_frame()
     images = torch.empty(3 * P, device=dev)
@@ -209,7 +227,8 @@ def main() -> int:
     ms_step = ev0.elapsed_time(ev1) / args.steps
     prof = M.mgs_profile_read(ctx)
     M.mgs_profile_enable(ctx, False)
-    log(f"[bench] batched: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}")
+    log(f"[bench] batched: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}, "
+        f"wide records = {fstats['n_wide']}")
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     for k, v in prof.items():
         if v[1]:
@@ -275,6 +294,8 @@ def main() -> int:
             "pixels": P,
             "evals_per_step_16x16": E16,
             "instances": fstats["n_instances"],
+            "wide_records": fstats["n_wide"],
+            "wide_tiles": args.wide_tiles,
             "views_per_s": V / (ms_step * 1e-3),
             "tile": args.tile,
             "batch_depth": args.batch_depth,

@@ -94,6 +94,12 @@ typedef struct {
                                 (tile_w * tile_h / ppt threads per workgroup, a
                                 multiple of 64) */
     int32_t bwd_ppt;         /* pixels per thread in backward compositing */
+    int32_t wide_tiles;      /* hybrid binning: a record covering more tiles than
+                                this is kept once in its view's depth-ordered wide
+                                list instead of being duplicated per tile; the
+                                compositing merges it into every tile list it
+                                covers, so results are those of plain binning.
+                                0: max(32, tiles of the view / 4); < 0: off */
 } mgs_settings;
 
 /* Gaussian parameters (device pointers, float32). */
@@ -124,6 +130,7 @@ typedef struct {
     int64_t n_instances;     /* K of the last forward */
     int64_t total_tiles;
     int64_t instance_capacity;
+    int64_t n_wide;          /* records in the wide lists (hybrid binning) */
     int32_t sort_passes;
     int32_t tile_bits;
 } mgs_frame_stats;
@@ -180,6 +187,38 @@ MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_ga
 MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float* dl_dimages,
                                 const mgs_gradients* grads);
 
+/* Copies one array the last forward left in the frame into dst (device,
+ * caller-owned, at least the reported size):
+ *   MGS_EXPORT_RECORDS  [R, 12] f32 projected records (layout of mgs_project)
+ *   MGS_EXPORT_DEPTH    [R] f32, MGS_EXPORT_RADIUS [R] f32, MGS_EXPORT_TILES [R] u32
+ *   MGS_EXPORT_VALUES   [K] u32 record ids in (tile, depth, record) order
+ *   MGS_EXPORT_RANGES   [total_tiles, 2] u32
+ *   MGS_EXPORT_T_FINAL  [P] f32, MGS_EXPORT_LAST [P] i32
+ *   MGS_EXPORT_STATS    [P, 4] i32 (examined, blended, blended with mask 0,
+ *                       entries up to the last blended one)
+ *   MGS_EXPORT_WIDE     [W, 4] u32 wide entries per view in (depth, record)
+ *                       order: depth bits, record, x0 | y0 << 16, x1 | y1 << 16
+ *                       (inclusive tile rectangle)
+ *   MGS_EXPORT_WIDE_RANGES [n_views, 2] u32 [start, end) into the wide entries
+ * VALUES and RANGES hold the narrow instances only; a tile's list is their
+ * merge with the wide entries of its view whose rectangle contains it, and
+ * LAST holds indices into that merged list.
+ * *bytes (host) receives the size; with dst NULL only the size is returned. */
+typedef enum {
+    MGS_EXPORT_RECORDS = 0,
+    MGS_EXPORT_DEPTH,
+    MGS_EXPORT_RADIUS,
+    MGS_EXPORT_TILES,
+    MGS_EXPORT_VALUES,
+    MGS_EXPORT_RANGES,
+    MGS_EXPORT_T_FINAL,
+    MGS_EXPORT_LAST,
+    MGS_EXPORT_STATS,
+    MGS_EXPORT_WIDE,
+    MGS_EXPORT_WIDE_RANGES
+} mgs_export;
+MGS_API mgs_status mgs_frame_export(mgs_frame* frame, mgs_stream stream, int what, void* dst, size_t* bytes);
+
 /* Gaussian-pixel work of the last forward on a frame, summed over pixels. */
 typedef struct {
     int64_t examined;        /* entries examined in the forward, up to and including
@@ -200,6 +239,7 @@ MGS_API mgs_status mgs_frame_count_evals(mgs_frame* frame, mgs_stream stream, mg
 
 typedef enum {
     MGS_STAGE_PROJECT = 0,
+    MGS_STAGE_DEPTH_SORT,
     MGS_STAGE_SCAN,
     MGS_STAGE_DUPLICATE,
     MGS_STAGE_SORT,

@@ -174,7 +174,7 @@ mgs_status check_gaussians(mgs_ctx* ctx, const mgs_gaussians* g, bool need_masks
 }
 
 // Host-side construction of the per-view device constants.
-ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t* total_px) {
+ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t* total_px, int wide_tiles = -1) {
     ViewSet vs;
     memset(&vs, 0, sizeof vs);
     vs.n_views = n_views;
@@ -198,6 +198,11 @@ ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t*
         d.grid_h = (c.height + th - 1) / th;
         d.tile_off = toff;
         d.px_off = poff;
+        // records covering more tiles than wide_min go to the view's wide list
+        const uint32_t vt = (uint32_t)(d.grid_w * d.grid_h);
+        if (wide_tiles < 0) d.wide_min = 0xffffffffu;
+        else if (wide_tiles > 0) d.wide_min = (uint32_t)wide_tiles;
+        else d.wide_min = std::max<uint32_t>(32u, vt / 4u);
         toff += (uint32_t)(d.grid_w * d.grid_h);
         poff += (uint32_t)(c.width * c.height);
     }
@@ -256,17 +261,29 @@ struct mgs_frame {
     CompositeConfig cfg_fwd{}, cfg_bwd{};
     int persistent = 0;
     int n_views = 0;
-    int64_t n = 0, R = 0, P = 0, K = 0, total_tiles = 0, capacity = 0;
+    int64_t n = 0, R = 0, P = 0, K = 0, W = 0, total_tiles = 0, capacity = 0;
     int sort_passes = 0, tile_bits = 0;
-    bool sorted_in_alt = false;
-    // device buffers
-    DevBuf rec, depth, radius, tiles, offsets, keys, vals, keys_alt, vals_alt, ranges, t_final, last, stats;
-    DevBuf d_rec, d_masks_tmp, scan_tmp, sort_tmp, misc, queue, sum_tmp;
-    uint64_t* h_pinned = nullptr;  // K, flags read-back
-    uint64_t* keys_sorted() { return (uint64_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
+    bool sorted_in_alt = false, order_in_alt = false;
+    // device buffers: per record, then per narrow instance (32-bit tile keys),
+    // wide entries, per tile, per pixel
+    DevBuf rec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, wide_pos;
+    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats;
+    DevBuf d_rec, d_masks_tmp, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;
+    // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
+    // 16, per-view wide ranges (u32 pairs) from 32
+    uint64_t* h_pinned = nullptr;  // read-back of misc
+    uint32_t* keys_sorted() { return (uint32_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
     uint32_t* vals_sorted() { return (uint32_t*)(sorted_in_alt ? vals_alt.p : vals.p); }
+    uint32_t* record_order() { return (uint32_t*)(order_in_alt ? rvals_alt.p : rvals.p); }
     uint32_t* flags() { return (uint32_t*)misc.p; }
     uint64_t* total() { return (uint64_t*)((char*)misc.p + 8); }
+    uint64_t* wide_total() { return (uint64_t*)((char*)misc.p + 16); }
+    uint32_t* wide_range() { return (uint32_t*)((char*)misc.p + 32); }
+    HybridBuffers hybrid() {
+        return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const float*)depth.p,
+                             (const uint32_t*)wide.p, wide_range(), (uint32_t*)cur.p,
+                             (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p};
+    }
 };
 
 extern "C" {
@@ -292,6 +309,7 @@ mgs_status mgs_default_settings(mgs_settings* out) {
     out->persistent = 0;
     out->fwd_ppt = 1;
     out->bwd_ppt = 4;
+    out->wide_tiles = 0;
     return MGS_OK;
 }
 
@@ -328,7 +346,7 @@ mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
     mgs_frame* f = new (std::nothrow) mgs_frame();
     if (!f) return fail(ctx, MGS_ERR_OOM, "frame allocation");
     f->ctx = ctx;
-    if (hipHostMalloc((void**)&f->h_pinned, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&f->h_pinned, 256, hipHostMallocDefault) != hipSuccess) {
         delete f;
         return fail(ctx, MGS_ERR_OOM, "pinned host allocation");
     }
@@ -344,9 +362,12 @@ mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
 mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&f->rec, &f->depth, &f->radius, &f->tiles, &f->offsets, &f->keys, &f->vals, &f->keys_alt,
-                      &f->vals_alt, &f->ranges, &f->t_final, &f->last, &f->stats, &f->d_rec, &f->d_masks_tmp,
-                      &f->scan_tmp, &f->sort_tmp, &f->misc, &f->queue, &f->sum_tmp};
+    DevBuf* bufs[] = {&f->rec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
+                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos,
+                      &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
+                      &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->t_final,  &f->last,
+                      &f->stats,    &f->d_rec,     &f->d_masks_tmp, &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
+                      &f->misc,     &f->queue,     &f->sum_tmp};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
     delete f;
@@ -362,6 +383,7 @@ mgs_status mgs_frame_get_stats(const mgs_frame* f, mgs_frame_stats* out) {
     out->n_instances = f->K;
     out->total_tiles = f->total_tiles;
     out->instance_capacity = f->capacity;
+    out->n_wide = f->W;
     out->sort_passes = f->sort_passes;
     out->tile_bits = f->tile_bits;
     return MGS_OK;
@@ -382,7 +404,7 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->n = g->n;
     f->n_views = n_views;
     f->R = g->n * n_views;
-    f->views = make_views(cams, n_views, st->tile_w, st->tile_h, &f->P);
+    f->views = make_views(cams, n_views, st->tile_w, st->tile_h, &f->P, st->wide_tiles);
     set_limits(f->views, cams, st->jac_clamp);
     f->st = make_settings(st);
     f->cfg_fwd = CompositeConfig{st->tile_w, st->tile_h, st->fwd_ppt};
@@ -390,13 +412,20 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->persistent = st->persistent;
     f->total_tiles = f->views.total_tiles;
     f->tile_bits = bits_for((uint64_t)f->total_tiles);
-    const int64_t R = f->R, P = f->P;
+    const int64_t R = f->R, P = f->P, T = f->total_tiles;
+    const int V = n_views;
     if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
-        (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) || (s = grow(ctx, f->ranges, (size_t)f->total_tiles * 8)) ||
+        (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
+        (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
+        (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) || (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->wide_pos, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->ranges, (size_t)T * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
+        (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow(ctx, f->nbatch, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
-        (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(R))) ||
-        (s = grow(ctx, f->queue, 256)))
+        (s = grow(ctx, f->stats, (size_t)P * 16)) ||
+        (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(std::max<int64_t>(R, T)))) ||
+        (s = grow(ctx, f->rsort_tmp, sort_scratch_bytes(R))) || (s = grow(ctx, f->queue, 256)))
         return s;
     launch_fill_u32(stream, f->flags(), 2, 0u);
     {
@@ -405,55 +434,93 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
                            (uint32_t*)f->tiles.p, f->flags());
     }
     {
+        // records in (view, depth, record) order, those without tiles last in
+        // their view; then narrow tile counts and wide flags in that order
+        StageTimer t(ctx, stream, MGS_STAGE_DEPTH_SORT);
+        launch_record_keys64(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R, f->n,
+                             (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
+        bool alt = false;
+        launch_radix_sort(stream, (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint64_t*)f->rkeys_alt.p,
+                          (uint32_t*)f->rvals_alt.p, R, nullptr, 32 + bits_for((uint64_t)V), f->rsort_tmp.p, &alt);
+        f->order_in_alt = alt;
+        launch_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, R, f->n, f->views,
+                        (uint32_t*)f->cnt_sorted.p, (uint32_t*)f->wide_flag.p);
+    }
+    {
         StageTimer t(ctx, stream, MGS_STAGE_SCAN);
-        launch_scan_u32(stream, (const uint32_t*)f->tiles.p, R, (uint32_t*)f->offsets.p, f->total(), f->scan_tmp.p);
+        launch_scan_u32(stream, (const uint32_t*)f->cnt_sorted.p, R, (uint32_t*)f->offsets.p, f->total(),
+                        f->scan_tmp.p);
+        launch_scan_u32(stream, (const uint32_t*)f->wide_flag.p, R, (uint32_t*)f->wide_pos.p, f->wide_total(),
+                        f->scan_tmp.p);
+        launch_wide_ranges(stream, (const uint32_t*)f->wide_pos.p, f->wide_total(), f->n, V, f->wide_range());
     }
     MGS_CHECK_LAUNCH(ctx);
-    // the one synchronisation of the plain path: K sizes the sort
-    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 16, hipMemcpyDeviceToHost, stream));
+    // the one synchronisation of the plain path: instance and wide counts
+    // size the instance sort and the batch checkpoints
+    const size_t rb = 32 + 8 * (size_t)V;
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, rb, hipMemcpyDeviceToHost, stream));
     MGS_HIP(ctx, hipStreamSynchronize(stream));
     const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
     const uint64_t K = f->h_pinned[1];
+    const uint64_t W = f->h_pinned[2];
     if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
     if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu instances exceed 2^31 - 1",
                                                 (unsigned long long)K);
     f->K = (int64_t)K;
-    if ((s = grow(ctx, f->keys, (size_t)K * 8 + 8)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 4)) ||
-        (s = grow(ctx, f->keys_alt, (size_t)K * 8 + 8)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 4)) ||
-        (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))))
+    f->W = (int64_t)W;
+    // checkpoints: per tile 2 (ceil(narrow / B) + ceil(wide of its view / B)) + 2
+    const int64_t B = st->batch_depth;
+    int64_t cur_bound = 2 * ((f->K + B - 1) / B + T) + 2 * T;
+    {
+        const uint32_t* wr = reinterpret_cast<const uint32_t*>(f->h_pinned + 4);
+        for (int v = 0; v < V; ++v) {
+            const int64_t wv = (int64_t)wr[2 * v + 1] - (int64_t)wr[2 * v];
+            const int64_t tv = (int64_t)f->views.v[v].grid_w * f->views.v[v].grid_h;
+            cur_bound += 2 * tv * ((wv + B - 1) / B);
+        }
+    }
+    if ((s = grow(ctx, f->keys, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 16)) ||
+        (s = grow(ctx, f->keys_alt, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 16)) ||
+        (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))) || (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) ||
+        (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)))
         return s;
-    f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 8, f->vals.bytes / 4);
+    f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 4, f->vals.bytes / 4);
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
-        launch_duplicate(stream, (const float*)f->rec.p, (const float*)f->radius.p, (const float*)f->depth.p,
-                         (const uint32_t*)f->tiles.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
-                         (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
+        launch_duplicate_sorted(stream, (const float*)f->rec.p, (const float*)f->radius.p, f->record_order(),
+                                (const uint32_t*)f->cnt_sorted.p, (const uint32_t*)f->offsets.p, R, f->n, f->views,
+                                f->st, (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
+        launch_wide_scatter(stream, f->record_order(), (const uint32_t*)f->wide_flag.p,
+                            (const uint32_t*)f->wide_pos.p, R, f->n, (const float*)f->rec.p,
+                            (const float*)f->radius.p, (const float*)f->depth.p, f->views, f->st,
+                            (uint32_t*)f->wide.p, f->W, f->flags());
     }
-    const int key_bits = 32 + f->tile_bits;
-    f->sort_passes = f->K > 1 ? (key_bits + 7) / 8 : 0;
+    // instances are already in (depth, record) order: a stable sort on the
+    // tile bits alone gives the (tile, depth, record) order
+    f->sort_passes = f->K > 1 ? (f->tile_bits + 7) / 8 : 0;
     bool in_alt = false;
     {
         StageTimer t(ctx, stream, MGS_STAGE_SORT);
-        launch_radix_sort(stream, (uint64_t*)f->keys.p, (uint32_t*)f->vals.p, (uint64_t*)f->keys_alt.p,
-                          (uint32_t*)f->vals_alt.p, f->K, nullptr, key_bits, f->sort_tmp.p, &in_alt);
+        launch_radix_sort32(stream, (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, (uint32_t*)f->keys_alt.p,
+                            (uint32_t*)f->vals_alt.p, f->K, nullptr, 0, 8 * f->sort_passes, f->sort_tmp.p, &in_alt);
     }
     f->sorted_in_alt = in_alt;
     {
         StageTimer t(ctx, stream, MGS_STAGE_RANGES);
-        launch_tile_ranges(stream, f->keys_sorted(), f->K, nullptr, f->total_tiles, (uint32_t*)f->ranges.p);
+        launch_tile_ranges32(stream, f->keys_sorted(), f->K, nullptr, T, (uint32_t*)f->ranges.p);
+        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->wide_range(), f->views, (int)B,
+                          (uint32_t*)f->caps.p);
+        launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, nullptr, f->scan_tmp.p);
     }
     uint32_t* queue = nullptr;
-    int grid = 0;
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
-        grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
-        launch_composite_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->vals_sorted(),
-                             (const uint32_t*)f->ranges.p, f->views, f->st, images, (float*)f->t_final.p,
-                             (int32_t*)f->last.p, nullptr, (int32_t*)f->stats.p, queue, grid);
+        launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->hybrid(), f->views, f->st, images,
+                          (float*)f->t_final.p, (int32_t*)f->last.p, (int32_t*)f->stats.p, queue, ctx->num_cus);
     }
     MGS_CHECK_LAUNCH(ctx);
     if (t_final_out)
@@ -478,19 +545,17 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         d_masks = (float*)f->d_masks_tmp.p;
     }
     uint32_t* queue = nullptr;
-    int grid = 0;
     launch_fill_f32(stream, (float*)f->d_rec.p, f->R * DREC, 0.f);
     launch_fill_f32(stream, d_masks, f->n, 0.f);
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
-        grid = (int)std::min<int64_t>(f->total_tiles, (int64_t)ctx->num_cus * 8);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_BWD);
-        launch_composite_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->vals_sorted(),
-                             (const uint32_t*)f->ranges.p, f->views, f->st, (const float*)f->t_final.p,
-                             (const int32_t*)f->last.p, dl_dimages, f->n, (float*)f->d_rec.p, d_masks, queue, grid);
+        launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->hybrid(), f->views, f->st,
+                          (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
+                          (float*)f->d_rec.p, d_masks, queue, ctx->num_cus);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT_BWD);
@@ -517,6 +582,31 @@ mgs_status mgs_frame_count_evals(mgs_frame* f, mgs_stream stream_, mgs_eval_coun
     out->blended = (int64_t)f->h_pinned[3];
     out->blended_masked = (int64_t)f->h_pinned[4];
     out->bwd_examined = (int64_t)f->h_pinned[5];
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_export(mgs_frame* f, mgs_stream stream, int what, void* dst, size_t* bytes) {
+    if (!f || !bytes) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "no forward on this frame");
+    const void* src = nullptr;
+    size_t n = 0;
+    switch (what) {
+        case MGS_EXPORT_RECORDS: src = f->rec.p; n = (size_t)f->R * 48; break;
+        case MGS_EXPORT_DEPTH: src = f->depth.p; n = (size_t)f->R * 4; break;
+        case MGS_EXPORT_RADIUS: src = f->radius.p; n = (size_t)f->R * 4; break;
+        case MGS_EXPORT_TILES: src = f->tiles.p; n = (size_t)f->R * 4; break;
+        case MGS_EXPORT_VALUES: src = f->vals_sorted(); n = (size_t)f->K * 4; break;
+        case MGS_EXPORT_RANGES: src = f->ranges.p; n = (size_t)f->total_tiles * 8; break;
+        case MGS_EXPORT_T_FINAL: src = f->t_final.p; n = (size_t)f->P * 4; break;
+        case MGS_EXPORT_LAST: src = f->last.p; n = (size_t)f->P * 4; break;
+        case MGS_EXPORT_STATS: src = f->stats.p; n = (size_t)f->P * 16; break;
+        case MGS_EXPORT_WIDE: src = f->wide.p; n = (size_t)f->W * 16; break;
+        case MGS_EXPORT_WIDE_RANGES: src = f->wide_range(); n = (size_t)f->n_views * 8; break;
+        default: return fail(ctx, MGS_ERR_INVALID_ARG, "unknown export %d", what);
+    }
+    *bytes = n;
+    if (dst && n) MGS_HIP(ctx, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return MGS_OK;
 }
 

@@ -19,6 +19,7 @@ struct DevView {
     int32_t grid_w, grid_h;
     uint32_t tile_off;  // first global tile id of this view
     uint32_t px_off;    // first pixel of this view in packed per-pixel arrays
+    uint32_t wide_min;  // records covering more tiles than this are kept in the wide list
 };
 
 // Passed by value as a kernel argument: no device copy, nothing to capture.
@@ -48,6 +49,31 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 constexpr int REC_F4 = 3;
 // Per-record 2D gradient layout: du, dv, da, db, dc, dopacity, dr, dg, db.
 constexpr int DREC = 9;
+
+// Tile rectangle (inclusive) of a record's square footprint; the same
+// double-precision arithmetic as the tile count of the projection.
+struct Rect {
+    int x0, y0, x1, y1;
+};
+
+__device__ __forceinline__ Rect record_rect(const float4* __restrict__ rec, const float* __restrict__ radius,
+                                            int64_t r, const DevView& cam, const DevSettings& st) {
+    Rect q;
+    if (st.full_rect) {
+        q.x0 = 0; q.y0 = 0; q.x1 = cam.grid_w - 1; q.y1 = cam.grid_h - 1;
+        return q;
+    }
+    const float4 A = rec[3 * r];
+    const double ud = A.x, vd = A.y, rd = radius[r];
+    const double fx0 = floor((ud - rd) / st.tile_w), fx1 = floor((ud + rd) / st.tile_w);
+    const double fy0 = floor((vd - rd) / st.tile_h), fy1 = floor((vd + rd) / st.tile_h);
+    // clamp into the grid before converting (values can be far outside it)
+    q.x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.grid_w);
+    q.y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.grid_h);
+    q.x1 = (int)fmax(fmin(fx1, (double)(cam.grid_w - 1)), -1.0);
+    q.y1 = (int)fmax(fmin(fy1, (double)(cam.grid_h - 1)), -1.0);
+    return q;
+}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

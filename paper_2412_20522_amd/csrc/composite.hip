@@ -24,55 +24,11 @@
 // tile when every pixel has.  With a queue pointer the launch is persistent:
 // workgroups pop tile ids from a device counter until the tiles run out.
 #include "common.hpp"
+#include "composite_common.hpp"
 #include "kernels.hpp"
 
 namespace mgs {
 namespace {
-
-constexpr int MAXB = 256;
-
-struct TileGeom {
-    int vi;
-    int tx0, ty0;
-};
-
-__device__ __forceinline__ TileGeom tile_geom(const ViewSet& views, uint32_t tile, int TW, int TH) {
-    TileGeom tg;
-    int vi = 0;
-    while (vi + 1 < views.n_views && tile >= views.v[vi + 1].tile_off) ++vi;
-    tg.vi = vi;
-    const DevView& cam = views.v[vi];
-    const uint32_t lt = tile - cam.tile_off;
-    tg.tx0 = (int)(lt % (uint32_t)cam.grid_w) * TW;
-    tg.ty0 = (int)(lt / (uint32_t)cam.grid_w) * TH;
-    return tg;
-}
-
-// Evaluation of one entry at one pixel, shared by forward and backward so
-// both take the same FP32 decisions (3-sigma cut, alpha clamp and filter).
-struct Eval {
-    float dx, dy, G, oG, alpha;
-};
-
-__device__ __forceinline__ bool eval_entry(const float4& A, const float4& B, float px, float py,
-                                           const DevSettings& st, Eval& e) {
-    e.dx = A.x - px;
-    e.dy = A.y - py;
-    const float Q = A.z * e.dx * e.dx + 2.f * A.w * e.dx * e.dy + B.x * e.dy * e.dy;
-    if (!(Q <= st.q_max)) return false;
-    e.G = __expf(-0.5f * Q);
-    e.oG = B.y * e.G;
-    e.alpha = fminf(st.alpha_max, e.oG);
-    return e.alpha >= st.alpha_min;
-}
-
-__device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* s_tile, uint32_t fixed) {
-    if (!queue) return fixed;
-    __syncthreads();
-    if (threadIdx.x == 0) *s_tile = atomicAdd(queue, 1u);
-    __syncthreads();
-    return *s_tile;
-}
 
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
@@ -309,18 +265,30 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
 }
 
 template <int TW, int TH, int PPT>
-void launch_fwd_t(hipStream_t s, int grid, const float* rec, const uint32_t* vals, const uint32_t* ranges,
+void launch_fwd_t(hipStream_t s, int num_cus, const float* rec, const uint32_t* vals, const uint32_t* ranges,
                   const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
                   int32_t* examined, int32_t* stats, uint32_t* queue) {
+    int grid = (int)views.total_tiles;
+    if (queue) {
+        static int full = 0;
+        if (!full) full = persistent_grid(composite_fwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
+        grid = min(full, grid);
+    }
     hipLaunchKernelGGL((composite_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
                        reinterpret_cast<const float4*>(rec), vals, reinterpret_cast<const uint2*>(ranges), views, st,
                        images, t_final, last, examined, reinterpret_cast<int4*>(stats), queue);
 }
 
 template <int TW, int TH, int PPT>
-void launch_bwd_t(hipStream_t s, int grid, const float* rec, const uint32_t* vals, const uint32_t* ranges,
+void launch_bwd_t(hipStream_t s, int num_cus, const float* rec, const uint32_t* vals, const uint32_t* ranges,
                   const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
                   const float* dl, int64_t n, float* d_rec, float* d_masks, uint32_t* queue) {
+    int grid = (int)views.total_tiles;
+    if (queue) {
+        static int full = 0;
+        if (!full) full = persistent_grid(composite_bwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
+        grid = min(full, grid);
+    }
     hipLaunchKernelGGL((composite_bwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
                        reinterpret_cast<const float4*>(rec), vals, reinterpret_cast<const uint2*>(ranges), views, st,
                        t_final, last, dl, n, d_rec, d_masks, queue);
@@ -351,12 +319,11 @@ bool composite_config_supported(const CompositeConfig& c) {
 void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
                           const uint32_t* ranges, const ViewSet& views, const DevSettings& st, float* images,
                           float* t_final, int32_t* last, int32_t* examined, int32_t* stats, uint32_t* queue,
-                          int grid_override) {
-    const int grid = grid_override > 0 ? grid_override : (int)views.total_tiles;
-    if (grid == 0) return;
+                          int num_cus) {
+    if (views.total_tiles == 0) return;
 #define MGS_FWD(A, B, P)                                                                                     \
     if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                \
-        launch_fwd_t<A, B, P>(stream, grid, rec, vals, ranges, views, st, images, t_final, last, examined, stats, \
+        launch_fwd_t<A, B, P>(stream, num_cus, rec, vals, ranges, views, st, images, t_final, last, examined, stats, \
                               queue);                                                                        \
         return;                                                                                              \
     }
@@ -367,12 +334,11 @@ void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const 
 void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
                           const uint32_t* ranges, const ViewSet& views, const DevSettings& st, const float* t_final,
                           const int32_t* last, const float* dl_dimages, int64_t n, float* d_rec, float* d_masks,
-                          uint32_t* queue, int grid_override) {
-    const int grid = grid_override > 0 ? grid_override : (int)views.total_tiles;
-    if (grid == 0) return;
+                          uint32_t* queue, int num_cus) {
+    if (views.total_tiles == 0) return;
 #define MGS_BWD(A, B, P)                                                                                        \
     if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                   \
-        launch_bwd_t<A, B, P>(stream, grid, rec, vals, ranges, views, st, t_final, last, dl_dimages, n, d_rec, \
+        launch_bwd_t<A, B, P>(stream, num_cus, rec, vals, ranges, views, st, t_final, last, dl_dimages, n, d_rec, \
                               d_masks, queue);                                                                  \
         return;                                                                                                 \
     }

@@ -1,0 +1,613 @@
+// Hybrid binning and compositing for scenes with screen-covering splats.
+//
+// A record whose tile footprint exceeds a per-view threshold ("wide") is not
+// duplicated into every tile it covers.  Wide records are kept once, in a
+// per-view list ordered by (depth, record) together with their tile
+// rectangle; only the remaining ("narrow") records are duplicated and sorted
+// by tile.  A tile's list in the sense of Sec. 3.1 -- every record whose
+// footprint covers the tile, in depth order -- is then the merge of the
+// tile's narrow entries with the wide entries whose rectangle contains the
+// tile.  The compositing kernels form that merged list batch by batch in LDS
+// (merge path over two depth-ordered windows), so the entries, their order
+// and the per-pixel results are exactly those of fully duplicated lists,
+// while the instance sort shrinks from every (tile, wide splat) pair to the
+// narrow pairs only.
+//
+// The forward records, per tile and batch, the stream cursors where the batch
+// began; the backward replays the same batches in reverse from those
+// checkpoints, so the merge is deterministic and nothing per pixel beyond the
+// final transmittance and the last blended entry is stored.
+#include "common.hpp"
+#include "composite_common.hpp"
+#include "kernels.hpp"
+
+namespace mgs {
+namespace {
+
+// ---------------------------------------------------------------------------
+// binning: (view, depth) order of records, wide list, batch checkpoints
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restrict__ depth,
+                                                             const uint32_t* __restrict__ tiles, int64_t R, int64_t n,
+                                                             uint64_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const uint64_t v = (uint64_t)(r / n);
+    keys[r] = (v << 32) | (tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu);
+    vals[r] = (uint32_t)r;
+}
+
+__global__ void __launch_bounds__(256) classify_kernel(const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ tiles, int64_t R, int64_t n,
+                                                        ViewSet views, uint32_t* __restrict__ narrow_cnt,
+                                                        uint32_t* __restrict__ wide_flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R) return;
+    const uint32_t r = order[i];
+    const uint32_t c = tiles[r];
+    const bool wide = c > views.v[r / n].wide_min;
+    narrow_cnt[i] = wide ? 0u : c;
+    wide_flag[i] = wide ? 1u : 0u;
+}
+
+// Wide entry: x = depth bits, y = record, z = x0 | y0 << 16, w = x1 | y1 << 16.
+__global__ void __launch_bounds__(256) wide_scatter_kernel(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ wide_flag, const uint32_t* __restrict__ wide_pos,
+    int64_t R, int64_t n, const float4* __restrict__ rec, const float* __restrict__ radius,
+    const float* __restrict__ depth, ViewSet views, DevSettings st, uint4* __restrict__ wide, int64_t wcap,
+    uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R || !wide_flag[i]) return;
+    const uint32_t r = order[i];
+    const Rect q = record_rect(rec, radius, r, views.v[r / n], st);
+    const uint32_t p = wide_pos[i];
+    if (p < wcap) {
+        wide[p] = make_uint4(__float_as_uint(depth[r]), r, (uint32_t)q.x0 | ((uint32_t)q.y0 << 16),
+                             (uint32_t)q.x1 | ((uint32_t)q.y1 << 16));
+    } else {
+        atomicOr(flags, FLAG_CAPACITY);
+    }
+}
+
+// [start, end) of every view's wide records (records are grouped by view in
+// the sorted order, n per view).
+__global__ void wide_ranges_kernel(const uint32_t* __restrict__ wide_pos, const uint64_t* __restrict__ wide_total,
+                                   int64_t n, int nv, uint2* __restrict__ wide_range) {
+    const int v = threadIdx.x;
+    if (v >= nv) return;
+    if (n == 0) {
+        wide_range[v] = make_uint2(0u, 0u);
+        return;
+    }
+    const uint32_t s = wide_pos[(int64_t)v * n];
+    const uint32_t e = v + 1 < nv ? wide_pos[(int64_t)(v + 1) * n] : (uint32_t)*wide_total;
+    wide_range[v] = make_uint2(s, e);
+}
+
+// Upper bound on the batches a tile can take: a batch either emits `batch`
+// merged entries or exhausts a whole window of one of the two streams.
+__global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict__ ranges,
+                                                          const uint2* __restrict__ wide_range, ViewSet views,
+                                                          int batch, uint32_t* __restrict__ caps) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= views.total_tiles) return;
+    int vi = 0;
+    while (vi + 1 < views.n_views && t >= views.v[vi + 1].tile_off) ++vi;
+    const uint32_t len1 = ranges[t].y - ranges[t].x;
+    const uint32_t len2 = wide_range[vi].y - wide_range[vi].x;
+    caps[t] = 2u * ((len1 + batch - 1) / batch + (len2 + batch - 1) / batch) + 2u;
+}
+
+// ---------------------------------------------------------------------------
+// merging two depth-ordered streams in LDS
+// ---------------------------------------------------------------------------
+
+struct MergeLDS {
+    uint64_t xk[MAXB];      // narrow window keys (depth bits << 32 | record)
+    uint64_t yk_raw[MAXB];  // wide window keys, before the rectangle test
+    uint64_t yk[MAXB];      // wide entries covering this tile
+    uint32_t xr[MAXB];
+    uint32_t yr_raw[MAXB];
+    uint32_t yr[MAXB];
+    uint32_t ypass[MAXB];
+    uint32_t m[MAXB];       // merged records of the batch
+    float4 A[MAXB], B[MAXB], C[MAXB];
+    uint32_t wsum[MAXB / 64 + 4];
+};
+
+__device__ __forceinline__ int count_le(const uint64_t* a, int n, uint64_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int count_lt(const uint64_t* a, int n, uint64_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Exclusive scan over a block of any multiple of 64 threads.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) before += wsum[i];
+        tot += wsum[i];
+    }
+    *total = tot;
+    return before + x - v;
+}
+
+struct Batch {
+    int M;      // merged entries staged in LDS
+    int nX;     // narrow entries consumed
+    int nYraw;  // wide entries consumed (including those not covering the tile)
+};
+
+// Stages the next (at most `batch`) entries of the tile's merged list in LDS.
+// Every thread of the block calls it; the result is uniform.
+__device__ Batch merge_batch(MergeLDS& L, const uint32_t* __restrict__ vals, const float* __restrict__ depth,
+                             const uint4* __restrict__ wide, const float4* __restrict__ rec, int i1, int e1, int i2,
+                             int e2, int batch, int tcx, int tcy) {
+    const int t = threadIdx.x, NT = blockDim.x;
+    const int cX = min(batch, e1 - i1), cY = min(batch, e2 - i2);
+    for (int l = t; l < cX; l += NT) {
+        const uint32_t r = vals[i1 + l];
+        L.xr[l] = r;
+        L.xk[l] = ((uint64_t)__float_as_uint(depth[r]) << 32) | r;
+    }
+    for (int l = t; l < cY; l += NT) {
+        const uint4 w = wide[i2 + l];
+        L.yr_raw[l] = w.y;
+        L.yk_raw[l] = ((uint64_t)w.x << 32) | w.y;
+        const int x0 = (int)(w.z & 0xffffu), y0 = (int)(w.z >> 16), x1 = (int)(w.w & 0xffffu), y1 = (int)(w.w >> 16);
+        L.ypass[l] = (tcx >= x0 && tcx <= x1 && tcy >= y0 && tcy <= y1) ? 1u : 0u;
+    }
+    __syncthreads();
+    // entries up to the smaller of the two window ends are final
+    uint64_t F = ~0ull;
+    if (i1 + cX < e1) F = L.xk[cX - 1];
+    if (i2 + cY < e2) F = min(F, L.yk_raw[cY - 1]);
+    int nX = count_le(L.xk, cX, F);
+    int nYr = count_le(L.yk_raw, cY, F);
+    // compact the covering wide entries among the consumed raw ones
+    const int per = (cY + NT - 1) / NT;
+    uint32_t cnt = 0;
+    for (int q = 0; q < per; ++q) {
+        const int l = t * per + q;
+        if (l < nYr) cnt += L.ypass[l];
+    }
+    uint32_t nYu;
+    uint32_t pos = block_scan_excl(cnt, L.wsum, &nYu);
+    for (int q = 0; q < per; ++q) {
+        const int l = t * per + q;
+        if (l < nYr && L.ypass[l]) {
+            L.yk[pos] = L.yk_raw[l];
+            L.yr[pos] = L.yr_raw[l];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    int nY = (int)nYu;
+    if (nX + nY > batch) {
+        // keep the `batch` smallest: co-rank of the diagonal d = batch
+        const int d = batch;
+        int lo = max(0, d - nY), hi = min(d, nX);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (L.xk[mid] < L.yk[d - mid - 1]) lo = mid + 1;
+            else hi = mid;
+        }
+        const int a = lo;
+        uint64_t last = 0;
+        if (a > 0) last = L.xk[a - 1];
+        if (d - a > 0) last = max(last, L.yk[d - a - 1]);
+        nX = a;
+        nY = d - a;
+        nYr = count_le(L.yk_raw, nYr, last);
+    }
+    for (int a = t; a < nX; a += NT) L.m[a + count_lt(L.yk, nY, L.xk[a])] = L.xr[a];
+    for (int b = t; b < nY; b += NT) L.m[b + count_lt(L.xk, nX, L.yk[b])] = L.yr[b];
+    __syncthreads();
+    const int M = nX + nY;
+    for (int j = t; j < M; j += NT) {
+        const uint32_t r = L.m[j];
+        L.A[j] = rec[3 * (size_t)r];
+        L.B[j] = rec[3 * (size_t)r + 1];
+        L.C[j] = rec[3 * (size_t)r + 2];
+    }
+    __syncthreads();
+    return Batch{M, nX, nYr};
+}
+
+struct HybridLists {
+    const uint32_t* vals;      // narrow instances in (tile, depth, record) order
+    const uint2* ranges;       // narrow [start, end) per tile
+    const float* depth;        // per record
+    const uint4* wide;         // wide entries, per view in (depth, record) order
+    const uint2* wide_range;   // per view
+    uint4* cur;                // batch checkpoints (narrow cursor, wide cursor, merged index)
+    const uint32_t* cur_off;   // first checkpoint of each tile
+    uint32_t* nbatch;          // batches the forward took per tile
+};
+
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
+    const float4* __restrict__ rec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
+    float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
+    uint32_t* __restrict__ queue) {
+    constexpr int NT = TW * TH / PPT;
+    __shared__ MergeLDS L;
+    __shared__ uint32_t s_tile;
+    const int t = threadIdx.x;
+    const int batch = st.batch;
+    for (;;) {
+        const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
+        if (tile >= views.total_tiles) break;
+        const TileGeom tg = tile_geom(views, tile, TW, TH);
+        const DevView& cam = views.v[tg.vi];
+        float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+        int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT];
+        bool done[PPT], inside[PPT];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int pidx = t + i * NT;
+            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            inside[i] = x < cam.width && y < cam.height;
+            px[i] = (float)x + 0.5f;
+            py[i] = (float)y + 0.5f;
+            T[i] = 1.f;
+            C0[i] = C1[i] = C2[i] = 0.f;
+            last[i] = -1;
+            stopk[i] = -1;
+            nblend[i] = nmasked[i] = 0;
+            done[i] = !inside[i];
+        }
+        const uint2 r1 = hl.ranges[tile];
+        const uint2 r2 = hl.wide_range[tg.vi];
+        const int e1 = (int)r1.y, e2 = (int)r2.y;
+        int i1 = (int)r1.x, i2 = (int)r2.x, m = 0, b = 0;
+        const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
+        uint4* cur = hl.cur + hl.cur_off[tile];
+        while (i1 < e1 || i2 < e2) {
+            bool active = false;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) active |= !done[i];
+            if (!__syncthreads_or(active)) break;
+            if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
+            const Batch bt = merge_batch(L, hl.vals, hl.depth, hl.wide, rec, i1, e1, i2, e2, batch, tcx, tcy);
+            for (int j = 0; j < bt.M; ++j) {
+                if (!__any(active)) break;
+                const float4 A = L.A[j], B = L.B[j], Cc = L.C[j];
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    if (done[i]) continue;
+                    Eval e;
+                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    const float ma = B.z * e.alpha;
+                    const float test = T[i] * (1.f - ma);
+                    if (test < st.t_min) {
+                        done[i] = true;
+                        stopk[i] = m + j;
+                        continue;
+                    }
+                    const float wgt = ma * T[i];
+                    C0[i] += wgt * Cc.x;
+                    C1[i] += wgt * Cc.y;
+                    C2[i] += wgt * Cc.z;
+                    T[i] = test;
+                    last[i] = m + j;
+                    ++nblend[i];
+                    nmasked[i] += B.z == 0.f;
+                }
+                active = false;
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) active |= !done[i];
+            }
+            i1 += bt.nX;
+            i2 += bt.nYraw;
+            m += bt.M;
+            ++b;
+            __syncthreads();  // the next batch overwrites L
+        }
+        if (t == 0) hl.nbatch[tile] = (uint32_t)b;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            if (!inside[i]) continue;
+            const int pidx = t + i * NT;
+            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            const int64_t pv = (int64_t)cam.width * cam.height;
+            const int64_t loc = (int64_t)y * cam.width + x;
+            float* im = images + 3 * (int64_t)cam.px_off;
+            im[loc] = C0[i] + T[i] * st.bg[0];
+            im[pv + loc] = C1[i] + T[i] * st.bg[1];
+            im[2 * pv + loc] = C2[i] + T[i] * st.bg[2];
+            const int64_t p = (int64_t)cam.px_off + loc;
+            t_final[p] = T[i];
+            last_out[p] = last[i];
+            // a pixel that never stopped saw the whole merged list (m entries)
+            if (stats_out)
+                stats_out[p] = make_int4(stopk[i] >= 0 ? stopk[i] + 1 : m, nblend[i], nmasked[i], last[i] + 1);
+        }
+        if (!queue) break;
+    }
+}
+
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
+    const float4* __restrict__ rec, HybridLists hl, ViewSet views, DevSettings st, const float* __restrict__ t_final,
+    const int32_t* __restrict__ last_in, const float* __restrict__ dl_dimages, int64_t n, float* __restrict__ d_rec,
+    float* __restrict__ d_masks, uint32_t* __restrict__ queue) {
+    constexpr int NT = TW * TH / PPT;
+    __shared__ MergeLDS L;
+    __shared__ uint32_t s_tile;
+    __shared__ int s_top;
+    const int t = threadIdx.x;
+    const int lane = lane_id();
+    const int batch = st.batch;
+    const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
+    for (;;) {
+        const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
+        if (tile >= views.total_tiles) break;
+        const TileGeom tg = tile_geom(views, tile, TW, TH);
+        const DevView& cam = views.v[tg.vi];
+        const int64_t rec_base = (int64_t)tg.vi * n;
+        float px[PPT], py[PPT], T[PPT], Tf[PPT], w0[PPT], w1[PPT], w2[PPT], wbg[PPT], b0[PPT], b1[PPT], b2[PPT];
+        int lastk[PPT];
+        int mylast = -1;
+        const int64_t pv = (int64_t)cam.width * cam.height;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int pidx = t + i * NT;
+            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            px[i] = (float)x + 0.5f;
+            py[i] = (float)y + 0.5f;
+            b0[i] = b1[i] = b2[i] = 0.f;
+            if (x < cam.width && y < cam.height) {
+                const int64_t loc = (int64_t)y * cam.width + x;
+                const int64_t p = (int64_t)cam.px_off + loc;
+                const float* dl = dl_dimages + 3 * (int64_t)cam.px_off;
+                lastk[i] = last_in[p];
+                Tf[i] = t_final[p];
+                w0[i] = dl[loc];
+                w1[i] = dl[pv + loc];
+                w2[i] = dl[2 * pv + loc];
+            } else {
+                lastk[i] = -1;
+                Tf[i] = 1.f;
+                w0[i] = w1[i] = w2[i] = 0.f;
+            }
+            T[i] = Tf[i];
+            wbg[i] = w0[i] * bg0 + w1[i] * bg1 + w2[i] * bg2;
+            mylast = max(mylast, lastk[i]);
+        }
+        for (int off = 32; off > 0; off >>= 1) mylast = max(mylast, __shfl_xor(mylast, off));
+        if (t == 0) s_top = -1;
+        __syncthreads();
+        if (lane == 0) atomicMax(&s_top, mylast);
+        __syncthreads();
+        const int top = s_top;
+        const uint4* cur = hl.cur + hl.cur_off[tile];
+        const uint2 r1 = hl.ranges[tile];
+        const uint2 r2 = hl.wide_range[tg.vi];
+        const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
+        // the batch holding the largest last-blended entry, then backwards
+        int bstar = -1;
+        if (top >= 0) {
+            const int nb = (int)hl.nbatch[tile];
+            for (int b = 0; b < nb; ++b)
+                if ((int)cur[b].z <= top) bstar = b;
+        }
+        for (int b = bstar; b >= 0; --b) {
+            const uint4 c = cur[b];
+            const int m = (int)c.z;
+            const Batch bt = merge_batch(L, hl.vals, hl.depth, hl.wide, rec, (int)c.x, (int)r1.y, (int)c.y,
+                                         (int)r2.y, batch, tcx, tcy);
+            const int jtop = min(bt.M - 1, top - m);
+            for (int j = jtop; j >= 0; --j) {
+                const int k = m + j;
+                const float4 A = L.A[j], B = L.B[j], Cc = L.C[j];
+                const float M = B.z;
+                float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
+                      gm = 0.f;
+                bool any = false;
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    if (k > lastk[i]) continue;
+                    Eval e;
+                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    any = true;
+                    const float alpha = e.alpha, G = e.G, dx = e.dx, dy = e.dy;
+                    const float ma = M * alpha;
+                    const float one_m = 1.f - ma;
+                    const float inv = __builtin_amdgcn_rcpf(one_m);
+                    const float Ti = T[i] * inv;
+                    const float X = Ti * (w0[i] * (Cc.x - b0[i]) + w1[i] * (Cc.y - b1[i]) + w2[i] * (Cc.z - b2[i])) -
+                                    Tf[i] * inv * wbg[i];
+                    gm += alpha * X;
+                    const float wt = ma * Ti;
+                    gr += wt * w0[i];
+                    gg += wt * w1[i];
+                    gbl += wt * w2[i];
+                    if (e.oG <= st.alpha_max) {
+                        const float dA = M * X;
+                        go += G * dA;
+                        const float dQ = -0.5f * B.y * G * dA;
+                        gu += dQ * 2.f * (A.z * dx + A.w * dy);
+                        gv += dQ * 2.f * (A.w * dx + B.x * dy);
+                        ga += dQ * dx * dx;
+                        gb += dQ * 2.f * dx * dy;
+                        gc += dQ * dy * dy;
+                    }
+                    b0[i] = ma * Cc.x + one_m * b0[i];
+                    b1[i] = ma * Cc.y + one_m * b1[i];
+                    b2[i] = ma * Cc.z + one_m * b2[i];
+                    T[i] = Ti;
+                }
+                if (__any(any)) {
+                    const uint32_t r = L.m[j];
+                    const int64_t g = (int64_t)r - rec_base;
+                    const float sm = wave_sum(gm);
+                    if (M != 0.f) {
+                        const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
+                                    sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
+                                    sbl = wave_sum(gbl);
+                        float v = lane == 0 ? su : lane == 1 ? sv : lane == 2 ? sa : lane == 3 ? sb : lane == 4 ? sc
+                                : lane == 5 ? so : lane == 6 ? sr : lane == 7 ? sg : lane == 8 ? sbl : sm;
+                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, v);
+                        else if (lane == DREC) atomicAdd(d_masks + g, v);
+                    } else if (lane == 0) {
+                        atomicAdd(d_masks + g, sm);
+                    }
+                }
+            }
+            __syncthreads();  // the next batch overwrites L
+        }
+        if (!queue) break;
+    }
+}
+
+template <int TW, int TH, int PPT>
+void hybrid_fwd_t(hipStream_t s, int num_cus, const float* rec, const HybridLists& hl, const ViewSet& views,
+                  const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
+                  uint32_t* queue) {
+    int grid = (int)views.total_tiles;
+    if (queue) {
+        static int full = 0;
+        if (!full) full = persistent_grid(hybrid_fwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
+        grid = min(full, grid);
+    }
+    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
+                       reinterpret_cast<const float4*>(rec), hl, views, st, images, t_final, last,
+                       reinterpret_cast<int4*>(stats), queue);
+}
+
+template <int TW, int TH, int PPT>
+void hybrid_bwd_t(hipStream_t s, int num_cus, const float* rec, const HybridLists& hl, const ViewSet& views,
+                  const DevSettings& st, const float* t_final, const int32_t* last, const float* dl, int64_t n,
+                  float* d_rec, float* d_masks, uint32_t* queue) {
+    int grid = (int)views.total_tiles;
+    if (queue) {
+        static int full = 0;
+        if (!full) full = persistent_grid(hybrid_bwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
+        grid = min(full, grid);
+    }
+    hipLaunchKernelGGL((hybrid_bwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
+                       reinterpret_cast<const float4*>(rec), hl, views, st, t_final, last, dl, n, d_rec, d_masks,
+                       queue);
+}
+
+#define MGS_HYBRID_SHAPES(X) \
+    X(8, 8, 1)               \
+    X(16, 8, 1)              \
+    X(16, 8, 2)              \
+    X(16, 16, 1)             \
+    X(16, 16, 2)             \
+    X(16, 16, 4)             \
+    X(32, 8, 1)              \
+    X(32, 8, 2)              \
+    X(32, 8, 4)
+
+HybridLists make_lists(const HybridBuffers& b) {
+    HybridLists hl;
+    hl.vals = b.vals;
+    hl.ranges = reinterpret_cast<const uint2*>(b.ranges);
+    hl.depth = b.depth;
+    hl.wide = reinterpret_cast<const uint4*>(b.wide);
+    hl.wide_range = reinterpret_cast<const uint2*>(b.wide_range);
+    hl.cur = reinterpret_cast<uint4*>(b.cur);
+    hl.cur_off = b.cur_off;
+    hl.nbatch = b.nbatch;
+    return hl;
+}
+
+}  // namespace
+
+void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
+                          uint64_t* keys, uint32_t* vals) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(record_keys64_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, depth, tiles,
+                       R, n, keys, vals);
+}
+
+void launch_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, int64_t R, int64_t n,
+                     const ViewSet& views, uint32_t* narrow_cnt, uint32_t* wide_flag) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, order, tiles, R, n,
+                       views, narrow_cnt, wide_flag);
+}
+
+void launch_wide_scatter(hipStream_t stream, const uint32_t* order, const uint32_t* wide_flag,
+                         const uint32_t* wide_pos, int64_t R, int64_t n, const float* rec, const float* radius,
+                         const float* depth, const ViewSet& views, const DevSettings& st, uint32_t* wide,
+                         int64_t wcap, uint32_t* flags) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(wide_scatter_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, order, wide_flag,
+                       wide_pos, R, n, reinterpret_cast<const float4*>(rec), radius, depth, views, st,
+                       reinterpret_cast<uint4*>(wide), wcap, flags);
+}
+
+void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
+                        int n_views, uint32_t* wide_range) {
+    hipLaunchKernelGGL(wide_ranges_kernel, dim3(1), dim3(64), 0, stream, wide_pos, wide_total, n, n_views,
+                       reinterpret_cast<uint2*>(wide_range));
+}
+
+void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
+                       int batch, uint32_t* caps) {
+    if (views.total_tiles == 0) return;
+    hipLaunchKernelGGL(batch_caps_kernel, dim3((views.total_tiles + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<const uint2*>(ranges), reinterpret_cast<const uint2*>(wide_range), views,
+                       batch, caps);
+}
+
+void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+                       const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
+                       int32_t* stats, uint32_t* queue, int num_cus) {
+    if (views.total_tiles == 0) return;
+    const HybridLists hl = make_lists(bufs);
+#define MGS_HFWD(A, B, P)                                                                                   \
+    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                               \
+        hybrid_fwd_t<A, B, P>(stream, num_cus, rec, hl, views, st, images, t_final, last, stats, queue);    \
+        return;                                                                                             \
+    }
+    MGS_HYBRID_SHAPES(MGS_HFWD)
+#undef MGS_HFWD
+}
+
+void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+                       const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
+                       const float* dl_dimages, int64_t n, float* d_rec, float* d_masks, uint32_t* queue,
+                       int num_cus) {
+    if (views.total_tiles == 0) return;
+    const HybridLists hl = make_lists(bufs);
+#define MGS_HBWD(A, B, P)                                                                                      \
+    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                  \
+        hybrid_bwd_t<A, B, P>(stream, num_cus, rec, hl, views, st, t_final, last, dl_dimages, n, d_rec, d_masks, \
+                              queue);                                                                          \
+        return;                                                                                                \
+    }
+    MGS_HYBRID_SHAPES(MGS_HBWD)
+#undef MGS_HBWD
+}
+
+}  // namespace mgs

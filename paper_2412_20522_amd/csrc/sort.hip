@@ -1,7 +1,16 @@
-// Binning and ordering of (tile, Gaussian) instances on gfx950:
-// exclusive scan of tile counts, key duplication, a stable LSD radix sort
-// of (tile << 32 | depth bits) keys, and per-tile ranges (Sec. 3.1: only
-// Gaussians that intersect a tile take part in that tile, in depth order).
+// Binning and ordering of (tile, Gaussian) instances on gfx950 (Sec. 3.1:
+// only Gaussians that intersect a tile take part in that tile, in depth
+// order).
+//
+// Two equivalent orderings are provided:
+//  - the literal one: duplicated 64-bit keys (tile << 32 | depth bits) with
+//    value = record id, sorted by a stable LSD radix sort over all
+//    significant bits (stage entry points mgs_duplicate / mgs_sort);
+//  - the one the whole path uses: records are first sorted by their 32-bit
+//    depth key (V*N elements), instances are then emitted in that order with
+//    32-bit tile ids, and a stable LSD sort over the tile bits alone (one or
+//    two passes) yields the same (tile, depth, record) order with a fraction
+//    of the memory traffic, since K is often 100x the record count.
 //
 // The sort is reduce-then-scan (per-block digit histograms, a device-wide
 // scan of the digit-major histogram, then a stable scatter); it has no
@@ -17,6 +26,7 @@ constexpr int NT = 256;
 constexpr int IPT = 16;
 constexpr int TILE = NT * IPT;  // 4096 elements per block
 constexpr int RADIX = 256;
+constexpr int64_t SORT_BLOCKS = 2048;  // 8 workgroups per CU on a 256-CU device
 
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
@@ -46,6 +56,8 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
     __syncthreads();
     return wo + inc - v;
 }
+
+inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
 
 // ---------------------------------------------------------------------------
 // scan of u32 counts (reduce, scan of block sums, downsweep)
@@ -122,7 +134,7 @@ __global__ void __launch_bounds__(NT) scan_down_kernel(const uint32_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// key duplication: one thread per record walks its tile rectangle
+// literal key duplication (stage API): one thread per record
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) duplicate_kernel(
@@ -136,26 +148,13 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     if (cnt == 0) return;
     const int vi = (int)(r / n_per_view);
     const DevView& cam = views.v[vi];
-    int x0, x1, y0, y1;
-    if (st.full_rect) {
-        x0 = 0; y0 = 0; x1 = cam.grid_w - 1; y1 = cam.grid_h - 1;
-    } else {
-        const float4 A = rec[3 * r];
-        const double ud = A.x, vd = A.y, rd = radius[r];
-        double fx0 = floor((ud - rd) / st.tile_w), fx1 = floor((ud + rd) / st.tile_w);
-        double fy0 = floor((vd - rd) / st.tile_h), fy1 = floor((vd + rd) / st.tile_h);
-        // clamp into the grid before converting (values can be far outside it)
-        x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.grid_w);
-        y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.grid_h);
-        x1 = (int)fmax(fmin(fx1, (double)(cam.grid_w - 1)), -1.0);
-        y1 = (int)fmax(fmin(fy1, (double)(cam.grid_h - 1)), -1.0);
-    }
+    const Rect q = record_rect(rec, radius, r, cam, st);
     const uint64_t dbits = (uint64_t)__float_as_uint(depth[r]);
     int64_t off = offsets[r];
     bool overflow = false;
-    for (int ty = y0; ty <= y1; ++ty) {
+    for (int ty = q.y0; ty <= q.y1; ++ty) {
         const uint64_t row = (uint64_t)cam.tile_off + (uint64_t)ty * cam.grid_w;
-        for (int tx = x0; tx <= x1; ++tx) {
+        for (int tx = q.x0; tx <= q.x1; ++tx) {
             if (off < capacity) {
                 keys[off] = ((row + tx) << 32) | dbits;
                 vals[off] = (uint32_t)r;
@@ -169,7 +168,96 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, 8 bits per pass
+// depth-ordered binning (whole path)
+// ---------------------------------------------------------------------------
+
+// Sort key of every record: its depth bits (positive floats order like their
+// bit patterns); records without tiles sort last.
+__global__ void __launch_bounds__(256) record_keys_kernel(const float* __restrict__ depth,
+                                                           const uint32_t* __restrict__ tiles, int64_t R,
+                                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    keys[r] = tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu;
+    vals[r] = (uint32_t)r;
+}
+
+__global__ void __launch_bounds__(256) gather_u32_kernel(const uint32_t* __restrict__ src,
+                                                          const uint32_t* __restrict__ idx, int64_t n,
+                                                          uint32_t* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// Instances of the records in depth order: sorted position i holds record
+// order[i] with tile count cnt[i] starting at offsets[i].  Records with few
+// tiles are written by their own lane; a record with many tiles is written by
+// the whole wave, 64 consecutive instances per store.
+constexpr uint32_t COOP_MIN = 16;
+
+__global__ void __launch_bounds__(256) duplicate_sorted_kernel(
+    const float4* __restrict__ rec, const float* __restrict__ radius, const uint32_t* __restrict__ order,
+    const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ offsets, int64_t R, int64_t n_per_view,
+    ViewSet views, DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
+    uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    uint32_t cnt = 0, r = 0;
+    int64_t off = 0;
+    int x0 = 0, y0 = 0, w = 1, gw = 1;
+    uint32_t toff = 0;
+    if (i < R) {
+        cnt = cnt_sorted[i];
+        if (cnt) {
+            r = order[i];
+            off = offsets[i];
+            const int vi = (int)(r / n_per_view);
+            const DevView& cam = views.v[vi];
+            const Rect q = record_rect(rec, radius, r, cam, st);
+            x0 = q.x0;
+            y0 = q.y0;
+            w = q.x1 - q.x0 + 1;
+            gw = cam.grid_w;
+            toff = cam.tile_off;
+        }
+    }
+    bool overflow = false;
+    const bool coop = cnt >= COOP_MIN;
+    if (!coop && cnt) {
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const int64_t o = off + j;
+            if (o < capacity) {
+                const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
+                keys[o] = toff + (uint32_t)(y0 + (int)ty) * (uint32_t)gw + (uint32_t)(x0 + (int)tx);
+                vals[o] = r;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    uint64_t pending = __ballot(coop);
+    while (pending) {
+        const int src = __ffsll((long long)pending) - 1;
+        pending &= pending - 1;
+        const uint32_t bc = __shfl(cnt, src), br = __shfl(r, src), bt = __shfl(toff, src);
+        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bgw = __shfl(gw, src);
+        const int64_t bo = __shfl(off, src);
+        for (uint32_t j = lane; j < bc; j += 64) {
+            const int64_t o = bo + j;
+            if (o < capacity) {
+                const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
+                keys[o] = bt + (uint32_t)(by0 + (int)ty) * (uint32_t)bgw + (uint32_t)(bx0 + (int)tx);
+                vals[o] = br;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    if (overflow) atomicOr(flags, FLAG_CAPACITY);
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8 bits per pass, 32- or 64-bit keys with u32 values
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int64_t live_count(int64_t K, const uint64_t* K_dev) {
@@ -178,21 +266,62 @@ __device__ __forceinline__ int64_t live_count(int64_t K, const uint64_t* K_dev) 
     return (int64_t)(k < (uint64_t)K ? k : (uint64_t)K);
 }
 
-__global__ void __launch_bounds__(NT) radix_upsweep_kernel(const uint64_t* __restrict__ keys, int64_t Kcap,
+template <typename KeyT>
+__device__ __forceinline__ uint32_t digit_of(KeyT k, int shift) {
+    return (uint32_t)(k >> shift) & (RADIX - 1);
+}
+
+// Per-block digit histograms, written digit-major: hist[d * nb + block].
+// Loads are vectorised and coalesced; each lane counts runs of equal digits
+// in registers before touching LDS, so keys clustered by digit (neighbouring
+// tiles of one splat) do not serialise on one LDS counter.
+// Each block owns a contiguous chunk of `chunk` keys (a multiple of TILE),
+// so a couple of thousand blocks cover any K and the digit-major histogram
+// stays small.
+template <typename KeyT>
+__global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restrict__ keys, int64_t Kcap,
                                                             const uint64_t* __restrict__ K_dev, int shift,
-                                                            uint32_t* __restrict__ hist, int64_t nb) {
+                                                            uint32_t* __restrict__ hist, int64_t nb, int64_t chunk) {
+    constexpr int VEC = 16 / sizeof(KeyT);  // keys per 16-byte load
     __shared__ uint32_t h[NT / 64][RADIX];
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&h[0][0])[i] = 0u;
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-#pragma unroll 4
-    for (int j = 0; j < IPT; ++j) {
-        const int64_t i = base + j * NT + threadIdx.x;
-        if (i < K) {
-            const uint32_t d = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
-            atomicAdd(&h[w][d], 1u);
+    const int64_t cbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t cend = min(cbeg + chunk, K);
+    for (int64_t base = cbeg; base < cend; base += TILE)
+#pragma unroll
+    for (int j = 0; j < IPT / VEC; ++j) {
+        const int64_t i0 = base + ((int64_t)j * NT + threadIdx.x) * VEC;
+        KeyT k[VEC];
+        int nv = 0;
+        if (i0 + VEC <= cend) {
+            if constexpr (VEC == 4) {
+                const uint4 q = *reinterpret_cast<const uint4*>(keys + i0);
+                k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+            } else {
+                const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(keys + i0);
+                k[0] = q.x; k[1] = q.y;
+            }
+            nv = VEC;
+        } else {
+            for (int v = 0; v < VEC; ++v)
+                if (i0 + v < cend) { k[v] = keys[i0 + v]; nv = v + 1; }
+        }
+        if (nv > 0) {
+            uint32_t cur = digit_of(k[0], shift), run = 1;
+            for (int v = 1; v < nv; ++v) {
+                const uint32_t d = digit_of(k[v], shift);
+                if (d == cur) {
+                    ++run;
+                } else {
+                    atomicAdd(&h[w][cur], run);
+                    cur = d;
+                    run = 1;
+                }
+            }
+            atomicAdd(&h[w][cur], run);
         }
     }
     __syncthreads();
@@ -203,11 +332,12 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const uint64_t* __res
     hist[(int64_t)d * nb + blockIdx.x] = s;
 }
 
+template <typename KeyT>
 __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
-    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint64_t* __restrict__ keys_out,
+    const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KeyT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
-    const uint32_t* __restrict__ hist_scan, int64_t nb) {
-    __shared__ uint64_t sk[TILE];
+    const uint32_t* __restrict__ hist_scan, int64_t nb, int64_t chunk) {
+    __shared__ KeyT sk[TILE];
     __shared__ uint32_t sv[TILE];
     __shared__ uint32_t wcnt[NT / 64][RADIX];
     __shared__ uint32_t dstart[RADIX];
@@ -215,16 +345,20 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     __shared__ uint32_t scan_sh[NT / 64];
 
     const int64_t K = live_count(Kcap, K_dev);
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    if (base >= K) return;  // uniform over the block
-    const int nvalid = (int)min((int64_t)TILE, K - base);
+    const int64_t cbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t cend = min(cbeg + chunk, K);
+    if (cbeg >= cend) return;  // uniform over the block
     const int w = threadIdx.x >> 6, lane = lane_id();
+    // global start of each digit for this chunk, advanced after every sub-tile
+    gstart[threadIdx.x] = hist_scan[(int64_t)threadIdx.x * nb + blockIdx.x];
+    for (int64_t base = cbeg; base < cend; base += TILE) {
+    const int nvalid = (int)min((int64_t)TILE, cend - base);
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
     __syncthreads();
 
     // wave w owns the contiguous span [w * 1024, (w + 1) * 1024) of the block;
     // round j covers 64 consecutive items, lane l the (j * 64 + l)-th
-    uint64_t key[IPT];
+    KeyT key[IPT];
     uint32_t val[IPT];
     uint32_t rank[IPT];
 #pragma unroll
@@ -234,14 +368,14 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
             key[j] = keys_in[base + li];
             val[j] = vals_in[base + li];
         } else {
-            key[j] = ~0ull;  // digit 255 at every shift, ranked after every valid item
+            key[j] = ~(KeyT)0;  // digit 255 at every shift, ranked after every valid item
             val[j] = 0u;
         }
     }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        const uint32_t d = (uint32_t)(key[j] >> shift) & (RADIX - 1);
+        const uint32_t d = digit_of(key[j], shift);
         uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -255,6 +389,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     }
     __syncthreads();
     // per digit: offsets of each wave, block total, then block-wide digit starts
+    uint32_t digit_total;
     {
         const int d = threadIdx.x;
         uint32_t run = 0;
@@ -266,23 +401,29 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
         }
         uint32_t tot;
         dstart[d] = block_exclusive_scan(run, scan_sh, &tot);
-        gstart[d] = hist_scan[(int64_t)d * nb + blockIdx.x];
+        digit_total = run;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        const uint32_t d = (uint32_t)(key[j] >> shift) & (RADIX - 1);
+        const uint32_t d = digit_of(key[j], shift);
         const uint32_t pos = dstart[d] + wcnt[w][d] + rank[j];
         sk[pos] = key[j];
         sv[pos] = val[j];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nvalid; i += NT) {
-        const uint64_t k = sk[i];
-        const uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
+        const KeyT k = sk[i];
+        const uint32_t d = digit_of(k, shift);
         const uint32_t o = gstart[d] + (uint32_t)i - dstart[d];
         keys_out[o] = k;
         vals_out[o] = sv[i];
+    }
+    __syncthreads();
+    // padded items all carry digit 255 and sit past nvalid; they are not counted
+    const uint32_t pad = (threadIdx.x == RADIX - 1) ? (uint32_t)(TILE - nvalid) : 0u;
+    gstart[threadIdx.x] += digit_total - pad;
+    __syncthreads();
     }
 }
 
@@ -290,17 +431,18 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
 // tile ranges, fills, sums
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t* __restrict__ keys, int64_t Kcap,
-                                                           const uint64_t* __restrict__ K_dev,
+template <typename KeyT>
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const KeyT* __restrict__ keys, int64_t Kcap,
+                                                           const uint64_t* __restrict__ K_dev, int shift,
                                                            uint2* __restrict__ ranges) {
     const int64_t K = live_count(Kcap, K_dev);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    const uint32_t t = (uint32_t)(keys[k] >> 32);
+    const uint32_t t = (uint32_t)(keys[k] >> shift);
     if (k == 0) {
         ranges[t].x = 0;
     } else {
-        const uint32_t p = (uint32_t)(keys[k - 1] >> 32);
+        const uint32_t p = (uint32_t)(keys[k - 1] >> shift);
         if (p != t) {
             ranges[p].y = (uint32_t)k;
             ranges[t].x = (uint32_t)k;
@@ -366,7 +508,37 @@ __global__ void __launch_bounds__(NT) sum_i32x4_partial_kernel(const int4* __res
     }
 }
 
-inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
+template <typename KeyT>
+void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t* vals_alt, int64_t K,
+                  const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch, bool* out_in_alt) {
+    *out_in_alt = false;
+    if (K <= 1 && !K_dev) return;
+    if (end_bit <= begin_bit) return;
+    // about SORT_BLOCKS workgroups, each over a contiguous chunk of whole tiles
+    const int64_t ntiles = nblocks(K > 0 ? K : 1);
+    const int64_t tiles_per_block = (ntiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    const int64_t chunk = tiles_per_block * TILE;
+    const int64_t nb = (ntiles + tiles_per_block - 1) / tiles_per_block;
+    const int64_t hn = nb * RADIX;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
+    uint32_t* hist_scan = hist + hn;
+    char* scan_tmp = reinterpret_cast<char*>(hist_scan + hn);
+    scan_tmp = reinterpret_cast<char*>(((uintptr_t)scan_tmp + 255) & ~(uintptr_t)255);
+    KeyT* kin = keys;
+    uint32_t* vin = vals;
+    KeyT* kout = keys_alt;
+    uint32_t* vout = vals_alt;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(radix_upsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift,
+                           hist, nb, chunk);
+        launch_scan_u32(stream, hist, hn, hist_scan, nullptr, scan_tmp);
+        hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout,
+                           K, K_dev, shift, (const uint32_t*)hist_scan, nb, chunk);
+        KeyT* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+        *out_in_alt = !*out_in_alt;
+    }
+}
 
 }  // namespace
 
@@ -397,6 +569,28 @@ void launch_duplicate(hipStream_t stream, const float* rec, const float* radius,
                        views, st, keys, vals, capacity, flags);
 }
 
+void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
+                        uint32_t* vals) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(record_keys_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, depth, tiles, R,
+                       keys, vals);
+}
+
+void launch_gather_u32(hipStream_t stream, const uint32_t* src, const uint32_t* idx, int64_t n, uint32_t* dst) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src, idx, n, dst);
+}
+
+void launch_duplicate_sorted(hipStream_t stream, const float* rec, const float* radius, const uint32_t* order,
+                             const uint32_t* cnt_sorted, const uint32_t* offsets, int64_t R, int64_t n_per_view,
+                             const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
+                             int64_t capacity, uint32_t* flags) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(duplicate_sorted_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const float4*>(rec), radius, order, cnt_sorted, offsets, R, n_per_view, views,
+                       st, keys, vals, capacity, flags);
+}
+
 size_t sort_scratch_bytes(int64_t K) {
     const int64_t nb = nblocks(K > 0 ? K : 1);
     const int64_t hist = nb * RADIX;
@@ -405,36 +599,29 @@ size_t sort_scratch_bytes(int64_t K) {
 
 void launch_radix_sort(hipStream_t stream, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                        int64_t K, const uint64_t* K_dev, int key_bits, void* scratch, bool* out_in_alt) {
-    *out_in_alt = false;
-    if (K <= 1 && !K_dev) return;
-    const int64_t nb = nblocks(K > 0 ? K : 1);
-    const int64_t hn = nb * RADIX;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
-    uint32_t* hist_scan = hist + hn;
-    char* scan_tmp = reinterpret_cast<char*>(hist_scan + hn);
-    scan_tmp = reinterpret_cast<char*>(((uintptr_t)scan_tmp + 255) & ~(uintptr_t)255);
-    uint64_t* kin = keys;
-    uint32_t* vin = vals;
-    uint64_t* kout = keys_alt;
-    uint32_t* vout = vals_alt;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        hipLaunchKernelGGL(radix_upsweep_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift, hist,
-                           nb);
-        launch_scan_u32(stream, hist, hn, hist_scan, nullptr, scan_tmp);
-        hipLaunchKernelGGL(radix_downsweep_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout, K,
-                           K_dev, shift, (const uint32_t*)hist_scan, nb);
-        uint64_t* tk = kin; kin = kout; kout = tk;
-        uint32_t* tv = vin; vin = vout; vout = tv;
-        *out_in_alt = !*out_in_alt;
-    }
+    radix_sort_t<uint64_t>(stream, keys, vals, keys_alt, vals_alt, K, K_dev, 0, key_bits, scratch, out_in_alt);
+}
+
+void launch_radix_sort32(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                         int64_t K, const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch,
+                         bool* out_in_alt) {
+    radix_sort_t<uint32_t>(stream, keys, vals, keys_alt, vals_alt, K, K_dev, begin_bit, end_bit, scratch, out_in_alt);
 }
 
 void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, const uint64_t* K_dev,
                         int64_t total_tiles, uint32_t* ranges) {
     launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
     if (K == 0) return;
-    hipLaunchKernelGGL(tile_ranges_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K, K_dev,
-                       reinterpret_cast<uint2*>(ranges));
+    hipLaunchKernelGGL(tile_ranges_kernel<uint64_t>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K,
+                       K_dev, 32, reinterpret_cast<uint2*>(ranges));
+}
+
+void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, const uint64_t* K_dev,
+                          int64_t total_tiles, uint32_t* ranges) {
+    launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
+    if (K == 0) return;
+    hipLaunchKernelGGL(tile_ranges_kernel<uint32_t>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K,
+                       K_dev, 0, reinterpret_cast<uint2*>(ranges));
 }
 
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {

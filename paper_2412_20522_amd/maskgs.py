@@ -40,7 +40,8 @@ class mgs_settings(C.Structure):
                 ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float), ("q_max", C.c_float),
                 ("near_plane", C.c_float), ("dilation", C.c_float), ("jac_clamp", C.c_float),
                 ("lambda_floor", C.c_float), ("bg", C.c_float * 3), ("exact_mode", C.c_int32),
-                ("persistent", C.c_int32), ("fwd_ppt", C.c_int32), ("bwd_ppt", C.c_int32)]
+                ("persistent", C.c_int32), ("fwd_ppt", C.c_int32), ("bwd_ppt", C.c_int32),
+                ("wide_tiles", C.c_int32)]
 
 
 class mgs_gaussians(C.Structure):
@@ -58,15 +59,18 @@ class mgs_eval_counts(C.Structure):
                 ("bwd_examined", C.c_int64)]
 
 
-STAGES = ("project", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd", "project_bwd",
-          "sample_masks", "mask_grad", "loss", "adam")
+STAGES = ("project", "depth_sort", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd",
+          "project_bwd", "sample_masks", "mask_grad", "loss", "adam")
+EXPORTS = {"records": 0, "depth": 1, "radius": 2, "tiles": 3, "values": 4, "ranges": 5, "t_final": 6, "last": 7,
+           "stats": 8, "wide": 9, "wide_ranges": 10}
 MGS_NUM_STAGES = len(STAGES)
 
 
 class mgs_frame_stats(C.Structure):
     _fields_ = [("n_gaussians", C.c_int64), ("n_views", C.c_int64), ("n_records", C.c_int64),
                 ("n_pixels", C.c_int64), ("n_instances", C.c_int64), ("total_tiles", C.c_int64),
-                ("instance_capacity", C.c_int64), ("sort_passes", C.c_int32), ("tile_bits", C.c_int32)]
+                ("instance_capacity", C.c_int64), ("n_wide", C.c_int64), ("sort_passes", C.c_int32),
+                ("tile_bits", C.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -84,6 +88,7 @@ _SIGS = {
                               C.POINTER(mgs_settings), _VP, _VP]),
     "mgs_backward": (C.c_int, [_VP, _VP, _VP, C.POINTER(mgs_gradients)]),
     "mgs_frame_count_evals": (C.c_int, [_VP, _VP, C.POINTER(mgs_eval_counts)]),
+    "mgs_frame_export": (C.c_int, [_VP, _VP, C.c_int, _VP, C.POINTER(_SZ)]),
     "mgs_profile_enable": (C.c_int, [_VP, C.c_int]),
     "mgs_profile_read": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "mgs_project": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
@@ -269,6 +274,23 @@ def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:
     out = mgs_eval_counts()
     _check(ctx, _lib.mgs_frame_count_evals(frame, _stream(stream), C.byref(out)))
     return {k: int(getattr(out, k)) for k, _ in mgs_eval_counts._fields_}
+
+
+_EXPORT_DTYPES = {"records": torch.float32, "depth": torch.float32, "radius": torch.float32, "tiles": torch.int32,
+                  "values": torch.int32, "ranges": torch.int32, "t_final": torch.float32, "last": torch.int32,
+                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32}
+
+
+def mgs_frame_export(ctx, frame, what: str, stream=None) -> torch.Tensor:
+    """A copy of one array of the frame's last forward (u32 arrays as int32)."""
+    code = EXPORTS[what]
+    nbytes = C.c_size_t()
+    _check(ctx, _lib.mgs_frame_export(frame, _stream(stream), code, None, C.byref(nbytes)))
+    dt = _EXPORT_DTYPES[what]
+    esize = torch.tensor([], dtype=dt).element_size()
+    out = torch.empty(max(nbytes.value // esize, 1), dtype=dt, device="cuda")
+    _check(ctx, _lib.mgs_frame_export(frame, _stream(stream), code, C.c_void_p(out.data_ptr()), C.byref(nbytes)))
+    return out[:nbytes.value // esize]
 
 
 def mgs_profile_enable(ctx, on: bool = True) -> None:

@@ -110,6 +110,100 @@ def test_tiles_and_lists_match_oracle_bitwise(ctx):
             assert np.all(gr[~nonempty, 0] == gr[~nonempty, 1])
 
 
+def merged_tile_lists(cams, tw, th, vals, ranges, wide, wide_ranges, depth_bits):
+    """Per-tile lists of the hybrid binning: the tile's narrow entries merged
+    with its view's wide entries whose tile rectangle contains the tile, in
+    (depth bits, record) order."""
+    out = []
+    for v, c in enumerate(cams):
+        gw, gh = (c["width"] + tw - 1) // tw, (c["height"] + th - 1) // th
+        ws, we = wide_ranges[v]
+        wv = wide[ws:we]
+        x0, y0 = wv[:, 2] & 0xFFFF, wv[:, 2] >> 16
+        x1, y1 = wv[:, 3] & 0xFFFF, wv[:, 3] >> 16
+        for ty in range(gh):
+            for tx in range(gw):
+                t = len(out)
+                narrow = vals[ranges[t, 0]:ranges[t, 1]].astype(np.int64)
+                cover = (x0 <= tx) & (tx <= x1) & (y0 <= ty) & (ty <= y1)
+                recs = np.concatenate([narrow, wv[cover, 1].astype(np.int64)])
+                order = np.lexsort((recs, depth_bits[recs].astype(np.int64)))
+                out.append(recs[order])
+    return out
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+@pytest.mark.parametrize("wide_tiles", [-1, 0, 1])
+def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
+    """mgs_forward bins in depth order, duplicates only records with few
+    tiles and keeps the others once per view in a wide list; the per-tile
+    merge of the two must equal the oracle's (tile, depth, record) lists
+    exactly, and the last blended entry and entries examined per pixel (as
+    indices into the merged list) must equal the oracle's."""
+    M = U.M()
+    s = _scene(kind)
+    cams = s["cameras"]
+    tw, th = tile
+    bg = (0.3, 0.5, 0.7)
+    ost, gst = U.settings_pair(sh_degree=s["sh_degree"], tile_w=tw, tile_h=th, fwd_ppt=1, bwd_ppt=1,
+                               wide_tiles=wide_tiles, batch_depth=64, bg=bg)
+    dev = U.to_device(s)
+    frame = M.mgs_frame_create(ctx)
+    try:
+        P = sum(c["width"] * c["height"] for c in cams)
+        img = torch.empty(3 * P, device="cuda")
+        M.mgs_forward(ctx, frame, U.gstruct(dev), cams, gst, img)
+        ex = {k: M.mgs_frame_export(ctx, frame, k) for k in
+              ("records", "radius", "depth", "values", "ranges", "wide", "wide_ranges", "last", "stats", "t_final")}
+        st = M.mgs_frame_get_stats(frame)
+        torch.cuda.synchronize()
+    finally:
+        M.mgs_frame_destroy(frame)
+    n = s["means"].shape[0]
+    rec = ex["records"].view(-1, 12)
+    oi = U.oracle_inputs_from_rec(rec)
+    rad = ex["radius"].cpu().numpy().astype(np.float64)
+    dbits = U.u32(ex["depth"])
+    ol = oracle.build_lists([c["width"] for c in cams], [c["height"] for c in cams], n, oi["mean2d"], rad, dbits,
+                            (rad > 0).astype(np.uint8), ost)
+    wide = U.u32(ex["wide"]).reshape(-1, 4)
+    assert wide.shape[0] == st["n_wide"]
+    if wide_tiles < 0:
+        assert st["n_wide"] == 0
+    if wide_tiles == 1:
+        assert st["n_wide"] > 0
+    lists = merged_tile_lists(cams, tw, th, U.u32(ex["values"]), U.u32(ex["ranges"]).reshape(-1, 2), wide,
+                              U.u32(ex["wide_ranges"]).reshape(-1, 2), dbits)
+    assert len(lists) == ol.ranges.shape[0]
+    assert st["n_instances"] == U.u32(ex["values"]).size
+    for t, lst in enumerate(lists):
+        a, b = ol.ranges[t]
+        assert np.array_equal(lst, ol.vals[a:b].astype(np.int64)), t
+    # per pixel: last blended entry and entries examined, local to the tile list
+    of = oracle.render_fwd([c["width"] for c in cams], [c["height"] for c in cams], n, oi["mean2d"], oi["conic"],
+                           oi["opacity"], oi["color"], s["masks"].astype(np.float64), ol, ost)
+    ok = of.flags == 0
+    assert ok.mean() > 0.99
+    start = np.empty(P, np.int64)
+    off = 0
+    toff = 0
+    for c in cams:
+        w, h = c["width"], c["height"]
+        gw = (w + tw - 1) // tw
+        yy, xx = np.divmod(np.arange(w * h), w)
+        start[off:off + w * h] = ol.ranges[toff + (yy // th) * gw + xx // tw, 0]
+        off += w * h
+        toff += gw * ((h + th - 1) // th)
+    o_last = np.where(of.last >= 0, of.last - start, -1)
+    assert np.array_equal(ex["last"].cpu().numpy()[ok], o_last[ok])
+    stats = ex["stats"].cpu().numpy().reshape(-1, 4)
+    assert np.array_equal(stats[ok, 0], of.examined[ok])
+    assert np.abs(ex["t_final"].cpu().numpy() - of.t_final)[ok].max() <= 1e-5
+    gi = img.cpu().numpy().astype(np.float64)
+    assert U.rel_err(gi, of.image) <= 1e-4
+
+
 # ---------------------------------------------------------------------------
 # scan and sort on synthetic inputs (bit-exact against the definitions)
 # ---------------------------------------------------------------------------
@@ -128,7 +222,8 @@ def test_scan_matches_cumsum(ctx, n):
     assert int(total.item()) == int(a.astype(np.uint64).sum())
 
 
-@pytest.mark.parametrize("K,bits", [(2, 40), (4096, 38), (4097, 46), (100_001, 47), (300_000, 64)])
+@pytest.mark.parametrize("K,bits", [(2, 40), (4096, 38), (4097, 46), (100_001, 47), (300_000, 64),
+                                    (9_000_003, 48)])
 def test_sort_is_stable_and_matches_lexsort(ctx, K, bits):
     rng = np.random.default_rng(K)
     tiles = rng.integers(0, 1 << max(bits - 32, 0), K, dtype=np.uint64) if bits > 32 else np.zeros(K, np.uint64)
