@@ -191,15 +191,18 @@ MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float
  * caller-owned, at least the reported size):
  *   MGS_EXPORT_RECORDS  [R, 12] f32 projected records (layout of mgs_project)
  *   MGS_EXPORT_DEPTH    [R] f32, MGS_EXPORT_RADIUS [R] f32, MGS_EXPORT_TILES [R] u32
- *   MGS_EXPORT_VALUES   [K] u32 record ids in (tile, depth, record) order
+ *   MGS_EXPORT_VALUES   [K] u32 narrow instances in (tile, depth, record) order,
+ *                       as positions into ORDER
  *   MGS_EXPORT_RANGES   [total_tiles, 2] u32
  *   MGS_EXPORT_T_FINAL  [P] f32, MGS_EXPORT_LAST [P] i32
  *   MGS_EXPORT_STATS    [P, 4] i32 (examined, blended, blended with mask 0,
  *                       entries up to the last blended one)
  *   MGS_EXPORT_WIDE     [W, 4] u32 wide entries per view in (depth, record)
- *                       order: depth bits, record, x0 | y0 << 16, x1 | y1 << 16
- *                       (inclusive tile rectangle)
+ *                       order: position into ORDER, record, x0 | y0 << 16,
+ *                       x1 | y1 << 16 (inclusive tile rectangle)
  *   MGS_EXPORT_WIDE_RANGES [n_views, 2] u32 [start, end) into the wide entries
+ *   MGS_EXPORT_ORDER    [R] u32 record ids in (view, depth, record) order,
+ *                       records without tiles last within their view
  * VALUES and RANGES hold the narrow instances only; a tile's list is their
  * merge with the wide entries of its view whose rectangle contains it, and
  * LAST holds indices into that merged list.
@@ -215,7 +218,8 @@ typedef enum {
     MGS_EXPORT_LAST,
     MGS_EXPORT_STATS,
     MGS_EXPORT_WIDE,
-    MGS_EXPORT_WIDE_RANGES
+    MGS_EXPORT_WIDE_RANGES,
+    MGS_EXPORT_ORDER
 } mgs_export;
 MGS_API mgs_status mgs_frame_export(mgs_frame* frame, mgs_stream stream, int what, void* dst, size_t* bytes);
 

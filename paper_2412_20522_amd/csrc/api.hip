@@ -266,7 +266,7 @@ struct mgs_frame {
     bool sorted_in_alt = false, order_in_alt = false;
     // device buffers: per record, then per narrow instance (32-bit tile keys),
     // wide entries, per tile, per pixel
-    DevBuf rec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, wide_pos;
+    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, wide_pos;
     DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats;
     DevBuf d_rec, d_masks_tmp, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;
     // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
@@ -280,9 +280,8 @@ struct mgs_frame {
     uint64_t* wide_total() { return (uint64_t*)((char*)misc.p + 16); }
     uint32_t* wide_range() { return (uint32_t*)((char*)misc.p + 32); }
     HybridBuffers hybrid() {
-        return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const float*)depth.p,
-                             (const uint32_t*)wide.p, wide_range(), (uint32_t*)cur.p,
-                             (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p};
+        return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const uint32_t*)wide.p, wide_range(),
+                             (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p};
     }
 };
 
@@ -307,8 +306,8 @@ mgs_status mgs_default_settings(mgs_settings* out) {
     out->lambda_floor = 0.1f;
     out->exact_mode = 0;
     out->persistent = 0;
-    out->fwd_ppt = 1;
-    out->bwd_ppt = 4;
+    out->fwd_ppt = 2;
+    out->bwd_ppt = 2;
     out->wide_tiles = 0;
     return MGS_OK;
 }
@@ -362,7 +361,7 @@ mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
 mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&f->rec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
+    DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
                       &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
                       &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->t_final,  &f->last,
@@ -414,7 +413,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->tile_bits = bits_for((uint64_t)f->total_tiles);
     const int64_t R = f->R, P = f->P, T = f->total_tiles;
     const int V = n_views;
-    if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
+    if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->srec, (size_t)R * 48 + 16)) ||
+        (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
@@ -435,7 +435,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     }
     {
         // records in (view, depth, record) order, those without tiles last in
-        // their view; then narrow tile counts and wide flags in that order
+        // their view; then the sorted record copy, narrow tile counts and
+        // wide flags in that order
         StageTimer t(ctx, stream, MGS_STAGE_DEPTH_SORT);
         launch_record_keys64(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R, f->n,
                              (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
@@ -443,8 +444,9 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         launch_radix_sort(stream, (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint64_t*)f->rkeys_alt.p,
                           (uint32_t*)f->rvals_alt.p, R, nullptr, 32 + bits_for((uint64_t)V), f->rsort_tmp.p, &alt);
         f->order_in_alt = alt;
-        launch_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, R, f->n, f->views,
-                        (uint32_t*)f->cnt_sorted.p, (uint32_t*)f->wide_flag.p);
+        launch_permute_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, (const float*)f->rec.p,
+                                (const float*)f->radius.p, R, f->n, f->views, (uint32_t*)f->cnt_sorted.p,
+                                (uint32_t*)f->wide_flag.p, (float*)f->srec.p);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_SCAN);
@@ -487,13 +489,11 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 4, f->vals.bytes / 4);
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
-        launch_duplicate_sorted(stream, (const float*)f->rec.p, (const float*)f->radius.p, f->record_order(),
-                                (const uint32_t*)f->cnt_sorted.p, (const uint32_t*)f->offsets.p, R, f->n, f->views,
-                                f->st, (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
-        launch_wide_scatter(stream, f->record_order(), (const uint32_t*)f->wide_flag.p,
-                            (const uint32_t*)f->wide_pos.p, R, f->n, (const float*)f->rec.p,
-                            (const float*)f->radius.p, (const float*)f->depth.p, f->views, f->st,
-                            (uint32_t*)f->wide.p, f->W, f->flags());
+        launch_duplicate_narrow(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
+                                (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
+                                (uint32_t*)f->vals.p, f->K, f->flags());
+        launch_wide_scatter(stream, (const uint32_t*)f->wide_flag.p, (const uint32_t*)f->wide_pos.p, R, f->n,
+                            (const float*)f->srec.p, f->views, f->st, (uint32_t*)f->wide.p, f->W, f->flags());
     }
     // instances are already in (depth, record) order: a stable sort on the
     // tile bits alone gives the (tile, depth, record) order
@@ -519,7 +519,7 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
-        launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->rec.p, f->hybrid(), f->views, f->st, images,
+        launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st, images,
                           (float*)f->t_final.p, (int32_t*)f->last.p, (int32_t*)f->stats.p, queue, ctx->num_cus);
     }
     MGS_CHECK_LAUNCH(ctx);
@@ -553,7 +553,7 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_BWD);
-        launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->rec.p, f->hybrid(), f->views, f->st,
+        launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st,
                           (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
                           (float*)f->d_rec.p, d_masks, queue, ctx->num_cus);
     }
@@ -603,6 +603,7 @@ mgs_status mgs_frame_export(mgs_frame* f, mgs_stream stream, int what, void* dst
         case MGS_EXPORT_STATS: src = f->stats.p; n = (size_t)f->P * 16; break;
         case MGS_EXPORT_WIDE: src = f->wide.p; n = (size_t)f->W * 16; break;
         case MGS_EXPORT_WIDE_RANGES: src = f->wide_range(); n = (size_t)f->n_views * 8; break;
+        case MGS_EXPORT_ORDER: src = f->record_order(); n = (size_t)f->R * 4; break;
         default: return fail(ctx, MGS_ERR_INVALID_ARG, "unknown export %d", what);
     }
     *bytes = n;

@@ -56,15 +56,13 @@ struct Rect {
     int x0, y0, x1, y1;
 };
 
-__device__ __forceinline__ Rect record_rect(const float4* __restrict__ rec, const float* __restrict__ radius,
-                                            int64_t r, const DevView& cam, const DevSettings& st) {
+__device__ __forceinline__ Rect rect_of(float u, float v, float radius, const DevView& cam, const DevSettings& st) {
     Rect q;
     if (st.full_rect) {
         q.x0 = 0; q.y0 = 0; q.x1 = cam.grid_w - 1; q.y1 = cam.grid_h - 1;
         return q;
     }
-    const float4 A = rec[3 * r];
-    const double ud = A.x, vd = A.y, rd = radius[r];
+    const double ud = u, vd = v, rd = radius;
     const double fx0 = floor((ud - rd) / st.tile_w), fx1 = floor((ud + rd) / st.tile_w);
     const double fy0 = floor((vd - rd) / st.tile_h), fy1 = floor((vd + rd) / st.tile_h);
     // clamp into the grid before converting (values can be far outside it)
@@ -73,6 +71,12 @@ __device__ __forceinline__ Rect record_rect(const float4* __restrict__ rec, cons
     q.x1 = (int)fmax(fmin(fx1, (double)(cam.grid_w - 1)), -1.0);
     q.y1 = (int)fmax(fmin(fy1, (double)(cam.grid_h - 1)), -1.0);
     return q;
+}
+
+__device__ __forceinline__ Rect record_rect(const float4* __restrict__ rec, const float* __restrict__ radius,
+                                            int64_t r, const DevView& cam, const DevSettings& st) {
+    const float4 A = rec[3 * r];
+    return rect_of(A.x, A.y, radius[r], cam, st);
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

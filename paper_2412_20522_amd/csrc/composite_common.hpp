@@ -55,9 +55,10 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t* queue, uint32_t* s_tile,
 // Workgroups a persistent launch needs to fill the device: resident blocks
 // per CU at the kernel's register and LDS use, times the CU count.
 template <typename Kernel>
-inline int persistent_grid(Kernel k, int block, int num_cus) {
+inline int persistent_grid(Kernel k, int block, int num_cus, size_t dyn_lds = 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess || per_cu <= 0) per_cu = 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, dyn_lds) != hipSuccess || per_cu <= 0)
+        per_cu = 4;
     return per_cu * num_cus;
 }
 

@@ -8,10 +8,15 @@
 // footprint covers the tile, in depth order -- is then the merge of the
 // tile's narrow entries with the wide entries whose rectangle contains the
 // tile.  The compositing kernels form that merged list batch by batch in LDS
-// (merge path over two depth-ordered windows), so the entries, their order
-// and the per-pixel results are exactly those of fully duplicated lists,
-// while the instance sort shrinks from every (tile, wide splat) pair to the
-// narrow pairs only.
+// (merge path over two ordered windows), so the entries, their order and the
+// per-pixel results are exactly those of fully duplicated lists, while the
+// instance sort shrinks from every (tile, wide splat) pair to the narrow
+// pairs only.
+//
+// Records are copied once into (view, depth, record) order ("sorted
+// records"); list entries hold positions in that order, which are unique and
+// order exactly as (depth, record) within a view, so the merge compares plain
+// 32-bit positions and the record gathers of a tile walk memory upwards.
 //
 // The forward records, per tile and batch, the stream cursors where the batch
 // began; the backward replays the same batches in reverse from those
@@ -25,7 +30,8 @@ namespace mgs {
 namespace {
 
 // ---------------------------------------------------------------------------
-// binning: (view, depth) order of records, wide list, batch checkpoints
+// binning: (view, depth) order of records, sorted records, wide list, batch
+// checkpoints
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restrict__ depth,
@@ -39,40 +45,115 @@ __global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restr
     vals[r] = (uint32_t)r;
 }
 
-__global__ void __launch_bounds__(256) classify_kernel(const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ tiles, int64_t R, int64_t n,
-                                                        ViewSet views, uint32_t* __restrict__ narrow_cnt,
-                                                        uint32_t* __restrict__ wide_flag) {
+// Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
+// to view v.  Writes the sorted record copy (radius in B.w, record id bits in
+// C.w), the narrow tile count and the wide flag of every position.
+__global__ void __launch_bounds__(256) permute_classify_kernel(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles, const float4* __restrict__ rec,
+    const float* __restrict__ radius, int64_t R, int64_t n, ViewSet views, uint32_t* __restrict__ narrow_cnt,
+    uint32_t* __restrict__ wide_flag, float4* __restrict__ srec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R) return;
     const uint32_t r = order[i];
     const uint32_t c = tiles[r];
-    const bool wide = c > views.v[r / n].wide_min;
+    const bool wide = c > views.v[i / n].wide_min;
     narrow_cnt[i] = wide ? 0u : c;
     wide_flag[i] = wide ? 1u : 0u;
+    float4 A = rec[3 * (size_t)r], B = rec[3 * (size_t)r + 1];
+    uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
+    B.w = radius[r];
+    C.w = r;
+    srec[3 * i] = A;
+    srec[3 * i + 1] = B;
+    reinterpret_cast<uint4*>(srec)[3 * i + 2] = C;
 }
 
-// Wide entry: x = depth bits, y = record, z = x0 | y0 << 16, w = x1 | y1 << 16.
-__global__ void __launch_bounds__(256) wide_scatter_kernel(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ wide_flag, const uint32_t* __restrict__ wide_pos,
-    int64_t R, int64_t n, const float4* __restrict__ rec, const float* __restrict__ radius,
-    const float* __restrict__ depth, ViewSet views, DevSettings st, uint4* __restrict__ wide, int64_t wcap,
-    uint32_t* __restrict__ flags) {
+// Narrow instances in sorted-position order: tile ids as keys, positions as
+// values.  Records with many tiles are spread over the lanes of a wave.
+constexpr uint32_t COOP_MIN = 16;
+
+__global__ void __launch_bounds__(256) duplicate_narrow_kernel(
+    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ offsets,
+    int64_t R, int64_t n, ViewSet views, DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    int64_t capacity, uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    uint32_t cnt = 0;
+    int64_t off = 0;
+    int x0 = 0, y0 = 0, w = 1, gw = 1;
+    uint32_t toff = 0;
+    if (i < R) {
+        cnt = cnt_sorted[i];
+        if (cnt) {
+            off = offsets[i];
+            const DevView& cam = views.v[i / n];
+            const float4 A = srec[3 * i], B = srec[3 * i + 1];
+            const Rect q = rect_of(A.x, A.y, B.w, cam, st);
+            x0 = q.x0;
+            y0 = q.y0;
+            w = q.x1 - q.x0 + 1;
+            gw = cam.grid_w;
+            toff = cam.tile_off;
+        }
+    }
+    bool overflow = false;
+    const bool coop = cnt >= COOP_MIN;
+    if (!coop && cnt) {
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const int64_t o = off + j;
+            if (o < capacity) {
+                const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
+                keys[o] = toff + (uint32_t)(y0 + (int)ty) * (uint32_t)gw + (uint32_t)(x0 + (int)tx);
+                vals[o] = (uint32_t)i;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    uint64_t pending = __ballot(coop);
+    while (pending) {
+        const int src = __ffsll((long long)pending) - 1;
+        pending &= pending - 1;
+        const uint32_t bc = __shfl(cnt, src), bt = __shfl(toff, src);
+        const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)i, src);
+        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bgw = __shfl(gw, src);
+        const int64_t bo = __shfl(off, src);
+        for (uint32_t j = lane; j < bc; j += 64) {
+            const int64_t o = bo + j;
+            if (o < capacity) {
+                const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
+                keys[o] = bt + (uint32_t)(by0 + (int)ty) * (uint32_t)bgw + (uint32_t)(bx0 + (int)tx);
+                vals[o] = bi;
+            } else {
+                overflow = true;
+            }
+        }
+    }
+    if (overflow) atomicOr(flags, FLAG_CAPACITY);
+}
+
+// Wide entry: x = sorted position, y = record, z = x0 | y0 << 16,
+// w = x1 | y1 << 16 (inclusive tile rectangle).
+__global__ void __launch_bounds__(256) wide_scatter_kernel(const uint32_t* __restrict__ wide_flag,
+                                                            const uint32_t* __restrict__ wide_pos, int64_t R,
+                                                            int64_t n, const float4* __restrict__ srec,
+                                                            ViewSet views, DevSettings st, uint4* __restrict__ wide,
+                                                            int64_t wcap, uint32_t* __restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= R || !wide_flag[i]) return;
-    const uint32_t r = order[i];
-    const Rect q = record_rect(rec, radius, r, views.v[r / n], st);
+    const float4 A = srec[3 * i], B = srec[3 * i + 1];
+    const uint32_t r = reinterpret_cast<const uint4*>(srec)[3 * i + 2].w;
+    const Rect q = rect_of(A.x, A.y, B.w, views.v[i / n], st);
     const uint32_t p = wide_pos[i];
     if (p < wcap) {
-        wide[p] = make_uint4(__float_as_uint(depth[r]), r, (uint32_t)q.x0 | ((uint32_t)q.y0 << 16),
+        wide[p] = make_uint4((uint32_t)i, r, (uint32_t)q.x0 | ((uint32_t)q.y0 << 16),
                              (uint32_t)q.x1 | ((uint32_t)q.y1 << 16));
     } else {
         atomicOr(flags, FLAG_CAPACITY);
     }
 }
 
-// [start, end) of every view's wide records (records are grouped by view in
-// the sorted order, n per view).
+// [start, end) of every view's wide entries.
 __global__ void wide_ranges_kernel(const uint32_t* __restrict__ wide_pos, const uint64_t* __restrict__ wide_total,
                                    int64_t n, int nv, uint2* __restrict__ wide_range) {
     const int v = threadIdx.x;
@@ -101,23 +182,41 @@ __global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// merging two depth-ordered streams in LDS
+// merging two ordered streams in LDS
 // ---------------------------------------------------------------------------
 
-struct MergeLDS {
-    uint64_t xk[MAXB];      // narrow window keys (depth bits << 32 | record)
-    uint64_t yk_raw[MAXB];  // wide window keys, before the rectangle test
-    uint64_t yk[MAXB];      // wide entries covering this tile
-    uint32_t xr[MAXB];
-    uint32_t yr_raw[MAXB];
-    uint32_t yr[MAXB];
-    uint32_t ypass[MAXB];
-    uint32_t m[MAXB];       // merged records of the batch
-    float4 A[MAXB], B[MAXB], C[MAXB];
-    uint32_t wsum[MAXB / 64 + 4];
+// Dynamic LDS of one workgroup for batch depth B: the staged records of the
+// batch (3 float4 per entry) share their space with the merge windows, which
+// are dead once the merged positions are known.
+struct Lds {
+    uint32_t* xk;     // narrow window (sorted positions)
+    uint32_t* yraw;   // wide window (sorted positions), before the rectangle test
+    uint32_t* yk;     // wide entries of the window that cover this tile
+    uint8_t* ypass;   // rectangle test of the wide window
+    float4* A;        // staged records of the batch
+    float4* Bv;
+    float4* C;
+    uint32_t* m;      // merged positions of the batch
+    uint32_t* wsum;   // per-wave partial counts
 };
 
-__device__ __forceinline__ int count_le(const uint64_t* a, int n, uint64_t key) {
+__host__ __device__ constexpr size_t lds_bytes(int batch) { return (size_t)batch * (48 + 4) + 64; }
+
+__device__ __forceinline__ Lds carve(char* smem, int batch) {
+    Lds L;
+    L.A = reinterpret_cast<float4*>(smem);
+    L.Bv = L.A + batch;
+    L.C = L.Bv + batch;
+    L.xk = reinterpret_cast<uint32_t*>(smem);
+    L.yraw = L.xk + batch;
+    L.yk = L.yraw + batch;
+    L.ypass = reinterpret_cast<uint8_t*>(L.yk + batch);
+    L.m = reinterpret_cast<uint32_t*>(smem + 48 * (size_t)batch);
+    L.wsum = L.m + batch;
+    return L;
+}
+
+__device__ __forceinline__ int count_le(const uint32_t* a, int n, uint32_t key) {
     int lo = 0, hi = n;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -127,7 +226,7 @@ __device__ __forceinline__ int count_le(const uint64_t* a, int n, uint64_t key) 
     return lo;
 }
 
-__device__ __forceinline__ int count_lt(const uint64_t* a, int n, uint64_t key) {
+__device__ __forceinline__ int count_lt(const uint32_t* a, int n, uint32_t key) {
     int lo = 0, hi = n;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -165,30 +264,26 @@ struct Batch {
 
 // Stages the next (at most `batch`) entries of the tile's merged list in LDS.
 // Every thread of the block calls it; the result is uniform.
-__device__ Batch merge_batch(MergeLDS& L, const uint32_t* __restrict__ vals, const float* __restrict__ depth,
-                             const uint4* __restrict__ wide, const float4* __restrict__ rec, int i1, int e1, int i2,
-                             int e2, int batch, int tcx, int tcy) {
+__device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, const uint4* __restrict__ wide,
+                             const float4* __restrict__ srec, int i1, int e1, int i2, int e2, int batch, int tcx,
+                             int tcy) {
     const int t = threadIdx.x, NT = blockDim.x;
     const int cX = min(batch, e1 - i1), cY = min(batch, e2 - i2);
-    for (int l = t; l < cX; l += NT) {
-        const uint32_t r = vals[i1 + l];
-        L.xr[l] = r;
-        L.xk[l] = ((uint64_t)__float_as_uint(depth[r]) << 32) | r;
-    }
+    for (int l = t; l < cX; l += NT) L.xk[l] = vals[i1 + l];
     for (int l = t; l < cY; l += NT) {
         const uint4 w = wide[i2 + l];
-        L.yr_raw[l] = w.y;
-        L.yk_raw[l] = ((uint64_t)w.x << 32) | w.y;
+        L.yraw[l] = w.x;
         const int x0 = (int)(w.z & 0xffffu), y0 = (int)(w.z >> 16), x1 = (int)(w.w & 0xffffu), y1 = (int)(w.w >> 16);
-        L.ypass[l] = (tcx >= x0 && tcx <= x1 && tcy >= y0 && tcy <= y1) ? 1u : 0u;
+        L.ypass[l] = (tcx >= x0 && tcx <= x1 && tcy >= y0 && tcy <= y1) ? 1 : 0;
     }
     __syncthreads();
-    // entries up to the smaller of the two window ends are final
-    uint64_t F = ~0ull;
+    // entries up to the smaller of the two window ends are final (positions
+    // are below 2^31, so the all-ones value means "no bound")
+    uint32_t F = 0xffffffffu;
     if (i1 + cX < e1) F = L.xk[cX - 1];
-    if (i2 + cY < e2) F = min(F, L.yk_raw[cY - 1]);
+    if (i2 + cY < e2) F = min(F, L.yraw[cY - 1]);
     int nX = count_le(L.xk, cX, F);
-    int nYr = count_le(L.yk_raw, cY, F);
+    int nYr = count_le(L.yraw, cY, F);
     // compact the covering wide entries among the consumed raw ones
     const int per = (cY + NT - 1) / NT;
     uint32_t cnt = 0;
@@ -200,11 +295,7 @@ __device__ Batch merge_batch(MergeLDS& L, const uint32_t* __restrict__ vals, con
     uint32_t pos = block_scan_excl(cnt, L.wsum, &nYu);
     for (int q = 0; q < per; ++q) {
         const int l = t * per + q;
-        if (l < nYr && L.ypass[l]) {
-            L.yk[pos] = L.yk_raw[l];
-            L.yr[pos] = L.yr_raw[l];
-            ++pos;
-        }
+        if (l < nYr && L.ypass[l]) L.yk[pos++] = L.yraw[l];
     }
     __syncthreads();
     int nY = (int)nYu;
@@ -218,32 +309,32 @@ __device__ Batch merge_batch(MergeLDS& L, const uint32_t* __restrict__ vals, con
             else hi = mid;
         }
         const int a = lo;
-        uint64_t last = 0;
+        uint32_t last = 0;
         if (a > 0) last = L.xk[a - 1];
         if (d - a > 0) last = max(last, L.yk[d - a - 1]);
         nX = a;
         nY = d - a;
-        nYr = count_le(L.yk_raw, nYr, last);
+        nYr = count_le(L.yraw, nYr, last);
     }
-    for (int a = t; a < nX; a += NT) L.m[a + count_lt(L.yk, nY, L.xk[a])] = L.xr[a];
-    for (int b = t; b < nY; b += NT) L.m[b + count_lt(L.xk, nX, L.yk[b])] = L.yr[b];
+    for (int a = t; a < nX; a += NT) L.m[a + count_lt(L.yk, nY, L.xk[a])] = L.xk[a];
+    for (int b = t; b < nY; b += NT) L.m[b + count_lt(L.xk, nX, L.yk[b])] = L.yk[b];
     __syncthreads();
+    // the windows are dead: stage the records over them
     const int M = nX + nY;
     for (int j = t; j < M; j += NT) {
-        const uint32_t r = L.m[j];
-        L.A[j] = rec[3 * (size_t)r];
-        L.B[j] = rec[3 * (size_t)r + 1];
-        L.C[j] = rec[3 * (size_t)r + 2];
+        const size_t i = L.m[j];
+        L.A[j] = srec[3 * i];
+        L.Bv[j] = srec[3 * i + 1];
+        L.C[j] = srec[3 * i + 2];
     }
     __syncthreads();
     return Batch{M, nX, nYr};
 }
 
 struct HybridLists {
-    const uint32_t* vals;      // narrow instances in (tile, depth, record) order
+    const uint32_t* vals;      // narrow instances (sorted positions) in (tile, position) order
     const uint2* ranges;       // narrow [start, end) per tile
-    const float* depth;        // per record
-    const uint4* wide;         // wide entries, per view in (depth, record) order
+    const uint4* wide;         // wide entries, per view in position order
     const uint2* wide_range;   // per view
     uint4* cur;                // batch checkpoints (narrow cursor, wide cursor, merged index)
     const uint32_t* cur_off;   // first checkpoint of each tile
@@ -252,14 +343,15 @@ struct HybridLists {
 
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
-    const float4* __restrict__ rec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
+    const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
     float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
     uint32_t* __restrict__ queue) {
     constexpr int NT = TW * TH / PPT;
-    __shared__ MergeLDS L;
+    extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_tile;
     const int t = threadIdx.x;
     const int batch = st.batch;
+    const Lds L = carve(smem, batch);
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
@@ -294,10 +386,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             for (int i = 0; i < PPT; ++i) active |= !done[i];
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
-            const Batch bt = merge_batch(L, hl.vals, hl.depth, hl.wide, rec, i1, e1, i2, e2, batch, tcx, tcy);
+            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, i1, e1, i2, e2, batch, tcx, tcy);
             for (int j = 0; j < bt.M; ++j) {
                 if (!__any(active)) break;
-                const float4 A = L.A[j], B = L.B[j], Cc = L.C[j];
+                const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
                     if (done[i]) continue;
@@ -327,7 +419,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             i2 += bt.nYraw;
             m += bt.M;
             ++b;
-            __syncthreads();  // the next batch overwrites L
+            __syncthreads();  // the next batch overwrites the LDS
         }
         if (t == 0) hl.nbatch[tile] = (uint32_t)b;
 #pragma unroll
@@ -354,16 +446,17 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
 
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
-    const float4* __restrict__ rec, HybridLists hl, ViewSet views, DevSettings st, const float* __restrict__ t_final,
+    const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, const float* __restrict__ t_final,
     const int32_t* __restrict__ last_in, const float* __restrict__ dl_dimages, int64_t n, float* __restrict__ d_rec,
     float* __restrict__ d_masks, uint32_t* __restrict__ queue) {
     constexpr int NT = TW * TH / PPT;
-    __shared__ MergeLDS L;
+    extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_tile;
     __shared__ int s_top;
     const int t = threadIdx.x;
     const int lane = lane_id();
     const int batch = st.batch;
+    const Lds L = carve(smem, batch);
     const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
@@ -420,12 +513,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
         for (int b = bstar; b >= 0; --b) {
             const uint4 c = cur[b];
             const int m = (int)c.z;
-            const Batch bt = merge_batch(L, hl.vals, hl.depth, hl.wide, rec, (int)c.x, (int)r1.y, (int)c.y,
-                                         (int)r2.y, batch, tcx, tcy);
+            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y,
+                                         batch, tcx, tcy);
             const int jtop = min(bt.M - 1, top - m);
             for (int j = jtop; j >= 0; --j) {
                 const int k = m + j;
-                const float4 A = L.A[j], B = L.B[j], Cc = L.C[j];
+                const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
                 const float M = B.z;
                 float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
                       gm = 0.f;
@@ -464,7 +557,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                     T[i] = Ti;
                 }
                 if (__any(any)) {
-                    const uint32_t r = L.m[j];
+                    const uint32_t r = __float_as_uint(Cc.w);
                     const int64_t g = (int64_t)r - rec_base;
                     const float sm = wave_sum(gm);
                     if (M != 0.f) {
@@ -480,39 +573,45 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                     }
                 }
             }
-            __syncthreads();  // the next batch overwrites L
+            __syncthreads();  // the next batch overwrites the LDS
         }
         if (!queue) break;
     }
 }
 
+// Persistent grid per batch depth (index log2(batch / 32)).
+template <typename Kernel>
+int cached_grid(int (&cache)[4], Kernel k, int block, int num_cus, int batch) {
+    const int idx = batch <= 32 ? 0 : batch <= 64 ? 1 : batch <= 128 ? 2 : 3;
+    if (!cache[idx]) cache[idx] = persistent_grid(k, block, num_cus, lds_bytes(batch));
+    return cache[idx];
+}
+
 template <int TW, int TH, int PPT>
-void hybrid_fwd_t(hipStream_t s, int num_cus, const float* rec, const HybridLists& hl, const ViewSet& views,
+void hybrid_fwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
                   uint32_t* queue) {
     int grid = (int)views.total_tiles;
     if (queue) {
-        static int full = 0;
-        if (!full) full = persistent_grid(hybrid_fwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
-        grid = min(full, grid);
+        static int cache[4] = {0, 0, 0, 0};
+        grid = min(cached_grid(cache, hybrid_fwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus, st.batch), grid);
     }
-    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
-                       reinterpret_cast<const float4*>(rec), hl, views, st, images, t_final, last,
+    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), lds_bytes(st.batch), s,
+                       reinterpret_cast<const float4*>(srec), hl, views, st, images, t_final, last,
                        reinterpret_cast<int4*>(stats), queue);
 }
 
 template <int TW, int TH, int PPT>
-void hybrid_bwd_t(hipStream_t s, int num_cus, const float* rec, const HybridLists& hl, const ViewSet& views,
+void hybrid_bwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, const float* t_final, const int32_t* last, const float* dl, int64_t n,
                   float* d_rec, float* d_masks, uint32_t* queue) {
     int grid = (int)views.total_tiles;
     if (queue) {
-        static int full = 0;
-        if (!full) full = persistent_grid(hybrid_bwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus);
-        grid = min(full, grid);
+        static int cache[4] = {0, 0, 0, 0};
+        grid = min(cached_grid(cache, hybrid_bwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus, st.batch), grid);
     }
-    hipLaunchKernelGGL((hybrid_bwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s,
-                       reinterpret_cast<const float4*>(rec), hl, views, st, t_final, last, dl, n, d_rec, d_masks,
+    hipLaunchKernelGGL((hybrid_bwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), lds_bytes(st.batch), s,
+                       reinterpret_cast<const float4*>(srec), hl, views, st, t_final, last, dl, n, d_rec, d_masks,
                        queue);
 }
 
@@ -531,7 +630,6 @@ HybridLists make_lists(const HybridBuffers& b) {
     HybridLists hl;
     hl.vals = b.vals;
     hl.ranges = reinterpret_cast<const uint2*>(b.ranges);
-    hl.depth = b.depth;
     hl.wide = reinterpret_cast<const uint4*>(b.wide);
     hl.wide_range = reinterpret_cast<const uint2*>(b.wide_range);
     hl.cur = reinterpret_cast<uint4*>(b.cur);
@@ -540,30 +638,43 @@ HybridLists make_lists(const HybridBuffers& b) {
     return hl;
 }
 
+unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
 }  // namespace
 
 void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
                           uint64_t* keys, uint32_t* vals) {
     if (R == 0) return;
-    hipLaunchKernelGGL(record_keys64_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, depth, tiles,
-                       R, n, keys, vals);
+    hipLaunchKernelGGL(record_keys64_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, depth, tiles, R, n, keys,
+                       vals);
 }
 
-void launch_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, int64_t R, int64_t n,
-                     const ViewSet& views, uint32_t* narrow_cnt, uint32_t* wide_flag) {
+void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
+                             const float* radius, int64_t R, int64_t n, const ViewSet& views, uint32_t* narrow_cnt,
+                             uint32_t* wide_flag, float* srec) {
     if (R == 0) return;
-    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, order, tiles, R, n,
-                       views, narrow_cnt, wide_flag);
+    hipLaunchKernelGGL(permute_classify_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, order, tiles,
+                       reinterpret_cast<const float4*>(rec), radius, R, n, views, narrow_cnt, wide_flag,
+                       reinterpret_cast<float4*>(srec));
 }
 
-void launch_wide_scatter(hipStream_t stream, const uint32_t* order, const uint32_t* wide_flag,
-                         const uint32_t* wide_pos, int64_t R, int64_t n, const float* rec, const float* radius,
-                         const float* depth, const ViewSet& views, const DevSettings& st, uint32_t* wide,
+void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
+                             const uint32_t* offsets, int64_t R, int64_t n, const ViewSet& views,
+                             const DevSettings& st, uint32_t* keys, uint32_t* vals, int64_t capacity,
+                             uint32_t* flags) {
+    if (R == 0) return;
+    hipLaunchKernelGGL(duplicate_narrow_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
+                       reinterpret_cast<const float4*>(srec), cnt_sorted, offsets, R, n, views, st, keys, vals,
+                       capacity, flags);
+}
+
+void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const uint32_t* wide_pos, int64_t R,
+                         int64_t n, const float* srec, const ViewSet& views, const DevSettings& st, uint32_t* wide,
                          int64_t wcap, uint32_t* flags) {
     if (R == 0) return;
-    hipLaunchKernelGGL(wide_scatter_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, order, wide_flag,
-                       wide_pos, R, n, reinterpret_cast<const float4*>(rec), radius, depth, views, st,
-                       reinterpret_cast<uint4*>(wide), wcap, flags);
+    hipLaunchKernelGGL(wide_scatter_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, wide_flag, wide_pos, R, n,
+                       reinterpret_cast<const float4*>(srec), views, st, reinterpret_cast<uint4*>(wide), wcap,
+                       flags);
 }
 
 void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
@@ -575,36 +686,36 @@ void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint
 void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
                        int batch, uint32_t* caps) {
     if (views.total_tiles == 0) return;
-    hipLaunchKernelGGL(batch_caps_kernel, dim3((views.total_tiles + 255) / 256), dim3(256), 0, stream,
+    hipLaunchKernelGGL(batch_caps_kernel, dim3(blocks_of(views.total_tiles)), dim3(256), 0, stream,
                        reinterpret_cast<const uint2*>(ranges), reinterpret_cast<const uint2*>(wide_range), views,
                        batch, caps);
 }
 
-void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
                        int32_t* stats, uint32_t* queue, int num_cus) {
     if (views.total_tiles == 0) return;
     const HybridLists hl = make_lists(bufs);
 #define MGS_HFWD(A, B, P)                                                                                   \
     if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                               \
-        hybrid_fwd_t<A, B, P>(stream, num_cus, rec, hl, views, st, images, t_final, last, stats, queue);    \
+        hybrid_fwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, images, t_final, last, stats, queue);   \
         return;                                                                                             \
     }
     MGS_HYBRID_SHAPES(MGS_HFWD)
 #undef MGS_HFWD
 }
 
-void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
                        const float* dl_dimages, int64_t n, float* d_rec, float* d_masks, uint32_t* queue,
                        int num_cus) {
     if (views.total_tiles == 0) return;
     const HybridLists hl = make_lists(bufs);
-#define MGS_HBWD(A, B, P)                                                                                      \
-    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                  \
-        hybrid_bwd_t<A, B, P>(stream, num_cus, rec, hl, views, st, t_final, last, dl_dimages, n, d_rec, d_masks, \
-                              queue);                                                                          \
-        return;                                                                                                \
+#define MGS_HBWD(A, B, P)                                                                                       \
+    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                   \
+        hybrid_bwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, t_final, last, dl_dimages, n, d_rec, d_masks, \
+                              queue);                                                                           \
+        return;                                                                                                 \
     }
     MGS_HYBRID_SHAPES(MGS_HBWD)
 #undef MGS_HBWD

@@ -34,17 +34,8 @@ void launch_radix_sort(hipStream_t stream, uint64_t* keys, uint32_t* vals, uint6
                        int64_t K, const uint64_t* K_dev, int key_bits, void* scratch, bool* out_in_alt);
 void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, const uint64_t* K_dev,
                         int64_t total_tiles, uint32_t* ranges);
-
-// depth-ordered binning: record depth keys, gather, duplication in sorted
-// order with 32-bit tile keys, 32-bit radix sort over [begin_bit, end_bit),
-// ranges from 32-bit tile keys
-void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
-                        uint32_t* vals);
-void launch_gather_u32(hipStream_t stream, const uint32_t* src, const uint32_t* idx, int64_t n, uint32_t* dst);
-void launch_duplicate_sorted(hipStream_t stream, const float* rec, const float* radius, const uint32_t* order,
-                             const uint32_t* cnt_sorted, const uint32_t* offsets, int64_t R, int64_t n_per_view,
-                             const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
-                             int64_t capacity, uint32_t* flags);
+// 32-bit keys sorted on bits [begin_bit, end_bit) (stable), and the tile
+// ranges of 32-bit tile keys
 void launch_radix_sort32(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                          int64_t K, const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch,
                          bool* out_in_alt);
@@ -74,34 +65,39 @@ void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const 
                           const int32_t* last, const float* dl_dimages, int64_t n, float* d_rec, float* d_masks,
                           uint32_t* queue, int num_cus);
 
-// hybrid binning: wide records kept once per view, merged per tile while
-// compositing
+// hybrid binning: records in (view, depth, record) order are copied once
+// ("sorted records": radius in B.w, record id bits in C.w); narrow records
+// are duplicated with sorted positions as values, wide records are kept once
+// per view and merged per tile while compositing
 void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
                           uint64_t* keys, uint32_t* vals);
-void launch_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, int64_t R, int64_t n,
-                     const ViewSet& views, uint32_t* narrow_cnt, uint32_t* wide_flag);
-void launch_wide_scatter(hipStream_t stream, const uint32_t* order, const uint32_t* wide_flag,
-                         const uint32_t* wide_pos, int64_t R, int64_t n, const float* rec, const float* radius,
-                         const float* depth, const ViewSet& views, const DevSettings& st, uint32_t* wide,
+void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
+                             const float* radius, int64_t R, int64_t n, const ViewSet& views, uint32_t* narrow_cnt,
+                             uint32_t* wide_flag, float* srec);
+void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
+                             const uint32_t* offsets, int64_t R, int64_t n, const ViewSet& views,
+                             const DevSettings& st, uint32_t* keys, uint32_t* vals, int64_t capacity,
+                             uint32_t* flags);
+void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const uint32_t* wide_pos, int64_t R,
+                         int64_t n, const float* srec, const ViewSet& views, const DevSettings& st, uint32_t* wide,
                          int64_t wcap, uint32_t* flags);
 void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
                         int n_views, uint32_t* wide_range);
 void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
                        int batch, uint32_t* caps);
 struct HybridBuffers {
-    const uint32_t* vals;        // narrow instances, (tile, depth, record) order
+    const uint32_t* vals;        // narrow instances (sorted positions), (tile, position) order
     const uint32_t* ranges;      // [tiles, 2] narrow ranges
-    const float* depth;          // [R]
     const uint32_t* wide;        // [W, 4] wide entries
     const uint32_t* wide_range;  // [views, 2]
     uint32_t* cur;               // [checkpoints, 4]
     const uint32_t* cur_off;     // [tiles]
     uint32_t* nbatch;            // [tiles]
 };
-void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
                        int32_t* stats, uint32_t* queue, int num_cus);
-void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const HybridBuffers& bufs,
+void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
                        const float* dl_dimages, int64_t n, float* d_rec, float* d_masks, uint32_t* queue,
                        int num_cus);

@@ -168,95 +168,6 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// depth-ordered binning (whole path)
-// ---------------------------------------------------------------------------
-
-// Sort key of every record: its depth bits (positive floats order like their
-// bit patterns); records without tiles sort last.
-__global__ void __launch_bounds__(256) record_keys_kernel(const float* __restrict__ depth,
-                                                           const uint32_t* __restrict__ tiles, int64_t R,
-                                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    keys[r] = tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu;
-    vals[r] = (uint32_t)r;
-}
-
-__global__ void __launch_bounds__(256) gather_u32_kernel(const uint32_t* __restrict__ src,
-                                                          const uint32_t* __restrict__ idx, int64_t n,
-                                                          uint32_t* __restrict__ dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[idx[i]];
-}
-
-// Instances of the records in depth order: sorted position i holds record
-// order[i] with tile count cnt[i] starting at offsets[i].  Records with few
-// tiles are written by their own lane; a record with many tiles is written by
-// the whole wave, 64 consecutive instances per store.
-constexpr uint32_t COOP_MIN = 16;
-
-__global__ void __launch_bounds__(256) duplicate_sorted_kernel(
-    const float4* __restrict__ rec, const float* __restrict__ radius, const uint32_t* __restrict__ order,
-    const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ offsets, int64_t R, int64_t n_per_view,
-    ViewSet views, DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
-    uint32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
-    uint32_t cnt = 0, r = 0;
-    int64_t off = 0;
-    int x0 = 0, y0 = 0, w = 1, gw = 1;
-    uint32_t toff = 0;
-    if (i < R) {
-        cnt = cnt_sorted[i];
-        if (cnt) {
-            r = order[i];
-            off = offsets[i];
-            const int vi = (int)(r / n_per_view);
-            const DevView& cam = views.v[vi];
-            const Rect q = record_rect(rec, radius, r, cam, st);
-            x0 = q.x0;
-            y0 = q.y0;
-            w = q.x1 - q.x0 + 1;
-            gw = cam.grid_w;
-            toff = cam.tile_off;
-        }
-    }
-    bool overflow = false;
-    const bool coop = cnt >= COOP_MIN;
-    if (!coop && cnt) {
-        for (uint32_t j = 0; j < cnt; ++j) {
-            const int64_t o = off + j;
-            if (o < capacity) {
-                const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
-                keys[o] = toff + (uint32_t)(y0 + (int)ty) * (uint32_t)gw + (uint32_t)(x0 + (int)tx);
-                vals[o] = r;
-            } else {
-                overflow = true;
-            }
-        }
-    }
-    uint64_t pending = __ballot(coop);
-    while (pending) {
-        const int src = __ffsll((long long)pending) - 1;
-        pending &= pending - 1;
-        const uint32_t bc = __shfl(cnt, src), br = __shfl(r, src), bt = __shfl(toff, src);
-        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bgw = __shfl(gw, src);
-        const int64_t bo = __shfl(off, src);
-        for (uint32_t j = lane; j < bc; j += 64) {
-            const int64_t o = bo + j;
-            if (o < capacity) {
-                const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
-                keys[o] = bt + (uint32_t)(by0 + (int)ty) * (uint32_t)bgw + (uint32_t)(bx0 + (int)tx);
-                vals[o] = br;
-            } else {
-                overflow = true;
-            }
-        }
-    }
-    if (overflow) atomicOr(flags, FLAG_CAPACITY);
-}
-
-// ---------------------------------------------------------------------------
 // LSD radix sort, 8 bits per pass, 32- or 64-bit keys with u32 values
 // ---------------------------------------------------------------------------
 
@@ -567,28 +478,6 @@ void launch_duplicate(hipStream_t stream, const float* rec, const float* radius,
     hipLaunchKernelGGL(duplicate_kernel, dim3((unsigned)((n_records + 255) / 256)), dim3(256), 0, stream,
                        reinterpret_cast<const float4*>(rec), radius, depth, tiles, offsets, n_records, n_per_view,
                        views, st, keys, vals, capacity, flags);
-}
-
-void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
-                        uint32_t* vals) {
-    if (R == 0) return;
-    hipLaunchKernelGGL(record_keys_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, depth, tiles, R,
-                       keys, vals);
-}
-
-void launch_gather_u32(hipStream_t stream, const uint32_t* src, const uint32_t* idx, int64_t n, uint32_t* dst) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(gather_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src, idx, n, dst);
-}
-
-void launch_duplicate_sorted(hipStream_t stream, const float* rec, const float* radius, const uint32_t* order,
-                             const uint32_t* cnt_sorted, const uint32_t* offsets, int64_t R, int64_t n_per_view,
-                             const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
-                             int64_t capacity, uint32_t* flags) {
-    if (R == 0) return;
-    hipLaunchKernelGGL(duplicate_sorted_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream,
-                       reinterpret_cast<const float4*>(rec), radius, order, cnt_sorted, offsets, R, n_per_view, views,
-                       st, keys, vals, capacity, flags);
 }
 
 size_t sort_scratch_bytes(int64_t K) {

@@ -62,7 +62,7 @@ class mgs_eval_counts(C.Structure):
 STAGES = ("project", "depth_sort", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd",
           "project_bwd", "sample_masks", "mask_grad", "loss", "adam")
 EXPORTS = {"records": 0, "depth": 1, "radius": 2, "tiles": 3, "values": 4, "ranges": 5, "t_final": 6, "last": 7,
-           "stats": 8, "wide": 9, "wide_ranges": 10}
+           "stats": 8, "wide": 9, "wide_ranges": 10, "order": 11}
 MGS_NUM_STAGES = len(STAGES)
 
 
@@ -278,7 +278,7 @@ def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:
 
 _EXPORT_DTYPES = {"records": torch.float32, "depth": torch.float32, "radius": torch.float32, "tiles": torch.int32,
                   "values": torch.int32, "ranges": torch.int32, "t_final": torch.float32, "last": torch.int32,
-                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32}
+                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32, "order": torch.int32}
 
 
 def mgs_frame_export(ctx, frame, what: str, stream=None) -> torch.Tensor:

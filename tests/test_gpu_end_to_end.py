@@ -46,7 +46,11 @@ def _defaults(deg, bg=(0.0, 0.0, 0.0), **kw):
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged"])
-def test_full_path_matches_oracle(rast, kind):
+@pytest.mark.parametrize("wide", [-1, 0, 1])
+def test_full_path_matches_oracle(rast, kind, wide):
+    """Whole path against the oracle with plain binning (wide = -1), the
+    automatic wide-list threshold (0) and nearly every record in the wide
+    lists (1)."""
     if kind == "tiny":
         s = scenegen.tiny_scene()
         bg = (0.0, 0.0, 0.0)
@@ -57,13 +61,19 @@ def test_full_path_matches_oracle(rast, kind):
     P = sum(c["width"] * c["height"] for c in cams)
     rng = np.random.default_rng(5)
     dl = rng.normal(size=3 * P).astype(np.float32)
-    img, tfin, g, stats, evals = _render(rast, s, cams, dl=dl, **_defaults(s["sh_degree"], bg))
+    img, tfin, g, stats, evals = _render(rast, s, cams, dl=dl, **_defaults(s["sh_degree"], bg, wide_tiles=wide))
     ost = oracle.RasterSettings(sh_degree=s["sh_degree"], bg=bg)
     op = oracle.run_pipeline(s, cams, s["masks"].astype(np.float64), ost, dl_dimage=dl.astype(np.float64))
     # images: FP32 pixel coordinates limit agreement with the FP64 projection
     assert U.rel_err(img, op.fwd.image) <= 2e-4
     assert np.abs(img - op.fwd.image).max() <= 2e-2
-    assert stats["n_instances"] == pytest.approx(op.lists.keys.size, rel=1e-3)
+    if wide < 0:
+        assert stats["n_wide"] == 0
+        assert stats["n_instances"] == pytest.approx(op.lists.keys.size, rel=1e-3)
+    else:
+        assert stats["n_instances"] <= op.lists.keys.size * (1 + 1e-3)
+    if wide == 1:
+        assert stats["n_wide"] > 0
     assert evals["examined"] == pytest.approx(int(op.fwd.examined.sum()), rel=1e-3)
     assert evals["blended"] == pytest.approx(int(op.fwd.n_blend.sum()), rel=1e-3)
     assert 0 < evals["blended_masked"] < evals["blended"]

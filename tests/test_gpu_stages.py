@@ -110,10 +110,10 @@ def test_tiles_and_lists_match_oracle_bitwise(ctx):
             assert np.all(gr[~nonempty, 0] == gr[~nonempty, 1])
 
 
-def merged_tile_lists(cams, tw, th, vals, ranges, wide, wide_ranges, depth_bits):
-    """Per-tile lists of the hybrid binning: the tile's narrow entries merged
-    with its view's wide entries whose tile rectangle contains the tile, in
-    (depth bits, record) order."""
+def merged_tile_lists(cams, tw, th, vals, ranges, wide, wide_ranges, order, depth_bits):
+    """Per-tile lists of the hybrid binning as record ids: the tile's narrow
+    entries (positions into `order`) merged with its view's wide entries whose
+    tile rectangle contains the tile, in (depth bits, record) order."""
     out = []
     for v, c in enumerate(cams):
         gw, gh = (c["width"] + tw - 1) // tw, (c["height"] + th - 1) // th
@@ -124,11 +124,11 @@ def merged_tile_lists(cams, tw, th, vals, ranges, wide, wide_ranges, depth_bits)
         for ty in range(gh):
             for tx in range(gw):
                 t = len(out)
-                narrow = vals[ranges[t, 0]:ranges[t, 1]].astype(np.int64)
+                narrow = order[vals[ranges[t, 0]:ranges[t, 1]]].astype(np.int64)
                 cover = (x0 <= tx) & (tx <= x1) & (y0 <= ty) & (ty <= y1)
                 recs = np.concatenate([narrow, wv[cover, 1].astype(np.int64)])
-                order = np.lexsort((recs, depth_bits[recs].astype(np.int64)))
-                out.append(recs[order])
+                perm = np.lexsort((recs, depth_bits[recs].astype(np.int64)))
+                out.append(recs[perm])
     return out
 
 
@@ -155,7 +155,8 @@ def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
         img = torch.empty(3 * P, device="cuda")
         M.mgs_forward(ctx, frame, U.gstruct(dev), cams, gst, img)
         ex = {k: M.mgs_frame_export(ctx, frame, k) for k in
-              ("records", "radius", "depth", "values", "ranges", "wide", "wide_ranges", "last", "stats", "t_final")}
+              ("records", "radius", "depth", "values", "ranges", "wide", "wide_ranges", "order", "last", "stats",
+               "t_final")}
         st = M.mgs_frame_get_stats(frame)
         torch.cuda.synchronize()
     finally:
@@ -174,7 +175,9 @@ def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
     if wide_tiles == 1:
         assert st["n_wide"] > 0
     lists = merged_tile_lists(cams, tw, th, U.u32(ex["values"]), U.u32(ex["ranges"]).reshape(-1, 2), wide,
-                              U.u32(ex["wide_ranges"]).reshape(-1, 2), dbits)
+                              U.u32(ex["wide_ranges"]).reshape(-1, 2), U.u32(ex["order"]), dbits)
+    # wide entries carry their position and record consistently
+    assert np.array_equal(U.u32(ex["order"])[wide[:, 0]], wide[:, 1])
     assert len(lists) == ol.ranges.shape[0]
     assert st["n_instances"] == U.u32(ex["values"]).size
     for t, lst in enumerate(lists):
