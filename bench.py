@@ -144,6 +144,8 @@ def main() -> int:
     ap.add_argument("--fwd-ppt", type=int, default=2)
     ap.add_argument("--bwd-ppt", type=int, default=2)
     ap.add_argument("--persistent", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
+    ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")
     ap.add_argument("--wide-tiles", type=int, default=0,
                     help="hybrid binning threshold in tiles (0: automatic, -1: every record duplicated)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -218,38 +220,84 @@ def main() -> int:
     rast.set(tile_w=tw, tile_h=th, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt, persistent=args.persistent)
     log(f"[bench] E16 = {E16:.4e} evals per step ({V} views, {P} pixels, {n} Gaussians)")
 
+    tuned = None
+    if args.autotune:
+        batched_step()  # fills the image gradient the tuner backpropagates
+        torch.cuda.synchronize()
+        t_at = time.perf_counter()
+        tuned, tune_ms = rast.autotune(frame, params, m_hard, cams, d_img, images=images, out=grads)
+        log(f"[bench] autotune: {tuned} ({tune_ms:.3f} ms fwd+bwd) in {time.perf_counter() - t_at:.1f} s")
     for _ in range(args.warmup):
         batched_step()
     torch.cuda.synchronize()
     counts = rast.count_evals(frame)
     fstats = rast.stats(frame)
+
+    # per-stage profile: eager steps with HIP events around every stage on
+    # the launch stream (a graph replay cannot be split by stage)
     M.mgs_profile_enable(ctx, True)
+    n_prof = max(1, min(args.steps, 5))
+    for _ in range(n_prof):
+        batched_step()
     torch.cuda.synchronize()
+    prof = M.mgs_profile_read(ctx)
+    M.mgs_profile_enable(ctx, False)
+    prof = {k: (v[0] / n_prof, v[1] // n_prof) for k, v in prof.items()}
+
+    graph = None
+    run = batched_step
+    if args.graph:
+        # fixed workspace, then capture one whole step into a hipGraph
+        rast.reserve(frame, 1.25)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            batched_step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            batched_step()
+        run = graph.replay
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        rast.check(frame)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     ev0.record()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        batched_step()
+        run()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = ev0.elapsed_time(ev1) / args.steps
-    prof = M.mgs_profile_read(ctx)
-    M.mgs_profile_enable(ctx, False)
-    log(f"[bench] batched: {ms_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}, "
-        f"wide records = {fstats['n_wide']}")
+    if graph is not None:
+        rast.check(frame)  # raises if a replay outgrew the fixed workspace
+        # the replayed step must equal an eager step on the same inputs
+        img_g, dm_g, dp_g = images.clone(), grads.masks.clone(), grads.means.clone()
+        batched_step()
+        torch.cuda.synchronize()
+        same_img = bool(torch.equal(img_g, images))
+        e_m = float((dm_g - grads.masks).norm() / grads.masks.norm().clamp_min(1e-30))
+        e_p = float((dp_g - grads.means).norm() / grads.means.norm().clamp_min(1e-30))
+        if not same_img or e_m > 1e-5 or e_p > 1e-5:
+            raise RuntimeError(f"graph replay differs from the eager step: images equal {same_img}, "
+                               f"dM rel {e_m:.2e}, dmeans rel {e_p:.2e}")
+    log(f"[bench] batched{' (graph)' if graph is not None else ''}: {ms_step:.3f} ms/step "
+        f"(wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}, wide records = {fstats['n_wide']}")
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     for k, v in prof.items():
         if v[1]:
-            log(f"[bench]   {k:14s} {v[0] / v[1]:9.3f} ms/launch x {v[1] // args.steps}")
+            log(f"[bench]   {k:14s} {v[0] / v[1]:9.3f} ms/launch x {v[1]}")
     dom = max(stage_ms, key=lambda k: prof[k][0])
     roof = stage_roofline(dom, stage_ms[dom], counts, fstats, n, V, deg)
     roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof, "traffic": None}
 
     plain = None
     if not args.no_plain and V > 1:
-        rast_p = Rasterizer(0, sh_degree=deg, tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=1, bwd_ppt=4,
-                            persistent=0)
+        rast_p = Rasterizer(0, sh_degree=deg, tile_w=16, tile_h=16, persistent=0)
         fr = rast_p.acquire_frame()
         offs = np.cumsum([0] + [3 * c["width"] * c["height"] for c in cams])
 
@@ -304,13 +352,16 @@ def main() -> int:
             "evals_per_step_16x16": E16,
             "instances": fstats["n_instances"],
             "wide_records": fstats["n_wide"],
-            "wide_tiles": args.wide_tiles,
             "views_per_s": V / (ms_step * 1e-3),
-            "tile": args.tile,
-            "batch_depth": args.batch_depth,
-            "fwd_ppt": args.fwd_ppt,
-            "bwd_ppt": args.bwd_ppt,
-            "persistent": bool(args.persistent),
+            "tile": f"{rast.settings.tile_w}x{rast.settings.tile_h}",
+            "batch_depth": rast.settings.batch_depth,
+            "fwd_ppt": rast.settings.fwd_ppt,
+            "bwd_ppt": rast.settings.bwd_ppt,
+            "wide_tiles": rast.settings.wide_tiles,
+            "autotuned": tuned is not None,
+            "graph": graph is not None,
+            "persistent": bool(rast.settings.persistent),
+            "eval_counts": counts,
             "plain": plain,
             "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if prof[k][1]},
         },

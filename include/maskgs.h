@@ -172,20 +172,61 @@ MGS_API mgs_status mgs_frame_get_stats(const mgs_frame* frame, mgs_frame_stats* 
 /* ---------------------------------------------------------------------- */
 
 /* Masked forward rendering of n_views cameras (host array cams[n_views],
- * 1 <= n_views <= MGS_MAX_VIEWS): projection, tile counts, scan, key
- * duplication, radix sort, tile ranges, masked compositing (Eq. 3-4 with the
- * background term).  images [3 * P] receives the rendering; t_final [P]
+ * 1 <= n_views <= MGS_MAX_VIEWS): projection, depth order of the records,
+ * narrow/wide split, key duplication, radix sort, tile ranges, masked
+ * compositing (Eq. 3-4 with the background term).  images [3 * P], packed
+ * per view and channel-planar, receives the rendering; t_final [P]
  * (optional, may be NULL) the final transmittance.  Synchronises the stream
- * once, to read K and size the sort. */
+ * once, to read the instance and wide counts and size the sort, unless the
+ * frame has a fixed workspace (mgs_frame_reserve).  Errors:
+ * MGS_ERR_INVALID_ARG, MGS_ERR_NONFINITE (non-finite projected geometry),
+ * MGS_ERR_CAPACITY, MGS_ERR_OOM, MGS_ERR_HIP. */
 MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
                                int n_views, const mgs_settings* st, float* images, float* t_final);
 
-/* Backward of the last mgs_forward on this frame.  dl_dimages [3 * P] is the
- * gradient of the loss w.r.t. the rendered images.  Writes every non-NULL
- * field of *grads (host struct of device pointers).  The Gaussian
- * parameters passed to the forward must be unchanged.  Asynchronous. */
+/* Backward of the last mgs_forward on this frame (Eq. 6 with the
+ * supplementary recursion and background term; reverse traversal with the
+ * transmittance recovered by division).  dl_dimages [3 * P] is the gradient
+ * of the loss w.r.t. the rendered images.  Writes every non-NULL field of
+ * *grads (host struct of device pointers); d_masks receives dL/dM_i for
+ * every Gaussian, masked or not, summed over views.  Per-record 2D gradients
+ * and mask gradients are accumulated with FP64 atomics and rounded once.
+ * The Gaussian parameters passed to the forward must be unchanged.
+ * Asynchronous. */
 MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float* dl_dimages,
                                 const mgs_gradients* grads);
+
+/* Fixed workspace for stream capture (hipGraph): after a plain mgs_forward on
+ * this frame, sizes the instance, wide-entry and batch-checkpoint buffers to
+ * that forward's counts times `slack` (>= 1) and switches the frame to a mode
+ * in which mgs_forward and mgs_backward neither allocate nor synchronise: the
+ * live counts stay on the device, the sort and the compositing read them
+ * there, and counts beyond the reservation raise a device flag instead of
+ * growing buffers.  Records (N * views), tiles and pixels may not exceed the
+ * forward the reservation was taken from (MGS_ERR_CAPACITY on the host).
+ * slack <= 0 releases the fixed workspace.  Synchronises `stream` once.
+ * Outputs of a forward whose counts overflowed are undefined; mgs_frame_check
+ * reports it. */
+MGS_API mgs_status mgs_frame_reserve(mgs_frame* frame, mgs_stream stream, double slack);
+
+/* Synchronises `stream`, then reads the device flags and counts of the
+ * frame's last forward: MGS_ERR_NONFINITE for non-finite projected geometry,
+ * MGS_ERR_CAPACITY when a count exceeded a fixed workspace.  Updates the
+ * frame statistics with the live counts. */
+MGS_API mgs_status mgs_frame_check(mgs_frame* frame, mgs_stream stream);
+
+/* Autotuner for the compositing configuration: times forward + backward
+ * (one warm-up, best of two, HIP events on `stream`) for tile shapes 16x16,
+ * 16x8, 32x8 and 8x8 with batch depths 32..256, then the pixels-per-thread
+ * pairs at the best shape, then the wide-list threshold, and returns the
+ * fastest settings in *best (the other fields copied from *base) and their
+ * time in *best_ms (may be NULL).  Images, tile lists and gradients agree
+ * across these settings (tile-size invariance of the per-pixel cut), so the
+ * choice affects time only.  Uses the plain path (frame without a fixed
+ * workspace); overwrites images, the gradients and the frame state. */
+MGS_API mgs_status mgs_autotune(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
+                                int n_views, const mgs_settings* base, float* images, const float* dl_dimages,
+                                const mgs_gradients* grads, mgs_settings* best, double* best_ms);
 
 /* Copies one array the last forward left in the frame into dst (device,
  * caller-owned, at least the reported size):

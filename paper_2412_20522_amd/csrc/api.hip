@@ -264,13 +264,17 @@ struct mgs_frame {
     int64_t n = 0, R = 0, P = 0, K = 0, W = 0, total_tiles = 0, capacity = 0;
     int sort_passes = 0, tile_bits = 0;
     bool sorted_in_alt = false, order_in_alt = false;
+    // fixed workspace (mgs_frame_reserve): no allocation, no synchronisation
+    bool reserved = false;
+    int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, W_cap = 0, cur_cap = 0;
     // device buffers: per record, then per narrow instance (32-bit tile keys),
     // wide entries, per tile, per pixel
-    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, wide_pos;
+    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag,
+        wide_pos;
     DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats;
-    DevBuf d_rec, d_masks_tmp, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;
+    DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
-    // 16, per-view wide ranges (u32 pairs) from 32
+    // 16, checkpoint count (u64) at 24, per-view wide ranges (u32 pairs) from 32
     uint64_t* h_pinned = nullptr;  // read-back of misc
     uint32_t* keys_sorted() { return (uint32_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
     uint32_t* vals_sorted() { return (uint32_t*)(sorted_in_alt ? vals_alt.p : vals.p); }
@@ -278,10 +282,13 @@ struct mgs_frame {
     uint32_t* flags() { return (uint32_t*)misc.p; }
     uint64_t* total() { return (uint64_t*)((char*)misc.p + 8); }
     uint64_t* wide_total() { return (uint64_t*)((char*)misc.p + 16); }
+    uint64_t* cur_need() { return (uint64_t*)((char*)misc.p + 24); }
     uint32_t* wide_range() { return (uint32_t*)((char*)misc.p + 32); }
     HybridBuffers hybrid() {
+        const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)(cur.bytes / 16);
         return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const uint32_t*)wide.p, wide_range(),
-                             (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p};
+                             (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
+                             flags()};
     }
 };
 
@@ -365,7 +372,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
                       &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
                       &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->t_final,  &f->last,
-                      &f->stats,    &f->d_rec,     &f->d_masks_tmp, &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
+                      &f->stats,    &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
                       &f->misc,     &f->queue,     &f->sum_tmp};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
@@ -385,6 +392,64 @@ mgs_status mgs_frame_get_stats(const mgs_frame* f, mgs_frame_stats* out) {
     out->n_wide = f->W;
     out->sort_passes = f->sort_passes;
     out->tile_bits = f->tile_bits;
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
+    if (!f) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (slack <= 0.0) {
+        f->reserved = false;
+        return MGS_OK;
+    }
+    if (!(slack >= 1.0)) return fail(ctx, MGS_ERR_INVALID_ARG, "slack %g must be >= 1 (or <= 0 to release)", slack);
+    if (!f->have_forward || f->reserved)
+        return fail(ctx, MGS_ERR_STATE, "mgs_frame_reserve needs a preceding plain mgs_forward");
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 32, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipStreamSynchronize(stream));
+    const double K = (double)f->h_pinned[1], W = (double)f->h_pinned[2], C = (double)f->h_pinned[3];
+    const int64_t K_cap = (int64_t)std::ceil(K * slack) + 4096;
+    const int64_t W_cap = (int64_t)std::ceil(W * slack) + 1024;
+    const int64_t cur_cap = (int64_t)std::ceil(C * slack) + 4096;
+    if (K_cap > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "instance capacity beyond 2^31 - 1");
+    mgs_status s;
+    const size_t kb = (size_t)K_cap * 4 + 16;
+    if ((s = grow(ctx, f->keys, kb)) || (s = grow(ctx, f->vals, kb)) || (s = grow(ctx, f->keys_alt, kb)) ||
+        (s = grow(ctx, f->vals_alt, kb)) || (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(K_cap))) ||
+        (s = grow(ctx, f->wide, (size_t)W_cap * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) ||
+        (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)))
+        return s;
+    f->K_cap = K_cap;
+    f->W_cap = W_cap;
+    f->cur_cap = cur_cap;
+    f->res_R = f->R;
+    f->res_P = f->P;
+    f->res_T = f->total_tiles;
+    f->reserved = true;
+    return MGS_OK;
+}
+
+mgs_status mgs_frame_check(mgs_frame* f, mgs_stream stream_) {
+    if (!f) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "no forward on this frame");
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 32, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipStreamSynchronize(stream));
+    const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
+    const uint64_t K = f->h_pinned[1], W = f->h_pinned[2], C = f->h_pinned[3];
+    if (f->reserved) {
+        f->K = (int64_t)std::min<uint64_t>(K, (uint64_t)f->K_cap);
+        f->W = (int64_t)std::min<uint64_t>(W, (uint64_t)f->W_cap);
+    }
+    if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
+    if (flags & FLAG_CAPACITY)
+        return fail(ctx, MGS_ERR_CAPACITY,
+                    "the last forward exceeded its workspace: %llu instances (capacity %lld), %llu wide entries "
+                    "(%lld), %llu checkpoints (%lld)",
+                    (unsigned long long)K, (long long)f->K_cap, (unsigned long long)W, (long long)f->W_cap,
+                    (unsigned long long)C, (long long)f->cur_cap);
     return MGS_OK;
 }
 
@@ -413,6 +478,11 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->tile_bits = bits_for((uint64_t)f->total_tiles);
     const int64_t R = f->R, P = f->P, T = f->total_tiles;
     const int V = n_views;
+    if (f->reserved && (R > f->res_R || P > f->res_P || T > f->res_T))
+        return fail(ctx, MGS_ERR_CAPACITY,
+                    "records %lld, pixels %lld or tiles %lld exceed the reserved workspace (%lld, %lld, %lld)",
+                    (long long)R, (long long)P, (long long)T, (long long)f->res_R, (long long)f->res_P,
+                    (long long)f->res_T);
     if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->srec, (size_t)R * 48 + 16)) ||
         (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
@@ -454,38 +524,49 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
                         f->scan_tmp.p);
         launch_scan_u32(stream, (const uint32_t*)f->wide_flag.p, R, (uint32_t*)f->wide_pos.p, f->wide_total(),
                         f->scan_tmp.p);
-        launch_wide_ranges(stream, (const uint32_t*)f->wide_pos.p, f->wide_total(), f->n, V, f->wide_range());
+        launch_wide_ranges(stream, (const uint32_t*)f->wide_pos.p, f->wide_total(), f->n, V,
+                           f->reserved ? f->W_cap : R, f->wide_range());
     }
     MGS_CHECK_LAUNCH(ctx);
-    // the one synchronisation of the plain path: instance and wide counts
-    // size the instance sort and the batch checkpoints
-    const size_t rb = 32 + 8 * (size_t)V;
-    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, rb, hipMemcpyDeviceToHost, stream));
-    MGS_HIP(ctx, hipStreamSynchronize(stream));
-    const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
-    const uint64_t K = f->h_pinned[1];
-    const uint64_t W = f->h_pinned[2];
-    if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
-    if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu instances exceed 2^31 - 1",
-                                                (unsigned long long)K);
-    f->K = (int64_t)K;
-    f->W = (int64_t)W;
-    // checkpoints: per tile 2 (ceil(narrow / B) + ceil(wide of its view / B)) + 2
     const int64_t B = st->batch_depth;
-    int64_t cur_bound = 2 * ((f->K + B - 1) / B + T) + 2 * T;
-    {
-        const uint32_t* wr = reinterpret_cast<const uint32_t*>(f->h_pinned + 4);
-        for (int v = 0; v < V; ++v) {
-            const int64_t wv = (int64_t)wr[2 * v + 1] - (int64_t)wr[2 * v];
-            const int64_t tv = (int64_t)f->views.v[v].grid_w * f->views.v[v].grid_h;
-            cur_bound += 2 * tv * ((wv + B - 1) / B);
+    const uint64_t* K_dev = nullptr;  // live instance count on the device (fixed workspace)
+    if (f->reserved) {
+        // no synchronisation: the sort, ranges and compositing take the live
+        // counts from the device and the capacities from the reservation;
+        // overflows raise device flags, read by mgs_frame_check
+        f->K = f->K_cap;
+        f->W = f->W_cap;
+        K_dev = f->total();
+    } else {
+        // the one synchronisation of the plain path: instance and wide counts
+        // size the instance sort and the batch checkpoints
+        const size_t rb = 32 + 8 * (size_t)V;
+        MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, rb, hipMemcpyDeviceToHost, stream));
+        MGS_HIP(ctx, hipStreamSynchronize(stream));
+        const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
+        const uint64_t K = f->h_pinned[1];
+        const uint64_t W = f->h_pinned[2];
+        if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
+        if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu instances exceed 2^31 - 1",
+                                                    (unsigned long long)K);
+        f->K = (int64_t)K;
+        f->W = (int64_t)W;
+        // checkpoints: per tile 2 (ceil(narrow / B) + ceil(wide of its view / B)) + 2
+        int64_t cur_bound = 2 * ((f->K + B - 1) / B + T) + 2 * T;
+        {
+            const uint32_t* wr = reinterpret_cast<const uint32_t*>(f->h_pinned + 4);
+            for (int v = 0; v < V; ++v) {
+                const int64_t wv = (int64_t)wr[2 * v + 1] - (int64_t)wr[2 * v];
+                const int64_t tv = (int64_t)f->views.v[v].grid_w * f->views.v[v].grid_h;
+                cur_bound += 2 * tv * ((wv + B - 1) / B);
+            }
         }
+        if ((s = grow(ctx, f->keys, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 16)) ||
+            (s = grow(ctx, f->keys_alt, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 16)) ||
+            (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))) ||
+            (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)))
+            return s;
     }
-    if ((s = grow(ctx, f->keys, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 16)) ||
-        (s = grow(ctx, f->keys_alt, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 16)) ||
-        (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))) || (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) ||
-        (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)))
-        return s;
     f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 4, f->vals.bytes / 4);
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
@@ -502,15 +583,16 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     {
         StageTimer t(ctx, stream, MGS_STAGE_SORT);
         launch_radix_sort32(stream, (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, (uint32_t*)f->keys_alt.p,
-                            (uint32_t*)f->vals_alt.p, f->K, nullptr, 0, 8 * f->sort_passes, f->sort_tmp.p, &in_alt);
+                            (uint32_t*)f->vals_alt.p, f->K, K_dev, 0, 8 * f->sort_passes, f->sort_tmp.p, &in_alt);
     }
     f->sorted_in_alt = in_alt;
     {
         StageTimer t(ctx, stream, MGS_STAGE_RANGES);
-        launch_tile_ranges32(stream, f->keys_sorted(), f->K, nullptr, T, (uint32_t*)f->ranges.p);
+        launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T, (uint32_t*)f->ranges.p);
         launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->wide_range(), f->views, (int)B,
                           (uint32_t*)f->caps.p);
-        launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, nullptr, f->scan_tmp.p);
+        launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, f->cur_need(),
+                        f->scan_tmp.p);
     }
     uint32_t* queue = nullptr;
     if (f->persistent) {
@@ -538,15 +620,13 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
         return fail(ctx, MGS_ERR_INVALID_ARG, "d_quats must be 16-byte aligned");
     mgs_status s;
-    if ((s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 4 + 4))) return s;
-    float* d_masks = grads->d_masks;
-    if (!d_masks) {
-        if ((s = grow(ctx, f->d_masks_tmp, (size_t)f->n * 4 + 4))) return s;
-        d_masks = (float*)f->d_masks_tmp.p;
-    }
+    // per-record 2D gradients and mask gradients accumulate in FP64: a wide
+    // splat takes atomics from thousands of tiles whose partial sums cancel
+    if ((s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)))
+        return s;
     uint32_t* queue = nullptr;
-    launch_fill_f32(stream, (float*)f->d_rec.p, f->R * DREC, 0.f);
-    launch_fill_f32(stream, d_masks, f->n, 0.f);
+    launch_fill_u32(stream, (uint32_t*)f->d_rec.p, 2 * f->R * DREC, 0u);  // +0.0 in every double
+    launch_fill_u32(stream, (uint32_t*)f->dm_acc.p, 2 * f->n, 0u);
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
@@ -555,13 +635,107 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_BWD);
         launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st,
                           (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
-                          (float*)f->d_rec.p, d_masks, queue, ctx->num_cus);
+                          (double*)f->d_rec.p, (double*)f->dm_acc.p, queue, ctx->num_cus);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT_BWD);
-        launch_project_bwd(stream, f->g, f->views, f->st, (const float*)f->d_rec.p, *grads);
+        launch_project_bwd64(stream, f->g, f->views, f->st, (const double*)f->d_rec.p, (const double*)f->dm_acc.p,
+                             *grads);
     }
     MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_autotune(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g, const mgs_camera* cams,
+                        int n_views, const mgs_settings* base, float* images, const float* dl_dimages,
+                        const mgs_gradients* grads, mgs_settings* best, double* best_ms) {
+    if (!f || !best) return MGS_ERR_INVALID_ARG;
+    mgs_ctx* ctx = f->ctx;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (f->reserved) return fail(ctx, MGS_ERR_STATE, "mgs_autotune needs a frame without a fixed workspace");
+    mgs_status s;
+    if ((s = check_settings(ctx, base)) != MGS_OK) return s;
+    if (!dl_dimages || !grads || !images) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    const bool was_on = ctx->prof_on;
+    ctx->prof_on = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        ctx->prof_on = was_on;
+        return fail(ctx, MGS_ERR_HIP, "event creation");
+    }
+    // one warm-up and two timed forward + backward passes; the faster counts
+    auto trial = [&](const mgs_settings& cand, double* ms) -> mgs_status {
+        mgs_status r;
+        *ms = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (rep > 0 && hipEventRecord(e0, stream) != hipSuccess) return fail(ctx, MGS_ERR_HIP, "event");
+            if ((r = mgs_forward(f, stream_, g, cams, n_views, &cand, images, nullptr)) != MGS_OK) return r;
+            if ((r = mgs_backward(f, stream_, dl_dimages, grads)) != MGS_OK) return r;
+            if (rep > 0) {
+                float e = 0.f;
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&e, e0, e1) != hipSuccess)
+                    return fail(ctx, MGS_ERR_HIP, "event timing");
+                *ms = std::min(*ms, (double)e);
+            }
+        }
+        return MGS_OK;
+    };
+    mgs_settings cur = *base, top = *base;
+    double top_ms = 1e300, ms = 0.0;
+    mgs_status r = MGS_OK;
+    // tile shape x batch depth at two pixels per thread (one for 8x8 tiles)
+    const int shapes[4][2] = {{16, 16}, {16, 8}, {32, 8}, {8, 8}};
+    const int depths[4] = {32, 64, 128, 256};
+    for (int a = 0; a < 4 && r == MGS_OK; ++a) {
+        for (int b = 0; b < 4 && r == MGS_OK; ++b) {
+            cur = *base;
+            cur.tile_w = shapes[a][0];
+            cur.tile_h = shapes[a][1];
+            cur.batch_depth = depths[b];
+            cur.fwd_ppt = cur.bwd_ppt = cur.tile_w * cur.tile_h >= 128 ? 2 : 1;
+            if ((r = trial(cur, &ms)) == MGS_OK && ms < top_ms) {
+                top_ms = ms;
+                top = cur;
+            }
+        }
+    }
+    // pixels per thread of each pass at the best shape
+    const mgs_settings shape = top;
+    for (int fp = 1; fp <= 4 && r == MGS_OK; fp *= 2) {
+        for (int bp = 1; bp <= 4 && r == MGS_OK; bp *= 2) {
+            cur = shape;
+            cur.fwd_ppt = fp;
+            cur.bwd_ppt = bp;
+            if (!composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, fp}) ||
+                !composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, bp}) ||
+                (fp == shape.fwd_ppt && bp == shape.bwd_ppt))
+                continue;
+            if ((r = trial(cur, &ms)) == MGS_OK && ms < top_ms) {
+                top_ms = ms;
+                top = cur;
+            }
+        }
+    }
+    // wide-list threshold
+    const mgs_settings pp = top;
+    const int wides[5] = {-1, 16, 64, 256, 1024};
+    for (int w = 0; w < 5 && r == MGS_OK; ++w) {
+        cur = pp;
+        cur.wide_tiles = wides[w];
+        if (cur.wide_tiles == pp.wide_tiles) continue;
+        if ((r = trial(cur, &ms)) == MGS_OK && ms < top_ms) {
+            top_ms = ms;
+            top = cur;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->prof_on = was_on;
+    if (r != MGS_OK) return r;
+    *best = top;
+    if (best_ms) *best_ms = top_ms;
     return MGS_OK;
 }
 

@@ -153,18 +153,20 @@ __global__ void __launch_bounds__(256) wide_scatter_kernel(const uint32_t* __res
     }
 }
 
-// [start, end) of every view's wide entries.
+// [start, end) of every view's wide entries, clamped to the entries the
+// wide buffer holds (a count beyond it is reported by the scatter).
 __global__ void wide_ranges_kernel(const uint32_t* __restrict__ wide_pos, const uint64_t* __restrict__ wide_total,
-                                   int64_t n, int nv, uint2* __restrict__ wide_range) {
+                                   int64_t n, int nv, int64_t wcap, uint2* __restrict__ wide_range) {
     const int v = threadIdx.x;
     if (v >= nv) return;
     if (n == 0) {
         wide_range[v] = make_uint2(0u, 0u);
         return;
     }
-    const uint32_t s = wide_pos[(int64_t)v * n];
-    const uint32_t e = v + 1 < nv ? wide_pos[(int64_t)(v + 1) * n] : (uint32_t)*wide_total;
-    wide_range[v] = make_uint2(s, e);
+    const uint64_t cap = (uint64_t)wcap;
+    const uint64_t s = wide_pos[(int64_t)v * n];
+    const uint64_t e = v + 1 < nv ? (uint64_t)wide_pos[(int64_t)(v + 1) * n] : *wide_total;
+    wide_range[v] = make_uint2((uint32_t)min(s, cap), (uint32_t)min(e, cap));
 }
 
 // Upper bound on the batches a tile can take: a batch either emits `batch`
@@ -339,6 +341,9 @@ struct HybridLists {
     uint4* cur;                // batch checkpoints (narrow cursor, wide cursor, merged index)
     const uint32_t* cur_off;   // first checkpoint of each tile
     uint32_t* nbatch;          // batches the forward took per tile
+    const uint64_t* cur_need;  // checkpoints the tiles may take (device)
+    uint64_t cur_cap;          // checkpoints the buffer holds
+    uint32_t* flags;
 };
 
 template <int TW, int TH, int PPT>
@@ -352,6 +357,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
     const int t = threadIdx.x;
     const int batch = st.batch;
     const Lds L = carve(smem, batch);
+    if (*hl.cur_need > hl.cur_cap) {  // a fixed workspace too small: report, write nothing
+        if (blockIdx.x == 0 && t == 0) atomicOr(hl.flags, FLAG_CAPACITY);
+        return;
+    }
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
@@ -447,8 +456,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, const float* __restrict__ t_final,
-    const int32_t* __restrict__ last_in, const float* __restrict__ dl_dimages, int64_t n, float* __restrict__ d_rec,
-    float* __restrict__ d_masks, uint32_t* __restrict__ queue) {
+    const int32_t* __restrict__ last_in, const float* __restrict__ dl_dimages, int64_t n, double* __restrict__ d_rec,
+    double* __restrict__ d_masks, uint32_t* __restrict__ queue) {
     constexpr int NT = TW * TH / PPT;
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_tile;
@@ -458,6 +467,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
     const int batch = st.batch;
     const Lds L = carve(smem, batch);
     const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
+    if (*hl.cur_need > hl.cur_cap) return;  // the forward reported it
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
@@ -566,10 +576,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                                     sbl = wave_sum(gbl);
                         float v = lane == 0 ? su : lane == 1 ? sv : lane == 2 ? sa : lane == 3 ? sb : lane == 4 ? sc
                                 : lane == 5 ? so : lane == 6 ? sr : lane == 7 ? sg : lane == 8 ? sbl : sm;
-                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, v);
-                        else if (lane == DREC) atomicAdd(d_masks + g, v);
+                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, (double)v);
+                        else if (lane == DREC) atomicAdd(d_masks + g, (double)v);
                     } else if (lane == 0) {
-                        atomicAdd(d_masks + g, sm);
+                        atomicAdd(d_masks + g, (double)sm);
                     }
                 }
             }
@@ -604,7 +614,7 @@ void hybrid_fwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLis
 template <int TW, int TH, int PPT>
 void hybrid_bwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, const float* t_final, const int32_t* last, const float* dl, int64_t n,
-                  float* d_rec, float* d_masks, uint32_t* queue) {
+                  double* d_rec, double* d_masks, uint32_t* queue) {
     int grid = (int)views.total_tiles;
     if (queue) {
         static int cache[4] = {0, 0, 0, 0};
@@ -635,6 +645,9 @@ HybridLists make_lists(const HybridBuffers& b) {
     hl.cur = reinterpret_cast<uint4*>(b.cur);
     hl.cur_off = b.cur_off;
     hl.nbatch = b.nbatch;
+    hl.cur_need = b.cur_need;
+    hl.cur_cap = b.cur_cap;
+    hl.flags = b.flags;
     return hl;
 }
 
@@ -678,8 +691,8 @@ void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const ui
 }
 
 void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
-                        int n_views, uint32_t* wide_range) {
-    hipLaunchKernelGGL(wide_ranges_kernel, dim3(1), dim3(64), 0, stream, wide_pos, wide_total, n, n_views,
+                        int n_views, int64_t wcap, uint32_t* wide_range) {
+    hipLaunchKernelGGL(wide_ranges_kernel, dim3(1), dim3(64), 0, stream, wide_pos, wide_total, n, n_views, wcap,
                        reinterpret_cast<uint2*>(wide_range));
 }
 
@@ -707,7 +720,7 @@ void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const flo
 
 void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
-                       const float* dl_dimages, int64_t n, float* d_rec, float* d_masks, uint32_t* queue,
+                       const float* dl_dimages, int64_t n, double* d_rec, double* d_masks, uint32_t* queue,
                        int num_cus) {
     if (views.total_tiles == 0) return;
     const HybridLists hl = make_lists(bufs);

@@ -14,6 +14,10 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
                         float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags);
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out);
+// Whole path: FP64 per-record gradients; dm_acc (FP64 mask gradients) is
+// rounded into out.d_masks.
+void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                          const double* d_rec, const double* dm_acc, const mgs_gradients& out);
 
 // scan / binning / sort / ranges
 size_t scan_scratch_bytes(int64_t n);
@@ -82,7 +86,7 @@ void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const ui
                          int64_t n, const float* srec, const ViewSet& views, const DevSettings& st, uint32_t* wide,
                          int64_t wcap, uint32_t* flags);
 void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
-                        int n_views, uint32_t* wide_range);
+                        int n_views, int64_t wcap, uint32_t* wide_range);
 void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
                        int batch, uint32_t* caps);
 struct HybridBuffers {
@@ -93,13 +97,16 @@ struct HybridBuffers {
     uint32_t* cur;               // [checkpoints, 4]
     const uint32_t* cur_off;     // [tiles]
     uint32_t* nbatch;            // [tiles]
+    const uint64_t* cur_need;    // device: checkpoints the tiles may take
+    uint64_t cur_cap;            // checkpoints the buffer holds
+    uint32_t* flags;             // device flags (capacity)
 };
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
                        int32_t* stats, uint32_t* queue, int num_cus);
 void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
-                       const float* dl_dimages, int64_t n, float* d_rec, float* d_masks, uint32_t* queue,
+                       const float* dl_dimages, int64_t n, double* d_rec, double* d_masks, uint32_t* queue,
                        int num_cus);
 
 // masks, loss, optimiser

@@ -290,12 +290,16 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     if (bad) atomicOr(flags, FLAG_NONFINITE);
 }
 
-template <int DEG>
+// AccT: type of the per-record 2D gradients (float from the stage entry
+// point, double from the whole path, which accumulates them with FP64
+// atomics); dm_acc (optional) holds FP64 mask gradients to round into d_masks.
+template <int DEG, typename AccT>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh, int64_t n, ViewSet views,
-    DevSettings st, const float* __restrict__ d_rec, float* __restrict__ d_means, float* __restrict__ d_log_scales,
-    float* __restrict__ d_quats, float* __restrict__ d_opacity_logits, float* __restrict__ d_sh) {
+    DevSettings st, const AccT* __restrict__ d_rec, const double* __restrict__ dm_acc, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
+    float* __restrict__ d_sh, float* __restrict__ d_masks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -307,7 +311,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
 
     double gS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma3 (symmetric full-matrix gradient)
     double gp[3] = {0.0, 0.0, 0.0};
-    float gop = 0.f;
+    double gop = 0.0;
     float gsh[3 * K];
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) gsh[i] = 0.f;
@@ -317,9 +321,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         const int64_t r = (int64_t)vi * n + g;
         const ViewGeom o = view_geom(cam, st, px, py, pz, cv.S);
         if (!o.valid) continue;
-        const float* dr = d_rec + r * DREC;
+        const AccT* dr = d_rec + r * DREC;
         const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
-        gop += dr[5];
+        gop += (double)dr[5];
         // colour: SH coefficients and viewing direction
         float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
         const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -332,7 +336,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             float acc = 0.5f;
 #pragma unroll
             for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
-            dcol[ch] = acc < 0.f ? 0.f : dr[6 + ch];
+            dcol[ch] = acc < 0.f ? 0.f : (float)dr[6 + ch];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -459,7 +463,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         d_log_scales[3 * g + 1] = (float)dls[1];
         d_log_scales[3 * g + 2] = (float)dls[2];
     }
-    if (d_opacity_logits) d_opacity_logits[g] = gop * opac * (1.f - opac);
+    if (d_opacity_logits) d_opacity_logits[g] = (float)(gop * opac * (1.0 - opac));
+    if (dm_acc && d_masks) d_masks[g] = (float)dm_acc[g];
     if (d_sh) {
         float* o = d_sh + g * 3 * K;
 #pragma unroll
@@ -486,14 +491,17 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 #undef MGS_PFWD
 }
 
-void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                        const float* d_rec, const mgs_gradients& out) {
+namespace {
+template <typename AccT>
+void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                   const AccT* d_rec, const double* dm_acc, const mgs_gradients& out) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
-#define MGS_PBWD(D)                                                                                                \
-    hipLaunchKernelGGL(project_bwd_kernel<D>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,          \
-                       g.opacity_logits, g.sh, g.n, views, st, d_rec, out.d_means, out.d_log_scales, out.d_quats,  \
-                       out.d_opacity_logits, out.d_sh)
+    float* d_masks = dm_acc ? out.d_masks : nullptr;
+#define MGS_PBWD(D)                                                                                               \
+    hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats, \
+                       g.opacity_logits, g.sh, g.n, views, st, d_rec, dm_acc, out.d_means, out.d_log_scales,      \
+                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;
@@ -501,6 +509,17 @@ void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
         default: MGS_PBWD(3); break;
     }
 #undef MGS_PBWD
+}
+}  // namespace
+
+void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                        const float* d_rec, const mgs_gradients& out) {
+    project_bwd_t<float>(stream, g, views, st, d_rec, nullptr, out);
+}
+
+void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
+                          const double* d_rec, const double* dm_acc, const mgs_gradients& out) {
+    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, out);
 }
 
 }  // namespace mgs

@@ -57,7 +57,15 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
     return wo + inc - v;
 }
 
-inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
+__host__ __device__ inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
+
+// Keys per workgroup of the sort: the host's chunk for a known count; with a
+// device-side live count, the live keys are spread evenly over the nb
+// workgroups the grid was sized for.
+__device__ __forceinline__ int64_t sort_chunk(int64_t K, const uint64_t* K_dev, int64_t nb, int64_t chunk) {
+    if (!K_dev) return chunk;
+    return ((nblocks(K) + nb - 1) / nb) * TILE;
+}
 
 // ---------------------------------------------------------------------------
 // scan of u32 counts (reduce, scan of block sums, downsweep)
@@ -199,6 +207,7 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&h[0][0])[i] = 0u;
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
+    chunk = sort_chunk(K, K_dev, nb, chunk);
     const int64_t cbeg = (int64_t)blockIdx.x * chunk;
     const int64_t cend = min(cbeg + chunk, K);
     for (int64_t base = cbeg; base < cend; base += TILE)
@@ -256,6 +265,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     __shared__ uint32_t scan_sh[NT / 64];
 
     const int64_t K = live_count(Kcap, K_dev);
+    chunk = sort_chunk(K, K_dev, nb, chunk);
     const int64_t cbeg = (int64_t)blockIdx.x * chunk;
     const int64_t cend = min(cbeg + chunk, K);
     if (cbeg >= cend) return;  // uniform over the block

@@ -87,6 +87,11 @@ _SIGS = {
     "mgs_forward": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                               C.POINTER(mgs_settings), _VP, _VP]),
     "mgs_backward": (C.c_int, [_VP, _VP, _VP, C.POINTER(mgs_gradients)]),
+    "mgs_frame_reserve": (C.c_int, [_VP, _VP, C.c_double]),
+    "mgs_frame_check": (C.c_int, [_VP, _VP]),
+    "mgs_autotune": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
+                               C.POINTER(mgs_settings), _VP, _VP, C.POINTER(mgs_gradients),
+                               C.POINTER(mgs_settings), C.POINTER(C.c_double)]),
     "mgs_frame_count_evals": (C.c_int, [_VP, _VP, C.POINTER(mgs_eval_counts)]),
     "mgs_frame_export": (C.c_int, [_VP, _VP, C.c_int, _VP, C.POINTER(_SZ)]),
     "mgs_profile_enable": (C.c_int, [_VP, C.c_int]),
@@ -268,6 +273,26 @@ def mgs_forward(ctx, frame, g: mgs_gaussians, cams: Sequence[dict], st: mgs_sett
 
 def mgs_backward(ctx, frame, dl_dimages: torch.Tensor, grads: mgs_gradients, stream=None) -> None:
     _check(ctx, _lib.mgs_backward(frame, _stream(stream), _ptr(dl_dimages, name="dl_dimages"), C.byref(grads)))
+
+
+def mgs_frame_reserve(ctx, frame, slack: float = 1.25, stream=None) -> None:
+    _check(ctx, _lib.mgs_frame_reserve(frame, _stream(stream), C.c_double(slack)))
+
+
+def mgs_frame_check(ctx, frame, stream=None) -> None:
+    _check(ctx, _lib.mgs_frame_check(frame, _stream(stream)))
+
+
+def mgs_autotune(ctx, frame, g: mgs_gaussians, cams: Sequence[dict], base: mgs_settings, images: torch.Tensor,
+                 dl_dimages: torch.Tensor, grads: mgs_gradients, stream=None):
+    """Returns (best settings, its forward + backward time in ms)."""
+    ca = cameras_array(cams)
+    best = mgs_settings()
+    ms = C.c_double()
+    _check(ctx, _lib.mgs_autotune(frame, _stream(stream), C.byref(g), ca, len(cams), C.byref(base),
+                                  _ptr(images, name="images"), _ptr(dl_dimages, name="dl_dimages"), C.byref(grads),
+                                  C.byref(best), C.byref(ms)))
+    return best, ms.value
 
 
 def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:

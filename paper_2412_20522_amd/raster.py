@@ -97,6 +97,35 @@ class Rasterizer:
         M.mgs_backward(self.ctx, frame, dl_dimages.contiguous(), gr)
         return out
 
+    # -- fixed workspace, capture, tuning ------------------------------------
+    def reserve(self, frame, slack: float = 1.25) -> None:
+        """Fix the frame's workspace after a plain forward, so that forward and
+        backward on it neither allocate nor synchronise (capturable)."""
+        M.mgs_frame_reserve(self.ctx, frame, slack)
+
+    def check(self, frame) -> None:
+        """Raise if the last forward on the frame overflowed its workspace or
+        projected non-finite geometry (synchronises)."""
+        M.mgs_frame_check(self.ctx, frame)
+
+    def autotune(self, frame, params: dict, masks: torch.Tensor, cams: Sequence[dict], dl_dimages: torch.Tensor,
+                 images: Optional[torch.Tensor] = None, out: Optional[Grads] = None, apply: bool = True):
+        """Time the compositing configurations on this workload; returns
+        (settings as a dict, ms) and, with apply, makes them current."""
+        dev = params["means"].device
+        if images is None:
+            images = torch.empty(3 * total_pixels(cams), dtype=torch.float32, device=dev)
+        if out is None:
+            out = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS),
+                        torch.empty(params["means"].shape[0], dtype=torch.float32, device=dev))
+        g = M.gaussians_struct(*(params[k] for k in PARAM_KEYS), masks)
+        gr = M.gradients_struct(out.means, out.log_scales, out.quats, out.opacity_logits, out.sh, out.masks)
+        best, ms = M.mgs_autotune(self.ctx, frame, g, cams, self.settings, images, dl_dimages.contiguous(), gr)
+        if apply:
+            self.settings = best
+        keys = ("tile_w", "tile_h", "batch_depth", "fwd_ppt", "bwd_ppt", "wide_tiles")
+        return {k: getattr(best, k) for k in keys}, ms
+
     def count_evals(self, frame) -> dict:
         """examined / blended / blended_masked / bwd_examined of the last forward."""
         return M.mgs_frame_count_evals(self.ctx, frame)
