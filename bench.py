@@ -74,13 +74,15 @@ def stage_roofline(stage: str, ms_per_launch: float, counts: dict, frame_stats: 
     P = frame_stats["n_pixels"]
     k3 = 3 * (sh_deg + 1) ** 2
     if stage == "composite_bwd":
+        # entries the backward evaluates: those up to each pixel's last blended
+        # one that can reach a pixel of their tile
         vis = counts["blended"] - counts["blended_masked"]
-        work = SLOTS_FILTER * counts["bwd_examined"] + SLOTS_BWD_VISIBLE * vis + SLOTS_BWD_MASKED * counts[
+        work = SLOTS_FILTER * counts["bwd_evaluated"] + SLOTS_BWD_VISIBLE * vis + SLOTS_BWD_MASKED * counts[
             "blended_masked"]
         return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
     if stage == "composite_fwd":
-        work = SLOTS_FILTER * counts["examined"] + SLOTS_BLEND * counts["blended"]
+        work = SLOTS_FILTER * counts["evaluated"] + SLOTS_BLEND * counts["blended"]
         return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
     if stage == "sort":
@@ -146,7 +148,8 @@ def main() -> int:
     ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
     ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")
-    ap.add_argument("--wide-tiles", type=int, default=0,
+    ap.add_argument("--tile-cull", type=int, default=1, help="narrow instances only for reachable tiles")
+    ap.add_argument("--wide-tiles", type=int, default=64,
                     help="hybrid binning threshold in tiles (0: automatic, -1: every record duplicated)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
@@ -191,7 +194,8 @@ def main() -> int:
     targets = torch.cat([torch.from_numpy(t.reshape(-1)) for t in scene["targets"]]).to(dev)
     tw, th = (int(x) for x in args.tile.split("x"))
     rast = Rasterizer(0, sh_degree=deg, tile_w=tw, tile_h=th, batch_depth=args.batch_depth, fwd_ppt=args.fwd_ppt,
-                      bwd_ppt=args.bwd_ppt, persistent=args.persistent, wide_tiles=args.wide_tiles)
+                      bwd_ppt=args.bwd_ppt, persistent=args.persistent, wide_tiles=args.wide_tiles,
+                      tile_cull=args.tile_cull)
     ctx = rast.ctx
     frame = rast.acquire_frame()
     images = torch.empty(3 * P, device=dev)
@@ -212,12 +216,15 @@ def main() -> int:
         M.mgs_mask_grad(ctx, grads.masks, m_hard, y_soft, tau, lambda_m, d_scores, loss_m, red_scratch)
 
     # the evaluation count at 16x16 tiles (the numerator), untimed
-    rast.set(tile_w=16, tile_h=16, fwd_ppt=1, bwd_ppt=4, persistent=0)
+    # (lists of Sec. 3.1 exactly: no tile culling, so the count is that of the
+    # full lists whatever the timed configuration skips)
+    rast.set(tile_w=16, tile_h=16, fwd_ppt=1, bwd_ppt=4, persistent=0, tile_cull=0)
     M.mgs_sample_masks(ctx, scores, tau, seed, step_id, m_hard, y_soft)
     rast.forward(frame, params, m_hard, cams, images=images)
     counts16 = rast.count_evals(frame)
     E16 = counts16["examined"]
-    rast.set(tile_w=tw, tile_h=th, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt, persistent=args.persistent)
+    rast.set(tile_w=tw, tile_h=th, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt, persistent=args.persistent,
+             tile_cull=args.tile_cull)
     log(f"[bench] E16 = {E16:.4e} evals per step ({V} views, {P} pixels, {n} Gaussians)")
 
     tuned = None
@@ -227,11 +234,17 @@ def main() -> int:
         t_at = time.perf_counter()
         tuned, tune_ms = rast.autotune(frame, params, m_hard, cams, d_img, images=images, out=grads)
         log(f"[bench] autotune: {tuned} ({tune_ms:.3f} ms fwd+bwd) in {time.perf_counter() - t_at:.1f} s")
-    for _ in range(args.warmup):
-        batched_step()
+    # work counters of the settings actually timed (one untimed step), then
+    # the timed configuration without counters
+    rast.set(stats=1)
+    batched_step()
     torch.cuda.synchronize()
     counts = rast.count_evals(frame)
     fstats = rast.stats(frame)
+    rast.set(stats=0)
+    for _ in range(args.warmup):
+        batched_step()
+    torch.cuda.synchronize()
 
     # per-stage profile: eager steps with HIP events around every stage on
     # the launch stream (a graph replay cannot be split by stage)
@@ -358,6 +371,7 @@ def main() -> int:
             "fwd_ppt": rast.settings.fwd_ppt,
             "bwd_ppt": rast.settings.bwd_ppt,
             "wide_tiles": rast.settings.wide_tiles,
+            "tile_cull": bool(rast.settings.tile_cull),
             "autotuned": tuned is not None,
             "graph": graph is not None,
             "persistent": bool(rast.settings.persistent),

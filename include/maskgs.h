@@ -99,7 +99,19 @@ typedef struct {
                                 list instead of being duplicated per tile; the
                                 compositing merges it into every tile list it
                                 covers, so results are those of plain binning.
-                                0: max(32, tiles of the view / 4); < 0: off */
+                                0: 64 tiles; < 0: off */
+    int32_t stats;           /* 1: the forward writes per-pixel work counters
+                                (mgs_frame_count_evals, exports STATS and EVALS);
+                                0: it does not (slightly faster) */
+    int32_t tile_cull;       /* 1: a narrow record covering at most 64 tiles is
+                                duplicated only into the tiles of its rectangle
+                                where it can pass the per-pixel filters
+                                (Q <= q_max, alpha >= alpha_min) at some pixel
+                                centre (a conservative exact test), which leaves
+                                every image and gradient unchanged;
+                                0: into every tile of its rectangle, the lists
+                                of Sec. 3.1 exactly (for list parity and for
+                                counting entries examined on those lists) */
 } mgs_settings;
 
 /* Gaussian parameters (device pointers, float32). */
@@ -238,6 +250,8 @@ MGS_API mgs_status mgs_autotune(mgs_frame* frame, mgs_stream stream, const mgs_g
  *   MGS_EXPORT_T_FINAL  [P] f32, MGS_EXPORT_LAST [P] i32
  *   MGS_EXPORT_STATS    [P, 4] i32 (examined, blended, blended with mask 0,
  *                       entries up to the last blended one)
+ *   MGS_EXPORT_EVALS    [P, 4] i32 (evaluated, evaluated up to the last blended
+ *                       entry, 0, 0)
  *   MGS_EXPORT_WIDE     [W, 4] u32 wide entries per view in (depth, record)
  *                       order: position into ORDER, record, x0 | y0 << 16,
  *                       x1 | y1 << 16 (inclusive tile rectangle)
@@ -260,7 +274,8 @@ typedef enum {
     MGS_EXPORT_STATS,
     MGS_EXPORT_WIDE,
     MGS_EXPORT_WIDE_RANGES,
-    MGS_EXPORT_ORDER
+    MGS_EXPORT_ORDER,
+    MGS_EXPORT_EVALS
 } mgs_export;
 MGS_API mgs_status mgs_frame_export(mgs_frame* frame, mgs_stream stream, int what, void* dst, size_t* bytes);
 
@@ -272,10 +287,16 @@ typedef struct {
     int64_t blended_masked;  /* ... of which with mask 0 */
     int64_t bwd_examined;    /* entries the backward revisits: from the range start
                                 to each pixel's last blended entry */
+    int64_t evaluated;       /* entries actually evaluated in the forward: those of
+                                the examined ones that can reach a pixel of their
+                                tile (an exact per-tile test drops the others,
+                                which cannot change any result) */
+    int64_t bwd_evaluated;   /* ... of which up to each pixel's last blended entry
+                                (the entries the backward evaluates) */
 } mgs_eval_counts;
 
 /* Sums the per-pixel counts of the last forward into *out (host).
- * Synchronises. */
+ * Synchronises.  MGS_ERR_STATE if that forward ran with settings.stats = 0. */
 MGS_API mgs_status mgs_frame_count_evals(mgs_frame* frame, mgs_stream stream, mgs_eval_counts* out);
 
 /* ---------------------------------------------------------------------- */

@@ -199,10 +199,9 @@ ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t*
         d.tile_off = toff;
         d.px_off = poff;
         // records covering more tiles than wide_min go to the view's wide list
-        const uint32_t vt = (uint32_t)(d.grid_w * d.grid_h);
         if (wide_tiles < 0) d.wide_min = 0xffffffffu;
         else if (wide_tiles > 0) d.wide_min = (uint32_t)wide_tiles;
-        else d.wide_min = std::max<uint32_t>(32u, vt / 4u);
+        else d.wide_min = 64u;
         toff += (uint32_t)(d.grid_w * d.grid_h);
         poff += (uint32_t)(c.width * c.height);
     }
@@ -234,11 +233,13 @@ DevSettings make_settings(const mgs_settings* s) {
         d.t_min = 0.f;
         d.q_max = INFINITY;
         d.full_rect = 1;
+        d.tile_cull = 0;
     } else {
         d.alpha_min = s->alpha_min;
         d.t_min = s->t_min;
         d.q_max = s->q_max;
         d.full_rect = 0;
+        d.tile_cull = s->tile_cull != 0;
     }
     return d;
 }
@@ -270,8 +271,9 @@ struct mgs_frame {
     // device buffers: per record, then per narrow instance (32-bit tile keys),
     // wide entries, per tile, per pixel
     DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag,
-        wide_pos;
-    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats;
+        wide_pos, tmask;
+    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats, evals;
+    bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
     // 16, checkpoint count (u64) at 24, per-view wide ranges (u32 pairs) from 32
@@ -316,6 +318,8 @@ mgs_status mgs_default_settings(mgs_settings* out) {
     out->fwd_ppt = 2;
     out->bwd_ppt = 2;
     out->wide_tiles = 0;
+    out->stats = 1;
+    out->tile_cull = 1;
     return MGS_OK;
 }
 
@@ -369,10 +373,10 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
-                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos,
+                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos, &f->tmask,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
                       &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->t_final,  &f->last,
-                      &f->stats,    &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
+                      &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
                       &f->misc,     &f->queue,     &f->sum_tmp};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
@@ -490,10 +494,11 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) || (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->wide_pos, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
         (s = grow(ctx, f->ranges, (size_t)T * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow(ctx, f->nbatch, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
-        (s = grow(ctx, f->stats, (size_t)P * 16)) ||
+        (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
         (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(std::max<int64_t>(R, T)))) ||
         (s = grow(ctx, f->rsort_tmp, sort_scratch_bytes(R))) || (s = grow(ctx, f->queue, 256)))
         return s;
@@ -515,8 +520,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
                           (uint32_t*)f->rvals_alt.p, R, nullptr, 32 + bits_for((uint64_t)V), f->rsort_tmp.p, &alt);
         f->order_in_alt = alt;
         launch_permute_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, (const float*)f->rec.p,
-                                (const float*)f->radius.p, R, f->n, f->views, (uint32_t*)f->cnt_sorted.p,
-                                (uint32_t*)f->wide_flag.p, (float*)f->srec.p);
+                                (const float*)f->radius.p, R, f->n, f->views, f->st, (uint32_t*)f->cnt_sorted.p,
+                                (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p);
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_SCAN);
@@ -571,8 +576,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
         launch_duplicate_narrow(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
-                                (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
-                                (uint32_t*)f->vals.p, f->K, f->flags());
+                                (const uint64_t*)f->tmask.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
+                                (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
         launch_wide_scatter(stream, (const uint32_t*)f->wide_flag.p, (const uint32_t*)f->wide_pos.p, R, f->n,
                             (const float*)f->srec.p, f->views, f->st, (uint32_t*)f->wide.p, f->W, f->flags());
     }
@@ -601,8 +606,10 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
+        f->have_stats = st->stats != 0;
         launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st, images,
-                          (float*)f->t_final.p, (int32_t*)f->last.p, (int32_t*)f->stats.p, queue, ctx->num_cus);
+                          (float*)f->t_final.p, (int32_t*)f->last.p, f->have_stats ? (int32_t*)f->stats.p : nullptr,
+                          f->have_stats ? (int32_t*)f->evals.p : nullptr, queue, ctx->num_cus);
     }
     MGS_CHECK_LAUNCH(ctx);
     if (t_final_out)
@@ -744,18 +751,22 @@ mgs_status mgs_frame_count_evals(mgs_frame* f, mgs_stream stream_, mgs_eval_coun
     mgs_ctx* ctx = f->ctx;
     hipStream_t stream = (hipStream_t)stream_;
     if (!f->have_forward) return fail(ctx, MGS_ERR_STATE, "no forward on this frame");
+    if (!f->have_stats) return fail(ctx, MGS_ERR_STATE, "the last forward ran with settings.stats = 0");
     mgs_status s;
     const size_t part = 4 * scan_scratch_bytes(f->P);
-    if ((s = grow(ctx, f->sum_tmp, part + 64))) return s;
-    uint64_t* dev = (uint64_t*)((char*)f->sum_tmp.p + part);
+    if ((s = grow(ctx, f->sum_tmp, 2 * part + 128))) return s;
+    uint64_t* dev = (uint64_t*)((char*)f->sum_tmp.p + 2 * part);
     launch_sum_i32x4(stream, (const int32_t*)f->stats.p, f->P, dev, f->sum_tmp.p);
+    launch_sum_i32x4(stream, (const int32_t*)f->evals.p, f->P, dev + 4, (char*)f->sum_tmp.p + part);
     MGS_CHECK_LAUNCH(ctx);
-    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned + 2, dev, 32, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned + 8, dev, 64, hipMemcpyDeviceToHost, stream));
     MGS_HIP(ctx, hipStreamSynchronize(stream));
-    out->examined = (int64_t)f->h_pinned[2];
-    out->blended = (int64_t)f->h_pinned[3];
-    out->blended_masked = (int64_t)f->h_pinned[4];
-    out->bwd_examined = (int64_t)f->h_pinned[5];
+    out->examined = (int64_t)f->h_pinned[8];
+    out->blended = (int64_t)f->h_pinned[9];
+    out->blended_masked = (int64_t)f->h_pinned[10];
+    out->bwd_examined = (int64_t)f->h_pinned[11];
+    out->evaluated = (int64_t)f->h_pinned[12];
+    out->bwd_evaluated = (int64_t)f->h_pinned[13];
     return MGS_OK;
 }
 
@@ -775,6 +786,7 @@ mgs_status mgs_frame_export(mgs_frame* f, mgs_stream stream, int what, void* dst
         case MGS_EXPORT_T_FINAL: src = f->t_final.p; n = (size_t)f->P * 4; break;
         case MGS_EXPORT_LAST: src = f->last.p; n = (size_t)f->P * 4; break;
         case MGS_EXPORT_STATS: src = f->stats.p; n = (size_t)f->P * 16; break;
+        case MGS_EXPORT_EVALS: src = f->evals.p; n = (size_t)f->P * 16; break;
         case MGS_EXPORT_WIDE: src = f->wide.p; n = (size_t)f->W * 16; break;
         case MGS_EXPORT_WIDE_RANGES: src = f->wide_range(); n = (size_t)f->n_views * 8; break;
         case MGS_EXPORT_ORDER: src = f->record_order(); n = (size_t)f->R * 4; break;

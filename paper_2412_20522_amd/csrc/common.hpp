@@ -36,6 +36,7 @@ struct DevSettings {
     float near_plane, dilation, lambda_floor;
     float bg[3];
     int32_t full_rect;  // every valid record covers every tile of its view
+    int32_t tile_cull;  // narrow instances only for tiles a record can reach
 };
 
 // Device flag bits.

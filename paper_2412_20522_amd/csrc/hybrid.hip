@@ -29,6 +29,81 @@
 namespace mgs {
 namespace {
 
+// The tile's pixel centres span [X0, X1] x [Y0, Y1].
+struct TileBox {
+    float X0, X1, Y0, Y1;
+};
+
+// Whether an entry can pass the per-pixel filters (Q <= q_max and
+// alpha >= alpha_min) at any pixel centre of the tile: the minimum of its
+// quadratic form over the box (zero if the centre is inside, else the
+// smallest of the clamped minima along the four edges) against the cut
+// min(q_max, 2 ln(opacity / alpha_min)).  The test is conservative (a small
+// margin over the cut), so an entry it drops contributes nothing to any
+// pixel of the tile in the forward or the backward pass; dropping it leaves
+// every result unchanged.
+struct TouchPrep {
+    float u, v, a, b, c;
+    float nbc, nba;  // -b / c and -b / a (minimisers along the box edges)
+    float cut;       // +huge: no cut (always touches); < 0: reaches no pixel
+};
+
+__device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B, const DevSettings& st) {
+    TouchPrep p;
+    p.u = A.x;
+    p.v = A.y;
+    p.a = A.z;
+    p.b = A.w;
+    p.c = B.x;
+    // reciprocal approximations only move the edge minimisers slightly, which
+    // raises the computed minimum by a second-order amount far inside the
+    // margin below
+    p.nbc = -p.b * __builtin_amdgcn_rcpf(p.c);
+    p.nba = -p.b * __builtin_amdgcn_rcpf(p.a);
+    float cut = st.q_max;
+    if (st.alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / st.alpha_min));
+    if (cut >= 3.0e38f) p.cut = 3.4e38f;          // no finite cut
+    else if (!(cut > -3.0e38f)) p.cut = -1.f;     // zero opacity
+    else p.cut = cut + 1e-3f * (1.f + fabsf(cut));
+    return p;
+}
+
+__device__ __forceinline__ bool touch_test(const TouchPrep& p, const TileBox& tb) {
+    if (p.cut >= 3.0e38f) return true;  // no cut (exact mode)
+    if (p.cut < 0.f) return false;
+    if (p.u >= tb.X0 && p.u <= tb.X1 && p.v >= tb.Y0 && p.v <= tb.Y1) return true;
+    const float dyl = p.v - tb.Y1, dyh = p.v - tb.Y0, dxl = p.u - tb.X1, dxh = p.u - tb.X0;
+    float q;
+    {
+        const float dx = dxh, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh);
+        q = p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy;
+    }
+    {
+        const float dx = dxl, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh);
+        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+    }
+    {
+        const float dy = dyh, dx = fminf(fmaxf(p.nba * dy, dxl), dxh);
+        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+    }
+    {
+        const float dy = dyl, dx = fminf(fmaxf(p.nba * dy, dxl), dxh);
+        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+    }
+    return q <= p.cut;
+}
+
+__device__ __forceinline__ bool may_touch(const float4& A, const float4& B, const TileBox& tb,
+                                          const DevSettings& st) {
+    return touch_test(touch_prep(A, B, st), tb);
+}
+
+__device__ __forceinline__ TileBox tile_box(int tx, int ty, const DevView& cam, const DevSettings& st) {
+    const int x0 = tx * st.tile_w, y0 = ty * st.tile_h;
+    return TileBox{(float)x0 + 0.5f, (float)min(x0 + st.tile_w, cam.width) - 0.5f, (float)y0 + 0.5f,
+                   (float)min(y0 + st.tile_h, cam.height) - 0.5f};
+}
+
 // ---------------------------------------------------------------------------
 // binning: (view, depth) order of records, sorted records, wide list, batch
 // checkpoints
@@ -48,85 +123,162 @@ __global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restr
 // Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
 // to view v.  Writes the sorted record copy (radius in B.w, record id bits in
 // C.w), the narrow tile count and the wide flag of every position.
+// Tile culling applies to narrow records of at most CULL_MAX tiles: the
+// classification tests each tile of the rectangle once and keeps the result
+// as a bit mask (bit j: j-th tile of the rectangle, row-major), which the
+// duplication then follows; larger narrow records keep their whole
+// rectangle.  Rectangles of at least COOP_MIN tiles are handled by a whole
+// wave, one tile per lane.
+constexpr uint32_t CULL_MAX = 64;
+constexpr uint32_t COOP_MIN = 16;
+
+__device__ __forceinline__ float4 shfl4(const float4& v, int src) {
+    return make_float4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
+}
+
+// Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
+// to view v.  Writes the sorted record copy (radius in B.w, record id bits in
+// C.w), the narrow tile count (after culling), the cull mask and the wide
+// flag of every position.
 __global__ void __launch_bounds__(256) permute_classify_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles, const float4* __restrict__ rec,
-    const float* __restrict__ radius, int64_t R, int64_t n, ViewSet views, uint32_t* __restrict__ narrow_cnt,
-    uint32_t* __restrict__ wide_flag, float4* __restrict__ srec) {
+    const float* __restrict__ radius, int64_t R, int64_t n, ViewSet views, DevSettings st,
+    uint32_t* __restrict__ narrow_cnt, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
+    float4* __restrict__ srec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= R) return;
-    const uint32_t r = order[i];
-    const uint32_t c = tiles[r];
-    const bool wide = c > views.v[i / n].wide_min;
-    narrow_cnt[i] = wide ? 0u : c;
-    wide_flag[i] = wide ? 1u : 0u;
-    float4 A = rec[3 * (size_t)r], B = rec[3 * (size_t)r + 1];
-    uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
-    B.w = radius[r];
-    C.w = r;
-    srec[3 * i] = A;
-    srec[3 * i + 1] = B;
-    reinterpret_cast<uint4*>(srec)[3 * i + 2] = C;
+    const int lane = lane_id();
+    const bool live = i < R;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+    uint32_t c = 0;
+    bool wide = false;
+    int vi = 0;
+    if (live) {
+        const uint32_t r = order[i];
+        c = tiles[r];
+        vi = (int)(i / n);
+        wide = c > views.v[vi].wide_min;
+        A = rec[3 * (size_t)r];
+        B = rec[3 * (size_t)r + 1];
+        uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
+        B.w = radius[r];
+        C.w = r;
+        srec[3 * i] = A;
+        srec[3 * i + 1] = B;
+        reinterpret_cast<uint4*>(srec)[3 * i + 2] = C;
+        wide_flag[i] = wide ? 1u : 0u;
+    }
+    uint32_t area = 0;
+    int x0 = 0, y0 = 0, w = 1;
+    if (live && !wide && c > 0) {
+        const Rect q = rect_of(A.x, A.y, B.w, views.v[vi], st);
+        x0 = q.x0;
+        y0 = q.y0;
+        w = q.x1 - q.x0 + 1;
+        area = (uint32_t)w * (uint32_t)(q.y1 - q.y0 + 1);
+    }
+    const bool cull = st.tile_cull && area > 0 && area <= CULL_MAX;
+    uint64_t mask = 0;
+    if (cull && area < COOP_MIN) {
+        const DevView& cam = views.v[vi];
+        const TouchPrep tp = touch_prep(A, B, st);
+        for (uint32_t j = 0; j < area; ++j) {
+            const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
+            if (touch_test(tp, tile_box(x0 + (int)tx, y0 + (int)ty, cam, st))) mask |= 1ull << j;
+        }
+    }
+    uint64_t pending = __ballot(cull && area >= COOP_MIN);
+    while (pending) {
+        const int src = __ffsll((long long)pending) - 1;
+        pending &= pending - 1;
+        const float4 bA = shfl4(A, src), bB = shfl4(B, src);
+        const uint32_t barea = __shfl(area, src);
+        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bvi = __shfl(vi, src);
+        bool pass = false;
+        const uint32_t j = (uint32_t)lane;
+        if (j < barea) {
+            const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
+            pass = may_touch(bA, bB, tile_box(bx0 + (int)tx, by0 + (int)ty, views.v[bvi], st), st);
+        }
+        const uint64_t bal = __ballot(pass);
+        if (lane == src) mask = bal;
+    }
+    if (live) {
+        narrow_cnt[i] = cull ? (uint32_t)__popcll(mask) : area;
+        tmask[i] = mask;
+    }
 }
 
 // Narrow instances in sorted-position order: tile ids as keys, positions as
-// values.  Records with many tiles are spread over the lanes of a wave.
-constexpr uint32_t COOP_MIN = 16;
-
+// values, for the tiles the classification kept.
 __global__ void __launch_bounds__(256) duplicate_narrow_kernel(
-    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ offsets,
-    int64_t R, int64_t n, ViewSet views, DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    int64_t capacity, uint32_t* __restrict__ flags) {
+    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ tmask,
+    const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views, DevSettings st,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
-    uint32_t cnt = 0;
+    uint32_t area = 0;
+    uint64_t mask = ~0ull;
     int64_t off = 0;
-    int x0 = 0, y0 = 0, w = 1, gw = 1;
-    uint32_t toff = 0;
-    if (i < R) {
-        cnt = cnt_sorted[i];
-        if (cnt) {
-            off = offsets[i];
-            const DevView& cam = views.v[i / n];
-            const float4 A = srec[3 * i], B = srec[3 * i + 1];
-            const Rect q = rect_of(A.x, A.y, B.w, cam, st);
-            x0 = q.x0;
-            y0 = q.y0;
-            w = q.x1 - q.x0 + 1;
-            gw = cam.grid_w;
-            toff = cam.tile_off;
-        }
+    int x0 = 0, y0 = 0, w = 1, vi = 0;
+    bool cull = false;
+    if (i < R && cnt_sorted[i]) {
+        off = offsets[i];
+        vi = (int)(i / n);
+        const float4 A = srec[3 * i], B = srec[3 * i + 1];
+        const Rect q = rect_of(A.x, A.y, B.w, views.v[vi], st);
+        x0 = q.x0;
+        y0 = q.y0;
+        w = q.x1 - q.x0 + 1;
+        area = (uint32_t)w * (uint32_t)(q.y1 - q.y0 + 1);
+        cull = st.tile_cull && area <= CULL_MAX;
+        if (cull) mask = tmask[i];
     }
     bool overflow = false;
-    const bool coop = cnt >= COOP_MIN;
-    if (!coop && cnt) {
-        for (uint32_t j = 0; j < cnt; ++j) {
-            const int64_t o = off + j;
+    const bool coop = area >= COOP_MIN;
+    if (!coop && area) {
+        const DevView& cam = views.v[vi];
+        int64_t o = off;
+        for (uint32_t j = 0; j < area; ++j) {
+            if (cull && !((mask >> j) & 1ull)) continue;
+            const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
             if (o < capacity) {
-                const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
-                keys[o] = toff + (uint32_t)(y0 + (int)ty) * (uint32_t)gw + (uint32_t)(x0 + (int)tx);
+                keys[o] = cam.tile_off + (uint32_t)(y0 + (int)ty) * (uint32_t)cam.grid_w + (uint32_t)(x0 + (int)tx);
                 vals[o] = (uint32_t)i;
             } else {
                 overflow = true;
             }
+            ++o;
         }
     }
     uint64_t pending = __ballot(coop);
     while (pending) {
         const int src = __ffsll((long long)pending) - 1;
         pending &= pending - 1;
-        const uint32_t bc = __shfl(cnt, src), bt = __shfl(toff, src);
+        const uint32_t barea = __shfl(area, src);
         const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)i, src);
-        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bgw = __shfl(gw, src);
+        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bvi = __shfl(vi, src);
+        const bool bcull = __shfl((int)cull, src) != 0;
+        const uint64_t bmask = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mask >> 32), src) << 32) |
+                               (uint64_t)(uint32_t)__shfl((int)(uint32_t)mask, src);
         const int64_t bo = __shfl(off, src);
-        for (uint32_t j = lane; j < bc; j += 64) {
-            const int64_t o = bo + j;
-            if (o < capacity) {
+        const DevView& cam = views.v[bvi];
+        int64_t base = bo;
+        for (uint32_t j0 = 0; j0 < barea; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const bool take = j < barea && (!bcull || ((bmask >> (j & 63u)) & 1ull));
+            const uint64_t bal = __ballot(take);
+            if (take) {
+                const int64_t o = base + __popcll(bal & lanemask_lt());
                 const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
-                keys[o] = bt + (uint32_t)(by0 + (int)ty) * (uint32_t)bgw + (uint32_t)(bx0 + (int)tx);
-                vals[o] = bi;
-            } else {
-                overflow = true;
+                if (o < capacity) {
+                    keys[o] = cam.tile_off + (uint32_t)(by0 + (int)ty) * (uint32_t)cam.grid_w +
+                              (uint32_t)(bx0 + (int)tx);
+                    vals[o] = bi;
+                } else {
+                    overflow = true;
+                }
             }
+            base += __popcll(bal);
         }
     }
     if (overflow) atomicOr(flags, FLAG_CAPACITY);
@@ -259,7 +411,8 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t* wsum, 
 }
 
 struct Batch {
-    int M;      // merged entries staged in LDS
+    int M;      // staged entries (those that can reach a pixel of the tile)
+    int Mfull;  // merged entries of the batch, staged or not
     int nX;     // narrow entries consumed
     int nYraw;  // wide entries consumed (including those not covering the tile)
 };
@@ -268,7 +421,7 @@ struct Batch {
 // Every thread of the block calls it; the result is uniform.
 __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, const uint4* __restrict__ wide,
                              const float4* __restrict__ srec, int i1, int e1, int i2, int e2, int batch, int tcx,
-                             int tcy) {
+                             int tcy, const TileBox& tb, const DevSettings& st) {
     const int t = threadIdx.x, NT = blockDim.x;
     const int cX = min(batch, e1 - i1), cY = min(batch, e2 - i2);
     for (int l = t; l < cX; l += NT) L.xk[l] = vals[i1 + l];
@@ -321,16 +474,37 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     for (int a = t; a < nX; a += NT) L.m[a + count_lt(L.yk, nY, L.xk[a])] = L.xk[a];
     for (int b = t; b < nY; b += NT) L.m[b + count_lt(L.xk, nX, L.yk[b])] = L.yk[b];
     __syncthreads();
-    // the windows are dead: stage the records over them
+    // the windows are dead: stage over them, in merged order, the records
+    // that can reach a pixel of the tile; B.w (the radius, unused here)
+    // carries the entry's index within the merged batch
     const int M = nX + nY;
-    for (int j = t; j < M; j += NT) {
+    const int run = (M + NT - 1) / NT;  // contiguous entries per thread (<= MAXB / 64)
+    uint32_t keep = 0, nkeep = 0;
+    for (int q = 0; q < run; ++q) {
+        const int j = t * run + q;
+        if (j < M) {
+            const size_t i = L.m[j];
+            if (may_touch(srec[3 * i], srec[3 * i + 1], tb, st)) {
+                keep |= 1u << q;
+                ++nkeep;
+            }
+        }
+    }
+    uint32_t Mc;
+    uint32_t p = block_scan_excl(nkeep, L.wsum, &Mc);
+    for (int q = 0; q < run; ++q) {
+        if (!((keep >> q) & 1u)) continue;
+        const int j = t * run + q;
         const size_t i = L.m[j];
-        L.A[j] = srec[3 * i];
-        L.Bv[j] = srec[3 * i + 1];
-        L.C[j] = srec[3 * i + 2];
+        float4 B = srec[3 * i + 1];
+        B.w = __int_as_float(j);
+        L.A[p] = srec[3 * i];
+        L.Bv[p] = B;
+        L.C[p] = srec[3 * i + 2];
+        ++p;
     }
     __syncthreads();
-    return Batch{M, nX, nYr};
+    return Batch{(int)Mc, M, nX, nYr};
 }
 
 struct HybridLists {
@@ -346,11 +520,12 @@ struct HybridLists {
     uint32_t* flags;
 };
 
-template <int TW, int TH, int PPT>
+// STATS: write the per-pixel work counters (stats_out, eval_out).
+template <int TW, int TH, int PPT, bool STATS>
 __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
     float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
-    uint32_t* __restrict__ queue) {
+    int4* __restrict__ eval_out, uint32_t* __restrict__ queue) {
     constexpr int NT = TW * TH / PPT;
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_tile;
@@ -367,7 +542,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
-        int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT];
+        int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT], nev[PPT], nev_last[PPT];
         bool done[PPT], inside[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -380,7 +555,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             C0[i] = C1[i] = C2[i] = 0.f;
             last[i] = -1;
             stopk[i] = -1;
-            nblend[i] = nmasked[i] = 0;
+            nblend[i] = nmasked[i] = nev[i] = nev_last[i] = 0;
             done[i] = !inside[i];
         }
         const uint2 r1 = hl.ranges[tile];
@@ -388,6 +563,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
         const int e1 = (int)r1.y, e2 = (int)r2.y;
         int i1 = (int)r1.x, i2 = (int)r2.x, m = 0, b = 0;
         const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
+        const TileBox tb{(float)tg.tx0 + 0.5f, (float)min(tg.tx0 + TW, cam.width) - 0.5f, (float)tg.ty0 + 0.5f,
+                         (float)min(tg.ty0 + TH, cam.height) - 0.5f};
         uint4* cur = hl.cur + hl.cur_off[tile];
         while (i1 < e1 || i2 < e2) {
             bool active = false;
@@ -395,20 +572,22 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             for (int i = 0; i < PPT; ++i) active |= !done[i];
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
-            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, i1, e1, i2, e2, batch, tcx, tcy);
+            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, st);
             for (int j = 0; j < bt.M; ++j) {
                 if (!__any(active)) break;
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
+                const int k = m + __float_as_int(B.w);  // index in the tile's full list
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
                     if (done[i]) continue;
+                    if (STATS) ++nev[i];
                     Eval e;
                     if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
                     const float ma = B.z * e.alpha;
                     const float test = T[i] * (1.f - ma);
                     if (test < st.t_min) {
                         done[i] = true;
-                        stopk[i] = m + j;
+                        stopk[i] = k;
                         continue;
                     }
                     const float wgt = ma * T[i];
@@ -416,9 +595,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
                     C1[i] += wgt * Cc.y;
                     C2[i] += wgt * Cc.z;
                     T[i] = test;
-                    last[i] = m + j;
-                    ++nblend[i];
-                    nmasked[i] += B.z == 0.f;
+                    last[i] = k;
+                    if (STATS) {
+                        ++nblend[i];
+                        nmasked[i] += B.z == 0.f;
+                        nev_last[i] = nev[i];
+                    }
                 }
                 active = false;
 #pragma unroll
@@ -426,7 +608,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             }
             i1 += bt.nX;
             i2 += bt.nYraw;
-            m += bt.M;
+            m += bt.Mfull;
             ++b;
             __syncthreads();  // the next batch overwrites the LDS
         }
@@ -445,9 +627,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             const int64_t p = (int64_t)cam.px_off + loc;
             t_final[p] = T[i];
             last_out[p] = last[i];
-            // a pixel that never stopped saw the whole merged list (m entries)
-            if (stats_out)
+            // a pixel that never stopped saw the whole merged list (m entries);
+            // entries it evaluated are those of the list that can reach the tile
+            if (STATS) {
                 stats_out[p] = make_int4(stopk[i] >= 0 ? stopk[i] + 1 : m, nblend[i], nmasked[i], last[i] + 1);
+                eval_out[p] = make_int4(nev[i], nev_last[i], 0, 0);
+            }
         }
         if (!queue) break;
     }
@@ -513,6 +698,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
         const uint2 r1 = hl.ranges[tile];
         const uint2 r2 = hl.wide_range[tg.vi];
         const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
+        const TileBox tb{(float)tg.tx0 + 0.5f, (float)min(tg.tx0 + TW, cam.width) - 0.5f, (float)tg.ty0 + 0.5f,
+                         (float)min(tg.ty0 + TH, cam.height) - 0.5f};
         // the batch holding the largest last-blended entry, then backwards
         int bstar = -1;
         if (top >= 0) {
@@ -524,11 +711,11 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
             const uint4 c = cur[b];
             const int m = (int)c.z;
             const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y,
-                                         batch, tcx, tcy);
-            const int jtop = min(bt.M - 1, top - m);
-            for (int j = jtop; j >= 0; --j) {
-                const int k = m + j;
+                                         batch, tcx, tcy, tb, st);
+            for (int j = bt.M - 1; j >= 0; --j) {
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
+                const int k = m + __float_as_int(B.w);  // index in the tile's full list
+                if (k > top) continue;                  // uniform: past every pixel's last entry
                 const float M = B.z;
                 float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
                       gm = 0.f;
@@ -597,18 +784,30 @@ int cached_grid(int (&cache)[4], Kernel k, int block, int num_cus, int batch) {
     return cache[idx];
 }
 
-template <int TW, int TH, int PPT>
-void hybrid_fwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
+template <int TW, int TH, int PPT, bool STATS>
+void hybrid_fwd_s(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
-                  uint32_t* queue) {
+                  int32_t* evals, uint32_t* queue) {
     int grid = (int)views.total_tiles;
     if (queue) {
         static int cache[4] = {0, 0, 0, 0};
-        grid = min(cached_grid(cache, hybrid_fwd_kernel<TW, TH, PPT>, TW * TH / PPT, num_cus, st.batch), grid);
+        grid = min(cached_grid(cache, hybrid_fwd_kernel<TW, TH, PPT, STATS>, TW * TH / PPT, num_cus, st.batch),
+                   grid);
     }
-    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), lds_bytes(st.batch), s,
-                       reinterpret_cast<const float4*>(srec), hl, views, st, images, t_final, last,
-                       reinterpret_cast<int4*>(stats), queue);
+    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT, STATS>), dim3(grid), dim3(TW * TH / PPT),
+                       lds_bytes(st.batch), s, reinterpret_cast<const float4*>(srec), hl, views, st, images, t_final,
+                       last, reinterpret_cast<int4*>(stats), reinterpret_cast<int4*>(evals), queue);
+}
+
+template <int TW, int TH, int PPT>
+void hybrid_fwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
+                  const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
+                  int32_t* evals, uint32_t* queue) {
+    if (stats && evals)
+        hybrid_fwd_s<TW, TH, PPT, true>(s, num_cus, srec, hl, views, st, images, t_final, last, stats, evals, queue);
+    else
+        hybrid_fwd_s<TW, TH, PPT, false>(s, num_cus, srec, hl, views, st, images, t_final, last, nullptr, nullptr,
+                                         queue);
 }
 
 template <int TW, int TH, int PPT>
@@ -663,22 +862,22 @@ void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t
 }
 
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
-                             const float* radius, int64_t R, int64_t n, const ViewSet& views, uint32_t* narrow_cnt,
-                             uint32_t* wide_flag, float* srec) {
+                             const float* radius, int64_t R, int64_t n, const ViewSet& views, const DevSettings& st,
+                             uint32_t* narrow_cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec) {
     if (R == 0) return;
     hipLaunchKernelGGL(permute_classify_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, order, tiles,
-                       reinterpret_cast<const float4*>(rec), radius, R, n, views, narrow_cnt, wide_flag,
+                       reinterpret_cast<const float4*>(rec), radius, R, n, views, st, narrow_cnt, wide_flag, tmask,
                        reinterpret_cast<float4*>(srec));
 }
 
 void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
-                             const uint32_t* offsets, int64_t R, int64_t n, const ViewSet& views,
-                             const DevSettings& st, uint32_t* keys, uint32_t* vals, int64_t capacity,
-                             uint32_t* flags) {
+                             const uint64_t* tmask, const uint32_t* offsets, int64_t R, int64_t n,
+                             const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
+                             int64_t capacity, uint32_t* flags) {
     if (R == 0) return;
     hipLaunchKernelGGL(duplicate_narrow_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
-                       reinterpret_cast<const float4*>(srec), cnt_sorted, offsets, R, n, views, st, keys, vals,
-                       capacity, flags);
+                       reinterpret_cast<const float4*>(srec), cnt_sorted, tmask, offsets, R, n, views, st, keys,
+                       vals, capacity, flags);
 }
 
 void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const uint32_t* wide_pos, int64_t R,
@@ -706,13 +905,13 @@ void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_
 
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
-                       int32_t* stats, uint32_t* queue, int num_cus) {
+                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus) {
     if (views.total_tiles == 0) return;
     const HybridLists hl = make_lists(bufs);
-#define MGS_HFWD(A, B, P)                                                                                   \
-    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                               \
-        hybrid_fwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, images, t_final, last, stats, queue);   \
-        return;                                                                                             \
+#define MGS_HFWD(A, B, P)                                                                                        \
+    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                    \
+        hybrid_fwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, images, t_final, last, stats, evals, queue); \
+        return;                                                                                                  \
     }
     MGS_HYBRID_SHAPES(MGS_HFWD)
 #undef MGS_HFWD

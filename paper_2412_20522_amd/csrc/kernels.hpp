@@ -76,9 +76,9 @@ void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const 
 void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
                           uint64_t* keys, uint32_t* vals);
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
-                             const float* radius, int64_t R, int64_t n, const ViewSet& views, uint32_t* narrow_cnt,
-                             uint32_t* wide_flag, float* srec);
-void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
+                             const float* radius, int64_t R, int64_t n, const ViewSet& views, const DevSettings& st,
+                             uint32_t* narrow_cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec);
+void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted, const uint64_t* tmask,
                              const uint32_t* offsets, int64_t R, int64_t n, const ViewSet& views,
                              const DevSettings& st, uint32_t* keys, uint32_t* vals, int64_t capacity,
                              uint32_t* flags);
@@ -101,9 +101,12 @@ struct HybridBuffers {
     uint64_t cur_cap;            // checkpoints the buffer holds
     uint32_t* flags;             // device flags (capacity)
 };
+// stats [P, 4] (examined, blended, blended with mask 0, last + 1) and evals
+// [P, 4] (evaluated, evaluated up to the last blended entry, 0, 0) are
+// written only when both are non-null.
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
-                       int32_t* stats, uint32_t* queue, int num_cus);
+                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus);
 void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
                        const float* dl_dimages, int64_t n, double* d_rec, double* d_masks, uint32_t* queue,

@@ -41,7 +41,7 @@ class mgs_settings(C.Structure):
                 ("near_plane", C.c_float), ("dilation", C.c_float), ("jac_clamp", C.c_float),
                 ("lambda_floor", C.c_float), ("bg", C.c_float * 3), ("exact_mode", C.c_int32),
                 ("persistent", C.c_int32), ("fwd_ppt", C.c_int32), ("bwd_ppt", C.c_int32),
-                ("wide_tiles", C.c_int32)]
+                ("wide_tiles", C.c_int32), ("stats", C.c_int32), ("tile_cull", C.c_int32)]
 
 
 class mgs_gaussians(C.Structure):
@@ -56,13 +56,13 @@ class mgs_gradients(C.Structure):
 
 class mgs_eval_counts(C.Structure):
     _fields_ = [("examined", C.c_int64), ("blended", C.c_int64), ("blended_masked", C.c_int64),
-                ("bwd_examined", C.c_int64)]
+                ("bwd_examined", C.c_int64), ("evaluated", C.c_int64), ("bwd_evaluated", C.c_int64)]
 
 
 STAGES = ("project", "depth_sort", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd",
           "project_bwd", "sample_masks", "mask_grad", "loss", "adam")
 EXPORTS = {"records": 0, "depth": 1, "radius": 2, "tiles": 3, "values": 4, "ranges": 5, "t_final": 6, "last": 7,
-           "stats": 8, "wide": 9, "wide_ranges": 10, "order": 11}
+           "stats": 8, "wide": 9, "wide_ranges": 10, "order": 11, "evals": 12}
 MGS_NUM_STAGES = len(STAGES)
 
 
@@ -303,7 +303,8 @@ def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:
 
 _EXPORT_DTYPES = {"records": torch.float32, "depth": torch.float32, "radius": torch.float32, "tiles": torch.int32,
                   "values": torch.int32, "ranges": torch.int32, "t_final": torch.float32, "last": torch.int32,
-                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32, "order": torch.int32}
+                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32, "order": torch.int32,
+                  "evals": torch.int32}
 
 
 def mgs_frame_export(ctx, frame, what: str, stream=None) -> torch.Tensor:

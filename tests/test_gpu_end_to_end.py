@@ -40,17 +40,20 @@ def _render(rast, scene, cams, masks=None, dl=None, **settings):
 
 
 def _defaults(deg, bg=(0.0, 0.0, 0.0), **kw):
-    base = dict(tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=1, bwd_ppt=4, persistent=0, exact_mode=0)
+    base = dict(tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=1, bwd_ppt=4, persistent=0, exact_mode=0,
+                wide_tiles=0, tile_cull=1, stats=1)
     base.update(kw)
     return dict(sh_degree=deg, bg=bg, **base)
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged"])
 @pytest.mark.parametrize("wide", [-1, 0, 1])
-def test_full_path_matches_oracle(rast, kind, wide):
+@pytest.mark.parametrize("cull", [0, 1])
+def test_full_path_matches_oracle(rast, kind, wide, cull):
     """Whole path against the oracle with plain binning (wide = -1), the
     automatic wide-list threshold (0) and nearly every record in the wide
-    lists (1)."""
+    lists (1); with the lists of Sec. 3.1 exactly (cull = 0) and with narrow
+    instances only for tiles a record can reach (cull = 1)."""
     if kind == "tiny":
         s = scenegen.tiny_scene()
         bg = (0.0, 0.0, 0.0)
@@ -61,7 +64,8 @@ def test_full_path_matches_oracle(rast, kind, wide):
     P = sum(c["width"] * c["height"] for c in cams)
     rng = np.random.default_rng(5)
     dl = rng.normal(size=3 * P).astype(np.float32)
-    img, tfin, g, stats, evals = _render(rast, s, cams, dl=dl, **_defaults(s["sh_degree"], bg, wide_tiles=wide))
+    img, tfin, g, stats, evals = _render(rast, s, cams, dl=dl, **_defaults(s["sh_degree"], bg, wide_tiles=wide,
+                                                                          tile_cull=cull))
     ost = oracle.RasterSettings(sh_degree=s["sh_degree"], bg=bg)
     op = oracle.run_pipeline(s, cams, s["masks"].astype(np.float64), ost, dl_dimage=dl.astype(np.float64))
     # images: FP32 pixel coordinates limit agreement with the FP64 projection
@@ -69,15 +73,21 @@ def test_full_path_matches_oracle(rast, kind, wide):
     assert np.abs(img - op.fwd.image).max() <= 2e-2
     if wide < 0:
         assert stats["n_wide"] == 0
+    if wide < 0 and not cull:
         assert stats["n_instances"] == pytest.approx(op.lists.keys.size, rel=1e-3)
     else:
         assert stats["n_instances"] <= op.lists.keys.size * (1 + 1e-3)
     if wide == 1:
         assert stats["n_wide"] > 0
-    assert evals["examined"] == pytest.approx(int(op.fwd.examined.sum()), rel=1e-3)
+    if not cull:
+        assert evals["examined"] == pytest.approx(int(op.fwd.examined.sum()), rel=1e-3)
+    else:
+        assert evals["examined"] <= int(op.fwd.examined.sum()) * (1 + 1e-3)
     assert evals["blended"] == pytest.approx(int(op.fwd.n_blend.sum()), rel=1e-3)
     assert 0 < evals["blended_masked"] < evals["blended"]
     assert evals["examined"] >= evals["bwd_examined"] >= evals["blended"]
+    # the per-tile test only drops entries that cannot reach a pixel of the tile
+    assert evals["examined"] >= evals["evaluated"] >= evals["bwd_evaluated"] >= evals["blended"]
     for name, a, b in [("means", g.means, op.grads.means), ("log_scales", g.log_scales, op.grads.log_scales),
                        ("quats", g.quats, op.grads.quats), ("opacity_logits", g.opacity_logits,
                                                              op.grads.opacity_logits),
@@ -112,6 +122,28 @@ def test_forward_is_deterministic_and_backward_reproducible(rast):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
     for x, y in zip((a[2].means, a[2].masks, a[2].sh), (b[2].means, b[2].masks, b[2].sh)):
         assert U.rel_err(x.cpu().numpy(), y.cpu().numpy()) <= 1e-5
+
+
+def test_tile_culling_changes_nothing_but_the_lists(rast):
+    """Dropping narrow instances whose record cannot reach a pixel of the
+    tile leaves images and final transmittance bit for bit and gradients to
+    FP64-atomics reordering, with fewer instances."""
+    s = scenegen.small_scene(4000, 140, 100, seed=206, sh_degree=2, log_scale_mean=-2.0, n_views=2)
+    s["cameras"][1] = scenegen.orbit_camera(4.0, 60.0, 10.0, 96, 64)
+    P = sum(c["width"] * c["height"] for c in s["cameras"])
+    dl = np.random.default_rng(11).normal(size=3 * P).astype(np.float32)
+    out = {}
+    for cull in (0, 1):
+        out[cull] = _render(rast, s, s["cameras"], dl=dl, **_defaults(2, (0.2, 0.3, 0.4), tile_cull=cull,
+                                                                     persistent=1))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[1][3]["n_instances"] < out[0][3]["n_instances"]
+    assert out[1][4]["blended"] == out[0][4]["blended"]
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh", "masks"):
+        a = getattr(out[1][2], name).cpu().numpy()
+        b = getattr(out[0][2], name).cpu().numpy()
+        assert U.rel_err(a, b) <= 1e-5, name
 
 
 def test_tile_shape_and_batch_invariance(rast):

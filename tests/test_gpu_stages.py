@@ -147,7 +147,7 @@ def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
     tw, th = tile
     bg = (0.3, 0.5, 0.7)
     ost, gst = U.settings_pair(sh_degree=s["sh_degree"], tile_w=tw, tile_h=th, fwd_ppt=1, bwd_ppt=1,
-                               wide_tiles=wide_tiles, batch_depth=64, bg=bg)
+                               wide_tiles=wide_tiles, batch_depth=64, bg=bg, tile_cull=0)
     dev = U.to_device(s)
     frame = M.mgs_frame_create(ctx)
     try:
