@@ -144,7 +144,7 @@ def main() -> int:
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--batch-depth", type=int, default=256)
     ap.add_argument("--fwd-ppt", type=int, default=2)
-    ap.add_argument("--bwd-ppt", type=int, default=2)
+    ap.add_argument("--bwd-ppt", type=int, default=4)
     ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
     ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")

@@ -507,6 +507,36 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     return Batch{(int)Mc, M, nX, nYr};
 }
 
+// Wave totals of ten per-lane quantities, transposed: on return lane q
+// (q < 10; also q + 16, q + 32, q + 48) holds the total of quantity q.  Each
+// quantity is first summed within its 16-lane row by DPP (the ten chains
+// interleave, so no wait states are needed between dependent DPP steps);
+// lane q of every row then picks quantity q and the four rows are folded by
+// two cross-row exchanges.  About half the instructions of ten separate
+// full-wave sums.
+__device__ __forceinline__ float wave_sum_transposed10(float (&v)[10], int lane) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0xb1, 0xf, 0xf, false));
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x4e, 0xf, 0xf, false));
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x124, 0xf, 0xf, false));
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x128, 0xf, 0xf, false));
+    const int lr = lane & 15;
+    float x = v[0];
+#pragma unroll
+    for (int q = 1; q < 10; ++q) x = lr == q ? v[q] : x;
+    // rows 0 + 1 and 2 + 3 (swizzle within 32 lanes: lane ^ 16), then the halves
+    x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401f));
+    x += __shfl_xor(x, 32);
+    return x;
+}
+
 struct HybridLists {
     const uint32_t* vals;      // narrow instances (sorted positions) in (tile, position) order
     const uint2* ranges;       // narrow [start, end) per tile
@@ -756,17 +786,15 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                 if (__any(any)) {
                     const uint32_t r = __float_as_uint(Cc.w);
                     const int64_t g = (int64_t)r - rec_base;
-                    const float sm = wave_sum(gm);
                     if (M != 0.f) {
-                        const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
-                                    sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
-                                    sbl = wave_sum(gbl);
-                        float v = lane == 0 ? su : lane == 1 ? sv : lane == 2 ? sa : lane == 3 ? sb : lane == 4 ? sc
-                                : lane == 5 ? so : lane == 6 ? sr : lane == 7 ? sg : lane == 8 ? sbl : sm;
-                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, (double)v);
-                        else if (lane == DREC) atomicAdd(d_masks + g, (double)v);
-                    } else if (lane == 0) {
-                        atomicAdd(d_masks + g, (double)sm);
+                        // lane q (< 10) of the wave receives the wave total of quantity q
+                        float v[10] = {gu, gv, ga, gb, gc, go, gr, gg, gbl, gm};
+                        const float x = wave_sum_transposed10(v, lane);
+                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, (double)x);
+                        else if (lane == DREC) atomicAdd(d_masks + g, (double)x);
+                    } else {
+                        const float sm = wave_sum(gm);
+                        if (lane == 0) atomicAdd(d_masks + g, (double)sm);
                     }
                 }
             }
