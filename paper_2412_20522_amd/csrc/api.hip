@@ -267,16 +267,18 @@ struct mgs_frame {
     bool sorted_in_alt = false, order_in_alt = false;
     // fixed workspace (mgs_frame_reserve): no allocation, no synchronisation
     bool reserved = false;
-    int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, W_cap = 0, cur_cap = 0;
+    int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, W_cap = 0, cur_cap = 0, stg_cap = 0;
     // device buffers: per record, then per narrow instance (32-bit tile keys),
     // wide entries, per tile, per pixel
     DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag,
         wide_pos, tmask;
-    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, t_final, last, stats, evals;
+    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, cur_stg, stg, t_final, last,
+        stats, evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
-    // 16, checkpoint count (u64) at 24, per-view wide ranges (u32 pairs) from 32
+    // 16, checkpoint count (u64) at 24, per-view wide ranges (u32 pairs) from
+    // 32, staged-entry counter (u32) at 192
     uint64_t* h_pinned = nullptr;  // read-back of misc
     uint32_t* keys_sorted() { return (uint32_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
     uint32_t* vals_sorted() { return (uint32_t*)(sorted_in_alt ? vals_alt.p : vals.p); }
@@ -285,12 +287,14 @@ struct mgs_frame {
     uint64_t* total() { return (uint64_t*)((char*)misc.p + 8); }
     uint64_t* wide_total() { return (uint64_t*)((char*)misc.p + 16); }
     uint64_t* cur_need() { return (uint64_t*)((char*)misc.p + 24); }
+    uint32_t* stg_count() { return (uint32_t*)((char*)misc.p + 192); }
     uint32_t* wide_range() { return (uint32_t*)((char*)misc.p + 32); }
     HybridBuffers hybrid() {
-        const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)(cur.bytes / 16);
+        const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)std::min(cur.bytes / 16, cur_stg.bytes / 8);
+        const uint64_t scap = reserved ? (uint64_t)stg_cap : (uint64_t)(stg.bytes / 8);
         return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const uint32_t*)wide.p, wide_range(),
                              (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
-                             flags()};
+                             flags(), (uint32_t*)cur_stg.p, (uint32_t*)stg.p, stg_count(), scap};
     }
 };
 
@@ -375,7 +379,8 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
                       &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos, &f->tmask,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
-                      &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->t_final,  &f->last,
+                      &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
+                      &f->t_final,  &f->last,
                       &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
                       &f->misc,     &f->queue,     &f->sum_tmp};
     for (DevBuf* b : bufs) release(*b);
@@ -410,20 +415,24 @@ mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
     if (!(slack >= 1.0)) return fail(ctx, MGS_ERR_INVALID_ARG, "slack %g must be >= 1 (or <= 0 to release)", slack);
     if (!f->have_forward || f->reserved)
         return fail(ctx, MGS_ERR_STATE, "mgs_frame_reserve needs a preceding plain mgs_forward");
-    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 32, hipMemcpyDeviceToHost, stream));
+    MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 200, hipMemcpyDeviceToHost, stream));
     MGS_HIP(ctx, hipStreamSynchronize(stream));
     const double K = (double)f->h_pinned[1], W = (double)f->h_pinned[2], C = (double)f->h_pinned[3];
+    const double S = (double)(f->h_pinned[24] & 0xffffffffu);
     const int64_t K_cap = (int64_t)std::ceil(K * slack) + 4096;
     const int64_t W_cap = (int64_t)std::ceil(W * slack) + 1024;
     const int64_t cur_cap = (int64_t)std::ceil(C * slack) + 4096;
+    const int64_t stg_cap = std::min<int64_t>((int64_t)std::ceil(S * slack) + 4096, 0xffffffffll);
     if (K_cap > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "instance capacity beyond 2^31 - 1");
     mgs_status s;
     const size_t kb = (size_t)K_cap * 4 + 16;
     if ((s = grow(ctx, f->keys, kb)) || (s = grow(ctx, f->vals, kb)) || (s = grow(ctx, f->keys_alt, kb)) ||
         (s = grow(ctx, f->vals_alt, kb)) || (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(K_cap))) ||
         (s = grow(ctx, f->wide, (size_t)W_cap * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) ||
-        (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)))
+        (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)) ||
+        (s = grow(ctx, f->cur_stg, (size_t)cur_cap * 8 + 8)) || (s = grow(ctx, f->stg, (size_t)stg_cap * 8 + 8)))
         return s;
+    f->stg_cap = stg_cap;
     f->K_cap = K_cap;
     f->W_cap = W_cap;
     f->cur_cap = cur_cap;
@@ -545,8 +554,7 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     } else {
         // the one synchronisation of the plain path: instance and wide counts
         // size the instance sort and the batch checkpoints
-        const size_t rb = 32 + 8 * (size_t)V;
-        MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, rb, hipMemcpyDeviceToHost, stream));
+        MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 200, hipMemcpyDeviceToHost, stream));
         MGS_HIP(ctx, hipStreamSynchronize(stream));
         const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
         const uint64_t K = f->h_pinned[1];
@@ -569,8 +577,15 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         if ((s = grow(ctx, f->keys, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 16)) ||
             (s = grow(ctx, f->keys_alt, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 16)) ||
             (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))) ||
-            (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)))
+            (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)) ||
+            (s = grow(ctx, f->cur_stg, (size_t)cur_bound * 8 + 8)))
             return s;
+        // the entries staged for the backward: room for the previous forward's
+        // count with a margin (a batch that does not fit is merged again)
+        const uint64_t prev = f->h_pinned[24] & 0xffffffffu;
+        const uint64_t want = std::min<uint64_t>(std::max<uint64_t>((uint64_t)P, prev + prev / 4), 0xffffffffull);
+        // (the count includes the unused tails of the workgroups' chunks)
+        if ((s = grow(ctx, f->stg, (size_t)want * 8 + 8))) return s;
     }
     f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 4, f->vals.bytes / 4);
     {
@@ -604,6 +619,7 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
     }
+    launch_fill_u32(stream, f->stg_count(), 1, 0u);
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
         f->have_stats = st->stats != 0;

@@ -537,6 +537,11 @@ __device__ __forceinline__ float wave_sum_transposed10(float (&v)[10], int lane)
     return x;
 }
 
+// Staged-list chunks: a persistent workgroup composites many tiles, a plain
+// one a single tile.
+constexpr uint32_t STG_CHUNK_PERSISTENT = 4096;
+constexpr uint32_t STG_CHUNK = 256;
+
 struct HybridLists {
     const uint32_t* vals;      // narrow instances (sorted positions) in (tile, position) order
     const uint2* ranges;       // narrow [start, end) per tile
@@ -548,6 +553,13 @@ struct HybridLists {
     const uint64_t* cur_need;  // checkpoints the tiles may take (device)
     uint64_t cur_cap;          // checkpoints the buffer holds
     uint32_t* flags;
+    // entries the forward staged per batch, kept for the backward:
+    // per checkpoint (offset into stg or all ones, count), and per staged
+    // entry (sorted position, index within the merged batch)
+    uint2* cur_stg;
+    uint2* stg;                // null: the backward merges again
+    uint32_t* stg_count;
+    uint64_t stg_cap;
 };
 
 // STATS: write the per-pixel work counters (stats_out, eval_out).
@@ -566,6 +578,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
         if (blockIdx.x == 0 && t == 0) atomicOr(hl.flags, FLAG_CAPACITY);
         return;
     }
+    // staged-list chunk of this workgroup (used by thread 0 only)
+    const uint32_t chunk = queue ? STG_CHUNK_PERSISTENT : STG_CHUNK;
+    uint32_t cbase = 0, cused = chunk;
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
@@ -603,6 +618,18 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
             const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, st);
+            // room for the staged entries in the list kept for the backward:
+            // thread 0 sub-allocates from a chunk the workgroup took from the
+            // global counter (one atomic per chunk, not per batch)
+            uint32_t my_off = 0;
+            if (hl.stg && t == 0) {
+                if (cused + (uint32_t)bt.M > chunk) {
+                    cbase = atomicAdd(hl.stg_count, chunk);
+                    cused = 0;
+                }
+                my_off = cbase + cused;
+                cused += (uint32_t)bt.M;
+            }
             for (int j = 0; j < bt.M; ++j) {
                 if (!__any(active)) break;
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
@@ -635,6 +662,21 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
                 active = false;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) active |= !done[i];
+            }
+            if (hl.stg) {
+                if (t == 0) {
+                    const uint32_t off = (uint64_t)my_off + (uint64_t)bt.M <= hl.stg_cap ? my_off : 0xffffffffu;
+                    L.wsum[8] = off;
+                    hl.cur_stg[hl.cur_off[tile] + b] = make_uint2(off, (uint32_t)bt.M);
+                }
+                __syncthreads();
+                const uint32_t off = L.wsum[8];
+                if (off != 0xffffffffu) {
+                    for (int p = t; p < bt.M; p += NT) {
+                        const uint32_t jj = __float_as_uint(L.Bv[p].w);
+                        hl.stg[off + p] = make_uint2(L.m[jj], jj);
+                    }
+                }
             }
             i1 += bt.nX;
             i2 += bt.nYraw;
@@ -737,12 +779,30 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
             for (int b = 0; b < nb; ++b)
                 if ((int)cur[b].z <= top) bstar = b;
         }
+        const uint2* cstg = hl.stg ? hl.cur_stg + hl.cur_off[tile] : nullptr;
         for (int b = bstar; b >= 0; --b) {
             const uint4 c = cur[b];
             const int m = (int)c.z;
-            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y,
-                                         batch, tcx, tcy, tb, st);
-            for (int j = bt.M - 1; j >= 0; --j) {
+            const uint2 cs = cstg ? cstg[b] : make_uint2(0xffffffffu, 0u);
+            int Mb;
+            if (cs.x != 0xffffffffu) {
+                // the entries the forward staged for this batch
+                Mb = (int)cs.y;
+                for (int p = t; p < Mb; p += NT) {
+                    const uint2 e = hl.stg[cs.x + p];
+                    const size_t i = e.x;
+                    float4 B = srec[3 * i + 1];
+                    B.w = __uint_as_float(e.y);
+                    L.A[p] = srec[3 * i];
+                    L.Bv[p] = B;
+                    L.C[p] = srec[3 * i + 2];
+                }
+                __syncthreads();
+            } else {
+                Mb = merge_batch(L, hl.vals, hl.wide, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y, batch, tcx,
+                                 tcy, tb, st).M;
+            }
+            for (int j = Mb - 1; j >= 0; --j) {
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
                 const int k = m + __float_as_int(B.w);  // index in the tile's full list
                 if (k > top) continue;                  // uniform: past every pixel's last entry
@@ -875,6 +935,10 @@ HybridLists make_lists(const HybridBuffers& b) {
     hl.cur_need = b.cur_need;
     hl.cur_cap = b.cur_cap;
     hl.flags = b.flags;
+    hl.cur_stg = reinterpret_cast<uint2*>(b.cur_stg);
+    hl.stg = reinterpret_cast<uint2*>(b.stg);
+    hl.stg_count = b.stg_count;
+    hl.stg_cap = b.stg_cap;
     return hl;
 }
 

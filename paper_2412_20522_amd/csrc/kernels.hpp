@@ -100,6 +100,10 @@ struct HybridBuffers {
     const uint64_t* cur_need;    // device: checkpoints the tiles may take
     uint64_t cur_cap;            // checkpoints the buffer holds
     uint32_t* flags;             // device flags (capacity)
+    uint32_t* cur_stg;           // [checkpoints, 2] staged-list offset (or ~0) and count
+    uint32_t* stg;               // [stg_cap, 2] staged entries; null: the backward merges again
+    uint32_t* stg_count;         // device counter of staged entries (zeroed before the forward)
+    uint64_t stg_cap;
 };
 // stats [P, 4] (examined, blended, blended with mask 0, last + 1) and evals
 // [P, 4] (evaluated, evaluated up to the last blended entry, 0, 0) are
