@@ -105,6 +105,28 @@ def stage_roofline(stage: str, ms_per_launch: float, counts: dict, frame_stats: 
                 algorithmic=byt, algorithmic_unit="bytes")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "counters_batched1M_8views.txt")
+TRAFFIC_SOURCES = ("hybrid.hip", "composite_common.hpp", "common.hpp")
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch of a compositing kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        line = next(l for l in open(TRAFFIC_FILE) if l.startswith("traffic: "))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line[len("traffic: "):])
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2412_20522_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16") or stage not in rec:
+        return None
+    return rec[stage]["bytes"]
+
+
 def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: float = 10.0) -> dict:
     """The FP64 oracle on a bounded sample of the same workload: the views
     of the batched step, one at a time (same masks, full masked fwd+bwd
@@ -306,7 +328,7 @@ def main() -> int:
             log(f"[bench]   {k:14s} {v[0] / v[1]:9.3f} ms/launch x {v[1]}")
     dom = max(stage_ms, key=lambda k: prof[k][0])
     roof = stage_roofline(dom, stage_ms[dom], counts, fstats, n, V, deg)
-    roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof, "traffic": None}
+    roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof, "traffic": measured_traffic(dom)}
 
     plain = None
     if not args.no_plain and V > 1:
