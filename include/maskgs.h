@@ -334,8 +334,10 @@ MGS_API mgs_status mgs_profile_read(mgs_ctx* ctx, double* ms, int64_t* launches)
 /* ---------------------------------------------------------------------- */
 
 /* EWA projection and SH colour (Sec. 3.1) of every Gaussian for every view.
- * rec [R, 12]: u, v, conic a, conic b, conic c, opacity, mask, 0, r, g, b, 0
- *   (conic (a, b, c) is the inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2);
+ * rec [R, 12]: u, v, a, b / a, c - b^2 / a, opacity, mask, 0, r, g, b, 0
+ *   (conic (a, b, c) is the inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2,
+ *   stored in the form a (dx + (b / a) dy)^2 + (c - b^2 / a) dy^2, which FP32
+ *   evaluates without cancellation for needle-shaped splats);
  * depth [R]: view-space z rounded to float32 from a double-precision
  *   transform (the sort key); radius [R]: ceil(3 sqrt(lambda_max));
  * tiles [R] (u32): number of tiles of the record's square footprint.
@@ -384,15 +386,20 @@ MGS_API mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const 
 
 /* Masked backward compositing in reverse order, recovering transmittance
  * by division.  d_rec [R, 9] (zeroed here, then accumulated): dL/du, dL/dv,
- * dL/d(conic a, b, c), dL/dopacity, dL/d(r, g, b); d_masks [n] (zeroed
- * here): dL/dM_i summed over views. */
+ * the conic gradient w.r.t. the three stored values (a, b / a, c - b^2 / a)
+ * of rec (per pixel t^2, 2 a t dy, dy^2 with t = dx + (b / a) dy, times
+ * dL/dQ: the thin and long directions of a needle stay apart in FP32),
+ * dL/dopacity, dL/d(r, g, b); d_masks [n] (zeroed here): dL/dM_i summed
+ * over views. */
 MGS_API mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
                                           const uint32_t* ranges, const mgs_camera* cams, int n_views,
                                           const mgs_settings* st, const float* t_final, const int32_t* last,
                                           const float* dl_dimages, int64_t n, float* d_rec, float* d_masks);
 
-/* Chain rule from d_rec [R, 9] to the Gaussian parameters, summed over
- * views (no atomics: one thread per Gaussian).  grads->d_masks is ignored. */
+/* Chain rule from d_rec [R, 9] (layout of mgs_composite_backward, conic
+ * gradient in the stored basis) to the Gaussian parameters, summed over
+ * views (no atomics: one thread per Gaussian), in double precision from the
+ * 3D covariance to the conic.  grads->d_masks is ignored. */
 MGS_API mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g,
                                         const mgs_camera* cams, int n_views, const mgs_settings* st,
                                         const float* d_rec, const mgs_gradients* grads);

@@ -44,9 +44,15 @@ constexpr uint32_t FLAG_CAPACITY = 1u;
 constexpr uint32_t FLAG_NONFINITE = 2u;
 
 // Record layout: 3 float4 per (view, Gaussian) record.
-//   A = (u, v, conic a, conic b)
-//   B = (conic c, opacity, mask, 0)
+//   A = (u, v, a, beta)
+//   B = (gamma, opacity, mask, 0)
 //   C = (r, g, b, 0)
+// The conic (inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2) is kept
+// as a, beta = b / a and gamma = c - b^2 / a, so that
+// Q = a (dx + beta dy)^2 + gamma dy^2 is a sum of two non-negative terms:
+// FP32 evaluation of the expanded form loses every digit for needle-shaped
+// splats (a c - b^2 tiny against a c), this one keeps full relative
+// precision.  The per-record gradients still refer to (a, b, c).
 constexpr int REC_F4 = 3;
 // Per-record 2D gradient layout: du, dv, da, db, dc, dopacity, dr, dg, db.
 constexpr int DREC = 9;

@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
                     Eval e;
                     if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
                     any = true;
-                    const float alpha = e.alpha, G = e.G, dx = e.dx, dy = e.dy;
+                    const float alpha = e.alpha, G = e.G, dy = e.dy;
                     const float ma = M * alpha;
                     const float one_m = 1.f - ma;
                     const float inv = __builtin_amdgcn_rcpf(one_m);
@@ -231,10 +231,13 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
                         const float dA = M * X;
                         go += G * dA;
                         const float dQ = -0.5f * B.y * G * dA;
-                        gu += dQ * 2.f * (A.z * dx + A.w * dy);
-                        gv += dQ * 2.f * (A.w * dx + B.x * dy);
-                        ga += dQ * dx * dx;
-                        gb += dQ * 2.f * dx * dy;
+                        // a dx + b dy = a t and b dx + c dy = beta a t + gamma dy; the
+                        // conic gradient is taken w.r.t. the stored (a, beta, gamma)
+                        const float at = A.z * e.t;
+                        gu += dQ * 2.f * at;
+                        gv += dQ * 2.f * fmaf(A.w, at, B.x * dy);
+                        ga += dQ * e.t * e.t;
+                        gb += dQ * 2.f * at * dy;
                         gc += dQ * dy * dy;
                     }
                     b0[i] = ma * Cc.x + one_m * b0[i];

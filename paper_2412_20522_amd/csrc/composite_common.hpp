@@ -27,14 +27,15 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewSet& views, uint32_t til
 // Evaluation of one entry at one pixel, shared by forward and backward so
 // both take the same FP32 decisions (3-sigma cut, alpha clamp and filter).
 struct Eval {
-    float dx, dy, G, oG, alpha;
+    float dx, dy, t, G, oG, alpha;  // t = dx + beta dy
 };
 
 __device__ __forceinline__ bool eval_entry(const float4& A, const float4& B, float px, float py,
                                            const DevSettings& st, Eval& e) {
     e.dx = A.x - px;
     e.dy = A.y - py;
-    const float Q = A.z * e.dx * e.dx + 2.f * A.w * e.dx * e.dy + B.x * e.dy * e.dy;
+    e.t = fmaf(A.w, e.dy, e.dx);
+    const float Q = A.z * e.t * e.t + B.x * e.dy * e.dy;
     if (!(Q <= st.q_max)) return false;
     e.G = __expf(-0.5f * Q);
     e.oG = B.y * e.G;

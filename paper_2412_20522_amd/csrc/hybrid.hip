@@ -43,8 +43,8 @@ struct TileBox {
 // pixel of the tile in the forward or the backward pass; dropping it leaves
 // every result unchanged.
 struct TouchPrep {
-    float u, v, a, b, c;
-    float nbc, nba;  // -b / c and -b / a (minimisers along the box edges)
+    float u, v, a, beta, gamma;
+    float nbc;       // -b / c: minimiser along a vertical edge (-beta along a horizontal one)
     float cut;       // +huge: no cut (always touches); < 0: reaches no pixel
 };
 
@@ -53,13 +53,13 @@ __device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B
     p.u = A.x;
     p.v = A.y;
     p.a = A.z;
-    p.b = A.w;
-    p.c = B.x;
-    // reciprocal approximations only move the edge minimisers slightly, which
-    // raises the computed minimum by a second-order amount far inside the
-    // margin below
-    p.nbc = -p.b * __builtin_amdgcn_rcpf(p.c);
-    p.nba = -p.b * __builtin_amdgcn_rcpf(p.a);
+    p.beta = A.w;
+    p.gamma = B.x;
+    // -b / c = -a beta / (a beta^2 + gamma); a reciprocal approximation only
+    // moves the edge minimiser slightly, which raises the computed minimum by
+    // a second-order amount far inside the margin below
+    const float ab = p.a * p.beta;
+    p.nbc = -ab * __builtin_amdgcn_rcpf(fmaf(ab, p.beta, p.gamma));
     float cut = st.q_max;
     if (st.alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / st.alpha_min));
     if (cut >= 3.0e38f) p.cut = 3.4e38f;          // no finite cut
@@ -75,20 +75,20 @@ __device__ __forceinline__ bool touch_test(const TouchPrep& p, const TileBox& tb
     const float dyl = p.v - tb.Y1, dyh = p.v - tb.Y0, dxl = p.u - tb.X1, dxh = p.u - tb.X0;
     float q;
     {
-        const float dx = dxh, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh);
-        q = p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy;
+        const float dx = dxh, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh), t = fmaf(p.beta, dy, dx);
+        q = p.a * t * t + p.gamma * dy * dy;
     }
     {
-        const float dx = dxl, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh);
-        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+        const float dx = dxl, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh), t = fmaf(p.beta, dy, dx);
+        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
     }
     {
-        const float dy = dyh, dx = fminf(fmaxf(p.nba * dy, dxl), dxh);
-        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+        const float dy = dyh, dx = fminf(fmaxf(-p.beta * dy, dxl), dxh), t = fmaf(p.beta, dy, dx);
+        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
     }
     {
-        const float dy = dyl, dx = fminf(fmaxf(p.nba * dy, dxl), dxh);
-        q = fminf(q, p.a * dx * dx + 2.f * p.b * dx * dy + p.c * dy * dy);
+        const float dy = dyl, dx = fminf(fmaxf(-p.beta * dy, dxl), dxh), t = fmaf(p.beta, dy, dx);
+        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
     }
     return q <= p.cut;
 }
@@ -816,7 +816,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                     Eval e;
                     if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
                     any = true;
-                    const float alpha = e.alpha, G = e.G, dx = e.dx, dy = e.dy;
+                    const float alpha = e.alpha, G = e.G, dy = e.dy;
                     const float ma = M * alpha;
                     const float one_m = 1.f - ma;
                     const float inv = __builtin_amdgcn_rcpf(one_m);
@@ -832,10 +832,13 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                         const float dA = M * X;
                         go += G * dA;
                         const float dQ = -0.5f * B.y * G * dA;
-                        gu += dQ * 2.f * (A.z * dx + A.w * dy);
-                        gv += dQ * 2.f * (A.w * dx + B.x * dy);
-                        ga += dQ * dx * dx;
-                        gb += dQ * 2.f * dx * dy;
+                        // a dx + b dy = a t and b dx + c dy = beta a t + gamma dy; the
+                        // conic gradient is taken w.r.t. the stored (a, beta, gamma)
+                        const float at = A.z * e.t;
+                        gu += dQ * 2.f * at;
+                        gv += dQ * 2.f * fmaf(A.w, at, B.x * dy);
+                        ga += dQ * e.t * e.t;
+                        gb += dQ * 2.f * at * dy;
                         gc += dQ * dy * dy;
                     }
                     b0[i] = ma * Cc.x + one_m * b0[i];

@@ -163,7 +163,9 @@ struct ViewGeom {
     bool clx, cly;
     double T0[3], T1[3];  // J W
     double a, b, c;       // 2D covariance incl. dilation
-    double ca, cb, cc;    // conic
+    double detv;          // its determinant
+    double ca;            // conic entry a = c / det
+    double beta, gamma;   // conic stored as (ca, cb / ca, cc - cb^2 / ca) = (ca, -b / c, 1 / c)
     float radius;
 };
 
@@ -210,15 +212,15 @@ __device__ __forceinline__ ViewGeom view_geom(const DevView& cam, const DevSetti
     o.c = U10 * o.T1[0] + U11 * o.T1[1] + U12 * o.T1[2] + dil;
     const double det = o.a * o.c - o.b * o.b;
     if (!(det > 0.0)) { o.valid = false; return o; }
-    const double idet = 1.0 / det;
-    o.ca = o.c * idet;
-    o.cb = -o.b * idet;
-    o.cc = o.a * idet;
+    o.detv = det;
+    o.ca = o.c / det;
+    o.beta = -o.b / o.c;
+    o.gamma = 1.0 / o.c;
     const double mid = 0.5 * (o.a + o.c);
     const double disc = fmax((double)st.lambda_floor, mid * mid - det);
     o.radius = (float)ceil(3.0 * sqrt(mid + sqrt(disc)));
-    if (!(isfinite(o.u) && isfinite(o.v) && isfinite((float)o.ca) && isfinite((float)o.cb) &&
-          isfinite((float)o.cc) && isfinite(o.radius) && o.radius > 0.f))
+    if (!(isfinite(o.u) && isfinite(o.v) && isfinite((float)o.ca) && isfinite((float)o.beta) &&
+          isfinite((float)o.gamma) && isfinite(o.radius) && o.radius > 0.f))
         o.valid = false;
     return o;
 }
@@ -280,8 +282,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             x1 = fmin(x1, (double)(cam.grid_w - 1)); y1 = fmin(y1, (double)(cam.grid_h - 1));
             count = (x0 <= x1 && y0 <= y1) ? (uint32_t)((x1 - x0 + 1.0) * (y1 - y0 + 1.0)) : 0u;
         }
-        rec[3 * r] = make_float4(o.u, o.v, (float)o.ca, (float)o.cb);
-        rec[3 * r + 1] = make_float4((float)o.cc, opac, mval, 0.f);
+        rec[3 * r] = make_float4(o.u, o.v, (float)o.ca, (float)o.beta);
+        rec[3 * r + 1] = make_float4((float)o.gamma, opac, mval, 0.f);
         rec[3 * r + 2] = make_float4(col[0], col[1], col[2], 0.f);
         depth_out[r] = o.depth;
         radius_out[r] = o.radius;
@@ -360,13 +362,15 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             gp[1] += (dd[1] - proj * dy) * dinv;
             gp[2] += (dd[2] - proj * dz) * dinv;
         }
-        // conic -> 2D covariance: H = -Conic Gc Conic, Gc = [[dca, dcb/2], [dcb/2, dcc]]
-        const double hb = 0.5 * dcb;
-        const double X00 = o.ca * dca + o.cb * hb, X01 = o.ca * hb + o.cb * dcc;
-        const double X10 = o.cb * dca + o.cc * hb, X11 = o.cb * hb + o.cc * dcc;
-        const double H00 = -(X00 * o.ca + X01 * o.cb);
-        const double H01 = -(X00 * o.cb + X01 * o.cc);
-        const double H11 = -(X10 * o.cb + X11 * o.cc);
+        // stored conic (a, beta, gamma) = (c / det, -b / c, 1 / c) of the 2D
+        // covariance [[a, b], [b, c]] -> H = dL/dcov2D (symmetric, H01 is half
+        // the derivative w.r.t. the shared off-diagonal entry).  The per-pixel
+        // sums arrive in this basis because it keeps the thin direction of a
+        // needle apart from the long one in FP32.
+        const double s2 = o.c * o.c, idet2 = 1.0 / (o.detv * o.detv);
+        const double H00 = -dca * s2 * idet2;
+        const double H01 = 0.5 * (2.0 * dca * o.b * o.c * idet2 - dcb / o.c);
+        const double H11 = (-dca * o.b * o.b * idet2 + dcb * o.b / s2) - dcc / s2;
         // dSigma3 += T^T H T ; dT = 2 H T Sigma3
         double HT0[3], HT1[3];
 #pragma unroll

@@ -75,9 +75,34 @@ def gpu_lists(ctx, rec, depth, radius, tiles, n, cams, gst):
     return offsets[:R], K, keys[:K], vals[:K], ranges
 
 
+def conic_from_rec(r) -> np.ndarray:
+    """Records keep the conic as (a, b / a, c - b^2 / a); back to (a, b, c)
+    in FP64 (b exactly, c to FP64 rounding)."""
+    r = np.asarray(r, np.float64)
+    a, beta, gamma = r[:, 2], r[:, 3], r[:, 4]
+    return np.stack([a, a * beta, gamma + (a * beta) * beta], 1)
+
+
+def dstable_from_dabc(a, beta, d) -> np.ndarray:
+    """Gradient w.r.t. the conic (A, B, C) -> gradient w.r.t. the stored
+    (a, beta, gamma) = (A, B / A, C - B^2 / A), the basis the kernels
+    accumulate in (chain rule through A = a, B = a beta, C = gamma + a beta^2)."""
+    a, beta, d = np.asarray(a, np.float64), np.asarray(beta, np.float64), np.asarray(d, np.float64)
+    dA, dB, dC = d[:, 0], d[:, 1], d[:, 2]
+    return np.stack([dA + beta * dB + beta * beta * dC, a * dB + 2.0 * a * beta * dC, dC], 1)
+
+
+def dabc_from_dstable(conic, d) -> np.ndarray:
+    """Inverse of dstable_from_dabc at the conic (A, B, C)."""
+    conic, d = np.asarray(conic, np.float64), np.asarray(d, np.float64)
+    A, B = conic[:, 0], conic[:, 1]
+    da, db, dg = d[:, 0], d[:, 1], d[:, 2]
+    return np.stack([da - db * B / (A * A) + dg * (B / A) ** 2, db / A - 2.0 * dg * B / A, dg], 1)
+
+
 def oracle_inputs_from_rec(rec: torch.Tensor):
     r = rec.detach().cpu().numpy().astype(np.float64)
-    return dict(mean2d=r[:, 0:2].copy(), conic=r[:, 2:5].copy(), opacity=r[:, 5].copy(), color=r[:, 8:11].copy(),
+    return dict(mean2d=r[:, 0:2].copy(), conic=conic_from_rec(r), opacity=r[:, 5].copy(), color=r[:, 8:11].copy(),
                 mask=r[:, 6].copy())
 
 

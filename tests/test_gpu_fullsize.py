@@ -1,0 +1,190 @@
+"""Parity at the full sizes of the object (200k Gaussians, 800x800), unbounded
+(1.5M, 1264x832) and batched (1M, 8 uneven views) workloads, in the launch
+configuration the benchmark times (16x16 tiles, batch depth 256, 2 / 4
+pixels per thread, persistent, wide lists, tile culling).
+
+Stage protocol: the GPU's own projected records (exported from the frame)
+are widened exactly to FP64 and fed to the oracle's lists, compositing and
+backward; images must then agree element-wise within 1e-5 of the image
+scale on unflagged pixels and every gradient within 2e-3 (norm-wise; the
+mask gradient also element-wise on Gaussians that touch no flagged pixel).
+On the unbounded workload dL/dM is also checked against finite differences:
+for 64 seeded Gaussians, the change of <w, C> over a mask step of 1/8, C
+rendered by the (parity-checked) forward, taken over the pixels whose stop
+entry does not move (where C is affine in the mask) and compared with the
+gradient of <w, C> restricted to those pixels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from tests import gpu_util as U
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+BENCH = dict(tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=2, bwd_ppt=4, persistent=1, wide_tiles=64,
+             tile_cull=1, stats=1)
+
+
+def _masks(scene):
+    if "masks" in scene:
+        return scene["masks"].astype(np.float32)
+    m, _ = oracle.sample_masks(scene["mask_scores"], float(scene.get("gumbel_tau", 0.5)), 2412, 0)
+    return np.asarray(m, np.float32)
+
+
+def _gpu(scene, masks, dl, bg):
+    from paper_2412_20522_amd import maskgs as M
+    from paper_2412_20522_amd.raster import Rasterizer
+    cams = scene["cameras"]
+    rast = Rasterizer(0, sh_degree=scene["sh_degree"], bg=bg, **BENCH)
+    dev = U.to_device(scene, masks)
+    params = {k: dev[k] for k in U.PARAM_KEYS}
+    frame = rast.acquire_frame()
+    img = rast.forward(frame, params, dev["masks"], cams)
+    grads = rast.backward(frame, params, torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    ex = {k: M.mgs_frame_export(rast.ctx, frame, k) for k in ("records", "radius", "depth")}
+    evals = rast.count_evals(frame)
+    torch.cuda.synchronize()
+    rast.release_frame(frame)
+    return img.cpu().numpy().astype(np.float64), grads, ex, evals
+
+
+def _oracle_on_gpu_records(scene, ex, masks, dl, bg):
+    cams = scene["cameras"]
+    n = scene["means"].shape[0]
+    ost = oracle.RasterSettings(sh_degree=scene["sh_degree"], bg=bg)
+    oi = U.oracle_inputs_from_rec(ex["records"].view(-1, 12))
+    rad = ex["radius"].cpu().numpy().astype(np.float64)
+    dbits = U.u32(ex["depth"])
+    ws, hs = [c["width"] for c in cams], [c["height"] for c in cams]
+    m64 = masks.astype(np.float64)
+    ol = oracle.build_lists(ws, hs, n, oi["mean2d"], rad, dbits, (rad > 0).astype(np.uint8), ost)
+    of = oracle.render_fwd(ws, hs, n, oi["mean2d"], oi["conic"], oi["opacity"], oi["color"], m64, ol, ost)
+    ob = oracle.render_bwd(ws, hs, n, oi["mean2d"], oi["conic"], oi["opacity"], oi["color"], m64, ol,
+                           dl.astype(np.float64), ost)
+    og = oracle.project_bwd(scene, cams, ost, ob.d_mean2d, ob.d_conic, ob.d_opacity, ob.d_color)
+    return ost, oi, rad, dbits, ol, of, ob, og
+
+
+def _pixel_mask(ok, cams):
+    """Per-pixel flags -> per-image-element mask (channel-planar per view)."""
+    out, off = [], 0
+    for c in cams:
+        p = c["width"] * c["height"]
+        out.append(np.tile(ok[off:off + p], 3))
+        off += p
+    return np.concatenate(out)
+
+
+def _check(scene, img, grads, evals, of, ob, og):
+    cams = scene["cameras"]
+    ok = of.flags == 0
+    # decisions within the oracle's margins (deep chains near T_min) are flagged
+    assert ok.mean() > 0.99
+    scale = max(np.abs(of.image).max(), 1.0)
+    err = np.abs(img - of.image)[_pixel_mask(ok, cams)].max()
+    assert err <= 1e-5 * scale, err
+    assert U.rel_err(img, of.image) <= 1e-5
+    # work counters: blends are those of the oracle's lists
+    assert evals["blended"] == pytest.approx(int(of.n_blend.sum()), rel=1e-5)
+    for name, a, b in [("means", grads.means, og.means), ("log_scales", grads.log_scales, og.log_scales),
+                       ("quats", grads.quats, og.quats), ("opacity_logits", grads.opacity_logits, og.opacity_logits),
+                       ("sh", grads.sh, og.sh), ("masks", grads.masks, ob.d_mask)]:
+        e = U.rel_err(a.cpu().numpy(), b)
+        assert e <= 2e-3, (name, e)
+    n = scene["means"].shape[0]
+    ex = ob.touched_flagged.astype(bool).reshape(-1, n).any(axis=0)
+    U.assert_grad_close(grads.masks.cpu().numpy(), ob.d_mask, ex, name="mask")
+
+
+def _dl(scene, seed):
+    P = sum(c["width"] * c["height"] for c in scene["cameras"])
+    return (np.random.default_rng(seed).normal(size=3 * P) * 1e-3).astype(np.float32)
+
+
+def test_object_scene_full_size():
+    s = scenegen.object_scene()
+    bg = (0.1, 0.2, 0.3)
+    masks = _masks(s)
+    dl = _dl(s, 21)
+    img, grads, ex, evals = _gpu(s, masks, dl, bg)
+    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
+    _check(s, img, grads, evals, of, ob, og)
+
+
+def test_unbounded_scene_full_size_and_mask_fd():
+    s = scenegen.unbounded_scene()
+    bg = (0.0, 0.0, 0.0)
+    masks = _masks(s)
+    dl = _dl(s, 22)
+    img, grads, ex, evals = _gpu(s, masks, dl, bg)
+    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
+    _check(s, img, grads, evals, of, ob, og)
+    # dL/dM against finite differences of the forward (parity-checked above)
+    # on 64 seeded Gaussians with a non-negligible mask gradient.  With
+    # L = <w, C>, C is affine in one mask on every pixel whose stop entry does
+    # not move over the step (T after the Gaussian is monotone in its mask), so
+    # a one-sided difference over a step of 1/8 inside [0, 1], taken over
+    # those pixels, equals the gradient of L restricted to them (w zeroed on
+    # the pixels whose stop moved).  The forward is deterministic: pixels
+    # outside the footprint cancel exactly.
+    from paper_2412_20522_amd import maskgs as M
+    from paper_2412_20522_amd.raster import Grads, Rasterizer
+    cams = s["cameras"]
+    P = cams[0]["width"] * cams[0]["height"]
+    rast = Rasterizer(0, sh_degree=s["sh_degree"], bg=bg, **BENCH)
+    dev = U.to_device(s, masks)
+    params = {k: dev[k] for k in U.PARAM_KEYS}
+    frame = rast.acquire_frame()
+    gpu_dm = grads.masks.cpu().numpy().astype(np.float64)
+    cand = np.nonzero(np.abs(gpu_dm) > 1e-3 * np.abs(gpu_dm).max())[0]
+    pick = np.random.default_rng(23).choice(cand, size=min(64, cand.size), replace=False)
+    out = Grads(*(torch.empty_like(params[k]) for k in U.PARAM_KEYS), torch.empty(masks.size, device="cuda"))
+    step = 1.0 / 8.0
+    fd, got, moved_frac, noise = [], [], [], []
+    for g in pick:
+        outs = []
+        hi = float(masks[g]) if masks[g] > 0.5 else step
+        for val in (hi, hi - step):
+            mm = masks.copy()
+            mm[g] = val
+            img = rast.forward(frame, params, torch.from_numpy(mm).cuda(), cams)
+            exam = M.mgs_frame_export(rast.ctx, frame, "stats").view(-1, 4)[:, 0].clone()
+            torch.cuda.synchronize()
+            outs.append((img.cpu().numpy().astype(np.float64), exam.cpu().numpy()))
+        moved = outs[0][1] != outs[1][1]
+        w = dl.astype(np.float64).copy()
+        w[np.tile(moved, 3)] = 0.0
+        moved_frac.append(moved.mean())
+        diff = outs[0][0] - outs[1][0]
+        fd.append(float(np.dot(w, diff)) / step)
+        # FP32 rounding of the two images on the pixels that changed (pixels
+        # that did not change cancel exactly): a 3-sigma bound of its effect
+        ch = diff != 0
+        ulp = 2.0 ** -24 * (np.abs(outs[0][0][ch]) + np.abs(outs[1][0][ch]))
+        noise.append(3.0 * float(np.sqrt(np.sum((w[ch] * ulp) ** 2))) / step)
+        rast.forward(frame, params, dev["masks"], cams)
+        rast.backward(frame, params, torch.from_numpy(w.astype(np.float32)).cuda(), out=out)
+        got.append(float(out.masks[int(g)].item()))
+    rast.release_frame(frame)
+    assert len(fd) >= 16, len(fd)
+    assert max(moved_frac) < 0.05
+    fd, got, noise = np.array(fd), np.array(got), np.array(noise)
+    tol = 2e-3 * np.abs(fd) + noise
+    assert np.all(np.abs(got - fd) <= tol), np.max(np.abs(got - fd) / tol)
+    # the difference is resolved well enough to test something
+    assert np.median(noise / np.abs(fd)) < 2e-3
+
+
+def test_batched_scene_full_size():
+    s = scenegen.batched_scene()
+    bg = (0.0, 0.0, 0.0)
+    masks = _masks(s)
+    dl = _dl(s, 24)
+    img, grads, ex, evals = _gpu(s, masks, dl, bg)
+    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
+    _check(s, img, grads, evals, of, ob, og)

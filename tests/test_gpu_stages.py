@@ -84,7 +84,7 @@ def test_project_matches_oracle(ctx, kind):
         r = rec[sl][gvalid]
         np.testing.assert_allclose(r[:, 0:2], pr.mean2d[gvalid], rtol=0, atol=2e-4 * max(cam["width"], 1) / 100)
         scale = np.abs(pr.conic[gvalid]).max(axis=1, keepdims=True)
-        np.testing.assert_allclose(r[:, 2:5] / scale, pr.conic[gvalid] / scale, rtol=0, atol=5e-5)
+        np.testing.assert_allclose(U.conic_from_rec(r) / scale, pr.conic[gvalid] / scale, rtol=0, atol=5e-5)
         np.testing.assert_allclose(r[:, 5], pr.opacity[gvalid], rtol=2e-6)
         np.testing.assert_allclose(r[:, 8:11], pr.color[gvalid], rtol=0, atol=5e-6)
         np.testing.assert_array_equal(r[:, 6], s["masks"][gvalid])
@@ -312,7 +312,8 @@ def test_composite_backward_matches_oracle(ctx, kind, shape):
     g = d_rec.cpu().numpy().astype(np.float64)
     ex = ob.touched_flagged.astype(bool)
     U.assert_grad_close(g[:, 0:2], ob.d_mean2d, ex, name="mean2d")
-    U.assert_grad_close(g[:, 2:5], ob.d_conic, ex, name="conic")
+    rec64 = r["rec"].cpu().numpy().reshape(-1, 12).astype(np.float64)
+    U.assert_grad_close(g[:, 2:5], U.dstable_from_dabc(rec64[:, 2], rec64[:, 3], ob.d_conic), ex, name="conic")
     U.assert_grad_close(g[:, 5], ob.d_opacity, ex, name="opacity")
     U.assert_grad_close(g[:, 6:9], ob.d_color, ex, name="color")
     n = r["n"]
@@ -341,7 +342,11 @@ def test_project_backward_matches_oracle(ctx):
         U.M().mgs_project_backward(ctx, U.gstruct(dev), cams, gst, d_rec_t, gr)
         torch.cuda.synchronize()
         dr = d_rec.astype(np.float32).astype(np.float64)
-        og = oracle.project_bwd(s, cams, ost, dr[:, 0:2], dr[:, 2:5], dr[:, 5], dr[:, 6:9])
+        # the kernel reads the conic gradient w.r.t. the stored (a, beta, gamma)
+        prs = [oracle.project(s, c, ost) for c in cams]
+        conic = np.concatenate([np.where(p.valid[:, None] > 0, p.conic, 1.0) for p in prs])
+        dabc = U.dabc_from_dstable(conic, dr[:, 2:5])
+        og = oracle.project_bwd(s, cams, ost, dr[:, 0:2], dabc, dr[:, 5], dr[:, 6:9])
         for k, o in [("means", og.means), ("log_scales", og.log_scales), ("quats", og.quats),
                      ("opacity_logits", og.opacity_logits), ("sh", og.sh)]:
             U.assert_grad_close(out[k].cpu().numpy().astype(np.float64), o, name=f"{kind}:{k}")
