@@ -49,6 +49,8 @@ extern "C" {
 
 #define MGS_API __attribute__((visibility("default")))
 #define MGS_MAX_VIEWS 16
+/* Side, in tiles, of the regions that list wide records. */
+#define MGS_REGION_TILES 4
 
 typedef struct ihipStream_t* mgs_stream; /* hipStream_t */
 
@@ -95,23 +97,25 @@ typedef struct {
                                 multiple of 64) */
     int32_t bwd_ppt;         /* pixels per thread in backward compositing */
     int32_t wide_tiles;      /* hybrid binning: a record covering more tiles than
-                                this is kept once in its view's depth-ordered wide
-                                list instead of being duplicated per tile; the
-                                compositing merges it into every tile list it
-                                covers, so results are those of plain binning.
-                                0: 64 tiles; < 0: off */
+                                this is listed once per region of
+                                MGS_REGION_TILES^2 tiles it overlaps instead of
+                                once per tile; the compositing merges a region's
+                                list into each of its tiles' lists, so results
+                                are those of plain binning.  0: 64 tiles;
+                                < 0: off */
     int32_t stats;           /* 1: the forward writes per-pixel work counters
                                 (mgs_frame_count_evals, exports STATS and EVALS);
                                 0: it does not (slightly faster) */
-    int32_t tile_cull;       /* 1: a narrow record covering at most 64 tiles is
-                                duplicated only into the tiles of its rectangle
-                                where it can pass the per-pixel filters
-                                (Q <= q_max, alpha >= alpha_min) at some pixel
-                                centre (a conservative exact test), which leaves
+    int32_t tile_cull;       /* 1: a record is listed only in the tiles (regions)
+                                of its rectangle where it can pass the per-pixel
+                                filters (Q <= q_max, alpha >= alpha_min) at some
+                                pixel centre (a conservative exact test), and a
+                                region entry joins a tile's list only if it
+                                passes the same test for that tile, which leaves
                                 every image and gradient unchanged;
-                                0: into every tile of its rectangle, the lists
-                                of Sec. 3.1 exactly (for list parity and for
-                                counting entries examined on those lists) */
+                                0: every tile (region) of its rectangle, the
+                                lists of Sec. 3.1 exactly (for list parity and
+                                for counting entries examined on those lists) */
 } mgs_settings;
 
 /* Gaussian parameters (device pointers, float32). */
@@ -139,10 +143,11 @@ typedef struct {
 
 typedef struct {
     int64_t n_gaussians, n_views, n_records, n_pixels;
-    int64_t n_instances;     /* K of the last forward */
+    int64_t n_instances;     /* K of the last forward: list entries (tile and
+                                region) */
     int64_t total_tiles;
     int64_t instance_capacity;
-    int64_t n_wide;          /* records in the wide lists (hybrid binning) */
+    int64_t n_wide;          /* records listed per region (hybrid binning) */
     int32_t sort_passes;
     int32_t tile_bits;
 } mgs_frame_stats;
@@ -185,11 +190,11 @@ MGS_API mgs_status mgs_frame_get_stats(const mgs_frame* frame, mgs_frame_stats* 
 
 /* Masked forward rendering of n_views cameras (host array cams[n_views],
  * 1 <= n_views <= MGS_MAX_VIEWS): projection, depth order of the records,
- * narrow/wide split, key duplication, radix sort, tile ranges, masked
+ * per-tile and per-region lists (key duplication, radix sort, ranges), masked
  * compositing (Eq. 3-4 with the background term).  images [3 * P], packed
  * per view and channel-planar, receives the rendering; t_final [P]
  * (optional, may be NULL) the final transmittance.  Synchronises the stream
- * once, to read the instance and wide counts and size the sort, unless the
+ * once, to read the list entry counts and size the sort, unless the
  * frame has a fixed workspace (mgs_frame_reserve).  Errors:
  * MGS_ERR_INVALID_ARG, MGS_ERR_NONFINITE (non-finite projected geometry),
  * MGS_ERR_CAPACITY, MGS_ERR_OOM, MGS_ERR_HIP. */
@@ -209,7 +214,7 @@ MGS_API mgs_status mgs_backward(mgs_frame* frame, mgs_stream stream, const float
                                 const mgs_gradients* grads);
 
 /* Fixed workspace for stream capture (hipGraph): after a plain mgs_forward on
- * this frame, sizes the instance, wide-entry and batch-checkpoint buffers to
+ * this frame, sizes the list-entry and batch-checkpoint buffers to
  * that forward's counts times `slack` (>= 1) and switches the frame to a mode
  * in which mgs_forward and mgs_backward neither allocate nor synchronise: the
  * live counts stay on the device, the sort and the compositing read them
@@ -244,23 +249,26 @@ MGS_API mgs_status mgs_autotune(mgs_frame* frame, mgs_stream stream, const mgs_g
  * caller-owned, at least the reported size):
  *   MGS_EXPORT_RECORDS  [R, 12] f32 projected records (layout of mgs_project)
  *   MGS_EXPORT_DEPTH    [R] f32, MGS_EXPORT_RADIUS [R] f32, MGS_EXPORT_TILES [R] u32
- *   MGS_EXPORT_VALUES   [K] u32 narrow instances in (tile, depth, record) order,
+ *   MGS_EXPORT_VALUES   [K] u32 list entries in (cell, depth, record) order,
  *                       as positions into ORDER
- *   MGS_EXPORT_RANGES   [total_tiles, 2] u32
+ *   MGS_EXPORT_RANGES   [total_tiles + total_regions, 2] u32 [start, end) into
+ *                       VALUES: per tile (global tile ids, views in order,
+ *                       row-major), then per region
  *   MGS_EXPORT_T_FINAL  [P] f32, MGS_EXPORT_LAST [P] i32
  *   MGS_EXPORT_STATS    [P, 4] i32 (examined, blended, blended with mask 0,
  *                       entries up to the last blended one)
  *   MGS_EXPORT_EVALS    [P, 4] i32 (evaluated, evaluated up to the last blended
  *                       entry, 0, 0)
- *   MGS_EXPORT_WIDE     [W, 4] u32 wide entries per view in (depth, record)
- *                       order: position into ORDER, record, x0 | y0 << 16,
- *                       x1 | y1 << 16 (inclusive tile rectangle)
- *   MGS_EXPORT_WIDE_RANGES [n_views, 2] u32 [start, end) into the wide entries
  *   MGS_EXPORT_ORDER    [R] u32 record ids in (view, depth, record) order,
  *                       records without tiles last within their view
- * VALUES and RANGES hold the narrow instances only; a tile's list is their
- * merge with the wide entries of its view whose rectangle contains it, and
- * LAST holds indices into that merged list.
+ * Records covering more tiles than the wide threshold are listed per region
+ * (MGS_REGION_TILES x MGS_REGION_TILES tiles, row-major per view, views in
+ * order) instead of per tile.  A tile's list is the merge, in (depth, record)
+ * order, of its own entries with the entries of its region that belong to
+ * it: with settings.tile_cull = 0 those whose square tile rectangle contains
+ * the tile (the lists of Sec. 3.1), else those that pass the exact touch
+ * test (as the tile's own entries then do).  LAST and STATS hold indices
+ * into that merged list.
  * *bytes (host) receives the size; with dst NULL only the size is returned. */
 typedef enum {
     MGS_EXPORT_RECORDS = 0,
@@ -272,8 +280,6 @@ typedef enum {
     MGS_EXPORT_T_FINAL,
     MGS_EXPORT_LAST,
     MGS_EXPORT_STATS,
-    MGS_EXPORT_WIDE,
-    MGS_EXPORT_WIDE_RANGES,
     MGS_EXPORT_ORDER,
     MGS_EXPORT_EVALS
 } mgs_export;

@@ -178,7 +178,7 @@ ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t*
     ViewSet vs;
     memset(&vs, 0, sizeof vs);
     vs.n_views = n_views;
-    uint32_t toff = 0, poff = 0;
+    uint32_t toff = 0, poff = 0, roff = 0;
     for (int i = 0; i < n_views; ++i) {
         const mgs_camera& c = cams[i];
         DevView& d = vs.v[i];
@@ -198,14 +198,19 @@ ViewSet make_views(const mgs_camera* cams, int n_views, int tw, int th, int64_t*
         d.grid_h = (c.height + th - 1) / th;
         d.tile_off = toff;
         d.px_off = poff;
-        // records covering more tiles than wide_min go to the view's wide list
+        // records covering more tiles than wide_min are listed per region
         if (wide_tiles < 0) d.wide_min = 0xffffffffu;
         else if (wide_tiles > 0) d.wide_min = (uint32_t)wide_tiles;
         else d.wide_min = 64u;
+        d.reg_w = (d.grid_w + REGION - 1) / REGION;
+        d.reg_h = (d.grid_h + REGION - 1) / REGION;
+        d.reg_off = roff;
         toff += (uint32_t)(d.grid_w * d.grid_h);
         poff += (uint32_t)(c.width * c.height);
+        roff += (uint32_t)(d.reg_w * d.reg_h);
     }
     vs.total_tiles = toff;
+    vs.total_regions = roff;
     if (total_px) *total_px = poff;
     return vs;
 }
@@ -267,17 +272,17 @@ struct mgs_frame {
     bool sorted_in_alt = false, order_in_alt = false;
     // fixed workspace (mgs_frame_reserve): no allocation, no synchronisation
     bool reserved = false;
-    int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, W_cap = 0, cur_cap = 0, stg_cap = 0;
-    // device buffers: per record, then per narrow instance (32-bit tile keys),
-    // wide entries, per tile, per pixel
-    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag,
-        wide_pos, tmask;
-    DevBuf keys, vals, keys_alt, vals_alt, wide, ranges, caps, cur_off, nbatch, cur, cur_stg, stg, t_final, last,
-        stats, evals;
+    int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, cur_cap = 0, stg_cap = 0;
+    // device buffers: per record, then per list entry (32-bit cell keys), per
+    // tile and region, per pixel
+    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, tmask,
+        cls_part;
+    DevBuf keys, vals, keys_alt, vals_alt, ranges, caps, cur_off, nbatch, cur, cur_stg, stg, t_final, last, stats,
+        evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
-    // misc: flags (u32) at 0, instance count (u64) at 8, wide count (u64) at
-    // 16, checkpoint count (u64) at 24, per-view wide ranges (u32 pairs) from
+    // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
+    // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
     // 32, staged-entry counter (u32) at 192
     uint64_t* h_pinned = nullptr;  // read-back of misc
     uint32_t* keys_sorted() { return (uint32_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
@@ -285,15 +290,13 @@ struct mgs_frame {
     uint32_t* record_order() { return (uint32_t*)(order_in_alt ? rvals_alt.p : rvals.p); }
     uint32_t* flags() { return (uint32_t*)misc.p; }
     uint64_t* total() { return (uint64_t*)((char*)misc.p + 8); }
-    uint64_t* wide_total() { return (uint64_t*)((char*)misc.p + 16); }
+    uint64_t* wide_counts() { return (uint64_t*)((char*)misc.p + 16); }
     uint64_t* cur_need() { return (uint64_t*)((char*)misc.p + 24); }
     uint32_t* stg_count() { return (uint32_t*)((char*)misc.p + 192); }
-    uint32_t* wide_range() { return (uint32_t*)((char*)misc.p + 32); }
     HybridBuffers hybrid() {
         const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)std::min(cur.bytes / 16, cur_stg.bytes / 8);
         const uint64_t scap = reserved ? (uint64_t)stg_cap : (uint64_t)(stg.bytes / 8);
-        return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (const uint32_t*)wide.p, wide_range(),
-                             (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
+        return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
                              flags(), (uint32_t*)cur_stg.p, (uint32_t*)stg.p, stg_count(), scap};
     }
 };
@@ -377,8 +380,8 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
-                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->wide_pos, &f->tmask,
-                      &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->wide,     &f->ranges,
+                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->tmask, &f->cls_part,
+                      &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
                       &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
                       &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
@@ -417,10 +420,9 @@ mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
         return fail(ctx, MGS_ERR_STATE, "mgs_frame_reserve needs a preceding plain mgs_forward");
     MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 200, hipMemcpyDeviceToHost, stream));
     MGS_HIP(ctx, hipStreamSynchronize(stream));
-    const double K = (double)f->h_pinned[1], W = (double)f->h_pinned[2], C = (double)f->h_pinned[3];
+    const double K = (double)f->h_pinned[1], C = (double)f->h_pinned[3];
     const double S = (double)(f->h_pinned[24] & 0xffffffffu);
     const int64_t K_cap = (int64_t)std::ceil(K * slack) + 4096;
-    const int64_t W_cap = (int64_t)std::ceil(W * slack) + 1024;
     const int64_t cur_cap = (int64_t)std::ceil(C * slack) + 4096;
     const int64_t stg_cap = std::min<int64_t>((int64_t)std::ceil(S * slack) + 4096, 0xffffffffll);
     if (K_cap > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "instance capacity beyond 2^31 - 1");
@@ -428,13 +430,11 @@ mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
     const size_t kb = (size_t)K_cap * 4 + 16;
     if ((s = grow(ctx, f->keys, kb)) || (s = grow(ctx, f->vals, kb)) || (s = grow(ctx, f->keys_alt, kb)) ||
         (s = grow(ctx, f->vals_alt, kb)) || (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(K_cap))) ||
-        (s = grow(ctx, f->wide, (size_t)W_cap * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) ||
-        (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)) ||
+        (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) || (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)) ||
         (s = grow(ctx, f->cur_stg, (size_t)cur_cap * 8 + 8)) || (s = grow(ctx, f->stg, (size_t)stg_cap * 8 + 8)))
         return s;
     f->stg_cap = stg_cap;
     f->K_cap = K_cap;
-    f->W_cap = W_cap;
     f->cur_cap = cur_cap;
     f->res_R = f->R;
     f->res_P = f->P;
@@ -452,17 +452,14 @@ mgs_status mgs_frame_check(mgs_frame* f, mgs_stream stream_) {
     MGS_HIP(ctx, hipStreamSynchronize(stream));
     const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
     const uint64_t K = f->h_pinned[1], W = f->h_pinned[2], C = f->h_pinned[3];
-    if (f->reserved) {
-        f->K = (int64_t)std::min<uint64_t>(K, (uint64_t)f->K_cap);
-        f->W = (int64_t)std::min<uint64_t>(W, (uint64_t)f->W_cap);
-    }
+    f->W = (int64_t)W;
+    if (f->reserved) f->K = (int64_t)std::min<uint64_t>(K, (uint64_t)f->K_cap);
     if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
     if (flags & FLAG_CAPACITY)
         return fail(ctx, MGS_ERR_CAPACITY,
-                    "the last forward exceeded its workspace: %llu instances (capacity %lld), %llu wide entries "
-                    "(%lld), %llu checkpoints (%lld)",
-                    (unsigned long long)K, (long long)f->K_cap, (unsigned long long)W, (long long)f->W_cap,
-                    (unsigned long long)C, (long long)f->cur_cap);
+                    "the last forward exceeded its workspace: %llu list entries (capacity %lld), %llu checkpoints "
+                    "(%lld)",
+                    (unsigned long long)K, (long long)f->K_cap, (unsigned long long)C, (long long)f->cur_cap);
     return MGS_OK;
 }
 
@@ -488,8 +485,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->cfg_bwd = CompositeConfig{st->tile_w, st->tile_h, st->bwd_ppt};
     f->persistent = st->persistent;
     f->total_tiles = f->views.total_tiles;
-    f->tile_bits = bits_for((uint64_t)f->total_tiles);
-    const int64_t R = f->R, P = f->P, T = f->total_tiles;
+    const int64_t R = f->R, P = f->P, T = f->total_tiles, NR = f->views.total_regions;
+    f->tile_bits = bits_for((uint64_t)(T + NR));
     const int V = n_views;
     if (f->reserved && (R > f->res_R || P > f->res_P || T > f->res_T))
         return fail(ctx, MGS_ERR_CAPACITY,
@@ -502,16 +499,16 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) || (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) ||
-        (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->wide_pos, (size_t)R * 4 + 4)) ||
-        (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
-        (s = grow(ctx, f->ranges, (size_t)T * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
+        (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
+        (s = grow(ctx, f->cls_part, classify_parts_bytes(R))) ||
+        (s = grow(ctx, f->ranges, (size_t)(T + NR) * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow(ctx, f->nbatch, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
         (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
         (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(std::max<int64_t>(R, T)))) ||
         (s = grow(ctx, f->rsort_tmp, sort_scratch_bytes(R))) || (s = grow(ctx, f->queue, 256)))
         return s;
-    launch_fill_u32(stream, f->flags(), 2, 0u);
+    launch_fill_u32(stream, f->flags(), 10, 0u);  // flags and the counters up to byte 40
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT);
         launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
@@ -519,8 +516,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     }
     {
         // records in (view, depth, record) order, those without tiles last in
-        // their view; then the sorted record copy, narrow tile counts and
-        // wide flags in that order
+        // their view; then the sorted record copy, list entry counts and wide
+        // flags in that order
         StageTimer t(ctx, stream, MGS_STAGE_DEPTH_SORT);
         launch_record_keys64(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R, f->n,
                              (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
@@ -530,16 +527,13 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         f->order_in_alt = alt;
         launch_permute_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, (const float*)f->rec.p,
                                 (const float*)f->radius.p, R, f->n, f->views, f->st, (uint32_t*)f->cnt_sorted.p,
-                                (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p);
+                                (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p,
+                                (uint32_t*)f->cls_part.p, f->wide_counts());
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_SCAN);
         launch_scan_u32(stream, (const uint32_t*)f->cnt_sorted.p, R, (uint32_t*)f->offsets.p, f->total(),
                         f->scan_tmp.p);
-        launch_scan_u32(stream, (const uint32_t*)f->wide_flag.p, R, (uint32_t*)f->wide_pos.p, f->wide_total(),
-                        f->scan_tmp.p);
-        launch_wide_ranges(stream, (const uint32_t*)f->wide_pos.p, f->wide_total(), f->n, V,
-                           f->reserved ? f->W_cap : R, f->wide_range());
     }
     MGS_CHECK_LAUNCH(ctx);
     const int64_t B = st->batch_depth;
@@ -549,35 +543,28 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         // counts from the device and the capacities from the reservation;
         // overflows raise device flags, read by mgs_frame_check
         f->K = f->K_cap;
-        f->W = f->W_cap;
         K_dev = f->total();
     } else {
-        // the one synchronisation of the plain path: instance and wide counts
-        // size the instance sort and the batch checkpoints
+        // the one synchronisation of the plain path: the list entry counts
+        // size the sort and the batch checkpoints
         MGS_HIP(ctx, hipMemcpyAsync(f->h_pinned, f->misc.p, 200, hipMemcpyDeviceToHost, stream));
         MGS_HIP(ctx, hipStreamSynchronize(stream));
         const uint32_t flags = (uint32_t)(f->h_pinned[0] & 0xffffffffu);
         const uint64_t K = f->h_pinned[1];
-        const uint64_t W = f->h_pinned[2];
+        const uint64_t W = f->h_pinned[2], KW = f->h_pinned[4];
         if (flags & FLAG_NONFINITE) return fail(ctx, MGS_ERR_NONFINITE, "non-finite projected geometry");
-        if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu instances exceed 2^31 - 1",
+        if (K > (uint64_t)0x7fffffff) return fail(ctx, MGS_ERR_CAPACITY, "%llu list entries exceed 2^31 - 1",
                                                     (unsigned long long)K);
         f->K = (int64_t)K;
         f->W = (int64_t)W;
-        // checkpoints: per tile 2 (ceil(narrow / B) + ceil(wide of its view / B)) + 2
-        int64_t cur_bound = 2 * ((f->K + B - 1) / B + T) + 2 * T;
-        {
-            const uint32_t* wr = reinterpret_cast<const uint32_t*>(f->h_pinned + 4);
-            for (int v = 0; v < V; ++v) {
-                const int64_t wv = (int64_t)wr[2 * v + 1] - (int64_t)wr[2 * v];
-                const int64_t tv = (int64_t)f->views.v[v].grid_w * f->views.v[v].grid_h;
-                cur_bound += 2 * tv * ((wv + B - 1) / B);
-            }
-        }
+        // checkpoints: per tile 2 (ceil(narrow / B) + ceil(region / B)) + 2,
+        // and a region list is read by at most REGION^2 tiles
+        const int64_t cur_bound =
+            2 * ((f->K + B - 1) / B + T) + 2 * (((int64_t)KW * REGION * REGION + B - 1) / B + T) + 2 * T;
         if ((s = grow(ctx, f->keys, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals, (size_t)K * 4 + 16)) ||
             (s = grow(ctx, f->keys_alt, (size_t)K * 4 + 16)) || (s = grow(ctx, f->vals_alt, (size_t)K * 4 + 16)) ||
             (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(f->K))) ||
-            (s = grow(ctx, f->wide, (size_t)W * 16 + 16)) || (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)) ||
+            (s = grow(ctx, f->cur, (size_t)cur_bound * 16 + 16)) ||
             (s = grow(ctx, f->cur_stg, (size_t)cur_bound * 8 + 8)))
             return s;
         // the entries staged for the backward: room for the previous forward's
@@ -590,14 +577,13 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->capacity = (int64_t)std::min<size_t>(f->keys.bytes / 4, f->vals.bytes / 4);
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
-        launch_duplicate_narrow(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
-                                (const uint64_t*)f->tmask.p, (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st,
-                                (uint32_t*)f->keys.p, (uint32_t*)f->vals.p, f->K, f->flags());
-        launch_wide_scatter(stream, (const uint32_t*)f->wide_flag.p, (const uint32_t*)f->wide_pos.p, R, f->n,
-                            (const float*)f->srec.p, f->views, f->st, (uint32_t*)f->wide.p, f->W, f->flags());
+        launch_duplicate_lists(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
+                               (const uint32_t*)f->wide_flag.p, (const uint64_t*)f->tmask.p,
+                               (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
+                               (uint32_t*)f->vals.p, f->K, f->flags());
     }
-    // instances are already in (depth, record) order: a stable sort on the
-    // tile bits alone gives the (tile, depth, record) order
+    // entries are already in (depth, record) order: a stable sort on the cell
+    // bits alone gives the (cell, depth, record) order
     f->sort_passes = f->K > 1 ? (f->tile_bits + 7) / 8 : 0;
     bool in_alt = false;
     {
@@ -608,9 +594,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
     f->sorted_in_alt = in_alt;
     {
         StageTimer t(ctx, stream, MGS_STAGE_RANGES);
-        launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T, (uint32_t*)f->ranges.p);
-        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->wide_range(), f->views, (int)B,
-                          (uint32_t*)f->caps.p);
+        launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T + NR, (uint32_t*)f->ranges.p);
+        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->views, (int)B, (uint32_t*)f->caps.p);
         launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, f->cur_need(),
                         f->scan_tmp.p);
     }
@@ -798,13 +783,11 @@ mgs_status mgs_frame_export(mgs_frame* f, mgs_stream stream, int what, void* dst
         case MGS_EXPORT_RADIUS: src = f->radius.p; n = (size_t)f->R * 4; break;
         case MGS_EXPORT_TILES: src = f->tiles.p; n = (size_t)f->R * 4; break;
         case MGS_EXPORT_VALUES: src = f->vals_sorted(); n = (size_t)f->K * 4; break;
-        case MGS_EXPORT_RANGES: src = f->ranges.p; n = (size_t)f->total_tiles * 8; break;
+        case MGS_EXPORT_RANGES: src = f->ranges.p; n = (size_t)(f->total_tiles + f->views.total_regions) * 8; break;
         case MGS_EXPORT_T_FINAL: src = f->t_final.p; n = (size_t)f->P * 4; break;
         case MGS_EXPORT_LAST: src = f->last.p; n = (size_t)f->P * 4; break;
         case MGS_EXPORT_STATS: src = f->stats.p; n = (size_t)f->P * 16; break;
         case MGS_EXPORT_EVALS: src = f->evals.p; n = (size_t)f->P * 16; break;
-        case MGS_EXPORT_WIDE: src = f->wide.p; n = (size_t)f->W * 16; break;
-        case MGS_EXPORT_WIDE_RANGES: src = f->wide_range(); n = (size_t)f->n_views * 8; break;
         case MGS_EXPORT_ORDER: src = f->record_order(); n = (size_t)f->R * 4; break;
         default: return fail(ctx, MGS_ERR_INVALID_ARG, "unknown export %d", what);
     }

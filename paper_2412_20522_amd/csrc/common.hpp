@@ -19,13 +19,16 @@ struct DevView {
     int32_t grid_w, grid_h;
     uint32_t tile_off;  // first global tile id of this view
     uint32_t px_off;    // first pixel of this view in packed per-pixel arrays
-    uint32_t wide_min;  // records covering more tiles than this are kept in the wide list
+    uint32_t wide_min;  // records covering more tiles than this are listed per region, not per tile
+    int32_t reg_w, reg_h;  // region grid (REGION x REGION tiles per region)
+    uint32_t reg_off;      // first region id of this view (region keys follow all tile keys)
 };
 
 // Passed by value as a kernel argument: no device copy, nothing to capture.
 struct ViewSet {
     int32_t n_views;
     uint32_t total_tiles;
+    uint32_t total_regions;
     DevView v[MGS_MAX_VIEWS];
 };
 
@@ -38,6 +41,10 @@ struct DevSettings {
     int32_t full_rect;  // every valid record covers every tile of its view
     int32_t tile_cull;  // narrow instances only for tiles a record can reach
 };
+
+// Side of a region in tiles.  Wide records are listed once per region they
+// can reach instead of once per tile.
+constexpr int REGION = 4;
 
 // Device flag bits.
 constexpr uint32_t FLAG_CAPACITY = 1u;
@@ -52,9 +59,10 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 // Q = a (dx + beta dy)^2 + gamma dy^2 is a sum of two non-negative terms:
 // FP32 evaluation of the expanded form loses every digit for needle-shaped
 // splats (a c - b^2 tiny against a c), this one keeps full relative
-// precision.  The per-record gradients still refer to (a, b, c).
+// precision.  The per-record conic gradients refer to the stored
+// (a, beta, gamma) as well.
 constexpr int REC_F4 = 3;
-// Per-record 2D gradient layout: du, dv, da, db, dc, dopacity, dr, dg, db.
+// Per-record 2D gradient layout: du, dv, da, dbeta, dgamma, dopacity, dr, dg, db.
 constexpr int DREC = 9;
 
 // Tile rectangle (inclusive) of a record's square footprint; the same

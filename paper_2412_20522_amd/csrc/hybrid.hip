@@ -1,17 +1,24 @@
 // Hybrid binning and compositing for scenes with screen-covering splats.
 //
 // A record whose tile footprint exceeds a per-view threshold ("wide") is not
-// duplicated into every tile it covers.  Wide records are kept once, in a
-// per-view list ordered by (depth, record) together with their tile
-// rectangle; only the remaining ("narrow") records are duplicated and sorted
-// by tile.  A tile's list in the sense of Sec. 3.1 -- every record whose
-// footprint covers the tile, in depth order -- is then the merge of the
-// tile's narrow entries with the wide entries whose rectangle contains the
-// tile.  The compositing kernels form that merged list batch by batch in LDS
-// (merge path over two ordered windows), so the entries, their order and the
-// per-pixel results are exactly those of fully duplicated lists, while the
-// instance sort shrinks from every (tile, wide splat) pair to the narrow
-// pairs only.
+// duplicated into every tile it covers but into every region (REGION x
+// REGION tiles) its footprint overlaps; the remaining ("narrow") records are
+// duplicated per tile.  Both kinds of entry share one key space (tile ids,
+// then region ids) and one stable sort, so each tile and each region holds
+// its entries in (depth, record) order.  A tile's list in the sense of
+// Sec. 3.1 -- every record whose footprint covers the tile, in depth order --
+// is then the merge of the tile's narrow entries with the entries of its
+// region whose rectangle contains the tile.  The compositing kernels form
+// that merged list batch by batch in LDS (merge path over two ordered
+// windows), so the entries, their order and the per-pixel results are
+// exactly those of fully duplicated lists, while the instance sort shrinks
+// from every (tile, wide splat) pair to one entry per region.
+//
+// With culling, an entry is kept only where the splat can pass the per-pixel
+// filters at some pixel centre of the cell (exact test, conservative
+// margin): narrow entries per tile at duplication, wide entries per region
+// at duplication and per tile before the merge.  Dropped entries contribute
+// nothing to any pixel; the merged lists are shorter, the results the same.
 //
 // Records are copied once into (view, depth, record) order ("sorted
 // records"); list entries hold positions in that order, which are unique and
@@ -48,7 +55,7 @@ struct TouchPrep {
     float cut;       // +huge: no cut (always touches); < 0: reaches no pixel
 };
 
-__device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B, const DevSettings& st) {
+__device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B, float q_max, float alpha_min) {
     TouchPrep p;
     p.u = A.x;
     p.v = A.y;
@@ -60,12 +67,16 @@ __device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B
     // a second-order amount far inside the margin below
     const float ab = p.a * p.beta;
     p.nbc = -ab * __builtin_amdgcn_rcpf(fmaf(ab, p.beta, p.gamma));
-    float cut = st.q_max;
-    if (st.alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / st.alpha_min));
+    float cut = q_max;
+    if (alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / alpha_min));
     if (cut >= 3.0e38f) p.cut = 3.4e38f;          // no finite cut
     else if (!(cut > -3.0e38f)) p.cut = -1.f;     // zero opacity
     else p.cut = cut + 1e-3f * (1.f + fabsf(cut));
     return p;
+}
+
+__device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B, const DevSettings& st) {
+    return touch_prep(A, B, st.q_max, st.alpha_min);
 }
 
 __device__ __forceinline__ bool touch_test(const TouchPrep& p, const TileBox& tb) {
@@ -98,15 +109,27 @@ __device__ __forceinline__ bool may_touch(const float4& A, const float4& B, cons
     return touch_test(touch_prep(A, B, st), tb);
 }
 
-__device__ __forceinline__ TileBox tile_box(int tx, int ty, const DevView& cam, const DevSettings& st) {
-    const int x0 = tx * st.tile_w, y0 = ty * st.tile_h;
-    return TileBox{(float)x0 + 0.5f, (float)min(x0 + st.tile_w, cam.width) - 0.5f, (float)y0 + 0.5f,
-                   (float)min(y0 + st.tile_h, cam.height) - 0.5f};
+// Pixel-centre box of cell (cx, cy) of a grid of cw x ch pixel cells.
+__device__ __forceinline__ TileBox cell_box(int cx, int cy, int cw, int ch, const DevView& cam) {
+    const int x0 = cx * cw, y0 = cy * ch;
+    return TileBox{(float)x0 + 0.5f, (float)min(x0 + cw, cam.width) - 0.5f, (float)y0 + 0.5f,
+                   (float)min(y0 + ch, cam.height) - 0.5f};
+}
+
+// The touch test of the binning kernels.  Classification counts the cells a
+// record can reach and duplication emits them, in two kernels; kept out of
+// line so that both run the same instructions and take identical decisions.
+__device__ __noinline__ bool cell_touch_ool(float4 A, float4 B, TileBox box, float q_max, float alpha_min) {
+    return touch_test(touch_prep(A, B, q_max, alpha_min), box);
+}
+
+__device__ __forceinline__ bool cell_touch(const float4& A, const float4& B, const TileBox& box, const DevSettings& st) {
+    return cell_touch_ool(A, B, box, st.q_max, st.alpha_min);
 }
 
 // ---------------------------------------------------------------------------
-// binning: (view, depth) order of records, sorted records, wide list, batch
-// checkpoints
+// binning: (view, depth) order of records, sorted records, per-tile and
+// per-region lists, batch checkpoints
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restrict__ depth,
@@ -120,17 +143,51 @@ __global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restr
     vals[r] = (uint32_t)r;
 }
 
-// Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
-// to view v.  Writes the sorted record copy (radius in B.w, record id bits in
-// C.w), the narrow tile count and the wide flag of every position.
-// Tile culling applies to narrow records of at most CULL_MAX tiles: the
-// classification tests each tile of the rectangle once and keeps the result
-// as a bit mask (bit j: j-th tile of the rectangle, row-major), which the
-// duplication then follows; larger narrow records keep their whole
-// rectangle.  Rectangles of at least COOP_MIN tiles are handled by a whole
-// wave, one tile per lane.
+// The cells a record is listed in: the tiles of its rectangle for a narrow
+// record, the regions (REGION x REGION tiles) its rectangle overlaps for a
+// wide one.  Cell j of the rectangle is (x0 + j % w, y0 + j / w).
+struct Cells {
+    int x0, y0, w;
+    uint32_t area;   // 0: the record is listed nowhere
+    int cw, ch;      // cell size in pixels
+};
+
+__device__ __forceinline__ Cells cells_of(const float4& A, const float4& B, bool wide, const DevView& cam,
+                                          const DevSettings& st) {
+    Cells c{0, 0, 1, 0u, st.tile_w, st.tile_h};
+    const Rect q = rect_of(A.x, A.y, B.w, cam, st);
+    if (q.x1 < q.x0 || q.y1 < q.y0) return c;
+    if (wide) {
+        c.x0 = q.x0 / REGION;
+        c.y0 = q.y0 / REGION;
+        c.w = q.x1 / REGION - c.x0 + 1;
+        c.area = (uint32_t)c.w * (uint32_t)(q.y1 / REGION - c.y0 + 1);
+        c.cw = REGION * st.tile_w;
+        c.ch = REGION * st.tile_h;
+    } else {
+        c.x0 = q.x0;
+        c.y0 = q.y0;
+        c.w = q.x1 - q.x0 + 1;
+        c.area = (uint32_t)c.w * (uint32_t)(q.y1 - q.y0 + 1);
+    }
+    return c;
+}
+
+// Sort key of cell (cx, cy): tile ids first, then region ids.
+__device__ __forceinline__ uint32_t cell_key(bool wide, int cx, int cy, const DevView& cam, const ViewSet& views) {
+    return wide ? views.total_tiles + cam.reg_off + (uint32_t)cy * (uint32_t)cam.reg_w + (uint32_t)cx
+                : cam.tile_off + (uint32_t)cy * (uint32_t)cam.grid_w + (uint32_t)cx;
+}
+
+// With culling, the tested cells of a rectangle of at most CULL_MAX cells are
+// kept as a bit mask (bit j: cell j) for the duplication to follow; larger
+// rectangles are tested again there.  Rectangles of at least COOP_MIN cells
+// are handled by a whole wave, one cell per lane.
 constexpr uint32_t CULL_MAX = 64;
 constexpr uint32_t COOP_MIN = 16;
+// Key of an emitted slot the duplication could not fill: past every cell,
+// so it sorts last and no range includes it.
+constexpr uint32_t KEY_NONE = 0xffffffffu;
 
 __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
     return make_float4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
@@ -138,13 +195,15 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 
 // Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
 // to view v.  Writes the sorted record copy (radius in B.w, record id bits in
-// C.w), the narrow tile count (after culling), the cull mask and the wide
-// flag of every position.
+// C.w), the wide flag, the number of list entries (tiles or regions, after
+// culling) and the cull mask of every position, and per workgroup the number
+// of wide records and of their region entries (part[b], part[nb + b]).
 __global__ void __launch_bounds__(256) permute_classify_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles, const float4* __restrict__ rec,
     const float* __restrict__ radius, int64_t R, int64_t n, ViewSet views, DevSettings st,
-    uint32_t* __restrict__ narrow_cnt, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
-    float4* __restrict__ srec) {
+    uint32_t* __restrict__ cnt_out, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
+    float4* __restrict__ srec, uint32_t* __restrict__ part) {
+    __shared__ uint32_t s_part[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     const bool live = i < R;
@@ -167,171 +226,223 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
         reinterpret_cast<uint4*>(srec)[3 * i + 2] = C;
         wide_flag[i] = wide ? 1u : 0u;
     }
-    uint32_t area = 0;
-    int x0 = 0, y0 = 0, w = 1;
-    if (live && !wide && c > 0) {
-        const Rect q = rect_of(A.x, A.y, B.w, views.v[vi], st);
-        x0 = q.x0;
-        y0 = q.y0;
-        w = q.x1 - q.x0 + 1;
-        area = (uint32_t)w * (uint32_t)(q.y1 - q.y0 + 1);
-    }
-    const bool cull = st.tile_cull && area > 0 && area <= CULL_MAX;
+    Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
+    if (live && c > 0) cl = cells_of(A, B, wide, views.v[vi], st);
+    const bool cull = st.tile_cull && cl.area > 0;
     uint64_t mask = 0;
-    if (cull && area < COOP_MIN) {
+    uint32_t cnt = cull ? 0u : cl.area;
+    if (cull && cl.area < COOP_MIN) {
         const DevView& cam = views.v[vi];
-        const TouchPrep tp = touch_prep(A, B, st);
-        for (uint32_t j = 0; j < area; ++j) {
-            const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
-            if (touch_test(tp, tile_box(x0 + (int)tx, y0 + (int)ty, cam, st))) mask |= 1ull << j;
+        for (uint32_t j = 0; j < cl.area; ++j) {
+            const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
+            if (cell_touch(A, B, cell_box(cl.x0 + (int)rx, cl.y0 + (int)ry, cl.cw, cl.ch, cam), st))
+                mask |= 1ull << j;
         }
+        cnt = (uint32_t)__popcll(mask);
     }
-    uint64_t pending = __ballot(cull && area >= COOP_MIN);
+    uint64_t pending = __ballot(cull && cl.area >= COOP_MIN);
     while (pending) {
         const int src = __ffsll((long long)pending) - 1;
         pending &= pending - 1;
         const float4 bA = shfl4(A, src), bB = shfl4(B, src);
-        const uint32_t barea = __shfl(area, src);
-        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bvi = __shfl(vi, src);
-        bool pass = false;
-        const uint32_t j = (uint32_t)lane;
-        if (j < barea) {
-            const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
-            pass = may_touch(bA, bB, tile_box(bx0 + (int)tx, by0 + (int)ty, views.v[bvi], st), st);
+        const uint32_t barea = __shfl(cl.area, src);
+        const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
+        const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
+        const DevView& cam = views.v[bvi];
+        uint32_t total = 0;
+        for (uint32_t j0 = 0; j0 < barea; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            bool pass = false;
+            if (j < barea) {
+                const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
+                pass = cell_touch(bA, bB, cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam), st);
+            }
+            const uint64_t bal = __ballot(pass);
+            total += (uint32_t)__popcll(bal);
+            if (lane == src && barea <= CULL_MAX) mask = bal;
         }
-        const uint64_t bal = __ballot(pass);
-        if (lane == src) mask = bal;
+        if (lane == src) cnt = total;
     }
     if (live) {
-        narrow_cnt[i] = cull ? (uint32_t)__popcll(mask) : area;
+        cnt_out[i] = cnt;
         tmask[i] = mask;
+    }
+    // wide records and their list entries of the workgroup (no atomics: one
+    // address updated by every wave serialises)
+    const uint64_t wb = __ballot(live && wide);
+    uint32_t e = live && wide ? cnt : 0u;
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    const int wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_part[0][wid] = (uint32_t)__popcll(wb);
+        s_part[1][wid] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            a += s_part[0][w];
+            b += s_part[1][w];
+        }
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
     }
 }
 
-// Narrow instances in sorted-position order: tile ids as keys, positions as
-// values, for the tiles the classification kept.
-__global__ void __launch_bounds__(256) duplicate_narrow_kernel(
-    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint64_t* __restrict__ tmask,
-    const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views, DevSettings st,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
+// Totals of the two per-workgroup counts of the classification (fixed
+// order, one workgroup): out[0] = wide records, out[2] = region entries.
+__global__ void __launch_bounds__(1024) sum_parts_kernel(const uint32_t* __restrict__ part, int nb,
+                                                          uint64_t* __restrict__ out) {
+    __shared__ uint64_t s[2][16];
+    uint64_t a = 0, b = 0;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        a += part[k];
+        b += part[nb + k];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s[0][wid] = a;
+        s[1][wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t ta = 0, tb = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            ta += s[0][w];
+            tb += s[1][w];
+        }
+        out[0] = ta;
+        out[2] = tb;
+    }
+}
+
+// List entries in sorted-position order: cell keys (tile or region ids) as
+// keys, positions as values, for the cells the classification counted.
+// Writes never leave the record's counted slots; a slot the emission does
+// not fill gets KEY_NONE.
+__global__ void __launch_bounds__(256) duplicate_kernel(
+    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
+    const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views,
+    DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
+    uint32_t* __restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
-    uint32_t area = 0;
+    Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
     uint64_t mask = ~0ull;
     int64_t off = 0;
-    int x0 = 0, y0 = 0, w = 1, vi = 0;
-    bool cull = false;
-    if (i < R && cnt_sorted[i]) {
+    uint32_t cnt = 0;
+    int vi = 0;
+    bool cull = false, wide = false;
+    float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
+    if (i < R && (cnt = cnt_sorted[i]) != 0) {
         off = offsets[i];
         vi = (int)(i / n);
-        const float4 A = srec[3 * i], B = srec[3 * i + 1];
-        const Rect q = rect_of(A.x, A.y, B.w, views.v[vi], st);
-        x0 = q.x0;
-        y0 = q.y0;
-        w = q.x1 - q.x0 + 1;
-        area = (uint32_t)w * (uint32_t)(q.y1 - q.y0 + 1);
-        cull = st.tile_cull && area <= CULL_MAX;
-        if (cull) mask = tmask[i];
+        wide = wide_flag[i] != 0;
+        A = srec[3 * i];
+        B = srec[3 * i + 1];
+        cl = cells_of(A, B, wide, views.v[vi], st);
+        cull = st.tile_cull && cl.area > 0;
+        if (cull && cl.area <= CULL_MAX) mask = tmask[i];
     }
     bool overflow = false;
-    const bool coop = area >= COOP_MIN;
-    if (!coop && area) {
+    const bool coop = cl.area >= COOP_MIN;
+    if (!coop && cl.area) {
         const DevView& cam = views.v[vi];
         int64_t o = off;
-        for (uint32_t j = 0; j < area; ++j) {
+        const int64_t end = off + cnt;
+        for (uint32_t j = 0; j < cl.area && o < end; ++j) {
             if (cull && !((mask >> j) & 1ull)) continue;
-            const uint32_t ty = j / (uint32_t)w, tx = j - ty * (uint32_t)w;
+            const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
             if (o < capacity) {
-                keys[o] = cam.tile_off + (uint32_t)(y0 + (int)ty) * (uint32_t)cam.grid_w + (uint32_t)(x0 + (int)tx);
+                keys[o] = cell_key(wide, cl.x0 + (int)rx, cl.y0 + (int)ry, cam, views);
                 vals[o] = (uint32_t)i;
             } else {
                 overflow = true;
             }
             ++o;
         }
+        for (; o < end; ++o) {
+            if (o < capacity) {
+                keys[o] = KEY_NONE;
+                vals[o] = 0u;
+            } else {
+                overflow = true;
+            }
+        }
     }
     uint64_t pending = __ballot(coop);
     while (pending) {
         const int src = __ffsll((long long)pending) - 1;
         pending &= pending - 1;
-        const uint32_t barea = __shfl(area, src);
+        const uint32_t barea = __shfl(cl.area, src), bcnt = __shfl(cnt, src);
         const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)i, src);
-        const int bx0 = __shfl(x0, src), by0 = __shfl(y0, src), bw = __shfl(w, src), bvi = __shfl(vi, src);
-        const bool bcull = __shfl((int)cull, src) != 0;
+        const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
+        const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
+        const bool bcull = __shfl((int)cull, src) != 0, bwide = __shfl((int)wide, src) != 0;
         const uint64_t bmask = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mask >> 32), src) << 32) |
                                (uint64_t)(uint32_t)__shfl((int)(uint32_t)mask, src);
+        const bool retest = bcull && barea > CULL_MAX;
+        const float4 bA = shfl4(A, src), bB = shfl4(B, src);
         const int64_t bo = __shfl(off, src);
+        const int64_t end = bo + bcnt;
         const DevView& cam = views.v[bvi];
         int64_t base = bo;
-        for (uint32_t j0 = 0; j0 < barea; j0 += 64) {
-            const uint32_t j = j0 + lane;
-            const bool take = j < barea && (!bcull || ((bmask >> (j & 63u)) & 1ull));
+        for (uint32_t j0 = 0; j0 < barea && base < end; j0 += 64) {
+            const uint32_t j = j0 + (uint32_t)lane;
+            const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
+            bool take = j < barea;
+            if (take && bcull) {
+                take = retest ? cell_touch(bA, bB, cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam), st)
+                              : ((bmask >> (j & 63u)) & 1ull) != 0;
+            }
             const uint64_t bal = __ballot(take);
             if (take) {
                 const int64_t o = base + __popcll(bal & lanemask_lt());
-                const uint32_t ty = j / (uint32_t)bw, tx = j - ty * (uint32_t)bw;
-                if (o < capacity) {
-                    keys[o] = cam.tile_off + (uint32_t)(by0 + (int)ty) * (uint32_t)cam.grid_w +
-                              (uint32_t)(bx0 + (int)tx);
-                    vals[o] = bi;
-                } else {
-                    overflow = true;
+                if (o < end) {
+                    if (o < capacity) {
+                        keys[o] = cell_key(bwide, bx0 + (int)rx, by0 + (int)ry, cam, views);
+                        vals[o] = bi;
+                    } else {
+                        overflow = true;
+                    }
                 }
             }
             base += __popcll(bal);
+        }
+        for (int64_t o = base + lane; o < end; o += 64) {
+            if (o < capacity) {
+                keys[o] = KEY_NONE;
+                vals[o] = 0u;
+            } else {
+                overflow = true;
+            }
         }
     }
     if (overflow) atomicOr(flags, FLAG_CAPACITY);
 }
 
-// Wide entry: x = sorted position, y = record, z = x0 | y0 << 16,
-// w = x1 | y1 << 16 (inclusive tile rectangle).
-__global__ void __launch_bounds__(256) wide_scatter_kernel(const uint32_t* __restrict__ wide_flag,
-                                                            const uint32_t* __restrict__ wide_pos, int64_t R,
-                                                            int64_t n, const float4* __restrict__ srec,
-                                                            ViewSet views, DevSettings st, uint4* __restrict__ wide,
-                                                            int64_t wcap, uint32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= R || !wide_flag[i]) return;
-    const float4 A = srec[3 * i], B = srec[3 * i + 1];
-    const uint32_t r = reinterpret_cast<const uint4*>(srec)[3 * i + 2].w;
-    const Rect q = rect_of(A.x, A.y, B.w, views.v[i / n], st);
-    const uint32_t p = wide_pos[i];
-    if (p < wcap) {
-        wide[p] = make_uint4((uint32_t)i, r, (uint32_t)q.x0 | ((uint32_t)q.y0 << 16),
-                             (uint32_t)q.x1 | ((uint32_t)q.y1 << 16));
-    } else {
-        atomicOr(flags, FLAG_CAPACITY);
-    }
-}
-
-// [start, end) of every view's wide entries, clamped to the entries the
-// wide buffer holds (a count beyond it is reported by the scatter).
-__global__ void wide_ranges_kernel(const uint32_t* __restrict__ wide_pos, const uint64_t* __restrict__ wide_total,
-                                   int64_t n, int nv, int64_t wcap, uint2* __restrict__ wide_range) {
-    const int v = threadIdx.x;
-    if (v >= nv) return;
-    if (n == 0) {
-        wide_range[v] = make_uint2(0u, 0u);
-        return;
-    }
-    const uint64_t cap = (uint64_t)wcap;
-    const uint64_t s = wide_pos[(int64_t)v * n];
-    const uint64_t e = v + 1 < nv ? (uint64_t)wide_pos[(int64_t)(v + 1) * n] : *wide_total;
-    wide_range[v] = make_uint2((uint32_t)min(s, cap), (uint32_t)min(e, cap));
-}
-
 // Upper bound on the batches a tile can take: a batch either emits `batch`
 // merged entries or exhausts a whole window of one of the two streams.
-__global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict__ ranges,
-                                                          const uint2* __restrict__ wide_range, ViewSet views,
-                                                          int batch, uint32_t* __restrict__ caps) {
+__device__ __forceinline__ uint32_t region_of_tile(int tx, int ty, const DevView& cam, const ViewSet& views) {
+    return views.total_tiles + cam.reg_off + (uint32_t)(ty / REGION) * (uint32_t)cam.reg_w + (uint32_t)(tx / REGION);
+}
+
+__global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict__ ranges, ViewSet views, int batch,
+                                                          uint32_t* __restrict__ caps) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= views.total_tiles) return;
     int vi = 0;
     while (vi + 1 < views.n_views && t >= views.v[vi + 1].tile_off) ++vi;
+    const DevView& cam = views.v[vi];
+    const uint32_t lt = t - cam.tile_off;
+    const int tx = (int)(lt % (uint32_t)cam.grid_w), ty = (int)(lt / (uint32_t)cam.grid_w);
+    const uint2 r2 = ranges[region_of_tile(tx, ty, cam, views)];
     const uint32_t len1 = ranges[t].y - ranges[t].x;
-    const uint32_t len2 = wide_range[vi].y - wide_range[vi].x;
+    const uint32_t len2 = r2.y - r2.x;
     caps[t] = 2u * ((len1 + batch - 1) / batch + (len2 + batch - 1) / batch) + 2u;
 }
 
@@ -344,9 +455,9 @@ __global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict
 // are dead once the merged positions are known.
 struct Lds {
     uint32_t* xk;     // narrow window (sorted positions)
-    uint32_t* yraw;   // wide window (sorted positions), before the rectangle test
-    uint32_t* yk;     // wide entries of the window that cover this tile
-    uint8_t* ypass;   // rectangle test of the wide window
+    uint32_t* yraw;   // region window (sorted positions), before the tile test
+    uint32_t* yk;     // entries of the region window that belong to this tile
+    uint8_t* ypass;   // tile test of the region window
     float4* A;        // staged records of the batch
     float4* Bv;
     float4* C;
@@ -414,22 +525,35 @@ struct Batch {
     int M;      // staged entries (those that can reach a pixel of the tile)
     int Mfull;  // merged entries of the batch, staged or not
     int nX;     // narrow entries consumed
-    int nYraw;  // wide entries consumed (including those not covering the tile)
+    int nYraw;  // region entries consumed (including those not belonging to the tile)
 };
 
 // Stages the next (at most `batch`) entries of the tile's merged list in LDS.
-// Every thread of the block calls it; the result is uniform.
-__device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, const uint4* __restrict__ wide,
-                             const float4* __restrict__ srec, int i1, int e1, int i2, int e2, int batch, int tcx,
-                             int tcy, const TileBox& tb, const DevSettings& st) {
+// Every thread of the block calls it; the result is uniform.  The first
+// stream is the tile's narrow list, the second its region list, of which
+// only the entries that reach the tile belong to the tile's list: with
+// culling, those that pass the exact touch test (narrow lists are already
+// culled the same way, so every merged entry is staged); without, those
+// whose tile rectangle contains the tile (the list of Sec. 3.1), and the
+// touch test then only decides which merged entries are staged.
+__device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, const float4* __restrict__ srec,
+                             int i1, int e1, int i2, int e2, int batch, int tcx, int tcy, const TileBox& tb,
+                             const DevView& cam, const DevSettings& st) {
     const int t = threadIdx.x, NT = blockDim.x;
     const int cX = min(batch, e1 - i1), cY = min(batch, e2 - i2);
     for (int l = t; l < cX; l += NT) L.xk[l] = vals[i1 + l];
     for (int l = t; l < cY; l += NT) {
-        const uint4 w = wide[i2 + l];
-        L.yraw[l] = w.x;
-        const int x0 = (int)(w.z & 0xffffu), y0 = (int)(w.z >> 16), x1 = (int)(w.w & 0xffffu), y1 = (int)(w.w >> 16);
-        L.ypass[l] = (tcx >= x0 && tcx <= x1 && tcy >= y0 && tcy <= y1) ? 1 : 0;
+        const uint32_t p = vals[i2 + l];
+        L.yraw[l] = p;
+        const float4 A = srec[3 * (size_t)p], B = srec[3 * (size_t)p + 1];
+        bool pass;
+        if (st.tile_cull) {
+            pass = may_touch(A, B, tb, st);
+        } else {
+            const Rect q = rect_of(A.x, A.y, B.w, cam, st);
+            pass = tcx >= q.x0 && tcx <= q.x1 && tcy >= q.y0 && tcy <= q.y1;
+        }
+        L.ypass[l] = pass ? 1 : 0;
     }
     __syncthreads();
     // entries up to the smaller of the two window ends are final (positions
@@ -439,7 +563,7 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     if (i2 + cY < e2) F = min(F, L.yraw[cY - 1]);
     int nX = count_le(L.xk, cX, F);
     int nYr = count_le(L.yraw, cY, F);
-    // compact the covering wide entries among the consumed raw ones
+    // compact the passing entries among the consumed raw ones
     const int per = (cY + NT - 1) / NT;
     uint32_t cnt = 0;
     for (int q = 0; q < per; ++q) {
@@ -478,6 +602,18 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     // that can reach a pixel of the tile; B.w (the radius, unused here)
     // carries the entry's index within the merged batch
     const int M = nX + nY;
+    if (st.tile_cull) {
+        for (int j = t; j < M; j += NT) {
+            const size_t i = L.m[j];
+            float4 B = srec[3 * i + 1];
+            B.w = __int_as_float(j);
+            L.A[j] = srec[3 * i];
+            L.Bv[j] = B;
+            L.C[j] = srec[3 * i + 2];
+        }
+        __syncthreads();
+        return Batch{M, M, nX, nYr};
+    }
     const int run = (M + NT - 1) / NT;  // contiguous entries per thread (<= MAXB / 64)
     uint32_t keep = 0, nkeep = 0;
     for (int q = 0; q < run; ++q) {
@@ -543,11 +679,9 @@ constexpr uint32_t STG_CHUNK_PERSISTENT = 4096;
 constexpr uint32_t STG_CHUNK = 256;
 
 struct HybridLists {
-    const uint32_t* vals;      // narrow instances (sorted positions) in (tile, position) order
-    const uint2* ranges;       // narrow [start, end) per tile
-    const uint4* wide;         // wide entries, per view in position order
-    const uint2* wide_range;   // per view
-    uint4* cur;                // batch checkpoints (narrow cursor, wide cursor, merged index)
+    const uint32_t* vals;      // list entries (sorted positions) in (cell, position) order
+    const uint2* ranges;       // [start, end) per tile, then per region
+    uint4* cur;                // batch checkpoints (narrow cursor, region cursor, merged index)
     const uint32_t* cur_off;   // first checkpoint of each tile
     uint32_t* nbatch;          // batches the forward took per tile
     const uint64_t* cur_need;  // checkpoints the tiles may take (device)
@@ -603,11 +737,11 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             nblend[i] = nmasked[i] = nev[i] = nev_last[i] = 0;
             done[i] = !inside[i];
         }
+        const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
         const uint2 r1 = hl.ranges[tile];
-        const uint2 r2 = hl.wide_range[tg.vi];
+        const uint2 r2 = hl.ranges[region_of_tile(tcx, tcy, cam, views)];
         const int e1 = (int)r1.y, e2 = (int)r2.y;
         int i1 = (int)r1.x, i2 = (int)r2.x, m = 0, b = 0;
-        const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
         const TileBox tb{(float)tg.tx0 + 0.5f, (float)min(tg.tx0 + TW, cam.width) - 0.5f, (float)tg.ty0 + 0.5f,
                          (float)min(tg.ty0 + TH, cam.height) - 0.5f};
         uint4* cur = hl.cur + hl.cur_off[tile];
@@ -617,7 +751,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
             for (int i = 0; i < PPT; ++i) active |= !done[i];
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
-            const Batch bt = merge_batch(L, hl.vals, hl.wide, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, st);
+            const Batch bt = merge_batch(L, hl.vals, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, cam, st);
             // room for the staged entries in the list kept for the backward:
             // thread 0 sub-allocates from a chunk the workgroup took from the
             // global counter (one atomic per chunk, not per batch)
@@ -767,9 +901,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
         __syncthreads();
         const int top = s_top;
         const uint4* cur = hl.cur + hl.cur_off[tile];
-        const uint2 r1 = hl.ranges[tile];
-        const uint2 r2 = hl.wide_range[tg.vi];
         const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
+        const uint2 r1 = hl.ranges[tile];
+        const uint2 r2 = hl.ranges[region_of_tile(tcx, tcy, cam, views)];
         const TileBox tb{(float)tg.tx0 + 0.5f, (float)min(tg.tx0 + TW, cam.width) - 0.5f, (float)tg.ty0 + 0.5f,
                          (float)min(tg.ty0 + TH, cam.height) - 0.5f};
         // the batch holding the largest last-blended entry, then backwards
@@ -799,8 +933,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                 }
                 __syncthreads();
             } else {
-                Mb = merge_batch(L, hl.vals, hl.wide, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y, batch, tcx,
-                                 tcy, tb, st).M;
+                Mb = merge_batch(L, hl.vals, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y, batch, tcx, tcy, tb,
+                                 cam, st).M;
             }
             for (int j = Mb - 1; j >= 0; --j) {
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
@@ -930,8 +1064,6 @@ HybridLists make_lists(const HybridBuffers& b) {
     HybridLists hl;
     hl.vals = b.vals;
     hl.ranges = reinterpret_cast<const uint2*>(b.ranges);
-    hl.wide = reinterpret_cast<const uint4*>(b.wide);
-    hl.wide_range = reinterpret_cast<const uint2*>(b.wide_range);
     hl.cur = reinterpret_cast<uint4*>(b.cur);
     hl.cur_off = b.cur_off;
     hl.nbatch = b.nbatch;
@@ -958,44 +1090,32 @@ void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t
 
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
                              const float* radius, int64_t R, int64_t n, const ViewSet& views, const DevSettings& st,
-                             uint32_t* narrow_cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec) {
+                             uint32_t* cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
+                             uint64_t* wide_counts) {
     if (R == 0) return;
-    hipLaunchKernelGGL(permute_classify_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, order, tiles,
-                       reinterpret_cast<const float4*>(rec), radius, R, n, views, st, narrow_cnt, wide_flag, tmask,
-                       reinterpret_cast<float4*>(srec));
+    const unsigned nb = blocks_of(R);
+    hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, tiles,
+                       reinterpret_cast<const float4*>(rec), radius, R, n, views, st, cnt, wide_flag, tmask,
+                       reinterpret_cast<float4*>(srec), part);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(1024), 0, stream, part, (int)nb, wide_counts);
 }
 
-void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
-                             const uint64_t* tmask, const uint32_t* offsets, int64_t R, int64_t n,
-                             const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
-                             int64_t capacity, uint32_t* flags) {
+size_t classify_parts_bytes(int64_t R) { return (size_t)blocks_of(R) * 8 + 8; }
+
+void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
+                            const uint32_t* wide_flag, const uint64_t* tmask, const uint32_t* offsets, int64_t R,
+                            int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
+                            int64_t capacity, uint32_t* flags) {
     if (R == 0) return;
-    hipLaunchKernelGGL(duplicate_narrow_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
-                       reinterpret_cast<const float4*>(srec), cnt_sorted, tmask, offsets, R, n, views, st, keys,
-                       vals, capacity, flags);
+    hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
+                       reinterpret_cast<const float4*>(srec), cnt_sorted, wide_flag, tmask, offsets, R, n, views, st,
+                       keys, vals, capacity, flags);
 }
 
-void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const uint32_t* wide_pos, int64_t R,
-                         int64_t n, const float* srec, const ViewSet& views, const DevSettings& st, uint32_t* wide,
-                         int64_t wcap, uint32_t* flags) {
-    if (R == 0) return;
-    hipLaunchKernelGGL(wide_scatter_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, wide_flag, wide_pos, R, n,
-                       reinterpret_cast<const float4*>(srec), views, st, reinterpret_cast<uint4*>(wide), wcap,
-                       flags);
-}
-
-void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
-                        int n_views, int64_t wcap, uint32_t* wide_range) {
-    hipLaunchKernelGGL(wide_ranges_kernel, dim3(1), dim3(64), 0, stream, wide_pos, wide_total, n, n_views, wcap,
-                       reinterpret_cast<uint2*>(wide_range));
-}
-
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
-                       int batch, uint32_t* caps) {
+void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps) {
     if (views.total_tiles == 0) return;
     hipLaunchKernelGGL(batch_caps_kernel, dim3(blocks_of(views.total_tiles)), dim3(256), 0, stream,
-                       reinterpret_cast<const uint2*>(ranges), reinterpret_cast<const uint2*>(wide_range), views,
-                       batch, caps);
+                       reinterpret_cast<const uint2*>(ranges), views, batch, caps);
 }
 
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,

@@ -71,29 +71,26 @@ void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const 
 
 // hybrid binning: records in (view, depth, record) order are copied once
 // ("sorted records": radius in B.w, record id bits in C.w); narrow records
-// are duplicated with sorted positions as values, wide records are kept once
-// per view and merged per tile while compositing
+// are listed per tile, wide records per region (one key space: tile ids, then
+// region ids), with sorted positions as values, and merged per tile while
+// compositing
 void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
                           uint64_t* keys, uint32_t* vals);
+// wide_counts (device u64): [0] = wide records, [2] = their region entries;
+// part: classify_parts_bytes(R) bytes of per-workgroup partial counts
+size_t classify_parts_bytes(int64_t R);
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
                              const float* radius, int64_t R, int64_t n, const ViewSet& views, const DevSettings& st,
-                             uint32_t* narrow_cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec);
-void launch_duplicate_narrow(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted, const uint64_t* tmask,
-                             const uint32_t* offsets, int64_t R, int64_t n, const ViewSet& views,
-                             const DevSettings& st, uint32_t* keys, uint32_t* vals, int64_t capacity,
-                             uint32_t* flags);
-void launch_wide_scatter(hipStream_t stream, const uint32_t* wide_flag, const uint32_t* wide_pos, int64_t R,
-                         int64_t n, const float* srec, const ViewSet& views, const DevSettings& st, uint32_t* wide,
-                         int64_t wcap, uint32_t* flags);
-void launch_wide_ranges(hipStream_t stream, const uint32_t* wide_pos, const uint64_t* wide_total, int64_t n,
-                        int n_views, int64_t wcap, uint32_t* wide_range);
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const uint32_t* wide_range, const ViewSet& views,
-                       int batch, uint32_t* caps);
+                             uint32_t* cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
+                             uint64_t* wide_counts);
+void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
+                            const uint32_t* wide_flag, const uint64_t* tmask, const uint32_t* offsets, int64_t R,
+                            int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
+                            int64_t capacity, uint32_t* flags);
+void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps);
 struct HybridBuffers {
-    const uint32_t* vals;        // narrow instances (sorted positions), (tile, position) order
-    const uint32_t* ranges;      // [tiles, 2] narrow ranges
-    const uint32_t* wide;        // [W, 4] wide entries
-    const uint32_t* wide_range;  // [views, 2]
+    const uint32_t* vals;        // list entries (sorted positions), (cell, position) order
+    const uint32_t* ranges;      // [tiles + regions, 2]
     uint32_t* cur;               // [checkpoints, 4]
     const uint32_t* cur_off;     // [tiles]
     uint32_t* nbatch;            // [tiles]

@@ -352,24 +352,27 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
 // tile ranges, fills, sums
 // ---------------------------------------------------------------------------
 
+// [start, end) of every bin of sorted keys; keys at or past nbins (entries
+// that belong nowhere, sorted last) are left out of every range.
 template <typename KeyT>
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const KeyT* __restrict__ keys, int64_t Kcap,
                                                            const uint64_t* __restrict__ K_dev, int shift,
-                                                           uint2* __restrict__ ranges) {
+                                                           uint64_t nbins, uint2* __restrict__ ranges) {
     const int64_t K = live_count(Kcap, K_dev);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    const uint32_t t = (uint32_t)(keys[k] >> shift);
+    const uint64_t t = (uint64_t)(keys[k] >> shift);
+    const bool tv = t < nbins;
     if (k == 0) {
-        ranges[t].x = 0;
+        if (tv) ranges[t].x = 0;
     } else {
-        const uint32_t p = (uint32_t)(keys[k - 1] >> shift);
+        const uint64_t p = (uint64_t)(keys[k - 1] >> shift);
         if (p != t) {
-            ranges[p].y = (uint32_t)k;
-            ranges[t].x = (uint32_t)k;
+            if (p < nbins) ranges[p].y = (uint32_t)k;
+            if (tv) ranges[t].x = (uint32_t)k;
         }
     }
-    if (k == K - 1) ranges[t].y = (uint32_t)K;
+    if (k == K - 1 && tv) ranges[t].y = (uint32_t)K;
 }
 
 __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -512,7 +515,7 @@ void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, con
     launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
     if (K == 0) return;
     hipLaunchKernelGGL(tile_ranges_kernel<uint64_t>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K,
-                       K_dev, 32, reinterpret_cast<uint2*>(ranges));
+                       K_dev, 32, (uint64_t)total_tiles, reinterpret_cast<uint2*>(ranges));
 }
 
 void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, const uint64_t* K_dev,
@@ -520,7 +523,7 @@ void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, c
     launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
     if (K == 0) return;
     hipLaunchKernelGGL(tile_ranges_kernel<uint32_t>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K,
-                       K_dev, 0, reinterpret_cast<uint2*>(ranges));
+                       K_dev, 0, (uint64_t)total_tiles, reinterpret_cast<uint2*>(ranges));
 }
 
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {

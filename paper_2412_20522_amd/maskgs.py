@@ -62,7 +62,8 @@ class mgs_eval_counts(C.Structure):
 STAGES = ("project", "depth_sort", "scan", "duplicate", "sort", "ranges", "composite_fwd", "composite_bwd",
           "project_bwd", "sample_masks", "mask_grad", "loss", "adam")
 EXPORTS = {"records": 0, "depth": 1, "radius": 2, "tiles": 3, "values": 4, "ranges": 5, "t_final": 6, "last": 7,
-           "stats": 8, "wide": 9, "wide_ranges": 10, "order": 11, "evals": 12}
+           "stats": 8, "order": 9, "evals": 10}
+REGION_TILES = 4  # side of the regions that list wide records, in tiles
 MGS_NUM_STAGES = len(STAGES)
 
 
@@ -303,7 +304,7 @@ def mgs_frame_count_evals(ctx, frame, stream=None) -> dict:
 
 _EXPORT_DTYPES = {"records": torch.float32, "depth": torch.float32, "radius": torch.float32, "tiles": torch.int32,
                   "values": torch.int32, "ranges": torch.int32, "t_final": torch.float32, "last": torch.int32,
-                  "stats": torch.int32, "wide": torch.int32, "wide_ranges": torch.int32, "order": torch.int32,
+                  "stats": torch.int32, "order": torch.int32,
                   "evals": torch.int32}
 
 

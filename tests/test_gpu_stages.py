@@ -110,26 +110,58 @@ def test_tiles_and_lists_match_oracle_bitwise(ctx):
             assert np.all(gr[~nonempty, 0] == gr[~nonempty, 1])
 
 
-def merged_tile_lists(cams, tw, th, vals, ranges, wide, wide_ranges, order, depth_bits):
-    """Per-tile lists of the hybrid binning as record ids: the tile's narrow
-    entries (positions into `order`) merged with its view's wide entries whose
-    tile rectangle contains the tile, in (depth bits, record) order."""
-    out = []
+def tile_rects(u, v, r, gw, gh, tw, th):
+    """Inclusive tile rectangle of each record's square footprint
+    [u - r, u + r] x [v - r, v + r], clamped to the grid (empty when
+    x0 > x1 or y0 > y1), in FP64 like the tile assignment of Sec. 3.1."""
+    x0 = np.maximum(np.floor((u - r) / tw), 0)
+    x1 = np.minimum(np.floor((u + r) / tw), gw - 1)
+    y0 = np.maximum(np.floor((v - r) / th), 0)
+    y1 = np.minimum(np.floor((v + r) / th), gh - 1)
+    return x0, y0, x1, y1
+
+
+def merged_tile_lists(cams, tw, th, vals, ranges, order, depth_bits, mean2d, radius, wide_mask):
+    """Per-tile lists of the hybrid binning as record ids: the tile's own
+    entries (positions into `order`) merged with the entries of its region
+    (MGS_REGION_TILES^2 tiles) whose tile rectangle contains the tile, in
+    (depth bits, record) order.  Also returns the records listed per region."""
+    RG = U.M().REGION_TILES
+    T = sum(((c["width"] + tw - 1) // tw) * ((c["height"] + th - 1) // th) for c in cams)
+    out, region_recs = [], []
+    roff = 0
+    n = wide_mask.size // len(cams)
     for v, c in enumerate(cams):
         gw, gh = (c["width"] + tw - 1) // tw, (c["height"] + th - 1) // th
-        ws, we = wide_ranges[v]
-        wv = wide[ws:we]
-        x0, y0 = wv[:, 2] & 0xFFFF, wv[:, 2] >> 16
-        x1, y1 = wv[:, 3] & 0xFFFF, wv[:, 3] >> 16
+        rw, rh = (gw + RG - 1) // RG, (gh + RG - 1) // RG
+        # every wide record of the view once in each region its rectangle overlaps
+        wr = v * n + np.nonzero(wide_mask[v * n:(v + 1) * n])[0]
+        x0, y0, x1, y1 = tile_rects(mean2d[wr, 0], mean2d[wr, 1], radius[wr], gw, gh, tw, th)
+        want = int(((x1 // RG - x0 // RG + 1) * (y1 // RG - y0 // RG + 1)).sum())
+        got = int(sum(ranges[T + roff + k, 1] - ranges[T + roff + k, 0] for k in range(rw * rh)))
+        assert got == want, (v, got, want)
+        for ry in range(rh):
+            for rx in range(rw):
+                rg = T + roff + ry * rw + rx
+                recs = order[vals[ranges[rg, 0]:ranges[rg, 1]]].astype(np.int64)
+                x0, y0, x1, y1 = tile_rects(mean2d[recs, 0], mean2d[recs, 1], radius[recs], gw, gh, tw, th)
+                # a region lists wide records whose rectangle overlaps it, each once
+                assert np.all((x0 // RG <= rx) & (rx <= x1 // RG) & (y0 // RG <= ry) & (ry <= y1 // RG))
+                assert np.all(wide_mask[recs]) and np.unique(recs).size == recs.size
+                region_recs.append(recs)
         for ty in range(gh):
             for tx in range(gw):
                 t = len(out)
                 narrow = order[vals[ranges[t, 0]:ranges[t, 1]]].astype(np.int64)
+                rg = T + roff + (ty // RG) * rw + tx // RG
+                cand = order[vals[ranges[rg, 0]:ranges[rg, 1]]].astype(np.int64)
+                x0, y0, x1, y1 = tile_rects(mean2d[cand, 0], mean2d[cand, 1], radius[cand], gw, gh, tw, th)
                 cover = (x0 <= tx) & (tx <= x1) & (y0 <= ty) & (ty <= y1)
-                recs = np.concatenate([narrow, wv[cover, 1].astype(np.int64)])
+                recs = np.concatenate([narrow, cand[cover]])
                 perm = np.lexsort((recs, depth_bits[recs].astype(np.int64)))
                 out.append(recs[perm])
-    return out
+        roff += rw * rh
+    return out, region_recs
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
@@ -155,8 +187,7 @@ def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
         img = torch.empty(3 * P, device="cuda")
         M.mgs_forward(ctx, frame, U.gstruct(dev), cams, gst, img)
         ex = {k: M.mgs_frame_export(ctx, frame, k) for k in
-              ("records", "radius", "depth", "values", "ranges", "wide", "wide_ranges", "order", "last", "stats",
-               "t_final")}
+              ("records", "radius", "depth", "tiles", "values", "ranges", "order", "last", "stats", "t_final")}
         st = M.mgs_frame_get_stats(frame)
         torch.cuda.synchronize()
     finally:
@@ -168,18 +199,23 @@ def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
     dbits = U.u32(ex["depth"])
     ol = oracle.build_lists([c["width"] for c in cams], [c["height"] for c in cams], n, oi["mean2d"], rad, dbits,
                             (rad > 0).astype(np.uint8), ost)
-    wide = U.u32(ex["wide"]).reshape(-1, 4)
-    assert wide.shape[0] == st["n_wide"]
+    # records covering more tiles than the threshold are listed per region
+    thr = {-1: None, 0: 64, 1: 1}[wide_tiles]
+    ntiles = U.u32(ex["tiles"]).astype(np.int64)
+    want_wide = np.zeros(ntiles.size, bool) if thr is None else ntiles > thr
+    assert st["n_wide"] == int(want_wide.sum())
     if wide_tiles < 0:
         assert st["n_wide"] == 0
     if wide_tiles == 1:
         assert st["n_wide"] > 0
-    lists = merged_tile_lists(cams, tw, th, U.u32(ex["values"]), U.u32(ex["ranges"]).reshape(-1, 2), wide,
-                              U.u32(ex["wide_ranges"]).reshape(-1, 2), U.u32(ex["order"]), dbits)
-    # wide entries carry their position and record consistently
-    assert np.array_equal(U.u32(ex["order"])[wide[:, 0]], wide[:, 1])
+    lists, region_recs = merged_tile_lists(cams, tw, th, U.u32(ex["values"]), U.u32(ex["ranges"]).reshape(-1, 2),
+                                           U.u32(ex["order"]), dbits, oi["mean2d"], rad, want_wide)
+    listed = np.unique(np.concatenate(region_recs)) if region_recs else np.zeros(0, np.int64)
+    assert np.array_equal(listed, np.nonzero(want_wide)[0])
     assert len(lists) == ol.ranges.shape[0]
     assert st["n_instances"] == U.u32(ex["values"]).size
+    rg = U.u32(ex["ranges"]).reshape(-1, 2).astype(np.int64)
+    assert int((rg[:, 1] - rg[:, 0]).sum()) == st["n_instances"]  # every entry in exactly one cell
     for t, lst in enumerate(lists):
         a, b = ol.ranges[t]
         assert np.array_equal(lst, ol.vals[a:b].astype(np.int64)), t
