@@ -164,14 +164,14 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--batch-depth", type=int, default=256)
-    ap.add_argument("--fwd-ppt", type=int, default=2)
+    ap.add_argument("--batch-depth", type=int, default=128)
+    ap.add_argument("--fwd-ppt", type=int, default=4)
     ap.add_argument("--bwd-ppt", type=int, default=4)
     ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
     ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")
     ap.add_argument("--tile-cull", type=int, default=1, help="narrow instances only for reachable tiles")
-    ap.add_argument("--wide-tiles", type=int, default=64,
+    ap.add_argument("--wide-tiles", type=int, default=16,
                     help="hybrid binning threshold in tiles (0: automatic, -1: every record duplicated)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")

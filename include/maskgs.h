@@ -233,7 +233,7 @@ MGS_API mgs_status mgs_frame_reserve(mgs_frame* frame, mgs_stream stream, double
 MGS_API mgs_status mgs_frame_check(mgs_frame* frame, mgs_stream stream);
 
 /* Autotuner for the compositing configuration: times forward + backward
- * (one warm-up, best of two, HIP events on `stream`) for tile shapes 16x16,
+ * (one warm-up, best of four, HIP events on `stream`) for tile shapes 16x16,
  * 16x8, 32x8 and 8x8 with batch depths 32..256, then the pixels-per-thread
  * pairs at the best shape, then the wide-list threshold, and returns the
  * fastest settings in *best (the other fields copied from *base) and their
@@ -340,7 +340,8 @@ MGS_API mgs_status mgs_profile_read(mgs_ctx* ctx, double* ms, int64_t* launches)
 /* ---------------------------------------------------------------------- */
 
 /* EWA projection and SH colour (Sec. 3.1) of every Gaussian for every view.
- * rec [R, 12]: u, v, a, b / a, c - b^2 / a, opacity, mask, 0, r, g, b, 0
+ * rec [R, 12]: u, v, a, b / a, c - b^2 / a, opacity, mask, radius, r, g, b,
+ *   tile count (u32 bits; the same values as radius[] and tiles[])
  *   (conic (a, b, c) is the inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2,
  *   stored in the form a (dx + (b / a) dy)^2 + (c - b^2 / a) dy^2, which FP32
  *   evaluates without cancellation for needle-shaped splats);

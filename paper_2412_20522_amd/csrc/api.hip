@@ -525,8 +525,8 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         launch_radix_sort(stream, (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint64_t*)f->rkeys_alt.p,
                           (uint32_t*)f->rvals_alt.p, R, nullptr, 32 + bits_for((uint64_t)V), f->rsort_tmp.p, &alt);
         f->order_in_alt = alt;
-        launch_permute_classify(stream, f->record_order(), (const uint32_t*)f->tiles.p, (const float*)f->rec.p,
-                                (const float*)f->radius.p, R, f->n, f->views, f->st, (uint32_t*)f->cnt_sorted.p,
+        launch_permute_classify(stream, f->record_order(), (const float*)f->rec.p, R, f->n, f->views, f->st,
+                                (uint32_t*)f->cnt_sorted.p,
                                 (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p,
                                 (uint32_t*)f->cls_part.p, f->wide_counts());
     }
@@ -672,11 +672,11 @@ mgs_status mgs_autotune(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         ctx->prof_on = was_on;
         return fail(ctx, MGS_ERR_HIP, "event creation");
     }
-    // one warm-up and two timed forward + backward passes; the faster counts
+    // one warm-up and four timed forward + backward passes; the fastest counts
     auto trial = [&](const mgs_settings& cand, double* ms) -> mgs_status {
         mgs_status r;
         *ms = 1e300;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < 5; ++rep) {
             if (rep > 0 && hipEventRecord(e0, stream) != hipSuccess) return fail(ctx, MGS_ERR_HIP, "event");
             if ((r = mgs_forward(f, stream_, g, cams, n_views, &cand, images, nullptr)) != MGS_OK) return r;
             if ((r = mgs_backward(f, stream_, dl_dimages, grads)) != MGS_OK) return r;
@@ -728,8 +728,8 @@ mgs_status mgs_autotune(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     }
     // wide-list threshold
     const mgs_settings pp = top;
-    const int wides[5] = {-1, 16, 64, 256, 1024};
-    for (int w = 0; w < 5 && r == MGS_OK; ++w) {
+    const int wides[6] = {-1, 8, 16, 32, 64, 256};
+    for (int w = 0; w < 6 && r == MGS_OK; ++w) {
         cur = pp;
         cur.wide_tiles = wides[w];
         if (cur.wide_tiles == pp.wide_tiles) continue;

@@ -52,8 +52,8 @@ constexpr uint32_t FLAG_NONFINITE = 2u;
 
 // Record layout: 3 float4 per (view, Gaussian) record.
 //   A = (u, v, a, beta)
-//   B = (gamma, opacity, mask, 0)
-//   C = (r, g, b, 0)
+//   B = (gamma, opacity, mask, radius)
+//   C = (r, g, b, number of tiles of the footprint as u32 bits)
 // The conic (inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2) is kept
 // as a, beta = b / a and gamma = c - b^2 / a, so that
 // Q = a (dx + beta dy)^2 + gamma dy^2 is a sum of two non-negative terms:

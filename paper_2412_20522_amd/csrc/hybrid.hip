@@ -199,8 +199,8 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 // culling) and the cull mask of every position, and per workgroup the number
 // of wide records and of their region entries (part[b], part[nb + b]).
 __global__ void __launch_bounds__(256) permute_classify_kernel(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ tiles, const float4* __restrict__ rec,
-    const float* __restrict__ radius, int64_t R, int64_t n, ViewSet views, DevSettings st,
+    const uint32_t* __restrict__ order, const float4* __restrict__ rec, int64_t R, int64_t n, ViewSet views,
+    DevSettings st,
     uint32_t* __restrict__ cnt_out, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
     float4* __restrict__ srec, uint32_t* __restrict__ part) {
     __shared__ uint32_t s_part[2][4];
@@ -212,14 +212,14 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     bool wide = false;
     int vi = 0;
     if (live) {
+        // one gather of the record (radius in B.w, tile count in C.w)
         const uint32_t r = order[i];
-        c = tiles[r];
-        vi = (int)(i / n);
-        wide = c > views.v[vi].wide_min;
         A = rec[3 * (size_t)r];
         B = rec[3 * (size_t)r + 1];
         uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
-        B.w = radius[r];
+        c = C.w;
+        vi = (int)(i / n);
+        wide = c > views.v[vi].wide_min;
         C.w = r;
         srec[3 * i] = A;
         srec[3 * i + 1] = B;
@@ -1088,14 +1088,13 @@ void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t
                        vals);
 }
 
-void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* tiles, const float* rec,
-                             const float* radius, int64_t R, int64_t n, const ViewSet& views, const DevSettings& st,
-                             uint32_t* cnt, uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
-                             uint64_t* wide_counts) {
+void launch_permute_classify(hipStream_t stream, const uint32_t* order, const float* rec, int64_t R, int64_t n,
+                             const ViewSet& views, const DevSettings& st, uint32_t* cnt, uint32_t* wide_flag,
+                             uint64_t* tmask, float* srec, uint32_t* part, uint64_t* wide_counts) {
     if (R == 0) return;
     const unsigned nb = blocks_of(R);
-    hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, tiles,
-                       reinterpret_cast<const float4*>(rec), radius, R, n, views, st, cnt, wide_flag, tmask,
+    hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order,
+                       reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, wide_flag, tmask,
                        reinterpret_cast<float4*>(srec), part);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(1024), 0, stream, part, (int)nb, wide_counts);
 }

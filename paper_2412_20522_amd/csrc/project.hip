@@ -283,8 +283,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             count = (x0 <= x1 && y0 <= y1) ? (uint32_t)((x1 - x0 + 1.0) * (y1 - y0 + 1.0)) : 0u;
         }
         rec[3 * r] = make_float4(o.u, o.v, (float)o.ca, (float)o.beta);
-        rec[3 * r + 1] = make_float4((float)o.gamma, opac, mval, 0.f);
-        rec[3 * r + 2] = make_float4(col[0], col[1], col[2], 0.f);
+        rec[3 * r + 1] = make_float4((float)o.gamma, opac, mval, o.radius);
+        rec[3 * r + 2] = make_float4(col[0], col[1], col[2], __uint_as_float(count));
         depth_out[r] = o.depth;
         radius_out[r] = o.radius;
         tiles_out[r] = count;
