@@ -246,6 +246,7 @@ DevSettings make_settings(const mgs_settings* s) {
         d.full_rect = 0;
         d.tile_cull = s->tile_cull != 0;
     }
+    d.qs_max = (float)(-0.5 / std::log(2.0) * (double)d.q_max);
     return d;
 }
 

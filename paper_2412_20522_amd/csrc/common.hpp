@@ -40,6 +40,7 @@ struct DevSettings {
     float bg[3];
     int32_t full_rect;  // every valid record covers every tile of its view
     int32_t tile_cull;  // narrow instances only for tiles a record can reach
+    float qs_max;       // -log2(e) / 2 * q_max: the cut on the scaled form of the compositing kernels
 };
 
 // Side of a region in tiles.  Wide records are listed once per region they

@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
     __shared__ uint32_t s_tile;
     const int t = threadIdx.x;
     const int batch = st.batch;
+    const EvalConsts ek = eval_consts(st);
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
@@ -74,8 +75,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
                 const int k = base + l;
                 if (k < end) {
                     const uint32_t r = vals[k];
-                    sA[l] = rec[3 * (size_t)r];
-                    sB[l] = rec[3 * (size_t)r + 1];
+                    sA[l] = stage_a(rec[3 * (size_t)r]);
+                    sB[l] = stage_b(rec[3 * (size_t)r + 1]);
                     sC[l] = rec[3 * (size_t)r + 2];
                 }
             }
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_fwd_kernel(
                 for (int i = 0; i < PPT; ++i) {
                     if (done[i]) continue;
                     Eval e;
-                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     const float ma = B.z * e.alpha;
                     const float test = T[i] * (1.f - ma);
                     if (test < st.t_min) {
@@ -147,13 +148,16 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
     const int lane = lane_id();
     const int batch = st.batch;
     const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
+    const EvalConsts ek = eval_consts(st);
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
         if (tile >= views.total_tiles) break;
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         const int64_t rec_base = (int64_t)tg.vi * n;
-        float px[PPT], py[PPT], T[PPT], Tf[PPT], w0[PPT], w1[PPT], w2[PPT], wbg[PPT], b0[PPT], b1[PPT], b2[PPT];
+        // sb = w . b: the pixel's loss weights dotted with the colour composited
+        // behind the current entry
+        float px[PPT], py[PPT], T[PPT], Tf[PPT], w0[PPT], w1[PPT], w2[PPT], wbg[PPT], sb[PPT];
         int lastk[PPT];
         int mylast = -1;
         const int64_t pv = (int64_t)cam.width * cam.height;
@@ -163,7 +167,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
             const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
             px[i] = (float)x + 0.5f;
             py[i] = (float)y + 0.5f;
-            b0[i] = b1[i] = b2[i] = 0.f;
+            sb[i] = 0.f;
             if (x < cam.width && y < cam.height) {
                 const int64_t loc = (int64_t)y * cam.width + x;
                 const int64_t p = (int64_t)cam.px_off + loc;
@@ -197,8 +201,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
             for (int l = t; l < cnt; l += NT) {
                 const uint32_t r = vals[lo + l];
                 sR[l] = r;
-                sA[l] = rec[3 * (size_t)r];
-                sB[l] = rec[3 * (size_t)r + 1];
+                sA[l] = stage_a(rec[3 * (size_t)r]);
+                sB[l] = stage_b(rec[3 * (size_t)r + 1]);
                 sC[l] = rec[3 * (size_t)r + 2];
             }
             __syncthreads();
@@ -206,6 +210,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
                 const int k = lo + j;
                 const float4 A = sA[j], B = sB[j], Cc = sC[j];
                 const float M = B.z;
+                const float okq = B.y * QSCALE_NINV;
                 float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
                       gm = 0.f;
                 bool any = false;
@@ -213,36 +218,33 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
                 for (int i = 0; i < PPT; ++i) {
                     if (k > lastk[i]) continue;
                     Eval e;
-                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     any = true;
-                    const float alpha = e.alpha, G = e.G, dy = e.dy;
-                    const float ma = M * alpha;
+                    const float ma = M * e.alpha;
                     const float one_m = 1.f - ma;
                     const float inv = __builtin_amdgcn_rcpf(one_m);
                     const float Ti = T[i] * inv;
-                    const float X = Ti * (w0[i] * (Cc.x - b0[i]) + w1[i] * (Cc.y - b1[i]) + w2[i] * (Cc.z - b2[i])) -
-                                    Tf[i] * inv * wbg[i];
-                    gm += alpha * X;
+                    const float d = fmaf(w0[i], Cc.x, fmaf(w1[i], Cc.y, w2[i] * Cc.z)) - sb[i];
+                    const float X = Ti * d - Tf[i] * inv * wbg[i];
+                    gm += e.alpha * X;
                     const float wt = ma * Ti;
                     gr += wt * w0[i];
                     gg += wt * w1[i];
                     gbl += wt * w2[i];
-                    if (e.oG <= st.alpha_max) {
-                        const float dA = M * X;
-                        go += G * dA;
-                        const float dQ = -0.5f * B.y * G * dA;
-                        // a dx + b dy = a t and b dx + c dy = beta a t + gamma dy; the
-                        // conic gradient is taken w.r.t. the stored (a, beta, gamma)
-                        const float at = A.z * e.t;
-                        gu += dQ * 2.f * at;
-                        gv += dQ * 2.f * fmaf(A.w, at, B.x * dy);
-                        ga += dQ * e.t * e.t;
-                        gb += dQ * 2.f * at * dy;
-                        gc += dQ * dy * dy;
+                    if (e.oG <= ek.amax) {
+                        // conic terms as multiples of kq = 2 dL/dQ / QSCALE (the
+                        // sums over t^2 and dy^2 are rescaled by QSCALE / 2 below)
+                        const float GdA = e.G * (M * X);
+                        go += GdA;
+                        const float kq = GdA * okq;
+                        const float kapt = kq * e.apt;
+                        gu += kapt;
+                        gv += kq * fmaf(A.w, e.apt, e.gdy);
+                        gb += kapt * e.dy;
+                        ga += (kq * e.t) * e.t;
+                        gc += (kq * e.dy) * e.dy;
                     }
-                    b0[i] = ma * Cc.x + one_m * b0[i];
-                    b1[i] = ma * Cc.y + one_m * b1[i];
-                    b2[i] = ma * Cc.z + one_m * b2[i];
+                    sb[i] = fmaf(ma, d, sb[i]);
                     T[i] = Ti;
                 }
                 if (__any(any)) {
@@ -250,10 +252,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) composite_bwd_kernel(
                     const int64_t g = (int64_t)r - rec_base;
                     const float sm = wave_sum(gm);
                     if (M != 0.f) {
-                        const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga), sb = wave_sum(gb),
-                                    sc = wave_sum(gc), so = wave_sum(go), sr = wave_sum(gr), sg = wave_sum(gg),
-                                    sbl = wave_sum(gbl);
-                        float v = lane == 0 ? su : lane == 1 ? sv : lane == 2 ? sa : lane == 3 ? sb : lane == 4 ? sc
+                        const float su = wave_sum(gu), sv = wave_sum(gv), sa = wave_sum(ga) * (0.5f * QSCALE),
+                                    sbt = wave_sum(gb), sc = wave_sum(gc) * (0.5f * QSCALE), so = wave_sum(go),
+                                    sr = wave_sum(gr), sg = wave_sum(gg), sbl = wave_sum(gbl);
+                        float v = lane == 0 ? su : lane == 1 ? sv : lane == 2 ? sa : lane == 3 ? sbt : lane == 4 ? sc
                                 : lane == 5 ? so : lane == 6 ? sr : lane == 7 ? sg : lane == 8 ? sbl : sm;
                         if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, v);
                         else if (lane == DREC) atomicAdd(d_masks + g, v);

@@ -24,23 +24,53 @@ __device__ __forceinline__ TileGeom tile_geom(const ViewSet& views, uint32_t til
     return tg;
 }
 
-// Evaluation of one entry at one pixel, shared by forward and backward so
-// both take the same FP32 decisions (3-sigma cut, alpha clamp and filter).
+// Entries staged in LDS hold a and gamma multiplied by QSCALE = -log2(e) / 2,
+// so the Gaussian weight exp(-Q / 2) is exp2 of the staged quadratic form
+// and the cut Q <= q_max reads qs >= QSCALE q_max (DevSettings::qs_max).
+constexpr float QSCALE = -0.72134752044448170f;
+// -1 / QSCALE = 2 ln 2
+constexpr float QSCALE_NINV = 1.38629436111989061f;
+
+__device__ __forceinline__ float4 stage_a(float4 A) {
+    A.z *= QSCALE;
+    return A;
+}
+__device__ __forceinline__ float4 stage_b(float4 B) {
+    B.x *= QSCALE;
+    return B;
+}
+
+// Per-kernel constants of the evaluation.
+struct EvalConsts {
+    float qs_max, amax, amin;
+};
+__device__ __forceinline__ EvalConsts eval_consts(const DevSettings& st) {
+    return EvalConsts{st.qs_max, st.alpha_max, st.alpha_min};
+}
+
+// Evaluation of one staged entry at one pixel, shared by forward and
+// backward so both take the same FP32 decisions (3-sigma cut, alpha clamp and
+// filter).  A = (u, v, a', beta), B = (gamma', opacity, mask, .) with
+// a' = QSCALE a and gamma' = QSCALE gamma.
 struct Eval {
-    float dx, dy, t, G, oG, alpha;  // t = dx + beta dy
+    float dy, t, apt, gdy, G, oG, alpha;  // t = dx + beta dy, apt = a' t, gdy = gamma' dy
 };
 
 __device__ __forceinline__ bool eval_entry(const float4& A, const float4& B, float px, float py,
-                                           const DevSettings& st, Eval& e) {
-    e.dx = A.x - px;
+                                           const EvalConsts& k, Eval& e) {
+    const float dx = A.x - px;
     e.dy = A.y - py;
-    e.t = fmaf(A.w, e.dy, e.dx);
-    const float Q = A.z * e.t * e.t + B.x * e.dy * e.dy;
-    if (!(Q <= st.q_max)) return false;
-    e.G = __expf(-0.5f * Q);
+    e.t = fmaf(A.w, e.dy, dx);
+    e.apt = A.z * e.t;
+    e.gdy = B.x * e.dy;
+    const float qs = fmaf(e.apt, e.t, e.gdy * e.dy);  // QSCALE Q <= 0
+    if (!(qs >= k.qs_max)) return false;
+    e.G = __builtin_amdgcn_exp2f(qs);
     e.oG = B.y * e.G;
-    e.alpha = fminf(st.alpha_max, e.oG);
-    return e.alpha >= st.alpha_min;
+    // min(alpha_max, oG) for oG >= 0 in one instruction (a min would first
+    // canonicalise its operands)
+    e.alpha = __builtin_amdgcn_fmed3f(e.oG, 0.f, k.amax);
+    return e.alpha >= k.amin;
 }
 
 // Persistent launches pop tile ids from a device counter; plain launches

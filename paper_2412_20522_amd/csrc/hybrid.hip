@@ -599,15 +599,16 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     for (int b = t; b < nY; b += NT) L.m[b + count_lt(L.xk, nX, L.yk[b])] = L.yk[b];
     __syncthreads();
     // the windows are dead: stage over them, in merged order, the records
-    // that can reach a pixel of the tile; B.w (the radius, unused here)
-    // carries the entry's index within the merged batch
+    // that can reach a pixel of the tile (a and gamma scaled for
+    // eval_entry); B.w (the radius, unused here) carries the entry's index
+    // within the merged batch
     const int M = nX + nY;
     if (st.tile_cull) {
         for (int j = t; j < M; j += NT) {
             const size_t i = L.m[j];
-            float4 B = srec[3 * i + 1];
+            float4 B = stage_b(srec[3 * i + 1]);
             B.w = __int_as_float(j);
-            L.A[j] = srec[3 * i];
+            L.A[j] = stage_a(srec[3 * i]);
             L.Bv[j] = B;
             L.C[j] = srec[3 * i + 2];
         }
@@ -632,9 +633,9 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
         if (!((keep >> q) & 1u)) continue;
         const int j = t * run + q;
         const size_t i = L.m[j];
-        float4 B = srec[3 * i + 1];
+        float4 B = stage_b(srec[3 * i + 1]);
         B.w = __int_as_float(j);
-        L.A[p] = srec[3 * i];
+        L.A[p] = stage_a(srec[3 * i]);
         L.Bv[p] = B;
         L.C[p] = srec[3 * i + 2];
         ++p;
@@ -708,6 +709,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
     const int t = threadIdx.x;
     const int batch = st.batch;
     const Lds L = carve(smem, batch);
+    const EvalConsts ek = eval_consts(st);
     if (*hl.cur_need > hl.cur_cap) {  // a fixed workspace too small: report, write nothing
         if (blockIdx.x == 0 && t == 0) atomicOr(hl.flags, FLAG_CAPACITY);
         return;
@@ -773,7 +775,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
                     if (done[i]) continue;
                     if (STATS) ++nev[i];
                     Eval e;
-                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     const float ma = B.z * e.alpha;
                     const float test = T[i] * (1.f - ma);
                     if (test < st.t_min) {
@@ -858,6 +860,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
     const int batch = st.batch;
     const Lds L = carve(smem, batch);
     const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
+    const EvalConsts ek = eval_consts(st);
+    // the wave totals of the sums over t^2 and dy^2 (quantities 2 and 4) are
+    // rescaled by QSCALE / 2 to give dL/da and dL/dgamma (see the pixel loop)
+    const float qscale = (lane == 2 || lane == 4) ? 0.5f * QSCALE : 1.f;
     if (*hl.cur_need > hl.cur_cap) return;  // the forward reported it
     for (;;) {
         const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
@@ -865,7 +871,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         const int64_t rec_base = (int64_t)tg.vi * n;
-        float px[PPT], py[PPT], T[PPT], Tf[PPT], w0[PPT], w1[PPT], w2[PPT], wbg[PPT], b0[PPT], b1[PPT], b2[PPT];
+        // s = w . b: the loss weights of the pixel dotted with the colour
+        // composited behind the current entry (scaled by its transmittance)
+        float px[PPT], py[PPT], T[PPT], Tf[PPT], w0[PPT], w1[PPT], w2[PPT], wbg[PPT], sb[PPT];
         int lastk[PPT];
         int mylast = -1;
         const int64_t pv = (int64_t)cam.width * cam.height;
@@ -875,7 +883,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
             const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
             px[i] = (float)x + 0.5f;
             py[i] = (float)y + 0.5f;
-            b0[i] = b1[i] = b2[i] = 0.f;
+            sb[i] = 0.f;
             if (x < cam.width && y < cam.height) {
                 const int64_t loc = (int64_t)y * cam.width + x;
                 const int64_t p = (int64_t)cam.px_off + loc;
@@ -925,9 +933,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                 for (int p = t; p < Mb; p += NT) {
                     const uint2 e = hl.stg[cs.x + p];
                     const size_t i = e.x;
-                    float4 B = srec[3 * i + 1];
+                    float4 B = stage_b(srec[3 * i + 1]);
                     B.w = __uint_as_float(e.y);
-                    L.A[p] = srec[3 * i];
+                    L.A[p] = stage_a(srec[3 * i]);
                     L.Bv[p] = B;
                     L.C[p] = srec[3 * i + 2];
                 }
@@ -941,6 +949,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                 const int k = m + __float_as_int(B.w);  // index in the tile's full list
                 if (k > top) continue;                  // uniform: past every pixel's last entry
                 const float M = B.z;
+                const float okq = B.y * QSCALE_NINV;
                 float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
                       gm = 0.f;
                 bool any = false;
@@ -948,36 +957,36 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                 for (int i = 0; i < PPT; ++i) {
                     if (k > lastk[i]) continue;
                     Eval e;
-                    if (!eval_entry(A, B, px[i], py[i], st, e)) continue;
+                    if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     any = true;
-                    const float alpha = e.alpha, G = e.G, dy = e.dy;
-                    const float ma = M * alpha;
+                    const float ma = M * e.alpha;
                     const float one_m = 1.f - ma;
                     const float inv = __builtin_amdgcn_rcpf(one_m);
                     const float Ti = T[i] * inv;
-                    const float X = Ti * (w0[i] * (Cc.x - b0[i]) + w1[i] * (Cc.y - b1[i]) + w2[i] * (Cc.z - b2[i])) -
-                                    Tf[i] * inv * wbg[i];
-                    gm += alpha * X;
+                    const float d = fmaf(w0[i], Cc.x, fmaf(w1[i], Cc.y, w2[i] * Cc.z)) - sb[i];
+                    const float X = Ti * d - Tf[i] * inv * wbg[i];
+                    gm += e.alpha * X;
                     const float wt = ma * Ti;
                     gr += wt * w0[i];
                     gg += wt * w1[i];
                     gbl += wt * w2[i];
-                    if (e.oG <= st.alpha_max) {
-                        const float dA = M * X;
-                        go += G * dA;
-                        const float dQ = -0.5f * B.y * G * dA;
-                        // a dx + b dy = a t and b dx + c dy = beta a t + gamma dy; the
-                        // conic gradient is taken w.r.t. the stored (a, beta, gamma)
-                        const float at = A.z * e.t;
-                        gu += dQ * 2.f * at;
-                        gv += dQ * 2.f * fmaf(A.w, at, B.x * dy);
-                        ga += dQ * e.t * e.t;
-                        gb += dQ * 2.f * at * dy;
-                        gc += dQ * dy * dy;
+                    if (e.oG <= ek.amax) {
+                        // dL/dalpha = M X, dL/dQ = -o G M X / 2; with a' = QSCALE a,
+                        // gamma' = QSCALE gamma: dL/du = kq a' t, dL/dv =
+                        // kq (beta a' t + gamma' dy), dL/dbeta = kq a' t dy, and
+                        // dL/da, dL/dgamma are QSCALE / 2 times the sums of kq t^2,
+                        // kq dy^2, where kq = 2 dL/dQ / QSCALE
+                        const float GdA = e.G * (M * X);
+                        go += GdA;
+                        const float kq = GdA * okq;
+                        const float kapt = kq * e.apt;
+                        gu += kapt;
+                        gv += kq * fmaf(A.w, e.apt, e.gdy);
+                        gb += kapt * e.dy;
+                        ga += (kq * e.t) * e.t;
+                        gc += (kq * e.dy) * e.dy;
                     }
-                    b0[i] = ma * Cc.x + one_m * b0[i];
-                    b1[i] = ma * Cc.y + one_m * b1[i];
-                    b2[i] = ma * Cc.z + one_m * b2[i];
+                    sb[i] = fmaf(ma, d, sb[i]);
                     T[i] = Ti;
                 }
                 if (__any(any)) {
@@ -986,7 +995,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
                     if (M != 0.f) {
                         // lane q (< 10) of the wave receives the wave total of quantity q
                         float v[10] = {gu, gv, ga, gb, gc, go, gr, gg, gbl, gm};
-                        const float x = wave_sum_transposed10(v, lane);
+                        const float x = wave_sum_transposed10(v, lane) * qscale;
                         if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, (double)x);
                         else if (lane == DREC) atomicAdd(d_masks + g, (double)x);
                     } else {
