@@ -171,7 +171,7 @@ def main() -> int:
     ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
     ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")
     ap.add_argument("--tile-cull", type=int, default=1, help="narrow instances only for reachable tiles")
-    ap.add_argument("--wide-tiles", type=int, default=16,
+    ap.add_argument("--wide-tiles", type=int, default=8,
                     help="hybrid binning threshold in tiles (0: automatic, -1: every record duplicated)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")

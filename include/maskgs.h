@@ -235,7 +235,8 @@ MGS_API mgs_status mgs_frame_check(mgs_frame* frame, mgs_stream stream);
 /* Autotuner for the compositing configuration: times forward + backward
  * (one warm-up, best of four, HIP events on `stream`) for tile shapes 16x16,
  * 16x8, 32x8 and 8x8 with batch depths 32..256, then the pixels-per-thread
- * pairs at the best shape, then the wide-list threshold, and returns the
+ * pairs with every batch depth at the best shape, then the wide-list
+ * threshold, and returns the
  * fastest settings in *best (the other fields copied from *base) and their
  * time in *best_ms (may be NULL).  Images, tile lists and gradients agree
  * across these settings (tile-size invariance of the per-pixel cut), so the

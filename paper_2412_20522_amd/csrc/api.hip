@@ -710,20 +710,24 @@ mgs_status mgs_autotune(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
             }
         }
     }
-    // pixels per thread of each pass at the best shape
+    // pixels per thread of each pass and batch depth at the best shape (the
+    // best depth depends on the pixels per thread)
     const mgs_settings shape = top;
-    for (int fp = 1; fp <= 4 && r == MGS_OK; fp *= 2) {
-        for (int bp = 1; bp <= 4 && r == MGS_OK; bp *= 2) {
-            cur = shape;
-            cur.fwd_ppt = fp;
-            cur.bwd_ppt = bp;
-            if (!composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, fp}) ||
-                !composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, bp}) ||
-                (fp == shape.fwd_ppt && bp == shape.bwd_ppt))
-                continue;
-            if ((r = trial(cur, &ms)) == MGS_OK && ms < top_ms) {
-                top_ms = ms;
-                top = cur;
+    for (int b = 0; b < 4 && r == MGS_OK; ++b) {
+        for (int fp = 1; fp <= 4 && r == MGS_OK; fp *= 2) {
+            for (int bp = 1; bp <= 4 && r == MGS_OK; bp *= 2) {
+                cur = shape;
+                cur.batch_depth = depths[b];
+                cur.fwd_ppt = fp;
+                cur.bwd_ppt = bp;
+                if (!composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, fp}) ||
+                    !composite_config_supported(CompositeConfig{cur.tile_w, cur.tile_h, bp}) ||
+                    (fp == shape.fwd_ppt && bp == shape.bwd_ppt && cur.batch_depth == shape.batch_depth))
+                    continue;
+                if ((r = trial(cur, &ms)) == MGS_OK && ms < top_ms) {
+                    top_ms = ms;
+                    top = cur;
+                }
             }
         }
     }
