@@ -116,9 +116,11 @@ __device__ __forceinline__ TileBox cell_box(int cx, int cy, int cw, int ch, cons
                    (float)min(y0 + ch, cam.height) - 0.5f};
 }
 
-// The touch test of the binning kernels.  Classification counts the cells a
-// record can reach and duplication emits them, in two kernels; kept out of
-// line so that both run the same instructions and take identical decisions.
+// The touch test of the binning kernels for rectangles of more than
+// CULL_MAX cells, which classification counts and duplication tests again
+// to emit: kept out of line so that both kernels run the same instructions
+// and take identical decisions.  (Smaller rectangles are tested once, inline,
+// and their result travels as a bit mask.)
 __device__ __noinline__ bool cell_touch_ool(float4 A, float4 B, TileBox box, float q_max, float alpha_min) {
     return touch_test(touch_prep(A, B, q_max, alpha_min), box);
 }
@@ -233,10 +235,10 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     uint32_t cnt = cull ? 0u : cl.area;
     if (cull && cl.area < COOP_MIN) {
         const DevView& cam = views.v[vi];
+        const TouchPrep tp = touch_prep(A, B, st);
         for (uint32_t j = 0; j < cl.area; ++j) {
             const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
-            if (cell_touch(A, B, cell_box(cl.x0 + (int)rx, cl.y0 + (int)ry, cl.cw, cl.ch, cam), st))
-                mask |= 1ull << j;
+            if (touch_test(tp, cell_box(cl.x0 + (int)rx, cl.y0 + (int)ry, cl.cw, cl.ch, cam))) mask |= 1ull << j;
         }
         cnt = (uint32_t)__popcll(mask);
     }
@@ -255,7 +257,8 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
             bool pass = false;
             if (j < barea) {
                 const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
-                pass = cell_touch(bA, bB, cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam), st);
+                const TileBox box = cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam);
+                pass = barea <= CULL_MAX ? touch_test(touch_prep(bA, bB, st), box) : cell_touch(bA, bB, box, st);
             }
             const uint64_t bal = __ballot(pass);
             total += (uint32_t)__popcll(bal);
@@ -354,8 +357,10 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         const DevView& cam = views.v[vi];
         int64_t o = off;
         const int64_t end = off + cnt;
-        for (uint32_t j = 0; j < cl.area && o < end; ++j) {
-            if (cull && !((mask >> j) & 1ull)) continue;
+        // the cells to emit: the set bits of the mask (all cells without culling)
+        uint64_t todo = cull ? mask : (cl.area >= 64 ? ~0ull : (1ull << cl.area) - 1ull);
+        for (; todo && o < end; todo &= todo - 1ull) {
+            const uint32_t j = (uint32_t)(__ffsll((long long)todo) - 1);
             const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
             if (o < capacity) {
                 keys[o] = cell_key(wide, cl.x0 + (int)rx, cl.y0 + (int)ry, cam, views);
