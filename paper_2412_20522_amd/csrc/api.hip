@@ -282,6 +282,9 @@ struct mgs_frame {
         evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
+    // d_rec is all zeros between backwards (the projection backward clears
+    // the rows it reads); false until a fill after (re)allocation
+    bool drec_zero = false;
     // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
     // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
     // 32, staged-entry counter (u32) at 192
@@ -408,6 +411,15 @@ mgs_status mgs_frame_get_stats(const mgs_frame* f, mgs_frame_stats* out) {
     return MGS_OK;
 }
 
+// Grows the FP64 per-record gradient accumulator; a new allocation is not
+// known to be zero.
+static mgs_status grow_drec(mgs_frame* f) {
+    const size_t before = f->d_rec.p ? f->d_rec.bytes : 0;  // grow reallocates only to a larger size
+    const mgs_status s = grow(f->ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8);
+    if (s != MGS_OK || f->d_rec.bytes != before) f->drec_zero = false;
+    return s;
+}
+
 mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
     if (!f) return MGS_ERR_INVALID_ARG;
     mgs_ctx* ctx = f->ctx;
@@ -431,7 +443,7 @@ mgs_status mgs_frame_reserve(mgs_frame* f, mgs_stream stream_, double slack) {
     const size_t kb = (size_t)K_cap * 4 + 16;
     if ((s = grow(ctx, f->keys, kb)) || (s = grow(ctx, f->vals, kb)) || (s = grow(ctx, f->keys_alt, kb)) ||
         (s = grow(ctx, f->vals_alt, kb)) || (s = grow(ctx, f->sort_tmp, sort_scratch_bytes(K_cap))) ||
-        (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) || (s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)) ||
+        (s = grow(ctx, f->cur, (size_t)cur_cap * 16 + 16)) || (s = grow_drec(f)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)) ||
         (s = grow(ctx, f->cur_stg, (size_t)cur_cap * 8 + 8)) || (s = grow(ctx, f->stg, (size_t)stg_cap * 8 + 8)))
         return s;
     f->stg_cap = stg_cap;
@@ -631,10 +643,14 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     mgs_status s;
     // per-record 2D gradients and mask gradients accumulate in FP64: a wide
     // splat takes atomics from thousands of tiles whose partial sums cancel
-    if ((s = grow(ctx, f->d_rec, (size_t)f->R * DREC * 8 + 8)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8)))
-        return s;
+    if ((s = grow_drec(f)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8))) return s;
     uint32_t* queue = nullptr;
-    launch_fill_u32(stream, (uint32_t*)f->d_rec.p, 2 * f->R * DREC, 0u);  // +0.0 in every double
+    if (!f->drec_zero) {
+        // +0.0 in every double, once per allocation: afterwards the
+        // projection backward leaves the rows it read at zero
+        launch_fill_u32(stream, (uint32_t*)f->d_rec.p, f->d_rec.bytes / 4, 0u);
+        f->drec_zero = true;
+    }
     launch_fill_u32(stream, (uint32_t*)f->dm_acc.p, 2 * f->n, 0u);
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;
@@ -648,7 +664,7 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     }
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT_BWD);
-        launch_project_bwd64(stream, f->g, f->views, f->st, (const double*)f->d_rec.p, (const double*)f->dm_acc.p,
+        launch_project_bwd64(stream, f->g, f->views, f->st, (double*)f->d_rec.p, (const double*)f->dm_acc.p,
                              *grads);
     }
     MGS_CHECK_LAUNCH(ctx);

@@ -14,10 +14,10 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
                         float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags);
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out);
-// Whole path: FP64 per-record gradients; dm_acc (FP64 mask gradients) is
-// rounded into out.d_masks.
+// Whole path: FP64 per-record gradients, which are set back to zero as they
+// are read; dm_acc (FP64 mask gradients) is rounded into out.d_masks.
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                          const double* d_rec, const double* dm_acc, const mgs_gradients& out);
+                          double* d_rec, const double* dm_acc, const mgs_gradients& out);
 
 // scan / binning / sort / ranges
 size_t scan_scratch_bytes(int64_t n);

@@ -295,11 +295,15 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
 // AccT: type of the per-record 2D gradients (float from the stage entry
 // point, double from the whole path, which accumulates them with FP64
 // atomics); dm_acc (optional) holds FP64 mask gradients to round into d_masks.
+// clear (optional, the same array as d_rec): each row read is set back to
+// zero, so the accumulator is clean for the next backward without a fill
+// (only records with a valid projection can have received gradients, and
+// every such row is read here).
 template <int DEG, typename AccT>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh, int64_t n, ViewSet views,
-    DevSettings st, const AccT* __restrict__ d_rec, const double* __restrict__ dm_acc, float* __restrict__ d_means,
+    DevSettings st, const AccT* d_rec, const double* __restrict__ dm_acc, AccT* clear, float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
     float* __restrict__ d_sh, float* __restrict__ d_masks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -325,7 +329,12 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         if (!o.valid) continue;
         const AccT* dr = d_rec + r * DREC;
         const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
+        const AccT dcol_in[3] = {dr[6], dr[7], dr[8]};
         gop += (double)dr[5];
+        if (clear) {
+#pragma unroll
+            for (int q = 0; q < DREC; ++q) clear[r * DREC + q] = (AccT)0;
+        }
         // colour: SH coefficients and viewing direction
         float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
         const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -338,7 +347,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             float acc = 0.5f;
 #pragma unroll
             for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
-            dcol[ch] = acc < 0.f ? 0.f : (float)dr[6 + ch];
+            dcol[ch] = acc < 0.f ? 0.f : (float)dcol_in[ch];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -498,13 +507,13 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 namespace {
 template <typename AccT>
 void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                   const AccT* d_rec, const double* dm_acc, const mgs_gradients& out) {
+                   const AccT* d_rec, const double* dm_acc, AccT* clear, const mgs_gradients& out) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     float* d_masks = dm_acc ? out.d_masks : nullptr;
 #define MGS_PBWD(D)                                                                                               \
     hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats, \
-                       g.opacity_logits, g.sh, g.n, views, st, d_rec, dm_acc, out.d_means, out.d_log_scales,      \
+                       g.opacity_logits, g.sh, g.n, views, st, d_rec, dm_acc, clear, out.d_means, out.d_log_scales, \
                        out.d_quats, out.d_opacity_logits, out.d_sh, d_masks)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
@@ -518,12 +527,12 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
 
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out) {
-    project_bwd_t<float>(stream, g, views, st, d_rec, nullptr, out);
+    project_bwd_t<float>(stream, g, views, st, d_rec, nullptr, nullptr, out);
 }
 
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                          const double* d_rec, const double* dm_acc, const mgs_gradients& out) {
-    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, out);
+                          double* d_rec, const double* dm_acc, const mgs_gradients& out) {
+    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, d_rec, out);
 }
 
 }  // namespace mgs
