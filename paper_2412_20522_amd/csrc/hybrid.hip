@@ -650,33 +650,53 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
 }
 
 // Wave totals of ten per-lane quantities, transposed: on return lane q
-// (q < 10; also q + 16, q + 32, q + 48) holds the total of quantity q.  Each
-// quantity is first summed within its 16-lane row by DPP (the ten chains
-// interleave, so no wait states are needed between dependent DPP steps);
-// lane q of every row then picks quantity q and the four rows are folded by
-// two cross-row exchanges.  About half the instructions of ten separate
-// full-wave sums.
-__device__ __forceinline__ float wave_sum_transposed10(float (&v)[10], int lane) {
+// (q < 10) holds the total of quantity q.  A butterfly within each 16-lane
+// row halves the values a lane carries at every step: the partner lane
+// (lane ^ 1, lane ^ 2 by DPP quad permutes, then the row rotations by 4 and
+// 8) receives one of each pair and keeps the other, so after four steps a
+// lane holds the row total of one quantity (lane & 7) and of quantity
+// 8 + (lane & 1); the four rows are then added by two lane swaps.
+__device__ __forceinline__ float dpp_xor1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_xor2(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_ror4(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_ror8(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+}
+// x(lane) + x(lane ^ 16) + x(lane ^ 32) + x(lane ^ 48)
+__device__ __forceinline__ float rows_sum(float x) {
+    const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
+    const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+}
+
+__device__ __forceinline__ float wave_sum_transposed10(const float (&v)[10], int lane) {
+    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
+    float w[5];
 #pragma unroll
-    for (int q = 0; q < 10; ++q)
-        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0xb1, 0xf, 0xf, false));
-#pragma unroll
-    for (int q = 0; q < 10; ++q)
-        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x4e, 0xf, 0xf, false));
-#pragma unroll
-    for (int q = 0; q < 10; ++q)
-        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x124, 0xf, 0xf, false));
-#pragma unroll
-    for (int q = 0; q < 10; ++q)
-        v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x128, 0xf, 0xf, false));
-    const int lr = lane & 15;
-    float x = v[0];
-#pragma unroll
-    for (int q = 1; q < 10; ++q) x = lr == q ? v[q] : x;
-    // rows 0 + 1 and 2 + 3 (swizzle within 32 lanes: lane ^ 16), then the halves
-    x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401f));
-    x += __shfl_xor(x, 32);
-    return x;
+    for (int p = 0; p < 5; ++p) {
+        // w[p]: quantity 2 p + b0 over lanes {l, l ^ 1}
+        const float keep = b0 ? v[2 * p + 1] : v[2 * p], send = b0 ? v[2 * p] : v[2 * p + 1];
+        w[p] = keep + dpp_xor1(send);
+    }
+    // x0: quantity 2 b1 + b0, x1: 4 + 2 b1 + b0, x2: 8 + b0, over the quad
+    const float x0 = (b1 ? w[1] : w[0]) + dpp_xor2(b1 ? w[0] : w[1]);
+    const float x1 = (b1 ? w[3] : w[2]) + dpp_xor2(b1 ? w[2] : w[3]);
+    const float x2 = w[4] + dpp_xor2(w[4]);
+    // the rotation by 4 pairs every lane with one of opposite b2 and equal
+    // low bits: y0 holds quantity lane & 7 over two quads, y1 quantity 8 + b0
+    const float y0 = (b2 ? x1 : x0) + dpp_ror4(b2 ? x0 : x1);
+    const float y1 = x2 + dpp_ror4(x2);
+    // rotation by 8 = lane ^ 8: row totals
+    const float z0 = rows_sum(y0 + dpp_ror8(y0));
+    const float z1 = rows_sum(y1 + dpp_ror8(y1));
+    return lane < 8 ? z0 : z1;
 }
 
 // Staged-list chunks: a persistent workgroup composites many tiles, a plain
