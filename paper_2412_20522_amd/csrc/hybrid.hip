@@ -55,7 +55,12 @@ struct TouchPrep {
     float cut;       // +huge: no cut (always touches); < 0: reaches no pixel
 };
 
+// Every operation below is written out (fmaf where a fused product is meant)
+// and contraction is off, so the rounding of each step is fixed by the
+// source: the binning kernels inline the test and still take identical
+// decisions for the same record and cell.
 __device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B, float q_max, float alpha_min) {
+#pragma clang fp contract(off)
     TouchPrep p;
     p.u = A.x;
     p.v = A.y;
@@ -71,7 +76,7 @@ __device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B
     if (alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / alpha_min));
     if (cut >= 3.0e38f) p.cut = 3.4e38f;          // no finite cut
     else if (!(cut > -3.0e38f)) p.cut = -1.f;     // zero opacity
-    else p.cut = cut + 1e-3f * (1.f + fabsf(cut));
+    else p.cut = fmaf(1e-3f, 1.f + fabsf(cut), cut);
     return p;
 }
 
@@ -79,28 +84,27 @@ __device__ __forceinline__ TouchPrep touch_prep(const float4& A, const float4& B
     return touch_prep(A, B, st.q_max, st.alpha_min);
 }
 
+// a (dx + beta dy)^2 + gamma dy^2
+__device__ __forceinline__ float touch_q(const TouchPrep& p, float dx, float dy) {
+#pragma clang fp contract(off)
+    const float t = fmaf(p.beta, dy, dx);
+    const float at = p.a * t;
+    const float gdy = p.gamma * dy;
+    return fmaf(at, t, gdy * dy);
+}
+
 __device__ __forceinline__ bool touch_test(const TouchPrep& p, const TileBox& tb) {
+#pragma clang fp contract(off)
     if (p.cut >= 3.0e38f) return true;  // no cut (exact mode)
     if (p.cut < 0.f) return false;
     if (p.u >= tb.X0 && p.u <= tb.X1 && p.v >= tb.Y0 && p.v <= tb.Y1) return true;
     const float dyl = p.v - tb.Y1, dyh = p.v - tb.Y0, dxl = p.u - tb.X1, dxh = p.u - tb.X0;
-    float q;
-    {
-        const float dx = dxh, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh), t = fmaf(p.beta, dy, dx);
-        q = p.a * t * t + p.gamma * dy * dy;
-    }
-    {
-        const float dx = dxl, dy = fminf(fmaxf(p.nbc * dx, dyl), dyh), t = fmaf(p.beta, dy, dx);
-        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
-    }
-    {
-        const float dy = dyh, dx = fminf(fmaxf(-p.beta * dy, dxl), dxh), t = fmaf(p.beta, dy, dx);
-        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
-    }
-    {
-        const float dy = dyl, dx = fminf(fmaxf(-p.beta * dy, dxl), dxh), t = fmaf(p.beta, dy, dx);
-        q = fminf(q, p.a * t * t + p.gamma * dy * dy);
-    }
+    // along the vertical edges dy minimises at -b/c dx, along the horizontal
+    // ones dx at -beta dy, each clamped to the edge
+    float q = touch_q(p, dxh, fminf(fmaxf(p.nbc * dxh, dyl), dyh));
+    q = fminf(q, touch_q(p, dxl, fminf(fmaxf(p.nbc * dxl, dyl), dyh)));
+    q = fminf(q, touch_q(p, fminf(fmaxf(-p.beta * dyh, dxl), dxh), dyh));
+    q = fminf(q, touch_q(p, fminf(fmaxf(-p.beta * dyl, dxl), dxh), dyl));
     return q <= p.cut;
 }
 
@@ -114,19 +118,6 @@ __device__ __forceinline__ TileBox cell_box(int cx, int cy, int cw, int ch, cons
     const int x0 = cx * cw, y0 = cy * ch;
     return TileBox{(float)x0 + 0.5f, (float)min(x0 + cw, cam.width) - 0.5f, (float)y0 + 0.5f,
                    (float)min(y0 + ch, cam.height) - 0.5f};
-}
-
-// The touch test of the binning kernels for rectangles of more than
-// CULL_MAX cells, which classification counts and duplication tests again
-// to emit: kept out of line so that both kernels run the same instructions
-// and take identical decisions.  (Smaller rectangles are tested once, inline,
-// and their result travels as a bit mask.)
-__device__ __noinline__ bool cell_touch_ool(float4 A, float4 B, TileBox box, float q_max, float alpha_min) {
-    return touch_test(touch_prep(A, B, q_max, alpha_min), box);
-}
-
-__device__ __forceinline__ bool cell_touch(const float4& A, const float4& B, const TileBox& box, const DevSettings& st) {
-    return cell_touch_ool(A, B, box, st.q_max, st.alpha_min);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,10 +172,84 @@ __device__ __forceinline__ uint32_t cell_key(bool wide, int cx, int cy, const De
                 : cam.tile_off + (uint32_t)cy * (uint32_t)cam.grid_w + (uint32_t)cx;
 }
 
-// With culling, the tested cells of a rectangle of at most CULL_MAX cells are
-// kept as a bit mask (bit j: cell j) for the duplication to follow; larger
-// rectangles are tested again there.  Rectangles of at least COOP_MIN cells
-// are handled by a whole wave, one cell per lane.
+// Row-wise culling of the binning.  Within a band of pixel-centre rows
+// [Y0, Y1] the points where an entry can pass the per-pixel filters form the
+// band's slice of the ellipse a (ex + beta ey)^2 + gamma ey^2 <= cut (ex, ey
+// offsets from the centre; cut = min(q_max, 2 ln(opacity / alpha_min)) plus a
+// margin), and the slice's x-extent is an interval: the chord's right end
+// -beta ey + sqrt((cut - gamma ey^2) / a) is concave in ey, so its maximum
+// over the band is at the ellipse's rightmost point (ey = eyR) clamped to the
+// band, and the left end's minimum at -eyR.  A cell of the row is kept iff
+// the interval meets the cell's pixel-centre columns -- the decision of a
+// test of the quadratic form's minimum over each cell's box, taken once per
+// row.  Every operation is written out and contraction is off, so the
+// classification (which counts) and the duplication (which emits) take
+// identical decisions; culled cells contribute nothing to any pixel.
+struct RowCull {
+    float u, v, beta, gamma, inva, cut, H, eyR;
+    int mode;  // 0: cull, 1: every cell (no finite cut), 2: no cell
+};
+
+__device__ __forceinline__ RowCull row_prep(const float4& A, const float4& B, const DevSettings& st) {
+#pragma clang fp contract(off)
+    RowCull p;
+    p.u = A.x;
+    p.v = A.y;
+    p.beta = A.w;
+    p.gamma = B.x;
+    const float a = A.z;
+    float cut = st.q_max;
+    if (st.alpha_min > 0.f) cut = fminf(cut, 2.f * __logf(B.y / st.alpha_min));
+    p.mode = 0;
+    p.cut = 0.f;
+    if (cut >= 3.0e38f) {
+        p.mode = 1;
+    } else if (!(cut > -3.0e38f)) {
+        p.mode = 2;
+    } else {
+        p.cut = fmaf(1e-3f, 1.f + fabsf(cut), cut);
+        if (!(p.cut >= 0.f)) p.mode = 2;
+    }
+    p.inva = 1.f / a;
+    p.H = sqrtf(p.cut / p.gamma);
+    const float D = fmaf(a * p.beta, p.beta, p.gamma);  // c = gamma + a beta^2
+    p.eyR = -p.beta * sqrtf(p.cut * a / (p.gamma * D));
+    return p;
+}
+
+// Columns [lo, hi] (within [x0, x1]) of cell row cy, cells of cw x ch pixels
+// (powers of two), that the entry can reach; false if none.
+__device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int ch, int x0, int x1,
+                                          const DevView& cam, int& lo, int& hi) {
+#pragma clang fp contract(off)
+    lo = x0;
+    hi = x1;
+    if (p.mode == 1) return true;
+    if (p.mode == 2) return false;
+    const float Y0 = (float)(cy * ch) + 0.5f, Y1 = (float)min((cy + 1) * ch, cam.height) - 0.5f;
+    const float e0 = fmaxf(Y0 - p.v, -p.H), e1 = fminf(Y1 - p.v, p.H);
+    if (!(e0 <= e1)) return false;
+    const float eR = fminf(fmaxf(p.eyR, e0), e1), eL = fminf(fmaxf(-p.eyR, e0), e1);
+    const float gR = p.gamma * eR, gL = p.gamma * eL;
+    const float sR = sqrtf(fmaxf(0.f, (p.cut - gR * eR) * p.inva));
+    const float sL = sqrtf(fmaxf(0.f, (p.cut - gL * eL) * p.inva));
+    const float xhi = p.u + (sR - p.beta * eR) + 1e-3f;
+    const float xlo = p.u - (sL + p.beta * eL) - 1e-3f;
+    if (!(xlo <= (float)cam.width - 0.5f && xhi >= 0.5f)) return false;
+    // cell cx spans pixel centres [cx cw + 0.5, (cx + 1) cw - 0.5]
+    const float icw = 1.f / (float)cw;
+    const float flo = fmaxf(ceilf((xlo + 0.5f) * icw - 1.f), (float)x0);
+    const float fhi = fminf(floorf((xhi - 0.5f) * icw), (float)x1);
+    if (!(flo <= fhi)) return false;
+    lo = (int)flo;
+    hi = (int)fhi;
+    return true;
+}
+
+// With culling, the kept cells of a rectangle of at most CULL_MAX cells
+// travel from the classification to the duplication as a bit mask (bit j:
+// cell j, row-major); larger rectangles have their rows recomputed.
+// Rectangles of at least COOP_MIN cells are emitted by a whole wave.
 constexpr uint32_t CULL_MAX = 64;
 constexpr uint32_t COOP_MIN = 16;
 // Key of an emitted slot the duplication could not fill: past every cell,
@@ -197,13 +262,12 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 
 // Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
 // to view v.  Writes the sorted record copy (radius in B.w, record id bits in
-// C.w), the wide flag, the number of list entries (tiles or regions, after
-// culling) and the cull mask of every position, and per workgroup the number
-// of wide records and of their region entries (part[b], part[nb + b]).
+// C.w), the wide flag and the number of list entries (tiles or regions, after
+// culling) of every position, and per workgroup the number of wide records
+// and of their region entries (part[b], part[nb + b]).
 __global__ void __launch_bounds__(256) permute_classify_kernel(
     const uint32_t* __restrict__ order, const float4* __restrict__ rec, int64_t R, int64_t n, ViewSet views,
-    DevSettings st,
-    uint32_t* __restrict__ cnt_out, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
+    DevSettings st, uint32_t* __restrict__ cnt_out, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
     float4* __restrict__ srec, uint32_t* __restrict__ part) {
     __shared__ uint32_t s_part[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -230,41 +294,23 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     }
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
     if (live && c > 0) cl = cells_of(A, B, wide, views.v[vi], st);
-    const bool cull = st.tile_cull && cl.area > 0;
+    uint32_t cnt = cl.area;
     uint64_t mask = 0;
-    uint32_t cnt = cull ? 0u : cl.area;
-    if (cull && cl.area < COOP_MIN) {
+    if (st.tile_cull && cl.area > 0) {
+        const RowCull rc = row_prep(A, B, st);
         const DevView& cam = views.v[vi];
-        const TouchPrep tp = touch_prep(A, B, st);
-        for (uint32_t j = 0; j < cl.area; ++j) {
-            const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
-            if (touch_test(tp, cell_box(cl.x0 + (int)rx, cl.y0 + (int)ry, cl.cw, cl.ch, cam))) mask |= 1ull << j;
-        }
-        cnt = (uint32_t)__popcll(mask);
-    }
-    uint64_t pending = __ballot(cull && cl.area >= COOP_MIN);
-    while (pending) {
-        const int src = __ffsll((long long)pending) - 1;
-        pending &= pending - 1;
-        const float4 bA = shfl4(A, src), bB = shfl4(B, src);
-        const uint32_t barea = __shfl(cl.area, src);
-        const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
-        const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
-        const DevView& cam = views.v[bvi];
-        uint32_t total = 0;
-        for (uint32_t j0 = 0; j0 < barea; j0 += 64) {
-            const uint32_t j = j0 + (uint32_t)lane;
-            bool pass = false;
-            if (j < barea) {
-                const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
-                const TileBox box = cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam);
-                pass = barea <= CULL_MAX ? touch_test(touch_prep(bA, bB, st), box) : cell_touch(bA, bB, box, st);
+        const int rows = (int)(cl.area / (uint32_t)cl.w);
+        cnt = 0;
+        for (int ry = 0; ry < rows; ++ry) {
+            int lo, hi;
+            if (!row_cells(rc, cl.y0 + ry, cl.cw, cl.ch, cl.x0, cl.x0 + cl.w - 1, cam, lo, hi)) continue;
+            cnt += (uint32_t)(hi - lo + 1);
+            if (cl.area <= CULL_MAX) {
+                // bits ry w + (lo - x0) .. ry w + (hi - x0)
+                const uint32_t b0 = (uint32_t)(ry * cl.w + (lo - cl.x0)), nb = (uint32_t)(hi - lo + 1);
+                mask |= (nb >= 64 ? ~0ull : ((1ull << nb) - 1ull)) << b0;
             }
-            const uint64_t bal = __ballot(pass);
-            total += (uint32_t)__popcll(bal);
-            if (lane == src && barea <= CULL_MAX) mask = bal;
         }
-        if (lane == src) cnt = total;
     }
     if (live) {
         cnt_out[i] = cnt;
@@ -324,22 +370,22 @@ __global__ void __launch_bounds__(1024) sum_parts_kernel(const uint32_t* __restr
 }
 
 // List entries in sorted-position order: cell keys (tile or region ids) as
-// keys, positions as values, for the cells the classification counted.
-// Writes never leave the record's counted slots; a slot the emission does
-// not fill gets KEY_NONE.
+// keys, positions as values, for the cells the classification counted (the
+// same row intervals).  Writes never leave the record's counted slots; a
+// slot the emission does not fill gets KEY_NONE.
 __global__ void __launch_bounds__(256) duplicate_kernel(
     const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
     const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views,
-    DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
-    uint32_t* __restrict__ flags) {
+    DevSettings st,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
-    uint64_t mask = ~0ull;
     int64_t off = 0;
     uint32_t cnt = 0;
     int vi = 0;
-    bool cull = false, wide = false;
+    bool wide = false;
+    uint64_t mask = ~0ull;
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
     if (i < R && (cnt = cnt_sorted[i]) != 0) {
         off = offsets[i];
@@ -348,18 +394,17 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         A = srec[3 * i];
         B = srec[3 * i + 1];
         cl = cells_of(A, B, wide, views.v[vi], st);
-        cull = st.tile_cull && cl.area > 0;
-        if (cull && cl.area <= CULL_MAX) mask = tmask[i];
     }
+    const bool cull = st.tile_cull != 0;
+    if (cull && cnt > 0 && cl.area <= CULL_MAX) mask = tmask[i];
     bool overflow = false;
-    const bool coop = cl.area >= COOP_MIN;
-    if (!coop && cl.area) {
+    if (cnt > 0 && cl.area < COOP_MIN) {
+        // the cells to emit: the set bits of the mask (all cells without culling)
         const DevView& cam = views.v[vi];
         int64_t o = off;
         const int64_t end = off + cnt;
-        // the cells to emit: the set bits of the mask (all cells without culling)
-        uint64_t todo = cull ? mask : (cl.area >= 64 ? ~0ull : (1ull << cl.area) - 1ull);
-        for (; todo && o < end; todo &= todo - 1ull) {
+        uint64_t todo = cull ? mask : (1ull << cl.area) - 1ull;
+        for (; todo && o < end; todo &= todo - 1ull, ++o) {
             const uint32_t j = (uint32_t)(__ffsll((long long)todo) - 1);
             const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
             if (o < capacity) {
@@ -368,7 +413,6 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
             } else {
                 overflow = true;
             }
-            ++o;
         }
         for (; o < end; ++o) {
             if (o < capacity) {
@@ -379,7 +423,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
             }
         }
     }
-    uint64_t pending = __ballot(coop);
+    uint64_t pending = __ballot(cnt > 0 && cl.area >= COOP_MIN);
     while (pending) {
         const int src = __ffsll((long long)pending) - 1;
         pending &= pending - 1;
@@ -387,36 +431,61 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)i, src);
         const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
         const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
-        const bool bcull = __shfl((int)cull, src) != 0, bwide = __shfl((int)wide, src) != 0;
+        const bool bwide = __shfl((int)wide, src) != 0;
         const uint64_t bmask = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mask >> 32), src) << 32) |
                                (uint64_t)(uint32_t)__shfl((int)(uint32_t)mask, src);
-        const bool retest = bcull && barea > CULL_MAX;
-        const float4 bA = shfl4(A, src), bB = shfl4(B, src);
         const int64_t bo = __shfl(off, src);
         const int64_t end = bo + bcnt;
         const DevView& cam = views.v[bvi];
         int64_t base = bo;
-        for (uint32_t j0 = 0; j0 < barea && base < end; j0 += 64) {
-            const uint32_t j = j0 + (uint32_t)lane;
-            const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
-            bool take = j < barea;
-            if (take && bcull) {
-                take = retest ? cell_touch(bA, bB, cell_box(bx0 + (int)rx, by0 + (int)ry, bcw, bch, cam), st)
-                              : ((bmask >> (j & 63u)) & 1ull) != 0;
+        if (!cull || barea <= CULL_MAX) {
+            // every cell, or the cells of the mask, 64 at a time
+            for (uint32_t j0 = 0; j0 < barea && base < end; j0 += 64) {
+                const uint32_t j = j0 + (uint32_t)lane;
+                const bool take = j < barea && (!cull || ((bmask >> (j & 63u)) & 1ull));
+                const uint64_t bal = __ballot(take);
+                if (take) {
+                    const int64_t o = base + __popcll(bal & lanemask_lt());
+                    const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
+                    if (o < end) {
+                        if (o < capacity) {
+                            keys[o] = cell_key(bwide, bx0 + (int)rx, by0 + (int)ry, cam, views);
+                            vals[o] = bi;
+                        } else {
+                            overflow = true;
+                        }
+                    }
+                }
+                base += __popcll(bal);
             }
-            const uint64_t bal = __ballot(take);
-            if (take) {
-                const int64_t o = base + __popcll(bal & lanemask_lt());
-                if (o < end) {
+        } else {
+            // large rectangles: the rows again, one row per lane; each row
+            // is a contiguous run of cells, placed by a prefix sum over lanes
+            const RowCull rc = row_prep(shfl4(A, src), shfl4(B, src), st);
+            const int rows = (int)(barea / (uint32_t)bw);
+            for (int r0 = 0; r0 < rows && base < end; r0 += 64) {
+                const int ry = r0 + lane;
+                int lo = 0, hi = -1;
+                if (ry < rows && !row_cells(rc, by0 + ry, bcw, bch, bx0, bx0 + bw - 1, cam, lo, hi)) hi = lo - 1;
+                if (ry >= rows) hi = lo - 1;
+                const int nrow = hi - lo + 1;
+                int incl = nrow;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int y = __shfl_up(incl, d);
+                    if (lane >= d) incl += y;
+                }
+                int64_t o = base + (incl - nrow);
+                for (int cx = lo; cx <= hi && o < end; ++cx, ++o) {
                     if (o < capacity) {
-                        keys[o] = cell_key(bwide, bx0 + (int)rx, by0 + (int)ry, cam, views);
+                        keys[o] = cell_key(bwide, cx, by0 + ry, cam, views);
                         vals[o] = bi;
                     } else {
                         overflow = true;
                     }
                 }
+                base += __shfl(incl, 63);
             }
-            base += __popcll(bal);
         }
         for (int64_t o = base + lane; o < end; o += 64) {
             if (o < capacity) {
