@@ -3,7 +3,8 @@ the change of basis between the conic gradient the oracle reports (w.r.t. the
 inverse covariance entries A, B, C of Q = A dx^2 + 2 B dx dy + C dy^2) and the
 one the kernels accumulate (w.r.t. the stored a = A, beta = B / A,
 gamma = C - B^2 / A).  Pinned by central finite differences of a smooth test
-function, not by re-deriving the chain rule."""
+function, not by re-deriving the chain rule.  Also the closed form of the
+row interval the binning's culling evaluates, against dense sampling."""
 import numpy as np
 
 from tests import gpu_util as U
@@ -62,3 +63,50 @@ def test_conic_gradient_bases_round_trip():
     A, B, C = con.T
     back = U.dabc_from_dstable(con, U.dstable_from_dabc(A, B / A, d))
     assert np.allclose(back, d, rtol=1e-9, atol=1e-9 * np.abs(d).max())
+
+
+def _row_interval(u, v, a, beta, gamma, cut, y0, y1):
+    """x-extent of {a (ex + beta ey)^2 + gamma ey^2 <= cut} within the band
+    of rows y0 <= y <= y1 (ex = x - u, ey = y - v): the rightmost point of the
+    ellipse, at ey = -beta sqrt(cut a / (gamma c)) with c = gamma + a beta^2,
+    clamped to the band bounds the right end, its mirror the left one.  The
+    binning kernels evaluate this interval per cell row."""
+    H = np.sqrt(cut / gamma)
+    ey_r = -beta * np.sqrt(cut * a / (gamma * (gamma + a * beta * beta)))
+    e0, e1 = max(y0 - v, -H), min(y1 - v, H)
+    if e0 > e1:
+        return None
+    er, el = min(max(ey_r, e0), e1), min(max(-ey_r, e0), e1)
+    sr = np.sqrt(max(0.0, (cut - gamma * er * er) / a))
+    sl = np.sqrt(max(0.0, (cut - gamma * el * el) / a))
+    return u - (sl + beta * el), u + (sr - beta * er)
+
+
+def test_row_interval_bounds_the_ellipse_slice():
+    """Against a dense sampling of the band: the interval holds every sampled
+    point of the slice and is no wider than the sampling resolution."""
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        l1, l2 = 10.0 ** rng.uniform(-1, 3, 2)
+        th = rng.uniform(0, np.pi)
+        c, s = np.cos(th), np.sin(th)
+        cov = np.array([[l1 * c * c + l2 * s * s, (l1 - l2) * c * s], [(l1 - l2) * c * s, l1 * s * s + l2 * c * c]])
+        A, B, C = np.linalg.inv(cov)[[0, 0, 1], [0, 1, 1]]
+        u, v = rng.uniform(-50, 150, 2)
+        y0 = rng.uniform(0, 100)
+        y1 = y0 + rng.uniform(0, 30)
+        iv = _row_interval(u, v, A, B / A, C - B * B / A, 9.0, y0, y1)
+        half = 3.0 * np.sqrt(cov[0, 0]) + 5.0
+        xs = np.linspace(u - half, u + half, 1500)
+        ys = np.linspace(y0, y1, 80)
+        X, Y = np.meshgrid(xs, ys)
+        ex, ey = X - u, Y - v
+        inside = A * ex * ex + 2 * B * ex * ey + C * ey * ey <= 9.0
+        if not inside.any():
+            continue
+        assert iv is not None
+        step = xs[1] - xs[0]
+        xmin, xmax = X[inside].min(), X[inside].max()
+        assert iv[0] <= xmin + 1e-9 * abs(xmin) and iv[1] >= xmax - 1e-9 * abs(xmax)
+        span = xmax - xmin + 1.0
+        assert iv[0] >= xmin - 2 * step - 0.05 * span and iv[1] <= xmax + 2 * step + 0.05 * span
