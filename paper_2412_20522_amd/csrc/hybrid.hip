@@ -249,9 +249,7 @@ __device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int 
 // With culling, the kept cells of a rectangle of at most CULL_MAX cells
 // travel from the classification to the duplication as a bit mask (bit j:
 // cell j, row-major); larger rectangles have their rows recomputed.
-// Rectangles of at least COOP_MIN cells are emitted by a whole wave.
 constexpr uint32_t CULL_MAX = 64;
-constexpr uint32_t COOP_MIN = 16;
 // Key of an emitted slot the duplication could not fill: past every cell,
 // so it sorts last and no range includes it.
 constexpr uint32_t KEY_NONE = 0xffffffffu;
@@ -369,23 +367,58 @@ __global__ void __launch_bounds__(1024) sum_parts_kernel(const uint32_t* __restr
     }
 }
 
+// Position of the r-th (0-based) set bit of m; r < popcount(m).
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t r) {
+    uint32_t pos = 0;
+    uint32_t x = (uint32_t)m;
+    uint32_t c = (uint32_t)__popc(x);
+    if (r >= c) {
+        r -= c;
+        x = (uint32_t)(m >> 32);
+        pos = 32;
+    }
+#pragma unroll
+    for (int sh = 16; sh >= 1; sh >>= 1) {
+        c = (uint32_t)__popc(x & ((1u << sh) - 1u));
+        if (r >= c) {
+            r -= c;
+            x >>= sh;
+            pos += (uint32_t)sh;
+        }
+    }
+    return pos;
+}
+
 // List entries in sorted-position order: cell keys (tile or region ids) as
-// keys, positions as values, for the cells the classification counted (the
-// same row intervals).  Writes never leave the record's counted slots; a
-// slot the emission does not fill gets KEY_NONE.
+// keys, positions as values, for the cells the classification counted.  The
+// outputs of a workgroup's records are contiguous, so the workgroup walks
+// them slot by slot with every lane busy and consecutive lanes writing
+// consecutive entries: slot -> record by binary search over the workgroup's
+// prefix of counts, record-local rank -> cell by selecting the rank-th bit of
+// the cull mask (the rank itself without culling).  Culled rectangles of more
+// than CULL_MAX cells re-derive their rows, one row per lane.  Writes never
+// leave a record's counted slots; a slot the emission does not fill gets
+// KEY_NONE.
 __global__ void __launch_bounds__(256) duplicate_kernel(
     const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
     const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views,
-    DevSettings st,
-    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
+    uint32_t* __restrict__ flags) {
+    __shared__ uint32_t s_pref[257];
+    __shared__ uint32_t s_rel[256];
+    __shared__ unsigned long long s_mask[256];
+    __shared__ uint2 s_geo[256];
+    __shared__ uint32_t s_wsum[4];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t i = i0 + t;
     const int lane = lane_id();
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
     int64_t off = 0;
     uint32_t cnt = 0;
     int vi = 0;
     bool wide = false;
-    uint64_t mask = ~0ull;
+    uint64_t mask = 0;
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
     if (i < R && (cnt = cnt_sorted[i]) != 0) {
         off = offsets[i];
@@ -397,33 +430,64 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     }
     const bool cull = st.tile_cull != 0;
     if (cull && cnt > 0 && cl.area <= CULL_MAX) mask = tmask[i];
+    const bool flat = cnt > 0 && (!cull || cl.area <= CULL_MAX);
+    const int64_t base = offsets[i0];  // start of the workgroup's output (i0 < R)
     bool overflow = false;
-    if (cnt > 0 && cl.area < COOP_MIN) {
-        // the cells to emit: the set bits of the mask (all cells without culling)
-        const DevView& cam = views.v[vi];
-        int64_t o = off;
-        const int64_t end = off + cnt;
-        uint64_t todo = cull ? mask : (1ull << cl.area) - 1ull;
-        for (; todo && o < end; todo &= todo - 1ull, ++o) {
-            const uint32_t j = (uint32_t)(__ffsll((long long)todo) - 1);
-            const uint32_t ry = j / (uint32_t)cl.w, rx = j - ry * (uint32_t)cl.w;
-            if (o < capacity) {
-                keys[o] = cell_key(wide, cl.x0 + (int)rx, cl.y0 + (int)ry, cam, views);
-                vals[o] = (uint32_t)i;
-            } else {
-                overflow = true;
-            }
+    {
+        uint32_t x = flat ? cnt : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
         }
-        for (; o < end; ++o) {
+        const int wid = t >> 6;
+        if (lane == 63) s_wsum[wid] = x;
+        s_rel[t] = (uint32_t)(off - base);
+        s_mask[t] = mask;
+        s_geo[t] = make_uint2((uint32_t)cl.x0 | ((uint32_t)cl.y0 << 16),
+                              (uint32_t)cl.w | (wide ? 0x1000u : 0u) | ((uint32_t)vi << 16));
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            if (w < wid) before += s_wsum[w];
+            total += s_wsum[w];
+        }
+        s_pref[t] = before + x - (flat ? cnt : 0u);
+        if (t == 0) s_pref[blockDim.x] = total;
+        __syncthreads();
+        const int nrec = (int)blockDim.x;
+        for (uint32_t e = (uint32_t)t; e < total; e += blockDim.x) {
+            int lo = 0, hi = nrec;  // owner k: s_pref[k] <= e < s_pref[k + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pref[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            const int k = lo;
+            const uint32_t r = e - s_pref[k];
+            const uint2 g = s_geo[k];
+            const int w = (int)(g.y & 0xfffu), kvi = (int)(g.y >> 16);
+            const bool kwide = (g.y & 0x1000u) != 0;
+            const uint64_t km = s_mask[k];
+            const int64_t o = base + (int64_t)s_rel[k] + (int64_t)r;
+            uint32_t key = KEY_NONE;
+            if (!cull || r < (uint32_t)__popcll(km)) {
+                const uint32_t j = cull ? select_bit(km, r) : r;
+                const uint32_t ry = j / (uint32_t)w, rx = j - ry * (uint32_t)w;
+                key = cell_key(kwide, (int)(g.x & 0xffffu) + (int)rx, (int)(g.x >> 16) + (int)ry, views.v[kvi],
+                               views);
+            }
             if (o < capacity) {
-                keys[o] = KEY_NONE;
-                vals[o] = 0u;
+                keys[o] = key;
+                vals[o] = key == KEY_NONE ? 0u : (uint32_t)(i0 + k);
             } else {
                 overflow = true;
             }
         }
     }
-    uint64_t pending = __ballot(cnt > 0 && cl.area >= COOP_MIN);
+    // culled rectangles of more than CULL_MAX cells: the rows again, one row
+    // per lane; each row is a contiguous run of cells placed by a prefix sum
+    uint64_t pending = __ballot(cnt > 0 && !flat);
     while (pending) {
         const int src = __ffsll((long long)pending) - 1;
         pending &= pending - 1;
@@ -432,62 +496,36 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
         const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
         const bool bwide = __shfl((int)wide, src) != 0;
-        const uint64_t bmask = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mask >> 32), src) << 32) |
-                               (uint64_t)(uint32_t)__shfl((int)(uint32_t)mask, src);
         const int64_t bo = __shfl(off, src);
         const int64_t end = bo + bcnt;
         const DevView& cam = views.v[bvi];
-        int64_t base = bo;
-        if (!cull || barea <= CULL_MAX) {
-            // every cell, or the cells of the mask, 64 at a time
-            for (uint32_t j0 = 0; j0 < barea && base < end; j0 += 64) {
-                const uint32_t j = j0 + (uint32_t)lane;
-                const bool take = j < barea && (!cull || ((bmask >> (j & 63u)) & 1ull));
-                const uint64_t bal = __ballot(take);
-                if (take) {
-                    const int64_t o = base + __popcll(bal & lanemask_lt());
-                    const uint32_t ry = j / (uint32_t)bw, rx = j - ry * (uint32_t)bw;
-                    if (o < end) {
-                        if (o < capacity) {
-                            keys[o] = cell_key(bwide, bx0 + (int)rx, by0 + (int)ry, cam, views);
-                            vals[o] = bi;
-                        } else {
-                            overflow = true;
-                        }
-                    }
-                }
-                base += __popcll(bal);
-            }
-        } else {
-            // large rectangles: the rows again, one row per lane; each row
-            // is a contiguous run of cells, placed by a prefix sum over lanes
-            const RowCull rc = row_prep(shfl4(A, src), shfl4(B, src), st);
-            const int rows = (int)(barea / (uint32_t)bw);
-            for (int r0 = 0; r0 < rows && base < end; r0 += 64) {
-                const int ry = r0 + lane;
-                int lo = 0, hi = -1;
-                if (ry < rows && !row_cells(rc, by0 + ry, bcw, bch, bx0, bx0 + bw - 1, cam, lo, hi)) hi = lo - 1;
-                if (ry >= rows) hi = lo - 1;
-                const int nrow = hi - lo + 1;
-                int incl = nrow;
+        const RowCull rc = row_prep(shfl4(A, src), shfl4(B, src), st);
+        const int rows = (int)(barea / (uint32_t)bw);
+        int64_t rbase = bo;
+        for (int r0 = 0; r0 < rows && rbase < end; r0 += 64) {
+            const int ry = r0 + lane;
+            int lo = 0, hi = -1;
+            if (ry < rows && !row_cells(rc, by0 + ry, bcw, bch, bx0, bx0 + bw - 1, cam, lo, hi)) hi = lo - 1;
+            if (ry >= rows) hi = lo - 1;
+            const int nrow = hi - lo + 1;
+            int incl = nrow;
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int y = __shfl_up(incl, d);
-                    if (lane >= d) incl += y;
-                }
-                int64_t o = base + (incl - nrow);
-                for (int cx = lo; cx <= hi && o < end; ++cx, ++o) {
-                    if (o < capacity) {
-                        keys[o] = cell_key(bwide, cx, by0 + ry, cam, views);
-                        vals[o] = bi;
-                    } else {
-                        overflow = true;
-                    }
-                }
-                base += __shfl(incl, 63);
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d);
+                if (lane >= d) incl += y;
             }
+            int64_t o = rbase + (incl - nrow);
+            for (int cx = lo; cx <= hi && o < end; ++cx, ++o) {
+                if (o < capacity) {
+                    keys[o] = cell_key(bwide, cx, by0 + ry, cam, views);
+                    vals[o] = bi;
+                } else {
+                    overflow = true;
+                }
+            }
+            rbase += __shfl(incl, 63);
         }
-        for (int64_t o = base + lane; o < end; o += 64) {
+        for (int64_t o = rbase + lane; o < end; o += 64) {
             if (o < capacity) {
                 keys[o] = KEY_NONE;
                 vals[o] = 0u;
