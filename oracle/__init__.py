@@ -321,6 +321,18 @@ def sample_masks(scores, tau: float, seed: int, step: int, return_noise: bool = 
     return (m, y, g) if return_noise else (m, y)
 
 
+def prune_keep(scores, seed: int, step0: int, n_draws: int = 10):
+    """Probabilistic pruning (Sec. 3.5, training and pruning): every Gaussian
+    draws n_draws hard masks -- the draws of sample_masks at steps step0 ..
+    step0 + n_draws - 1 -- and survives iff at least one of them is 1."""
+    n = _f64(scores).reshape(-1, 2).shape[0]
+    keep = np.zeros(n, bool)
+    for d in range(n_draws):
+        m, _ = sample_masks(scores, 1.0, seed, step0 + d)
+        keep |= m > 0.5
+    return keep
+
+
 def mask_grad(d_mask, m_hard, y_soft, tau: float, lambda_m: float):
     n = len(m_hard)
     d = np.zeros((n, 2))

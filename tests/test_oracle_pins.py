@@ -520,6 +520,34 @@ def test_gumbel_frequency_matches_sigmoid(orc):
         assert abs(hits / N - p) <= 5 * math.sqrt(p * (1 - p) / N)
 
 
+def test_prune_keep_rate_matches_closed_form(orc):
+    """Sec. 3.5: a Gaussian survives unless all n_draws independent hard draws
+    are 0, so P(keep) = 1 - (1 - sigmoid(s0 - s1))^n_draws; checked within a
+    5-sigma binomial bound, with the draws' independence across steps implied."""
+    n = 200_000
+    for ell, draws in ((-3.0, 10), (-1.0, 10), (0.5, 3), (-2.0, 1)):
+        scores = np.zeros((n, 2), np.float32)
+        scores[:, 0] = ell
+        keep = orc.prune_keep(scores, seed=77, step0=1000, n_draws=draws)
+        p = 1 / (1 + math.exp(-float(np.float32(ell))))
+        q = 1 - (1 - p) ** draws
+        assert abs(keep.mean() - q) <= 5 * math.sqrt(q * (1 - q) / n)
+
+
+def test_prune_keep_limits_and_single_draw(orc):
+    """A Gaussian whose "exists" score dominates by far is always kept, one
+    dominated by far never; with one draw, keep equals that step's hard mask."""
+    scores = np.zeros((1000, 2), np.float32)
+    scores[:500, 0] = 60.0
+    scores[500:, 1] = 60.0
+    keep = orc.prune_keep(scores, seed=5, step0=0, n_draws=10)
+    assert keep[:500].all() and not keep[500:].any()
+    rng = np.random.default_rng(4)
+    sc = rng.normal(size=(5000, 2)).astype(np.float32)
+    m, _ = orc.sample_masks(sc, 0.5, seed=9, step=42)
+    assert np.array_equal(orc.prune_keep(sc, seed=9, step0=42, n_draws=1), m > 0.5)
+
+
 def test_gumbel_noise_is_standard_gumbel(orc):
     scores = np.zeros((400_000, 2), np.float32)
     _, _, g = orc.sample_masks(scores, 1.0, seed=99, step=3, return_noise=True)
