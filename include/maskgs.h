@@ -435,6 +435,26 @@ MGS_API mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d
                                  const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores,
                                  float* loss_m, void* scratch);
 
+/* Probabilistic pruning (Sec. 3.5, training and pruning): every Gaussian
+ * draws n_draws (>= 1; 10 in the paper) hard masks with the rule of
+ * mgs_sample_masks, at steps step0 .. step0 + n_draws - 1, and is kept iff at
+ * least one draw is 1.  scores [n, 2] (8-byte aligned); keep [n] u32 (0/1,
+ * device, caller-owned).  Asynchronous. */
+MGS_API mgs_status mgs_prune_sample(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, uint64_t seed,
+                                    uint64_t step0, int n_draws, uint32_t* keep);
+
+/* Removal of the pruned Gaussians from every per-Gaussian array (parameters,
+ * scores, optimiser state; Sec. 3.5): stable compaction of the rows with
+ * keep[i] != 0.  n_arrays arrays, host arrays of device pointers in[a] and
+ * out[a] (distinct, caller-owned, out[a] holding at least as many rows as
+ * are kept) with widths[a] (>= 1) floats per row.  n_kept (device, one u64,
+ * optional) receives the number of kept rows.  scratch (device) holds
+ * mgs_compact_scratch_bytes(n) bytes.  Asynchronous, no allocation. */
+MGS_API size_t mgs_compact_scratch_bytes(int64_t n);
+MGS_API mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* keep, int64_t n, int n_arrays,
+                                    const float* const* in, float* const* out, const int* widths, uint64_t* n_kept,
+                                    void* scratch);
+
 /* L1 rendering loss over m elements (mean |image - target|, sign(0) = 0):
  * d_images [m] = sign(image - target) / m; loss (device, one float,
  * optional).  scratch holds mgs_reduce_scratch_bytes(m) bytes. */

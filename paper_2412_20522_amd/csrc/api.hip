@@ -1019,6 +1019,47 @@ mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores
 
 size_t mgs_reduce_scratch_bytes(int64_t n) { return reduce_scratch_bytes(n); }
 
+mgs_status mgs_prune_sample(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, uint64_t seed,
+                            uint64_t step0, int n_draws, uint32_t* keep) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (n_draws < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "n_draws must be >= 1");
+    if (n > 0 && (!scores || !keep)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "scores must be 8-byte aligned");
+    launch_prune_sample((hipStream_t)stream, scores, n, seed, step0, n_draws, keep);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+size_t mgs_compact_scratch_bytes(int64_t n) {
+    return ((size_t)(n > 0 ? n : 1) * 4 + 255) / 256 * 256 + scan_scratch_bytes(n);
+}
+
+mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* keep, int64_t n, int n_arrays,
+                            const float* const* in, float* const* out, const int* widths, uint64_t* n_kept,
+                            void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0 || n_arrays < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "negative size");
+    if (n_arrays > 0 && (!in || !out || !widths)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (n > 0 && (!keep || !scratch)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    for (int a = 0; a < n_arrays; ++a) {
+        if (widths[a] < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "width of array %d must be >= 1", a);
+        if (n > 0 && (!in[a] || !out[a])) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL array %d", a);
+        if (n > 0 && in[a] == out[a]) return fail(ctx, MGS_ERR_INVALID_ARG, "array %d compacts in place", a);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t* pos = reinterpret_cast<uint32_t*>(scratch);
+    char* scan_tmp = reinterpret_cast<char*>(scratch) + ((size_t)(n > 0 ? n : 1) * 4 + 255) / 256 * 256;
+    if (n > 0) {
+        launch_scan_u32(st, keep, n, pos, n_kept, scan_tmp);
+        for (int a = 0; a < n_arrays; ++a) launch_compact_rows(st, keep, pos, n, widths[a], in[a], out[a]);
+    } else if (n_kept) {
+        launch_fill_u32(st, reinterpret_cast<uint32_t*>(n_kept), 2, 0u);
+    }
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
 mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
                          const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores, float* loss_m,
                          void* scratch) {

@@ -1,5 +1,6 @@
-// Mask sampling and mask gradient (Sec. 3.3, Eq. 7-8), L1 rendering loss
-// and Adam on gfx950.
+// Mask sampling and mask gradient (Sec. 3.3, Eq. 7-8), probabilistic
+// pruning and row compaction (Sec. 3.5), L1 rendering loss and Adam on
+// gfx950.
 //
 // Masks: two scores per Gaussian, Gumbel-Softmax with a hard forward value
 // and the soft sample's derivative in the backward (straight-through).  The
@@ -51,6 +52,41 @@ __global__ void __launch_bounds__(RNT) sample_masks_kernel(const float* __restri
     const double z1 = (double)s.y + gumbel_from_bits(c1);
     m_hard[i] = z0 > z1 ? 1.f : 0.f;
     y_soft[i] = (float)(1.0 / (1.0 + exp(-(z0 - z1) / (double)tau)));
+}
+
+// Probabilistic pruning (Sec. 3.5): n_draws hard masks per Gaussian with the
+// rule above (steps step0 .. step0 + n_draws - 1); keep[i] = 1 iff any is 1.
+__global__ void __launch_bounds__(RNT) prune_sample_kernel(const float* __restrict__ scores, int64_t n,
+                                                            uint64_t seed, uint64_t step0, int n_draws,
+                                                            uint32_t* __restrict__ keep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 s = reinterpret_cast<const float2*>(scores)[i];
+    uint32_t k = 0;
+    for (int d = 0; d < n_draws && !k; ++d) {
+        const uint64_t step = step0 + (uint64_t)d;
+        uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32), c2 = (uint32_t)step,
+                 c3 = (uint32_t)(step >> 32);
+        philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double z0 = (double)s.x + gumbel_from_bits(c0);
+        const double z1 = (double)s.y + gumbel_from_bits(c1);
+        k = z0 > z1 ? 1u : 0u;
+    }
+    keep[i] = k;
+}
+
+// Stable compaction of one per-Gaussian array of `width` floats per row:
+// row i goes to row pos[i] (exclusive scan of keep) when keep[i] != 0.  One
+// thread per element: reads are coalesced, writes contiguous within the
+// kept rows.
+__global__ void __launch_bounds__(RNT) compact_rows_kernel(const uint32_t* __restrict__ keep,
+                                                            const uint32_t* __restrict__ pos, int64_t n, int width,
+                                                            const float* __restrict__ in, float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * width) return;
+    const int64_t i = e / width;
+    if (!keep[i]) return;
+    out[(int64_t)pos[i] * width + (e - i * width)] = in[e];
 }
 
 // Deterministic two-level sums in double.
@@ -131,6 +167,21 @@ void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, flo
     if (n == 0) return;
     hipLaunchKernelGGL(sample_masks_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores, n,
                        tau, seed, step, m_hard, y_soft);
+}
+
+void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uint64_t seed, uint64_t step0,
+                         int n_draws, uint32_t* keep) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(prune_sample_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores, n,
+                       seed, step0, n_draws, keep);
+}
+
+void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int width,
+                         const float* in, float* out) {
+    const int64_t m = n * (int64_t)width;
+    if (m == 0) return;
+    hipLaunchKernelGGL(compact_rows_kernel, dim3((unsigned)((m + RNT - 1) / RNT)), dim3(RNT), 0, stream, keep, pos,
+                       n, width, in, out);
 }
 
 void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,

@@ -114,6 +114,9 @@ _SIGS = {
                                        C.POINTER(mgs_settings), _VP, C.POINTER(mgs_gradients)]),
     "mgs_sample_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _U64, _U64, _VP, _VP]),
     "mgs_reduce_scratch_bytes": (_SZ, [_I64]),
+    "mgs_prune_sample": (C.c_int, [_VP, _VP, _VP, _I64, _U64, _U64, C.c_int, _VP]),
+    "mgs_compact_scratch_bytes": (_SZ, [_I64]),
+    "mgs_compact_rows": (C.c_int, [_VP, _VP, _VP, _I64, C.c_int, _VP, _VP, _VP, _VP, _VP]),
     "mgs_mask_grad": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _VP, _VP, _VP]),
     "mgs_l1_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP, _VP]),
     "mgs_adam_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _F, _F, _I64]),
@@ -398,6 +401,36 @@ def mgs_project_backward(ctx, g: mgs_gaussians, cams, st, d_rec, grads: mgs_grad
 def mgs_sample_masks(ctx, scores, tau: float, seed: int, step: int, m_hard, y_soft, stream=None) -> None:
     _check(ctx, _lib.mgs_sample_masks(ctx, _stream(stream), _ptr(scores, name="scores"), scores.shape[0], tau,
                                       seed, step, _ptr(m_hard, name="m_hard"), _ptr(y_soft, name="y_soft")))
+
+
+def mgs_prune_sample(ctx, scores, seed: int, step0: int, n_draws: int, keep, stream=None) -> None:
+    """keep [n] int32 (0/1): Gaussians with at least one of n_draws hard masks."""
+    _check(ctx, _lib.mgs_prune_sample(ctx, _stream(stream), _ptr(scores, name="scores"), scores.shape[0], seed,
+                                      step0, n_draws, _ptr(keep, torch.int32, "keep")))
+
+
+def mgs_compact_rows(ctx, keep, ins, outs, n_kept=None, scratch=None, stream=None) -> None:
+    """Stable compaction of the rows of every tensor in `ins` (leading size n,
+    float32, contiguous) with keep != 0 into the matching tensor of `outs`;
+    n_kept (int64 device scalar, optional) receives the number kept."""
+    n = keep.numel()
+    if len(ins) != len(outs):
+        raise ValueError("ins and outs differ in length")
+    widths = []
+    for a, b in zip(ins, outs):
+        if a.shape[0] != n:
+            raise ValueError("every array needs one row per Gaussian")
+        widths.append(max(a.numel() // max(n, 1), 1))
+        if b.numel() < a.numel():
+            raise ValueError("an output array is smaller than its input")
+    if scratch is None:
+        scratch = torch.empty(int(_lib.mgs_compact_scratch_bytes(n)), dtype=torch.uint8, device=keep.device)
+    k = len(ins)
+    pin = (C.c_void_p * max(k, 1))(*[_ptr(a, name="in") for a in ins])
+    pout = (C.c_void_p * max(k, 1))(*[_ptr(b, name="out") for b in outs])
+    pw = (C.c_int * max(k, 1))(*widths)
+    _check(ctx, _lib.mgs_compact_rows(ctx, _stream(stream), _ptr(keep, torch.int32, "keep"), n, k, pin, pout, pw,
+                                      _ptr(n_kept, torch.int64, "n_kept"), _ptr(scratch, torch.uint8, "scratch")))
 
 
 def mgs_mask_grad(ctx, d_masks, m_hard, y_soft, tau: float, lambda_m: float, d_scores, loss_m=None,

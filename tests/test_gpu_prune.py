@@ -1,0 +1,99 @@
+"""Probabilistic pruning (Sec. 3.5) through the C ABI: the keep mask bit for
+bit against the oracle, the row compaction against boolean indexing, and the
+invariance that removing Gaussians whose mask is 0 leaves the rendering
+unchanged bit for bit (Eq. 3-4: a masked Gaussian neither adds colour nor
+attenuates transmittance) while the survivors' gradients agree."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return U.M().mgs_create(0)
+
+
+@pytest.mark.parametrize("n,draws", [(0, 10), (1, 10), (4097, 1), (200_003, 10)])
+def test_prune_sample_matches_oracle(ctx, n, draws):
+    rng = np.random.default_rng(n + draws)
+    scores = (rng.normal(size=(n, 2)) * np.array([1.5, 1.0]) + np.array([-1.0, 0.0])).astype(np.float32)
+    keep = torch.full((max(n, 1),), 7, dtype=torch.int32, device="cuda")
+    U.M().mgs_prune_sample(ctx, torch.from_numpy(scores).cuda().reshape(n, 2), 2412, 300, draws, keep[:n])
+    torch.cuda.synchronize()
+    want = oracle.prune_keep(scores, 2412, 300, draws)
+    assert np.array_equal(keep[:n].cpu().numpy(), want.astype(np.int32))
+
+
+@pytest.mark.parametrize("n", [0, 1, 257, 100_003])
+@pytest.mark.parametrize("pattern", ["random", "all", "none"])
+def test_compact_rows_matches_boolean_indexing(ctx, n, pattern):
+    rng = np.random.default_rng(n)
+    if pattern == "random":
+        keep = (rng.random(n) < 0.6).astype(np.int32)
+    else:
+        keep = np.full(n, 1 if pattern == "all" else 0, np.int32)
+    widths = [1, 2, 3, 4, 48]
+    ins = [rng.normal(size=(n, w)).astype(np.float32) for w in widths]
+    din = [torch.from_numpy(a).cuda() for a in ins]
+    dout = [torch.full_like(t, -7.0) for t in din]
+    n_kept = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    U.M().mgs_compact_rows(ctx, torch.from_numpy(keep).cuda(), din, dout, n_kept=n_kept)
+    torch.cuda.synchronize()
+    k = int(keep.sum())
+    assert int(n_kept.item()) == k
+    for a, o in zip(ins, dout):
+        got = o.cpu().numpy()
+        assert np.array_equal(got[:k], a[keep.astype(bool)])
+        assert np.all(got[k:] == -7.0)  # rows past the kept ones are untouched
+
+
+def test_compact_rows_rejects_in_place(ctx):
+    t = torch.zeros(10, 3, device="cuda")
+    with pytest.raises(U.M().MaskGSError):
+        U.M().mgs_compact_rows(ctx, torch.ones(10, dtype=torch.int32, device="cuda"), [t], [t])
+
+
+@pytest.mark.parametrize("cull", [0, 1])
+def test_pruning_masked_gaussians_changes_nothing(cull):
+    """Gaussians outside the keep set are masked in the full render; the
+    pruned set renders the same image bit for bit, and the survivors'
+    gradients match those of the full set."""
+    from paper_2412_20522_amd import prune as P
+    from paper_2412_20522_amd.raster import PARAM_KEYS, Rasterizer
+    s = scenegen.small_scene(6000, 120, 96, seed=411, sh_degree=2, log_scale_mean=-2.6, n_views=2)
+    cams = s["cameras"]
+    rast = Rasterizer(0, sh_degree=2, bg=(0.2, 0.1, 0.3), tile_cull=cull, wide_tiles=8, persistent=1)
+    n = s["means"].shape[0]
+    rng = np.random.default_rng(12)
+    scores = torch.from_numpy(rng.normal(size=(n, 2)).astype(np.float32) * 2.0).cuda()
+    dev = U.to_device(s)
+    params = {k: dev[k] for k in PARAM_KEYS}
+    pruned, keep, k = P.prune(rast.ctx, scores, {**params, "masks": dev["masks"]}, seed=5, step0=0, n_draws=2)
+    keep_np = keep.cpu().numpy().astype(bool)
+    assert 0 < k < n and k == int(keep_np.sum())
+    # full set with the pruned Gaussians masked
+    masks_full = dev["masks"] * keep.float()
+    P_ = sum(c["width"] * c["height"] for c in cams)
+    dl = torch.from_numpy(rng.normal(size=3 * P_).astype(np.float32)).cuda()
+    f_full = rast.acquire_frame()
+    img_full = rast.forward(f_full, params, masks_full, cams).clone()
+    g_full = rast.backward(f_full, params, dl)
+    f_pr = rast.acquire_frame()
+    pp = {kk: pruned[kk] for kk in PARAM_KEYS}
+    img_pr = rast.forward(f_pr, pp, pruned["masks"].contiguous(), cams).clone()
+    g_pr = rast.backward(f_pr, pp, dl)
+    torch.cuda.synchronize()
+    assert torch.equal(img_full, img_pr)
+    kt = torch.from_numpy(keep_np).cuda()
+    for name in PARAM_KEYS + ("masks",):
+        a = getattr(g_full, name)[kt].cpu().numpy().astype(np.float64)
+        b = getattr(g_pr, name).cpu().numpy().astype(np.float64)
+        assert U.rel_err(b, a) <= 1e-6, name
+    rast.release_frame(f_full)
+    rast.release_frame(f_pr)

@@ -110,3 +110,25 @@ def test_row_interval_bounds_the_ellipse_slice():
         assert iv[0] <= xmin + 1e-9 * abs(xmin) and iv[1] >= xmax - 1e-9 * abs(xmax)
         span = xmax - xmin + 1.0
         assert iv[0] >= xmin - 2 * step - 0.05 * span and iv[1] <= xmax + 2 * step + 0.05 * span
+
+
+def test_lambda_schedules_follow_the_experiments():
+    """Sec. 4.1 (implementation details): alpha = 0.1 from iteration 19000 to
+    20000, beta = 0.0005 and gamma = 0.001 throughout."""
+    from paper_2412_20522_amd import prune as P
+    assert P.lambda_m(18_999, "alpha") == 0.0
+    assert P.lambda_m(19_000, "alpha") == 0.1 and P.lambda_m(19_999, "alpha") == 0.1
+    assert P.lambda_m(20_000, "alpha") == 0.0
+    for it in (0, 1, 15_000, 29_999):
+        assert P.lambda_m(it, "beta") == 0.0005 and P.lambda_m(it, "gamma") == 0.001
+
+
+def test_prune_cadence():
+    """Sec. 3.5: pruning at every densification step and every 1000
+    iterations afterwards (densification every 100 iterations in [500, 15000])."""
+    from paper_2412_20522_amd import prune as P
+    due = [it for it in range(0, 20_001) if P.prune_due(it)]
+    assert due[:3] == [500, 600, 700]
+    assert 15_000 in due and 15_100 not in due and 16_000 in due and 20_000 in due
+    assert all(it % 100 == 0 for it in due)
+    assert sum(1 for it in due if it > 15_000) == 5
