@@ -154,6 +154,70 @@ def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: flo
             "views_per_s": len(done) / dt, "seconds": dt}
 
 
+def prune_and_render(rast, params: dict, scores, cams, n: int, seed: int, reps: int = 5) -> dict:
+    """Probabilistic pruning of the scene's whole per-Gaussian training state
+    (parameters, mask scores and both Adam moments of each: 183 floats per
+    Gaussian), timed with HIP events, and forward-only rendering (all masks 1)
+    of the full and of the pruned set, as views per second."""
+    import torch
+    from paper_2412_20522_amd import maskgs as M
+    from paper_2412_20522_amd.raster import PARAM_KEYS
+    dev = scores.device
+    state = {k: v for k, v in params.items()}
+    for k, v in list(params.items()) + [("scores", scores)]:
+        state[f"adam_m_{k}"] = torch.zeros_like(v)
+        state[f"adam_v_{k}"] = torch.zeros_like(v)
+    floats = sum(v.numel() for v in state.values()) // n + 2
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    ins = [scores, *state.values()]
+    outs = [torch.empty_like(t) for t in ins]
+    n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    scratch = torch.empty(int(M.lib().mgs_compact_scratch_bytes(n)), dtype=torch.uint8, device=dev)
+
+    def prune_once(step0):
+        M.mgs_prune_sample(rast.ctx, scores, seed, step0, 10, keep)
+        M.mgs_compact_rows(rast.ctx, keep, ins, outs, n_kept=n_kept, scratch=scratch)
+
+    prune_once(10_000)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        prune_once(10_000 + 10 * r)
+    e1.record()
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1) / reps
+    k = int(n_kept.item())
+    moved = n * 4 + n * floats * 4 + k * floats * 4  # keep mask, every row read, kept rows written
+    pruned = {name: t[:k] for name, t in zip(["scores", *state.keys()], outs)}
+
+    def render_ms(ps: dict, count: int) -> float:
+        fr = rast.acquire_frame()
+        ones = torch.ones(count, device=dev)
+        imgs = torch.empty(3 * sum(c["width"] * c["height"] for c in cams), device=dev)
+        for _ in range(2):
+            rast.forward(fr, ps, ones, cams, images=imgs)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            rast.forward(fr, ps, ones, cams, images=imgs)
+        b.record()
+        torch.cuda.synchronize()
+        rast.release_frame(fr)
+        return a.elapsed_time(b) / reps
+
+    full_ms = render_ms(params, n)
+    pr_ms = render_ms({key: pruned[key] for key in PARAM_KEYS}, k)
+    V = len(cams)
+    return {
+        "prune": {"ms": pms, "gaussians": n, "kept": k, "draws": 10, "floats_per_gaussian": floats,
+                  "GB_per_s": moved / (pms * 1e-3) / 1e9},
+        "render_only": {"full": {"ms": full_ms, "views_per_s": V / (full_ms * 1e-3)},
+                        "pruned": {"ms": pr_ms, "views_per_s": V / (pr_ms * 1e-3), "gaussians": k}},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +227,7 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the pruning and forward-only timings")
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--batch-depth", type=int, default=128)
     ap.add_argument("--fwd-ppt", type=int, default=4)
@@ -359,6 +424,13 @@ def main() -> int:
         plain = {"ms_per_step": pms, "evals_per_s": E16 / (pms * 1e-3), "views_per_s": V / (pms * 1e-3)}
         log(f"[bench] plain: {pms:.3f} ms/step")
 
+    extras = None
+    if not args.no_extras:
+        extras = prune_and_render(rast, params, scores, cams, n, seed)
+        log(f"[bench] pruning: {extras['prune']['ms']:.3f} ms ({extras['prune']['kept']} of {n} kept, "
+            f"{extras['prune']['GB_per_s']:.0f} GB/s); forward only: full {extras['render_only']['full']['ms']:.3f} ms, "
+            f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {V} views")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample of the views ...")
@@ -399,6 +471,8 @@ def main() -> int:
             "persistent": bool(rast.settings.persistent),
             "eval_counts": counts,
             "plain": plain,
+            "pruning": extras["prune"] if extras else None,
+            "render_only": extras["render_only"] if extras else None,
             "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if prof[k][1]},
         },
         "roofline": roof,
