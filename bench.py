@@ -154,22 +154,27 @@ def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: flo
             "views_per_s": len(done) / dt, "seconds": dt}
 
 
-def prune_and_render(rast, params: dict, scores, cams, n: int, seed: int, reps: int = 5) -> dict:
-    """Probabilistic pruning of the scene's whole per-Gaussian training state
+def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 5) -> dict:
+    """Probabilistic pruning (10 draws) of a whole per-Gaussian training state
     (parameters, mask scores and both Adam moments of each: 183 floats per
-    Gaussian), timed with HIP events, and forward-only rendering (all masks 1)
-    of the full and of the pruned set, as views per second."""
+    Gaussian) whose scores are those of late training (62.4 % of the Gaussians
+    with scores that all but rule them out, Sec. 4.2), timed with HIP events;
+    then forward-only rendering (all masks 1) of the full and of the pruned
+    set on a fixed workspace, as views per second."""
     import torch
+    import scenegen
     from paper_2412_20522_amd import maskgs as M
     from paper_2412_20522_amd.raster import PARAM_KEYS
-    dev = scores.device
-    state = {k: v for k, v in params.items()}
+    dev = params["means"].device
+    scores = torch.from_numpy(scenegen.converged_mask_scores(n)).to(dev)
+    state = dict(params)
     for k, v in list(params.items()) + [("scores", scores)]:
         state[f"adam_m_{k}"] = torch.zeros_like(v)
         state[f"adam_v_{k}"] = torch.zeros_like(v)
-    floats = sum(v.numel() for v in state.values()) // n + 2
-    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    names = ["scores", *state.keys()]
     ins = [scores, *state.values()]
+    floats = sum(t.numel() for t in ins) // n
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
     outs = [torch.empty_like(t) for t in ins]
     n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
     scratch = torch.empty(int(M.lib().mgs_compact_scratch_bytes(n)), dtype=torch.uint8, device=dev)
@@ -178,23 +183,30 @@ def prune_and_render(rast, params: dict, scores, cams, n: int, seed: int, reps: 
         M.mgs_prune_sample(rast.ctx, scores, seed, step0, 10, keep)
         M.mgs_compact_rows(rast.ctx, keep, ins, outs, n_kept=n_kept, scratch=scratch)
 
-    prune_once(10_000)
+    prune_once(20_000)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for r in range(reps):
-        prune_once(10_000 + 10 * r)
+        prune_once(20_000 + 10 * r)
     e1.record()
     torch.cuda.synchronize()
     pms = e0.elapsed_time(e1) / reps
     k = int(n_kept.item())
-    moved = n * 4 + n * floats * 4 + k * floats * 4  # keep mask, every row read, kept rows written
-    pruned = {name: t[:k] for name, t in zip(["scores", *state.keys()], outs)}
+    # algorithmic bytes: scores read by the draws, keep written and read twice
+    # (scan, compaction), every row read, the kept rows written
+    moved = 8 * n + 12 * n + 4 * floats * (n + k)
+    pruned = {name: t[:k] for name, t in zip(names, outs)}
+
+    frames = []
 
     def render_ms(ps: dict, count: int) -> float:
-        fr = rast.acquire_frame()
+        fr = rast.acquire_frame()  # a frame of its own (fixed workspaces are per frame)
+        frames.append(fr)
         ones = torch.ones(count, device=dev)
         imgs = torch.empty(3 * sum(c["width"] * c["height"] for c in cams), device=dev)
+        rast.forward(fr, ps, ones, cams, images=imgs)
+        rast.reserve(fr, 1.25)  # fixed workspace: no host synchronisation per forward
         for _ in range(2):
             rast.forward(fr, ps, ones, cams, images=imgs)
         torch.cuda.synchronize()
@@ -204,17 +216,21 @@ def prune_and_render(rast, params: dict, scores, cams, n: int, seed: int, reps: 
             rast.forward(fr, ps, ones, cams, images=imgs)
         b.record()
         torch.cuda.synchronize()
-        rast.release_frame(fr)
+        rast.check(fr)
         return a.elapsed_time(b) / reps
 
     full_ms = render_ms(params, n)
     pr_ms = render_ms({key: pruned[key] for key in PARAM_KEYS}, k)
+    for fr in frames:
+        rast.release_frame(fr)
     V = len(cams)
     return {
         "prune": {"ms": pms, "gaussians": n, "kept": k, "draws": 10, "floats_per_gaussian": floats,
-                  "GB_per_s": moved / (pms * 1e-3) / 1e9},
-        "render_only": {"full": {"ms": full_ms, "views_per_s": V / (full_ms * 1e-3)},
-                        "pruned": {"ms": pr_ms, "views_per_s": V / (pr_ms * 1e-3), "gaussians": k}},
+                  "scores": "62.4 % of the Gaussians with s0 - s1 = -8, the rest +8 (seeded)",
+                  "algorithmic_bytes": moved, "GB_per_s": moved / (pms * 1e-3) / 1e9},
+        "render_only": {"full": {"ms": full_ms, "views_per_s": V / (full_ms * 1e-3), "gaussians": n},
+                        "pruned": {"ms": pr_ms, "views_per_s": V / (pr_ms * 1e-3), "gaussians": k},
+                        "speedup": full_ms / pr_ms},
     }
 
 
@@ -426,10 +442,11 @@ def main() -> int:
 
     extras = None
     if not args.no_extras:
-        extras = prune_and_render(rast, params, scores, cams, n, seed)
+        extras = prune_and_render(rast, params, n, cams, seed)
         log(f"[bench] pruning: {extras['prune']['ms']:.3f} ms ({extras['prune']['kept']} of {n} kept, "
             f"{extras['prune']['GB_per_s']:.0f} GB/s); forward only: full {extras['render_only']['full']['ms']:.3f} ms, "
-            f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {V} views")
+            f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {V} views "
+            f"(x{extras['render_only']['speedup']:.2f})")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -447,9 +447,11 @@ MGS_API mgs_status mgs_prune_sample(mgs_ctx* ctx, mgs_stream stream, const float
  * scores, optimiser state; Sec. 3.5): stable compaction of the rows with
  * keep[i] != 0.  n_arrays arrays, host arrays of device pointers in[a] and
  * out[a] (distinct, caller-owned, out[a] holding at least as many rows as
- * are kept) with widths[a] (>= 1) floats per row.  n_kept (device, one u64,
- * optional) receives the number of kept rows.  scratch (device) holds
- * mgs_compact_scratch_bytes(n) bytes.  Asynchronous, no allocation. */
+ * are kept) with widths[a] (1 .. 2^20) floats per row; n < 2^31.  Rows past
+ * the kept ones are left untouched.  n_kept (device, one u64, optional)
+ * receives the number of kept rows.  scratch (device) holds
+ * mgs_compact_scratch_bytes(n) bytes.  One launch per 32 arrays after the
+ * scan.  Asynchronous, no allocation. */
 MGS_API size_t mgs_compact_scratch_bytes(int64_t n);
 MGS_API mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* keep, int64_t n, int n_arrays,
                                     const float* const* in, float* const* out, const int* widths, uint64_t* n_kept,

@@ -1040,10 +1040,12 @@ mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* kee
                             void* scratch) {
     if (!ctx) return MGS_ERR_INVALID_ARG;
     if (n < 0 || n_arrays < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "negative size");
+    if (n > (int64_t)0x7fffffff) return fail(ctx, MGS_ERR_INVALID_ARG, "n = %lld exceeds 2^31 - 1", (long long)n);
     if (n_arrays > 0 && (!in || !out || !widths)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (n > 0 && (!keep || !scratch)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     for (int a = 0; a < n_arrays; ++a) {
-        if (widths[a] < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "width of array %d must be >= 1", a);
+        if (widths[a] < 1 || widths[a] > (1 << 20))
+            return fail(ctx, MGS_ERR_INVALID_ARG, "width of array %d must be in 1 .. 2^20", a);
         if (n > 0 && (!in[a] || !out[a])) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL array %d", a);
         if (n > 0 && in[a] == out[a]) return fail(ctx, MGS_ERR_INVALID_ARG, "array %d compacts in place", a);
     }
@@ -1052,7 +1054,7 @@ mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* kee
     char* scan_tmp = reinterpret_cast<char*>(scratch) + ((size_t)(n > 0 ? n : 1) * 4 + 255) / 256 * 256;
     if (n > 0) {
         launch_scan_u32(st, keep, n, pos, n_kept, scan_tmp);
-        for (int a = 0; a < n_arrays; ++a) launch_compact_rows(st, keep, pos, n, widths[a], in[a], out[a]);
+        launch_compact_rows(st, keep, pos, n, n_arrays, in, out, widths);
     } else if (n_kept) {
         launch_fill_u32(st, reinterpret_cast<uint32_t*>(n_kept), 2, 0u);
     }

@@ -119,8 +119,8 @@ void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, flo
 void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uint64_t seed, uint64_t step0,
                          int n_draws, uint32_t* keep);
 // pos: exclusive scan of keep
-void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int width,
-                         const float* in, float* out);
+void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int n_arrays,
+                         const float* const* in, float* const* out, const int* widths);
 void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
                       float tau, float lambda_m, float* d_scores, float* loss_m, void* scratch);
 void launch_l1_loss_grad(hipStream_t stream, const float* images, const float* targets, int64_t m, float* d_images,

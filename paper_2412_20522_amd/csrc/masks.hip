@@ -75,18 +75,54 @@ __global__ void __launch_bounds__(RNT) prune_sample_kernel(const float* __restri
     keep[i] = k;
 }
 
-// Stable compaction of one per-Gaussian array of `width` floats per row:
-// row i goes to row pos[i] (exclusive scan of keep) when keep[i] != 0.  One
-// thread per element: reads are coalesced, writes contiguous within the
-// kept rows.
+// Stable compaction of per-Gaussian arrays: row i of every array goes to row
+// pos[i] (exclusive scan of keep) when keep[i] != 0.  One launch covers up to
+// CR_MAX arrays; each workgroup takes CR_ROWS rows of one array, stages their
+// destinations in LDS, and moves the rows in units of `vec` floats (4, 2 or
+// 1, as the width and the pointers' alignment allow).  Reads are coalesced
+// over the workgroup's rows; writes are contiguous over runs of kept rows.
+constexpr int CR_MAX = 32;
+constexpr int CR_ROWS = RNT;
+constexpr uint32_t CR_DROP = 0xffffffffu;
+
+struct CompactSet {
+    const float* in[CR_MAX];
+    float* out[CR_MAX];
+    uint32_t width[CR_MAX];
+    uint32_t vec[CR_MAX];
+    uint32_t block0[CR_MAX + 1];  // first workgroup of each array; block0[count] = grid size
+    int count;
+};
+
 __global__ void __launch_bounds__(RNT) compact_rows_kernel(const uint32_t* __restrict__ keep,
-                                                            const uint32_t* __restrict__ pos, int64_t n, int width,
-                                                            const float* __restrict__ in, float* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * width) return;
-    const int64_t i = e / width;
-    if (!keep[i]) return;
-    out[(int64_t)pos[i] * width + (e - i * width)] = in[e];
+                                                            const uint32_t* __restrict__ pos, int64_t n,
+                                                            CompactSet cs) {
+    __shared__ uint32_t s_dst[CR_ROWS];
+    const uint32_t b = blockIdx.x;
+    int a = 0;
+    while (a + 1 < cs.count && cs.block0[a + 1] <= b) ++a;
+    const int64_t r0 = (int64_t)(b - cs.block0[a]) * CR_ROWS;
+    const int rows = (int)min((int64_t)CR_ROWS, n - r0);
+    const int t = threadIdx.x;
+    if (t < rows) s_dst[t] = keep[r0 + t] ? pos[r0 + t] : CR_DROP;
+    __syncthreads();
+    const uint32_t w = cs.width[a], vw = cs.vec[a], units = w / vw;
+    const uint32_t total = (uint32_t)rows * units;
+    const float* in = cs.in[a] + r0 * (int64_t)w;
+    float* out = cs.out[a];
+    for (uint32_t l = t; l < total; l += RNT) {
+        const uint32_t r = l / units, c = l - r * units;
+        const uint32_t d = s_dst[r];
+        if (d == CR_DROP) continue;
+        const int64_t src = (int64_t)l * vw, dst = (int64_t)d * w + (int64_t)c * vw;
+        if (vw == 4) {
+            *reinterpret_cast<float4*>(out + dst) = *reinterpret_cast<const float4*>(in + src);
+        } else if (vw == 2) {
+            *reinterpret_cast<float2*>(out + dst) = *reinterpret_cast<const float2*>(in + src);
+        } else {
+            out[dst] = in[src];
+        }
+    }
 }
 
 // Deterministic two-level sums in double.
@@ -176,12 +212,26 @@ void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uin
                        seed, step0, n_draws, keep);
 }
 
-void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int width,
-                         const float* in, float* out) {
-    const int64_t m = n * (int64_t)width;
-    if (m == 0) return;
-    hipLaunchKernelGGL(compact_rows_kernel, dim3((unsigned)((m + RNT - 1) / RNT)), dim3(RNT), 0, stream, keep, pos,
-                       n, width, in, out);
+void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int n_arrays,
+                         const float* const* in, float* const* out, const int* widths) {
+    if (n == 0) return;
+    const uint32_t per = (uint32_t)((n + CR_ROWS - 1) / CR_ROWS);
+    for (int a0 = 0; a0 < n_arrays; a0 += CR_MAX) {
+        CompactSet cs{};
+        cs.count = min(CR_MAX, n_arrays - a0);
+        for (int j = 0; j < cs.count; ++j) {
+            const int a = a0 + j;
+            const uint32_t w = (uint32_t)widths[a];
+            const uintptr_t al = (uintptr_t)in[a] | (uintptr_t)out[a];
+            cs.in[j] = in[a];
+            cs.out[j] = out[a];
+            cs.width[j] = w;
+            cs.vec[j] = (w % 4 == 0 && al % 16 == 0) ? 4u : (w % 2 == 0 && al % 8 == 0) ? 2u : 1u;
+            cs.block0[j] = (uint32_t)j * per;
+        }
+        cs.block0[cs.count] = (uint32_t)cs.count * per;
+        hipLaunchKernelGGL(compact_rows_kernel, dim3(cs.block0[cs.count]), dim3(RNT), 0, stream, keep, pos, n, cs);
+    }
 }
 
 void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,

@@ -187,6 +187,21 @@ def _bernoulli_masks(rng, mask_logits):
     return (rng.uniform(0.0, 1.0, mask_logits.shape) < p).astype(np.float32)
 
 
+def converged_mask_scores(n: int, pruned_fraction: float = 0.624, gap: float = 8.0, config: int = 4,
+                          salt: int = 7) -> np.ndarray:
+    """Mask scores [n, 2] as late training leaves them: the two scores of
+    each Gaussian differ by `gap` (s0 - s1 = -gap for a seeded random
+    `pruned_fraction` of the Gaussians, +gap for the rest).  The default
+    fraction is the share of Gaussians the method removes on Mip-NeRF360
+    (Sec. 4.2); which Gaussians they are is drawn uniformly, one uniform per
+    Gaussian, since the synthetic scenes carry no learned contribution."""
+    rng = rng_for(config, salt)
+    u = rng.uniform(0.0, 1.0, n)
+    scores = np.zeros((n, 2), np.float32)
+    scores[:, 0] = np.where(u < pruned_fraction, -gap, gap)
+    return scores
+
+
 def _targets(rng, cams):
     return [rng.uniform(0.0, 1.0, (3, c["height"], c["width"])).astype(np.float32) for c in cams]
 

@@ -53,6 +53,37 @@ def test_compact_rows_matches_boolean_indexing(ctx, n, pattern):
         assert np.all(got[k:] == -7.0)  # rows past the kept ones are untouched
 
 
+def test_compact_rows_many_arrays_and_misaligned_views(ctx):
+    """More arrays than one launch takes (32), widths that pick each vector
+    unit, and views offset by one float so no vector access is aligned."""
+    n = 70_001
+    rng = np.random.default_rng(3)
+    keep = (rng.random(n) < 0.3).astype(np.int32)
+    widths = [(1, 2, 3, 4, 8, 48, 6, 5)[a % 8] for a in range(40)]
+    ins, din, dout = [], [], []
+    for a, w in enumerate(widths):
+        x = rng.normal(size=(n, w)).astype(np.float32)
+        ins.append(x)
+        if a % 3 == 0:  # offset by one float inside a larger buffer
+            bi = torch.empty(n * w + 1, device="cuda")
+            bi[1:] = torch.from_numpy(x.reshape(-1)).cuda()
+            bo = torch.full((n * w + 1,), -7.0, device="cuda")
+            din.append(bi[1:].view(n, w))
+            dout.append(bo[1:].view(n, w))
+        else:
+            din.append(torch.from_numpy(x).cuda())
+            dout.append(torch.full((n, w), -7.0, device="cuda"))
+    n_kept = torch.full((1,), -1, dtype=torch.int64, device="cuda")
+    U.M().mgs_compact_rows(ctx, torch.from_numpy(keep).cuda(), din, dout, n_kept=n_kept)
+    torch.cuda.synchronize()
+    k = int(keep.sum())
+    assert int(n_kept.item()) == k
+    for x, o in zip(ins, dout):
+        got = o.cpu().numpy()
+        assert np.array_equal(got[:k], x[keep.astype(bool)])
+        assert np.all(got[k:] == -7.0)
+
+
 def test_compact_rows_rejects_in_place(ctx):
     t = torch.zeros(10, 3, device="cuda")
     with pytest.raises(U.M().MaskGSError):
