@@ -321,6 +321,18 @@ def sample_masks(scores, tau: float, seed: int, step: int, return_noise: bool = 
     return (m, y, g) if return_noise else (m, y)
 
 
+def threshold_masks(scores, threshold: float):
+    """Straight-through alternative of the ablation (Sec. 4.3, Table 6):
+    y = sigmoid(s0 - s1) and the deterministic mask [y > threshold]; with
+    mask_grad at tau = 1 the gradient passes through the threshold as if it
+    were the identity."""
+    s = _f64(scores).reshape(-1, 2)
+    n = s.shape[0]
+    m, y = np.zeros(n), np.zeros(n)
+    lib().orc_threshold_masks(C.c_int64(n), _p(s), C.c_double(threshold), _p(m), _p(y))
+    return m, y
+
+
 def prune_keep(scores, seed: int, step0: int, n_draws: int = 10):
     """Probabilistic pruning (Sec. 3.5, training and pruning): every Gaussian
     draws n_draws hard masks -- the draws of sample_masks at steps step0 ..
@@ -386,9 +398,18 @@ def stack_projected(projs):
 
 
 def run_pipeline(scene: dict, cams: list, mask, st: RasterSettings, targets=None, dl_dimage=None,
-                 backward: bool = True) -> Pipeline:
+                 backward: bool = True, mask_mode: str = "raster") -> Pipeline:
     """Projection, lists, forward, L1 loss (or a given image gradient),
-    backward and projection backward, all in FP64."""
+    backward and projection backward, all in FP64.
+
+    mask_mode "raster": masked rasterization (Eq. 3-4, gradient Eq. 6).
+    mask_mode "opacity": the alternative of the ablation in Sec. 4.3 (Table
+    7): the mask multiplies the opacity before rasterization, which then runs
+    unmasked (mask 1); dL/dM follows by the chain rule through the product,
+    dL/dM_i = sum over views of dL/d(M_i o_i) * o_i, and the opacity's own
+    gradient takes the factor M_i."""
+    if mask_mode not in ("raster", "opacity"):
+        raise ValueError(mask_mode)
     n = scene["means"].shape[0]
     out = Pipeline()
     out.proj = [project(scene, c, st) for c in cams]
@@ -396,7 +417,13 @@ def run_pipeline(scene: dict, cams: list, mask, st: RasterSettings, targets=None
     heights = [c["height"] for c in cams]
     m2d, con, opa, col, rad, dbits, val = stack_projected(out.proj)
     out.lists = build_lists(widths, heights, n, m2d, rad, dbits, val, st)
-    out.fwd = render_fwd(widths, heights, n, m2d, con, opa, col, mask, out.lists, st)
+    mask = _f64(mask).reshape(-1)
+    V = len(cams)
+    if mask_mode == "opacity":
+        opa_r, mask_r = opa * np.tile(mask, V), np.ones(n)
+    else:
+        opa_r, mask_r = opa, mask
+    out.fwd = render_fwd(widths, heights, n, m2d, con, opa_r, col, mask_r, out.lists, st)
     if not backward:
         return out
     if dl_dimage is None:
@@ -404,6 +431,10 @@ def run_pipeline(scene: dict, cams: list, mask, st: RasterSettings, targets=None
         out.loss, out.d_image = l1_loss(out.fwd.image, tgt)
     else:
         out.d_image = _f64(dl_dimage).reshape(-1)
-    out.bwd = render_bwd(widths, heights, n, m2d, con, opa, col, mask, out.lists, out.d_image, st)
-    out.grads = project_bwd(scene, cams, st, out.bwd.d_mean2d, out.bwd.d_conic, out.bwd.d_opacity, out.bwd.d_color)
+    out.bwd = render_bwd(widths, heights, n, m2d, con, opa_r, col, mask_r, out.lists, out.d_image, st)
+    d_opa = out.bwd.d_opacity
+    if mask_mode == "opacity":
+        out.bwd.d_mask = (d_opa * opa).reshape(V, n).sum(axis=0)
+        d_opa = d_opa * np.tile(mask, V)
+    out.grads = project_bwd(scene, cams, st, out.bwd.d_mean2d, out.bwd.d_conic, d_opa, out.bwd.d_color)
     return out

@@ -977,6 +977,19 @@ ORC_API void orc_sample_masks(int64_t n, const double* scores, double tau, uint6
 }
 
 /*
+ * Deterministic masks of the straight-through alternative in the ablation of
+ * Sec. 4.3: the existence probability sigmoid(s0 - s1), and a hard mask that
+ * is 1 exactly when it exceeds the threshold.
+ */
+ORC_API void orc_threshold_masks(int64_t n, const double* scores, double threshold, double* m_hard, double* y_soft) {
+    for (int64_t i = 0; i < n; i++) {
+        const double p = 1.0 / (1.0 + exp(scores[2 * i + 1] - scores[2 * i]));
+        m_hard[i] = p > threshold ? 1.0 : 0.0;
+        y_soft[i] = p;
+    }
+}
+
+/*
  * Gradient to the two scores through the straight-through mask, including
  * the mask-count loss L_m = (mean M)^2 weighted by lambda_m (Eq. 7-8).
  */
