@@ -116,7 +116,21 @@ typedef struct {
                                 0: every tile (region) of its rectangle, the
                                 lists of Sec. 3.1 exactly (for list parity and
                                 for counting entries examined on those lists) */
+    int32_t mask_mode;       /* how M_i enters the rendering:
+                                MGS_MASK_RASTER (0): masked rasterization,
+                                Eq. 3-4, with dL/dM_i of Eq. 6 for every
+                                Gaussian, sampled or not;
+                                MGS_MASK_OPACITY (1): the prior-art product
+                                of the ablation in Sec. 4.3 (Table 7): the
+                                opacity becomes M_i * sigmoid(logit) before
+                                the alpha clamp and filter, so an unsampled
+                                Gaussian is filtered out and receives no
+                                gradient at all; dL/dM_i is the chain rule
+                                through that product */
 } mgs_settings;
+
+#define MGS_MASK_RASTER 0
+#define MGS_MASK_OPACITY 1
 
 /* Gaussian parameters (device pointers, float32). */
 typedef struct {
@@ -342,7 +356,8 @@ MGS_API mgs_status mgs_profile_read(mgs_ctx* ctx, double* ms, int64_t* launches)
 
 /* EWA projection and SH colour (Sec. 3.1) of every Gaussian for every view.
  * rec [R, 12]: u, v, a, b / a, c - b^2 / a, opacity, mask, radius, r, g, b,
- *   tile count (u32 bits; the same values as radius[] and tiles[])
+ *   tile count (u32 bits; the same values as radius[] and tiles[]);
+ *   under MGS_MASK_OPACITY opacity is M_i * sigmoid(logit) and mask 1
  *   (conic (a, b, c) is the inverse 2D covariance, Q = a dx^2 + 2 b dx dy + c dy^2,
  *   stored in the form a (dx + (b / a) dy)^2 + (c - b^2 / a) dy^2, which FP32
  *   evaluates without cancellation for needle-shaped splats);
@@ -407,7 +422,9 @@ MGS_API mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const
 /* Chain rule from d_rec [R, 9] (layout of mgs_composite_backward, conic
  * gradient in the stored basis) to the Gaussian parameters, summed over
  * views (no atomics: one thread per Gaussian), in double precision from the
- * 3D covariance to the conic.  grads->d_masks is ignored. */
+ * 3D covariance to the conic.  grads->d_masks is ignored.  Under
+ * MGS_MASK_OPACITY the d_rec opacity entry is dL/d(M_i opacity) and g->masks
+ * is required (the logit gradient carries the factor M_i). */
 MGS_API mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g,
                                         const mgs_camera* cams, int n_views, const mgs_settings* st,
                                         const float* d_rec, const mgs_gradients* grads);
@@ -424,6 +441,16 @@ MGS_API mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const m
  * sigmoid((s0 + g0 - s1 - g1) / tau). */
 MGS_API mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float tau,
                                     uint64_t seed, uint64_t step, float* m_hard, float* y_soft);
+
+/* Deterministic masks with a straight-through estimator, the alternative to
+ * Gumbel sampling in the ablation of Sec. 4.3 (Table 6): y = sigmoid(s0 - s1)
+ * and m_hard = [y > threshold], both in double precision; y_soft = y.
+ * mgs_mask_grad with tau = 1 then gives the straight-through gradient
+ * (dL/dy taken as dL/dM).  threshold in (0, 1); the paper takes the value
+ * of the method it compares with without printing it.  scores [n, 2]
+ * (8-byte aligned); m_hard, y_soft [n] (device, caller-owned). */
+MGS_API mgs_status mgs_threshold_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n,
+                                       float threshold, float* m_hard, float* y_soft);
 
 /* Gradient to the scores through the straight-through mask, adding the
  * mask-count loss L_m = (mean M)^2 weighted by lambda_m (Eq. 7-8):

@@ -146,6 +146,8 @@ mgs_status check_settings(mgs_ctx* ctx, const mgs_settings* st) {
                     st->bwd_ppt, st->tile_w, st->tile_h);
     if (!(st->alpha_max > 0.f && st->alpha_max < 1.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "alpha_max in (0, 1)");
     if (!(st->near_plane > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "near_plane must be > 0");
+    if (st->mask_mode != MGS_MASK_RASTER && st->mask_mode != MGS_MASK_OPACITY)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "mask_mode %d not MGS_MASK_RASTER or MGS_MASK_OPACITY", st->mask_mode);
     return MGS_OK;
 }
 
@@ -247,6 +249,7 @@ DevSettings make_settings(const mgs_settings* s) {
         d.tile_cull = s->tile_cull != 0;
     }
     d.qs_max = (float)(-0.5 / std::log(2.0) * (double)d.q_max);
+    d.mask_opacity = s->mask_mode == MGS_MASK_OPACITY;
     return d;
 }
 
@@ -986,8 +989,8 @@ mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gauss
                                 int n_views, const mgs_settings* st, const float* d_rec, const mgs_gradients* grads) {
     if (!ctx) return MGS_ERR_INVALID_ARG;
     mgs_status s;
-    if ((s = check_gaussians(ctx, g, false)) || (s = check_cameras(ctx, cams, n_views)) ||
-        (s = check_settings(ctx, st)))
+    if ((s = check_settings(ctx, st)) || (s = check_gaussians(ctx, g, st->mask_mode == MGS_MASK_OPACITY)) ||
+        (s = check_cameras(ctx, cams, n_views)))
         return s;
     if (!grads || (g->n > 0 && !d_rec)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
@@ -1018,6 +1021,19 @@ mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores
 }
 
 size_t mgs_reduce_scratch_bytes(int64_t n) { return reduce_scratch_bytes(n); }
+
+mgs_status mgs_threshold_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float threshold,
+                               float* m_hard, float* y_soft) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (!(threshold > 0.f && threshold < 1.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "threshold must be in (0, 1)");
+    if (n > 0 && (!scores || !m_hard || !y_soft)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "scores must be 8-byte aligned");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_SAMPLE_MASKS);
+    launch_threshold_masks((hipStream_t)stream, scores, n, (double)threshold, m_hard, y_soft);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
 
 mgs_status mgs_prune_sample(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, uint64_t seed,
                             uint64_t step0, int n_draws, uint32_t* keep) {

@@ -41,6 +41,7 @@ struct DevSettings {
     int32_t full_rect;  // every valid record covers every tile of its view
     int32_t tile_cull;  // narrow instances only for tiles a record can reach
     float qs_max;       // -log2(e) / 2 * q_max: the cut on the scaled form of the compositing kernels
+    int32_t mask_opacity;  // 1: M multiplies the opacity in the projection (records carry mask 1)
 };
 
 // Side of a region in tiles.  Wide records are listed once per region they

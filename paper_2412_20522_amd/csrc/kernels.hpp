@@ -116,6 +116,8 @@ void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const flo
 size_t reduce_scratch_bytes(int64_t n);
 void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, float tau, uint64_t seed, uint64_t step,
                          float* m_hard, float* y_soft);
+void launch_threshold_masks(hipStream_t stream, const float* scores, int64_t n, double threshold, float* m_hard,
+                            float* y_soft);
 void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uint64_t seed, uint64_t step0,
                          int n_draws, uint32_t* keep);
 // pos: exclusive scan of keep

@@ -54,6 +54,21 @@ __global__ void __launch_bounds__(RNT) sample_masks_kernel(const float* __restri
     y_soft[i] = (float)(1.0 / (1.0 + exp(-(z0 - z1) / (double)tau)));
 }
 
+// Deterministic masks with a straight-through estimator (the alternative to
+// Gumbel sampling in the ablation of Sec. 4.3): y = sigmoid(s0 - s1) and
+// M = 1 iff y > threshold, both in double precision.  y_soft = y, so the mask
+// gradient with tau = 1 is the straight-through one, dL/dy = dL/dM.
+__global__ void __launch_bounds__(RNT) threshold_masks_kernel(const float* __restrict__ scores, int64_t n,
+                                                               double threshold, float* __restrict__ m_hard,
+                                                               float* __restrict__ y_soft) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 s = reinterpret_cast<const float2*>(scores)[i];
+    const double y = 1.0 / (1.0 + exp((double)s.y - (double)s.x));
+    m_hard[i] = y > threshold ? 1.f : 0.f;
+    y_soft[i] = (float)y;
+}
+
 // Probabilistic pruning (Sec. 3.5): n_draws hard masks per Gaussian with the
 // rule above (steps step0 .. step0 + n_draws - 1); keep[i] = 1 iff any is 1.
 __global__ void __launch_bounds__(RNT) prune_sample_kernel(const float* __restrict__ scores, int64_t n,
@@ -203,6 +218,13 @@ void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, flo
     if (n == 0) return;
     hipLaunchKernelGGL(sample_masks_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores, n,
                        tau, seed, step, m_hard, y_soft);
+}
+
+void launch_threshold_masks(hipStream_t stream, const float* scores, int64_t n, double threshold, float* m_hard,
+                            float* y_soft) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(threshold_masks_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores,
+                       n, threshold, m_hard, y_soft);
 }
 
 void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uint64_t seed, uint64_t step0,

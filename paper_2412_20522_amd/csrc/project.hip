@@ -236,8 +236,11 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     if (g >= n) return;
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
     const Cov3 cv = cov3(log_scales, quats, g);
-    const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
-    const float mval = masks[g];
+    const float opac_raw = 1.f / (1.f + __expf(-opacity_logits[g]));
+    // mask x opacity (the ablation's alternative): the record's opacity is
+    // M * sigmoid(logit) and its mask 1; masked rasterization keeps them apart
+    const float opac = st.mask_opacity ? masks[g] * opac_raw : opac_raw;
+    const float mval = st.mask_opacity ? 1.f : masks[g];
     float coef[3 * K];
     load_sh<DEG>(sh, g, coef);
     bool bad = false;
@@ -302,8 +305,9 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
 template <int DEG, typename AccT>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
-    const float* __restrict__ opacity_logits, const float* __restrict__ sh, int64_t n, ViewSet views,
-    DevSettings st, const AccT* d_rec, const double* __restrict__ dm_acc, AccT* clear, float* __restrict__ d_means,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh, const float* __restrict__ masks,
+    int64_t n, ViewSet views, DevSettings st, const AccT* d_rec, const double* __restrict__ dm_acc, AccT* clear,
+    float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
     float* __restrict__ d_sh, float* __restrict__ d_masks) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -476,8 +480,12 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         d_log_scales[3 * g + 1] = (float)dls[1];
         d_log_scales[3 * g + 2] = (float)dls[2];
     }
-    if (d_opacity_logits) d_opacity_logits[g] = (float)(gop * opac * (1.0 - opac));
-    if (dm_acc && d_masks) d_masks[g] = (float)dm_acc[g];
+    // mask x opacity: gop is dL/d(M sigmoid(logit)) summed over the views, so
+    // dL/dM = gop sigmoid(logit) and dL/dlogit = gop M sigmoid'(logit); the
+    // compositing's own mask gradient (of records with mask 1) is not used
+    const double mval = st.mask_opacity ? (double)masks[g] : 1.0;
+    if (d_opacity_logits) d_opacity_logits[g] = (float)(gop * mval * opac * (1.0 - opac));
+    if (dm_acc && d_masks) d_masks[g] = (float)(st.mask_opacity ? gop * opac : dm_acc[g]);
     if (d_sh) {
         float* o = d_sh + g * 3 * K;
 #pragma unroll
@@ -513,7 +521,8 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     float* d_masks = dm_acc ? out.d_masks : nullptr;
 #define MGS_PBWD(D)                                                                                               \
     hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats, \
-                       g.opacity_logits, g.sh, g.n, views, st, d_rec, dm_acc, clear, out.d_means, out.d_log_scales, \
+                       g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
+                       out.d_log_scales,                                                                            \
                        out.d_quats, out.d_opacity_logits, out.d_sh, d_masks)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;

@@ -41,7 +41,8 @@ class mgs_settings(C.Structure):
                 ("near_plane", C.c_float), ("dilation", C.c_float), ("jac_clamp", C.c_float),
                 ("lambda_floor", C.c_float), ("bg", C.c_float * 3), ("exact_mode", C.c_int32),
                 ("persistent", C.c_int32), ("fwd_ppt", C.c_int32), ("bwd_ppt", C.c_int32),
-                ("wide_tiles", C.c_int32), ("stats", C.c_int32), ("tile_cull", C.c_int32)]
+                ("wide_tiles", C.c_int32), ("stats", C.c_int32), ("tile_cull", C.c_int32),
+                ("mask_mode", C.c_int32)]
 
 
 class mgs_gaussians(C.Structure):
@@ -64,6 +65,8 @@ STAGES = ("project", "depth_sort", "scan", "duplicate", "sort", "ranges", "compo
 EXPORTS = {"records": 0, "depth": 1, "radius": 2, "tiles": 3, "values": 4, "ranges": 5, "t_final": 6, "last": 7,
            "stats": 8, "order": 9, "evals": 10}
 REGION_TILES = 4  # side of the regions that list wide records, in tiles
+MASK_RASTER = 0   # mgs_settings.mask_mode: masked rasterization (Eq. 3-4, 6)
+MASK_OPACITY = 1  # mgs_settings.mask_mode: M multiplies the opacity (ablation, Sec. 4.3)
 MGS_NUM_STAGES = len(STAGES)
 
 
@@ -115,6 +118,7 @@ _SIGS = {
     "mgs_sample_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _U64, _U64, _VP, _VP]),
     "mgs_reduce_scratch_bytes": (_SZ, [_I64]),
     "mgs_prune_sample": (C.c_int, [_VP, _VP, _VP, _I64, _U64, _U64, C.c_int, _VP]),
+    "mgs_threshold_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _VP, _VP]),
     "mgs_compact_scratch_bytes": (_SZ, [_I64]),
     "mgs_compact_rows": (C.c_int, [_VP, _VP, _VP, _I64, C.c_int, _VP, _VP, _VP, _VP, _VP]),
     "mgs_mask_grad": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _VP, _VP, _VP]),
@@ -401,6 +405,12 @@ def mgs_project_backward(ctx, g: mgs_gaussians, cams, st, d_rec, grads: mgs_grad
 def mgs_sample_masks(ctx, scores, tau: float, seed: int, step: int, m_hard, y_soft, stream=None) -> None:
     _check(ctx, _lib.mgs_sample_masks(ctx, _stream(stream), _ptr(scores, name="scores"), scores.shape[0], tau,
                                       seed, step, _ptr(m_hard, name="m_hard"), _ptr(y_soft, name="y_soft")))
+
+
+def mgs_threshold_masks(ctx, scores, threshold: float, m_hard, y_soft, stream=None) -> None:
+    """Deterministic straight-through masks: m_hard = [sigmoid(s0 - s1) > threshold]."""
+    _check(ctx, _lib.mgs_threshold_masks(ctx, _stream(stream), _ptr(scores, name="scores"), scores.shape[0],
+                                         threshold, _ptr(m_hard, name="m_hard"), _ptr(y_soft, name="y_soft")))
 
 
 def mgs_prune_sample(ctx, scores, seed: int, step0: int, n_draws: int, keep, stream=None) -> None:

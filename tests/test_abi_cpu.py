@@ -50,7 +50,7 @@ def test_default_settings_and_version():
 def test_struct_layouts_match_header():
     M = _lib()
     assert C.sizeof(M.mgs_camera) == 16 * 4 + 4 * 4 + 2 * 4
-    assert C.sizeof(M.mgs_settings) == 4 * 4 + 8 * 4 + 3 * 4 + 7 * 4
+    assert C.sizeof(M.mgs_settings) == 4 * 4 + 8 * 4 + 3 * 4 + 8 * 4
     assert C.sizeof(M.mgs_eval_counts) == 6 * 8
     assert C.sizeof(M.mgs_gaussians) == 6 * 8 + 8
 
