@@ -238,6 +238,33 @@ def render_fwd(widths, heights, n: int, mean2d, conic, opacity, color, mask, lis
     return out
 
 
+def importance(widths, heights, n: int, mean2d, conic, opacity, color, mask, lists: Lists, st: RasterSettings):
+    """Per Gaussian, the sum and the maximum over every pixel of every view of
+    the blending weight M_i alpha_i T_i (the alpha T of score-based pruning,
+    Sec. 2; Sec. 3.4).  Returns (imp_sum [n], imp_max [n])."""
+    w = np.ascontiguousarray(widths, np.int32)
+    h = np.ascontiguousarray(heights, np.int32)
+    s, m = np.zeros(n), np.zeros(n)
+    stc = st.c()
+    vals = np.ascontiguousarray(lists.vals, np.uint32)
+    ranges = np.ascontiguousarray(lists.ranges, np.uint32)
+    lib().orc_importance(C.c_int(len(w)), _p(w), _p(h), C.byref(stc), C.c_int64(n),
+                         *[_p(a) for a in _splat_args(mean2d, conic, opacity, color, mask)], _p(vals), _p(ranges),
+                         _p(s), _p(m))
+    return s, m
+
+
+def scene_importance(scene: dict, cams: list, mask, st: RasterSettings):
+    """importance() of a scene: projection and lists as in run_pipeline."""
+    n = scene["means"].shape[0]
+    projs = [project(scene, c, st) for c in cams]
+    widths = [c["width"] for c in cams]
+    heights = [c["height"] for c in cams]
+    m2d, con, opa, col, rad, dbits, val = stack_projected(projs)
+    lists = build_lists(widths, heights, n, m2d, rad, dbits, val, st)
+    return importance(widths, heights, n, m2d, con, opa, col, _f64(mask).reshape(-1), lists, st)
+
+
 @dataclass
 class BwdOut:
     d_mean2d: np.ndarray

@@ -624,6 +624,77 @@ ORC_API void orc_render_fwd(int n_views, const int32_t* widths, const int32_t* h
 }
 
 /*
+ * Importance of every Gaussian from the forward (the alpha_i T_i of
+ * score-based pruning, Sec. 2; the factor Eq. 6 carries, Sec. 3.4): over
+ * every pixel of every view, the weight M_i alpha_i T_i with which the
+ * Gaussian enters the pixel's colour in Eq. 3, summed (imp_sum) and
+ * maximised (imp_max), over the entries the pixel blends.  Each thread
+ * accumulates pixels of its own static share; the shares are added in
+ * thread order.
+ */
+ORC_API void orc_importance(int n_views, const int32_t* widths, const int32_t* heights, const orc_settings* st,
+                            int64_t n, const double* mean2d, const double* conic, const double* opacity,
+                            const double* color, const double* mask, const uint32_t* vals, const uint32_t* ranges,
+                            double* imp_sum, double* imp_max) {
+    orc_splats sp = {mean2d, conic, opacity, color, mask, n};
+    orc_view_geom* geo = make_geoms(n_views, widths, heights, st);
+#ifdef _OPENMP
+    const int nt = omp_get_max_threads();
+#else
+    const int nt = 1;
+#endif
+    double* part_sum = (double*)calloc((size_t)nt * (size_t)n + 1, sizeof(double));
+    double* part_max = (double*)calloc((size_t)nt * (size_t)n + 1, sizeof(double));
+    for (int v = 0; v < n_views; v++) {
+        const orc_view_geom gv = geo[v];
+        const int64_t P = (int64_t)gv.w * gv.h;
+#pragma omp parallel num_threads(nt)
+        {
+#ifdef _OPENMP
+            const int tid = omp_get_thread_num();
+#else
+            const int tid = 0;
+#endif
+            double* ps = part_sum + (size_t)tid * (size_t)n;
+            double* pm = part_max + (size_t)tid * (size_t)n;
+            int64_t cap = 1024;
+            orc_blend* list = (orc_blend*)malloc(sizeof(orc_blend) * (size_t)cap);
+#pragma omp for schedule(static)
+            for (int64_t p = 0; p < P; p++) {
+                const int x = (int)(p % gv.w), y = (int)(p / gv.w);
+                const int64_t tile = gv.view_tile_off + (int64_t)(y / st->tile_h) * gv.gw + (x / st->tile_w);
+                const int64_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+                if (e - s > cap) {
+                    cap = e - s;
+                    list = (orc_blend*)realloc(list, sizeof(orc_blend) * (size_t)cap);
+                }
+                orc_pixel px;
+                composite_pixel(&sp, vals, s, e, x + 0.5, y + 0.5, st, list, &px);
+                for (int64_t i = 0; i < px.n_blend; i++) {
+                    const int64_t g = (int64_t)(list[i].rec % (uint32_t)n);
+                    const double w = mask[g] * list[i].alpha * list[i].T;
+                    ps[g] += w;
+                    if (w > pm[g]) pm[g] = w;
+                }
+            }
+            free(list);
+        }
+    }
+    for (int64_t g = 0; g < n; g++) {
+        double s = 0.0, m = 0.0;
+        for (int t = 0; t < nt; t++) {
+            s += part_sum[(size_t)t * (size_t)n + (size_t)g];
+            if (part_max[(size_t)t * (size_t)n + (size_t)g] > m) m = part_max[(size_t)t * (size_t)n + (size_t)g];
+        }
+        imp_sum[g] = s;
+        imp_max[g] = m;
+    }
+    free(part_sum);
+    free(part_max);
+    free(geo);
+}
+
+/*
  * Backward over every pixel of every view.  dL_dimage has the image layout.
  * Gradients are accumulated per record (view, Gaussian) for the 2D
  * quantities and per Gaussian for the mask.  touched_flagged[rec] is set for
