@@ -215,6 +215,21 @@ MGS_API mgs_status mgs_frame_get_stats(const mgs_frame* frame, mgs_frame_stats* 
 MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
                                int n_views, const mgs_settings* st, float* images, float* t_final);
 
+/* mgs_forward that also returns the importance by-products of the
+ * compositing: the weight w = M_i alpha_i T_i with which Gaussian i enters a
+ * pixel's colour (Eq. 3; the alpha_i T_i that score-based pruning ranks by,
+ * Sec. 2, and that Eq. 6 contains, Sec. 3.4), summed (imp_sum [n]) and
+ * maximised (imp_max [n]) over every pixel of every view where the Gaussian
+ * is blended (after the alpha filter, before the early stop).  Both device,
+ * caller-owned, float32, overwritten; the sums accumulate in FP64 and are
+ * rounded once.  A masked Gaussian scores 0.  Per pixel the weights and the
+ * final transmittance add up to 1.  The frame supports mgs_backward as after
+ * mgs_forward, but keeps no work counters.  The first call on a frame with a
+ * fixed workspace allocates an n-element FP64 accumulator. */
+MGS_API mgs_status mgs_forward_importance(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g,
+                                          const mgs_camera* cams, int n_views, const mgs_settings* st, float* images,
+                                          float* t_final, float* imp_sum, float* imp_max);
+
 /* Backward of the last mgs_forward on this frame (Eq. 6 with the
  * supplementary recursion and background term; reverse traversal with the
  * transmittance recovered by division).  dl_dimages [3 * P] is the gradient

@@ -285,6 +285,7 @@ struct mgs_frame {
         evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
+    DevBuf imp_acc;  // FP64 sums of the importance forward
     // d_rec is all zeros between backwards (the projection backward clears
     // the rows it reads); false until a fill after (re)allocation
     bool drec_zero = false;
@@ -479,8 +480,9 @@ mgs_status mgs_frame_check(mgs_frame* f, mgs_stream stream_) {
     return MGS_OK;
 }
 
-mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g, const mgs_camera* cams, int n_views,
-                       const mgs_settings* st, float* images, float* t_final_out) {
+namespace {
+mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g, const mgs_camera* cams, int n_views,
+                        const mgs_settings* st, float* images, float* t_final_out, float* imp_sum, float* imp_max) {
     if (!f) return MGS_ERR_INVALID_ARG;
     mgs_ctx* ctx = f->ctx;
     hipStream_t stream = (hipStream_t)stream_;
@@ -621,18 +623,42 @@ mgs_status mgs_forward(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g,
         launch_fill_u32(stream, queue, 1, 0u);
     }
     launch_fill_u32(stream, f->stg_count(), 1, 0u);
+    const bool imp = imp_sum != nullptr;
+    if (imp) {
+        if ((s = grow(ctx, f->imp_acc, (size_t)f->n * 8 + 8))) return s;
+        launch_fill_u32(stream, (uint32_t*)f->imp_acc.p, 2 * f->n, 0u);
+        launch_fill_u32(stream, (uint32_t*)imp_max, f->n, 0u);
+    }
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
-        f->have_stats = st->stats != 0;
+        f->have_stats = st->stats != 0 && !imp;
         launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st, images,
                           (float*)f->t_final.p, (int32_t*)f->last.p, f->have_stats ? (int32_t*)f->stats.p : nullptr,
-                          f->have_stats ? (int32_t*)f->evals.p : nullptr, queue, ctx->num_cus);
+                          f->have_stats ? (int32_t*)f->evals.p : nullptr, queue, ctx->num_cus, f->n,
+                          imp ? (double*)f->imp_acc.p : nullptr, imp ? (uint32_t*)imp_max : nullptr);
     }
+    if (imp) launch_round_f64(stream, (const double*)f->imp_acc.p, imp_sum, f->n);
     MGS_CHECK_LAUNCH(ctx);
     if (t_final_out)
         MGS_HIP(ctx, hipMemcpyAsync(t_final_out, f->t_final.p, (size_t)P * 4, hipMemcpyDeviceToDevice, stream));
     f->have_forward = true;
     return MGS_OK;
+}
+}  // namespace
+
+mgs_status mgs_forward(mgs_frame* f, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams, int n_views,
+                       const mgs_settings* st, float* images, float* t_final) {
+    return forward_impl(f, stream, g, cams, n_views, st, images, t_final, nullptr, nullptr);
+}
+
+mgs_status mgs_forward_importance(mgs_frame* f, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
+                                  int n_views, const mgs_settings* st, float* images, float* t_final,
+                                  float* imp_sum, float* imp_max) {
+    if (!f) return MGS_ERR_INVALID_ARG;
+    if (g && g->n > 0 && (!imp_sum || !imp_max))
+        return fail(f->ctx, MGS_ERR_INVALID_ARG, "imp_sum and imp_max are required");
+    if (g && g->n == 0) return forward_impl(f, stream, g, cams, n_views, st, images, t_final, nullptr, nullptr);
+    return forward_impl(f, stream, g, cams, n_views, st, images, t_final, imp_sum, imp_max);
 }
 
 mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimages, const mgs_gradients* grads) {

@@ -124,6 +124,24 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Maximum over the 64 lanes of a wave of non-negative values, with the
+// pattern of wave_sum (lanes a DPP step leaves out contribute 0).
+__device__ __forceinline__ float wave_max(float v) {
+    int x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x124, 0xf, 0xf, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false)));
+    x = __float_as_int(v);
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ double block_sum_double(double v, double* sh) {
     // 256-thread block: wave partials through LDS, deterministic order.
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);

@@ -830,11 +830,15 @@ struct HybridLists {
 };
 
 // STATS: write the per-pixel work counters (stats_out, eval_out).
-template <int TW, int TH, int PPT, bool STATS>
+// IMP: accumulate every Gaussian's blending weights M alpha T over the
+// pixels it enters: the wave's sum (FP64 atomic) into imp_sum and its
+// maximum (as float bits, the weights being non-negative) into imp_max.
+template <int TW, int TH, int PPT, bool STATS, bool IMP>
 __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
     float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
-    int4* __restrict__ eval_out, uint32_t* __restrict__ queue) {
+    int4* __restrict__ eval_out, uint32_t* __restrict__ queue, int64_t n, double* __restrict__ imp_sum,
+    uint32_t* __restrict__ imp_max) {
     constexpr int NT = TW * TH / PPT;
     extern __shared__ __align__(16) char smem[];
     __shared__ uint32_t s_tile;
@@ -902,6 +906,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
                 if (!__any(active)) break;
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
                 const int k = m + __float_as_int(B.w);  // index in the tile's full list
+                float isum = 0.f, imax = 0.f;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
                     if (done[i]) continue;
@@ -925,6 +930,18 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
                         ++nblend[i];
                         nmasked[i] += B.z == 0.f;
                         nev_last[i] = nev[i];
+                    }
+                    if (IMP) {
+                        isum += wgt;
+                        imax = fmaxf(imax, wgt);
+                    }
+                }
+                if (IMP && __any(isum > 0.f)) {
+                    const float ws = wave_sum(isum), wm = wave_max(imax);
+                    if (lane_id() == 0) {
+                        const int64_t g = (int64_t)__float_as_uint(Cc.w) - (int64_t)tg.vi * n;
+                        atomicAdd(imp_sum + g, (double)ws);
+                        atomicMax(imp_max + g, __float_as_uint(wm));
                     }
                 }
                 active = false;
@@ -1150,30 +1167,36 @@ int cached_grid(int (&cache)[4], Kernel k, int block, int num_cus, int batch) {
     return cache[idx];
 }
 
-template <int TW, int TH, int PPT, bool STATS>
+template <int TW, int TH, int PPT, bool STATS, bool IMP>
 void hybrid_fwd_s(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
-                  int32_t* evals, uint32_t* queue) {
+                  int32_t* evals, uint32_t* queue, int64_t n, double* imp_sum, uint32_t* imp_max) {
     int grid = (int)views.total_tiles;
     if (queue) {
         static int cache[4] = {0, 0, 0, 0};
-        grid = min(cached_grid(cache, hybrid_fwd_kernel<TW, TH, PPT, STATS>, TW * TH / PPT, num_cus, st.batch),
+        grid = min(cached_grid(cache, hybrid_fwd_kernel<TW, TH, PPT, STATS, IMP>, TW * TH / PPT, num_cus,
+                               st.batch),
                    grid);
     }
-    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT, STATS>), dim3(grid), dim3(TW * TH / PPT),
+    hipLaunchKernelGGL((hybrid_fwd_kernel<TW, TH, PPT, STATS, IMP>), dim3(grid), dim3(TW * TH / PPT),
                        lds_bytes(st.batch), s, reinterpret_cast<const float4*>(srec), hl, views, st, images, t_final,
-                       last, reinterpret_cast<int4*>(stats), reinterpret_cast<int4*>(evals), queue);
+                       last, reinterpret_cast<int4*>(stats), reinterpret_cast<int4*>(evals), queue, n, imp_sum,
+                       imp_max);
 }
 
 template <int TW, int TH, int PPT>
 void hybrid_fwd_t(hipStream_t s, int num_cus, const float* srec, const HybridLists& hl, const ViewSet& views,
                   const DevSettings& st, float* images, float* t_final, int32_t* last, int32_t* stats,
-                  int32_t* evals, uint32_t* queue) {
-    if (stats && evals)
-        hybrid_fwd_s<TW, TH, PPT, true>(s, num_cus, srec, hl, views, st, images, t_final, last, stats, evals, queue);
+                  int32_t* evals, uint32_t* queue, int64_t n, double* imp_sum, uint32_t* imp_max) {
+    if (imp_sum && imp_max)
+        hybrid_fwd_s<TW, TH, PPT, false, true>(s, num_cus, srec, hl, views, st, images, t_final, last, nullptr,
+                                               nullptr, queue, n, imp_sum, imp_max);
+    else if (stats && evals)
+        hybrid_fwd_s<TW, TH, PPT, true, false>(s, num_cus, srec, hl, views, st, images, t_final, last, stats, evals,
+                                               queue, n, nullptr, nullptr);
     else
-        hybrid_fwd_s<TW, TH, PPT, false>(s, num_cus, srec, hl, views, st, images, t_final, last, nullptr, nullptr,
-                                         queue);
+        hybrid_fwd_s<TW, TH, PPT, false, false>(s, num_cus, srec, hl, views, st, images, t_final, last, nullptr,
+                                                nullptr, queue, n, nullptr, nullptr);
 }
 
 template <int TW, int TH, int PPT>
@@ -1260,13 +1283,15 @@ void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet
 
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
-                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus) {
+                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus, int64_t n, double* imp_sum,
+                       uint32_t* imp_max) {
     if (views.total_tiles == 0) return;
     const HybridLists hl = make_lists(bufs);
-#define MGS_HFWD(A, B, P)                                                                                        \
-    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                    \
-        hybrid_fwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, images, t_final, last, stats, evals, queue); \
-        return;                                                                                                  \
+#define MGS_HFWD(A, B, P)                                                                                          \
+    if (cfg.tile_w == A && cfg.tile_h == B && cfg.ppt == P) {                                                      \
+        hybrid_fwd_t<A, B, P>(stream, num_cus, srec, hl, views, st, images, t_final, last, stats, evals, queue, n, \
+                              imp_sum, imp_max);                                                                   \
+        return;                                                                                                    \
     }
     MGS_HYBRID_SHAPES(MGS_HFWD)
 #undef MGS_HFWD

@@ -104,9 +104,13 @@ struct HybridBuffers {
 // stats [P, 4] (examined, blended, blended with mask 0, last + 1) and evals
 // [P, 4] (evaluated, evaluated up to the last blended entry, 0, 0) are
 // written only when both are non-null.
+// imp_sum (FP64, zeroed) and imp_max (float bits, zeroed), both [n] or both
+// null: per-Gaussian sum and maximum of the blending weights M alpha T.
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, float* images, float* t_final, int32_t* last,
-                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus);
+                       int32_t* stats, int32_t* evals, uint32_t* queue, int num_cus, int64_t n = 0,
+                       double* imp_sum = nullptr, uint32_t* imp_max = nullptr);
+void launch_round_f64(hipStream_t stream, const double* in, float* out, int64_t n);
 void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,
                        const ViewSet& views, const DevSettings& st, const float* t_final, const int32_t* last,
                        const float* dl_dimages, int64_t n, double* d_rec, double* d_masks, uint32_t* queue,

@@ -385,6 +385,12 @@ __global__ void __launch_bounds__(256) fill_f32_kernel(float* __restrict__ p, in
     if (i < n) p[i] = v;
 }
 
+__global__ void __launch_bounds__(256) round_f64_kernel(const double* __restrict__ in, float* __restrict__ out,
+                                                         int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 __global__ void __launch_bounds__(NT) sum_i32_partial_kernel(const int32_t* __restrict__ in, int64_t n,
                                                               uint64_t* __restrict__ partial) {
     __shared__ uint64_t sh[NT / 64];
@@ -529,6 +535,11 @@ void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, c
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {
     if (n <= 0) return;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+}
+
+void launch_round_f64(hipStream_t stream, const double* in, float* out, int64_t n) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(round_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, in, out, n);
 }
 
 void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value) {

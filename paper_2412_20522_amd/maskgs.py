@@ -90,6 +90,8 @@ _SIGS = {
     "mgs_frame_get_stats": (C.c_int, [_VP, C.POINTER(mgs_frame_stats)]),
     "mgs_forward": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                               C.POINTER(mgs_settings), _VP, _VP]),
+    "mgs_forward_importance": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
+                                         C.POINTER(mgs_settings), _VP, _VP, _VP, _VP]),
     "mgs_backward": (C.c_int, [_VP, _VP, _VP, C.POINTER(mgs_gradients)]),
     "mgs_frame_reserve": (C.c_int, [_VP, _VP, C.c_double]),
     "mgs_frame_check": (C.c_int, [_VP, _VP]),
@@ -277,6 +279,17 @@ def mgs_forward(ctx, frame, g: mgs_gaussians, cams: Sequence[dict], st: mgs_sett
     ca = cameras_array(cams)
     _check(ctx, _lib.mgs_forward(frame, _stream(stream), C.byref(g), ca, len(cams), C.byref(st),
                                  _ptr(images, name="images"), _ptr(t_final, name="t_final")))
+
+
+def mgs_forward_importance(ctx, frame, g: mgs_gaussians, cams: Sequence[dict], st: mgs_settings,
+                           images: torch.Tensor, imp_sum: torch.Tensor, imp_max: torch.Tensor,
+                           t_final: Optional[torch.Tensor] = None, stream=None) -> None:
+    """mgs_forward plus per-Gaussian sum and maximum of the blending weights
+    M alpha T over every pixel of every view (imp_sum, imp_max: [n] float32)."""
+    ca = cameras_array(cams)
+    _check(ctx, _lib.mgs_forward_importance(frame, _stream(stream), C.byref(g), ca, len(cams), C.byref(st),
+                                            _ptr(images, name="images"), _ptr(t_final, name="t_final"),
+                                            _ptr(imp_sum, name="imp_sum"), _ptr(imp_max, name="imp_max")))
 
 
 def mgs_backward(ctx, frame, dl_dimages: torch.Tensor, grads: mgs_gradients, stream=None) -> None:

@@ -89,6 +89,24 @@ class Rasterizer:
         M.mgs_forward(self.ctx, frame, g, cams, self.settings, images, t_final)
         return images
 
+    def forward_importance(self, frame, params: dict, masks: torch.Tensor, cams: Sequence[dict],
+                           images: Optional[torch.Tensor] = None, imp_sum: Optional[torch.Tensor] = None,
+                           imp_max: Optional[torch.Tensor] = None):
+        """forward() that also returns each Gaussian's sum and maximum of its
+        blending weights M alpha T over every pixel of every view (the scores
+        of score-based pruning): (images, imp_sum, imp_max)."""
+        dev = params["means"].device
+        n = params["means"].shape[0]
+        if images is None:
+            images = torch.empty(3 * total_pixels(cams), dtype=torch.float32, device=dev)
+        if imp_sum is None:
+            imp_sum = torch.empty(n, dtype=torch.float32, device=dev)
+        if imp_max is None:
+            imp_max = torch.empty(n, dtype=torch.float32, device=dev)
+        g = M.gaussians_struct(*(params[k] for k in PARAM_KEYS), masks)
+        M.mgs_forward_importance(self.ctx, frame, g, cams, self.settings, images, imp_sum, imp_max)
+        return images, imp_sum, imp_max
+
     def backward(self, frame, params: dict, dl_dimages: torch.Tensor, out: Optional[Grads] = None) -> Grads:
         if out is None:
             out = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS),
