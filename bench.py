@@ -200,20 +200,28 @@ def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 5)
 
     frames = []
 
-    def render_ms(ps: dict, count: int) -> float:
+    def render_ms(ps: dict, count: int, importance: bool = False) -> float:
         fr = rast.acquire_frame()  # a frame of its own (fixed workspaces are per frame)
         frames.append(fr)
         ones = torch.ones(count, device=dev)
         imgs = torch.empty(3 * sum(c["width"] * c["height"] for c in cams), device=dev)
-        rast.forward(fr, ps, ones, cams, images=imgs)
+        isum, imax = torch.empty(count, device=dev), torch.empty(count, device=dev)
+
+        def once():
+            if importance:
+                rast.forward_importance(fr, ps, ones, cams, images=imgs, imp_sum=isum, imp_max=imax)
+            else:
+                rast.forward(fr, ps, ones, cams, images=imgs)
+
+        once()
         rast.reserve(fr, 1.25)  # fixed workspace: no host synchronisation per forward
         for _ in range(2):
-            rast.forward(fr, ps, ones, cams, images=imgs)
+            once()
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(reps):
-            rast.forward(fr, ps, ones, cams, images=imgs)
+            once()
         b.record()
         torch.cuda.synchronize()
         rast.check(fr)
@@ -221,6 +229,7 @@ def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 5)
 
     full_ms = render_ms(params, n)
     pr_ms = render_ms({key: pruned[key] for key in PARAM_KEYS}, k)
+    imp_ms = render_ms(params, n, importance=True)
     for fr in frames:
         rast.release_frame(fr)
     V = len(cams)
@@ -231,6 +240,9 @@ def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 5)
         "render_only": {"full": {"ms": full_ms, "views_per_s": V / (full_ms * 1e-3), "gaussians": n},
                         "pruned": {"ms": pr_ms, "views_per_s": V / (pr_ms * 1e-3), "gaussians": k},
                         "speedup": full_ms / pr_ms},
+        "importance": {"ms": imp_ms, "overhead_vs_forward": imp_ms / full_ms - 1.0,
+                       "what": "forward-only render of the full set that also returns every Gaussian's sum and "
+                               "max of M alpha T"},
     }
 
 
@@ -446,7 +458,7 @@ def main() -> int:
         log(f"[bench] pruning: {extras['prune']['ms']:.3f} ms ({extras['prune']['kept']} of {n} kept, "
             f"{extras['prune']['GB_per_s']:.0f} GB/s); forward only: full {extras['render_only']['full']['ms']:.3f} ms, "
             f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {V} views "
-            f"(x{extras['render_only']['speedup']:.2f})")
+            f"(x{extras['render_only']['speedup']:.2f}); with importance {extras['importance']['ms']:.3f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -490,6 +502,7 @@ def main() -> int:
             "plain": plain,
             "pruning": extras["prune"] if extras else None,
             "render_only": extras["render_only"] if extras else None,
+            "importance": extras["importance"] if extras else None,
             "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if prof[k][1]},
         },
         "roofline": roof,
