@@ -154,7 +154,7 @@ def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: flo
             "views_per_s": len(done) / dt, "seconds": dt}
 
 
-def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 5) -> dict:
+def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 20) -> dict:
     """Probabilistic pruning (10 draws) of a whole per-Gaussian training state
     (parameters, mask scores and both Adam moments of each: 183 floats per
     Gaussian) whose scores are those of late training (62.4 % of the Gaussians
