@@ -126,13 +126,11 @@ struct Cov3 {
     double S[6];     // covariance entries 00, 01, 02, 11, 12, 22
 };
 
-__device__ __forceinline__ Cov3 cov3(const float* __restrict__ log_scales, const float* __restrict__ quats,
-                                     int64_t g) {
+__device__ __forceinline__ Cov3 cov3_of(float l0, float l1, float l2, float4 q4) {
     Cov3 c;
-    c.s[0] = exp((double)log_scales[3 * g]);
-    c.s[1] = exp((double)log_scales[3 * g + 1]);
-    c.s[2] = exp((double)log_scales[3 * g + 2]);
-    const float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+    c.s[0] = exp((double)l0);
+    c.s[1] = exp((double)l1);
+    c.s[2] = exp((double)l2);
     const double qw = q4.x, qx = q4.y, qy = q4.z, qz = q4.w;
     c.qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     const double w = qw * c.qinv, x = qx * c.qinv, y = qy * c.qinv, z = qz * c.qinv;
@@ -152,6 +150,12 @@ __device__ __forceinline__ Cov3 cov3(const float* __restrict__ log_scales, const
     c.S[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
     c.S[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
     return c;
+}
+
+__device__ __forceinline__ Cov3 cov3(const float* __restrict__ log_scales, const float* __restrict__ quats,
+                                     int64_t g) {
+    return cov3_of(log_scales[3 * g], log_scales[3 * g + 1], log_scales[3 * g + 2],
+                   reinterpret_cast<const float4*>(quats)[g]);
 }
 
 struct ViewGeom {
@@ -314,171 +318,206 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
-    const Cov3 cv = cov3(log_scales, quats, g);
     const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
-    float coef[3 * K];
-    load_sh<DEG>(sh, g, coef);
-
-    double gS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma3 (symmetric full-matrix gradient)
+    // Two passes over the views, so that the double-precision covariance
+    // chain and the SH colour (coefficients and their gradients) are never
+    // live together: one pass holding both needs more than 256 registers,
+    // which leaves one wave per SIMD.  The first pass notes which views
+    // project validly; the second reads the colour gradients and clears the
+    // rows.
+    uint32_t valid = 0;
     double gp[3] = {0.0, 0.0, 0.0};
     double gop = 0.0;
-    float gsh[3 * K];
+    {
+        // the loop needs the 3D covariance only; rotation and scales are
+        // formed again after it
+        double Sig[6];
+        {
+            const Cov3 c0 = cov3(log_scales, quats, g);
 #pragma unroll
-    for (int i = 0; i < 3 * K; ++i) gsh[i] = 0.f;
-
-    for (int vi = 0; vi < views.n_views; ++vi) {
-        const DevView& cam = views.v[vi];
-        const int64_t r = (int64_t)vi * n + g;
-        const ViewGeom o = view_geom(cam, st, px, py, pz, cv.S);
-        if (!o.valid) continue;
-        const AccT* dr = d_rec + r * DREC;
-        const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
-        const AccT dcol_in[3] = {dr[6], dr[7], dr[8]};
-        gop += (double)dr[5];
-        if (clear) {
-#pragma unroll
-            for (int q = 0; q < DREC; ++q) clear[r * DREC + q] = (AccT)0;
+            for (int i = 0; i < 6; ++i) Sig[i] = c0.S[i];
         }
-        // colour: SH coefficients and viewing direction
-        float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
-        const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= dinv; dy *= dinv; dz *= dinv;
-        float Y[K];
-        sh_basis<DEG>(dx, dy, dz, Y);
-        float dcol[3];
+        double gS[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/dSigma3 (symmetric full-matrix gradient)
+        for (int vi = 0; vi < views.n_views; ++vi) {
+            const DevView& cam = views.v[vi];
+            const int64_t r = (int64_t)vi * n + g;
+            const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
+            if (!o.valid) continue;
+            valid |= 1u << vi;
+            const AccT* dr = d_rec + r * DREC;
+            const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
+            gop += (double)dr[5];
+            // stored conic (a, beta, gamma) = (c / det, -b / c, 1 / c) of the 2D
+            // covariance [[a, b], [b, c]] -> H = dL/dcov2D (symmetric, H01 is half
+            // the derivative w.r.t. the shared off-diagonal entry).  The per-pixel
+            // sums arrive in this basis because it keeps the thin direction of a
+            // needle apart from the long one in FP32.
+            const double s2 = o.c * o.c, idet2 = 1.0 / (o.detv * o.detv);
+            const double H00 = -dca * s2 * idet2;
+            const double H01 = 0.5 * (2.0 * dca * o.b * o.c * idet2 - dcb / o.c);
+            const double H11 = (-dca * o.b * o.b * idet2 + dcb * o.b / s2) - dcc / s2;
+            // dSigma3 += T^T H T ; dT = 2 H T Sigma3
+            double HT0[3], HT1[3];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.5f;
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
-            dcol[ch] = acc < 0.f ? 0.f : (float)dcol_in[ch];
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            gsh[3 * k] += dcol[0] * Y[k];
-            gsh[3 * k + 1] += dcol[1] * Y[k];
-            gsh[3 * k + 2] += dcol[2] * Y[k];
-        }
-        if (DEG > 0) {
-            float D[K][3];
-            sh_basis_grad<DEG>(dx, dy, dz, D);
-            float dd[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 1; k < K; ++k) {
-                const float w = dcol[0] * coef[3 * k] + dcol[1] * coef[3 * k + 1] + dcol[2] * coef[3 * k + 2];
-                dd[0] += w * D[k][0];
-                dd[1] += w * D[k][1];
-                dd[2] += w * D[k][2];
+            for (int j = 0; j < 3; ++j) {
+                HT0[j] = H00 * o.T0[j] + H01 * o.T1[j];
+                HT1[j] = H01 * o.T0[j] + H11 * o.T1[j];
             }
-            const float proj = dd[0] * dx + dd[1] * dy + dd[2] * dz;
-            gp[0] += (dd[0] - proj * dx) * dinv;
-            gp[1] += (dd[1] - proj * dy) * dinv;
-            gp[2] += (dd[2] - proj * dz) * dinv;
+            gS[0] += o.T0[0] * HT0[0] + o.T1[0] * HT1[0];
+            gS[1] += o.T0[0] * HT0[1] + o.T1[0] * HT1[1];
+            gS[2] += o.T0[0] * HT0[2] + o.T1[0] * HT1[2];
+            gS[3] += o.T0[1] * HT0[1] + o.T1[1] * HT1[1];
+            gS[4] += o.T0[1] * HT0[2] + o.T1[1] * HT1[2];
+            gS[5] += o.T0[2] * HT0[2] + o.T1[2] * HT1[2];
+            const double* S = Sig;
+            double dT0[3], dT1[3];
+            dT0[0] = 2.0 * (HT0[0] * S[0] + HT0[1] * S[1] + HT0[2] * S[2]);
+            dT0[1] = 2.0 * (HT0[0] * S[1] + HT0[1] * S[3] + HT0[2] * S[4]);
+            dT0[2] = 2.0 * (HT0[0] * S[2] + HT0[1] * S[4] + HT0[2] * S[5]);
+            dT1[0] = 2.0 * (HT1[0] * S[0] + HT1[1] * S[1] + HT1[2] * S[2]);
+            dT1[1] = 2.0 * (HT1[0] * S[1] + HT1[1] * S[3] + HT1[2] * S[4]);
+            dT1[2] = 2.0 * (HT1[0] * S[2] + HT1[1] * S[4] + HT1[2] * S[5]);
+            // T = J W  ->  dJ = dT W^T (only J00, J02, J11, J12 are variables)
+            const double W0 = cam.W[0], W1 = cam.W[1], W2 = cam.W[2], W3 = cam.W[3], W4 = cam.W[4], W5 = cam.W[5];
+            const double W6 = cam.W[6], W7 = cam.W[7], W8 = cam.W[8];
+            const double dJ00 = dT0[0] * W0 + dT0[1] * W1 + dT0[2] * W2;
+            const double dJ02 = dT0[0] * W6 + dT0[1] * W7 + dT0[2] * W8;
+            const double dJ11 = dT1[0] * W3 + dT1[1] * W4 + dT1[2] * W5;
+            const double dJ12 = dT1[0] * W6 + dT1[1] * W7 + dT1[2] * W8;
+            // view-space centre
+            const double fx = cam.fx, fy = cam.fy;
+            const double iz = 1.0 / o.tz, iz2 = iz * iz;
+            double dtx = du * fx * iz;
+            double dty = dv * fy * iz;
+            double dtz = -(du * fx * o.tx + dv * fy * o.ty) * iz2;
+            dtz += -(dJ00 * fx + dJ11 * fy) * iz2;
+            if (!o.clx) {
+                dtx += -dJ02 * fx * iz2;
+                dtz += dJ02 * 2.0 * fx * o.tx * iz2 * iz;
+            } else {
+                dtz += dJ02 * fx * o.sx * iz2;
+            }
+            if (!o.cly) {
+                dty += -dJ12 * fy * iz2;
+                dtz += dJ12 * 2.0 * fy * o.ty * iz2 * iz;
+            } else {
+                dtz += dJ12 * fy * o.sy * iz2;
+            }
+            // t = W p + t  ->  dp = W^T dt
+            gp[0] += W0 * dtx + W3 * dty + W6 * dtz;
+            gp[1] += W1 * dtx + W4 * dty + W7 * dtz;
+            gp[2] += W2 * dtx + W5 * dty + W8 * dtz;
         }
-        // stored conic (a, beta, gamma) = (c / det, -b / c, 1 / c) of the 2D
-        // covariance [[a, b], [b, c]] -> H = dL/dcov2D (symmetric, H01 is half
-        // the derivative w.r.t. the shared off-diagonal entry).  The per-pixel
-        // sums arrive in this basis because it keeps the thin direction of a
-        // needle apart from the long one in FP32.
-        const double s2 = o.c * o.c, idet2 = 1.0 / (o.detv * o.detv);
-        const double H00 = -dca * s2 * idet2;
-        const double H01 = 0.5 * (2.0 * dca * o.b * o.c * idet2 - dcb / o.c);
-        const double H11 = (-dca * o.b * o.b * idet2 + dcb * o.b / s2) - dcc / s2;
-        // dSigma3 += T^T H T ; dT = 2 H T Sigma3
-        double HT0[3], HT1[3];
+        // the inputs pass through an empty asm statement, which hides from
+        // the compiler that they equal the values loaded before the loop, so
+        // it forms rotation and scales anew instead of keeping them live
+        // (in registers) across the loop
+        float l0 = log_scales[3 * g], l1 = log_scales[3 * g + 1], l2 = log_scales[3 * g + 2];
+        float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+        asm volatile("" : "+v"(l0), "+v"(l1), "+v"(l2), "+v"(q4.x), "+v"(q4.y), "+v"(q4.z), "+v"(q4.w));
+        const Cov3 cv = cov3_of(l0, l1, l2, q4);
+        // Sigma3 = R diag(s^2) R^T with G = dL/dSigma3 (symmetric)
+        const double G[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
+        const double* R = cv.R;
+        double GR[9];  // G R
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            HT0[j] = H00 * o.T0[j] + H01 * o.T1[j];
-            HT1[j] = H01 * o.T0[j] + H11 * o.T1[j];
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) GR[3 * i + k] = G[3 * i] * R[k] + G[3 * i + 1] * R[3 + k] + G[3 * i + 2] * R[6 + k];
+        double dR[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) dR[3 * i + k] = 2.0 * GR[3 * i + k] * cv.s[k] * cv.s[k];
+        double dls[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double rgr = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];  // (R^T G R)_kk
+            dls[k] = 2.0 * cv.s[k] * cv.s[k] * rgr;
         }
-        gS[0] += o.T0[0] * HT0[0] + o.T1[0] * HT1[0];
-        gS[1] += o.T0[0] * HT0[1] + o.T1[0] * HT1[1];
-        gS[2] += o.T0[0] * HT0[2] + o.T1[0] * HT1[2];
-        gS[3] += o.T0[1] * HT0[1] + o.T1[1] * HT1[1];
-        gS[4] += o.T0[1] * HT0[2] + o.T1[1] * HT1[2];
-        gS[5] += o.T0[2] * HT0[2] + o.T1[2] * HT1[2];
-        const double* S = cv.S;
-        double dT0[3], dT1[3];
-        dT0[0] = 2.0 * (HT0[0] * S[0] + HT0[1] * S[1] + HT0[2] * S[2]);
-        dT0[1] = 2.0 * (HT0[0] * S[1] + HT0[1] * S[3] + HT0[2] * S[4]);
-        dT0[2] = 2.0 * (HT0[0] * S[2] + HT0[1] * S[4] + HT0[2] * S[5]);
-        dT1[0] = 2.0 * (HT1[0] * S[0] + HT1[1] * S[1] + HT1[2] * S[2]);
-        dT1[1] = 2.0 * (HT1[0] * S[1] + HT1[1] * S[3] + HT1[2] * S[4]);
-        dT1[2] = 2.0 * (HT1[0] * S[2] + HT1[1] * S[4] + HT1[2] * S[5]);
-        // T = J W  ->  dJ = dT W^T (only J00, J02, J11, J12 are variables)
-        const double W0 = cam.W[0], W1 = cam.W[1], W2 = cam.W[2], W3 = cam.W[3], W4 = cam.W[4], W5 = cam.W[5];
-        const double W6 = cam.W[6], W7 = cam.W[7], W8 = cam.W[8];
-        const double dJ00 = dT0[0] * W0 + dT0[1] * W1 + dT0[2] * W2;
-        const double dJ02 = dT0[0] * W6 + dT0[1] * W7 + dT0[2] * W8;
-        const double dJ11 = dT1[0] * W3 + dT1[1] * W4 + dT1[2] * W5;
-        const double dJ12 = dT1[0] * W6 + dT1[1] * W7 + dT1[2] * W8;
-        // view-space centre
-        const double fx = cam.fx, fy = cam.fy;
-        const double iz = 1.0 / o.tz, iz2 = iz * iz;
-        double dtx = du * fx * iz;
-        double dty = dv * fy * iz;
-        double dtz = -(du * fx * o.tx + dv * fy * o.ty) * iz2;
-        dtz += -(dJ00 * fx + dJ11 * fy) * iz2;
-        if (!o.clx) {
-            dtx += -dJ02 * fx * iz2;
-            dtz += dJ02 * 2.0 * fx * o.tx * iz2 * iz;
-        } else {
-            dtz += dJ02 * fx * o.sx * iz2;
+        // rotation matrix -> normalised quaternion -> raw quaternion
+        const double qw = cv.q[0], qx = cv.q[1], qy = cv.q[2], qz = cv.q[3];
+        const double gw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
+        const double gx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
+                                 qw * dR[7] - 2.0 * qx * dR[8]);
+        const double gy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
+                                 qz * dR[7] - 2.0 * qy * dR[8]);
+        const double gz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
+                                 qy * dR[5] + qx * dR[6] + qy * dR[7]);
+        const double dotq = qw * gw + qx * gx + qy * gy + qz * gz;
+        if (d_quats)
+            reinterpret_cast<float4*>(d_quats)[g] =
+                make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
+                            (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
+        if (d_log_scales) {
+            d_log_scales[3 * g] = (float)dls[0];
+            d_log_scales[3 * g + 1] = (float)dls[1];
+            d_log_scales[3 * g + 2] = (float)dls[2];
         }
-        if (!o.cly) {
-            dty += -dJ12 * fy * iz2;
-            dtz += dJ12 * 2.0 * fy * o.ty * iz2 * iz;
-        } else {
-            dtz += dJ12 * fy * o.sy * iz2;
-        }
-        // t = W p + t  ->  dp = W^T dt
-        gp[0] += W0 * dtx + W3 * dty + W6 * dtz;
-        gp[1] += W1 * dtx + W4 * dty + W7 * dtz;
-        gp[2] += W2 * dtx + W5 * dty + W8 * dtz;
     }
-
-    // Sigma3 = R diag(s^2) R^T with G = dL/dSigma3 (symmetric)
-    const double G[9] = {gS[0], gS[1], gS[2], gS[1], gS[3], gS[4], gS[2], gS[4], gS[5]};
-    const double* R = cv.R;
-    double GR[9];  // G R
+    {
+        float coef[3 * K];
+        load_sh<DEG>(sh, g, coef);
+        float gsh[3 * K];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < 3 * K; ++i) gsh[i] = 0.f;
+        for (int vi = 0; vi < views.n_views; ++vi) {
+            if (!((valid >> vi) & 1u)) continue;
+            const DevView& cam = views.v[vi];
+            const int64_t r = (int64_t)vi * n + g;
+            const AccT* dr = d_rec + r * DREC;
+            const AccT dcol_in[3] = {dr[6], dr[7], dr[8]};
+            if (clear) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) GR[3 * i + k] = G[3 * i] * R[k] + G[3 * i + 1] * R[3 + k] + G[3 * i + 2] * R[6 + k];
-    double dR[9];
+                for (int q = 0; q < DREC; ++q) clear[r * DREC + q] = (AccT)0;
+            }
+            // colour: SH coefficients and viewing direction
+            float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
+            const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= dinv; dy *= dinv; dz *= dinv;
+            float Y[K];
+            sh_basis<DEG>(dx, dy, dz, Y);
+            float dcol[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) dR[3 * i + k] = 2.0 * GR[3 * i + k] * cv.s[k] * cv.s[k];
-    double dls[3];
+                for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
+                dcol[ch] = acc < 0.f ? 0.f : (float)dcol_in[ch];
+            }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double rgr = R[k] * GR[k] + R[3 + k] * GR[3 + k] + R[6 + k] * GR[6 + k];  // (R^T G R)_kk
-        dls[k] = 2.0 * cv.s[k] * cv.s[k] * rgr;
+            for (int k = 0; k < K; ++k) {
+                gsh[3 * k] += dcol[0] * Y[k];
+                gsh[3 * k + 1] += dcol[1] * Y[k];
+                gsh[3 * k + 2] += dcol[2] * Y[k];
+            }
+            if (DEG > 0) {
+                float D[K][3];
+                sh_basis_grad<DEG>(dx, dy, dz, D);
+                float dd[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 1; k < K; ++k) {
+                    const float w = dcol[0] * coef[3 * k] + dcol[1] * coef[3 * k + 1] + dcol[2] * coef[3 * k + 2];
+                    dd[0] += w * D[k][0];
+                    dd[1] += w * D[k][1];
+                    dd[2] += w * D[k][2];
+                }
+                const float proj = dd[0] * dx + dd[1] * dy + dd[2] * dz;
+                gp[0] += (dd[0] - proj * dx) * dinv;
+                gp[1] += (dd[1] - proj * dy) * dinv;
+                gp[2] += (dd[2] - proj * dz) * dinv;
+            }
+        }
+        if (d_sh) {
+            float* o = d_sh + g * 3 * K;
+#pragma unroll
+            for (int i = 0; i < 3 * K; ++i) o[i] = gsh[i];
+        }
     }
-    // rotation matrix -> normalised quaternion -> raw quaternion
-    const double qw = cv.q[0], qx = cv.q[1], qy = cv.q[2], qz = cv.q[3];
-    const double gw = 2.0 * (-qz * dR[1] + qy * dR[2] + qz * dR[3] - qx * dR[5] - qy * dR[6] + qx * dR[7]);
-    const double gx = 2.0 * (qy * dR[1] + qz * dR[2] + qy * dR[3] - 2.0 * qx * dR[4] - qw * dR[5] + qz * dR[6] +
-                             qw * dR[7] - 2.0 * qx * dR[8]);
-    const double gy = 2.0 * (-2.0 * qy * dR[0] + qx * dR[1] + qw * dR[2] + qx * dR[3] + qz * dR[5] - qw * dR[6] +
-                             qz * dR[7] - 2.0 * qy * dR[8]);
-    const double gz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
-                             qy * dR[5] + qx * dR[6] + qy * dR[7]);
-    const double dotq = qw * gw + qx * gx + qy * gy + qz * gz;
-    if (d_quats)
-        reinterpret_cast<float4*>(d_quats)[g] =
-            make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
-                        (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
     if (d_means) {
         d_means[3 * g] = (float)gp[0];
         d_means[3 * g + 1] = (float)gp[1];
         d_means[3 * g + 2] = (float)gp[2];
-    }
-    if (d_log_scales) {
-        d_log_scales[3 * g] = (float)dls[0];
-        d_log_scales[3 * g + 1] = (float)dls[1];
-        d_log_scales[3 * g + 2] = (float)dls[2];
     }
     // mask x opacity: gop is dL/d(M sigmoid(logit)) summed over the views, so
     // dL/dM = gop sigmoid(logit) and dL/dlogit = gop M sigmoid'(logit); the
@@ -486,11 +525,6 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     const double mval = st.mask_opacity ? (double)masks[g] : 1.0;
     if (d_opacity_logits) d_opacity_logits[g] = (float)(gop * mval * opac * (1.0 - opac));
     if (dm_acc && d_masks) d_masks[g] = (float)(st.mask_opacity ? gop * opac : dm_acc[g]);
-    if (d_sh) {
-        float* o = d_sh + g * 3 * K;
-#pragma unroll
-        for (int i = 0; i < 3 * K; ++i) o[i] = gsh[i];
-    }
 }
 
 }  // namespace
