@@ -59,12 +59,27 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
 
 __host__ __device__ inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
 
+// Items per thread of the sort's tiles: 8 for 64-bit keys (with 16, the
+// keys, values and ranks a thread holds take 188 registers, two waves per
+// SIMD), 16 for 32-bit keys.
+template <typename KeyT>
+constexpr int sort_ipt() {
+    return sizeof(KeyT) == 8 ? 8 : 16;
+}
+template <typename KeyT>
+constexpr int sort_tile() {
+    return NT * sort_ipt<KeyT>();
+}
+constexpr int SORT_TILE_MIN = NT * 8;  // the smallest sort tile (sizes the histograms)
+
 // Keys per workgroup of the sort: the host's chunk for a known count; with a
 // device-side live count, the live keys are spread evenly over the nb
 // workgroups the grid was sized for.
+template <typename KeyT>
 __device__ __forceinline__ int64_t sort_chunk(int64_t K, const uint64_t* K_dev, int64_t nb, int64_t chunk) {
     if (!K_dev) return chunk;
-    return ((nblocks(K) + nb - 1) / nb) * TILE;
+    constexpr int64_t ST = sort_tile<KeyT>();
+    return (((K + ST - 1) / ST + nb - 1) / nb) * ST;
 }
 
 // ---------------------------------------------------------------------------
@@ -194,7 +209,7 @@ __device__ __forceinline__ uint32_t digit_of(KeyT k, int shift) {
 // Loads are vectorised and coalesced; each lane counts runs of equal digits
 // in registers before touching LDS, so keys clustered by digit (neighbouring
 // tiles of one splat) do not serialise on one LDS counter.
-// Each block owns a contiguous chunk of `chunk` keys (a multiple of TILE),
+// Each block owns a contiguous chunk of `chunk` keys (a multiple of the sort tile),
 // so a couple of thousand blocks cover any K and the digit-major histogram
 // stays small.
 template <typename KeyT>
@@ -202,17 +217,18 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
                                                             const uint64_t* __restrict__ K_dev, int shift,
                                                             uint32_t* __restrict__ hist, int64_t nb, int64_t chunk) {
     constexpr int VEC = 16 / sizeof(KeyT);  // keys per 16-byte load
+    constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
     __shared__ uint32_t h[NT / 64][RADIX];
     const int w = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&h[0][0])[i] = 0u;
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
-    chunk = sort_chunk(K, K_dev, nb, chunk);
+    chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
     const int64_t cbeg = (int64_t)blockIdx.x * chunk;
     const int64_t cend = min(cbeg + chunk, K);
-    for (int64_t base = cbeg; base < cend; base += TILE)
+    for (int64_t base = cbeg; base < cend; base += STILE)
 #pragma unroll
-    for (int j = 0; j < IPT / VEC; ++j) {
+    for (int j = 0; j < SIPT / VEC; ++j) {
         const int64_t i0 = base + ((int64_t)j * NT + threadIdx.x) * VEC;
         KeyT k[VEC];
         int nv = 0;
@@ -257,34 +273,35 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KeyT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
     const uint32_t* __restrict__ hist_scan, int64_t nb, int64_t chunk) {
-    __shared__ KeyT sk[TILE];
-    __shared__ uint32_t sv[TILE];
+    constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
+    __shared__ KeyT sk[STILE];
+    __shared__ uint32_t sv[STILE];
     __shared__ uint32_t wcnt[NT / 64][RADIX];
     __shared__ uint32_t dstart[RADIX];
     __shared__ uint32_t gstart[RADIX];
     __shared__ uint32_t scan_sh[NT / 64];
 
     const int64_t K = live_count(Kcap, K_dev);
-    chunk = sort_chunk(K, K_dev, nb, chunk);
+    chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
     const int64_t cbeg = (int64_t)blockIdx.x * chunk;
     const int64_t cend = min(cbeg + chunk, K);
     if (cbeg >= cend) return;  // uniform over the block
     const int w = threadIdx.x >> 6, lane = lane_id();
     // global start of each digit for this chunk, advanced after every sub-tile
     gstart[threadIdx.x] = hist_scan[(int64_t)threadIdx.x * nb + blockIdx.x];
-    for (int64_t base = cbeg; base < cend; base += TILE) {
-    const int nvalid = (int)min((int64_t)TILE, cend - base);
+    for (int64_t base = cbeg; base < cend; base += STILE) {
+    const int nvalid = (int)min((int64_t)STILE, cend - base);
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
     __syncthreads();
 
-    // wave w owns the contiguous span [w * 1024, (w + 1) * 1024) of the block;
+    // wave w owns the contiguous span [w * 64 SIPT, (w + 1) * 64 SIPT) of the tile;
     // round j covers 64 consecutive items, lane l the (j * 64 + l)-th
-    KeyT key[IPT];
-    uint32_t val[IPT];
-    uint32_t rank[IPT];
+    KeyT key[SIPT];
+    uint32_t val[SIPT];
+    uint32_t rank[SIPT];
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-        const int li = w * (IPT * 64) + j * 64 + lane;
+    for (int j = 0; j < SIPT; ++j) {
+        const int li = w * (SIPT * 64) + j * 64 + lane;
         if (li < nvalid) {
             key[j] = keys_in[base + li];
             val[j] = vals_in[base + li];
@@ -295,7 +312,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
+    for (int j = 0; j < SIPT; ++j) {
         const uint32_t d = digit_of(key[j], shift);
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -326,7 +343,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < IPT; ++j) {
+    for (int j = 0; j < SIPT; ++j) {
         const uint32_t d = digit_of(key[j], shift);
         const uint32_t pos = dstart[d] + wcnt[w][d] + rank[j];
         sk[pos] = key[j];
@@ -342,7 +359,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     }
     __syncthreads();
     // padded items all carry digit 255 and sit past nvalid; they are not counted
-    const uint32_t pad = (threadIdx.x == RADIX - 1) ? (uint32_t)(TILE - nvalid) : 0u;
+    const uint32_t pad = (threadIdx.x == RADIX - 1) ? (uint32_t)(STILE - nvalid) : 0u;
     gstart[threadIdx.x] += digit_total - pad;
     __syncthreads();
     }
@@ -445,9 +462,10 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
     if (K <= 1 && !K_dev) return;
     if (end_bit <= begin_bit) return;
     // about SORT_BLOCKS workgroups, each over a contiguous chunk of whole tiles
-    const int64_t ntiles = nblocks(K > 0 ? K : 1);
+    constexpr int64_t STILE = sort_tile<KeyT>();
+    const int64_t ntiles = ((K > 0 ? K : 1) + STILE - 1) / STILE;
     const int64_t tiles_per_block = (ntiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
-    const int64_t chunk = tiles_per_block * TILE;
+    const int64_t chunk = tiles_per_block * STILE;
     const int64_t nb = (ntiles + tiles_per_block - 1) / tiles_per_block;
     const int64_t hn = nb * RADIX;
     uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
@@ -500,7 +518,9 @@ void launch_duplicate(hipStream_t stream, const float* rec, const float* radius,
 }
 
 size_t sort_scratch_bytes(int64_t K) {
-    const int64_t nb = nblocks(K > 0 ? K : 1);
+    // workgroups of a sort of K keys: at most one per tile of the smallest
+    // tile size, and at most SORT_BLOCKS (the launcher's bound)
+    const int64_t nb = std::min<int64_t>(((K > 0 ? K : 1) + SORT_TILE_MIN - 1) / SORT_TILE_MIN, SORT_BLOCKS);
     const int64_t hist = nb * RADIX;
     return (size_t)hist * sizeof(uint32_t) * 2 + scan_scratch_bytes(hist) + 1024;
 }
