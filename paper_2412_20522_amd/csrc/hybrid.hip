@@ -829,12 +829,16 @@ struct HybridLists {
     uint64_t stg_cap;
 };
 
+// Both compositing kernels are built for at least five waves per SIMD (at
+// most 96 registers): the forward fits without spilling, the backward
+// spills a few values, and both run faster than at four waves (measured on
+// the batched workload: forward 0.65 -> 0.63 ms, backward 1.02 -> 0.99 ms).
 // STATS: write the per-pixel work counters (stats_out, eval_out).
 // IMP: accumulate every Gaussian's blending weights M alpha T over the
 // pixels it enters: the wave's sum (FP64 atomic) into imp_sum and its
 // maximum (as float bits, the weights being non-negative) into imp_max.
 template <int TW, int TH, int PPT, bool STATS, bool IMP>
-__global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
+__global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_fwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
     float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
     int4* __restrict__ eval_out, uint32_t* __restrict__ queue, int64_t n, double* __restrict__ imp_sum,
@@ -996,7 +1000,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) hybrid_fwd_kernel(
 }
 
 template <int TW, int TH, int PPT>
-__global__ void __launch_bounds__(TW * TH / PPT) hybrid_bwd_kernel(
+__global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, const float* __restrict__ t_final,
     const int32_t* __restrict__ last_in, const float* __restrict__ dl_dimages, int64_t n, double* __restrict__ d_rec,
     double* __restrict__ d_masks, uint32_t* __restrict__ queue) {
