@@ -322,9 +322,11 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     // Two passes over the views, so that the double-precision covariance
     // chain and the SH colour (coefficients and their gradients) are never
     // live together: one pass holding both needs more than 256 registers,
-    // which leaves one wave per SIMD.  The first pass notes which views
-    // project validly; the second reads the colour gradients and clears the
-    // rows.
+    // which leaves one wave per SIMD.  The first pass reads each valid
+    // view's whole gradient row once (and clears it), keeping the colour
+    // gradients in LDS (3 floats per view and thread) for the second.
+    extern __shared__ float s_dcol[];  // [n_views][3][blockDim.x]
+    const int tid = threadIdx.x, nth = blockDim.x;
     uint32_t valid = 0;
     double gp[3] = {0.0, 0.0, 0.0};
     double gop = 0.0;
@@ -347,6 +349,12 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             const AccT* dr = d_rec + r * DREC;
             const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
             gop += (double)dr[5];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) s_dcol[(vi * 3 + ch) * nth + tid] = (float)dr[6 + ch];
+            if (clear) {
+#pragma unroll
+                for (int q = 0; q < DREC; ++q) clear[r * DREC + q] = (AccT)0;
+            }
             // stored conic (a, beta, gamma) = (c / det, -b / c, 1 / c) of the 2D
             // covariance [[a, b], [b, c]] -> H = dL/dcov2D (symmetric, H01 is half
             // the derivative w.r.t. the shared off-diagonal entry).  The per-pixel
@@ -464,13 +472,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         for (int vi = 0; vi < views.n_views; ++vi) {
             if (!((valid >> vi) & 1u)) continue;
             const DevView& cam = views.v[vi];
-            const int64_t r = (int64_t)vi * n + g;
-            const AccT* dr = d_rec + r * DREC;
-            const AccT dcol_in[3] = {dr[6], dr[7], dr[8]};
-            if (clear) {
-#pragma unroll
-                for (int q = 0; q < DREC; ++q) clear[r * DREC + q] = (AccT)0;
-            }
+            const float dcol_in[3] = {s_dcol[(vi * 3) * nth + tid], s_dcol[(vi * 3 + 1) * nth + tid],
+                                      s_dcol[(vi * 3 + 2) * nth + tid]};
             // colour: SH coefficients and viewing direction
             float dx = px - cam.campos[0], dy = py - cam.campos[1], dz = pz - cam.campos[2];
             const float dinv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -483,7 +486,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
                 float acc = 0.5f;
 #pragma unroll
                 for (int k = 0; k < K; ++k) acc += coef[3 * k + ch] * Y[k];
-                dcol[ch] = acc < 0.f ? 0.f : (float)dcol_in[ch];
+                dcol[ch] = acc < 0.f ? 0.f : dcol_in[ch];
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -552,9 +555,10 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
                    const AccT* d_rec, const double* dm_acc, AccT* clear, const mgs_gradients& out) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
+    const size_t lds = (size_t)views.n_views * 3 * 256 * sizeof(float);  // colour gradients of every view
     float* d_masks = dm_acc ? out.d_masks : nullptr;
 #define MGS_PBWD(D)                                                                                               \
-    hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats, \
+    hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), lds, stream, g.means, g.log_scales, g.quats, \
                        g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
                        out.d_log_scales,                                                                            \
                        out.d_quats, out.d_opacity_logits, out.d_sh, d_masks)
