@@ -185,3 +185,96 @@ def test_graph_step_matches_oracle(rast):
     finally:
         rast.reserve(frame, 0)
         rast.release_frame(frame)
+
+
+def test_captured_importance_forward_matches_eager(rast):
+    """The importance forward inside a captured step: every replay (with eager
+    work between) gives the eager images bit for bit, the eager maxima bit
+    for bit and the eager sums up to the order of the FP64 atomics."""
+    s = _multiview_scene()
+    dev, params, cams, images, dl, grads = _setup(rast, s)
+    n = params["means"].shape[0]
+    isum, imax = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    frame = rast.acquire_frame()
+    try:
+        def step():
+            rast.forward_importance(frame, params, dev["masks"], cams, images=images, imp_sum=isum, imp_max=imax)
+            rast.backward(frame, params, dl, out=grads)
+
+        step()
+        rast.reserve(frame, 1.25)
+        step()  # first call on the fixed workspace allocates the accumulator
+        rast.check(frame)
+        torch.cuda.synchronize()
+        ref = (images.cpu().numpy().copy(), isum.cpu().numpy().copy(), imax.cpu().numpy().copy())
+        assert np.count_nonzero(ref[1]) > 100
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for rep in range(3):
+            isum.fill_(-1.0)
+            imax.fill_(-1.0)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            rast.check(frame)
+            assert np.array_equal(images.cpu().numpy(), ref[0]), rep
+            assert np.array_equal(imax.cpu().numpy(), ref[2]), rep
+            assert U.rel_err(isum.cpu().numpy(), ref[1]) <= 1e-6, rep
+            _ = (isum * 2.0).sum().item()
+        del graph
+    finally:
+        rast.reserve(frame, 0)
+        rast.release_frame(frame)
+
+
+def test_captured_pruning_matches_eager():
+    """Draws and compaction with a caller-provided scratch are capturable:
+    replays reproduce the eager keep mask, kept count and compacted rows."""
+    from paper_2412_20522_amd import maskgs as M
+    ctx = M.mgs_create(0)
+    n = 50_001
+    rng = np.random.default_rng(21)
+    scores = torch.from_numpy(scenegen.converged_mask_scores(n)).cuda()
+    data = torch.from_numpy(rng.normal(size=(n, 7)).astype(np.float32)).cuda()
+    keep = torch.empty(n, dtype=torch.int32, device="cuda")
+    outs = [torch.empty_like(scores), torch.empty_like(data)]
+    n_kept = torch.zeros(1, dtype=torch.int64, device="cuda")
+    scratch = torch.empty(int(M.lib().mgs_compact_scratch_bytes(n)), dtype=torch.uint8, device="cuda")
+
+    def step():
+        M.mgs_prune_sample(ctx, scores, 77, 500, 10, keep)
+        M.mgs_compact_rows(ctx, keep, [scores, data], outs, n_kept=n_kept, scratch=scratch)
+
+    step()
+    torch.cuda.synchronize()
+    k = int(n_kept.item())
+    ref = [keep.cpu().numpy().copy(), outs[0][:k].cpu().numpy().copy(), outs[1][:k].cpu().numpy().copy()]
+    assert np.array_equal(ref[0].astype(bool), oracle.prune_keep(scenegen.converged_mask_scores(n), 77, 500))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-3.0)
+        n_kept.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(n_kept.item()) == k, rep
+        assert np.array_equal(keep.cpu().numpy(), ref[0]), rep
+        assert np.array_equal(outs[0][:k].cpu().numpy(), ref[1]), rep
+        assert np.array_equal(outs[1][:k].cpu().numpy(), ref[2]), rep
+    del graph

@@ -120,3 +120,30 @@ def test_invalid_mask_mode_is_rejected(rast):
     finally:
         rast.release_frame(frame)
         rast.set(mask_mode=0)
+
+
+def test_opacity_mode_exact_mode_matches_oracle(rast):
+    """No alpha filter, stop or Q cut: mask x opacity against the oracle with
+    fractional masks, where unsampled Gaussians do receive gradients."""
+    s, bg = _scene("tiny")
+    cams = s["cameras"]
+    n = s["means"].shape[0]
+    P = sum(c["width"] * c["height"] for c in cams)
+    rng = np.random.default_rng(19)
+    masks = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    masks[::5] = 0.0
+    dl = rng.normal(size=3 * P).astype(np.float32)
+    st = _settings(s["sh_degree"], bg, 1, -1, 0)
+    st["exact_mode"] = 1
+    img, g = _run(rast, s, cams, masks, dl, **st)
+    ost = oracle.RasterSettings(sh_degree=s["sh_degree"], bg=bg, exact_mode=True)
+    op = oracle.run_pipeline(s, cams, masks.astype(np.float64), ost, dl_dimage=dl.astype(np.float64),
+                             mask_mode="opacity")
+    assert U.rel_err(img, op.fwd.image) <= 2e-4
+    for name, a, b in [("means", g.means, op.grads.means), ("opacity_logits", g.opacity_logits,
+                                                             op.grads.opacity_logits),
+                       ("sh", g.sh, op.grads.sh), ("masks", g.masks, op.bwd.d_mask)]:
+        e = U.rel_err(a.cpu().numpy(), b)
+        assert e <= 2e-3, (name, e)
+    # without the filter an unsampled Gaussian's alpha is 0, not filtered out
+    assert np.count_nonzero(op.bwd.d_mask[masks == 0]) > 0
