@@ -505,7 +505,6 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     f->total_tiles = f->views.total_tiles;
     const int64_t R = f->R, P = f->P, T = f->total_tiles, NR = f->views.total_regions;
     f->tile_bits = bits_for((uint64_t)(T + NR));
-    const int V = n_views;
     if (f->reserved && (R > f->res_R || P > f->res_P || T > f->res_T))
         return fail(ctx, MGS_ERR_CAPACITY,
                     "records %lld, pixels %lld or tiles %lld exceed the reserved workspace (%lld, %lld, %lld)",
@@ -537,11 +536,13 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         // their view; then the sorted record copy, list entry counts and wide
         // flags in that order
         StageTimer t(ctx, stream, MGS_STAGE_DEPTH_SORT);
-        launch_record_keys64(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R, f->n,
-                             (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
+        // 32-bit depth keys sorted within each view's segment of n records:
+        // the order of 64-bit (view, depth) keys in 4 passes instead of 5
+        launch_record_keys(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R,
+                           (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
         bool alt = false;
-        launch_radix_sort(stream, (uint64_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint64_t*)f->rkeys_alt.p,
-                          (uint32_t*)f->rvals_alt.p, R, nullptr, 32 + bits_for((uint64_t)V), f->rsort_tmp.p, &alt);
+        launch_radix_sort_segmented(stream, (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint32_t*)f->rkeys_alt.p,
+                                    (uint32_t*)f->rvals_alt.p, R, f->n, f->rsort_tmp.p, &alt);
         f->order_in_alt = alt;
         launch_permute_classify(stream, f->record_order(), (const float*)f->rec.p, R, f->n, f->views, f->st,
                                 (uint32_t*)f->cnt_sorted.p,

@@ -125,14 +125,16 @@ __device__ __forceinline__ TileBox cell_box(int cx, int cy, int cw, int ch, cons
 // per-region lists, batch checkpoints
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) record_keys64_kernel(const float* __restrict__ depth,
-                                                             const uint32_t* __restrict__ tiles, int64_t R, int64_t n,
-                                                             uint64_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals) {
+// Depth keys of the records, sorted per view (the records of view v are the
+// segment [v n, (v + 1) n)): the float bits of the view-space depth (positive,
+// so the bits order like the values), all ones for a record without tiles,
+// which sorts it after every listed record of its view.
+__global__ void __launch_bounds__(256) record_keys_kernel(const float* __restrict__ depth,
+                                                          const uint32_t* __restrict__ tiles, int64_t R,
+                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
-    const uint64_t v = (uint64_t)(r / n);
-    keys[r] = (v << 32) | (tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu);
+    keys[r] = tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu;
     vals[r] = (uint32_t)r;
 }
 
@@ -1249,11 +1251,10 @@ unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
-                          uint64_t* keys, uint32_t* vals) {
+void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
+                        uint32_t* vals) {
     if (R == 0) return;
-    hipLaunchKernelGGL(record_keys64_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, depth, tiles, R, n, keys,
-                       vals);
+    hipLaunchKernelGGL(record_keys_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, depth, tiles, R, keys, vals);
 }
 
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const float* rec, int64_t R, int64_t n,

@@ -43,6 +43,10 @@ void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, con
 void launch_radix_sort32(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                          int64_t K, const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch,
                          bool* out_in_alt);
+// Stable sort of 32-bit keys (all bits) within consecutive segments of
+// seg_len keys each (at most 16 segments; the last may be shorter).
+void launch_radix_sort_segmented(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                                 uint32_t* vals_alt, int64_t K, int64_t seg_len, void* scratch, bool* out_in_alt);
 void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, const uint64_t* K_dev,
                           int64_t total_tiles, uint32_t* ranges);
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value);
@@ -74,8 +78,9 @@ void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const 
 // are listed per tile, wide records per region (one key space: tile ids, then
 // region ids), with sorted positions as values, and merged per tile while
 // compositing
-void launch_record_keys64(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, int64_t n,
-                          uint64_t* keys, uint32_t* vals);
+// depth keys (u32) and record ids of the records, to be sorted per view
+void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
+                        uint32_t* vals);
 // wide_counts (device u64): [0] = wide records, [2] = their region entries;
 // part: classify_parts_bytes(R) bytes of per-workgroup partial counts
 size_t classify_parts_bytes(int64_t R);

@@ -71,6 +71,7 @@ constexpr int sort_tile() {
     return NT * sort_ipt<KeyT>();
 }
 constexpr int SORT_TILE_MIN = NT * 8;  // the smallest sort tile (sizes the histograms)
+constexpr int64_t MAX_SORT_SEGMENTS = 16;  // segments of a segmented sort (one per view)
 
 // Keys per workgroup of the sort: the host's chunk for a known count; with a
 // device-side live count, the live keys are spread evenly over the nb
@@ -205,7 +206,27 @@ __device__ __forceinline__ uint32_t digit_of(KeyT k, int shift) {
     return (uint32_t)(k >> shift) & (RADIX - 1);
 }
 
-// Per-block digit histograms, written digit-major: hist[d * nb + block].
+// Segments: the keys may form consecutive segments of seg_len keys each
+// (the last one shorter), sorted each on its own: block b works in segment
+// b / nbs, on the (b % nbs)-th chunk of it, and the histograms are laid out
+// (segment, digit, block), so that one exclusive scan over them gives every
+// block's output position for each digit.  With one segment (seg_len >= K,
+// nbs = nb) this is the plain digit-major layout hist[d * nb + block].
+struct SortSeg {
+    int64_t seg, bl, beg, end;  // segment, block within it, chunk [beg, end)
+};
+__device__ __forceinline__ SortSeg sort_seg(int64_t K, int64_t seg_len, int64_t nbs, int64_t chunk) {
+    SortSeg s;
+    s.seg = (int64_t)blockIdx.x / nbs;
+    s.bl = (int64_t)blockIdx.x - s.seg * nbs;
+    const int64_t sbeg = s.seg * seg_len;
+    const int64_t send = min(sbeg + seg_len, K);
+    s.beg = sbeg + s.bl * chunk;
+    s.end = min(s.beg + chunk, send);
+    return s;
+}
+
+// Per-block digit histograms, written (segment, digit, block)-major.
 // Loads are vectorised and coalesced; each lane counts runs of equal digits
 // in registers before touching LDS, so keys clustered by digit (neighbouring
 // tiles of one splat) do not serialise on one LDS counter.
@@ -215,7 +236,8 @@ __device__ __forceinline__ uint32_t digit_of(KeyT k, int shift) {
 template <typename KeyT>
 __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restrict__ keys, int64_t Kcap,
                                                             const uint64_t* __restrict__ K_dev, int shift,
-                                                            uint32_t* __restrict__ hist, int64_t nb, int64_t chunk) {
+                                                            uint32_t* __restrict__ hist, int64_t nb, int64_t chunk,
+                                                            int64_t seg_len, int64_t nbs) {
     constexpr int VEC = 16 / sizeof(KeyT);  // keys per 16-byte load
     constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
     __shared__ uint32_t h[NT / 64][RADIX];
@@ -224,8 +246,8 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
-    const int64_t cbeg = (int64_t)blockIdx.x * chunk;
-    const int64_t cend = min(cbeg + chunk, K);
+    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk);
+    const int64_t cbeg = sg.beg, cend = sg.end;
     for (int64_t base = cbeg; base < cend; base += STILE)
 #pragma unroll
     for (int j = 0; j < SIPT / VEC; ++j) {
@@ -265,14 +287,14 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     uint32_t s = 0;
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) s += h[i][d];
-    hist[(int64_t)d * nb + blockIdx.x] = s;
+    hist[(sg.seg * RADIX + d) * nbs + sg.bl] = s;
 }
 
 template <typename KeyT>
 __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KeyT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
-    const uint32_t* __restrict__ hist_scan, int64_t nb, int64_t chunk) {
+    const uint32_t* __restrict__ hist_scan, int64_t nb, int64_t chunk, int64_t seg_len, int64_t nbs) {
     constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
     __shared__ KeyT sk[STILE];
     __shared__ uint32_t sv[STILE];
@@ -283,12 +305,12 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
 
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
-    const int64_t cbeg = (int64_t)blockIdx.x * chunk;
-    const int64_t cend = min(cbeg + chunk, K);
+    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk);
+    const int64_t cbeg = sg.beg, cend = sg.end;
     if (cbeg >= cend) return;  // uniform over the block
     const int w = threadIdx.x >> 6, lane = lane_id();
     // global start of each digit for this chunk, advanced after every sub-tile
-    gstart[threadIdx.x] = hist_scan[(int64_t)threadIdx.x * nb + blockIdx.x];
+    gstart[threadIdx.x] = hist_scan[(sg.seg * RADIX + threadIdx.x) * nbs + sg.bl];
     for (int64_t base = cbeg; base < cend; base += STILE) {
     const int nvalid = (int)min((int64_t)STILE, cend - base);
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
@@ -455,18 +477,28 @@ __global__ void __launch_bounds__(NT) sum_i32x4_partial_kernel(const int4* __res
     }
 }
 
+// seg_len > 0: the keys form segments of seg_len keys, each sorted on its own
+// (no device-side count then); otherwise one segment.
 template <typename KeyT>
 void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t* vals_alt, int64_t K,
-                  const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch, bool* out_in_alt) {
+                  const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch, bool* out_in_alt,
+                  int64_t seg_len = 0) {
     *out_in_alt = false;
     if (K <= 1 && !K_dev) return;
     if (end_bit <= begin_bit) return;
-    // about SORT_BLOCKS workgroups, each over a contiguous chunk of whole tiles
+    // about SORT_BLOCKS workgroups, each over a contiguous chunk of whole
+    // tiles of one segment
     constexpr int64_t STILE = sort_tile<KeyT>();
-    const int64_t ntiles = ((K > 0 ? K : 1) + STILE - 1) / STILE;
-    const int64_t tiles_per_block = (ntiles + SORT_BLOCKS - 1) / SORT_BLOCKS;
+    const bool segmented = seg_len > 0 && seg_len < K && !K_dev;
+    const int64_t slen = segmented ? seg_len : (K > 0 ? K : 1);
+    const int64_t nseg = segmented ? (K + seg_len - 1) / seg_len : 1;
+    const int64_t per_seg = std::max<int64_t>(1, SORT_BLOCKS / nseg);
+    const int64_t ntiles = (slen + STILE - 1) / STILE;
+    const int64_t tiles_per_block = (ntiles + per_seg - 1) / per_seg;
     const int64_t chunk = tiles_per_block * STILE;
-    const int64_t nb = (ntiles + tiles_per_block - 1) / tiles_per_block;
+    const int64_t nbs = (ntiles + tiles_per_block - 1) / tiles_per_block;
+    const int64_t nb = nseg * nbs;
+    const int64_t seg_arg = segmented ? seg_len : INT64_MAX / 4;
     const int64_t hn = nb * RADIX;
     uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
     uint32_t* hist_scan = hist + hn;
@@ -478,10 +510,10 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
     uint32_t* vout = vals_alt;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         hipLaunchKernelGGL(radix_upsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift,
-                           hist, nb, chunk);
+                           hist, nb, chunk, seg_arg, nbs);
         launch_scan_u32(stream, hist, hn, hist_scan, nullptr, scan_tmp);
         hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout,
-                           K, K_dev, shift, (const uint32_t*)hist_scan, nb, chunk);
+                           K, K_dev, shift, (const uint32_t*)hist_scan, nb, chunk, seg_arg, nbs);
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
         *out_in_alt = !*out_in_alt;
@@ -519,8 +551,10 @@ void launch_duplicate(hipStream_t stream, const float* rec, const float* radius,
 
 size_t sort_scratch_bytes(int64_t K) {
     // workgroups of a sort of K keys: at most one per tile of the smallest
-    // tile size, and at most SORT_BLOCKS (the launcher's bound)
-    const int64_t nb = std::min<int64_t>(((K > 0 ? K : 1) + SORT_TILE_MIN - 1) / SORT_TILE_MIN, SORT_BLOCKS);
+    // tile size plus one per segment (at most MAX_SORT_SEGMENTS), and at
+    // most SORT_BLOCKS (the launcher's bound)
+    const int64_t nb = std::min<int64_t>(((K > 0 ? K : 1) + SORT_TILE_MIN - 1) / SORT_TILE_MIN + MAX_SORT_SEGMENTS,
+                                         SORT_BLOCKS);
     const int64_t hist = nb * RADIX;
     return (size_t)hist * sizeof(uint32_t) * 2 + scan_scratch_bytes(hist) + 1024;
 }
@@ -534,6 +568,12 @@ void launch_radix_sort32(hipStream_t stream, uint32_t* keys, uint32_t* vals, uin
                          int64_t K, const uint64_t* K_dev, int begin_bit, int end_bit, void* scratch,
                          bool* out_in_alt) {
     radix_sort_t<uint32_t>(stream, keys, vals, keys_alt, vals_alt, K, K_dev, begin_bit, end_bit, scratch, out_in_alt);
+}
+
+void launch_radix_sort_segmented(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                                 uint32_t* vals_alt, int64_t K, int64_t seg_len, void* scratch, bool* out_in_alt) {
+    if (seg_len > 0 && (K + seg_len - 1) / seg_len > MAX_SORT_SEGMENTS) seg_len = 0;  // not reached: views <= 16
+    radix_sort_t<uint32_t>(stream, keys, vals, keys_alt, vals_alt, K, nullptr, 0, 32, scratch, out_in_alt, seg_len);
 }
 
 void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, const uint64_t* K_dev,
