@@ -35,9 +35,12 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     }
 }
 
+__device__ __forceinline__ double u01_from_bits(uint32_t x) {
+    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+
 __device__ __forceinline__ double gumbel_from_bits(uint32_t x) {
-    const double u = ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
-    return -log(-log(u));
+    return -log(-log(u01_from_bits(x)));
 }
 
 __global__ void __launch_bounds__(RNT) sample_masks_kernel(const float* __restrict__ scores, int64_t n, float tau,
@@ -71,18 +74,35 @@ __global__ void __launch_bounds__(RNT) threshold_masks_kernel(const float* __res
 
 // Probabilistic pruning (Sec. 3.5): n_draws hard masks per Gaussian with the
 // rule above (steps step0 .. step0 + n_draws - 1); keep[i] = 1 iff any is 1.
+// Most draws are decided without the four logarithms: g(u) = -log(-log u)
+// increases with u and is at least G_MIN = g(2^-25) over the uniforms the
+// generator yields, so with d = s0 - s1 a draw is 0 whatever u1 once
+// g(u0) < G_MIN - d, and 1 whatever u0 once g(u1) < G_MIN + d.  Both tests
+// compare u with the inverse image of the bound, less 1e-6: the exact gap
+// between the two sides is then at least e 1e-6 (g' >= e), far above the
+// rounding of the double-precision rule, which therefore decides the same
+// way.  The remaining draws take that rule itself.
 __global__ void __launch_bounds__(RNT) prune_sample_kernel(const float* __restrict__ scores, int64_t n,
                                                             uint64_t seed, uint64_t step0, int n_draws,
                                                             uint32_t* __restrict__ keep) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float2 s = reinterpret_cast<const float2*>(scores)[i];
+    const double d = (double)s.x - (double)s.y;
+    const double g_min = -log(-log(0.5 / 16777216.0));
+    const double u0_zero = exp(-exp(d - g_min)) - 1e-6;   // u0 below: the draw is 0
+    const double u1_one = exp(-exp(-d - g_min)) - 1e-6;   // u1 below: the draw is 1
     uint32_t k = 0;
-    for (int d = 0; d < n_draws && !k; ++d) {
-        const uint64_t step = step0 + (uint64_t)d;
+    for (int dr = 0; dr < n_draws && !k; ++dr) {
+        const uint64_t step = step0 + (uint64_t)dr;
         uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32), c2 = (uint32_t)step,
                  c3 = (uint32_t)(step >> 32);
         philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+        if (u01_from_bits(c0) < u0_zero) continue;
+        if (u01_from_bits(c1) < u1_one) {
+            k = 1u;
+            break;
+        }
         const double z0 = (double)s.x + gumbel_from_bits(c0);
         const double z1 = (double)s.y + gumbel_from_bits(c1);
         k = z0 > z1 ? 1u : 0u;
