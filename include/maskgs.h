@@ -153,6 +153,13 @@ typedef struct {
     float* d_opacity_logits; /* [N] */
     float* d_sh;             /* [N, (d+1)^2, 3] */
     float* d_masks;          /* [N], dL/dM_i, Eq. (6) plus background term */
+    float* d_records;        /* [R = n_views N, 9] (mgs_backward only): the
+                                per-record 2D gradients before the chain
+                                rule, record v N + i for view v, Gaussian i:
+                                dL/d(u, v), dL/d(a, b / a, c - b^2 / a) of the
+                                stored conic, dL/dopacity (of M_i o_i under
+                                MGS_MASK_OPACITY), dL/d(r, g, b); rows of
+                                records without a valid projection are 0 */
 } mgs_gradients;
 
 typedef struct {
@@ -168,7 +175,6 @@ typedef struct {
 
 typedef struct mgs_ctx mgs_ctx;
 typedef struct mgs_frame mgs_frame;
-typedef struct mgs_graph mgs_graph;
 
 /* ---------------------------------------------------------------------- */
 /* lifecycle                                                               */

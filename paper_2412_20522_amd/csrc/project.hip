@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     int64_t n, ViewSet views, DevSettings st, const AccT* d_rec, const double* __restrict__ dm_acc, AccT* clear,
     float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
-    float* __restrict__ d_sh, float* __restrict__ d_masks) {
+    float* __restrict__ d_sh, float* __restrict__ d_masks, float* __restrict__ d_rec_out) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -344,9 +344,19 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             const DevView& cam = views.v[vi];
             const int64_t r = (int64_t)vi * n + g;
             const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
-            if (!o.valid) continue;
+            if (!o.valid) {
+                if (d_rec_out) {
+#pragma unroll
+                    for (int q = 0; q < DREC; ++q) d_rec_out[r * DREC + q] = 0.f;
+                }
+                continue;
+            }
             valid |= 1u << vi;
             const AccT* dr = d_rec + r * DREC;
+            if (d_rec_out) {
+#pragma unroll
+                for (int q = 0; q < DREC; ++q) d_rec_out[r * DREC + q] = (float)dr[q];
+            }
             const double du = dr[0], dv = dr[1], dca = dr[2], dcb = dr[3], dcc = dr[4];
             gop += (double)dr[5];
 #pragma unroll
@@ -557,11 +567,12 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     const dim3 grid((unsigned)((g.n + 255) / 256));
     const size_t lds = (size_t)views.n_views * 3 * 256 * sizeof(float);  // colour gradients of every view
     float* d_masks = dm_acc ? out.d_masks : nullptr;
+    float* rec_out = dm_acc ? out.d_records : nullptr;  // whole path only
 #define MGS_PBWD(D)                                                                                               \
     hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), lds, stream, g.means, g.log_scales, g.quats, \
                        g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
                        out.d_log_scales,                                                                            \
-                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks)
+                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;

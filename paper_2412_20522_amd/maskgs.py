@@ -52,7 +52,8 @@ class mgs_gaussians(C.Structure):
 
 class mgs_gradients(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_log_scales", C.c_void_p), ("d_quats", C.c_void_p),
-                ("d_opacity_logits", C.c_void_p), ("d_sh", C.c_void_p), ("d_masks", C.c_void_p)]
+                ("d_opacity_logits", C.c_void_p), ("d_sh", C.c_void_p), ("d_masks", C.c_void_p),
+                ("d_records", C.c_void_p)]
 
 
 class mgs_eval_counts(C.Structure):
@@ -214,7 +215,7 @@ def gaussians_struct(means, log_scales, quats, opacity_logits, sh, masks=None) -
 
 
 def gradients_struct(d_means=None, d_log_scales=None, d_quats=None, d_opacity_logits=None, d_sh=None,
-                     d_masks=None) -> mgs_gradients:
+                     d_masks=None, d_records=None) -> mgs_gradients:
     gr = mgs_gradients()
     gr.d_means = _ptr(d_means, name="d_means")
     gr.d_log_scales = _ptr(d_log_scales, name="d_log_scales")
@@ -222,6 +223,7 @@ def gradients_struct(d_means=None, d_log_scales=None, d_quats=None, d_opacity_lo
     gr.d_opacity_logits = _ptr(d_opacity_logits, name="d_opacity_logits")
     gr.d_sh = _ptr(d_sh, name="d_sh")
     gr.d_masks = _ptr(d_masks, name="d_masks")
+    gr.d_records = _ptr(d_records, name="d_records")
     return gr
 
 

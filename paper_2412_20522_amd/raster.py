@@ -107,11 +107,16 @@ class Rasterizer:
         M.mgs_forward_importance(self.ctx, frame, g, cams, self.settings, images, imp_sum, imp_max)
         return images, imp_sum, imp_max
 
-    def backward(self, frame, params: dict, dl_dimages: torch.Tensor, out: Optional[Grads] = None) -> Grads:
+    def backward(self, frame, params: dict, dl_dimages: torch.Tensor, out: Optional[Grads] = None,
+                 records: Optional[torch.Tensor] = None) -> Grads:
+        """records (optional, [n_views N, 9] float32) receives the per-record 2D
+        gradients before the chain rule (dL/d(u, v), the stored conic,
+        opacity and colour)."""
         if out is None:
             out = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS),
                         torch.empty(params["means"].shape[0], dtype=torch.float32, device=params["means"].device))
-        gr = M.gradients_struct(out.means, out.log_scales, out.quats, out.opacity_logits, out.sh, out.masks)
+        gr = M.gradients_struct(out.means, out.log_scales, out.quats, out.opacity_logits, out.sh, out.masks,
+                                records)
         M.mgs_backward(self.ctx, frame, dl_dimages.contiguous(), gr)
         return out
 

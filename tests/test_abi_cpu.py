@@ -53,6 +53,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(M.mgs_settings) == 4 * 4 + 8 * 4 + 3 * 4 + 8 * 4
     assert C.sizeof(M.mgs_eval_counts) == 6 * 8
     assert C.sizeof(M.mgs_gaussians) == 6 * 8 + 8
+    assert C.sizeof(M.mgs_gradients) == 7 * 8
 
 
 def test_host_validation_without_device():

@@ -206,3 +206,38 @@ def test_autograd_function_straight_through(rast):
     assert U.rel_err(scores.grad.cpu().numpy(), od) <= 2e-3
     assert U.rel_err(params["means"].grad.cpu().numpy(), op.grads.means) <= 2e-3
     assert abs(mask_loss.item() - om.mean() ** 2) <= 1e-6
+
+
+@pytest.mark.parametrize("n_views", [1, 3])
+def test_backward_returns_per_record_2d_gradients(rast, n_views):
+    """The optional per-record output of mgs_backward against the oracle's
+    per-record gradients (conic converted to the stored basis), and the
+    parameter gradients unchanged by asking for it."""
+    s = scenegen.small_scene(3000, 120, 96, seed=211, sh_degree=2, log_scale_mean=-2.5, n_views=n_views)
+    bg = (0.3, 0.1, 0.2)
+    cams = s["cameras"]
+    n = s["means"].shape[0]
+    P = sum(c["width"] * c["height"] for c in cams)
+    dl = np.random.default_rng(12).normal(size=3 * P).astype(np.float32)
+    rast.set(**_defaults(2, bg))
+    dev = U.to_device(s)
+    frame = rast.acquire_frame()
+    rast.forward(frame, _params(dev), dev["masks"], cams)
+    recs = torch.full((n_views * n, 9), 7.0, device="cuda")
+    g = rast.backward(frame, _params(dev), torch.from_numpy(dl).cuda(), records=recs)
+    g_plain = rast.backward(frame, _params(dev), torch.from_numpy(dl).cuda())
+    torch.cuda.synchronize()
+    rast.release_frame(frame)
+    ost = oracle.RasterSettings(sh_degree=2, bg=bg)
+    op = oracle.run_pipeline(s, cams, s["masks"].astype(np.float64), ost, dl_dimage=dl.astype(np.float64))
+    got = recs.cpu().numpy().astype(np.float64)
+    m2d, con, _, _, _, _, valid = oracle.stack_projected(op.proj)
+    assert np.all(got[~valid.astype(bool)] == 0.0)
+    want_conic = U.dstable_from_dabc(con[:, 0], con[:, 1] / np.where(con[:, 0] != 0, con[:, 0], 1.0), op.bwd.d_conic)
+    for name, a, b in [("mean2d", got[:, 0:2], op.bwd.d_mean2d), ("conic", got[:, 2:5], want_conic),
+                       ("opacity", got[:, 5], op.bwd.d_opacity), ("color", got[:, 6:9], op.bwd.d_color)]:
+        e = U.rel_err(a, b)
+        assert e <= 2e-3, (name, e)
+    for name in U.PARAM_KEYS + ("masks",):
+        a, b = getattr(g, name).cpu().numpy(), getattr(g_plain, name).cpu().numpy()
+        assert U.rel_err(a, b.astype(np.float64)) <= 1e-6, name
