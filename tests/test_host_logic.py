@@ -132,3 +132,30 @@ def test_prune_cadence():
     assert 15_000 in due and 15_100 not in due and 16_000 in due and 20_000 in due
     assert all(it % 100 == 0 for it in due)
     assert sum(1 for it in due if it > 15_000) == 5
+
+
+def test_gumbel_bound_decides_pruning_draws_like_the_exact_rule():
+    """The pruning draws settle most draws by comparing the uniforms with two
+    per-Gaussian thresholds: g(u) = -log(-log u) increases with u and is at
+    least g(2^-25) over the generator's uniforms, so u0 below
+    g^-1(g_min - d) - 1e-6 forces a 0 and u1 below g^-1(g_min + d) - 1e-6
+    forces a 1 (d = s0 - s1).  Over the whole 24-bit grid of one uniform and
+    random partners, both never contradict the double-precision rule."""
+    rng = np.random.default_rng(31)
+    g = lambda u: -np.log(-np.log(u))
+    g_min = g(0.5 / 16777216.0)
+    u_grid = (np.arange(0, 2 ** 24, 97) + 0.5) / 16777216.0
+    for d in (-12.0, -8.0, -1.5, 0.0, 0.7, 8.0, 12.0):
+        s0, s1 = d / 2, -d / 2
+        u_other = (rng.integers(0, 2 ** 24, u_grid.size) + 0.5) / 16777216.0
+        t0 = np.exp(-np.exp(d - g_min)) - 1e-6
+        t1 = np.exp(-np.exp(-d - g_min)) - 1e-6
+        # u0 on the grid, u1 random: the "0" shortcut
+        exact = (s0 + g(u_grid)) > (s1 + g(u_other))
+        assert not np.any(exact[u_grid < t0]), d
+        # u1 on the grid, u0 random: the "1" shortcut
+        exact = (s0 + g(u_other)) > (s1 + g(u_grid))
+        assert np.all(exact[u_grid < t1]), d
+        # the extreme partner (the smallest uniform) is the worst case
+        u_min = 0.5 / 16777216.0
+        assert not np.any(((s0 + g(u_grid)) > (s1 + g(u_min)))[u_grid < t0]), d
