@@ -215,7 +215,8 @@ MGS_API mgs_status mgs_frame_get_stats(const mgs_frame* frame, mgs_frame_stats* 
  * per view and channel-planar, receives the rendering; t_final [P]
  * (optional, may be NULL) the final transmittance.  Synchronises the stream
  * once, to read the list entry counts and size the sort, unless the
- * frame has a fixed workspace (mgs_frame_reserve).  Errors:
+ * frame has a fixed workspace (mgs_frame_reserve).  Limits: n_views * n
+ * records and the pixels of all views each below 2^32.  Errors:
  * MGS_ERR_INVALID_ARG, MGS_ERR_NONFINITE (non-finite projected geometry),
  * MGS_ERR_CAPACITY, MGS_ERR_OOM, MGS_ERR_HIP. */
 MGS_API mgs_status mgs_forward(mgs_frame* frame, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,

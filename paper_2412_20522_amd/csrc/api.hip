@@ -155,12 +155,17 @@ mgs_status check_cameras(mgs_ctx* ctx, const mgs_camera* cams, int n_views) {
     if (n_views < 1 || n_views > MGS_MAX_VIEWS)
         return fail(ctx, MGS_ERR_INVALID_ARG, "n_views %d not in [1, %d]", n_views, MGS_MAX_VIEWS);
     if (!cams) return fail(ctx, MGS_ERR_INVALID_ARG, "cams is NULL");
+    int64_t pixels = 0;
     for (int v = 0; v < n_views; ++v) {
         const mgs_camera& c = cams[v];
         if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
             return fail(ctx, MGS_ERR_INVALID_ARG, "view %d: size %dx%d", v, c.width, c.height);
         if (!(c.fx > 0.f && c.fy > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "view %d: focal lengths", v);
+        pixels += (int64_t)c.width * c.height;
     }
+    // per-view pixel offsets are 32-bit
+    if (pixels > (int64_t)0xffffffffll)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "%lld pixels over all views exceed 2^32 - 1", (long long)pixels);
     return MGS_OK;
 }
 
@@ -491,6 +496,10 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     if ((s = check_cameras(ctx, cams, n_views)) != MGS_OK) return s;
     if ((s = check_settings(ctx, st)) != MGS_OK) return s;
     if (!images) return fail(ctx, MGS_ERR_INVALID_ARG, "images is NULL");
+    // record ids (view * n + Gaussian) are 32-bit
+    if (g->n * (int64_t)n_views > (int64_t)0xffffffffll)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "%lld records (views x Gaussians) exceed 2^32 - 1",
+                    (long long)(g->n * (int64_t)n_views));
     f->have_forward = false;
     f->g = *g;
     f->n = g->n;
