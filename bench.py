@@ -14,7 +14,7 @@ metric: Gaussian-pixel evaluations per second, counting for every pixel the
 sorted entries its 16x16 tile list presents up to and including its stop
 entry (the forward evaluations; each has a backward counterpart).
 
-Prints one JSON line.  --gpus N > 1 is rejected: this build measures one GPU.
+Prints one JSON line.  --gpus N > 1 is rejected: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -271,7 +271,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU; runs on several GPUs are not supported (got --gpus {args.gpus})",
               file=sys.stderr)
         return 2
 
