@@ -414,6 +414,40 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const KeyT* __restrict
     if (k == K - 1 && tv) ranges[t].y = (uint32_t)K;
 }
 
+// The same for 32-bit keys, four consecutive keys per thread (one 16-byte
+// load of keys 4 j .. 4 j + 3 and the key before them).
+__global__ void __launch_bounds__(256) tile_ranges4_kernel(const uint32_t* __restrict__ keys, int64_t Kcap,
+                                                            const uint64_t* __restrict__ K_dev, uint64_t nbins,
+                                                            uint2* __restrict__ ranges) {
+    const int64_t K = live_count(Kcap, K_dev);
+    const int64_t k0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (k0 >= K) return;
+    uint32_t v[4];
+    if (k0 + 4 <= K) {
+        const uint4 q = *reinterpret_cast<const uint4*>(keys + k0);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = k0 + i < K ? keys[k0 + i] : 0u;
+    }
+    uint64_t p = k0 > 0 ? (uint64_t)keys[k0 - 1] : 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t k = k0 + i;
+        if (k >= K) break;
+        const uint64_t t = v[i];
+        const bool tv = t < nbins;
+        if (k == 0) {
+            if (tv) ranges[t].x = 0;
+        } else if (p != t) {
+            if (p < nbins) ranges[p].y = (uint32_t)k;
+            if (tv) ranges[t].x = (uint32_t)k;
+        }
+        if (k == K - 1 && tv) ranges[t].y = (uint32_t)K;
+        p = t;
+    }
+}
+
 __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -588,8 +622,9 @@ void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, c
                           int64_t total_tiles, uint32_t* ranges) {
     launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
     if (K == 0) return;
-    hipLaunchKernelGGL(tile_ranges_kernel<uint32_t>, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, stream, keys, K,
-                       K_dev, 0, (uint64_t)total_tiles, reinterpret_cast<uint2*>(ranges));
+    // keys come from the library's own buffers (16-byte aligned)
+    hipLaunchKernelGGL(tile_ranges4_kernel, dim3((unsigned)((K + 1023) / 1024)), dim3(256), 0, stream, keys, K, K_dev,
+                       (uint64_t)total_tiles, reinterpret_cast<uint2*>(ranges));
 }
 
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {
