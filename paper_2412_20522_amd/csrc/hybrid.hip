@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
         B = rec[3 * (size_t)r + 1];
         uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
         c = C.w;
-        vi = (int)(i / n);
+        vi = (int)((uint32_t)i / (uint32_t)n);  // positions are below 2^32
         wide = c > views.v[vi].wide_min;
         C.w = r;
         srec[3 * i] = A;
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
     if (i < R && (cnt = cnt_sorted[i]) != 0) {
         off = offsets[i];
-        vi = (int)(i / n);
+        vi = (int)((uint32_t)i / (uint32_t)n);  // positions are below 2^32
         wide = wide_flag[i] != 0;
         A = srec[3 * i];
         B = srec[3 * i + 1];
