@@ -704,7 +704,7 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT_BWD);
         launch_project_bwd64(stream, f->g, f->views, f->st, (double*)f->d_rec.p, (const double*)f->dm_acc.p,
-                             *grads);
+                             *grads, (const uint32_t*)f->tiles.p);
     }
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;

@@ -17,7 +17,8 @@ void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 // Whole path: FP64 per-record gradients, which are set back to zero as they
 // are read; dm_acc (FP64 mask gradients) is rounded into out.d_masks.
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                          double* d_rec, const double* dm_acc, const mgs_gradients& out);
+                          double* d_rec, const double* dm_acc, const mgs_gradients& out,
+                          const uint32_t* tiles);
 
 // scan / binning / sort / ranges
 size_t scan_scratch_bytes(int64_t n);

@@ -304,8 +304,9 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
 // atomics); dm_acc (optional) holds FP64 mask gradients to round into d_masks.
 // clear (optional, the same array as d_rec): each row read is set back to
 // zero, so the accumulator is clean for the next backward without a fill
-// (only records with a valid projection can have received gradients, and
-// every such row is read here).
+// (only records listed in some tile can have received gradients, and every
+// such row is read here).  tiles (optional): the forward's per-record tile
+// counts; rows of records without tiles are neither read nor cleared.
 template <int DEG, typename AccT>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
@@ -313,7 +314,8 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     int64_t n, ViewSet views, DevSettings st, const AccT* d_rec, const double* __restrict__ dm_acc, AccT* clear,
     float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
-    float* __restrict__ d_sh, float* __restrict__ d_masks, float* __restrict__ d_rec_out) {
+    float* __restrict__ d_sh, float* __restrict__ d_masks, float* __restrict__ d_rec_out,
+    const uint32_t* __restrict__ tiles) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -344,7 +346,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             const DevView& cam = views.v[vi];
             const int64_t r = (int64_t)vi * n + g;
             const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
-            if (!o.valid) {
+            // a record without tiles was listed nowhere: its row was never
+            // written and is zero (tiles: the forward's per-record counts)
+            if (!o.valid || (tiles && tiles[r] == 0u)) {
                 if (d_rec_out) {
 #pragma unroll
                     for (int q = 0; q < DREC; ++q) d_rec_out[r * DREC + q] = 0.f;
@@ -562,7 +566,8 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 namespace {
 template <typename AccT>
 void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                   const AccT* d_rec, const double* dm_acc, AccT* clear, const mgs_gradients& out) {
+                   const AccT* d_rec, const double* dm_acc, AccT* clear, const mgs_gradients& out,
+                   const uint32_t* tiles = nullptr) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     const size_t lds = (size_t)views.n_views * 3 * 256 * sizeof(float);  // colour gradients of every view
@@ -572,7 +577,7 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), lds, stream, g.means, g.log_scales, g.quats, \
                        g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
                        out.d_log_scales,                                                                            \
-                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out)
+                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;
@@ -589,8 +594,8 @@ void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 }
 
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                          double* d_rec, const double* dm_acc, const mgs_gradients& out) {
-    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, d_rec, out);
+                          double* d_rec, const double* dm_acc, const mgs_gradients& out, const uint32_t* tiles) {
+    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, d_rec, out, tiles);
 }
 
 }  // namespace mgs
