@@ -345,10 +345,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         for (int vi = 0; vi < views.n_views; ++vi) {
             const DevView& cam = views.v[vi];
             const int64_t r = (int64_t)vi * n + g;
-            const ViewGeom o = view_geom(cam, st, px, py, pz, Sig);
-            // a record without tiles was listed nowhere: its row was never
-            // written and is zero (tiles: the forward's per-record counts)
-            if (!o.valid || (tiles && tiles[r] == 0u)) {
+            // a record without tiles (every invalid one among them) was listed
+            // nowhere: its row was never written and is zero (tiles: the
+            // forward's per-record counts); its geometry is not formed
+            const bool listed = !tiles || tiles[r] != 0u;
+            ViewGeom o;
+            if (listed) o = view_geom(cam, st, px, py, pz, Sig);
+            if (!listed || !o.valid) {
                 if (d_rec_out) {
 #pragma unroll
                     for (int q = 0; q < DREC; ++q) d_rec_out[r * DREC + q] = 0.f;
