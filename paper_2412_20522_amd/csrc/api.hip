@@ -553,7 +553,9 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         launch_radix_sort_segmented(stream, (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint32_t*)f->rkeys_alt.p,
                                     (uint32_t*)f->rvals_alt.p, R, f->n, f->rsort_tmp.p, &alt);
         f->order_in_alt = alt;
-        launch_permute_classify(stream, f->record_order(), (const float*)f->rec.p, R, f->n, f->views, f->st,
+        launch_permute_classify(stream, f->record_order(),
+                                (const uint32_t*)(f->order_in_alt ? f->rkeys_alt.p : f->rkeys.p),
+                                (const float*)f->rec.p, R, f->n, f->views, f->st,
                                 (uint32_t*)f->cnt_sorted.p,
                                 (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p,
                                 (uint32_t*)f->cls_part.p, f->wide_counts());

@@ -260,15 +260,18 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
     return make_float4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
 }
 
-// Sorted position i holds record order[i]; positions [v n, (v + 1) n) belong
-// to view v.  Writes the sorted record copy (radius in B.w, record id bits in
-// C.w), the wide flag and the number of list entries (tiles or regions, after
-// culling) of every position, and per workgroup the number of wide records
-// and of their region entries (part[b], part[nb + b]).
+// Sorted position i holds record order[i] with depth key skeys[i]; positions
+// [v n, (v + 1) n) belong to view v.  Writes the sorted record copy (radius in
+// B.w, record id bits in C.w), the wide flag and the number of list entries
+// (tiles or regions, after culling) of every position, and per workgroup the
+// number of wide records and of their region entries (part[b], part[nb + b]).
+// A record without tiles (key all ones, sorted last in its view) is listed
+// nowhere: it gets no copy, which nothing reads.
 __global__ void __launch_bounds__(256) permute_classify_kernel(
-    const uint32_t* __restrict__ order, const float4* __restrict__ rec, int64_t R, int64_t n, ViewSet views,
-    DevSettings st, uint32_t* __restrict__ cnt_out, uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask,
-    float4* __restrict__ srec, uint32_t* __restrict__ part) {
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ skeys, const float4* __restrict__ rec,
+    int64_t R, int64_t n, ViewSet views, DevSettings st, uint32_t* __restrict__ cnt_out,
+    uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask, float4* __restrict__ srec,
+    uint32_t* __restrict__ part) {
     __shared__ uint32_t s_part[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
@@ -277,7 +280,9 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     uint32_t c = 0;
     bool wide = false;
     int vi = 0;
-    if (live) {
+    if (live && skeys[i] == 0xffffffffu) {
+        wide_flag[i] = 0u;
+    } else if (live) {
         // one gather of the record (radius in B.w, tile count in C.w)
         const uint32_t r = order[i];
         A = rec[3 * (size_t)r];
@@ -1259,12 +1264,13 @@ void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* 
     hipLaunchKernelGGL(record_keys_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, depth, tiles, R, keys, vals);
 }
 
-void launch_permute_classify(hipStream_t stream, const uint32_t* order, const float* rec, int64_t R, int64_t n,
-                             const ViewSet& views, const DevSettings& st, uint32_t* cnt, uint32_t* wide_flag,
-                             uint64_t* tmask, float* srec, uint32_t* part, uint64_t* wide_counts) {
+void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
+                             int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
+                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
+                             uint64_t* wide_counts) {
     if (R == 0) return;
     const unsigned nb = blocks_of(R);
-    hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order,
+    hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, skeys,
                        reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, wide_flag, tmask,
                        reinterpret_cast<float4*>(srec), part);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(1024), 0, stream, part, (int)nb, wide_counts);

@@ -85,9 +85,10 @@ void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* 
 // wide_counts (device u64): [0] = wide records, [2] = their region entries;
 // part: classify_parts_bytes(R) bytes of per-workgroup partial counts
 size_t classify_parts_bytes(int64_t R);
-void launch_permute_classify(hipStream_t stream, const uint32_t* order, const float* rec, int64_t R, int64_t n,
-                             const ViewSet& views, const DevSettings& st, uint32_t* cnt, uint32_t* wide_flag,
-                             uint64_t* tmask, float* srec, uint32_t* part, uint64_t* wide_counts);
+void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
+                             int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
+                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
+                             uint64_t* wide_counts);
 void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
                             const uint32_t* wide_flag, const uint64_t* tmask, const uint32_t* offsets, int64_t R,
                             int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
