@@ -176,7 +176,24 @@ __global__ void __launch_bounds__(RNT) partial_abs_diff_kernel(const float* __re
                                                                 double* __restrict__ partial) {
     __shared__ double sh[RNT / 64];
     double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RNT) {
+    const int64_t stride = (int64_t)gridDim.x * RNT;
+    int64_t head = 0;  // elements before this index go four at a time
+    if ((((uintptr_t)a | (uintptr_t)b | (uintptr_t)d) & 15) == 0) {
+        head = n & ~(int64_t)3;
+        for (int64_t q = (int64_t)blockIdx.x * RNT + threadIdx.x; 4 * q < head; q += stride) {
+            const float4 x = reinterpret_cast<const float4*>(a)[q], y = reinterpret_cast<const float4*>(b)[q];
+            const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+            float o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float e = xs[k] - ys[k];
+                s += fabs((double)xs[k] - (double)ys[k]);
+                o[k] = e > 0.f ? inv_m : (e < 0.f ? -inv_m : 0.f);
+            }
+            reinterpret_cast<float4*>(d)[q] = make_float4(o[0], o[1], o[2], o[3]);
+        }
+    }
+    for (int64_t i = head + (int64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += stride) {
         const float x = a[i] - b[i];
         s += fabs((double)a[i] - (double)b[i]);
         d[i] = x > 0.f ? inv_m : (x < 0.f ? -inv_m : 0.f);

@@ -443,3 +443,24 @@ def test_mask_grad_l1_and_adam_match_oracle(ctx):
         oracle.adam(po, g.astype(np.float64), m1, m2, 1e-2, 0.9, 0.999, 1e-15, step)
     torch.cuda.synchronize()
     np.testing.assert_allclose(pt.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("m,offset", [(30_001, 0), (30_003, 0), (7, 0), (30_000, 1), (1, 0)])
+def test_l1_loss_tails_and_misaligned_views(ctx, m, offset):
+    """Lengths that leave a tail after the four-wide loop, and views one
+    float off the 16-byte alignment (the scalar loop alone)."""
+    rng = np.random.default_rng(m + offset)
+    img = rng.uniform(size=m).astype(np.float32)
+    tgt = rng.uniform(size=m).astype(np.float32)
+    tgt[: min(3, m)] = img[: min(3, m)]
+    bi = torch.zeros(m + offset, device="cuda")
+    bt = torch.zeros(m + offset, device="cuda")
+    bd = torch.full((m + offset,), 9.0, device="cuda")
+    bi[offset:] = torch.from_numpy(img).cuda()
+    bt[offset:] = torch.from_numpy(tgt).cuda()
+    loss = torch.zeros(1, device="cuda")
+    U.M().mgs_l1_loss_grad(ctx, bi[offset:], bt[offset:], bd[offset:], loss)
+    torch.cuda.synchronize()
+    ol, od = oracle.l1_loss(img.astype(np.float64), tgt)
+    assert abs(float(loss.item()) - ol) <= 1e-6 * max(ol, 1e-30)
+    assert np.array_equal(bd[offset:].cpu().numpy(), od.astype(np.float32))
