@@ -837,17 +837,17 @@ struct HybridLists {
 };
 
 // Both compositing kernels are built for at least five waves per SIMD (at
-// most 96 registers), the forward with up to two pixels per thread for six
-// (80 registers): the forward fits without spilling, the backward spills a
-// few values, and all run faster than with fewer waves (measured on the
-// batched workload: forward 0.65 -> 0.63 ms at four pixels per thread, 0.62
-// -> 0.59 ms at two; backward 1.02 -> 0.99 ms).
+// most 96 registers), the forward with up to two pixels per thread for seven
+// (72 registers): both spill a few values at most, and all run faster than
+// with fewer waves (measured on the batched workload: forward 0.65 -> 0.63
+// ms at four pixels per thread, 0.62 -> 0.58 ms at two; backward 1.02 ->
+// 0.99 ms; eight waves for the forward spill more and are slower).
 // STATS: write the per-pixel work counters (stats_out, eval_out).
 // IMP: accumulate every Gaussian's blending weights M alpha T over the
 // pixels it enters: the wave's sum (FP64 atomic) into imp_sum and its
 // maximum (as float bits, the weights being non-negative) into imp_max.
 template <int TW, int TH, int PPT, bool STATS, bool IMP>
-__global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 6) hybrid_fwd_kernel(
+__global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_kernel(
     const float4* __restrict__ srec, HybridLists hl, ViewSet views, DevSettings st, float* __restrict__ images,
     float* __restrict__ t_final, int32_t* __restrict__ last_out, int4* __restrict__ stats_out,
     int4* __restrict__ eval_out, uint32_t* __restrict__ queue, int64_t n, double* __restrict__ imp_sum,
