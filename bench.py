@@ -8,11 +8,17 @@ masked backward compositing, projection backward and the mask-score
 gradient.  The default workload is the batched multi-view case: a
 1M-Gaussian unbounded scene (SH degree 3, heavy-tailed scales) rendered for
 8 views of uneven size in one call ("batched"), compared with 8 single-view
-calls ("plain").
+calls of the same work ("plain").
 
 metric: Gaussian-pixel evaluations per second, counting for every pixel the
 sorted entries its 16x16 tile list presents up to and including its stop
 entry (the forward evaluations; each has a backward counterpart).
+
+Also reported (not the headline): the evaluated pairs per second, the
+single-view workloads (tiny, object, unbounded), the 200-step training run of
+the 3M-Gaussian workload (autograd step with Adam, captured per camera batch),
+pruning and forward-only rendering, the FP64 oracle on the host cores, and an
+oracle parity check of one view of the timed step.
 
 Prints one JSON line.  --gpus N > 1 is rejected: the benchmark measures one GPU.
 """
@@ -20,8 +26,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -40,7 +46,6 @@ SLOTS_BWD_VISIBLE = 44  # T recovery (rcp), X, dL/dM, dL/dc, dL/do, dL/dQ, dL/du
 SLOTS_BWD_MASKED = 11   # X with T unchanged, dL/dM
 PEAK_SLOTS = 256 * 64 * 2.4e9   # 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz
 PEAK_HBM = 8.0e12
-
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
@@ -65,44 +70,67 @@ def build_workload(name: str):
     return s, desc
 
 
-def stage_roofline(stage: str, ms_per_launch: float, counts: dict, frame_stats: dict, n: int, views: int,
-                   sh_deg: int):
-    """Algorithmic work of one launch of `stage` and its roofline."""
-    t = ms_per_launch * 1e-3
-    K = frame_stats["n_instances"]
-    R = frame_stats["n_records"]
-    P = frame_stats["n_pixels"]
+def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
+    """Algorithmic (HBM bytes, VALU lane-slots) of one launch of a stage."""
+    K = fs["n_instances"]
+    R = fs["n_records"]
     k3 = 3 * (sh_deg + 1) ** 2
-    if stage == "composite_bwd":
-        # entries the backward evaluates: those up to each pixel's last blended
-        # one that can reach a pixel of their tile
-        vis = counts["blended"] - counts["blended_masked"]
-        work = SLOTS_FILTER * counts["bwd_evaluated"] + SLOTS_BWD_VISIBLE * vis + SLOTS_BWD_MASKED * counts[
-            "blended_masked"]
-        return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
-                    frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
     if stage == "composite_fwd":
-        work = SLOTS_FILTER * counts["evaluated"] + SLOTS_BLEND * counts["blended"]
-        return dict(bound="alu", achieved=work / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
-                    frac=work / t / PEAK_SLOTS, algorithmic=work, algorithmic_unit="VALU lane-slots")
+        slots = SLOTS_FILTER * counts["evaluated"] + SLOTS_BLEND * counts["blended"]
+        return 48 * K + 20 * P, slots
+    if stage == "composite_bwd":
+        vis = counts["blended"] - counts["blended_masked"]
+        slots = (SLOTS_FILTER * counts["bwd_evaluated"] + SLOTS_BWD_VISIBLE * vis +
+                 SLOTS_BWD_MASKED * counts["blended_masked"])
+        return 48 * K + 20 * P + 12 * P, slots
     if stage == "sort":
-        # stable pass over 32-bit tile keys and 32-bit values: read and write both
-        passes = frame_stats["sort_passes"]
-        byt = 16 * K * passes
-    elif stage == "depth_sort":
-        byt = 16 * R * 4 + R * 12
-    elif stage == "project":
-        byt = n * 4 * (11 + k3 + 1) + R * (48 + 12)
-    elif stage == "project_bwd":
-        byt = n * 4 * (11 + k3) + R * 36 + n * 4 * (10 + k3)
-    elif stage == "duplicate":
-        byt = R * 16 + K * 12
-    elif stage == "scan":
-        byt = R * 8
-    else:
-        byt = P * 16
+        # stable pass over 32-bit cell keys and 32-bit values: read and write both
+        return 16 * K * fs["sort_passes"], 0
+    if stage == "depth_sort":
+        return 16 * R * 4 + R * 12, 0
+    if stage == "project":
+        return n * 4 * (11 + k3 + 1) + R * (48 + 12), 0
+    if stage == "project_bwd":
+        return n * 4 * (11 + k3) + R * 36 + n * 4 * (10 + k3), 0
+    if stage == "duplicate":
+        return R * 16 + K * 12, 0
+    if stage == "scan":
+        return R * 8, 0
+    if stage == "ranges":
+        return K * 4 + 8 * fs["total_tiles"], 0
+    if stage == "sample_masks":
+        return 16 * n, 0
+    if stage == "mask_grad":
+        return 24 * n, 0
+    if stage == "loss":
+        return 36 * P, 0
+    return 0, 0
+
+
+def stage_roofline(stage: str, ms_per_launch: float, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
+    """The roofline of the bound that limits a stage: VALU lane-slots for
+    the compositing kernels, HBM bytes for the rest."""
+    t = ms_per_launch * 1e-3
+    byt, slots = stage_work(stage, counts, fs, n, sh_deg, P)
+    if slots:
+        return dict(bound="alu", achieved=slots / t / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                    frac=slots / t / PEAK_SLOTS, algorithmic=slots, algorithmic_unit="VALU lane-slots")
     return dict(bound="hbm", achieved=byt / t / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s", frac=byt / t / PEAK_HBM,
                 algorithmic=byt, algorithmic_unit="bytes")
+
+
+def combined_roofline(stage_ms: dict, counts: dict, fs: dict, n: int, sh_deg: int, P: int, ms_step: float):
+    """t_roof = sum over stages of max(bytes / HBM peak, slots / VALU peak),
+    against the measured step; plus each stage's own fraction."""
+    t_roof, per = 0.0, {}
+    for st, ms in stage_ms.items():
+        byt, slots = stage_work(st, counts, fs, n, sh_deg, P)
+        t = max(byt / PEAK_HBM, slots / PEAK_SLOTS)
+        t_roof += t
+        if ms > 0:
+            per[st] = {"ms": round(ms, 4), "roof_ms": round(1e3 * t, 4), "frac": round(1e3 * t / ms, 3),
+                       "bound": "alu" if slots / PEAK_SLOTS > byt / PEAK_HBM else "hbm"}
+    return {"t_roof_ms": 1e3 * t_roof, "ms_per_step": ms_step, "frac": 1e3 * t_roof / ms_step, "stages": per}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "counters_batched1M_8views.txt")
@@ -126,6 +154,242 @@ def measured_traffic(stage: str):
         return None
     return rec[stage]["bytes"]
 
+
+def host_cpu() -> dict:
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+# ---------------------------------------------------------------------------
+# one workload: the step, its evaluation count, its timing and roofline
+# ---------------------------------------------------------------------------
+
+class Workload:
+    """Device inputs and buffers of one workload and its batched step."""
+
+    def __init__(self, scene: dict, desc: str, settings: dict, lambda_m: float = 0.1, seed: int = 2412,
+                 step_id: int = 0):
+        import torch
+        from paper_2412_20522_amd import maskgs as M
+        from paper_2412_20522_amd.raster import PARAM_KEYS, Grads, Rasterizer
+        self.M, self.torch = M, torch
+        self.scene, self.desc = scene, desc
+        self.cams = scene["cameras"]
+        self.V = len(self.cams)
+        self.n = scene["means"].shape[0]
+        self.deg = scene["sh_degree"]
+        self.tau = float(scene.get("gumbel_tau", 0.5))
+        self.lambda_m, self.seed, self.step_id = lambda_m, seed, step_id
+        dev = torch.device("cuda:0")
+        self.params = {k: torch.from_numpy(np.ascontiguousarray(scene[k], np.float32)).to(dev) for k in PARAM_KEYS}
+        self.scores = torch.from_numpy(np.ascontiguousarray(scene["mask_scores"], np.float32)).to(dev)
+        self.P = sum(c["width"] * c["height"] for c in self.cams)
+        self.targets = torch.cat([torch.from_numpy(t.reshape(-1)) for t in scene["targets"]]).to(dev)
+        self.rast = Rasterizer(0, sh_degree=self.deg, **settings)
+        self.frame = self.rast.acquire_frame()
+        self.images = torch.empty(3 * self.P, device=dev)
+        self.d_img = torch.empty_like(self.images)
+        self.loss = torch.zeros(1, device=dev)
+        self.loss_m = torch.zeros(1, device=dev)
+        self.grads = Grads(*(torch.empty_like(self.params[k]) for k in PARAM_KEYS), torch.empty(self.n, device=dev))
+        self.d_scores = torch.empty(self.n, 2, device=dev)
+        self.m_hard = torch.empty(self.n, device=dev)
+        self.y_soft = torch.empty(self.n, device=dev)
+        self.red = torch.empty(int(M.lib().mgs_reduce_scratch_bytes(3 * self.P)), dtype=torch.uint8, device=dev)
+
+    def step(self):
+        M, r = self.M, self.rast
+        M.mgs_sample_masks(r.ctx, self.scores, self.tau, self.seed, self.step_id, self.m_hard, self.y_soft)
+        r.forward(self.frame, self.params, self.m_hard, self.cams, images=self.images)
+        M.mgs_l1_loss_grad(r.ctx, self.images, self.targets, self.d_img, self.loss, self.red)
+        r.backward(self.frame, self.params, self.d_img, out=self.grads)
+        M.mgs_mask_grad(r.ctx, self.grads.masks, self.m_hard, self.y_soft, self.tau, self.lambda_m, self.d_scores,
+                        self.loss_m, self.red)
+
+    def settings_dict(self) -> dict:
+        st = self.rast.settings
+        return {k: getattr(st, k) for k in ("tile_w", "tile_h", "batch_depth", "fwd_ppt", "bwd_ppt", "wide_tiles",
+                                           "tile_cull")}
+
+
+def measure(w: Workload, steps: int, warmup: int, autotune: bool, graph: bool, label: str) -> dict:
+    """E16 at 16x16 tiles (untimed), optional autotuning, work counters, a
+    per-stage profile of eager steps, then `steps` graph replays timed with
+    HIP events on the launch stream, checked against an eager step."""
+    torch, M, rast = w.torch, w.M, w.rast
+    timed = w.settings_dict()
+    # the evaluation count at 16x16 tiles on the lists of Sec. 3.1 exactly
+    # (no culling), whatever the timed configuration skips
+    rast.set(tile_w=16, tile_h=16, fwd_ppt=1, bwd_ppt=4, persistent=0, tile_cull=0, stats=1)
+    M.mgs_sample_masks(rast.ctx, w.scores, w.tau, w.seed, w.step_id, w.m_hard, w.y_soft)
+    rast.forward(w.frame, w.params, w.m_hard, w.cams, images=w.images)
+    E16 = rast.count_evals(w.frame)["examined"]
+    rast.set(persistent=1, **timed)
+    log(f"[bench] {label}: E16 = {E16:.4e} evals per step ({w.V} views, {w.P} pixels, {w.n} Gaussians)")
+    tuned = None
+    if autotune:
+        w.step()  # fills the image gradient the tuner backpropagates
+        torch.cuda.synchronize()
+        t_at = time.perf_counter()
+        tuned, tune_ms = rast.autotune(w.frame, w.params, w.m_hard, w.cams, w.d_img, images=w.images, out=w.grads)
+        log(f"[bench] {label}: autotune {tuned} ({tune_ms:.3f} ms fwd+bwd) in {time.perf_counter() - t_at:.1f} s")
+    # work counters of the settings actually timed (one untimed step), then
+    # the timed configuration without counters
+    rast.set(stats=1)
+    w.step()
+    torch.cuda.synchronize()
+    counts = rast.count_evals(w.frame)
+    fstats = rast.stats(w.frame)
+    rast.set(stats=0)
+    for _ in range(warmup):
+        w.step()
+    torch.cuda.synchronize()
+    # per-stage profile: eager steps with HIP events around every stage on
+    # the launch stream (a graph replay cannot be split by stage)
+    M.mgs_profile_enable(rast.ctx, True)
+    n_prof = max(1, min(steps, 5))
+    for _ in range(n_prof):
+        w.step()
+    torch.cuda.synchronize()
+    prof = M.mgs_profile_read(rast.ctx)
+    M.mgs_profile_enable(rast.ctx, False)
+    stage_ms = {k: v[0] / v[1] for k, v in prof.items() if v[1]}
+    g = None
+    run = w.step
+    if graph:
+        rast.reserve(w.frame, 1.25)  # fixed workspace, then one whole step captured
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            w.step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            w.step()
+        run = g.replay
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        rast.check(w.frame)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / steps
+    if g is not None:
+        rast.check(w.frame)  # raises if a replay outgrew the fixed workspace
+        # the replayed step must equal an eager step on the same inputs
+        img_g, dm_g, dp_g = w.images.clone(), w.grads.masks.clone(), w.grads.means.clone()
+        w.step()
+        torch.cuda.synchronize()
+        same_img = bool(torch.equal(img_g, w.images))
+        e_m = float((dm_g - w.grads.masks).norm() / w.grads.masks.norm().clamp_min(1e-30))
+        e_p = float((dp_g - w.grads.means).norm() / w.grads.means.norm().clamp_min(1e-30))
+        if not same_img or e_m > 1e-5 or e_p > 1e-5:
+            raise RuntimeError(f"graph replay differs from the eager step: images equal {same_img}, "
+                               f"dM rel {e_m:.2e}, dmeans rel {e_p:.2e}")
+    log(f"[bench] {label}{' (graph)' if g is not None else ''}: {ms_step:.3f} ms/step "
+        f"(wall {1e3 * wall / steps:.3f}), K = {fstats['n_instances']}, wide records = {fstats['n_wide']}")
+    for k, v in stage_ms.items():
+        log(f"[bench]   {k:14s} {v:9.3f} ms/launch")
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    roof = stage_roofline(dom, stage_ms[dom], counts, fstats, w.n, w.deg, w.P)
+    roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof}
+    comb = combined_roofline(stage_ms, counts, fstats, w.n, w.deg, w.P, ms_step)
+    return {"E16": E16, "ms_per_step": ms_step, "counts": counts, "fstats": fstats, "stage_ms": stage_ms,
+            "roofline": roof, "combined": comb, "tuned": tuned, "graph": g}
+
+
+def plain_path(w: Workload, reps: int, warmup: int, autotune: bool) -> dict:
+    """The same step as 8 single-view calls: one forward and backward per
+    view, no graph and no persistent queue, no counters.  The compositing
+    settings are the autotuner's for the largest view (autotune) or the
+    batched path's tuned ones.  The L1 gradient of each view is weighted by
+    its share of the elements (so the per-view losses add up to the mean over
+    all views) and the per-view parameter gradients are summed by the library
+    (accumulating backward), so the step computes what the batched step
+    does; checked once."""
+    torch, M = w.torch, w.M
+    from paper_2412_20522_amd.raster import PARAM_KEYS, Grads, Rasterizer
+    st = w.settings_dict()
+    rp = Rasterizer(0, sh_degree=w.deg, persistent=0, stats=0, **st)
+    fr = rp.acquire_frame()
+    if autotune:
+        big = max(range(w.V), key=lambda v: w.cams[v]["width"] * w.cams[v]["height"])
+        cam = w.cams[big]
+        M.mgs_sample_masks(rp.ctx, w.scores, w.tau, w.seed, w.step_id, w.m_hard, w.y_soft)
+        im = rp.forward(fr, w.params, w.m_hard, [cam])
+        off = sum(3 * c["width"] * c["height"] for c in w.cams[:big])
+        d1 = torch.empty_like(im)
+        M.mgs_l1_loss_grad(rp.ctx, im, w.targets[off:off + im.numel()], d1, None, w.red)
+        rp.autotune(fr, w.params, w.m_hard, [cam], d1, images=im)
+        st = {k: getattr(rp.settings, k) for k in st}
+    offs = np.cumsum([0] + [3 * c["width"] * c["height"] for c in w.cams])
+    m_tot = float(offs[-1])
+    scale = [torch.full((1,), float(offs[v + 1] - offs[v]) / m_tot, device="cuda") for v in range(w.V)]
+    grads = Grads(*(torch.empty_like(w.params[k]) for k in PARAM_KEYS), torch.empty(w.n, device="cuda"))
+    d_scores = torch.empty_like(w.d_scores)
+    images = torch.empty_like(w.images)
+    d_img = torch.empty_like(w.d_img)
+    loss_v = torch.zeros(1, device="cuda")
+    m_hard, y_soft = torch.empty_like(w.m_hard), torch.empty_like(w.y_soft)
+
+    def plain_step():
+        M.mgs_sample_masks(rp.ctx, w.scores, w.tau, w.seed, w.step_id, m_hard, y_soft)
+        for v, c in enumerate(w.cams):
+            im = images[offs[v]:offs[v + 1]]
+            dv = d_img[offs[v]:offs[v + 1]]
+            rp.forward(fr, w.params, m_hard, [c], images=im)
+            M.mgs_l1_loss_grad(rp.ctx, im, w.targets[offs[v]:offs[v + 1]], dv, loss_v, w.red, grad_scale=scale[v])
+            rp.backward(fr, w.params, dv, out=grads, accumulate=v > 0)
+        M.mgs_mask_grad(rp.ctx, grads.masks, m_hard, y_soft, w.tau, w.lambda_m, d_scores, None, w.red)
+
+    for _ in range(max(1, warmup)):
+        plain_step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plain_step()
+    e1.record()
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1) / reps
+    # the same result as the batched step
+    w.step()
+    torch.cuda.synchronize()
+    same = {"images_equal": bool(torch.equal(images, w.images))}
+    for k in PARAM_KEYS + ("masks",):
+        a, b = getattr(grads, k), getattr(w.grads, k)
+        same[k] = float((a - b).norm() / b.norm().clamp_min(1e-30))
+    same["mask_scores"] = float((d_scores - w.d_scores).norm() / w.d_scores.norm().clamp_min(1e-30))
+    same["ok"] = bool(same["images_equal"] and max(v for k, v in same.items() if k != "images_equal") <= 1e-5)
+    if not same["ok"]:
+        log(f"[bench] the plain path's step differs from the batched step: {same}")
+    rp.release_frame(fr)
+    return {"ms_per_step": pms, "views_per_s": w.V / (pms * 1e-3), "settings": {**st, "persistent": 0, "stats": 0},
+            "same_result_as_batched": same}
+
+
+# ---------------------------------------------------------------------------
+# oracle legs (host cores; outside every timed region)
+# ---------------------------------------------------------------------------
 
 def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: float = 10.0) -> dict:
     """The FP64 oracle on a bounded sample of the same workload: the views
@@ -151,8 +415,43 @@ def cpu_baseline(scene: dict, tau: float, seed: int, step: int, min_seconds: flo
     return {"value": evals / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{len(done)} single-view fwd+bwd passes of the same scene and masks (views {', '.join(done)}), "
                       f"FP64, {evals} evals in {dt:.1f} s",
-            "views_per_s": len(done) / dt, "seconds": dt}
+            "views_per_s": len(done) / dt, "seconds": dt, **host_cpu()}
 
+
+def parity_check(w: Workload, view: int = 0) -> dict:
+    """The timed step's image of one view against the oracle run on the
+    GPU's own projected records of that view (stage protocol): element-wise
+    on the pixels whose discrete decisions are away from their thresholds."""
+    import oracle
+    torch, M = w.torch, w.M
+    ex = {k: M.mgs_frame_export(w.rast.ctx, w.frame, k) for k in ("records", "radius", "depth")}
+    torch.cuda.synchronize()
+    n = w.n
+    rec = ex["records"].view(-1, 12)[view * n:(view + 1) * n].cpu().numpy().astype(np.float64)
+    rad = ex["radius"][view * n:(view + 1) * n].cpu().numpy().astype(np.float64)
+    dbits = ex["depth"][view * n:(view + 1) * n].cpu().numpy().view(np.uint32)
+    a, beta, gamma = rec[:, 2], rec[:, 3], rec[:, 4]
+    conic = np.stack([a, a * beta, gamma + (a * beta) * beta], 1)
+    cam = w.cams[view]
+    ost = oracle.RasterSettings(sh_degree=w.deg)
+    masks = w.m_hard.cpu().numpy().astype(np.float64)
+    lists = oracle.build_lists([cam["width"]], [cam["height"]], n, rec[:, 0:2], rad, dbits,
+                               (rad > 0).astype(np.uint8), ost)
+    of = oracle.render_fwd([cam["width"]], [cam["height"]], n, rec[:, 0:2], conic, rec[:, 5], rec[:, 8:11], masks,
+                           lists, ost)
+    p = cam["width"] * cam["height"]
+    img = w.images[:3 * p].cpu().numpy().astype(np.float64)
+    ok = np.tile(of.flags == 0, 3)
+    scale = max(float(np.abs(of.image).max()), 1.0)
+    err = float(np.abs(img - of.image)[ok].max())
+    return {"view": f"{cam['width']}x{cam['height']}", "pixels": p, "flagged_fraction": float(1 - ok.mean()),
+            "max_abs_err_unflagged": err, "tolerance": 1e-5 * scale, "ok": bool(err <= 1e-5 * scale),
+            "protocol": "oracle compositing on the GPU's own records of the timed step"}
+
+
+# ---------------------------------------------------------------------------
+# extras: pruning, forward-only rendering, training
+# ---------------------------------------------------------------------------
 
 def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 20) -> dict:
     """Probabilistic pruning (10 draws) of a whole per-Gaussian training state
@@ -231,6 +530,7 @@ def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 20
     pr_ms = render_ms({key: pruned[key] for key in PARAM_KEYS}, k)
     imp_ms = render_ms(params, n, importance=True)
     for fr in frames:
+        rast.reserve(fr, 0)
         rast.release_frame(fr)
     V = len(cams)
     return {
@@ -246,6 +546,106 @@ def prune_and_render(rast, params: dict, n: int, cams, seed: int, reps: int = 20
     }
 
 
+def training_run(n: int, steps: int, lambda_m: float, settings: dict, oracle_eval: bool = True,
+                 batch: int = 4, seed: int = 5) -> dict:
+    """The training workload: targets rendered from the ground-truth set
+    (all masks 1) at 32 poses, then `steps` steps of the autograd training
+    step (Gumbel masks, masked forward, L1 + lambda_m L_m, backward, Adam on
+    every attribute and both scores) in batches of 4 views, each batch's step
+    captured once into a hipGraph.  Reports ms per step, the trajectory of the
+    sampled mask fraction and of the L1 loss, and the PSNR on the 128x128
+    evaluation crop of view 0 against the ground truth, rendered by the GPU
+    and by the FP64 oracle (masks from 10 pruning draws)."""
+    import torch
+    import scenegen
+    from paper_2412_20522_amd import maskgs as M
+    from paper_2412_20522_amd.raster import PARAM_KEYS, Rasterizer
+    from paper_2412_20522_amd.train import TRAIN_KEYS, Trainer
+    t_gen = time.perf_counter()
+    ts = scenegen.training_scene(n=n)
+    gt, tr, cams = ts["gt"], ts["trainee"], ts["cameras"]
+    log(f"[bench] training: generated {ts['name']} in {time.perf_counter() - t_gen:.1f} s")
+    dev = torch.device("cuda:0")
+    rast = Rasterizer(0, sh_degree=3, bg=(0.0, 0.0, 0.0), persistent=1, stats=0, **settings)
+    batches = [cams[i:i + batch] for i in range(0, len(cams), batch)]
+    gtp = {k: torch.from_numpy(np.ascontiguousarray(gt[k], np.float32)).to(dev) for k in PARAM_KEYS}
+    ones = torch.ones(n, device=dev)
+    fr = rast.acquire_frame()
+    targets = [rast.forward(fr, gtp, ones, b).clone() for b in batches]
+    params = {k: torch.from_numpy(np.ascontiguousarray(tr[k], np.float32)).to(dev) for k in TRAIN_KEYS}
+    crop = scenegen.crop_camera(cams[0], 896, 480, 128, 128)
+    gt_crop = rast.forward(fr, gtp, ones, [crop]).clone()
+    eval_seed = 777
+
+    def evaluate(label: str) -> dict:
+        keep = torch.empty(n, dtype=torch.int32, device=dev)
+        M.mgs_prune_sample(rast.ctx, params["mask_scores"].detach(), eval_seed, 0, 10, keep)
+        m_eval = keep.to(torch.float32)
+        img = rast.forward(fr, {k: params[k].detach() for k in PARAM_KEYS}, m_eval, [crop]).clone()
+        torch.cuda.synchronize()
+        out = {"kept_fraction": float(m_eval.mean()),
+               "psnr_gpu": float(-10 * torch.log10(((img - gt_crop) ** 2).mean()))}
+        if oracle_eval:
+            import oracle
+            host = {k: params[k].detach().cpu().numpy() for k in TRAIN_KEYS}
+            mk = oracle.prune_keep(host["mask_scores"], eval_seed, 0, 10).astype(np.float64)
+            ost = oracle.RasterSettings(sh_degree=3)
+            o_img = oracle.run_pipeline(host, [crop], mk, ost, backward=False).fwd.image
+            o_gt = oracle.run_pipeline(gt, [crop], np.ones(n), ost, backward=False).fwd.image
+            g_img = img.cpu().numpy().astype(np.float64)
+            out["psnr_oracle"] = oracle.psnr(o_img, o_gt)
+            out["masks_equal_oracle"] = bool(np.array_equal(mk, m_eval.cpu().numpy().astype(np.float64)))
+            out["gpu_vs_oracle_max_abs"] = float(np.abs(g_img - o_img).max())
+            out["gpu_vs_oracle_psnr"] = oracle.psnr(g_img, o_img)
+        log(f"[bench] training {label}: {out}")
+        return out
+
+    before = evaluate("before")
+    trainer = Trainer(rast, params, batches, targets, tau=0.5, seed=seed, lambda_m=lambda_m)
+    t_prep = time.perf_counter()
+    trainer.reserve(1.5)
+    warm = 3
+    hist_l1 = torch.zeros(steps, device=dev)
+    hist_lm = torch.zeros(steps, device=dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for i in range(warm):
+            rec = trainer.step()
+            hist_l1[i].copy_(rec.l1)
+            hist_lm[i].copy_(rec.mask_loss)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    trainer.capture()
+    log(f"[bench] training: reserved and captured {len(batches)} graphs in {time.perf_counter() - t_prep:.1f} s")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(warm, steps):
+        rec = trainer.step()
+        hist_l1[i].copy_(rec.l1)
+        hist_lm[i].copy_(rec.mask_loss)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(steps - warm, 1)
+    trainer.check()
+    after = evaluate("after")
+    l1 = hist_l1.cpu().numpy()
+    frac = np.sqrt(hist_lm.cpu().numpy())  # L_m = (mean M)^2
+    pick = sorted(set(list(range(0, steps, 10)) + [steps - 1]))
+    sc = params["mask_scores"].detach()
+    p_exist = float(torch.sigmoid(sc[:, 0] - sc[:, 1]).mean())
+    trainer.close()
+    rast.release_frame(fr)
+    return {"gaussians": n, "views_per_step": batch, "view_size": f"{cams[0]['width']}x{cams[0]['height']}",
+            "poses": len(cams), "steps": steps, "lambda_m": lambda_m, "graphs": len(batches),
+            "ms_per_step": ms, "views_per_s": batch / (ms * 1e-3),
+            "timed": f"{steps - warm} graph replays after {warm} eager steps",
+            "sampled_mask_fraction": {str(i): round(float(frac[i]), 5) for i in pick},
+            "l1": {str(i): round(float(l1[i]), 5) for i in pick},
+            "mean_existence_probability_end": p_exist,
+            "crop_eval": {"crop": "view 0, origin (896, 480), 128x128", "before": before, "after": after}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,11 +656,14 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the pruning and forward-only timings")
+    ap.add_argument("--no-single-view", action="store_true", help="skip the single-view workloads")
+    ap.add_argument("--train-steps", type=int, default=200, help="training run length (0: skip it)")
+    ap.add_argument("--train-gaussians", type=int, default=3_000_000)
+    ap.add_argument("--train-lambda", type=float, default=0.1)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--batch-depth", type=int, default=128)
-    ap.add_argument("--fwd-ppt", type=int, default=4)
+    ap.add_argument("--fwd-ppt", type=int, default=2)
     ap.add_argument("--bwd-ppt", type=int, default=4)
-    ap.add_argument("--persistent", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="pick tile shape / batch depth / pixels per thread")
     ap.add_argument("--graph", type=int, default=1, help="time replays of a hipGraph-captured step")
     ap.add_argument("--tile-cull", type=int, default=1, help="narrow instances only for reachable tiles")
@@ -279,8 +682,6 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
-    from paper_2412_20522_amd import maskgs as M
-    from paper_2412_20522_amd.raster import PARAM_KEYS, Grads, Rasterizer
 
     if args.copy_calibration_mib > 0:
         # a plain copy of known size: reads and writes exactly this many bytes
@@ -296,175 +697,69 @@ def main() -> int:
     t_gen = time.perf_counter()
     scene, desc = build_workload(args.workload)
     log(f"[bench] generated {scene['name']} in {time.perf_counter() - t_gen:.1f} s")
-    cams = scene["cameras"]
-    V = len(cams)
-    n = scene["means"].shape[0]
-    deg = scene["sh_degree"]
-    tau = float(scene.get("gumbel_tau", 0.5))
-    lambda_m, seed, step_id = 0.1, 2412, 0
-    dev = torch.device("cuda:0")
-    params = {k: torch.from_numpy(np.ascontiguousarray(scene[k], np.float32)).to(dev) for k in PARAM_KEYS}
-    scores = torch.from_numpy(scene["mask_scores"]).to(dev)
-    P = sum(c["width"] * c["height"] for c in cams)
-    targets = torch.cat([torch.from_numpy(t.reshape(-1)) for t in scene["targets"]]).to(dev)
     tw, th = (int(x) for x in args.tile.split("x"))
-    rast = Rasterizer(0, sh_degree=deg, tile_w=tw, tile_h=th, batch_depth=args.batch_depth, fwd_ppt=args.fwd_ppt,
-                      bwd_ppt=args.bwd_ppt, persistent=args.persistent, wide_tiles=args.wide_tiles,
-                      tile_cull=args.tile_cull)
-    ctx = rast.ctx
-    frame = rast.acquire_frame()
-    images = torch.empty(3 * P, device=dev)
-    d_img = torch.empty_like(images)
-    loss = torch.zeros(1, device=dev)
-    loss_m = torch.zeros(1, device=dev)
-    grads = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS), torch.empty(n, device=dev))
-    d_scores = torch.empty(n, 2, device=dev)
-    m_hard = torch.empty(n, device=dev)
-    y_soft = torch.empty(n, device=dev)
-    red_scratch = torch.empty(int(M.lib().mgs_reduce_scratch_bytes(3 * P)), dtype=torch.uint8, device=dev)
-
-    def batched_step():
-        M.mgs_sample_masks(ctx, scores, tau, seed, step_id, m_hard, y_soft)
-        rast.forward(frame, params, m_hard, cams, images=images)
-        M.mgs_l1_loss_grad(ctx, images, targets, d_img, loss, red_scratch)
-        rast.backward(frame, params, d_img, out=grads)
-        M.mgs_mask_grad(ctx, grads.masks, m_hard, y_soft, tau, lambda_m, d_scores, loss_m, red_scratch)
-
-    # the evaluation count at 16x16 tiles (the numerator), untimed
-    # (lists of Sec. 3.1 exactly: no tile culling, so the count is that of the
-    # full lists whatever the timed configuration skips)
-    rast.set(tile_w=16, tile_h=16, fwd_ppt=1, bwd_ppt=4, persistent=0, tile_cull=0)
-    M.mgs_sample_masks(ctx, scores, tau, seed, step_id, m_hard, y_soft)
-    rast.forward(frame, params, m_hard, cams, images=images)
-    counts16 = rast.count_evals(frame)
-    E16 = counts16["examined"]
-    rast.set(tile_w=tw, tile_h=th, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt, persistent=args.persistent,
-             tile_cull=args.tile_cull)
-    log(f"[bench] E16 = {E16:.4e} evals per step ({V} views, {P} pixels, {n} Gaussians)")
-
-    tuned = None
-    if args.autotune:
-        batched_step()  # fills the image gradient the tuner backpropagates
-        torch.cuda.synchronize()
-        t_at = time.perf_counter()
-        tuned, tune_ms = rast.autotune(frame, params, m_hard, cams, d_img, images=images, out=grads)
-        log(f"[bench] autotune: {tuned} ({tune_ms:.3f} ms fwd+bwd) in {time.perf_counter() - t_at:.1f} s")
-    # work counters of the settings actually timed (one untimed step), then
-    # the timed configuration without counters
-    rast.set(stats=1)
-    batched_step()
-    torch.cuda.synchronize()
-    counts = rast.count_evals(frame)
-    fstats = rast.stats(frame)
-    rast.set(stats=0)
-    for _ in range(args.warmup):
-        batched_step()
-    torch.cuda.synchronize()
-
-    # per-stage profile: eager steps with HIP events around every stage on
-    # the launch stream (a graph replay cannot be split by stage)
-    M.mgs_profile_enable(ctx, True)
-    n_prof = max(1, min(args.steps, 5))
-    for _ in range(n_prof):
-        batched_step()
-    torch.cuda.synchronize()
-    prof = M.mgs_profile_read(ctx)
-    M.mgs_profile_enable(ctx, False)
-    prof = {k: (v[0] / n_prof, v[1] // n_prof) for k, v in prof.items()}
-
-    graph = None
-    run = batched_step
-    if args.graph:
-        # fixed workspace, then capture one whole step into a hipGraph
-        rast.reserve(frame, 1.25)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            batched_step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            batched_step()
-        run = graph.replay
-        for _ in range(args.warmup):
-            run()
-        torch.cuda.synchronize()
-        rast.check(frame)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    if graph is not None:
-        rast.check(frame)  # raises if a replay outgrew the fixed workspace
-        # the replayed step must equal an eager step on the same inputs
-        img_g, dm_g, dp_g = images.clone(), grads.masks.clone(), grads.means.clone()
-        batched_step()
-        torch.cuda.synchronize()
-        same_img = bool(torch.equal(img_g, images))
-        e_m = float((dm_g - grads.masks).norm() / grads.masks.norm().clamp_min(1e-30))
-        e_p = float((dp_g - grads.means).norm() / grads.means.norm().clamp_min(1e-30))
-        if not same_img or e_m > 1e-5 or e_p > 1e-5:
-            raise RuntimeError(f"graph replay differs from the eager step: images equal {same_img}, "
-                               f"dM rel {e_m:.2e}, dmeans rel {e_p:.2e}")
-    log(f"[bench] batched{' (graph)' if graph is not None else ''}: {ms_step:.3f} ms/step "
-        f"(wall {1e3 * wall / args.steps:.3f}), K = {fstats['n_instances']}, wide records = {fstats['n_wide']}")
-    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
-    for k, v in prof.items():
-        if v[1]:
-            log(f"[bench]   {k:14s} {v[0] / v[1]:9.3f} ms/launch x {v[1]}")
-    dom = max(stage_ms, key=lambda k: prof[k][0])
-    roof = stage_roofline(dom, stage_ms[dom], counts, fstats, n, V, deg)
-    roof = {"kernel": dom, "ms_per_launch": stage_ms[dom], **roof, "traffic": measured_traffic(dom)}
+    base = dict(tile_w=tw, tile_h=th, batch_depth=args.batch_depth, fwd_ppt=args.fwd_ppt, bwd_ppt=args.bwd_ppt,
+                wide_tiles=args.wide_tiles, tile_cull=args.tile_cull)
+    w = Workload(scene, desc, dict(base, persistent=1))
+    res = measure(w, args.steps, args.warmup, bool(args.autotune), bool(args.graph), args.workload)
+    ms_step, E16, counts, fstats = res["ms_per_step"], res["E16"], res["counts"], res["fstats"]
+    tuned = w.settings_dict()
+    roof = dict(res["roofline"])
+    roof["traffic"] = measured_traffic(roof["kernel"])
+    roof["combined"] = res["combined"]
 
     plain = None
-    if not args.no_plain and V > 1:
-        rast_p = Rasterizer(0, sh_degree=deg, tile_w=16, tile_h=16, persistent=0)
-        fr = rast_p.acquire_frame()
-        offs = np.cumsum([0] + [3 * c["width"] * c["height"] for c in cams])
-
-        def plain_step():
-            M.mgs_sample_masks(rast_p.ctx, scores, tau, seed, step_id, m_hard, y_soft)
-            for v, c in enumerate(cams):
-                im = images[offs[v]:offs[v + 1]]
-                dv = d_img[offs[v]:offs[v + 1]]
-                rast_p.forward(fr, params, m_hard, [c], images=im)
-                M.mgs_l1_loss_grad(rast_p.ctx, im, targets[offs[v]:offs[v + 1]], dv, loss, red_scratch)
-                rast_p.backward(fr, params, dv, out=grads)
-            M.mgs_mask_grad(rast_p.ctx, grads.masks, m_hard, y_soft, tau, lambda_m, d_scores, loss_m, red_scratch)
-
-        for _ in range(max(1, args.warmup // 2)):
-            plain_step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.plain_steps):
-            plain_step()
-        e1.record()
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1) / args.plain_steps
-        plain = {"ms_per_step": pms, "evals_per_s": E16 / (pms * 1e-3), "views_per_s": V / (pms * 1e-3)}
-        log(f"[bench] plain: {pms:.3f} ms/step")
+    if not args.no_plain and w.V > 1:
+        plain = plain_path(w, args.plain_steps, max(1, args.warmup // 2), autotune=bool(args.autotune))
+        log(f"[bench] plain: {plain['ms_per_step']:.3f} ms/step with {plain['settings']}, "
+            f"same result: {plain['same_result_as_batched']}")
+        if args.autotune:
+            alt = plain_path(w, args.plain_steps, max(1, args.warmup // 2), autotune=False)
+            plain["with_batched_settings"] = {k: alt[k] for k in ("ms_per_step", "views_per_s", "settings")}
+            log(f"[bench] plain with the batched settings: {alt['ms_per_step']:.3f} ms/step")
 
     extras = None
     if not args.no_extras:
-        extras = prune_and_render(rast, params, n, cams, seed)
-        log(f"[bench] pruning: {extras['prune']['ms']:.3f} ms ({extras['prune']['kept']} of {n} kept, "
+        extras = prune_and_render(w.rast, w.params, w.n, w.cams, w.seed)
+        log(f"[bench] pruning: {extras['prune']['ms']:.3f} ms ({extras['prune']['kept']} of {w.n} kept, "
             f"{extras['prune']['GB_per_s']:.0f} GB/s); forward only: full {extras['render_only']['full']['ms']:.3f} ms, "
-            f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {V} views "
+            f"pruned {extras['render_only']['pruned']['ms']:.3f} ms for {w.V} views "
             f"(x{extras['render_only']['speedup']:.2f}); with importance {extras['importance']['ms']:.3f} ms")
 
+    single = None
+    if not args.no_single_view and args.workload == "batched":
+        single = {}
+        for name in ("tiny", "object", "unbounded"):
+            sc, d = build_workload(name)
+            ws = Workload(sc, d, dict(base, persistent=1))
+            r = measure(ws, args.steps, args.warmup, bool(args.autotune), bool(args.graph), name)
+            single[name] = {"workload": d, "ms_per_step": r["ms_per_step"], "evals_per_step_16x16": r["E16"],
+                            "evals_per_s": r["E16"] / (r["ms_per_step"] * 1e-3),
+                            "evaluated_pairs_per_s": r["counts"]["evaluated"] / (r["ms_per_step"] * 1e-3),
+                            "views_per_s": 1.0 / (r["ms_per_step"] * 1e-3), "settings": ws.settings_dict(),
+                            "roofline": {k: r["roofline"][k] for k in ("kernel", "bound", "frac", "ms_per_launch")},
+                            "combined_frac": r["combined"]["frac"],
+                            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}}
+            ws.rast.reserve(ws.frame, 0)
+            ws.rast.release_frame(ws.frame)
+            del ws
+
+    training = None
+    if args.train_steps > 0 and args.workload == "batched":
+        training = training_run(args.train_gaussians, args.train_steps, args.train_lambda,
+                                {k: tuned[k] for k in ("tile_w", "tile_h", "batch_depth", "fwd_ppt", "bwd_ppt",
+                                                       "wide_tiles", "tile_cull")},
+                                oracle_eval=not args.no_cpu_baseline)
+        log(f"[bench] training: {training['ms_per_step']:.3f} ms/step")
+
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
+        parity = parity_check(w, 0)
+        log(f"[bench] parity of the timed step (view {parity['view']}): {parity}")
         log("[bench] timing the FP64 oracle on a bounded sample of the views ...")
-        cpu = cpu_baseline(scene, tau, seed, step_id)
-        log(f"[bench] oracle: {cpu['sample']} on {cpu['cores']} threads")
+        cpu = cpu_baseline(scene, w.tau, w.seed, w.step_id)
+        log(f"[bench] oracle: {cpu['sample']} on {cpu['cores']} threads ({cpu['cpu_model']}, nproc {cpu['nproc']})")
 
     value = E16 / (ms_step * 1e-3)
     out = {
@@ -482,32 +777,41 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "gaussians": n,
-            "views": V,
-            "pixels": P,
+            "gaussians": w.n,
+            "views": w.V,
+            "pixels": w.P,
             "evals_per_step_16x16": E16,
+            "evaluated_pairs_per_step": counts["evaluated"],
+            "evaluated_pairs_per_s": counts["evaluated"] / (ms_step * 1e-3),
             "instances": fstats["n_instances"],
             "wide_records": fstats["n_wide"],
-            "views_per_s": V / (ms_step * 1e-3),
-            "tile": f"{rast.settings.tile_w}x{rast.settings.tile_h}",
-            "batch_depth": rast.settings.batch_depth,
-            "fwd_ppt": rast.settings.fwd_ppt,
-            "bwd_ppt": rast.settings.bwd_ppt,
-            "wide_tiles": rast.settings.wide_tiles,
-            "tile_cull": bool(rast.settings.tile_cull),
-            "autotuned": tuned is not None,
-            "graph": graph is not None,
-            "persistent": bool(rast.settings.persistent),
+            "views_per_s": w.V / (ms_step * 1e-3),
+            "tile": f"{tuned['tile_w']}x{tuned['tile_h']}",
+            "batch_depth": tuned["batch_depth"],
+            "fwd_ppt": tuned["fwd_ppt"],
+            "bwd_ppt": tuned["bwd_ppt"],
+            "wide_tiles": tuned["wide_tiles"],
+            "tile_cull": bool(tuned["tile_cull"]),
+            "autotuned": res["tuned"] is not None,
+            "graph": res["graph"] is not None,
+            "persistent": True,
             "eval_counts": counts,
             "plain": plain,
+            "parity": parity,
+            "single_view": single,
+            "training": training,
             "pruning": extras["prune"] if extras else None,
             "render_only": extras["render_only"] if extras else None,
             "importance": extras["importance"] if extras else None,
-            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if prof[k][1]},
+            "stage_ms": {k: round(v, 4) for k, v in res["stage_ms"].items()},
         },
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if parity is not None and not parity["ok"]:
+        log("[bench] the timed step failed its parity check")
+        print(json.dumps(out), flush=True)
+        return 1
     print(json.dumps(out), flush=True)
     return 0
 

@@ -144,8 +144,11 @@ typedef struct {
     int64_t n;
 } mgs_gaussians;
 
-/* Gradient outputs (device pointers, float32, overwritten, not accumulated).
- * Any pointer may be NULL to skip that output. */
+/* Gradient outputs (device pointers, float32).  Any pointer may be NULL to
+ * skip that output.  With accumulate = 0 every output is overwritten; with
+ * accumulate = 1 the parameter and mask gradients are added to what the
+ * arrays hold (per-view calls summing a multi-view gradient), d_records is
+ * still overwritten. */
 typedef struct {
     float* d_means;          /* [N, 3] */
     float* d_log_scales;     /* [N, 3] */
@@ -160,6 +163,7 @@ typedef struct {
                                 stored conic, dL/dopacity (of M_i o_i under
                                 MGS_MASK_OPACITY), dL/d(r, g, b); rows of
                                 records without a valid projection are 0 */
+    int32_t accumulate;      /* 0: overwrite, 1: add (see above) */
 } mgs_gradients;
 
 typedef struct {
@@ -391,14 +395,22 @@ MGS_API mgs_status mgs_project(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussi
                                int n_views, const mgs_settings* st, float* rec, float* depth, float* radius,
                                uint32_t* tiles);
 
-/* Exclusive prefix sum of n u32 values; total_dev (device, one u64) gets
+/* Binning stages.  Sec. 3.1 renders each pixel from the Gaussians that
+ * intersect its 16x16 tile, in depth order; these four calls build those
+ * per-tile lists: offsets of every record's entries (scan of the tile
+ * counts), one (tile, depth) key per covered tile (duplication), the keys in
+ * (tile, depth, record) order (stable radix sort) and each tile's slice of
+ * the sorted list (ranges).
+ *
+ * Exclusive prefix sum of n u32 values; total_dev (device, one u64) gets
  * the sum.  scratch must hold mgs_scan_scratch_bytes(n) bytes. */
 MGS_API size_t mgs_scan_scratch_bytes(int64_t n);
 MGS_API mgs_status mgs_scan(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
                             uint64_t* total_dev, void* scratch);
 
-/* Writes, for every record r with tiles > 0 and every tile t of its
- * footprint, key = (global tile id << 32) | float bits of depth and
+/* Tile lists of Sec. 3.1: writes, for every record r with tiles > 0 and
+ * every tile t of its footprint, key = (global tile id << 32) | float bits
+ * of depth and
  * value = r, starting at offsets[r].  Global tile ids number the tiles of
  * view 0 first, row-major.  Entries at or beyond capacity are not written
  * and raise the capacity flag. */
@@ -407,16 +419,17 @@ MGS_API mgs_status mgs_duplicate(mgs_ctx* ctx, mgs_stream stream, const float* r
                                  const mgs_camera* cams, int n_views, const mgs_settings* st, uint64_t* keys,
                                  uint32_t* vals, int64_t capacity);
 
-/* Stable LSD radix sort of K (key, value) pairs on the low key_bits bits of
- * the key (8 bits per pass).  Sorted pairs end in keys/vals; keys_alt and
+/* Depth order within each tile (Sec. 3.1): stable LSD radix sort of K
+ * (key, value) pairs on the low key_bits bits of the key (8 bits per pass).  Sorted pairs end in keys/vals; keys_alt and
  * vals_alt (K entries each) are scratch; scratch holds
  * mgs_sort_scratch_bytes(K) bytes. */
 MGS_API size_t mgs_sort_scratch_bytes(int64_t K);
 MGS_API mgs_status mgs_sort(mgs_ctx* ctx, mgs_stream stream, uint64_t* keys, uint32_t* vals, int64_t K,
                             int key_bits, uint64_t* keys_alt, uint32_t* vals_alt, void* scratch);
 
-/* [start, end) of every global tile in the sorted keys; tiles without
- * entries get [0, 0).  ranges [total_tiles, 2] (u32). */
+/* Each tile's list (Sec. 3.1): [start, end) of every global tile in the
+ * sorted keys; tiles without entries get [0, 0).  ranges [total_tiles, 2]
+ * (u32). */
 MGS_API mgs_status mgs_tile_ranges(mgs_ctx* ctx, mgs_stream stream, const uint64_t* keys, int64_t K,
                                    int64_t total_tiles, uint32_t* ranges);
 
@@ -457,12 +470,16 @@ MGS_API mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const m
 
 /* Straight-through Gumbel-Softmax over two scores per Gaussian (Sec. 3.3).
  * scores [n, 2] (column 0 = exists).  Philox4x32-10 with counter
- * (i lo, i hi, step lo, step hi) and key (seed lo, seed hi) gives uniforms
+ * (i lo, i hi, t lo, t hi) and key (seed lo, seed hi) gives uniforms
  * u = (bits >> 8 + 0.5) 2^-24 for the two scores, g = -log(-log u), computed
  * in double.  m_hard [n] = [s0 + g0 > s1 + g1]; y_soft [n] =
- * sigmoid((s0 + g0 - s1 - g1) / tau). */
+ * sigmoid((s0 + g0 - s1 - g1) / tau).  The counter step is
+ * t = step + *step_offset when step_offset (device, one u64, optional) is
+ * given: a captured training step then draws fresh masks at every replay
+ * while mgs_step_advance moves the counter. */
 MGS_API mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float tau,
-                                    uint64_t seed, uint64_t step, float* m_hard, float* y_soft);
+                                    uint64_t seed, uint64_t step, const uint64_t* step_offset, float* m_hard,
+                                    float* y_soft);
 
 /* Deterministic masks with a straight-through estimator, the alternative to
  * Gumbel sampling in the ablation of Sec. 4.3 (Table 6): y = sigmoid(s0 - s1)
@@ -474,15 +491,24 @@ MGS_API mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float
 MGS_API mgs_status mgs_threshold_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n,
                                        float threshold, float* m_hard, float* y_soft);
 
-/* Gradient to the scores through the straight-through mask, adding the
- * mask-count loss L_m = (mean M)^2 weighted by lambda_m (Eq. 7-8):
- * d_scores[i, 0] = (d_masks[i] + lambda_m 2 sum(M) / n^2) y (1 - y) / tau,
- * d_scores[i, 1] = -d_scores[i, 0].  loss_m (device, one float, optional)
- * receives L_m.  scratch holds mgs_reduce_scratch_bytes(n) bytes. */
+/* The mask-count loss of Eq. (7), L_m = (mean M)^2 over the n hard masks,
+ * into loss_m (device, one float; 0 for n = 0), summed in double.  scratch
+ * holds mgs_reduce_scratch_bytes(n) bytes.  Asynchronous. */
 MGS_API size_t mgs_reduce_scratch_bytes(int64_t n);
+MGS_API mgs_status mgs_mask_loss(mgs_ctx* ctx, mgs_stream stream, const float* m_hard, int64_t n, float* loss_m,
+                                 void* scratch);
+
+/* Gradient to the scores through the straight-through mask, adding the
+ * mask-count loss L_m = (mean M)^2 with weight w (Eq. 7-8):
+ * d_scores[i, 0] = (d_masks[i] + w 2 sum(M) / n^2) y (1 - y) / tau,
+ * d_scores[i, 1] = -d_scores[i, 0], where w = lambda_m, times *lambda_scale
+ * when lambda_scale (device, one float, optional) is given -- under autograd
+ * the incoming gradient of L_m, so that no value crosses to the host.
+ * loss_m (device, one float, optional) receives L_m.  scratch holds
+ * mgs_reduce_scratch_bytes(n) bytes.  d_scores 8-byte aligned. */
 MGS_API mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
-                                 const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores,
-                                 float* loss_m, void* scratch);
+                                 const float* y_soft, int64_t n, float tau, float lambda_m, const float* lambda_scale,
+                                 float* d_scores, float* loss_m, void* scratch);
 
 /* Probabilistic pruning (Sec. 3.5, training and pruning): every Gaussian
  * draws n_draws (>= 1; 10 in the paper) hard masks with the rule of
@@ -506,16 +532,48 @@ MGS_API mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint3
                                     const float* const* in, float* const* out, const int* widths, uint64_t* n_kept,
                                     void* scratch);
 
-/* L1 rendering loss over m elements (mean |image - target|, sign(0) = 0):
- * d_images [m] = sign(image - target) / m; loss (device, one float,
- * optional).  scratch holds mgs_reduce_scratch_bytes(m) bytes. */
+/* L1 rendering loss over m elements, the rendering loss L_render of Eq. (8)
+ * (mean |image - target|, sign(0) = 0): d_images [m] (optional) =
+ * sign(image - target) / m, times *grad_scale when grad_scale (device, one
+ * float, optional) is given (the upstream gradient under autograd); loss
+ * (device, one float, optional; 0 for m = 0).  At least one of d_images and
+ * loss.  scratch holds mgs_reduce_scratch_bytes(m) bytes. */
 MGS_API mgs_status mgs_l1_loss_grad(mgs_ctx* ctx, mgs_stream stream, const float* images, const float* targets,
-                                    int64_t m, float* d_images, float* loss, void* scratch);
+                                    int64_t m, float* d_images, const float* grad_scale, float* loss, void* scratch);
 
 /* One Adam step (Kingma and Ba) over n float32 parameters, in place on
- * params, m and v; step >= 1 is the bias-correction step count. */
+ * params, m and v; step >= 1 is the bias-correction step count.  (The paper
+ * trains every attribute and the mask scores with the optimiser of 3DGS,
+ * Sec. 4.1, without restating it.) */
 MGS_API mgs_status mgs_adam_step(mgs_ctx* ctx, mgs_stream stream, float* params, const float* grads, float* m,
                                  float* v, int64_t n, float lr, float beta1, float beta2, float eps, int64_t step);
+
+/* One array of an Adam step over several arrays (device pointers, float32,
+ * n elements each, updated in place; lr is this array's learning rate). */
+typedef struct {
+    float* params;
+    const float* grads;
+    float* m;
+    float* v;
+    int64_t n;
+    float lr;
+} mgs_adam_array;
+
+/* The Adam step of mgs_adam_step over n_arrays arrays (host array of
+ * descriptors; every attribute and the mask scores of a training step, each
+ * with its own learning rate) in one launch per 16 arrays.  The
+ * bias-correction step is t = step + *step_offset when step_offset (device,
+ * one i64, optional) is given, else step; t must be >= 1 (with a device
+ * offset this is not checked).  Arrays with n = 0 are skipped; n < 2^40.
+ * Asynchronous, no allocation. */
+MGS_API mgs_status mgs_adam_step_multi(mgs_ctx* ctx, mgs_stream stream, const mgs_adam_array* arrays, int n_arrays,
+                                       float beta1, float beta2, float eps, int64_t step,
+                                       const int64_t* step_offset);
+
+/* counter[0] += delta on the device (one i64, caller-owned): advances the
+ * step counter that mgs_sample_masks and mgs_adam_step_multi read, inside a
+ * captured step.  Asynchronous. */
+MGS_API mgs_status mgs_step_advance(mgs_ctx* ctx, mgs_stream stream, int64_t* counter, int64_t delta);
 
 #ifdef __cplusplus
 }

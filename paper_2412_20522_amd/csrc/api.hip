@@ -316,7 +316,7 @@ struct mgs_frame {
 
 extern "C" {
 
-int mgs_version(void) { return 100; }
+int mgs_version(void) { return 200; }
 
 mgs_status mgs_default_settings(mgs_settings* out) {
     if (!out) return MGS_ERR_INVALID_ARG;
@@ -398,7 +398,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
                       &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
                       &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
-                      &f->misc,     &f->queue,     &f->sum_tmp};
+                      &f->misc,     &f->queue,     &f->sum_tmp,  &f->imp_acc};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
     delete f;
@@ -681,6 +681,8 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     if (!dl_dimages || !grads) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
         return fail(ctx, MGS_ERR_INVALID_ARG, "d_quats must be 16-byte aligned");
+    if (grads->accumulate != 0 && grads->accumulate != 1)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     mgs_status s;
     // per-record 2D gradients and mask gradients accumulate in FP64: a wide
     // splat takes atomics from thousands of tiles whose partial sums cancel
@@ -722,6 +724,9 @@ mgs_status mgs_autotune(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     mgs_status s;
     if ((s = check_settings(ctx, base)) != MGS_OK) return s;
     if (!dl_dimages || !grads || !images) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    mgs_gradients gw = *grads;
+    gw.accumulate = 0;  // every trial overwrites the gradients
+    grads = &gw;
     const bool was_on = ctx->prof_on;
     ctx->prof_on = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1033,6 +1038,8 @@ mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gauss
     if (!grads || (g->n > 0 && !d_rec)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (grads->d_quats && ((uintptr_t)grads->d_quats & 15) != 0)
         return fail(ctx, MGS_ERR_INVALID_ARG, "d_quats must be 16-byte aligned");
+    if (grads->accumulate != 0 && grads->accumulate != 1)
+        return fail(ctx, MGS_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
     set_limits(vs, cams, st->jac_clamp);
     DevSettings ds = make_settings(st);
@@ -1046,14 +1053,14 @@ mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gauss
 // ---------------------------------------------------------------------------
 
 mgs_status mgs_sample_masks(mgs_ctx* ctx, mgs_stream stream, const float* scores, int64_t n, float tau, uint64_t seed,
-                            uint64_t step, float* m_hard, float* y_soft) {
+                            uint64_t step, const uint64_t* step_offset, float* m_hard, float* y_soft) {
     if (!ctx) return MGS_ERR_INVALID_ARG;
     if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
     if (!(tau > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "tau must be > 0");
     if (n > 0 && (!scores || !m_hard || !y_soft)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (((uintptr_t)scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "scores must be 8-byte aligned");
     StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_SAMPLE_MASKS);
-    launch_sample_masks((hipStream_t)stream, scores, n, tau, seed, step, m_hard, y_soft);
+    launch_sample_masks((hipStream_t)stream, scores, n, tau, seed, step, step_offset, m_hard, y_soft);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }
@@ -1116,9 +1123,20 @@ mgs_status mgs_compact_rows(mgs_ctx* ctx, mgs_stream stream, const uint32_t* kee
     return MGS_OK;
 }
 
-mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
-                         const float* y_soft, int64_t n, float tau, float lambda_m, float* d_scores, float* loss_m,
+mgs_status mgs_mask_loss(mgs_ctx* ctx, mgs_stream stream, const float* m_hard, int64_t n, float* loss_m,
                          void* scratch) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (!loss_m || (n > 0 && (!m_hard || !scratch))) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_MASK_GRAD);
+    launch_mask_loss((hipStream_t)stream, m_hard, n, loss_m, scratch);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, const float* m_hard,
+                         const float* y_soft, int64_t n, float tau, float lambda_m, const float* lambda_scale,
+                         float* d_scores, float* loss_m, void* scratch) {
     if (!ctx) return MGS_ERR_INVALID_ARG;
     if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
     if (!(tau > 0.f)) return fail(ctx, MGS_ERR_INVALID_ARG, "tau must be > 0");
@@ -1126,19 +1144,25 @@ mgs_status mgs_mask_grad(mgs_ctx* ctx, mgs_stream stream, const float* d_masks, 
         return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (((uintptr_t)d_scores & 7) != 0) return fail(ctx, MGS_ERR_INVALID_ARG, "d_scores must be 8-byte aligned");
     StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_MASK_GRAD);
-    launch_mask_grad((hipStream_t)stream, d_masks, m_hard, y_soft, n, tau, lambda_m, d_scores, loss_m, scratch);
+    launch_mask_grad((hipStream_t)stream, d_masks, m_hard, y_soft, n, tau, lambda_m, lambda_scale, d_scores, loss_m,
+                     scratch);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }
 
 mgs_status mgs_l1_loss_grad(mgs_ctx* ctx, mgs_stream stream, const float* images, const float* targets, int64_t m,
-                            float* d_images, float* loss, void* scratch) {
+                            float* d_images, const float* grad_scale, float* loss, void* scratch) {
     if (!ctx) return MGS_ERR_INVALID_ARG;
     if (m < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "m < 0");
-    if (m > 0 && (!images || !targets || !d_images || !scratch))
-        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (m > 0 && (!images || !targets || !scratch)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (!d_images && !loss) return fail(ctx, MGS_ERR_INVALID_ARG, "neither d_images nor loss requested");
+    if (m == 0 && loss) {
+        launch_fill_f32((hipStream_t)stream, loss, 1, 0.f);
+        MGS_CHECK_LAUNCH(ctx);
+        return MGS_OK;
+    }
     StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_LOSS);
-    launch_l1_loss_grad((hipStream_t)stream, images, targets, m, d_images, loss, scratch);
+    launch_l1_loss_grad((hipStream_t)stream, images, targets, m, d_images, grad_scale, loss, scratch);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }
@@ -1150,6 +1174,37 @@ mgs_status mgs_adam_step(mgs_ctx* ctx, mgs_stream stream, float* params, const f
     if (n > 0 && (!params || !grads || !m || !v)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_ADAM);
     launch_adam((hipStream_t)stream, params, grads, m, v, n, lr, beta1, beta2, eps, step);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_adam_step_multi(mgs_ctx* ctx, mgs_stream stream, const mgs_adam_array* arrays, int n_arrays,
+                               float beta1, float beta2, float eps, int64_t step, const int64_t* step_offset) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n_arrays < 0 || (n_arrays > 0 && !arrays)) return fail(ctx, MGS_ERR_INVALID_ARG, "arrays");
+    if (!step_offset && step < 1) return fail(ctx, MGS_ERR_INVALID_ARG, "step < 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+        return fail(ctx, MGS_ERR_INVALID_ARG, "betas must be in [0, 1)");
+    std::vector<AdamArray> xs;
+    xs.reserve((size_t)n_arrays);
+    for (int a = 0; a < n_arrays; ++a) {
+        const mgs_adam_array& x = arrays[a];
+        if (x.n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "array %d: n < 0", a);
+        if (x.n > 0 && (!x.params || !x.grads || !x.m || !x.v))
+            return fail(ctx, MGS_ERR_INVALID_ARG, "array %d: NULL pointer", a);
+        if (x.n > ((int64_t)1 << 40)) return fail(ctx, MGS_ERR_INVALID_ARG, "array %d: n beyond 2^40", a);
+        xs.push_back(AdamArray{x.params, x.grads, x.m, x.v, x.n, x.lr});
+    }
+    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_ADAM);
+    launch_adam_multi((hipStream_t)stream, xs.data(), n_arrays, beta1, beta2, eps, step, step_offset);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_step_advance(mgs_ctx* ctx, mgs_stream stream, int64_t* counter, int64_t delta) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (!counter) return fail(ctx, MGS_ERR_INVALID_ARG, "counter is NULL");
+    launch_step_advance((hipStream_t)stream, counter, delta);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }

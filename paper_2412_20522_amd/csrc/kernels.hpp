@@ -125,8 +125,9 @@ void launch_hybrid_bwd(hipStream_t stream, const CompositeConfig& cfg, const flo
 
 // masks, loss, optimiser
 size_t reduce_scratch_bytes(int64_t n);
+// step_off (optional, device): added to step
 void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, float tau, uint64_t seed, uint64_t step,
-                         float* m_hard, float* y_soft);
+                         const uint64_t* step_off, float* m_hard, float* y_soft);
 void launch_threshold_masks(hipStream_t stream, const float* scores, int64_t n, double threshold, float* m_hard,
                             float* y_soft);
 void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uint64_t seed, uint64_t step0,
@@ -134,10 +135,27 @@ void launch_prune_sample(hipStream_t stream, const float* scores, int64_t n, uin
 // pos: exclusive scan of keep
 void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_t* pos, int64_t n, int n_arrays,
                          const float* const* in, float* const* out, const int* widths);
+void launch_mask_loss(hipStream_t stream, const float* m_hard, int64_t n, float* loss_m, void* scratch);
+// lambda_scale (optional, device): multiplies lambda_m
 void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
-                      float tau, float lambda_m, float* d_scores, float* loss_m, void* scratch);
+                      float tau, float lambda_m, const float* lambda_scale, float* d_scores, float* loss_m,
+                      void* scratch);
+// d_images and loss optional; grad_scale (optional, device) multiplies d_images
 void launch_l1_loss_grad(hipStream_t stream, const float* images, const float* targets, int64_t m, float* d_images,
-                         float* loss, void* scratch);
+                         const float* grad_scale, float* loss, void* scratch);
+struct AdamArray {
+    float* params;
+    const float* grads;
+    float* m;
+    float* v;
+    int64_t n;
+    float lr;
+};
+int adam_multi_max();
+// step_off (optional, device): added to step for the bias corrections
+void launch_adam_multi(hipStream_t stream, const AdamArray* arrays, int n_arrays, float b1, float b2, float eps,
+                       int64_t step, const int64_t* step_off);
+void launch_step_advance(hipStream_t stream, int64_t* counter, int64_t delta);
 void launch_adam(hipStream_t stream, float* params, const float* grads, float* m, float* v, int64_t n, float lr,
                  float b1, float b2, float eps, int64_t step);
 

@@ -44,10 +44,14 @@ __device__ __forceinline__ double gumbel_from_bits(uint32_t x) {
 }
 
 __global__ void __launch_bounds__(RNT) sample_masks_kernel(const float* __restrict__ scores, int64_t n, float tau,
-                                                            uint64_t seed, uint64_t step, float* __restrict__ m_hard,
-                                                            float* __restrict__ y_soft) {
+                                                            uint64_t seed, uint64_t step0,
+                                                            const uint64_t* __restrict__ step_off,
+                                                            float* __restrict__ m_hard, float* __restrict__ y_soft) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // a step counter kept on the device lets a captured training step draw
+    // fresh masks at every replay
+    const uint64_t step = step0 + (step_off ? *step_off : 0ull);
     uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32), c2 = (uint32_t)step, c3 = (uint32_t)(step >> 32);
     philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     const float2 s = reinterpret_cast<const float2*>(scores)[i];
@@ -170,11 +174,16 @@ __global__ void __launch_bounds__(RNT) partial_sum_kernel(const float* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// d (optional) receives sign(a - b) * inv_m, times *scale when scale is given
+// (the upstream gradient of the loss, read on the device).
 __global__ void __launch_bounds__(RNT) partial_abs_diff_kernel(const float* __restrict__ a,
                                                                 const float* __restrict__ b, int64_t n,
-                                                                float inv_m, float* __restrict__ d,
+                                                                float inv_m, const float* __restrict__ scale,
+                                                                float* __restrict__ d,
                                                                 double* __restrict__ partial) {
     __shared__ double sh[RNT / 64];
+    if (scale) inv_m *= *scale;
+    const bool write = d != nullptr;
     double s = 0.0;
     const int64_t stride = (int64_t)gridDim.x * RNT;
     int64_t head = 0;  // elements before this index go four at a time
@@ -190,13 +199,13 @@ __global__ void __launch_bounds__(RNT) partial_abs_diff_kernel(const float* __re
                 s += fabs((double)xs[k] - (double)ys[k]);
                 o[k] = e > 0.f ? inv_m : (e < 0.f ? -inv_m : 0.f);
             }
-            reinterpret_cast<float4*>(d)[q] = make_float4(o[0], o[1], o[2], o[3]);
+            if (write) reinterpret_cast<float4*>(d)[q] = make_float4(o[0], o[1], o[2], o[3]);
         }
     }
     for (int64_t i = head + (int64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += stride) {
         const float x = a[i] - b[i];
         s += fabs((double)a[i] - (double)b[i]);
-        d[i] = x > 0.f ? inv_m : (x < 0.f ? -inv_m : 0.f);
+        if (write) d[i] = x > 0.f ? inv_m : (x < 0.f ? -inv_m : 0.f);
     }
     s = block_sum_double(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -220,10 +229,14 @@ __global__ void __launch_bounds__(RNT) finish_sum_kernel(const double* __restric
 
 __global__ void __launch_bounds__(RNT) mask_grad_kernel(const float* __restrict__ d_masks,
                                                          const float* __restrict__ y_soft, int64_t n, float tau,
-                                                         float lambda_m, const double* __restrict__ sum_m,
+                                                         float lambda_m, const float* __restrict__ lambda_scale,
+                                                         const double* __restrict__ sum_m,
                                                          float* __restrict__ d_scores) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // the weight of L_m in L (Eq. 8), optionally scaled by a device value (the
+    // incoming gradient of L_m under autograd)
+    if (lambda_scale) lambda_m *= *lambda_scale;
     // d L_m / d M_i = 2 mean(M) / n
     const float dlm = (float)(2.0 * (*sum_m) / ((double)n * (double)n));
     const float y = y_soft[i];
@@ -244,6 +257,84 @@ __global__ void __launch_bounds__(RNT) adam_kernel(float* __restrict__ p, const 
     p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
 }
 
+// Adam over up to AM_MAX arrays in one launch.  Array j owns the blocks
+// [block0[j], block0[j + 1]); each block updates AM_CHUNK consecutive
+// elements.  The bias corrections use the step t = step + *step_off, read on
+// the device, so a captured step advances with a device counter.
+constexpr int AM_MAX = 16;
+constexpr int AM_PER_THREAD = 16;
+constexpr int64_t AM_CHUNK = (int64_t)RNT * AM_PER_THREAD;
+struct AdamSet {
+    float* p[AM_MAX];
+    const float* g[AM_MAX];
+    float* m[AM_MAX];
+    float* v[AM_MAX];
+    int64_t n[AM_MAX];
+    float lr[AM_MAX];
+    uint32_t vec[AM_MAX];  // 1: every pointer 16-byte aligned
+    uint32_t block0[AM_MAX + 1];
+    int count;
+};
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
+                                         float eps, float inv_c1, float inv_c2) {
+    m = b1 * m + (1.f - b1) * g;
+    v = b2 * v + (1.f - b2) * g * g;
+    p -= lr * (m * inv_c1) / (sqrtf(v * inv_c2) + eps);
+}
+
+__global__ void __launch_bounds__(RNT) adam_multi_kernel(AdamSet set, float b1, float b2, float eps, int64_t step,
+                                                          const int64_t* __restrict__ step_off) {
+    __shared__ float corr[2];
+    int j = 0;
+    while (j + 1 < set.count && blockIdx.x >= set.block0[j + 1]) ++j;
+    if (threadIdx.x == 0) {
+        const double t = (double)(step + (step_off ? *step_off : 0));
+        corr[0] = (float)(1.0 / (1.0 - pow((double)b1, t)));
+        corr[1] = (float)(1.0 / (1.0 - pow((double)b2, t)));
+    }
+    __syncthreads();
+    const float inv_c1 = corr[0], inv_c2 = corr[1];
+    const int64_t n = set.n[j];
+    const float lr = set.lr[j];
+    float* __restrict__ P = set.p[j];
+    const float* __restrict__ G = set.g[j];
+    float* __restrict__ Mo = set.m[j];
+    float* __restrict__ Vo = set.v[j];
+    const int64_t base = (int64_t)(blockIdx.x - set.block0[j]) * AM_CHUNK;
+#pragma unroll
+    for (int k = 0; k < AM_PER_THREAD / 4; ++k) {
+        const int64_t i = base + 4 * ((int64_t)k * RNT + threadIdx.x);
+        if (i >= n) break;
+        if (set.vec[j] && i + 4 <= n) {
+            float4 p = *reinterpret_cast<const float4*>(P + i);
+            const float4 g = *reinterpret_cast<const float4*>(G + i);
+            float4 m = *reinterpret_cast<const float4*>(Mo + i);
+            float4 v = *reinterpret_cast<const float4*>(Vo + i);
+            adam_one(p.x, g.x, m.x, v.x, lr, b1, b2, eps, inv_c1, inv_c2);
+            adam_one(p.y, g.y, m.y, v.y, lr, b1, b2, eps, inv_c1, inv_c2);
+            adam_one(p.z, g.z, m.z, v.z, lr, b1, b2, eps, inv_c1, inv_c2);
+            adam_one(p.w, g.w, m.w, v.w, lr, b1, b2, eps, inv_c1, inv_c2);
+            *reinterpret_cast<float4*>(P + i) = p;
+            *reinterpret_cast<float4*>(Mo + i) = m;
+            *reinterpret_cast<float4*>(Vo + i) = v;
+        } else {
+            const int64_t e = i + 4 < n ? i + 4 : n;
+            for (int64_t q = i; q < e; ++q) {
+                float p = P[q], m = Mo[q], v = Vo[q];
+                adam_one(p, G[q], m, v, lr, b1, b2, eps, inv_c1, inv_c2);
+                P[q] = p;
+                Mo[q] = m;
+                Vo[q] = v;
+            }
+        }
+    }
+}
+
+__global__ void step_advance_kernel(int64_t* __restrict__ counter, int64_t delta) {
+    if (threadIdx.x == 0) counter[0] += delta;
+}
+
 constexpr int REDUCE_BLOCKS = 1024;
 
 }  // namespace
@@ -251,10 +342,10 @@ constexpr int REDUCE_BLOCKS = 1024;
 size_t reduce_scratch_bytes(int64_t) { return (REDUCE_BLOCKS + 8) * sizeof(double); }
 
 void launch_sample_masks(hipStream_t stream, const float* scores, int64_t n, float tau, uint64_t seed, uint64_t step,
-                         float* m_hard, float* y_soft) {
+                         const uint64_t* step_off, float* m_hard, float* y_soft) {
     if (n == 0) return;
     hipLaunchKernelGGL(sample_masks_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, scores, n,
-                       tau, seed, step, m_hard, y_soft);
+                       tau, seed, step, step_off, m_hard, y_soft);
 }
 
 void launch_threshold_masks(hipStream_t stream, const float* scores, int64_t n, double threshold, float* m_hard,
@@ -293,29 +384,79 @@ void launch_compact_rows(hipStream_t stream, const uint32_t* keep, const uint32_
     }
 }
 
-void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
-                      float tau, float lambda_m, float* d_scores, float* loss_m, void* scratch) {
-    if (n == 0) return;
+// (mean M)^2 into loss_m (optional); the double sum of M stays in the
+// scratch for the gradient.
+static const double* mask_sum(hipStream_t stream, const float* m_hard, int64_t n, float* loss_m, void* scratch) {
     double* partial = reinterpret_cast<double*>(scratch);
     double* total = partial + REDUCE_BLOCKS;
     const int nb = (int)std::min<int64_t>(REDUCE_BLOCKS, (n + RNT - 1) / RNT);
     hipLaunchKernelGGL(partial_sum_kernel, dim3(nb), dim3(RNT), 0, stream, m_hard, n, partial);
     hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RNT), 0, stream, (const double*)partial, nb, 1.0 / (double)n,
                        total, loss_m, 1);
+    return total;
+}
+
+void launch_mask_loss(hipStream_t stream, const float* m_hard, int64_t n, float* loss_m, void* scratch) {
+    if (n == 0) {
+        launch_fill_f32(stream, loss_m, 1, 0.f);
+        return;
+    }
+    (void)mask_sum(stream, m_hard, n, loss_m, scratch);
+}
+
+void launch_mask_grad(hipStream_t stream, const float* d_masks, const float* m_hard, const float* y_soft, int64_t n,
+                      float tau, float lambda_m, const float* lambda_scale, float* d_scores, float* loss_m,
+                      void* scratch) {
+    if (n == 0) return;
+    const double* total = mask_sum(stream, m_hard, n, loss_m, scratch);
     hipLaunchKernelGGL(mask_grad_kernel, dim3((unsigned)((n + RNT - 1) / RNT)), dim3(RNT), 0, stream, d_masks, y_soft,
-                       n, tau, lambda_m, (const double*)total, d_scores);
+                       n, tau, lambda_m, lambda_scale, total, d_scores);
 }
 
 void launch_l1_loss_grad(hipStream_t stream, const float* images, const float* targets, int64_t m, float* d_images,
-                         float* loss, void* scratch) {
+                         const float* grad_scale, float* loss, void* scratch) {
     if (m == 0) return;
     double* partial = reinterpret_cast<double*>(scratch);
     double* total = partial + REDUCE_BLOCKS;
     const int nb = (int)std::min<int64_t>(REDUCE_BLOCKS, (m + RNT - 1) / RNT);
     hipLaunchKernelGGL(partial_abs_diff_kernel, dim3(nb), dim3(RNT), 0, stream, images, targets, m,
-                       (float)(1.0 / (double)m), d_images, partial);
-    hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RNT), 0, stream, (const double*)partial, nb, 1.0 / (double)m,
-                       total, loss, 0);
+                       (float)(1.0 / (double)m), grad_scale, d_images, partial);
+    if (loss)
+        hipLaunchKernelGGL(finish_sum_kernel, dim3(1), dim3(RNT), 0, stream, (const double*)partial, nb,
+                           1.0 / (double)m, total, loss, 0);
+}
+
+int adam_multi_max() { return AM_MAX; }
+
+void launch_adam_multi(hipStream_t stream, const AdamArray* arrays, int n_arrays, float b1, float b2, float eps,
+                       int64_t step, const int64_t* step_off) {
+    for (int a0 = 0; a0 < n_arrays; a0 += AM_MAX) {
+        AdamSet set{};
+        set.count = 0;
+        uint32_t blocks = 0;
+        for (int j = 0; j < AM_MAX && a0 + j < n_arrays; ++j) {
+            const AdamArray& x = arrays[a0 + j];
+            if (x.n <= 0) continue;
+            const int k = set.count++;
+            set.p[k] = x.params;
+            set.g[k] = x.grads;
+            set.m[k] = x.m;
+            set.v[k] = x.v;
+            set.n[k] = x.n;
+            set.lr[k] = x.lr;
+            const uintptr_t al = (uintptr_t)x.params | (uintptr_t)x.grads | (uintptr_t)x.m | (uintptr_t)x.v;
+            set.vec[k] = (al & 15) == 0 ? 1u : 0u;
+            set.block0[k] = blocks;
+            blocks += (uint32_t)((x.n + AM_CHUNK - 1) / AM_CHUNK);
+        }
+        if (set.count == 0) continue;
+        set.block0[set.count] = blocks;
+        hipLaunchKernelGGL(adam_multi_kernel, dim3(blocks), dim3(RNT), 0, stream, set, b1, b2, eps, step, step_off);
+    }
+}
+
+void launch_step_advance(hipStream_t stream, int64_t* counter, int64_t delta) {
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, stream, counter, delta);
 }
 
 void launch_adam(hipStream_t stream, float* params, const float* grads, float* m, float* v, int64_t n, float lr,

@@ -315,10 +315,11 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
     float* __restrict__ d_sh, float* __restrict__ d_masks, float* __restrict__ d_rec_out,
-    const uint32_t* __restrict__ tiles) {
+    const uint32_t* __restrict__ tiles, int accumulate) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
+    // parameter gradients are written, or added to what the outputs hold
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
     const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
     // Two passes over the views, so that the double-precision covariance
@@ -470,14 +471,19 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         const double gz = 2.0 * (-2.0 * qz * dR[0] - qw * dR[1] + qx * dR[2] + qw * dR[3] - 2.0 * qz * dR[4] +
                                  qy * dR[5] + qx * dR[6] + qy * dR[7]);
         const double dotq = qw * gw + qx * gx + qy * gy + qz * gz;
-        if (d_quats)
-            reinterpret_cast<float4*>(d_quats)[g] =
-                make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
-                            (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
+        if (d_quats) {
+            float4 dq = make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
+                                    (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
+            if (accumulate) {
+                const float4 o = reinterpret_cast<const float4*>(d_quats)[g];
+                dq.x += o.x; dq.y += o.y; dq.z += o.z; dq.w += o.w;
+            }
+            reinterpret_cast<float4*>(d_quats)[g] = dq;
+        }
         if (d_log_scales) {
-            d_log_scales[3 * g] = (float)dls[0];
-            d_log_scales[3 * g + 1] = (float)dls[1];
-            d_log_scales[3 * g + 2] = (float)dls[2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                d_log_scales[3 * g + k] = accumulate ? d_log_scales[3 * g + k] + (float)dls[k] : (float)dls[k];
         }
     }
     {
@@ -531,20 +537,25 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         if (d_sh) {
             float* o = d_sh + g * 3 * K;
 #pragma unroll
-            for (int i = 0; i < 3 * K; ++i) o[i] = gsh[i];
+            for (int i = 0; i < 3 * K; ++i) o[i] = accumulate ? o[i] + gsh[i] : gsh[i];
         }
     }
     if (d_means) {
-        d_means[3 * g] = (float)gp[0];
-        d_means[3 * g + 1] = (float)gp[1];
-        d_means[3 * g + 2] = (float)gp[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d_means[3 * g + k] = accumulate ? d_means[3 * g + k] + (float)gp[k] : (float)gp[k];
     }
     // mask x opacity: gop is dL/d(M sigmoid(logit)) summed over the views, so
     // dL/dM = gop sigmoid(logit) and dL/dlogit = gop M sigmoid'(logit); the
     // compositing's own mask gradient (of records with mask 1) is not used
     const double mval = st.mask_opacity ? (double)masks[g] : 1.0;
-    if (d_opacity_logits) d_opacity_logits[g] = (float)(gop * mval * opac * (1.0 - opac));
-    if (dm_acc && d_masks) d_masks[g] = (float)(st.mask_opacity ? gop * opac : dm_acc[g]);
+    if (d_opacity_logits) {
+        const float v = (float)(gop * mval * opac * (1.0 - opac));
+        d_opacity_logits[g] = accumulate ? d_opacity_logits[g] + v : v;
+    }
+    if (dm_acc && d_masks) {
+        const float v = (float)(st.mask_opacity ? gop * opac : dm_acc[g]);
+        d_masks[g] = accumulate ? d_masks[g] + v : v;
+    }
 }
 
 }  // namespace
@@ -580,7 +591,7 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), lds, stream, g.means, g.log_scales, g.quats, \
                        g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
                        out.d_log_scales,                                                                            \
-                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles)
+                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles, out.accumulate)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;

@@ -53,7 +53,7 @@ class mgs_gaussians(C.Structure):
 class mgs_gradients(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_log_scales", C.c_void_p), ("d_quats", C.c_void_p),
                 ("d_opacity_logits", C.c_void_p), ("d_sh", C.c_void_p), ("d_masks", C.c_void_p),
-                ("d_records", C.c_void_p)]
+                ("d_records", C.c_void_p), ("accumulate", C.c_int32)]
 
 
 class mgs_eval_counts(C.Structure):
@@ -76,6 +76,11 @@ class mgs_frame_stats(C.Structure):
                 ("n_pixels", C.c_int64), ("n_instances", C.c_int64), ("total_tiles", C.c_int64),
                 ("instance_capacity", C.c_int64), ("n_wide", C.c_int64), ("sort_passes", C.c_int32),
                 ("tile_bits", C.c_int32)]
+
+
+class mgs_adam_array(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("grads", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_float)]
 
 
 # name -> (restype, argtypes)
@@ -118,15 +123,18 @@ _SIGS = {
                                          C.POINTER(mgs_settings), _VP, _VP, _VP, _I64, _VP, _VP]),
     "mgs_project_backward": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                                        C.POINTER(mgs_settings), _VP, C.POINTER(mgs_gradients)]),
-    "mgs_sample_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _U64, _U64, _VP, _VP]),
+    "mgs_sample_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _U64, _U64, _VP, _VP, _VP]),
     "mgs_reduce_scratch_bytes": (_SZ, [_I64]),
     "mgs_prune_sample": (C.c_int, [_VP, _VP, _VP, _I64, _U64, _U64, C.c_int, _VP]),
     "mgs_threshold_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _VP, _VP]),
     "mgs_compact_scratch_bytes": (_SZ, [_I64]),
     "mgs_compact_rows": (C.c_int, [_VP, _VP, _VP, _I64, C.c_int, _VP, _VP, _VP, _VP, _VP]),
-    "mgs_mask_grad": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _VP, _VP, _VP]),
-    "mgs_l1_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP, _VP]),
+    "mgs_mask_loss": (C.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
+    "mgs_mask_grad": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _VP, _VP, _VP, _VP]),
+    "mgs_l1_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "mgs_adam_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _I64, _F, _F, _F, _F, _I64]),
+    "mgs_adam_step_multi": (C.c_int, [_VP, _VP, C.POINTER(mgs_adam_array), C.c_int, _F, _F, _F, _I64, _VP]),
+    "mgs_step_advance": (C.c_int, [_VP, _VP, _VP, _I64]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -215,8 +223,9 @@ def gaussians_struct(means, log_scales, quats, opacity_logits, sh, masks=None) -
 
 
 def gradients_struct(d_means=None, d_log_scales=None, d_quats=None, d_opacity_logits=None, d_sh=None,
-                     d_masks=None, d_records=None) -> mgs_gradients:
+                     d_masks=None, d_records=None, accumulate: bool = False) -> mgs_gradients:
     gr = mgs_gradients()
+    gr.accumulate = 1 if accumulate else 0
     gr.d_means = _ptr(d_means, name="d_means")
     gr.d_log_scales = _ptr(d_log_scales, name="d_log_scales")
     gr.d_quats = _ptr(d_quats, name="d_quats")
@@ -417,9 +426,12 @@ def mgs_project_backward(ctx, g: mgs_gaussians, cams, st, d_rec, grads: mgs_grad
                                           _ptr(d_rec, name="d_rec"), C.byref(grads)))
 
 
-def mgs_sample_masks(ctx, scores, tau: float, seed: int, step: int, m_hard, y_soft, stream=None) -> None:
+def mgs_sample_masks(ctx, scores, tau: float, seed: int, step: int, m_hard, y_soft, step_offset=None,
+                     stream=None) -> None:
+    """step_offset (optional): int64 device scalar added to step on the device."""
     _check(ctx, _lib.mgs_sample_masks(ctx, _stream(stream), _ptr(scores, name="scores"), scores.shape[0], tau,
-                                      seed, step, _ptr(m_hard, name="m_hard"), _ptr(y_soft, name="y_soft")))
+                                      seed, step, _ptr(step_offset, torch.int64, "step_offset"),
+                                      _ptr(m_hard, name="m_hard"), _ptr(y_soft, name="y_soft")))
 
 
 def mgs_threshold_masks(ctx, scores, threshold: float, m_hard, y_soft, stream=None) -> None:
@@ -458,23 +470,61 @@ def mgs_compact_rows(ctx, keep, ins, outs, n_kept=None, scratch=None, stream=Non
                                       _ptr(n_kept, torch.int64, "n_kept"), _ptr(scratch, torch.uint8, "scratch")))
 
 
+def mgs_mask_loss(ctx, m_hard, loss_m, scratch=None, stream=None) -> None:
+    n = m_hard.numel()
+    if scratch is None:
+        scratch = torch.empty(int(_lib.mgs_reduce_scratch_bytes(n)), dtype=torch.uint8, device=m_hard.device)
+    _check(ctx, _lib.mgs_mask_loss(ctx, _stream(stream), _ptr(m_hard, name="m_hard"), n, _ptr(loss_m, name="loss_m"),
+                                   _ptr(scratch, torch.uint8, "scratch")))
+
+
 def mgs_mask_grad(ctx, d_masks, m_hard, y_soft, tau: float, lambda_m: float, d_scores, loss_m=None,
-                  scratch=None, stream=None) -> None:
+                  scratch=None, lambda_scale=None, stream=None) -> None:
+    """lambda_scale (optional): float32 device scalar multiplying lambda_m."""
     n = m_hard.numel()
     if scratch is None:
         scratch = torch.empty(int(_lib.mgs_reduce_scratch_bytes(n)), dtype=torch.uint8, device=m_hard.device)
     _check(ctx, _lib.mgs_mask_grad(ctx, _stream(stream), _ptr(d_masks, name="d_masks"), _ptr(m_hard, name="m_hard"),
-                                   _ptr(y_soft, name="y_soft"), n, tau, lambda_m, _ptr(d_scores, name="d_scores"),
+                                   _ptr(y_soft, name="y_soft"), n, tau, lambda_m,
+                                   _ptr(lambda_scale, name="lambda_scale"), _ptr(d_scores, name="d_scores"),
                                    _ptr(loss_m, name="loss_m"), _ptr(scratch, torch.uint8, "scratch")))
 
 
-def mgs_l1_loss_grad(ctx, images, targets, d_images, loss=None, scratch=None, stream=None) -> None:
+def mgs_l1_loss_grad(ctx, images, targets, d_images, loss=None, scratch=None, grad_scale=None, stream=None) -> None:
+    """d_images may be None (loss only); grad_scale (optional): float32 device
+    scalar multiplying the gradient."""
     m = images.numel()
+    if targets.numel() != m or (d_images is not None and d_images.numel() != m):
+        raise ValueError("images, targets and d_images differ in size")
     if scratch is None:
         scratch = torch.empty(int(_lib.mgs_reduce_scratch_bytes(m)), dtype=torch.uint8, device=images.device)
     _check(ctx, _lib.mgs_l1_loss_grad(ctx, _stream(stream), _ptr(images, name="images"),
                                       _ptr(targets, name="targets"), m, _ptr(d_images, name="d_images"),
-                                      _ptr(loss, name="loss"), _ptr(scratch, torch.uint8, "scratch")))
+                                      _ptr(grad_scale, name="grad_scale"), _ptr(loss, name="loss"),
+                                      _ptr(scratch, torch.uint8, "scratch")))
+
+
+def mgs_adam_step_multi(ctx, groups, beta1: float, beta2: float, eps: float, step: int, step_offset=None,
+                        stream=None) -> None:
+    """groups: sequence of (params, grads, m, v, lr) with float32 device
+    tensors of equal size per group; step_offset (optional): int64 device
+    scalar added to step for the bias corrections."""
+    arr = (mgs_adam_array * max(len(groups), 1))()
+    for i, (p, g, m1, m2, lr) in enumerate(groups):
+        if not (p.numel() == g.numel() == m1.numel() == m2.numel()):
+            raise ValueError(f"group {i}: params, grads and moments differ in size")
+        arr[i].params = _ptr(p, name="params")
+        arr[i].grads = _ptr(g, name="grads")
+        arr[i].m = _ptr(m1, name="m")
+        arr[i].v = _ptr(m2, name="v")
+        arr[i].n = p.numel()
+        arr[i].lr = float(lr)
+    _check(ctx, _lib.mgs_adam_step_multi(ctx, _stream(stream), arr, len(groups), beta1, beta2, eps, step,
+                                         _ptr(step_offset, torch.int64, "step_offset")))
+
+
+def mgs_step_advance(ctx, counter, delta: int = 1, stream=None) -> None:
+    _check(ctx, _lib.mgs_step_advance(ctx, _stream(stream), _ptr(counter, torch.int64, "counter"), delta))
 
 
 def mgs_adam_step(ctx, params, grads, m, v, lr: float, beta1: float, beta2: float, eps: float, step: int,

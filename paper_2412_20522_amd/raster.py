@@ -11,6 +11,7 @@ blended entry is kept.
 """
 from __future__ import annotations
 
+import weakref
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -108,15 +109,18 @@ class Rasterizer:
         return images, imp_sum, imp_max
 
     def backward(self, frame, params: dict, dl_dimages: torch.Tensor, out: Optional[Grads] = None,
-                 records: Optional[torch.Tensor] = None) -> Grads:
+                 records: Optional[torch.Tensor] = None, accumulate: bool = False) -> Grads:
         """records (optional, [n_views N, 9] float32) receives the per-record 2D
         gradients before the chain rule (dL/d(u, v), the stored conic,
-        opacity and colour)."""
+        opacity and colour); accumulate adds the parameter and mask
+        gradients to what `out` holds."""
         if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs the output gradients")
             out = Grads(*(torch.empty_like(params[k]) for k in PARAM_KEYS),
                         torch.empty(params["means"].shape[0], dtype=torch.float32, device=params["means"].device))
         gr = M.gradients_struct(out.means, out.log_scales, out.quats, out.opacity_logits, out.sh, out.masks,
-                                records)
+                                records, accumulate)
         M.mgs_backward(self.ctx, frame, dl_dimages.contiguous(), gr)
         return out
 
@@ -156,37 +160,60 @@ class Rasterizer:
     def stats(self, frame) -> dict:
         return M.mgs_frame_get_stats(frame)
 
-    def sample_masks(self, scores: torch.Tensor, tau: float, seed: int, step: int):
+    def sample_masks(self, scores: torch.Tensor, tau: float, seed: int, step: int,
+                     step_offset: Optional[torch.Tensor] = None):
+        """Hard and soft straight-through Gumbel masks; step_offset (int64
+        device scalar, optional) is added to step on the device."""
         n = scores.shape[0]
         m = torch.empty(n, dtype=torch.float32, device=scores.device)
         y = torch.empty_like(m)
-        M.mgs_sample_masks(self.ctx, scores.contiguous(), tau, seed, step, m, y)
+        M.mgs_sample_masks(self.ctx, scores.contiguous(), tau, seed, step, m, y, step_offset=step_offset)
         return m, y
 
 
 class MaskedRasterize(torch.autograd.Function):
     """images, mask_loss = MaskedRasterize.apply(means, log_scales, quats,
-    opacity_logits, sh, mask_scores, rasterizer, cams, tau, seed, step)
+    opacity_logits, sh, mask_scores, rasterizer, cams, tau, seed, step,
+    frame=None, step_offset=None)
 
-    images is the packed [3 * P] rendering of all views; mask_loss is
-    (mean M)^2 (Eq. 7) so a caller forms L = L_render + lambda_m * mask_loss
-    (Eq. 8).  The hard masks are available as ``rasterizer.last_masks``.
+    images is the packed [3 * P] rendering of all views; mask_loss is the
+    0-dim (mean M)^2 of Eq. (7), computed by the library, so a caller forms
+    L = L_render + lambda_m * mask_loss (Eq. 8).  The hard masks are
+    available as ``rasterizer.last_masks``.
+
+    frame: a frame the caller owns (for a captured step, one with a fixed
+    workspace, see Rasterizer.reserve); without one a frame is taken from the
+    rasterizer's pool and given back after the backward, or when the graph
+    is dropped without a backward (evaluation, no_grad).  step_offset: int64
+    device scalar added to step when the masks are drawn.  Nothing in
+    forward or backward reads a device value on the host, so a whole step
+    (with the loss, backward and optimiser) can be captured into a hipGraph.
     """
 
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, mask_scores, rasterizer: Rasterizer,
-                cams, tau: float, seed: int, step: int):
+                cams, tau: float, seed: int, step: int, frame=None, step_offset: Optional[torch.Tensor] = None):
         params = {"means": means.detach().contiguous(), "log_scales": log_scales.detach().contiguous(),
                   "quats": quats.detach().contiguous(), "opacity_logits": opacity_logits.detach().contiguous(),
                   "sh": sh.detach().contiguous()}
-        m_hard, y_soft = rasterizer.sample_masks(mask_scores.detach(), tau, seed, step)
-        frame = rasterizer.acquire_frame()
-        images = rasterizer.forward(frame, params, m_hard, cams)
-        mask_loss = (m_hard.sum(dtype=torch.float64) / max(m_hard.numel(), 1)).square().to(torch.float32)
+        m_hard, y_soft = rasterizer.sample_masks(mask_scores.detach(), tau, seed, step, step_offset)
+        own = frame is None
+        fr = rasterizer.acquire_frame() if own else frame
+        try:
+            images = rasterizer.forward(fr, params, m_hard, cams)
+        except Exception:
+            if own:
+                rasterizer.release_frame(fr)
+            raise
+        mask_loss = torch.empty((), dtype=torch.float32, device=m_hard.device)
+        M.mgs_mask_loss(rasterizer.ctx, m_hard, mask_loss)
         ctx.rasterizer = rasterizer
-        ctx.frame = frame
+        ctx.frame = fr
         ctx.params = params
         ctx.tau = tau
+        # a pooled frame goes back to the pool once: after the backward, or
+        # when this node is freed without one
+        ctx.release = weakref.finalize(ctx, rasterizer.release_frame, fr) if own else None
         ctx.save_for_backward(m_hard, y_soft)
         rasterizer.last_masks = m_hard
         return images, mask_loss
@@ -199,15 +226,46 @@ class MaskedRasterize(torch.autograd.Function):
             n_px = M.mgs_frame_get_stats(ctx.frame)["n_pixels"]
             dl_dimages = torch.zeros(3 * n_px, dtype=torch.float32, device=m_hard.device)
         g = r.backward(ctx.frame, ctx.params, dl_dimages.contiguous())
-        r.release_frame(ctx.frame)
+        if ctx.release is not None:
+            ctx.release()
         ctx.frame = None
-        lam = float(dl_dmask_loss) if dl_dmask_loss is not None else 0.0
         d_scores = torch.empty(m_hard.shape[0], 2, dtype=torch.float32, device=m_hard.device)
-        M.mgs_mask_grad(r.ctx, g.masks, m_hard, y_soft, ctx.tau, lam, d_scores)
-        return g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, d_scores, None, None, None, None, None
+        if dl_dmask_loss is None:
+            M.mgs_mask_grad(r.ctx, g.masks, m_hard, y_soft, ctx.tau, 0.0, d_scores)
+        else:
+            # the weight of L_m stays on the device: lambda_m = 1 scaled by
+            # the incoming gradient of mask_loss
+            scale = dl_dmask_loss.detach().to(torch.float32).reshape(1).contiguous()
+            M.mgs_mask_grad(r.ctx, g.masks, m_hard, y_soft, ctx.tau, 1.0, d_scores, lambda_scale=scale)
+        return (g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, d_scores,
+                None, None, None, None, None, None, None)
+
+
+class L1Loss(torch.autograd.Function):
+    """loss = L1Loss.apply(images, targets, rasterizer): the rendering loss
+    mean |images - targets| (L_render of Eq. 8) and its gradient, both from
+    the library's loss kernels (sign(0) = 0).  0-dim float32 result."""
+
+    @staticmethod
+    def forward(ctx, images, targets, rasterizer: Rasterizer):
+        img = images.detach().contiguous()
+        tgt = targets.detach().contiguous()
+        loss = torch.empty((), dtype=torch.float32, device=img.device)
+        M.mgs_l1_loss_grad(rasterizer.ctx, img, tgt, None, loss.reshape(1))
+        ctx.rasterizer = rasterizer
+        ctx.save_for_backward(img, tgt)
+        return loss
+
+    @staticmethod
+    def backward(ctx, dl_dloss):
+        img, tgt = ctx.saved_tensors
+        d = torch.empty_like(img)
+        M.mgs_l1_loss_grad(ctx.rasterizer.ctx, img, tgt, d, None,
+                           grad_scale=dl_dloss.detach().to(torch.float32).reshape(1).contiguous())
+        return d, None, None
 
 
 def masked_rasterize(params: dict, mask_scores: torch.Tensor, rasterizer: Rasterizer, cams, tau: float = 0.5,
-                     seed: int = 0, step: int = 0):
+                     seed: int = 0, step: int = 0, frame=None, step_offset: Optional[torch.Tensor] = None):
     return MaskedRasterize.apply(params["means"], params["log_scales"], params["quats"], params["opacity_logits"],
-                                 params["sh"], mask_scores, rasterizer, cams, tau, seed, step)
+                                 params["sh"], mask_scores, rasterizer, cams, tau, seed, step, frame, step_offset)

@@ -43,9 +43,17 @@ SEED_BASE = 2412_20522_0
 _Y00 = 0.5 / math.sqrt(math.pi)
 
 # Largest per-axis log-scale drawn from the heavy-tailed Student-t recipe.
-# Scales above ~50 world units already cover the whole screen from every
-# camera used here, so capping changes neither the tile lists nor which
-# pixels a splat covers, while keeping s^2 finite in FP32.
+# The 2D covariance of a splat, its determinant a c - b^2, the conic and the
+# chain rule back to the scales are evaluated in double precision by the
+# oracle and by the GPU alike, and keep about 16 - log10(lambda_max /
+# lambda_min) significant digits (the smaller eigenvalue is at least the
+# 0.3 px^2 dilation).  A 50-unit axis seen from the nearest depths of these
+# cameras reaches an eigenvalue ratio of about 1e11, where the FP64 result is
+# still good to the parity tolerances; much longer axes (the uncapped tail
+# reaches e^130) leave no correct digit in the determinant on either side, and
+# the GPU reports such a splat as non-finite geometry.  Capping changes about
+# 0.1 % of the draws (per axis P(t3 > 9.9)); which pixels a capped splat
+# covers changes, but the capped scene is rendered and differentiated exactly.
 LOG_SCALE_CAP = math.log(50.0)
 
 

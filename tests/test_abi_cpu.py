@@ -44,7 +44,7 @@ def test_default_settings_and_version():
     assert (s.tile_w, s.tile_h, s.batch_depth) == (16, 16, 256)
     assert abs(s.alpha_min - 1 / 255) < 1e-9 and abs(s.alpha_max - 0.99) < 1e-7
     assert abs(s.t_min - 1e-4) < 1e-10 and s.q_max == 9.0
-    assert M.mgs_version() >= 100
+    assert M.mgs_version() >= 200
 
 
 def test_struct_layouts_match_header():
@@ -53,7 +53,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(M.mgs_settings) == 4 * 4 + 8 * 4 + 3 * 4 + 8 * 4
     assert C.sizeof(M.mgs_eval_counts) == 6 * 8
     assert C.sizeof(M.mgs_gaussians) == 6 * 8 + 8
-    assert C.sizeof(M.mgs_gradients) == 7 * 8
+    assert C.sizeof(M.mgs_gradients) == 7 * 8 + 8
+    assert C.sizeof(M.mgs_adam_array) == 5 * 8 + 8
 
 
 def test_host_validation_without_device():
@@ -64,7 +65,10 @@ def test_host_validation_without_device():
     assert L.mgs_frame_create(None, None) == 1
     assert L.mgs_scan(None, None, None, 0, None, None, None) == 1
     assert L.mgs_sort(None, None, None, None, 0, 40, None, None, None) == 1
-    assert L.mgs_sample_masks(None, None, None, 0, 0.5, 0, 0, None, None) == 1
+    assert L.mgs_sample_masks(None, None, None, 0, 0.5, 0, 0, None, None, None) == 1
+    assert L.mgs_mask_loss(None, None, None, 0, None, None) == 1
+    assert L.mgs_adam_step_multi(None, None, None, 0, 0.9, 0.999, 1e-15, 1, None) == 1
+    assert L.mgs_step_advance(None, None, None, 1) == 1
     assert L.mgs_default_settings(None) == 1
     assert L.mgs_scan_scratch_bytes(10_000) > 0
     assert L.mgs_sort_scratch_bytes(1_000_000) > L.mgs_sort_scratch_bytes(1000)
