@@ -395,6 +395,11 @@ MGS_API mgs_status mgs_project(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussi
                                int n_views, const mgs_settings* st, float* rec, float* depth, float* radius,
                                uint32_t* tiles);
 
+/* Scratch held by the library for mgs_scan_noalloc, per GPU (bytes). */
+#define MGS_SCAN_NOALLOC_BYTES 65536
+/* Largest n mgs_scan_noalloc accepts: ((65536 - 256) / 8 - 1) blocks of 4096. */
+#define MGS_SCAN_NOALLOC_MAX_N 33419264
+
 /* Binning stages.  Sec. 3.1 renders each pixel from the Gaussians that
  * intersect its 16x16 tile, in depth order; these four calls build those
  * per-tile lists: offsets of every record's entries (scan of the tile
@@ -407,6 +412,20 @@ MGS_API mgs_status mgs_project(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussi
 MGS_API size_t mgs_scan_scratch_bytes(int64_t n);
 MGS_API mgs_status mgs_scan(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
                             uint64_t* total_dev, void* scratch);
+
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mgs_scan
+ * without the scratch argument.  Same result as mgs_scan.  Its scratch is a
+ * library-owned device array of MGS_SCAN_NOALLOC_BYTES that every GPU holds
+ * until the process ends (the address is taken per device by mgs_create);
+ * nothing is allocated by this call.  n <= MGS_SCAN_NOALLOC_MAX_N, else
+ * MGS_ERR_INVALID_ARG.  All calls on one GPU share the array: calls on one
+ * stream are ordered, calls that overlap in time on one GPU (other streams,
+ * other threads or contexts) race and give wrong results.  in, out
+ * (device, caller-owned, n u32 each); total_dev (device, one u64,
+ * optional).  Asynchronous. */
+MGS_API mgs_status mgs_scan_noalloc(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
+                                    uint64_t* total_dev);
 
 /* Tile lists of Sec. 3.1: writes, for every record r with tiles > 0 and
  * every tile t of its footprint, key = (global tile id << 32) | float bits

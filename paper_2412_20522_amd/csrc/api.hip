@@ -19,6 +19,7 @@ using namespace mgs;
 struct mgs_ctx {
     int device = 0;
     int num_cus = 256;
+    void* scan_noalloc = nullptr;  // this device's address of the scratch of mgs_scan_noalloc
     std::string err;
     // per-stage timing
     bool prof_on = false;
@@ -356,9 +357,14 @@ mgs_status mgs_create(int device, mgs_ctx** out) {
         return fail(nullptr, MGS_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", device,
                     prop.gcnArchName);
     if (hipSetDevice(device) != hipSuccess) return fail(nullptr, MGS_ERR_HIP, "hipSetDevice(%d)", device);
+    void* noalloc = nullptr;
+    const hipError_t ne = scan_noalloc_init(device, &noalloc);
+    if (ne != hipSuccess)
+        return fail(nullptr, MGS_ERR_HIP, "address of the scan scratch: %s", hipGetErrorString(ne));
     mgs_ctx* c = new (std::nothrow) mgs_ctx();
     if (!c) return fail(nullptr, MGS_ERR_OOM, "context allocation");
     c->device = device;
+    c->scan_noalloc = noalloc;
     c->num_cus = prop.multiProcessorCount;
     *out = c;
     return MGS_OK;
@@ -929,6 +935,20 @@ mgs_status mgs_scan(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t
     if (n > 0 && (!in || !out || !scratch)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
     if (!scratch) return fail(ctx, MGS_ERR_INVALID_ARG, "scratch is NULL");
     launch_scan_u32((hipStream_t)stream, in, n, out, total_dev, scratch);
+    MGS_CHECK_LAUNCH(ctx);
+    return MGS_OK;
+}
+
+mgs_status mgs_scan_noalloc(mgs_ctx* ctx, mgs_stream stream, const uint32_t* in, int64_t n, uint32_t* out,
+                            uint64_t* total_dev) {
+    if (!ctx) return MGS_ERR_INVALID_ARG;
+    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
+    if (n > scan_noalloc_max_n())
+        return fail(ctx, MGS_ERR_INVALID_ARG, "n = %lld exceeds the %lld elements the scan's fixed scratch serves",
+                    (long long)n, (long long)scan_noalloc_max_n());
+    if (n > 0 && (!in || !out)) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
+    if (!ctx->scan_noalloc) return fail(ctx, MGS_ERR_STATE, "no scratch address for device %d", ctx->device);
+    launch_scan_u32((hipStream_t)stream, in, n, out, total_dev, ctx->scan_noalloc);
     MGS_CHECK_LAUNCH(ctx);
     return MGS_OK;
 }

@@ -27,6 +27,13 @@ size_t scan_scratch_bytes(int64_t n);
 // are treated as zero.
 void launch_scan_u32(hipStream_t stream, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total_dev,
                      void* scratch);
+// The allocation-free scan: a library-owned device array of
+// SCAN_NOALLOC_BYTES per GPU holds its scratch.  scan_noalloc_init, called
+// with `device` current, returns that GPU's address of the array (looked up
+// once per device); scan_noalloc_max_n is the largest n it serves.
+constexpr size_t SCAN_NOALLOC_BYTES = MGS_SCAN_NOALLOC_BYTES;
+hipError_t scan_noalloc_init(int device, void** out);
+int64_t scan_noalloc_max_n();
 void launch_duplicate(hipStream_t stream, const float* rec, const float* radius, const float* depth,
                       const uint32_t* tiles, const uint32_t* offsets, int64_t n_records, int64_t n_per_view,
                       const ViewSet& views, const DevSettings& st, uint64_t* keys, uint32_t* vals, int64_t capacity,

@@ -16,11 +16,23 @@
 // scan of the digit-major histogram, then a stable scatter); it has no
 // inter-block spin waits, so it needs no forward-progress guarantee between
 // workgroups.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace mgs {
 namespace {
+
+// Scratch of the allocation-free scan (mgs_scan_noalloc): file-scope device
+// memory, one copy per GPU, held until the process ends.  Host code never
+// uses this name as an address: the per-device address comes from
+// hipGetSymbolAddress (scan_noalloc_init) and is passed to the kernels.
+static __device__ __align__(256) unsigned char scratch[SCAN_NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[MAX_DEVICES] = {};
 
 constexpr int NT = 256;
 constexpr int IPT = 16;
@@ -557,6 +569,27 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
 }  // namespace
 
 size_t scan_scratch_bytes(int64_t n) { return (size_t)(nblocks(n) + 1) * sizeof(uint64_t) + 256; }
+
+int64_t scan_noalloc_max_n() {
+    // the scan needs (blocks + 1) u64 partial sums plus 256 bytes
+    const int64_t blocks = (int64_t)((SCAN_NOALLOC_BYTES - 256) / sizeof(uint64_t)) - 1;
+    return blocks * TILE;
+}
+
+hipError_t scan_noalloc_init(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        // with `device` current: its own copy of the array
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = p;
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
 
 void launch_scan_u32(hipStream_t stream, const uint32_t* in, int64_t n, uint32_t* out, uint64_t* total_dev,
                      void* scratch) {

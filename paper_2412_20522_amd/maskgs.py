@@ -112,6 +112,7 @@ _SIGS = {
                               C.POINTER(mgs_settings), _VP, _VP, _VP, _VP]),
     "mgs_scan_scratch_bytes": (_SZ, [_I64]),
     "mgs_scan": (C.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, _VP]),
+    "mgs_scan_noalloc": (C.c_int, [_VP, _VP, _VP, _I64, _VP, _VP]),
     "mgs_duplicate": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _I64, C.POINTER(mgs_camera), C.c_int,
                                 C.POINTER(mgs_settings), _VP, _VP, _I64]),
     "mgs_sort_scratch_bytes": (_SZ, [_I64]),
@@ -375,6 +376,16 @@ def mgs_scan(ctx, inp: torch.Tensor, out: torch.Tensor, total: torch.Tensor, str
     scratch = torch.empty(int(_lib.mgs_scan_scratch_bytes(n)), dtype=torch.uint8, device=inp.device)
     _check(ctx, _lib.mgs_scan(ctx, _stream(stream), _ptr(inp, torch.int32, "in"), n, _ptr(out, torch.int32, "out"),
                               _ptr(total, torch.int64, "total"), _ptr(scratch, torch.uint8, "scratch")))
+
+
+SCAN_NOALLOC_MAX_N = 33419264  # MGS_SCAN_NOALLOC_MAX_N
+
+
+def mgs_scan_noalloc(ctx, inp: torch.Tensor, out: torch.Tensor, total: Optional[torch.Tensor] = None,
+                     stream=None) -> None:
+    """mgs_scan with the library's fixed per-GPU scratch (allocates nothing)."""
+    _check(ctx, _lib.mgs_scan_noalloc(ctx, _stream(stream), _ptr(inp, torch.int32, "in"), inp.numel(),
+                                      _ptr(out, torch.int32, "out"), _ptr(total, torch.int64, "total")))
 
 
 def mgs_duplicate(ctx, rec, depth, radius, tiles, offsets, n: int, cams, st, keys, vals, stream=None) -> None:

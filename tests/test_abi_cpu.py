@@ -69,9 +69,19 @@ def test_host_validation_without_device():
     assert L.mgs_mask_loss(None, None, None, 0, None, None) == 1
     assert L.mgs_adam_step_multi(None, None, None, 0, 0.9, 0.999, 1e-15, 1, None) == 1
     assert L.mgs_step_advance(None, None, None, 1) == 1
+    assert L.mgs_scan_noalloc(None, None, None, 0, None, None) == 1
     assert L.mgs_default_settings(None) == 1
     assert L.mgs_scan_scratch_bytes(10_000) > 0
     assert L.mgs_sort_scratch_bytes(1_000_000) > L.mgs_sort_scratch_bytes(1000)
+
+
+def test_noalloc_scan_limit_matches_its_scratch():
+    txt = open(HEADER).read()
+    nbytes = int(re.search(r"#define MGS_SCAN_NOALLOC_BYTES (\d+)", txt).group(1))
+    max_n = int(re.search(r"#define MGS_SCAN_NOALLOC_MAX_N (\d+)", txt).group(1))
+    # (blocks + 1) u64 partial sums and 256 bytes, blocks of 4096 elements
+    assert max_n == ((nbytes - 256) // 8 - 1) * 4096
+    assert _lib().SCAN_NOALLOC_MAX_N == max_n
 
 
 def test_create_fails_cleanly_without_gfx950():
