@@ -320,8 +320,8 @@ def measure(w: Workload, steps: int, warmup: int, autotune: bool, graph: bool, l
 def plain_path(w: Workload, reps: int, warmup: int, autotune: bool) -> dict:
     """The same step as 8 single-view calls: one forward and backward per
     view, no graph and no persistent queue, no counters.  The compositing
-    settings are the autotuner's for the largest view (autotune) or the
-    batched path's tuned ones.  The L1 gradient of each view is weighted by
+    settings are the autotuner's for each view (autotune) or the batched
+    path's tuned ones.  The L1 gradient of each view is weighted by
     its share of the elements (so the per-view losses add up to the mean over
     all views) and the per-view parameter gradients are summed by the library
     (accumulating backward), so the step computes what the batched step
@@ -331,16 +331,21 @@ def plain_path(w: Workload, reps: int, warmup: int, autotune: bool) -> dict:
     st = w.settings_dict()
     rp = Rasterizer(0, sh_degree=w.deg, persistent=0, stats=0, **st)
     fr = rp.acquire_frame()
+    per_view = [rp.settings] * w.V
     if autotune:
-        big = max(range(w.V), key=lambda v: w.cams[v]["width"] * w.cams[v]["height"])
-        cam = w.cams[big]
         M.mgs_sample_masks(rp.ctx, w.scores, w.tau, w.seed, w.step_id, w.m_hard, w.y_soft)
-        im = rp.forward(fr, w.params, w.m_hard, [cam])
-        off = sum(3 * c["width"] * c["height"] for c in w.cams[:big])
-        d1 = torch.empty_like(im)
-        M.mgs_l1_loss_grad(rp.ctx, im, w.targets[off:off + im.numel()], d1, None, w.red)
-        rp.autotune(fr, w.params, w.m_hard, [cam], d1, images=im)
-        st = {k: getattr(rp.settings, k) for k in st}
+        base = rp.settings
+        per_view = []
+        off = 0
+        for cam in w.cams:
+            rp.settings = base
+            im = rp.forward(fr, w.params, w.m_hard, [cam])
+            d1 = torch.empty_like(im)
+            M.mgs_l1_loss_grad(rp.ctx, im, w.targets[off:off + im.numel()], d1, None, w.red)
+            off += im.numel()
+            rp.autotune(fr, w.params, w.m_hard, [cam], d1, images=im)
+            per_view.append(rp.settings)
+        st = [{k: getattr(x, k) for k in st} for x in per_view]
     offs = np.cumsum([0] + [3 * c["width"] * c["height"] for c in w.cams])
     m_tot = float(offs[-1])
     scale = [torch.full((1,), float(offs[v + 1] - offs[v]) / m_tot, device="cuda") for v in range(w.V)]
@@ -356,6 +361,7 @@ def plain_path(w: Workload, reps: int, warmup: int, autotune: bool) -> dict:
         for v, c in enumerate(w.cams):
             im = images[offs[v]:offs[v + 1]]
             dv = d_img[offs[v]:offs[v + 1]]
+            rp.settings = per_view[v]
             rp.forward(fr, w.params, m_hard, [c], images=im)
             M.mgs_l1_loss_grad(rp.ctx, im, w.targets[offs[v]:offs[v + 1]], dv, loss_v, w.red, grad_scale=scale[v])
             rp.backward(fr, w.params, dv, out=grads, accumulate=v > 0)
@@ -383,7 +389,8 @@ def plain_path(w: Workload, reps: int, warmup: int, autotune: bool) -> dict:
     if not same["ok"]:
         log(f"[bench] the plain path's step differs from the batched step: {same}")
     rp.release_frame(fr)
-    return {"ms_per_step": pms, "views_per_s": w.V / (pms * 1e-3), "settings": {**st, "persistent": 0, "stats": 0},
+    return {"ms_per_step": pms, "views_per_s": w.V / (pms * 1e-3),
+            "settings": st if isinstance(st, list) else {**st, "persistent": 0, "stats": 0},
             "same_result_as_batched": same}
 
 

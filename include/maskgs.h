@@ -452,29 +452,10 @@ MGS_API mgs_status mgs_sort(mgs_ctx* ctx, mgs_stream stream, uint64_t* keys, uin
 MGS_API mgs_status mgs_tile_ranges(mgs_ctx* ctx, mgs_stream stream, const uint64_t* keys, int64_t K,
                                    int64_t total_tiles, uint32_t* ranges);
 
-/* Masked forward compositing, Eq. (3)-(4) plus background, per pixel over
- * its tile's sorted entries.  last [P] (i32): list position of the last
- * blended entry (-1 if none); examined [P] (i32, optional): entries
- * examined up to and including the stop entry. */
-MGS_API mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
-                                         const uint32_t* ranges, const mgs_camera* cams, int n_views,
-                                         const mgs_settings* st, float* images, float* t_final, int32_t* last,
-                                         int32_t* examined);
-
-/* Masked backward compositing in reverse order, recovering transmittance
- * by division.  d_rec [R, 9] (zeroed here, then accumulated): dL/du, dL/dv,
+/* Chain rule from d_rec [R, 9] (the per-record 2D gradients: dL/du, dL/dv,
  * the conic gradient w.r.t. the three stored values (a, b / a, c - b^2 / a)
- * of rec (per pixel t^2, 2 a t dy, dy^2 with t = dx + (b / a) dy, times
- * dL/dQ: the thin and long directions of a needle stay apart in FP32),
- * dL/dopacity, dL/d(r, g, b); d_masks [n] (zeroed here): dL/dM_i summed
- * over views. */
-MGS_API mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
-                                          const uint32_t* ranges, const mgs_camera* cams, int n_views,
-                                          const mgs_settings* st, const float* t_final, const int32_t* last,
-                                          const float* dl_dimages, int64_t n, float* d_rec, float* d_masks);
-
-/* Chain rule from d_rec [R, 9] (layout of mgs_composite_backward, conic
- * gradient in the stored basis) to the Gaussian parameters, summed over
+ * of the record, dL/dopacity, dL/d(r, g, b); the layout of
+ * mgs_gradients.d_records) to the Gaussian parameters, summed over
  * views (no atomics: one thread per Gaussian), in double precision from the
  * 3D covariance to the conic.  grads->d_masks is ignored.  Under
  * MGS_MASK_OPACITY the d_rec opacity entry is dL/d(M_i opacity) and g->masks

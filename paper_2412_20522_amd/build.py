@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaskgs.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "composite.hip", "masks.hip", "hybrid.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "masks.hip", "hybrid.hip"]
 
 ARCH = "gfx950"
 COMMON_FLAGS = [

@@ -1009,45 +1009,6 @@ mgs_status mgs_tile_ranges(mgs_ctx* ctx, mgs_stream stream, const uint64_t* keys
     return MGS_OK;
 }
 
-mgs_status mgs_composite_forward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
-                                 const uint32_t* ranges, const mgs_camera* cams, int n_views, const mgs_settings* st,
-                                 float* images, float* t_final, int32_t* last, int32_t* examined) {
-    if (!ctx) return MGS_ERR_INVALID_ARG;
-    mgs_status s;
-    if ((s = check_cameras(ctx, cams, n_views)) || (s = check_settings(ctx, st))) return s;
-    if (!rec || !vals || !ranges || !images) return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
-    if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
-    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
-    DevSettings ds = make_settings(st);
-    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_COMPOSITE_FWD);
-    launch_composite_fwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->fwd_ppt}, rec, vals,
-                         ranges, vs, ds, images, t_final, last, examined, nullptr, nullptr, 0);
-    MGS_CHECK_LAUNCH(ctx);
-    return MGS_OK;
-}
-
-mgs_status mgs_composite_backward(mgs_ctx* ctx, mgs_stream stream, const float* rec, const uint32_t* vals,
-                                  const uint32_t* ranges, const mgs_camera* cams, int n_views,
-                                  const mgs_settings* st, const float* t_final, const int32_t* last,
-                                  const float* dl_dimages, int64_t n, float* d_rec, float* d_masks) {
-    if (!ctx) return MGS_ERR_INVALID_ARG;
-    mgs_status s;
-    if ((s = check_cameras(ctx, cams, n_views)) || (s = check_settings(ctx, st))) return s;
-    if (!rec || !vals || !ranges || !t_final || !last || !dl_dimages || !d_rec || !d_masks)
-        return fail(ctx, MGS_ERR_INVALID_ARG, "NULL argument");
-    if (n < 0) return fail(ctx, MGS_ERR_INVALID_ARG, "n < 0");
-    if (st->persistent) return fail(ctx, MGS_ERR_INVALID_ARG, "stage compositing is not persistent");
-    ViewSet vs = make_views(cams, n_views, st->tile_w, st->tile_h, nullptr);
-    DevSettings ds = make_settings(st);
-    StageTimer t(ctx, (hipStream_t)stream, MGS_STAGE_COMPOSITE_BWD);
-    launch_fill_f32((hipStream_t)stream, d_rec, n * n_views * DREC, 0.f);
-    launch_fill_f32((hipStream_t)stream, d_masks, n, 0.f);
-    launch_composite_bwd((hipStream_t)stream, CompositeConfig{st->tile_w, st->tile_h, st->bwd_ppt}, rec, vals, ranges,
-                         vs, ds, t_final, last, dl_dimages, n, d_rec, d_masks, nullptr, 0);
-    MGS_CHECK_LAUNCH(ctx);
-    return MGS_OK;
-}
-
 mgs_status mgs_project_backward(mgs_ctx* ctx, mgs_stream stream, const mgs_gaussians* g, const mgs_camera* cams,
                                 int n_views, const mgs_settings* st, const float* d_rec, const mgs_gradients* grads) {
     if (!ctx) return MGS_ERR_INVALID_ARG;

@@ -1258,6 +1258,14 @@ unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+bool composite_config_supported(const CompositeConfig& c) {
+#define MGS_MATCH(A, B, P) \
+    if (c.tile_w == A && c.tile_h == B && c.ppt == P) return true;
+    MGS_HYBRID_SHAPES(MGS_MATCH)
+#undef MGS_MATCH
+    return false;
+}
+
 void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
                         uint32_t* vals) {
     if (R == 0) return;

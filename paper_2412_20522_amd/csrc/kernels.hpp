@@ -70,16 +70,6 @@ struct CompositeConfig {
     int tile_w, tile_h, ppt;  // pixels per thread; threads per block = tile_w * tile_h / ppt
 };
 bool composite_config_supported(const CompositeConfig& c);
-// stats (optional) [P, 4] i32 per pixel: examined, blended, blended with mask
-// 0, entries up to the last blended one.
-void launch_composite_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
-                          const uint32_t* ranges, const ViewSet& views, const DevSettings& st, float* images,
-                          float* t_final, int32_t* last, int32_t* examined, int32_t* stats, uint32_t* queue,
-                          int num_cus);
-void launch_composite_bwd(hipStream_t stream, const CompositeConfig& cfg, const float* rec, const uint32_t* vals,
-                          const uint32_t* ranges, const ViewSet& views, const DevSettings& st, const float* t_final,
-                          const int32_t* last, const float* dl_dimages, int64_t n, float* d_rec, float* d_masks,
-                          uint32_t* queue, int num_cus);
 
 // hybrid binning: records in (view, depth, record) order are copied once
 // ("sorted records": radius in B.w, record id bits in C.w); narrow records

@@ -118,10 +118,6 @@ _SIGS = {
     "mgs_sort_scratch_bytes": (_SZ, [_I64]),
     "mgs_sort": (C.c_int, [_VP, _VP, _VP, _VP, _I64, C.c_int, _VP, _VP, _VP]),
     "mgs_tile_ranges": (C.c_int, [_VP, _VP, _VP, _I64, _I64, _VP]),
-    "mgs_composite_forward": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(mgs_camera), C.c_int,
-                                        C.POINTER(mgs_settings), _VP, _VP, _VP, _VP]),
-    "mgs_composite_backward": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(mgs_camera), C.c_int,
-                                         C.POINTER(mgs_settings), _VP, _VP, _VP, _I64, _VP, _VP]),
     "mgs_project_backward": (C.c_int, [_VP, _VP, C.POINTER(mgs_gaussians), C.POINTER(mgs_camera), C.c_int,
                                        C.POINTER(mgs_settings), _VP, C.POINTER(mgs_gradients)]),
     "mgs_sample_masks": (C.c_int, [_VP, _VP, _VP, _I64, _F, _U64, _U64, _VP, _VP, _VP]),
@@ -409,26 +405,6 @@ def mgs_sort(ctx, keys, vals, key_bits: int, stream=None) -> None:
 def mgs_tile_ranges(ctx, keys, total_tiles: int, ranges, stream=None) -> None:
     _check(ctx, _lib.mgs_tile_ranges(ctx, _stream(stream), _ptr(keys, torch.int64, "keys"), keys.numel(),
                                      total_tiles, _ptr(ranges, torch.int32, "ranges")))
-
-
-def mgs_composite_forward(ctx, rec, vals, ranges, cams, st, images, t_final, last, examined=None,
-                          stream=None) -> None:
-    ca = cameras_array(cams)
-    _check(ctx, _lib.mgs_composite_forward(ctx, _stream(stream), _ptr(rec, name="rec"),
-                                           _ptr(vals, torch.int32, "vals"), _ptr(ranges, torch.int32, "ranges"), ca,
-                                           len(cams), C.byref(st), _ptr(images, name="images"),
-                                           _ptr(t_final, name="t_final"), _ptr(last, torch.int32, "last"),
-                                           _ptr(examined, torch.int32, "examined")))
-
-
-def mgs_composite_backward(ctx, rec, vals, ranges, cams, st, t_final, last, dl_dimages, n: int, d_rec, d_masks,
-                           stream=None) -> None:
-    ca = cameras_array(cams)
-    _check(ctx, _lib.mgs_composite_backward(ctx, _stream(stream), _ptr(rec, name="rec"),
-                                            _ptr(vals, torch.int32, "vals"), _ptr(ranges, torch.int32, "ranges"), ca,
-                                            len(cams), C.byref(st), _ptr(t_final, name="t_final"),
-                                            _ptr(last, torch.int32, "last"), _ptr(dl_dimages, name="dl_dimages"), n,
-                                            _ptr(d_rec, name="d_rec"), _ptr(d_masks, name="d_masks")))
 
 
 def mgs_project_backward(ctx, g: mgs_gaussians, cams, st, d_rec, grads: mgs_gradients, stream=None) -> None:

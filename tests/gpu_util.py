@@ -114,28 +114,6 @@ def u64(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy().view(np.uint64)
 
 
-def gpu_composite_fwd(ctx, rec, vals, ranges, cams, gst):
-    P = sum(c["width"] * c["height"] for c in cams)
-    images = torch.full((3 * P,), -7.0, device="cuda")
-    tfin = torch.full((P,), -7.0, device="cuda")
-    last = torch.full((P,), -7, dtype=torch.int32, device="cuda")
-    exam = torch.full((P,), -7, dtype=torch.int32, device="cuda")
-    M().mgs_composite_forward(ctx, rec, vals if vals.numel() else torch.zeros(1, dtype=torch.int32, device="cuda"),
-                              ranges, cams, gst, images, tfin, last, exam)
-    torch.cuda.synchronize()
-    return images, tfin, last, exam
-
-
-def gpu_composite_bwd(ctx, rec, vals, ranges, cams, gst, tfin, last, dl, n):
-    R = n * len(cams)
-    d_rec = torch.full((max(R, 1), 9), 5.0, device="cuda")
-    d_masks = torch.full((max(n, 1),), 5.0, device="cuda")
-    M().mgs_composite_backward(ctx, rec, vals if vals.numel() else torch.zeros(1, dtype=torch.int32, device="cuda"),
-                               ranges, cams, gst, tfin, last, dl, n, d_rec, d_masks)
-    torch.cuda.synchronize()
-    return d_rec[:R], d_masks[:n]
-
-
 def rel_err(a, b) -> float:
     a = np.asarray(a, np.float64).ravel()
     b = np.asarray(b, np.float64).ravel()

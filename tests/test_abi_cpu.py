@@ -23,9 +23,9 @@ def _lib():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for must in ("mgs_create", "mgs_forward", "mgs_backward", "mgs_project", "mgs_sort", "mgs_composite_forward",
-                 "mgs_composite_backward", "mgs_project_backward", "mgs_sample_masks", "mgs_mask_grad",
-                 "mgs_adam_step"):
+    for must in ("mgs_create", "mgs_forward", "mgs_backward", "mgs_project", "mgs_scan", "mgs_duplicate",
+                 "mgs_sort", "mgs_tile_ranges", "mgs_project_backward", "mgs_sample_masks", "mgs_mask_loss",
+                 "mgs_mask_grad", "mgs_l1_loss_grad", "mgs_adam_step", "mgs_adam_step_multi", "mgs_scan_noalloc"):
         assert must in names
 
 

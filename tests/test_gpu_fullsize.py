@@ -1,18 +1,24 @@
 """Parity at the full sizes of the object (200k Gaussians, 800x800), unbounded
 (1.5M, 1264x832) and batched (1M, 8 uneven views) workloads, in the launch
-configuration the benchmark times (16x16 tiles, batch depth 256, 2 / 4
-pixels per thread, persistent, wide lists, tile culling).
+configuration the benchmark times (16x16 tiles, batch depth 128, 2 / 4
+pixels per thread, wide threshold 8 tiles, persistent, tile culling; the
+autotuner's choice on the batched workload) and in a second one (batch depth
+256, wide threshold 64).
 
 Stage protocol: the GPU's own projected records (exported from the frame)
 are widened exactly to FP64 and fed to the oracle's lists, compositing and
-backward; images must then agree element-wise within 1e-5 of the image
-scale on unflagged pixels and every gradient within 2e-3 (norm-wise; the
-mask gradient also element-wise on Gaussians that touch no flagged pixel).
-On the unbounded workload dL/dM is also checked against finite differences:
-for 64 seeded Gaussians, the change of <w, C> over a mask step of 1/8, C
-rendered by the (parity-checked) forward, taken over the pixels whose stop
-entry does not move (where C is affine in the mask) and compared with the
-gradient of <w, C> restricted to those pixels.
+backward.  Element-wise: images (1e-5 of the image scale) on unflagged
+pixels; the per-record 2D gradients (dL/d(u, v), conic in the stored basis,
+opacity, colour) of the compositing backward on records that touch no
+flagged pixel; every parameter gradient (means, log-scales, quaternions,
+opacity logits, SH) and dL/dM on Gaussians that touch no flagged pixel
+(2e-3 |o| + 2e-5 rms(o)); all of them also norm-wise.  The flagged fraction
+of pixels is printed and bounded per workload.  On the unbounded workload
+dL/dM is also checked against finite differences: for 64 seeded Gaussians,
+the change of <w, C> over a mask step of 1/8, C rendered by the
+(parity-checked) forward, taken over the pixels whose stop entry does not
+move (where C is affine in the mask) and compared with the gradient of
+<w, C> restricted to those pixels.
 """
 import numpy as np
 import pytest
@@ -24,8 +30,13 @@ from tests import gpu_util as U
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-BENCH = dict(tile_w=16, tile_h=16, batch_depth=256, fwd_ppt=2, bwd_ppt=4, persistent=1, wide_tiles=64,
+# the benchmark's timed configuration, and a second one
+TIMED = dict(tile_w=16, tile_h=16, batch_depth=128, fwd_ppt=2, bwd_ppt=4, persistent=1, wide_tiles=8,
              tile_cull=1, stats=1)
+OTHER = dict(TIMED, batch_depth=256, wide_tiles=64)
+# flagged pixels (decisions within the oracle's margins of a threshold), as
+# measured on these workloads, with headroom
+MAX_FLAGGED = {"object": 2e-3, "unbounded": 1e-2, "batched": 1e-2}
 
 
 def _masks(scene):
@@ -35,22 +46,24 @@ def _masks(scene):
     return np.asarray(m, np.float32)
 
 
-def _gpu(scene, masks, dl, bg):
+def _gpu(scene, masks, dl, bg, settings=TIMED):
     from paper_2412_20522_amd import maskgs as M
     from paper_2412_20522_amd.raster import Rasterizer
     cams = scene["cameras"]
-    rast = Rasterizer(0, sh_degree=scene["sh_degree"], bg=bg, **BENCH)
+    rast = Rasterizer(0, sh_degree=scene["sh_degree"], bg=bg, **settings)
     dev = U.to_device(scene, masks)
     params = {k: dev[k] for k in U.PARAM_KEYS}
     frame = rast.acquire_frame()
     img = rast.forward(frame, params, dev["masks"], cams)
-    grads = rast.backward(frame, params, torch.from_numpy(dl).cuda())
+    n = scene["means"].shape[0]
+    records = torch.empty(n * len(cams), 9, device="cuda")
+    grads = rast.backward(frame, params, torch.from_numpy(dl).cuda(), records=records)
     torch.cuda.synchronize()
     ex = {k: M.mgs_frame_export(rast.ctx, frame, k) for k in ("records", "radius", "depth")}
     evals = rast.count_evals(frame)
     torch.cuda.synchronize()
     rast.release_frame(frame)
-    return img.cpu().numpy().astype(np.float64), grads, ex, evals
+    return img.cpu().numpy().astype(np.float64), grads, ex, evals, records.cpu().numpy().astype(np.float64)
 
 
 def _oracle_on_gpu_records(scene, ex, masks, dl, bg):
@@ -80,25 +93,46 @@ def _pixel_mask(ok, cams):
     return np.concatenate(out)
 
 
-def _check(scene, img, grads, evals, of, ob, og):
+def _check(name, scene, img, grads, evals, of, ob, og, records, ex):
     cams = scene["cameras"]
     ok = of.flags == 0
-    # decisions within the oracle's margins (deep chains near T_min) are flagged
-    assert ok.mean() > 0.99
+    flagged = 1.0 - ok.mean()
+    print(f"{name}: flagged pixels {flagged:.3e} ({int((~ok).sum())} of {ok.size}); "
+          f"records touching a flagged pixel {ob.touched_flagged.mean():.3e}")
+    assert flagged <= MAX_FLAGGED[name], flagged
     scale = max(np.abs(of.image).max(), 1.0)
     err = np.abs(img - of.image)[_pixel_mask(ok, cams)].max()
     assert err <= 1e-5 * scale, err
     assert U.rel_err(img, of.image) <= 1e-5
     # work counters: blends are those of the oracle's lists
     assert evals["blended"] == pytest.approx(int(of.n_blend.sum()), rel=1e-5)
-    for name, a, b in [("means", grads.means, og.means), ("log_scales", grads.log_scales, og.log_scales),
-                       ("quats", grads.quats, og.quats), ("opacity_logits", grads.opacity_logits, og.opacity_logits),
-                       ("sh", grads.sh, og.sh), ("masks", grads.masks, ob.d_mask)]:
-        e = U.rel_err(a.cpu().numpy(), b)
-        assert e <= 2e-3, (name, e)
     n = scene["means"].shape[0]
-    ex = ob.touched_flagged.astype(bool).reshape(-1, n).any(axis=0)
-    U.assert_grad_close(grads.masks.cpu().numpy(), ob.d_mask, ex, name="mask")
+    exr = ob.touched_flagged.astype(bool)
+    exg = exr.reshape(-1, n).any(axis=0)
+    rec64 = ex["records"].view(-1, 12).cpu().numpy().astype(np.float64)
+    U.assert_grad_close(records[:, 0:2], ob.d_mean2d, exr, name="mean2d")
+    U.assert_grad_close(records[:, 2:5], U.dstable_from_dabc(rec64[:, 2], rec64[:, 3], ob.d_conic), exr,
+                        name="conic")
+    U.assert_grad_close(records[:, 5], ob.d_opacity, exr, name="opacity")
+    U.assert_grad_close(records[:, 6:9], ob.d_color, exr, name="color")
+    for key, a, b in [("means", grads.means, og.means), ("log_scales", grads.log_scales, og.log_scales),
+                      ("quats", grads.quats, og.quats), ("opacity_logits", grads.opacity_logits, og.opacity_logits),
+                      ("sh", grads.sh, og.sh), ("masks", grads.masks, ob.d_mask)]:
+        U.assert_grad_close(a.cpu().numpy(), b, exg, name=key)
+
+
+def _run(name, scene, bg, dl_seed):
+    """Both configurations on the GPU; the oracle once (the records do not
+    depend on the compositing configuration: checked)."""
+    masks = _masks(scene)
+    dl = _dl(scene, dl_seed)
+    img, grads, ex, evals, records = _gpu(scene, masks, dl, bg, TIMED)
+    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(scene, ex, masks, dl, bg)
+    _check(name, scene, img, grads, evals, of, ob, og, records, ex)
+    img2, grads2, ex2, evals2, records2 = _gpu(scene, masks, dl, bg, OTHER)
+    assert torch.equal(ex2["records"], ex["records"])
+    _check(name, scene, img2, grads2, evals2, of, ob, og, records2, ex2)
+    return masks, dl, grads
 
 
 def _dl(scene, seed):
@@ -107,23 +141,13 @@ def _dl(scene, seed):
 
 
 def test_object_scene_full_size():
-    s = scenegen.object_scene()
-    bg = (0.1, 0.2, 0.3)
-    masks = _masks(s)
-    dl = _dl(s, 21)
-    img, grads, ex, evals = _gpu(s, masks, dl, bg)
-    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
-    _check(s, img, grads, evals, of, ob, og)
+    _run("object", scenegen.object_scene(), (0.1, 0.2, 0.3), 21)
 
 
 def test_unbounded_scene_full_size_and_mask_fd():
     s = scenegen.unbounded_scene()
     bg = (0.0, 0.0, 0.0)
-    masks = _masks(s)
-    dl = _dl(s, 22)
-    img, grads, ex, evals = _gpu(s, masks, dl, bg)
-    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
-    _check(s, img, grads, evals, of, ob, og)
+    masks, dl, grads = _run("unbounded", s, bg, 22)
     # dL/dM against finite differences of the forward (parity-checked above)
     # on 64 seeded Gaussians with a non-negligible mask gradient.  With
     # L = <w, C>, C is affine in one mask on every pixel whose stop entry does
@@ -136,7 +160,7 @@ def test_unbounded_scene_full_size_and_mask_fd():
     from paper_2412_20522_amd.raster import Grads, Rasterizer
     cams = s["cameras"]
     P = cams[0]["width"] * cams[0]["height"]
-    rast = Rasterizer(0, sh_degree=s["sh_degree"], bg=bg, **BENCH)
+    rast = Rasterizer(0, sh_degree=s["sh_degree"], bg=bg, **TIMED)
     dev = U.to_device(s, masks)
     params = {k: dev[k] for k in U.PARAM_KEYS}
     frame = rast.acquire_frame()
@@ -181,10 +205,4 @@ def test_unbounded_scene_full_size_and_mask_fd():
 
 
 def test_batched_scene_full_size():
-    s = scenegen.batched_scene()
-    bg = (0.0, 0.0, 0.0)
-    masks = _masks(s)
-    dl = _dl(s, 24)
-    img, grads, ex, evals = _gpu(s, masks, dl, bg)
-    _, _, _, _, _, of, ob, og = _oracle_on_gpu_records(s, ex, masks, dl, bg)
-    _check(s, img, grads, evals, of, ob, og)
+    _run("batched", scenegen.batched_scene(), (0.0, 0.0, 0.0), 24)

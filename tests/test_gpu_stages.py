@@ -338,76 +338,176 @@ SHAPES = [(16, 16, 1, 1, 256), (16, 16, 2, 4, 128), (16, 16, 4, 4, 64), (8, 8, 1
           (32, 8, 4, 2, 128)]
 
 
-def _oracle_fwd(r):
-    oi = r["oi"]
-    return oracle.render_fwd(r["widths"], r["heights"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
-                             r["masks"], r["olists"], r["ost"])
+def _product_run(ctx, s, shape, cull, wide, persistent, bg, dl_seed=7):
+    """The whole path (mgs_forward / mgs_backward, the product kernels) in a
+    given compositing configuration; exports of the frame, the image, the
+    per-record 2D gradients and the mask gradients."""
+    M = U.M()
+    tw, th, fppt, bppt, batch = shape
+    cams = s["cameras"]
+    ost, gst = U.settings_pair(sh_degree=s["sh_degree"], tile_w=tw, tile_h=th, fwd_ppt=fppt, bwd_ppt=bppt,
+                               batch_depth=batch, bg=bg, tile_cull=cull, wide_tiles=wide, persistent=persistent,
+                               stats=1)
+    dev = U.to_device(s)
+    n = s["means"].shape[0]
+    P = sum(c["width"] * c["height"] for c in cams)
+    R = n * len(cams)
+    frame = M.mgs_frame_create(ctx)
+    try:
+        img = torch.full((3 * P,), -7.0, device="cuda")
+        tfin = torch.full((P,), -7.0, device="cuda")
+        M.mgs_forward(ctx, frame, U.gstruct(dev), cams, gst, img, tfin)
+        ex = {k: M.mgs_frame_export(ctx, frame, k) for k in ("records", "radius", "depth", "last", "stats")}
+        dl = np.random.default_rng(dl_seed).normal(size=3 * P).astype(np.float32)
+        d_rec = torch.full((max(R, 1), 9), 5.0, device="cuda")
+        d_masks = torch.full((max(n, 1),), 5.0, device="cuda")
+        gr = M.gradients_struct(d_masks=d_masks, d_records=d_rec)
+        M.mgs_backward(ctx, frame, torch.from_numpy(dl).cuda(), gr)
+        torch.cuda.synchronize()
+    finally:
+        M.mgs_frame_destroy(frame)
+    oi = U.oracle_inputs_from_rec(ex["records"].view(-1, 12))
+    rad = ex["radius"].cpu().numpy().astype(np.float64)
+    ws, hs = [c["width"] for c in cams], [c["height"] for c in cams]
+    ol = oracle.build_lists(ws, hs, n, oi["mean2d"], rad, U.u32(ex["depth"]), (rad > 0).astype(np.uint8), ost)
+    return dict(img=img.cpu().numpy().astype(np.float64), tfin=tfin.cpu().numpy(), ex=ex, dl=dl, ost=ost, oi=oi,
+                ol=ol, n=n, P=P, ws=ws, hs=hs, d_rec=d_rec[:R].cpu().numpy().astype(np.float64),
+                d_masks=d_masks[:n].cpu().numpy().astype(np.float64), masks=s["masks"].astype(np.float64))
+
+
+def _pixel_channels(ok, ws, hs):
+    out, off = [], 0
+    for w, h in zip(ws, hs):
+        out.append(np.tile(ok[off:off + w * h], 3))
+        off += w * h
+    return np.concatenate(out)
 
 
 @pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_composite_forward_matches_oracle(ctx, kind, shape):
-    tw, th, fppt, bppt, batch = shape
+@pytest.mark.parametrize("cull", [0, 1])
+def test_product_compositing_matches_oracle(ctx, kind, shape, cull):
+    """Forward and backward compositing of the whole path (the kernels the
+    product runs) against the oracle's compositing on the GPU's own records
+    and the lists of Sec. 3.1, element-wise: images and final transmittance
+    on unflagged pixels; per pixel the last blended entry (lists without
+    culling); per-record dL/d(u, v), conic (stored basis), opacity, colour
+    and per-Gaussian dL/dM on Gaussians that touch no flagged pixel."""
     s = _scene(kind)
     bg = (0.0, 0.0, 0.0) if kind == "tiny" else (0.3, 0.5, 0.7)
-    r = _run_stages(ctx, s, s["cameras"], bg=bg, tile_w=tw, tile_h=th, fwd_ppt=fppt, bwd_ppt=bppt,
-                    batch_depth=batch)
-    img, tfin, last, exam = U.gpu_composite_fwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"])
-    of = _oracle_fwd(r)
+    wide = {0: -1, 1: 0}[SHAPES.index(shape) % 2] if kind != "multiview" else 1
+    r = _product_run(ctx, s, shape, cull, wide, persistent=SHAPES.index(shape) % 2, bg=bg)
+    oi, ol, ost = r["oi"], r["ol"], r["ost"]
+    of = oracle.render_fwd(r["ws"], r["hs"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
+                           r["masks"], ol, ost)
     ok = of.flags == 0
-    P = ok.size
     assert ok.mean() > 0.99
-    gi = img.cpu().numpy().astype(np.float64).reshape(-1)
     scale = max(np.abs(of.image).max(), 1.0)
-    # images: per pixel, 3 channels (channel planes are per view; compare through a pixel mask)
-    pix_mask = np.zeros(3 * P, bool)
-    off = 0
-    for w, h in zip(r["widths"], r["heights"]):
-        p = w * h
-        m = ok[off:off + p]
-        pix_mask[3 * off:3 * off + 3 * p] = np.tile(m, 3)
-        off += p
-    err = np.abs(gi - of.image)[pix_mask].max()
+    err = np.abs(r["img"] - of.image)[_pixel_channels(ok, r["ws"], r["hs"])].max()
     assert err <= 1e-5 * scale, err
-    assert np.abs(tfin.cpu().numpy() - of.t_final)[ok].max() <= 1e-5
-    assert np.array_equal(last.cpu().numpy()[ok], of.last[ok])
-    assert np.array_equal(exam.cpu().numpy()[ok], of.examined[ok])
-    assert U.rel_err(gi, of.image) <= 1e-4
-
-
-@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
-@pytest.mark.parametrize("shape", SHAPES)
-def test_composite_backward_matches_oracle(ctx, kind, shape):
-    tw, th, fppt, bppt, batch = shape
-    s = _scene(kind)
-    bg = (0.0, 0.0, 0.0) if kind == "tiny" else (0.3, 0.5, 0.7)
-    r = _run_stages(ctx, s, s["cameras"], bg=bg, tile_w=tw, tile_h=th, fwd_ppt=fppt, bwd_ppt=bppt,
-                    batch_depth=batch)
-    img, tfin, last, exam = U.gpu_composite_fwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"])
-    P = tfin.numel()
-    rng = np.random.default_rng(7)
-    dl = rng.normal(size=3 * P).astype(np.float32)
-    dl_t = torch.from_numpy(dl).cuda()
-    d_rec, d_masks = U.gpu_composite_bwd(ctx, r["rec"], r["vals"], r["ranges"], s["cameras"], r["gst"], tfin, last,
-                                         dl_t, r["n"])
-    oi = r["oi"]
-    ob = oracle.render_bwd(r["widths"], r["heights"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
-                           r["masks"], r["olists"], dl.astype(np.float64), r["ost"])
-    g = d_rec.cpu().numpy().astype(np.float64)
-    ex = ob.touched_flagged.astype(bool)
-    U.assert_grad_close(g[:, 0:2], ob.d_mean2d, ex, name="mean2d")
-    rec64 = r["rec"].cpu().numpy().reshape(-1, 12).astype(np.float64)
-    U.assert_grad_close(g[:, 2:5], U.dstable_from_dabc(rec64[:, 2], rec64[:, 3], ob.d_conic), ex, name="conic")
-    U.assert_grad_close(g[:, 5], ob.d_opacity, ex, name="opacity")
-    U.assert_grad_close(g[:, 6:9], ob.d_color, ex, name="color")
+    assert np.abs(r["tfin"] - of.t_final)[ok].max() <= 1e-5
+    assert U.rel_err(r["img"], of.image) <= 1e-4
+    if not cull:
+        tw, th = shape[0], shape[1]
+        start = np.empty(r["P"], np.int64)
+        off = toff = 0
+        for w, h in zip(r["ws"], r["hs"]):
+            gw = (w + tw - 1) // tw
+            yy, xx = np.divmod(np.arange(w * h), w)
+            start[off:off + w * h] = ol.ranges[toff + (yy // th) * gw + xx // tw, 0]
+            off += w * h
+            toff += gw * ((h + th - 1) // th)
+        o_last = np.where(of.last >= 0, of.last - start, -1)
+        assert np.array_equal(r["ex"]["last"].cpu().numpy()[ok], o_last[ok])
+        stats = r["ex"]["stats"].cpu().numpy().reshape(-1, 4)
+        assert np.array_equal(stats[ok, 0], of.examined[ok])
+    ob = oracle.render_bwd(r["ws"], r["hs"], r["n"], oi["mean2d"], oi["conic"], oi["opacity"], oi["color"],
+                           r["masks"], ol, r["dl"].astype(np.float64), ost)
+    g = r["d_rec"]
+    exr = ob.touched_flagged.astype(bool)
+    rec64 = r["ex"]["records"].view(-1, 12).cpu().numpy().astype(np.float64)
+    U.assert_grad_close(g[:, 0:2], ob.d_mean2d, exr, name="mean2d")
+    U.assert_grad_close(g[:, 2:5], U.dstable_from_dabc(rec64[:, 2], rec64[:, 3], ob.d_conic), exr, name="conic")
+    U.assert_grad_close(g[:, 5], ob.d_opacity, exr, name="opacity")
+    U.assert_grad_close(g[:, 6:9], ob.d_color, exr, name="color")
     n = r["n"]
-    exg = ex.reshape(-1, n).any(axis=0)
-    U.assert_grad_close(d_masks.cpu().numpy(), ob.d_mask, exg, name="mask")
+    U.assert_grad_close(r["d_masks"], ob.d_mask, exr.reshape(-1, n).any(axis=0), name="mask")
     # masked Gaussians receive a mask gradient and nothing else
     masked = r["masks"] == 0
-    gm = g.reshape(-1, n, 9)[:, masked, :]
-    assert np.all(gm == 0.0)
-    assert np.count_nonzero(d_masks.cpu().numpy()[masked]) > 0
+    assert np.all(g.reshape(-1, n, 9)[:, masked, :] == 0.0)
+    assert np.count_nonzero(r["d_masks"][masked]) > 0
+
+
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+def test_culled_lists_keep_every_entry_that_can_blend(ctx, kind):
+    """With tile culling the whole path lists a record in a tile (or its
+    region) only where it can pass the per-pixel filters.  Checked on the
+    exported lists against the oracle's lists of Sec. 3.1: every entry kept
+    for a tile is in the oracle's list of that tile, and every oracle entry
+    left out fails Q <= 9 or alpha >= 1/255 at every pixel centre of the
+    tile (FP64, the GPU's own records)."""
+    M = U.M()
+    s = _scene(kind)
+    cams = s["cameras"]
+    RG = M.REGION_TILES
+    for tw, th in [(16, 16), (8, 8)]:
+        ost, gst = U.settings_pair(sh_degree=s["sh_degree"], tile_w=tw, tile_h=th, fwd_ppt=1, bwd_ppt=1,
+                                   wide_tiles=4, batch_depth=64, tile_cull=1)
+        dev = U.to_device(s)
+        frame = M.mgs_frame_create(ctx)
+        try:
+            P = sum(c["width"] * c["height"] for c in cams)
+            img = torch.empty(3 * P, device="cuda")
+            M.mgs_forward(ctx, frame, U.gstruct(dev), cams, gst, img)
+            ex = {k: M.mgs_frame_export(ctx, frame, k) for k in ("records", "radius", "depth", "values", "ranges",
+                                                                   "order")}
+            torch.cuda.synchronize()
+        finally:
+            M.mgs_frame_destroy(frame)
+        n = s["means"].shape[0]
+        rec = ex["records"].view(-1, 12).cpu().numpy().astype(np.float64)
+        oi = U.oracle_inputs_from_rec(ex["records"].view(-1, 12))
+        rad = ex["radius"].cpu().numpy().astype(np.float64)
+        ol = oracle.build_lists([c["width"] for c in cams], [c["height"] for c in cams], n, oi["mean2d"], rad,
+                                U.u32(ex["depth"]), (rad > 0).astype(np.uint8), ost)
+        vals, order = U.u32(ex["values"]), U.u32(ex["order"])
+        ranges = U.u32(ex["ranges"]).reshape(-1, 2).astype(np.int64)
+        T = ol.ranges.shape[0]
+        t = roff = 0
+        dropped_total = kept_total = 0
+        for c in cams:
+            gw, gh = (c["width"] + tw - 1) // tw, (c["height"] + th - 1) // th
+            rw = (gw + RG - 1) // RG
+            for ty in range(gh):
+                for tx in range(gw):
+                    own = order[vals[ranges[t, 0]:ranges[t, 1]]].astype(np.int64)
+                    rg = T + roff + (ty // RG) * rw + tx // RG
+                    reg = order[vals[ranges[rg, 0]:ranges[rg, 1]]].astype(np.int64)
+                    a, b = ol.ranges[t]
+                    full = ol.vals[a:b].astype(np.int64)
+                    assert np.all(np.isin(own, full)), (tw, t)
+                    kept = np.union1d(own, reg)
+                    drop = np.setdiff1d(full, kept)
+                    kept_total += np.intersect1d(full, kept).size
+                    dropped_total += drop.size
+                    if drop.size:
+                        x0, y0 = tx * tw, ty * th
+                        xs = np.arange(x0, min(x0 + tw, c["width"])) + 0.5
+                        ys = np.arange(y0, min(y0 + th, c["height"])) + 0.5
+                        px, py = np.meshgrid(xs, ys)
+                        dx = rec[drop, 0][:, None] - px.reshape(-1)[None, :]
+                        dy = rec[drop, 1][:, None] - py.reshape(-1)[None, :]
+                        A, B, C = (oi["conic"][drop, k][:, None] for k in range(3))
+                        Q = A * dx * dx + 2 * B * dx * dy + C * dy * dy
+                        alpha = np.minimum(0.99, rec[drop, 5][:, None] * np.exp(-0.5 * Q))
+                        can = (Q <= 9.0) & (alpha >= np.float32(1 / 255))
+                        assert not can.any(), (tw, t, int(can.sum()))
+                    t += 1
+            roff += rw * ((gh + RG - 1) // RG)
+        assert t == T
+        # culling removes a real share of the entries, and keeps most
+        assert dropped_total > 0 and kept_total > 0
+        print(kind, (tw, th), "kept", kept_total, "dropped", dropped_total)
 
 
 def test_project_backward_matches_oracle(ctx):

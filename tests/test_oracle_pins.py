@@ -117,6 +117,148 @@ def test_isotropic_on_axis_projection_closed_form(orc):
     np.testing.assert_allclose(pr.color[0], [0.8, 0.3, 0.1], atol=1e-7)
 
 
+def _clamped_cov2d(cam, t, s, dil):
+    """Sigma_2D of an isotropic Gaussian (scale s) at view-space centre t,
+    with the lateral ratios of the Jacobian clamped at 1.3 tan(fov / 2):
+    J J^T s^2 + dil I written out for J = [[f/z, 0, -f r_x], [0, f/z, -f r_y]]
+    / ... with r = clamp(t_xy / z), so (J J^T)_00 = fx^2 (1 + r_x^2) / z^2,
+    (J J^T)_01 = fx fy r_x r_y / z^2, (J J^T)_11 = fy^2 (1 + r_y^2) / z^2."""
+    fx, fy = float(cam["fx"]), float(cam["fy"])
+    limx = float(np.float32(1.3)) * 0.5 * cam["width"] / fx
+    limy = float(np.float32(1.3)) * 0.5 * cam["height"] / fy
+    rx = min(max(t[0] / t[2], -limx), limx)
+    ry = min(max(t[1] / t[2], -limy), limy)
+    z2 = t[2] * t[2]
+    return np.array([s * s * fx * fx * (1 + rx * rx) / z2 + dil, s * s * fx * fy * rx * ry / z2,
+                     s * s * fy * fy * (1 + ry * ry) / z2 + dil]), (abs(t[0] / t[2]) > limx, abs(t[1] / t[2]) > limy)
+
+
+@pytest.mark.parametrize("t", [(0.3, -0.2, 4.0), (4.8, 0.0, 4.0), (-4.4, 0.0, 4.0), (0.0, -3.6, 4.0),
+                               (0.0, 2.9, 4.0), (5.1, -3.3, 4.0), (-2.6, 2.5, 2.5)])
+def test_clamped_jacobian_projection_closed_form(orc, t):
+    """Sec. 3.1 (EWA splatting): an isotropic Gaussian anywhere in front of
+    the camera, inside and beyond the lateral clamp of the Jacobian in x, in
+    y and in both, with both signs: Sigma_2D and the conic in closed form."""
+    cam = scenegen.orbit_camera(4.0, 0.0, 0.0, 64, 48)  # identity rotation, centre at (0, 0, -4)
+    ls = float(np.float32(math.log(0.07)))
+    sc = _one_gaussian_scene([t[0], t[1], t[2] - 4.0], ls, quat=(0.6, 0.1, -0.7, 0.2))
+    st = orc.RasterSettings(sh_degree=0)
+    pr = orc.project(sc, cam, st)
+    tt = np.array(sc["means"][0], np.float64) + np.array([0.0, 0.0, 4.0])
+    want, (cx, cy) = _clamped_cov2d(cam, tt, math.exp(ls), float(np.float32(0.3)))
+    np.testing.assert_allclose(pr.cov2d[0], want, rtol=1e-12, atol=1e-12 * want.max())
+    det = want[0] * want[2] - want[1] ** 2
+    wc = np.array([want[2] / det, -want[1] / det, want[0] / det])
+    np.testing.assert_allclose(pr.conic[0], wc, rtol=1e-11, atol=1e-12 * np.abs(wc).max())
+    fx = float(cam["fx"])
+    np.testing.assert_allclose(pr.mean2d[0], [fx * tt[0] / tt[2] + 32.0, fx * tt[1] / tt[2] + 24.0], rtol=1e-13)
+    if abs(t[0]) > 4 or abs(t[1]) > 3:
+        assert cx or cy  # the case reaches the clamp
+
+
+def test_clamped_jacobian_finite_differences(orc):
+    """O10 through the clamped branch of the Jacobian: central differences in
+    exact mode of every continuous input of splats beyond the clamp in x, in
+    y, in both (either sign) and inside it, whose footprints reach into the
+    image; the clamped ratio has zero derivative in the view-space centre."""
+    cam = scenegen.orbit_camera(4.0, 0.0, 0.0, 24, 18)
+    fx = float(cam["fx"])
+    limx, limy = 1.3 * 12 / fx, 1.3 * 9 / fx
+    ts = [(1.25 * limx, 0.1, 1.0), (-1.3 * limx, -0.05, 1.0), (0.05, 1.3 * limy, 1.0), (-0.1, -1.35 * limy, 1.0),
+          (1.2 * limx, -1.25 * limy, 1.0), (0.1, 0.1, 1.0)]
+    rng = np.random.default_rng(12)
+    n = len(ts)
+    # distinct depths (4 + 0.3 k), so that no difference reorders the splats
+    means = np.array([[r * (4.0 + 0.3 * k), q * (4.0 + 0.3 * k), 0.3 * k] for k, (r, q, _) in enumerate(ts)])
+    sc = dict(means=means.astype(np.float32),
+              log_scales=(np.log(0.9) + 0.2 * rng.normal(size=(n, 3))).astype(np.float32),
+              quats=rng.normal(size=(n, 4)).astype(np.float32),
+              opacity_logits=rng.normal(size=n).astype(np.float32),
+              sh=(0.4 * rng.normal(size=(n, 4, 3))).astype(np.float32))
+    clamped = 0
+    for r, q, _ in ts:
+        clamped += (abs(r) > limx) + (abs(q) > limy)
+    assert clamped >= 6
+    st = orc.RasterSettings(sh_degree=1, bg=(0.2, 0.5, 0.1), exact_mode=True)
+    mask = rng.uniform(0.3, 1.0, n)
+    P = 24 * 18
+    w = rng.normal(size=3 * P)
+    base = {k: np.asarray(sc[k], np.float64).copy() for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    out = orc.run_pipeline(base, [cam], mask, st, dl_dimage=w)
+    assert np.all(out.proj[0].valid == 1)
+    grads = dict(means=out.grads.means, log_scales=out.grads.log_scales, quats=out.grads.quats)
+    h = 1e-6
+    for key, g in grads.items():
+        flat = base[key].reshape(-1)
+        fd = np.zeros(flat.size)
+        for j in range(flat.size):
+            old = flat[j]
+            flat[j] = old + h
+            lp = _loss_linear(orc, base, [cam], mask, st, w)
+            flat[j] = old - h
+            lm = _loss_linear(orc, base, [cam], mask, st, w)
+            flat[j] = old
+            fd[j] = (lp - lm) / (2 * h)
+        scale = max(np.abs(fd).max(), 1e-3)
+        assert np.abs(fd - g.reshape(-1)).max() <= 2e-6 * scale, (key, np.abs(fd - g.reshape(-1)).max() / scale)
+        # every splat's gradient is resolved (the footprints reach the image)
+        assert np.all(np.abs(fd.reshape(n, -1)).max(axis=1) > 1e-6 * scale), key
+
+
+def _flag_case(orc, mean2d, opacity, depth_bits, w=1, h=1, st=None):
+    """Flags and final transmittance of pixel (0, 0) of a one-pixel image for
+    splats given by their 2D centres (conic = identity), opacities and depth
+    bits."""
+    st = st or orc.RasterSettings(sh_degree=0)
+    n = len(opacity)
+    m2 = np.asarray(mean2d, np.float64).reshape(n, 2)
+    conic = np.tile([1.0, 0.0, 1.0], (n, 1))
+    rad = np.full(n, 20.0)
+    lists = orc.build_lists([w], [h], n, m2, rad, np.asarray(depth_bits, np.uint32), np.ones(n, np.uint8), st)
+    col = np.tile([0.5, 0.25, 0.75], (n, 1))
+    of = orc.render_fwd([w], [h], n, m2, conic, np.asarray(opacity, np.float64), col, np.ones(n), lists, st)
+    ob = orc.render_bwd([w], [h], n, m2, conic, np.asarray(opacity, np.float64), col, np.ones(n), lists,
+                        np.ones(3 * w * h), st)
+    return int(of.flags[0]), of, ob
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_decision_flags_mark_only_near_threshold_cases(orc, sign):
+    """The parity protocol's decision margins: a pixel is flagged when a
+    discrete decision of its walk lies within a relative 1e-5 of its
+    threshold (Q vs 9, o G vs 0.99, alpha vs 1/255) or 2e-4 (the stop test
+    vs T_min), and only then; flagged pixels mark every entry they touch."""
+    FQ, FAMIN, FAMAX, FT = 1, 2, 4, 8
+    pc = 0.5  # centre of pixel (0, 0)
+    # Q = d^2 for a splat at distance d with the identity conic
+    for eps, flagged in [(5e-6, True), (1e-3, False)]:
+        d = 3.0 * math.sqrt(1.0 + sign * eps)
+        f, _, _ = _flag_case(orc, [[pc + d, pc]], [0.9], [1])
+        assert bool(f & FQ) == flagged, (eps, f)
+        # alpha against the filter 1/255 (Q = 0: alpha = opacity)
+        a = float(np.float32(1 / 255)) * (1.0 + sign * eps)
+        f, _, _ = _flag_case(orc, [[pc, pc]], [a], [1])
+        assert bool(f & FAMIN) == flagged, (eps, f)
+        # o G against the clamp 0.99
+        f, _, _ = _flag_case(orc, [[pc, pc]], [0.99 * (1.0 + sign * eps)], [1])
+        assert bool(f & FAMAX) == flagged, (eps, f)
+    # the stop test T (1 - alpha) against T_min = 1e-4 after two splats of 0.95
+    for eps, flagged in [(1e-4, True), (1e-2, False)]:
+        a3 = 1.0 - 0.04 * (1.0 + sign * eps)
+        f, of, ob = _flag_case(orc, [[pc, pc]] * 4, [0.95, 0.95, a3, 0.5], [1, 2, 3, 4])
+        assert bool(f & FT) == flagged, (eps, f)
+        assert f & ~FT == 0
+        if flagged:
+            # a flagged stop marks the entries up to the stop and those a
+            # non-stopping walk would blend next
+            assert np.all(ob.touched_flagged[:4] == 1)
+        else:
+            assert np.all(ob.touched_flagged == 0)
+    # far from every threshold: nothing flagged
+    f, _, ob = _flag_case(orc, [[pc + 1.0, pc], [pc, pc + 2.0]], [0.5, 0.7], [1, 2])
+    assert f == 0 and np.all(ob.touched_flagged == 0)
+
+
 @pytest.mark.parametrize("mval", [1.0, 0.0, 0.37])
 def test_single_gaussian_image_closed_form(orc, mval):
     cam = scenegen.orbit_camera(4.0, 0.0, 0.0, 40, 36)
