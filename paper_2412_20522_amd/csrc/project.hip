@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
 // (only records listed in some tile can have received gradients, and every
 // such row is read here).  tiles (optional): the forward's per-record tile
 // counts; rows of records without tiles are neither read nor cleared.
-template <int DEG, typename AccT>
+template <int DEG, typename AccT, bool ACC>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh, const float* __restrict__ masks,
@@ -315,11 +315,13 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     float* __restrict__ d_means,
     float* __restrict__ d_log_scales, float* __restrict__ d_quats, float* __restrict__ d_opacity_logits,
     float* __restrict__ d_sh, float* __restrict__ d_masks, float* __restrict__ d_rec_out,
-    const uint32_t* __restrict__ tiles, int accumulate) {
+    const uint32_t* __restrict__ tiles) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    // parameter gradients are written, or added to what the outputs hold
+    // ACC: parameter gradients are added to what the outputs hold (a
+    // template parameter: the overwriting kernel keeps its vector stores)
+    constexpr bool accumulate = ACC;
     const float px = means[3 * g], py = means[3 * g + 1], pz = means[3 * g + 2];
     const float opac = 1.f / (1.f + __expf(-opacity_logits[g]));
     // Two passes over the views, so that the double-precision covariance
@@ -474,7 +476,7 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
         if (d_quats) {
             float4 dq = make_float4((float)((gw - qw * dotq) * cv.qinv), (float)((gx - qx * dotq) * cv.qinv),
                                     (float)((gy - qy * dotq) * cv.qinv), (float)((gz - qz * dotq) * cv.qinv));
-            if (accumulate) {
+            if constexpr (ACC) {
                 const float4 o = reinterpret_cast<const float4*>(d_quats)[g];
                 dq.x += o.x; dq.y += o.y; dq.z += o.z; dq.w += o.w;
             }
@@ -587,11 +589,15 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     const size_t lds = (size_t)views.n_views * 3 * 256 * sizeof(float);  // colour gradients of every view
     float* d_masks = dm_acc ? out.d_masks : nullptr;
     float* rec_out = dm_acc ? out.d_records : nullptr;  // whole path only
-#define MGS_PBWD(D)                                                                                               \
-    hipLaunchKernelGGL((project_bwd_kernel<D, AccT>), grid, dim3(256), lds, stream, g.means, g.log_scales, g.quats, \
-                       g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means,         \
-                       out.d_log_scales,                                                                            \
-                       out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles, out.accumulate)
+#define MGS_PBWD_A(D, A)                                                                                          \
+    hipLaunchKernelGGL((project_bwd_kernel<D, AccT, A>), grid, dim3(256), lds, stream, g.means, g.log_scales,       \
+                       g.quats, g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means, \
+                       out.d_log_scales, out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles)
+#define MGS_PBWD(D)              \
+    if (out.accumulate)          \
+        MGS_PBWD_A(D, true);     \
+    else                         \
+        MGS_PBWD_A(D, false)
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;
@@ -599,6 +605,7 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
         default: MGS_PBWD(3); break;
     }
 #undef MGS_PBWD
+#undef MGS_PBWD_A
 }
 }  // namespace
 

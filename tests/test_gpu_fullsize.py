@@ -34,9 +34,9 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 TIMED = dict(tile_w=16, tile_h=16, batch_depth=128, fwd_ppt=2, bwd_ppt=4, persistent=1, wide_tiles=8,
              tile_cull=1, stats=1)
 OTHER = dict(TIMED, batch_depth=256, wide_tiles=64)
-# flagged pixels (decisions within the oracle's margins of a threshold), as
-# measured on these workloads, with headroom
-MAX_FLAGGED = {"object": 2e-3, "unbounded": 1e-2, "batched": 1e-2}
+# flagged pixels (decisions within the oracle's margins of a threshold):
+# twice the fractions measured on these workloads (6.3e-4, 2.8e-3, 3.2e-3)
+MAX_FLAGGED = {"object": 1.3e-3, "unbounded": 5.7e-3, "batched": 6.3e-3}
 
 
 def _masks(scene):

@@ -272,7 +272,10 @@ def test_training_step_matches_oracle_on_crop():
         agree = np.sign(g[k]) == np.sign(o)
         nz = (g[k] != 0) | (o != 0)
         assert (~agree).sum() <= max(2, 1e-2 * nz.sum()), (k, int((~agree).sum()), int(nz.sum()))
-        assert np.all(np.abs(after[k] - p2)[agree] <= 2e-6 * (np.abs(p2) + lr)[agree]), k
+        # (gradients within a few decades of eps = 1e-15 move by lr g / (|g| + eps),
+        # which depends on |g| itself: those are left to the check above)
+        sure = agree & ((np.abs(o) > 1e-9) | (o == 0))
+        assert np.all(np.abs(after[k] - p2)[sure] <= 2e-6 * (np.abs(p2) + lr)[sure]), k
     trainer.close()
 
 
