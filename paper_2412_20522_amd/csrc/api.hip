@@ -544,17 +544,16 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT);
         launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
-                           (uint32_t*)f->tiles.p, f->flags());
+                           (uint32_t*)f->tiles.p, f->flags(), (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
     }
     {
         // records in (view, depth, record) order, those without tiles last in
         // their view; then the sorted record copy, list entry counts and wide
         // flags in that order
         StageTimer t(ctx, stream, MGS_STAGE_DEPTH_SORT);
-        // 32-bit depth keys sorted within each view's segment of n records:
-        // the order of 64-bit (view, depth) keys in 4 passes instead of 5
-        launch_record_keys(stream, (const float*)f->depth.p, (const uint32_t*)f->tiles.p, R,
-                           (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
+        // 32-bit depth keys (written by the projection) sorted within each
+        // view's segment of n records: the order of 64-bit (view, depth) keys
+        // in 4 passes instead of 5
         bool alt = false;
         launch_radix_sort_segmented(stream, (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p, (uint32_t*)f->rkeys_alt.p,
                                     (uint32_t*)f->rvals_alt.p, R, f->n, f->rsort_tmp.p, &alt);

@@ -129,15 +129,6 @@ __device__ __forceinline__ TileBox cell_box(int cx, int cy, int cw, int ch, cons
 // segment [v n, (v + 1) n)): the float bits of the view-space depth (positive,
 // so the bits order like the values), all ones for a record without tiles,
 // which sorts it after every listed record of its view.
-__global__ void __launch_bounds__(256) record_keys_kernel(const float* __restrict__ depth,
-                                                          const uint32_t* __restrict__ tiles, int64_t R,
-                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    keys[r] = tiles[r] ? __float_as_uint(depth[r]) : 0xffffffffu;
-    vals[r] = (uint32_t)r;
-}
-
 // The cells a record is listed in: the tiles of its rectangle for a narrow
 // record, the regions (REGION x REGION tiles) its rectangle overlaps for a
 // wide one.  Cell j of the rectangle is (x0 + j % w, y0 + j / w).
@@ -343,13 +334,16 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     }
 }
 
-// Totals of the two per-workgroup counts of the classification (fixed
-// order, one workgroup): out[0] = wide records, out[2] = region entries.
-__global__ void __launch_bounds__(1024) sum_parts_kernel(const uint32_t* __restrict__ part, int nb,
-                                                          uint64_t* __restrict__ out) {
-    __shared__ uint64_t s[2][16];
+// Totals of the two per-workgroup counts of the classification: out[0] =
+// wide records, out[2] = region entries (integer sums: any order gives the
+// same totals).
+__global__ void __launch_bounds__(256) sum_parts_kernel(const uint32_t* __restrict__ part, int nb,
+                                                         uint64_t* __restrict__ out) {
+    // out[0] and out[2] are zero (cleared with the flags before the
+    // forward); every workgroup adds the sums of its slice of the parts
+    __shared__ uint64_t s[2][4];
     uint64_t a = 0, b = 0;
-    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    for (int k = (int)blockIdx.x * 256 + (int)threadIdx.x; k < nb; k += (int)gridDim.x * 256) {
         a += part[k];
         b += part[nb + k];
     }
@@ -364,13 +358,10 @@ __global__ void __launch_bounds__(1024) sum_parts_kernel(const uint32_t* __restr
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t ta = 0, tb = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-            ta += s[0][w];
-            tb += s[1][w];
-        }
-        out[0] = ta;
-        out[2] = tb;
+        const uint64_t ta = s[0][0] + s[0][1] + s[0][2] + s[0][3];
+        const uint64_t tb = s[1][0] + s[1][1] + s[1][2] + s[1][3];
+        if (ta) atomicAdd(reinterpret_cast<unsigned long long*>(out), (unsigned long long)ta);
+        if (tb) atomicAdd(reinterpret_cast<unsigned long long*>(out + 2), (unsigned long long)tb);
     }
 }
 
@@ -813,6 +804,17 @@ __device__ __forceinline__ float wave_sum_transposed10(const float (&v)[10], int
     return lane < 8 ? z0 : z1;
 }
 
+// Pixel of slot i of thread t: every wave's slot covers one 8x8 block of
+// the tile (block w PPT + i of the tile's TW / 8 x TH / 8 blocks), so that an
+// entry whose footprint covers part of the tile leaves fewer lanes idle than
+// with rows of the tile per slot.
+template <int TW, int PPT>
+__device__ __forceinline__ void pixel_of(int t, int i, const TileGeom& tg, int& x, int& y) {
+    const int b = (t >> 6) * PPT + i, l = t & 63;
+    x = tg.tx0 + (b % (TW / 8)) * 8 + (l & 7);
+    y = tg.ty0 + (b / (TW / 8)) * 8 + (l >> 3);
+}
+
 // Staged-list chunks: a persistent workgroup composites many tiles, a plain
 // one a single tile.
 constexpr uint32_t STG_CHUNK_PERSISTENT = 4096;
@@ -876,8 +878,8 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         bool done[PPT], inside[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const int pidx = t + i * NT;
-            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            int x, y;
+            pixel_of<TW, PPT>(t, i, tg, x, y);
             inside[i] = x < cam.width && y < cam.height;
             px[i] = (float)x + 0.5f;
             py[i] = (float)y + 0.5f;
@@ -986,8 +988,8 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             if (!inside[i]) continue;
-            const int pidx = t + i * NT;
-            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            int x, y;
+            pixel_of<TW, PPT>(t, i, tg, x, y);
             const int64_t pv = (int64_t)cam.width * cam.height;
             const int64_t loc = (int64_t)y * cam.width + x;
             float* im = images + 3 * (int64_t)cam.px_off;
@@ -1041,8 +1043,8 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
         const int64_t pv = (int64_t)cam.width * cam.height;
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
-            const int pidx = t + i * NT;
-            const int x = tg.tx0 + pidx % TW, y = tg.ty0 + pidx / TW;
+            int x, y;
+            pixel_of<TW, PPT>(t, i, tg, x, y);
             px[i] = (float)x + 0.5f;
             py[i] = (float)y + 0.5f;
             sb[i] = 0.f;
@@ -1084,6 +1086,9 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
                 if ((int)cur[b].z <= top) bstar = b;
         }
         const uint2* cstg = hl.stg ? hl.cur_stg + hl.cur_off[tile] : nullptr;
+        // per-entry partial sums of this lane's pixels; zero between entries
+        // (reset after each reduction), so no per-entry initialisation
+        float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f, gm = 0.f;
         for (int b = bstar; b >= 0; --b) {
             const uint4 c = cur[b];
             const int m = (int)c.z;
@@ -1112,8 +1117,6 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
                 if (k > top) continue;                  // uniform: past every pixel's last entry
                 const float M = B.z;
                 const float okq = B.y * QSCALE_NINV;
-                float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f,
-                      gm = 0.f;
                 bool any = false;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
@@ -1164,6 +1167,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
                         const float sm = wave_sum(gm);
                         if (lane == 0) atomicAdd(d_masks + g, (double)sm);
                     }
+                    gu = gv = ga = gb = gc = go = gr = gg = gbl = gm = 0.f;
                 }
             }
             __syncthreads();  // the next batch overwrites the LDS
@@ -1266,12 +1270,6 @@ bool composite_config_supported(const CompositeConfig& c) {
     return false;
 }
 
-void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
-                        uint32_t* vals) {
-    if (R == 0) return;
-    hipLaunchKernelGGL(record_keys_kernel, dim3(blocks_of(R)), dim3(256), 0, stream, depth, tiles, R, keys, vals);
-}
-
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
                              int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
                              uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
@@ -1281,7 +1279,8 @@ void launch_permute_classify(hipStream_t stream, const uint32_t* order, const ui
     hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, skeys,
                        reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, wide_flag, tmask,
                        reinterpret_cast<float4*>(srec), part);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(1024), 0, stream, part, (int)nb, wide_counts);
+    const unsigned sb = (unsigned)std::min<int64_t>(256, ((int64_t)nb + 255) / 256);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(sb), dim3(256), 0, stream, part, (int)nb, wide_counts);
 }
 
 size_t classify_parts_bytes(int64_t R) { return (size_t)blocks_of(R) * 8 + 8; }

@@ -10,8 +10,12 @@
 namespace mgs {
 
 // projection
+// rkeys, rvals (optional, both or neither): the keys of the per-view depth
+// order of the records (depth bits, all ones for records without tiles) and
+// the record ids
 void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags);
+                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags,
+                        uint32_t* rkeys = nullptr, uint32_t* rvals = nullptr);
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out);
 // Whole path: FP64 per-record gradients, which are set back to zero as they
@@ -76,9 +80,6 @@ bool composite_config_supported(const CompositeConfig& c);
 // are listed per tile, wide records per region (one key space: tile ids, then
 // region ids), with sorted positions as values, and merged per tile while
 // compositing
-// depth keys (u32) and record ids of the records, to be sorted per view
-void launch_record_keys(hipStream_t stream, const float* depth, const uint32_t* tiles, int64_t R, uint32_t* keys,
-                        uint32_t* vals);
 // wide_counts (device u64): [0] = wide records, [2] = their region entries;
 // part: classify_parts_bytes(R) bytes of per-workgroup partial counts
 size_t classify_parts_bytes(int64_t R);

@@ -234,7 +234,8 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh, const float* __restrict__ masks,
     int64_t n, ViewSet views, DevSettings st, float4* __restrict__ rec, float* __restrict__ depth_out,
-    float* __restrict__ radius_out, uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ flags) {
+    float* __restrict__ radius_out, uint32_t* __restrict__ tiles_out, uint32_t* __restrict__ flags,
+    uint32_t* __restrict__ rkeys, uint32_t* __restrict__ rvals) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -261,6 +262,10 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             depth_out[r] = o.depth;
             radius_out[r] = 0.f;
             tiles_out[r] = 0;
+            if (rkeys) {
+                rkeys[r] = 0xffffffffu;
+                rvals[r] = (uint32_t)r;
+            }
             continue;
         }
         // colour in the viewing direction
@@ -295,6 +300,12 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
         depth_out[r] = o.depth;
         radius_out[r] = o.radius;
         tiles_out[r] = count;
+        // keys of the depth order of the records (per view): the depth bits,
+        // all ones for a record listed nowhere (sorted last in its view)
+        if (rkeys) {
+            rkeys[r] = count ? __float_as_uint(o.depth) : 0xffffffffu;
+            rvals[r] = (uint32_t)r;
+        }
     }
     if (bad) atomicOr(flags, FLAG_NONFINITE);
 }
@@ -563,13 +574,15 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
 }  // namespace
 
 void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
-                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags) {
+                        float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags, uint32_t* rkeys,
+                        uint32_t* rvals) {
     if (g.n == 0) return;
     const dim3 grid((unsigned)((g.n + 255) / 256));
     float4* rec4 = reinterpret_cast<float4*>(rec);
 #define MGS_PFWD(D)                                                                                                \
     hipLaunchKernelGGL(project_fwd_kernel<D>, grid, dim3(256), 0, stream, g.means, g.log_scales, g.quats,          \
-                       g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags)
+                       g.opacity_logits, g.sh, g.masks, g.n, views, st, rec4, depth, radius, tiles, flags, rkeys, \
+                       rvals)
     switch (st.sh_degree) {
         case 0: MGS_PFWD(0); break;
         case 1: MGS_PFWD(1); break;
