@@ -292,8 +292,9 @@ struct mgs_frame {
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     DevBuf imp_acc;  // FP64 sums of the importance forward
-    // d_rec is all zeros between backwards (the projection backward clears
-    // the rows it reads); false until a fill after (re)allocation
+    // d_rec is all zeros from the forward compositing (which clears it) to
+    // the backward that accumulates into it; false after a backward and
+    // after (re)allocation (a backward then fills it first)
     bool drec_zero = false;
     // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
     // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
@@ -307,11 +308,15 @@ struct mgs_frame {
     uint64_t* wide_counts() { return (uint64_t*)((char*)misc.p + 16); }
     uint64_t* cur_need() { return (uint64_t*)((char*)misc.p + 24); }
     uint32_t* stg_count() { return (uint32_t*)((char*)misc.p + 192); }
-    HybridBuffers hybrid() {
+    HybridBuffers hybrid(bool clear_drec = false) {
         const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)std::min(cur.bytes / 16, cur_stg.bytes / 8);
         const uint64_t scap = reserved ? (uint64_t)stg_cap : (uint64_t)(stg.bytes / 8);
+        // pairs of doubles covering the R x DREC accumulator (the allocation
+        // has 8 bytes of slack for an odd count)
+        const uint64_t n2 = clear_drec ? ((uint64_t)R * DREC + 1) / 2 : 0;
         return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
-                             flags(), (uint32_t*)cur_stg.p, (uint32_t*)stg.p, stg_count(), scap};
+                             flags(), (uint32_t*)cur_stg.p, (uint32_t*)stg.p, stg_count(), scap,
+                             clear_drec ? (double*)d_rec.p : nullptr, n2};
     }
 };
 
@@ -646,10 +651,13 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         launch_fill_u32(stream, (uint32_t*)f->imp_acc.p, 2 * f->n, 0u);
         launch_fill_u32(stream, (uint32_t*)imp_max, f->n, 0u);
     }
+    // the compositing clears the backward's accumulator (sized here; a fixed
+    // workspace already holds it)
+    if ((s = grow_drec(f))) return s;
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_FWD);
         f->have_stats = st->stats != 0 && !imp;
-        launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st, images,
+        launch_hybrid_fwd(stream, f->cfg_fwd, (const float*)f->srec.p, f->hybrid(true), f->views, f->st, images,
                           (float*)f->t_final.p, (int32_t*)f->last.p, f->have_stats ? (int32_t*)f->stats.p : nullptr,
                           f->have_stats ? (int32_t*)f->evals.p : nullptr, queue, ctx->num_cus, f->n,
                           imp ? (double*)f->imp_acc.p : nullptr, imp ? (uint32_t*)imp_max : nullptr);
@@ -658,6 +666,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     MGS_CHECK_LAUNCH(ctx);
     if (t_final_out)
         MGS_HIP(ctx, hipMemcpyAsync(t_final_out, f->t_final.p, (size_t)P * 4, hipMemcpyDeviceToDevice, stream));
+    f->drec_zero = true;
     f->have_forward = true;
     return MGS_OK;
 }
@@ -694,11 +703,12 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     if ((s = grow_drec(f)) || (s = grow(ctx, f->dm_acc, (size_t)f->n * 8 + 8))) return s;
     uint32_t* queue = nullptr;
     if (!f->drec_zero) {
-        // +0.0 in every double, once per allocation: afterwards the
-        // projection backward leaves the rows it read at zero
+        // +0.0 in every double: normally the forward compositing has cleared
+        // the accumulator; a second backward after one forward, or a new
+        // allocation, fills it here
         launch_fill_u32(stream, (uint32_t*)f->d_rec.p, f->d_rec.bytes / 4, 0u);
-        f->drec_zero = true;
     }
+    f->drec_zero = false;  // this backward accumulates into it
     launch_fill_u32(stream, (uint32_t*)f->dm_acc.p, 2 * f->n, 0u);
     if (f->persistent) {
         queue = (uint32_t*)f->queue.p;

@@ -836,6 +836,8 @@ struct HybridLists {
     uint2* stg;                // null: the backward merges again
     uint32_t* stg_count;
     uint64_t stg_cap;
+    double* drec_clear;        // the backward's FP64 accumulator, cleared by the forward
+    uint64_t drec_clear_n2;    // its size in pairs of doubles
 };
 
 // Both compositing kernels are built for at least five waves per SIMD (at
@@ -985,6 +987,17 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
             __syncthreads();  // the next batch overwrites the LDS
         }
         if (t == 0) hl.nbatch[tile] = (uint32_t)b;
+        if (hl.drec_clear) {
+            // the backward's FP64 accumulator of per-record gradients is
+            // cleared here, one slice per tile: this kernel is bound by VALU
+            // issue and leaves HBM bandwidth idle, the projection backward
+            // (HBM-bound) then only reads the rows
+            const uint64_t per = (hl.drec_clear_n2 + views.total_tiles - 1) / views.total_tiles;
+            const uint64_t q0 = (uint64_t)tile * per;
+            const uint64_t q1 = min(q0 + per, hl.drec_clear_n2);
+            double2* z = reinterpret_cast<double2*>(hl.drec_clear);
+            for (uint64_t q = q0 + (uint64_t)t; q < q1; q += NT) z[q] = make_double2(0.0, 0.0);
+        }
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             if (!inside[i]) continue;
@@ -1255,6 +1268,8 @@ HybridLists make_lists(const HybridBuffers& b) {
     hl.stg = reinterpret_cast<uint2*>(b.stg);
     hl.stg_count = b.stg_count;
     hl.stg_cap = b.stg_cap;
+    hl.drec_clear = b.drec_clear;
+    hl.drec_clear_n2 = b.drec_clear_n2;
     return hl;
 }
 

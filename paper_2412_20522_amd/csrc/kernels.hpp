@@ -18,8 +18,9 @@ void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
                         uint32_t* rkeys = nullptr, uint32_t* rvals = nullptr);
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out);
-// Whole path: FP64 per-record gradients, which are set back to zero as they
-// are read; dm_acc (FP64 mask gradients) is rounded into out.d_masks.
+// Whole path: FP64 per-record gradients (zeroed by the forward compositing
+// before the backward accumulates them); dm_acc (FP64 mask gradients) is
+// rounded into out.d_masks.
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                           double* d_rec, const double* dm_acc, const mgs_gradients& out,
                           const uint32_t* tiles);
@@ -105,6 +106,8 @@ struct HybridBuffers {
     uint32_t* stg;               // [stg_cap, 2] staged entries; null: the backward merges again
     uint32_t* stg_count;         // device counter of staged entries (zeroed before the forward)
     uint64_t stg_cap;
+    double* drec_clear;          // optional: FP64 per-record gradient accumulator the forward clears
+    uint64_t drec_clear_n2;      // its size in pairs of doubles
 };
 // stats [P, 4] (examined, blended, blended with mask 0, last + 1) and evals
 // [P, 4] (evaluated, evaluated up to the last blended entry, 0, 0) are

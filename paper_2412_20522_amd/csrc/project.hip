@@ -629,7 +629,7 @@ void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSe
 
 void launch_project_bwd64(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                           double* d_rec, const double* dm_acc, const mgs_gradients& out, const uint32_t* tiles) {
-    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, d_rec, out, tiles);
+    project_bwd_t<double>(stream, g, views, st, d_rec, dm_acc, nullptr, out, tiles);
 }
 
 }  // namespace mgs
