@@ -80,8 +80,11 @@ __device__ __forceinline__ Rect rect_of(float u, float v, float radius, const De
         return q;
     }
     const double ud = u, vd = v, rd = radius;
-    const double fx0 = floor((ud - rd) / st.tile_w), fx1 = floor((ud + rd) / st.tile_w);
-    const double fy0 = floor((vd - rd) / st.tile_h), fy1 = floor((vd + rd) / st.tile_h);
+    // tile sizes are powers of two: scaling by 2^-k is exact, so it equals
+    // the FP64 division by the tile size
+    const int kw = __builtin_ctz((unsigned)st.tile_w), kh = __builtin_ctz((unsigned)st.tile_h);
+    const double fx0 = floor(ldexp(ud - rd, -kw)), fx1 = floor(ldexp(ud + rd, -kw));
+    const double fy0 = floor(ldexp(vd - rd, -kh)), fy1 = floor(ldexp(vd + rd, -kh));
     // clamp into the grid before converting (values can be far outside it)
     q.x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.grid_w);
     q.y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.grid_h);

@@ -212,14 +212,14 @@ __device__ __forceinline__ RowCull row_prep(const float4& A, const float4& B, co
 
 // Columns [lo, hi] (within [x0, x1]) of cell row cy, cells of cw x ch pixels
 // (powers of two), that the entry can reach; false if none.
-__device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int ch, int x0, int x1,
-                                          const DevView& cam, int& lo, int& hi) {
+__device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int ch, int x0, int x1, int width,
+                                          int height, int& lo, int& hi) {
 #pragma clang fp contract(off)
     lo = x0;
     hi = x1;
     if (p.mode == 1) return true;
     if (p.mode == 2) return false;
-    const float Y0 = (float)(cy * ch) + 0.5f, Y1 = (float)min((cy + 1) * ch, cam.height) - 0.5f;
+    const float Y0 = (float)(cy * ch) + 0.5f, Y1 = (float)min((cy + 1) * ch, height) - 0.5f;
     const float e0 = fmaxf(Y0 - p.v, -p.H), e1 = fminf(Y1 - p.v, p.H);
     if (!(e0 <= e1)) return false;
     const float eR = fminf(fmaxf(p.eyR, e0), e1), eL = fminf(fmaxf(-p.eyR, e0), e1);
@@ -228,7 +228,7 @@ __device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int 
     const float sL = sqrtf(fmaxf(0.f, (p.cut - gL * eL) * p.inva));
     const float xhi = p.u + (sR - p.beta * eR) + 1e-3f;
     const float xlo = p.u - (sL + p.beta * eL) - 1e-3f;
-    if (!(xlo <= (float)cam.width - 0.5f && xhi >= 0.5f)) return false;
+    if (!(xlo <= (float)width - 0.5f && xhi >= 0.5f)) return false;
     // cell cx spans pixel centres [cx cw + 0.5, (cx + 1) cw - 0.5]
     const float icw = 1.f / (float)cw;
     const float flo = fmaxf(ceilf((xlo + 0.5f) * icw - 1.f), (float)x0);
@@ -257,7 +257,7 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 // (tiles or regions, after culling) of every position, and per workgroup the
 // number of wide records and of their region entries (part[b], part[nb + b]).
 // A record without tiles (key all ones, sorted last in its view) is listed
-// nowhere: it gets no copy, which nothing reads.
+// nowhere: it gets no copy, which nothing uses.
 __global__ void __launch_bounds__(256) permute_classify_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ skeys, const float4* __restrict__ rec,
     int64_t R, int64_t n, ViewSet views, DevSettings st, uint32_t* __restrict__ cnt_out,
@@ -271,11 +271,13 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     uint32_t c = 0;
     bool wide = false;
     int vi = 0;
-    if (live && skeys[i] == 0xffffffffu) {
+    // both loads of the position in one round trip, then the record
+    const uint32_t key = live ? skeys[i] : 0xffffffffu;
+    const uint32_t r = live ? order[i] : 0u;
+    if (live && key == 0xffffffffu) {
         wide_flag[i] = 0u;
     } else if (live) {
         // one gather of the record (radius in B.w, tile count in C.w)
-        const uint32_t r = order[i];
         A = rec[3 * (size_t)r];
         B = rec[3 * (size_t)r + 1];
         uint4 C = reinterpret_cast<const uint4*>(rec)[3 * (size_t)r + 2];
@@ -294,12 +296,12 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     uint64_t mask = 0;
     if (st.tile_cull && cl.area > 0) {
         const RowCull rc = row_prep(A, B, st);
-        const DevView& cam = views.v[vi];
+        const int width = views.v[vi].width, height = views.v[vi].height;  // loaded once, not per row
         const int rows = (int)(cl.area / (uint32_t)cl.w);
         cnt = 0;
         for (int ry = 0; ry < rows; ++ry) {
             int lo, hi;
-            if (!row_cells(rc, cl.y0 + ry, cl.cw, cl.ch, cl.x0, cl.x0 + cl.w - 1, cam, lo, hi)) continue;
+            if (!row_cells(rc, cl.y0 + ry, cl.cw, cl.ch, cl.x0, cl.x0 + cl.w - 1, width, height, lo, hi)) continue;
             cnt += (uint32_t)(hi - lo + 1);
             if (cl.area <= CULL_MAX) {
                 // bits ry w + (lo - x0) .. ry w + (hi - x0)
@@ -387,30 +389,46 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t r) {
     return pos;
 }
 
+// Inclusive maximum scan over the 64 lanes of a wave, for values >= -1:
+// shifts within each 16-lane row, then the broadcasts of lane 15 into rows
+// 1 and 3 and of lane 31 into rows 2 and 3 (a lane with no source keeps -1).
+__device__ __forceinline__ int wave_max_scan(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));  // row_shr 1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));  // row_shr 2
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));  // row_shr 4
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));  // row_shr 8
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));  // row_bcast 15
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));  // row_bcast 31
+    return x;
+}
+
 // List entries in sorted-position order: cell keys (tile or region ids) as
 // keys, positions as values, for the cells the classification counted.  The
-// outputs of a workgroup's records are contiguous, so the workgroup walks
-// them slot by slot with every lane busy and consecutive lanes writing
-// consecutive entries: slot -> record by binary search over the workgroup's
-// prefix of counts, record-local rank -> cell by selecting the rank-th bit of
-// the cull mask (the rank itself without culling).  Culled rectangles of more
-// than CULL_MAX cells re-derive their rows, one row per lane.  Writes never
-// leave a record's counted slots; a slot the emission does not fill gets
-// KEY_NONE.
+// outputs of a wave's records are contiguous, so each wave walks them 64
+// slots at a time with every lane busy and consecutive lanes writing
+// consecutive entries.  The owner of a slot is the last record whose first
+// slot is at or before it: every record marks its first slot (records with
+// entries start at distinct slots), and a running maximum over the slots
+// fills the rest.  Record-local rank -> cell by selecting the rank-th bit of
+// the cull mask (the rank itself without culling).  Culled rectangles of
+// more than CULL_MAX cells re-derive their rows, one row per lane.  Writes
+// never leave a record's counted slots; a slot the emission does not fill
+// gets KEY_NONE.  No step waits on another wave.
 __global__ void __launch_bounds__(256) duplicate_kernel(
     const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
     const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views,
     DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
     uint32_t* __restrict__ flags) {
-    __shared__ uint32_t s_pref[257];
+    __shared__ uint32_t s_first[256];
     __shared__ uint32_t s_rel[256];
     __shared__ unsigned long long s_mask[256];
     __shared__ uint2 s_geo[256];
-    __shared__ uint32_t s_wsum[4];
+    __shared__ int s_own[256];
     const int t = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t i = i0 + t;
     const int lane = lane_id();
+    const int wb = t & ~63;  // the wave's first thread
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
     int64_t off = 0;
     uint32_t cnt = 0;
@@ -418,62 +436,71 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     bool wide = false;
     uint64_t mask = 0;
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
-    if (i < R && (cnt = cnt_sorted[i]) != 0) {
+    const bool cull = st.tile_cull != 0;
+    if (i < R) {
+        // every load of the position at once (one memory round trip); the
+        // copy and the mask of a position without entries are not used
+        cnt = cnt_sorted[i];
         off = offsets[i];
-        vi = (int)((uint32_t)i / (uint32_t)n);  // positions are below 2^32
         wide = wide_flag[i] != 0;
         A = srec[3 * i];
         B = srec[3 * i + 1];
-        cl = cells_of(A, B, wide, views.v[vi], st);
+        if (cull) mask = tmask[i];
     }
-    const bool cull = st.tile_cull != 0;
-    if (cull && cnt > 0 && cl.area <= CULL_MAX) mask = tmask[i];
+    // the record's view, loaded once: cell (x0 + rx, y0 + ry) has key
+    // key0 + ry stride + rx
+    uint32_t key0 = 0, stride = 0;
+    int width = 0, height = 0;
+    if (cnt != 0) {
+        vi = (int)((uint32_t)i / (uint32_t)n);  // positions are below 2^32
+        const DevView& cam = views.v[vi];
+        cl = cells_of(A, B, wide, cam, st);
+        key0 = cell_key(wide, cl.x0, cl.y0, cam, views);
+        stride = (uint32_t)(wide ? cam.reg_w : cam.grid_w);
+        width = cam.width;
+        height = cam.height;
+    }
+    if (cnt == 0 || cl.area > CULL_MAX) mask = 0;
     const bool flat = cnt > 0 && (!cull || cl.area <= CULL_MAX);
     const int64_t base = offsets[i0];  // start of the workgroup's output (i0 < R)
     bool overflow = false;
     {
+        // first slot of each record among the wave's flat slots
         uint32_t x = flat ? cnt : 0u;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const uint32_t y = __shfl_up(x, d);
             if (lane >= d) x += y;
         }
-        const int wid = t >> 6;
-        if (lane == 63) s_wsum[wid] = x;
+        const uint32_t first = x - (flat ? cnt : 0u);
+        const uint32_t total = (uint32_t)__shfl((int)x, 63);
+        s_first[t] = first;
         s_rel[t] = (uint32_t)(off - base);
         s_mask[t] = mask;
-        s_geo[t] = make_uint2((uint32_t)cl.x0 | ((uint32_t)cl.y0 << 16),
-                              (uint32_t)cl.w | (wide ? 0x1000u : 0u) | ((uint32_t)vi << 16));
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-            if (w < wid) before += s_wsum[w];
-            total += s_wsum[w];
-        }
-        s_pref[t] = before + x - (flat ? cnt : 0u);
-        if (t == 0) s_pref[blockDim.x] = total;
-        __syncthreads();
-        const int nrec = (int)blockDim.x;
-        for (uint32_t e = (uint32_t)t; e < total; e += blockDim.x) {
-            int lo = 0, hi = nrec;  // owner k: s_pref[k] <= e < s_pref[k + 1]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_pref[mid] <= e) lo = mid;
-                else hi = mid;
-            }
-            const int k = lo;
-            const uint32_t r = e - s_pref[k];
+        s_geo[t] = make_uint2(key0, (uint32_t)cl.w | (stride << 16));
+        int carry = -1;
+        for (uint32_t w0 = 0; w0 < total; w0 += 64) {
+            // LDS operations of one wave complete in program order
+            s_own[t] = -1;
+            __builtin_amdgcn_wave_barrier();
+            if (flat && first >= w0 && first < w0 + 64u) s_own[wb + (int)(first - w0)] = lane;
+            __builtin_amdgcn_wave_barrier();
+            const int own = max(wave_max_scan(s_own[t]), carry);
+            carry = __builtin_amdgcn_readlane(own, 63);
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t e = w0 + (uint32_t)lane;
+            if (e >= total) continue;
+            const int k = wb + own;
+            const uint32_t r = e - s_first[k];
             const uint2 g = s_geo[k];
-            const int w = (int)(g.y & 0xfffu), kvi = (int)(g.y >> 16);
-            const bool kwide = (g.y & 0x1000u) != 0;
+            const uint32_t w = g.y & 0xffffu, kstride = g.y >> 16;
             const uint64_t km = s_mask[k];
             const int64_t o = base + (int64_t)s_rel[k] + (int64_t)r;
             uint32_t key = KEY_NONE;
             if (!cull || r < (uint32_t)__popcll(km)) {
                 const uint32_t j = cull ? select_bit(km, r) : r;
-                const uint32_t ry = j / (uint32_t)w, rx = j - ry * (uint32_t)w;
-                key = cell_key(kwide, (int)(g.x & 0xffffu) + (int)rx, (int)(g.x >> 16) + (int)ry, views.v[kvi],
-                               views);
+                const uint32_t ry = j / w, rx = j - ry * w;
+                key = g.x + ry * kstride + rx;
             }
             if (o < capacity) {
                 keys[o] = key;
@@ -492,18 +519,19 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         const uint32_t barea = __shfl(cl.area, src), bcnt = __shfl(cnt, src);
         const uint32_t bi = (uint32_t)__shfl((int)(uint32_t)i, src);
         const int bx0 = __shfl(cl.x0, src), by0 = __shfl(cl.y0, src), bw = __shfl(cl.w, src);
-        const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src), bvi = __shfl(vi, src);
-        const bool bwide = __shfl((int)wide, src) != 0;
+        const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src);
+        const int bwidth = __shfl(width, src), bheight = __shfl(height, src);
+        const uint32_t bkey0 = (uint32_t)__shfl((int)key0, src), bstride = (uint32_t)__shfl((int)stride, src);
         const int64_t bo = __shfl(off, src);
         const int64_t end = bo + bcnt;
-        const DevView& cam = views.v[bvi];
         const RowCull rc = row_prep(shfl4(A, src), shfl4(B, src), st);
         const int rows = (int)(barea / (uint32_t)bw);
         int64_t rbase = bo;
         for (int r0 = 0; r0 < rows && rbase < end; r0 += 64) {
             const int ry = r0 + lane;
             int lo = 0, hi = -1;
-            if (ry < rows && !row_cells(rc, by0 + ry, bcw, bch, bx0, bx0 + bw - 1, cam, lo, hi)) hi = lo - 1;
+            if (ry < rows && !row_cells(rc, by0 + ry, bcw, bch, bx0, bx0 + bw - 1, bwidth, bheight, lo, hi))
+                hi = lo - 1;
             if (ry >= rows) hi = lo - 1;
             const int nrow = hi - lo + 1;
             int incl = nrow;
@@ -515,7 +543,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
             int64_t o = rbase + (incl - nrow);
             for (int cx = lo; cx <= hi && o < end; ++cx, ++o) {
                 if (o < capacity) {
-                    keys[o] = cell_key(bwide, cx, by0 + ry, cam, views);
+                    keys[o] = bkey0 + (uint32_t)ry * bstride + (uint32_t)(cx - bx0);
                     vals[o] = bi;
                 } else {
                     overflow = true;

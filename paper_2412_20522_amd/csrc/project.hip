@@ -288,8 +288,10 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             count = (uint32_t)(cam.grid_w * cam.grid_h);
         } else {
             const double ud = o.u, vd = o.v, rd = o.radius;
-            double x0 = floor((ud - rd) / st.tile_w), x1 = floor((ud + rd) / st.tile_w);
-            double y0 = floor((vd - rd) / st.tile_h), y1 = floor((vd + rd) / st.tile_h);
+            // tile sizes are powers of two: ldexp by -log2 equals the division
+            const int kw = __builtin_ctz((unsigned)st.tile_w), kh = __builtin_ctz((unsigned)st.tile_h);
+            double x0 = floor(ldexp(ud - rd, -kw)), x1 = floor(ldexp(ud + rd, -kw));
+            double y0 = floor(ldexp(vd - rd, -kh)), y1 = floor(ldexp(vd + rd, -kh));
             x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
             x1 = fmin(x1, (double)(cam.grid_w - 1)); y1 = fmin(y1, (double)(cam.grid_h - 1));
             count = (x0 <= x1 && y0 <= y1) ? (uint32_t)((x1 - x0 + 1.0) * (y1 - y0 + 1.0)) : 0u;

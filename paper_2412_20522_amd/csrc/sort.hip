@@ -12,10 +12,9 @@
 //    two passes) yields the same (tile, depth, record) order with a fraction
 //    of the memory traffic, since K is often 100x the record count.
 //
-// The sort is reduce-then-scan (per-block digit histograms, a device-wide
-// scan of the digit-major histogram, then a stable scatter); it has no
-// inter-block spin waits, so it needs no forward-progress guarantee between
-// workgroups.
+// The sort is reduce-then-scan (per-block digit histograms, a scan of each
+// digit's row of them, then a stable scatter); it has no inter-block spin
+// waits, so it needs no forward-progress guarantee between workgroups.
 #include <mutex>
 
 #include "common.hpp"
@@ -221,16 +220,31 @@ __device__ __forceinline__ uint32_t digit_of(KeyT k, int shift) {
 // Segments: the keys may form consecutive segments of seg_len keys each
 // (the last one shorter), sorted each on its own: block b works in segment
 // b / nbs, on the (b % nbs)-th chunk of it, and the histograms are laid out
-// (segment, digit, block), so that one exclusive scan over them gives every
-// block's output position for each digit.  With one segment (seg_len >= K,
-// nbs = nb) this is the plain digit-major layout hist[d * nb + block].
+// (segment, digit, block).  A block's output position for digit d is the
+// segment's start (seg * seg_len), plus the segment's counts of the digits
+// below d, plus the counts of d in the segment's earlier blocks: the
+// row scan gives the last term and the row totals, the scatter adds the
+// rest.  With one segment (seg_len >= K, nbs = nb) the layout is the plain
+// digit-major hist[d * nb + block].
 struct SortSeg {
     int64_t seg, bl, beg, end;  // segment, block within it, chunk [beg, end)
 };
-__device__ __forceinline__ SortSeg sort_seg(int64_t K, int64_t seg_len, int64_t nbs, int64_t chunk) {
+
+// Logical block of this workgroup.  Workgroups are dealt to the 8 XCDs in
+// turn (workgroup i to XCD i mod 8); the mapping gives every XCD one run of
+// consecutive logical blocks, so the digit runs that neighbouring blocks
+// scatter next to each other are written through the same L2.
+__device__ __forceinline__ int64_t sort_block(int64_t nb) {
+    const int64_t i = (int64_t)blockIdx.x;
+    const int64_t q = nb >> 3, r = nb & 7, x = i & 7;
+    return x * q + (x < r ? x : r) + (i >> 3);
+}
+
+__device__ __forceinline__ SortSeg sort_seg(int64_t K, int64_t seg_len, int64_t nbs, int64_t chunk, int64_t nb) {
     SortSeg s;
-    s.seg = (int64_t)blockIdx.x / nbs;
-    s.bl = (int64_t)blockIdx.x - s.seg * nbs;
+    const int64_t b = sort_block(nb);
+    s.seg = b / nbs;
+    s.bl = b - s.seg * nbs;
     const int64_t sbeg = s.seg * seg_len;
     const int64_t send = min(sbeg + seg_len, K);
     s.beg = sbeg + s.bl * chunk;
@@ -258,7 +272,7 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
-    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk);
+    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk, nb);
     const int64_t cbeg = sg.beg, cend = sg.end;
     for (int64_t base = cbeg; base < cend; base += STILE)
 #pragma unroll
@@ -302,11 +316,42 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     hist[(sg.seg * RADIX + d) * nbs + sg.bl] = s;
 }
 
+// Exclusive prefix of every (segment, digit) row of the block histograms
+// over the row's blocks, and the row's total: one workgroup per row, each
+// thread over a run of at most SORT_BLOCKS / NT consecutive blocks.
+constexpr int ROW_PER_THREAD = (int)(SORT_BLOCKS / NT);
+__global__ void __launch_bounds__(NT) radix_rowscan_kernel(const uint32_t* __restrict__ hist, int64_t nbs,
+                                                            uint32_t* __restrict__ row_pre,
+                                                            uint32_t* __restrict__ row_tot) {
+    __shared__ uint32_t sh[NT / 64];
+    const int64_t row = blockIdx.x;
+    const uint32_t* h = hist + row * nbs;
+    uint32_t* p = row_pre + row * nbs;
+    const int per = (int)((nbs + NT - 1) / NT);
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    uint32_t v[ROW_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < ROW_PER_THREAD; ++j) {
+        v[j] = (j < per && b0 + j < nbs) ? h[b0 + j] : 0u;
+        s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, sh, &tot);
+#pragma unroll
+    for (int j = 0; j < ROW_PER_THREAD; ++j) {
+        if (j < per && b0 + j < nbs) p[b0 + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) row_tot[row] = tot;
+}
+
 template <typename KeyT>
 __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KeyT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
-    const uint32_t* __restrict__ hist_scan, int64_t nb, int64_t chunk, int64_t seg_len, int64_t nbs) {
+    const uint32_t* __restrict__ row_pre, const uint32_t* __restrict__ row_tot, int64_t nb, int64_t chunk,
+    int64_t seg_len, int64_t nbs) {
     constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
     __shared__ KeyT sk[STILE];
     __shared__ uint32_t sv[STILE];
@@ -317,12 +362,17 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
 
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
-    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk);
+    const SortSeg sg = sort_seg(K, seg_len, nbs, chunk, nb);
     const int64_t cbeg = sg.beg, cend = sg.end;
     if (cbeg >= cend) return;  // uniform over the block
     const int w = threadIdx.x >> 6, lane = lane_id();
     // global start of each digit for this chunk, advanced after every sub-tile
-    gstart[threadIdx.x] = hist_scan[(sg.seg * RADIX + threadIdx.x) * nbs + sg.bl];
+    {
+        const int64_t row = sg.seg * RADIX + threadIdx.x;
+        uint32_t tot;
+        const uint32_t below = block_exclusive_scan(row_tot[row], scan_sh, &tot);
+        gstart[threadIdx.x] = (uint32_t)(sg.seg * seg_len) + below + row_pre[row * nbs + sg.bl];
+    }
     for (int64_t base = cbeg; base < cend; base += STILE) {
     const int nvalid = (int)min((int64_t)STILE, cend - base);
     for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
@@ -545,11 +595,11 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
     const int64_t nbs = (ntiles + tiles_per_block - 1) / tiles_per_block;
     const int64_t nb = nseg * nbs;
     const int64_t seg_arg = segmented ? seg_len : INT64_MAX / 4;
-    const int64_t hn = nb * RADIX;
+    static_assert(SORT_BLOCKS % NT == 0, "row scan: whole runs per thread");
+    const int64_t hn = nb * RADIX, rows = nseg * RADIX;
     uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
-    uint32_t* hist_scan = hist + hn;
-    char* scan_tmp = reinterpret_cast<char*>(hist_scan + hn);
-    scan_tmp = reinterpret_cast<char*>(((uintptr_t)scan_tmp + 255) & ~(uintptr_t)255);
+    uint32_t* row_pre = hist + hn;
+    uint32_t* row_tot = row_pre + hn;
     KeyT* kin = keys;
     uint32_t* vin = vals;
     KeyT* kout = keys_alt;
@@ -557,9 +607,11 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         hipLaunchKernelGGL(radix_upsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift,
                            hist, nb, chunk, seg_arg, nbs);
-        launch_scan_u32(stream, hist, hn, hist_scan, nullptr, scan_tmp);
+        hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)rows), dim3(NT), 0, stream, (const uint32_t*)hist,
+                           nbs, row_pre, row_tot);
         hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout,
-                           K, K_dev, shift, (const uint32_t*)hist_scan, nb, chunk, seg_arg, nbs);
+                           K, K_dev, shift, (const uint32_t*)row_pre, (const uint32_t*)row_tot, nb, chunk, seg_arg,
+                           nbs);
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
         *out_in_alt = !*out_in_alt;
@@ -623,7 +675,7 @@ size_t sort_scratch_bytes(int64_t K) {
     const int64_t nb = std::min<int64_t>(((K > 0 ? K : 1) + SORT_TILE_MIN - 1) / SORT_TILE_MIN + MAX_SORT_SEGMENTS,
                                          SORT_BLOCKS);
     const int64_t hist = nb * RADIX;
-    return (size_t)hist * sizeof(uint32_t) * 2 + scan_scratch_bytes(hist) + 1024;
+    return (size_t)(2 * hist + MAX_SORT_SEGMENTS * RADIX) * sizeof(uint32_t) + 1024;
 }
 
 void launch_radix_sort(hipStream_t stream, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
