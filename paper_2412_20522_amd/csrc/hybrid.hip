@@ -178,6 +178,9 @@ __device__ __forceinline__ uint32_t cell_key(bool wide, int cx, int cy, const De
 // row.  Every operation is written out and contraction is off, so the
 // classification (which counts) and the duplication (which emits) take
 // identical decisions; culled cells contribute nothing to any pixel.
+// Reciprocals and square roots are the hardware's single instructions (about
+// one ulp): their error is orders of magnitude inside the margins (1e-3 of
+// the cut, 1e-3 pixel), so the test stays conservative.
 struct RowCull {
     float u, v, beta, gamma, inva, cut, H, eyR;
     int mode;  // 0: cull, 1: every cell (no finite cut), 2: no cell
@@ -203,10 +206,10 @@ __device__ __forceinline__ RowCull row_prep(const float4& A, const float4& B, co
         p.cut = fmaf(1e-3f, 1.f + fabsf(cut), cut);
         if (!(p.cut >= 0.f)) p.mode = 2;
     }
-    p.inva = 1.f / a;
-    p.H = sqrtf(p.cut / p.gamma);
+    p.inva = __builtin_amdgcn_rcpf(a);
+    p.H = __builtin_amdgcn_sqrtf(p.cut * __builtin_amdgcn_rcpf(p.gamma));
     const float D = fmaf(a * p.beta, p.beta, p.gamma);  // c = gamma + a beta^2
-    p.eyR = -p.beta * sqrtf(p.cut * a / (p.gamma * D));
+    p.eyR = -p.beta * __builtin_amdgcn_sqrtf(p.cut * a * __builtin_amdgcn_rcpf(p.gamma * D));
     return p;
 }
 
@@ -224,13 +227,13 @@ __device__ __forceinline__ bool row_cells(const RowCull& p, int cy, int cw, int 
     if (!(e0 <= e1)) return false;
     const float eR = fminf(fmaxf(p.eyR, e0), e1), eL = fminf(fmaxf(-p.eyR, e0), e1);
     const float gR = p.gamma * eR, gL = p.gamma * eL;
-    const float sR = sqrtf(fmaxf(0.f, (p.cut - gR * eR) * p.inva));
-    const float sL = sqrtf(fmaxf(0.f, (p.cut - gL * eL) * p.inva));
+    const float sR = __builtin_amdgcn_sqrtf(fmaxf(0.f, (p.cut - gR * eR) * p.inva));
+    const float sL = __builtin_amdgcn_sqrtf(fmaxf(0.f, (p.cut - gL * eL) * p.inva));
     const float xhi = p.u + (sR - p.beta * eR) + 1e-3f;
     const float xlo = p.u - (sL + p.beta * eL) - 1e-3f;
     if (!(xlo <= (float)width - 0.5f && xhi >= 0.5f)) return false;
     // cell cx spans pixel centres [cx cw + 0.5, (cx + 1) cw - 0.5]
-    const float icw = 1.f / (float)cw;
+    const float icw = ldexpf(1.f, -__builtin_ctz((unsigned)cw));  // exact: cw is a power of two
     const float flo = fmaxf(ceilf((xlo + 0.5f) * icw - 1.f), (float)x0);
     const float fhi = fminf(floorf((xhi - 0.5f) * icw), (float)x1);
     if (!(flo <= fhi)) return false;
@@ -499,7 +502,10 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
             uint32_t key = KEY_NONE;
             if (!cull || r < (uint32_t)__popcll(km)) {
                 const uint32_t j = cull ? select_bit(km, r) : r;
-                const uint32_t ry = j / w, rx = j - ry * w;
+                // with culling j < 64 and w <= 64: (j + 1/2) / w is at least
+                // 1/128 from an integer, far beyond the product's rounding
+                const uint32_t ry = cull ? (uint32_t)(((float)j + 0.5f) * __builtin_amdgcn_rcpf((float)w)) : j / w;
+                const uint32_t rx = j - ry * w;
                 key = g.x + ry * kstride + rx;
             }
             if (o < capacity) {
