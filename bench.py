@@ -77,7 +77,9 @@ def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
     k3 = 3 * (sh_deg + 1) ** 2
     if stage == "composite_fwd":
         slots = SLOTS_FILTER * counts["evaluated"] + SLOTS_BLEND * counts["blended"]
-        return 48 * K + 20 * P, slots
+        # staged records, per-pixel outputs, and the clearing of the
+        # backward's FP64 accumulator (9 doubles per record)
+        return 48 * K + 20 * P + 72 * R, slots
     if stage == "composite_bwd":
         vis = counts["blended"] - counts["blended_masked"]
         slots = (SLOTS_FILTER * counts["bwd_evaluated"] + SLOTS_BWD_VISIBLE * vis +
@@ -87,13 +89,22 @@ def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
         # stable pass over 32-bit cell keys and 32-bit values: read and write both
         return 16 * K * fs["sort_passes"], 0
     if stage == "depth_sort":
-        return 16 * R * 4 + R * 12, 0
+        # 4 passes over 32-bit keys and values (read and written), then the
+        # classification: order and key read, one record gathered (48 B),
+        # the sorted copy (48 B), count, wide flag and cull mask written
+        return 16 * R * 4 + R * (8 + 48 + 48 + 4 + 4 + 8), 0
     if stage == "project":
-        return n * 4 * (11 + k3 + 1) + R * (48 + 12), 0
+        # parameters read once; record (48 B), depth, radius, tile count,
+        # depth key and order written per record
+        return n * 4 * (11 + k3 + 1) + R * (48 + 5 * 4), 0
     if stage == "project_bwd":
-        return n * 4 * (11 + k3) + R * 36 + n * 4 * (10 + k3), 0
+        # parameters read, the FP64 gradient row (9 doubles) read per record,
+        # parameter gradients written
+        return n * 4 * (11 + k3) + R * 72 + n * 4 * (10 + k3), 0
     if stage == "duplicate":
-        return R * 16 + K * 12, 0
+        # per position: count, offset, wide flag, cull mask and the record's
+        # geometry (32 B); per list entry a key and a value written
+        return R * (4 + 4 + 4 + 8 + 32) + K * 8, 0
     if stage == "scan":
         return R * 8, 0
     if stage == "ranges":
