@@ -24,6 +24,9 @@ ARCH = "gfx950"
 COMMON_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-munsafe-fp-atomics",
+    # no lane-combining rewrite of atomics: the library's atomics are issued
+    # by one lane, or by lanes with distinct addresses
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
