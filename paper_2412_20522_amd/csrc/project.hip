@@ -341,8 +341,9 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
     // chain and the SH colour (coefficients and their gradients) are never
     // live together: one pass holding both needs more than 256 registers,
     // which leaves one wave per SIMD.  The first pass reads each valid
-    // view's whole gradient row once (and clears it), keeping the colour
-    // gradients in LDS (3 floats per view and thread) for the second.
+    // view's whole gradient row once (and clears it when asked to), keeping
+    // the colour gradients in LDS (3 floats per view and thread) for the
+    // second.
     extern __shared__ float s_dcol[];  // [n_views][3][blockDim.x]
     const int tid = threadIdx.x, nth = blockDim.x;
     uint32_t valid = 0;
