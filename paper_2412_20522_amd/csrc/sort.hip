@@ -37,6 +37,7 @@ constexpr int NT = 256;
 constexpr int IPT = 16;
 constexpr int TILE = NT * IPT;  // 4096 elements per block
 constexpr int RADIX = 256;
+static_assert(NT == RADIX, "one thread per digit in the histogram and scatter steps");
 constexpr int64_t SORT_BLOCKS = 2048;  // 8 workgroups per CU on a 256-CU device
 
 template <typename T>
