@@ -954,7 +954,15 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                 cused += (uint32_t)bt.M;
             }
             for (int j = 0; j < bt.M; ++j) {
-                if (!__any(active)) break;
+                // the wave leaves the batch once all its pixels are done,
+                // tested every 16 entries (a done pixel's slot costs only
+                // its skip; a test per entry costs more than it saves)
+                if ((j & 15) == 0) {
+                    active = false;
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) active |= !done[i];
+                    if (!__any(active)) break;
+                }
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
                 const int k = m + __float_as_int(B.w);  // index in the tile's full list
                 float isum = 0.f, imax = 0.f;
@@ -995,10 +1003,10 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                         atomicMax(imp_max + g, __float_as_uint(wm));
                     }
                 }
-                active = false;
-#pragma unroll
-                for (int i = 0; i < PPT; ++i) active |= !done[i];
             }
+            active = false;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) active |= !done[i];
             if (hl.stg) {
                 if (t == 0) {
                     const uint32_t off = (uint64_t)my_off + (uint64_t)bt.M <= hl.stg_cap ? my_off : 0xffffffffu;
