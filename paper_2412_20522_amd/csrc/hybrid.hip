@@ -911,7 +911,9 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         const DevView& cam = views.v[tg.vi];
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
         int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT], nev[PPT], nev_last[PPT];
-        bool done[PPT], inside[PPT];
+        // done as a full int (0 / 1): tested with one compare per slot and entry
+        int done[PPT];
+        bool inside[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
             int x, y;
@@ -924,7 +926,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
             last[i] = -1;
             stopk[i] = -1;
             nblend[i] = nmasked[i] = nev[i] = nev_last[i] = 0;
-            done[i] = !inside[i];
+            done[i] = inside[i] ? 0 : 1;
         }
         const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
         const uint2 r1 = hl.ranges[tile];
@@ -937,7 +939,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         while (i1 < e1 || i2 < e2) {
             bool active = false;
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) active |= !done[i];
+            for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
             const Batch bt = merge_batch(L, hl.vals, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, cam, st);
@@ -960,7 +962,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                 if ((j & 15) == 0) {
                     active = false;
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) active |= !done[i];
+                    for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
                     if (!__any(active)) break;
                 }
                 const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
@@ -968,14 +970,14 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                 float isum = 0.f, imax = 0.f;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
-                    if (done[i]) continue;
+                    if (done[i] != 0) continue;
                     if (STATS) ++nev[i];
                     Eval e;
                     if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     const float ma = B.z * e.alpha;
                     const float test = T[i] * (1.f - ma);
                     if (test < st.t_min) {
-                        done[i] = true;
+                        done[i] = 1;
                         stopk[i] = k;
                         continue;
                     }
@@ -1006,7 +1008,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
             }
             active = false;
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) active |= !done[i];
+            for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
             if (hl.stg) {
                 if (t == 0) {
                     const uint32_t off = (uint64_t)my_off + (uint64_t)bt.M <= hl.stg_cap ? my_off : 0xffffffffu;
