@@ -287,8 +287,10 @@ struct mgs_frame {
     // tile and region, per pixel
     DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, tmask,
         cls_part;
-    DevBuf keys, vals, keys_alt, vals_alt, ranges, caps, cur_off, nbatch, cur, cur_stg, stg, t_final, last, stats,
-        evals;
+    // order, order_b: the tile orders of the forward and the backward
+    // compositing (most expensive first), tcost: the forward's cost keys
+    DevBuf keys, vals, keys_alt, vals_alt, ranges, caps, tcost, order, order_b, cur_off, nbatch, cur, cur_stg, stg,
+        t_final, last, stats, evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
     DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     DevBuf imp_acc;  // FP64 sums of the importance forward
@@ -298,7 +300,8 @@ struct mgs_frame {
     bool drec_zero = false;
     // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
     // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
-    // 32, staged-entry counter (u32) at 192
+    // 32, staged-entry counter (u32) at 192; the tile orders' histogram and
+    // cursors (2 x 256 u32) from 256
     uint64_t* h_pinned = nullptr;  // read-back of misc
     uint32_t* keys_sorted() { return (uint32_t*)(sorted_in_alt ? keys_alt.p : keys.p); }
     uint32_t* vals_sorted() { return (uint32_t*)(sorted_in_alt ? vals_alt.p : vals.p); }
@@ -308,6 +311,7 @@ struct mgs_frame {
     uint64_t* wide_counts() { return (uint64_t*)((char*)misc.p + 16); }
     uint64_t* cur_need() { return (uint64_t*)((char*)misc.p + 24); }
     uint32_t* stg_count() { return (uint32_t*)((char*)misc.p + 192); }
+    uint32_t* order_hist() { return (uint32_t*)((char*)misc.p + 256); }
     HybridBuffers hybrid(bool clear_drec = false) {
         const uint64_t cap = reserved ? (uint64_t)cur_cap : (uint64_t)std::min(cur.bytes / 16, cur_stg.bytes / 8);
         const uint64_t scap = reserved ? (uint64_t)stg_cap : (uint64_t)(stg.bytes / 8);
@@ -316,7 +320,7 @@ struct mgs_frame {
         const uint64_t n2 = clear_drec ? ((uint64_t)R * DREC + 1) / 2 : 0;
         return HybridBuffers{vals_sorted(), (const uint32_t*)ranges.p, (uint32_t*)cur.p, (const uint32_t*)cur_off.p, (uint32_t*)nbatch.p, cur_need(), cap,
                              flags(), (uint32_t*)cur_stg.p, (uint32_t*)stg.p, stg_count(), scap,
-                             clear_drec ? (double*)d_rec.p : nullptr, n2};
+                             clear_drec ? (double*)d_rec.p : nullptr, n2, (const uint32_t*)order.p};
     }
 };
 
@@ -391,7 +395,7 @@ mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
         delete f;
         return fail(ctx, MGS_ERR_OOM, "pinned host allocation");
     }
-    if (grow(ctx, f->misc, 256) != MGS_OK) {
+    if (grow(ctx, f->misc, 256 + 2048) != MGS_OK) {
         (void)hipHostFree(f->h_pinned);
         delete f;
         return MGS_ERR_OOM;
@@ -406,7 +410,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
                       &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->tmask, &f->cls_part,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
-                      &f->caps,     &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
+                      &f->caps,     &f->tcost,     &f->order,     &f->order_b,   &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
                       &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
                       &f->misc,     &f->queue,     &f->sum_tmp,  &f->imp_acc};
@@ -539,6 +543,8 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
         (s = grow(ctx, f->cls_part, classify_parts_bytes(R))) ||
         (s = grow(ctx, f->ranges, (size_t)(T + NR) * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
+        (s = grow(ctx, f->tcost, (size_t)T * 4 + 4)) || (s = grow(ctx, f->order, (size_t)T * 4 + 4)) ||
+        (s = grow(ctx, f->order_b, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow(ctx, f->nbatch, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
         (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
@@ -635,7 +641,10 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     {
         StageTimer t(ctx, stream, MGS_STAGE_RANGES);
         launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T + NR, (uint32_t*)f->ranges.p);
-        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->views, (int)B, (uint32_t*)f->caps.p);
+        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->views, (int)B, (uint32_t*)f->caps.p,
+                          (uint32_t*)f->tcost.p);
+        // the forward takes the tiles with the longest lists first
+        launch_tile_order(stream, (const uint32_t*)f->tcost.p, (uint32_t)T, f->order_hist(), (uint32_t*)f->order.p);
         launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, f->cur_need(),
                         f->scan_tmp.p);
     }
@@ -714,9 +723,15 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         queue = (uint32_t*)f->queue.p;
         launch_fill_u32(stream, queue, 1, 0u);
     }
+    HybridBuffers hb = f->hybrid();
     {
         StageTimer t(ctx, stream, MGS_STAGE_COMPOSITE_BWD);
-        launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, f->hybrid(), f->views, f->st,
+        // the backward takes first the tiles where the forward took most
+        // batches (the backward replays them)
+        const uint32_t T = f->views.total_tiles;
+        launch_tile_order(stream, (const uint32_t*)f->nbatch.p, T, f->order_hist(), (uint32_t*)f->order_b.p);
+        hb.order = (const uint32_t*)f->order_b.p;
+        launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, hb, f->views, f->st,
                           (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
                           (double*)f->d_rec.p, (double*)f->dm_acc.p, queue, ctx->num_cus);
     }

@@ -576,7 +576,7 @@ __device__ __forceinline__ uint32_t region_of_tile(int tx, int ty, const DevView
 }
 
 __global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict__ ranges, ViewSet views, int batch,
-                                                          uint32_t* __restrict__ caps) {
+                                                          uint32_t* __restrict__ caps, uint32_t* __restrict__ cost) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= views.total_tiles) return;
     int vi = 0;
@@ -588,6 +588,60 @@ __global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict
     const uint32_t len1 = ranges[t].y - ranges[t].x;
     const uint32_t len2 = r2.y - r2.x;
     caps[t] = 2u * ((len1 + batch - 1) / batch + (len2 + batch - 1) / batch) + 2u;
+    // cost key of the forward's tile order: entries of the two lists, in
+    // units of 8
+    if (cost) cost[t] = min((len1 + len2) >> 3, 255u);
+}
+
+// Queue order of the tiles, most expensive first, so that the last tiles a
+// persistent launch takes are cheap (its tail is the cost of the tiles
+// still running when the queue runs dry).  A counting sort on a per-tile
+// cost key (0..255, descending): order_hist_kernel adds every workgroup's
+// histogram of the keys into hist[256]; order_place_kernel scans hist for the
+// bins' starts, takes for each of its bins a run of slots with one atomic
+// on cursor[256] and places its tiles in the run (ties in any order: the
+// tiles are independent).  hist and cursor are zero before the first kernel.
+__global__ void __launch_bounds__(256) order_hist_kernel(const uint32_t* __restrict__ key, uint32_t n,
+                                                          uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    const int t = threadIdx.x;
+    h[t] = 0u;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * 256u + (uint32_t)t;
+    if (i < n) atomicAdd(&h[255u - min(key[i], 255u)], 1u);
+    __syncthreads();
+    if (h[t]) atomicAdd(&hist[t], h[t]);
+}
+
+__global__ void __launch_bounds__(256) order_place_kernel(const uint32_t* __restrict__ key, uint32_t n,
+                                                           const uint32_t* __restrict__ hist,
+                                                           uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_cnt[256];
+    __shared__ uint32_t s_wsum[4];
+    const int t = threadIdx.x, lane = lane_id();
+    // bin starts: exclusive scan of hist
+    const uint32_t c = hist[t];
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wsum[t >> 6] = x;
+    s_cnt[t] = 0u;
+    __syncthreads();
+    uint32_t start = x - c;
+    for (int v = 0; v < (t >> 6); ++v) start += s_wsum[v];
+    // this workgroup's tiles per bin, and each tile's rank within its bin
+    const uint32_t i = blockIdx.x * 256u + (uint32_t)t;
+    const uint32_t b = i < n ? 255u - min(key[i], 255u) : 0u;
+    const uint32_t rank = i < n ? atomicAdd(&s_cnt[b], 1u) : 0u;
+    __syncthreads();
+    // a run of slots per non-empty bin
+    if (s_cnt[t]) s_base[t] = start + atomicAdd(&cursor[t], s_cnt[t]);
+    __syncthreads();
+    if (i < n) order[s_base[b] + rank] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -872,6 +926,7 @@ struct HybridLists {
     uint64_t stg_cap;
     double* drec_clear;        // the backward's FP64 accumulator, cleared by the forward
     uint64_t drec_clear_n2;    // its size in pairs of doubles
+    const uint32_t* order;     // optional: tile taken at each queue position
 };
 
 // Both compositing kernels are built for at least five waves per SIMD (at
@@ -905,8 +960,9 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
     const uint32_t chunk = queue ? STG_CHUNK_PERSISTENT : STG_CHUNK;
     uint32_t cbase = 0, cused = chunk;
     for (;;) {
-        const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
-        if (tile >= views.total_tiles) break;
+        const uint32_t q = next_tile(queue, &s_tile, blockIdx.x);
+        if (q >= views.total_tiles) break;
+        const uint32_t tile = hl.order ? hl.order[q] : q;
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
@@ -1087,8 +1143,9 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
     const float qscale = (lane == 2 || lane == 4) ? 0.5f * QSCALE : 1.f;
     if (*hl.cur_need > hl.cur_cap) return;  // the forward reported it
     for (;;) {
-        const uint32_t tile = next_tile(queue, &s_tile, blockIdx.x);
-        if (tile >= views.total_tiles) break;
+        const uint32_t q = next_tile(queue, &s_tile, blockIdx.x);
+        if (q >= views.total_tiles) break;
+        const uint32_t tile = hl.order ? hl.order[q] : q;
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         const int64_t rec_base = (int64_t)tg.vi * n;
@@ -1311,6 +1368,7 @@ HybridLists make_lists(const HybridBuffers& b) {
     hl.cur_stg = reinterpret_cast<uint2*>(b.cur_stg);
     hl.stg = reinterpret_cast<uint2*>(b.stg);
     hl.stg_count = b.stg_count;
+    hl.order = b.order;
     hl.stg_cap = b.stg_cap;
     hl.drec_clear = b.drec_clear;
     hl.drec_clear_n2 = b.drec_clear_n2;
@@ -1354,10 +1412,20 @@ void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_
                        keys, vals, capacity, flags);
 }
 
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps) {
+void launch_tile_order(hipStream_t stream, const uint32_t* key, uint32_t tiles, uint32_t* hist_cursor,
+                       uint32_t* order) {
+    if (tiles == 0) return;
+    launch_fill_u32(stream, hist_cursor, 512, 0u);
+    hipLaunchKernelGGL(order_hist_kernel, dim3(blocks_of(tiles)), dim3(256), 0, stream, key, tiles, hist_cursor);
+    hipLaunchKernelGGL(order_place_kernel, dim3(blocks_of(tiles)), dim3(256), 0, stream, key, tiles,
+                       (const uint32_t*)hist_cursor, hist_cursor + 256, order);
+}
+
+void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps,
+                       uint32_t* cost) {
     if (views.total_tiles == 0) return;
     hipLaunchKernelGGL(batch_caps_kernel, dim3(blocks_of(views.total_tiles)), dim3(256), 0, stream,
-                       reinterpret_cast<const uint2*>(ranges), views, batch, caps);
+                       reinterpret_cast<const uint2*>(ranges), views, batch, caps, cost);
 }
 
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,

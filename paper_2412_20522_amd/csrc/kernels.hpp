@@ -92,7 +92,15 @@ void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_
                             const uint32_t* wide_flag, const uint64_t* tmask, const uint32_t* offsets, int64_t R,
                             int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
                             int64_t capacity, uint32_t* flags);
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps);
+// Tile order of a persistent launch: the tiles by descending cost key
+// (key[t] in 0..255, ties in any order), so that the most expensive start
+// first.  hist_cursor: [512] u32 of scratch (cleared here).
+void launch_tile_order(hipStream_t stream, const uint32_t* key, uint32_t tiles, uint32_t* hist_cursor,
+                       uint32_t* order);
+// cost (optional, [tiles]): the forward's tile-order key, the entries of a
+// tile's two lists in units of 8, at most 255
+void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps,
+                       uint32_t* cost = nullptr);
 struct HybridBuffers {
     const uint32_t* vals;        // list entries (sorted positions), (cell, position) order
     const uint32_t* ranges;      // [tiles + regions, 2]
@@ -108,6 +116,7 @@ struct HybridBuffers {
     uint64_t stg_cap;
     double* drec_clear;          // optional: FP64 per-record gradient accumulator the forward clears
     uint64_t drec_clear_n2;      // its size in pairs of doubles
+    const uint32_t* order;       // optional [tiles]: the order in which a persistent launch takes the tiles
 };
 // stats [P, 4] (examined, blended, blended with mask 0, last + 1) and evals
 // [P, 4] (evaluated, evaluated up to the last blended entry, 0, 0) are
