@@ -298,6 +298,10 @@ struct mgs_frame {
     // the backward that accumulates into it; false after a backward and
     // after (re)allocation (a backward then fills it first)
     bool drec_zero = false;
+    // views of the last forward, whose per-tile batch counts (nbatch) order
+    // the tiles of the next forward over the same views
+    ViewSet order_views{};
+    bool order_valid = false;
     // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
     // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
     // 32, staged-entry counter (u32) at 192; the tile orders' histogram and
@@ -435,6 +439,15 @@ mgs_status mgs_frame_get_stats(const mgs_frame* f, mgs_frame_stats* out) {
     return MGS_OK;
 }
 
+// Grows the per-tile batch counts; a new allocation holds no counts of an
+// earlier forward.
+static mgs_status grow_nbatch(mgs_frame* f, size_t bytes) {
+    const size_t before = f->nbatch.p ? f->nbatch.bytes : 0;
+    const mgs_status s = grow(f->ctx, f->nbatch, bytes);
+    if (s != MGS_OK || f->nbatch.bytes != before) f->order_valid = false;
+    return s;
+}
+
 // Grows the FP64 per-record gradient accumulator; a new allocation is not
 // known to be zero.
 static mgs_status grow_drec(mgs_frame* f) {
@@ -545,7 +558,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->ranges, (size_t)(T + NR) * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->tcost, (size_t)T * 4 + 4)) || (s = grow(ctx, f->order, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->order_b, (size_t)T * 4 + 4)) ||
-        (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow(ctx, f->nbatch, (size_t)T * 4 + 4)) ||
+        (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow_nbatch(f, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
         (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
         (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(std::max<int64_t>(R, T)))) ||
@@ -643,8 +656,11 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T + NR, (uint32_t*)f->ranges.p);
         launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->views, (int)B, (uint32_t*)f->caps.p,
                           (uint32_t*)f->tcost.p);
-        // the forward takes the tiles with the longest lists first
-        launch_tile_order(stream, (const uint32_t*)f->tcost.p, (uint32_t)T, f->order_hist(), (uint32_t*)f->order.p);
+        // the forward takes the most expensive tiles first: by the batches the
+        // last forward over the same views took, else by list length
+        const bool measured = f->order_valid && std::memcmp(&f->order_views, &f->views, sizeof(ViewSet)) == 0;
+        launch_tile_order(stream, (const uint32_t*)(measured ? f->nbatch.p : f->tcost.p), (uint32_t)T,
+                          f->order_hist(), (uint32_t*)f->order.p);
         launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, f->cur_need(),
                         f->scan_tmp.p);
     }
@@ -677,6 +693,8 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         MGS_HIP(ctx, hipMemcpyAsync(t_final_out, f->t_final.p, (size_t)P * 4, hipMemcpyDeviceToDevice, stream));
     f->drec_zero = true;
     f->have_forward = true;
+    f->order_views = f->views;  // nbatch now holds this forward's batch counts
+    f->order_valid = true;
     return MGS_OK;
 }
 }  // namespace
