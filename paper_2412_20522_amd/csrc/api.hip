@@ -285,7 +285,7 @@ struct mgs_frame {
     int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, cur_cap = 0, stg_cap = 0;
     // device buffers: per record, then per list entry (32-bit cell keys), per
     // tile and region, per pixel
-    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, offsets, wide_flag, tmask,
+    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, wide_flag, tmask,
         cls_part;
     // order, order_b: the tile orders of the forward and the backward
     // compositing (most expensive first), tcost: the forward's cost keys
@@ -412,7 +412,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
-                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->offsets,  &f->wide_flag, &f->tmask, &f->cls_part,
+                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->wide_flag, &f->tmask, &f->cls_part,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
                       &f->caps,     &f->tcost,     &f->order,     &f->order_b,   &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
@@ -552,7 +552,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
-        (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) || (s = grow(ctx, f->offsets, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
         (s = grow(ctx, f->cls_part, classify_parts_bytes(R))) ||
         (s = grow(ctx, f->ranges, (size_t)(T + NR) * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
@@ -561,7 +561,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow_nbatch(f, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
         (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
-        (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(std::max<int64_t>(R, T)))) ||
+        (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(T))) ||
         (s = grow(ctx, f->rsort_tmp, sort_scratch_bytes(R))) || (s = grow(ctx, f->queue, 256)))
         return s;
     launch_fill_u32(stream, f->flags(), 10, 0u);  // flags and the counters up to byte 40
@@ -587,12 +587,13 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
                                 (const float*)f->rec.p, R, f->n, f->views, f->st,
                                 (uint32_t*)f->cnt_sorted.p,
                                 (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p,
-                                (uint32_t*)f->cls_part.p, f->wide_counts());
+                                (uint32_t*)f->cls_part.p);
     }
     {
+        // list offsets: one scan over the classification's per-workgroup
+        // counts; the duplication adds the counts within its workgroup
         StageTimer t(ctx, stream, MGS_STAGE_SCAN);
-        launch_scan_u32(stream, (const uint32_t*)f->cnt_sorted.p, R, (uint32_t*)f->offsets.p, f->total(),
-                        f->scan_tmp.p);
+        launch_list_offsets(stream, (uint32_t*)f->cls_part.p, R, f->total(), f->wide_counts());
     }
     MGS_CHECK_LAUNCH(ctx);
     const int64_t B = st->batch_depth;
@@ -638,7 +639,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
         launch_duplicate_lists(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
                                (const uint32_t*)f->wide_flag.p, (const uint64_t*)f->tmask.p,
-                               (const uint32_t*)f->offsets.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
+                               (uint32_t*)f->cls_part.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
                                (uint32_t*)f->vals.p, f->K, f->flags());
     }
     // entries are already in (depth, record) order: a stable sort on the cell

@@ -258,7 +258,9 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 // [v n, (v + 1) n) belong to view v.  Writes the sorted record copy (radius in
 // B.w, record id bits in C.w), the wide flag and the number of list entries
 // (tiles or regions, after culling) of every position, and per workgroup the
-// number of wide records and of their region entries (part[b], part[nb + b]).
+// number of wide records and of their region entries (part[b], part[nb +
+// b]), and per wave the number of all list entries (part[2 nb + wave]; a
+// position has fewer than 2^24 entries, so a wave's 64 stay below 2^32).
 // A record without tiles (key all ones, sorted last in its view) is listed
 // nowhere: it gets no copy, which nothing uses.
 __global__ void __launch_bounds__(256) permute_classify_kernel(
@@ -321,11 +323,16 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     // address updated by every wave serialises)
     const uint64_t wb = __ballot(live && wide);
     uint32_t e = live && wide ? cnt : 0u;
-    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    uint32_t ea = live ? cnt : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        e += __shfl_xor(e, off);
+        ea += __shfl_xor(ea, off);
+    }
     const int wid = threadIdx.x >> 6;
     if (lane == 0) {
         s_part[0][wid] = (uint32_t)__popcll(wb);
         s_part[1][wid] = e;
+        part[2 * gridDim.x + (blockIdx.x * blockDim.x + threadIdx.x) / 64] = ea;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -339,34 +346,109 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     }
 }
 
-// Totals of the two per-workgroup counts of the classification: out[0] =
-// wide records, out[2] = region entries (integer sums: any order gives the
-// same totals).
-__global__ void __launch_bounds__(256) sum_parts_kernel(const uint32_t* __restrict__ part, int nb,
-                                                         uint64_t* __restrict__ out) {
-    // out[0] and out[2] are zero (cleared with the flags before the
-    // forward); every workgroup adds the sums of its slice of the parts
-    __shared__ uint64_t s[2][4];
-    uint64_t a = 0, b = 0;
-    for (int k = (int)blockIdx.x * 256 + (int)threadIdx.x; k < nb; k += (int)gridDim.x * 256) {
-        a += part[k];
-        b += part[nb + k];
+// List offsets from the classification's counts, in two steps.  A group is
+// LO_GROUP waves (LO_GROUP / 4 classification workgroups).  Step 1, one
+// workgroup per group: each wave's first entry relative to its group (an
+// exclusive scan of the per-wave entry counts), the group's entry total and
+// its totals of wide records and their region entries.  Step 2, one
+// workgroup: the groups' first entries, the entry total (*total) and the
+// wide totals (wide[0], wide[2]).  A wave's first entry is then
+// wave_rel[wave] + group_off[wave / LO_GROUP].  Integer sums: no result
+// depends on an order.
+constexpr int LO_GROUP = 1024;
+struct ListOffsets {
+    uint64_t* wave_rel;   // [waves]
+    uint64_t* group_tot;  // [groups, 3]: entries, wide records, region entries
+    uint64_t* group_off;  // [groups]
+};
+
+__global__ void __launch_bounds__(LO_GROUP) list_offsets_group_kernel(const uint32_t* __restrict__ part, int64_t nb,
+                                                                     int64_t nw, ListOffsets lo) {
+    __shared__ uint64_t s_w[LO_GROUP / 64][3];
+    const int t = threadIdx.x, lane = lane_id(), wid = t >> 6;
+    const int64_t w = (int64_t)blockIdx.x * LO_GROUP + t;  // this thread's wave
+    const uint64_t c = w < nw ? part[2 * nb + w] : 0u;
+    // the group's classification workgroups: LO_GROUP / 4 of them
+    const int64_t b = (int64_t)blockIdx.x * (LO_GROUP / 4) + t;
+    uint64_t a = 0, r = 0;
+    if (t < LO_GROUP / 4 && b < nb) {
+        a = part[b];
+        r = part[nb + b];
+    }
+    uint64_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
     }
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
+        r += __shfl_xor(r, off);
     }
-    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    if (lane == 63) s_w[wid][0] = x;
     if (lane == 0) {
-        s[0][wid] = a;
-        s[1][wid] = b;
+        s_w[wid][1] = a;
+        s_w[wid][2] = r;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint64_t ta = s[0][0] + s[0][1] + s[0][2] + s[0][3];
-        const uint64_t tb = s[1][0] + s[1][1] + s[1][2] + s[1][3];
-        if (ta) atomicAdd(reinterpret_cast<unsigned long long*>(out), (unsigned long long)ta);
-        if (tb) atomicAdd(reinterpret_cast<unsigned long long*>(out + 2), (unsigned long long)tb);
+    uint64_t wo = 0;
+    for (int v = 0; v < wid; ++v) wo += s_w[v][0];
+    if (w < nw) lo.wave_rel[w] = wo + x - c;
+    if (t < 3) {
+        uint64_t tot = 0;
+        for (int v = 0; v < LO_GROUP / 64; ++v) tot += s_w[v][t];
+        lo.group_tot[3 * blockIdx.x + t] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(LO_GROUP) list_offsets_total_kernel(int64_t ng, ListOffsets lo,
+                                                                     uint64_t* __restrict__ total,
+                                                                     uint64_t* __restrict__ wide) {
+    __shared__ uint64_t s_w[LO_GROUP / 64][3];
+    const int t = threadIdx.x, lane = lane_id(), wid = t >> 6;
+    uint64_t carry = 0, a = 0, r = 0;
+    for (int64_t base = 0; base < ng; base += LO_GROUP) {
+        const int64_t g = base + t;
+        const uint64_t c = g < ng ? lo.group_tot[3 * g] : 0u;
+        if (g < ng) {
+            a += lo.group_tot[3 * g + 1];
+            r += lo.group_tot[3 * g + 2];
+        }
+        uint64_t x = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) s_w[wid][0] = x;
+        __syncthreads();
+        uint64_t wo = 0, tot = 0;
+        for (int v = 0; v < LO_GROUP / 64; ++v) {
+            if (v < wid) wo += s_w[v][0];
+            tot += s_w[v][0];
+        }
+        if (g < ng) lo.group_off[g] = carry + wo + x - c;
+        carry += tot;
+        __syncthreads();  // s_w is written again by the next round
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        r += __shfl_xor(r, off);
+    }
+    if (lane == 0) {
+        s_w[wid][1] = a;
+        s_w[wid][2] = r;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint64_t ta = 0, tr = 0;
+        for (int v = 0; v < LO_GROUP / 64; ++v) {
+            ta += s_w[v][1];
+            tr += s_w[v][2];
+        }
+        *total = carry;
+        wide[0] = ta;
+        wide[2] = tr;
     }
 }
 
@@ -419,9 +501,8 @@ __device__ __forceinline__ int wave_max_scan(int x) {
 // gets KEY_NONE.  No step waits on another wave.
 __global__ void __launch_bounds__(256) duplicate_kernel(
     const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
-    const uint64_t* __restrict__ tmask, const uint32_t* __restrict__ offsets, int64_t R, int64_t n, ViewSet views,
-    DevSettings st, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity,
-    uint32_t* __restrict__ flags) {
+    const uint64_t* __restrict__ tmask, ListOffsets lo, int64_t R, int64_t n, ViewSet views, DevSettings st,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_first[256];
     __shared__ uint32_t s_rel[256];
     __shared__ unsigned long long s_mask[256];
@@ -433,7 +514,6 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     const int lane = lane_id();
     const int wb = t & ~63;  // the wave's first thread
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
-    int64_t off = 0;
     uint32_t cnt = 0;
     int vi = 0;
     bool wide = false;
@@ -444,7 +524,6 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         // every load of the position at once (one memory round trip); the
         // copy and the mask of a position without entries are not used
         cnt = cnt_sorted[i];
-        off = offsets[i];
         wide = wide_flag[i] != 0;
         A = srec[3 * i];
         B = srec[3 * i + 1];
@@ -465,20 +544,31 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     }
     if (cnt == 0 || cl.area > CULL_MAX) mask = 0;
     const bool flat = cnt > 0 && (!cull || cl.area <= CULL_MAX);
-    const int64_t base = offsets[i0];  // start of the workgroup's output (i0 < R)
+    // start of the wave's output: its offset within its group of waves plus
+    // the group's
+    const int64_t wave = i0 / 64 + (t >> 6);
+    const int64_t base = (int64_t)(lo.wave_rel[wave] + lo.group_off[wave / LO_GROUP]);
     bool overflow = false;
+    // the record's first entry: the wave's start plus the entries of the
+    // wave's earlier positions (below 2^32, see the classification)
+    uint32_t rel;
     {
-        // first slot of each record among the wave's flat slots
-        uint32_t x = flat ? cnt : 0u;
+        // inclusive scans over the wave: all entries (ax), flat slots (x)
+        uint32_t x = flat ? cnt : 0u, ax = cnt;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d);
-            if (lane >= d) x += y;
+            const uint32_t y = __shfl_up(x, d), ay = __shfl_up(ax, d);
+            if (lane >= d) {
+                x += y;
+                ax += ay;
+            }
         }
+        rel = ax - cnt;
+        // first slot of each record among the wave's flat slots
         const uint32_t first = x - (flat ? cnt : 0u);
         const uint32_t total = (uint32_t)__shfl((int)x, 63);
         s_first[t] = first;
-        s_rel[t] = (uint32_t)(off - base);
+        s_rel[t] = rel;
         s_mask[t] = mask;
         s_geo[t] = make_uint2(key0, (uint32_t)cl.w | (stride << 16));
         int carry = -1;
@@ -528,7 +618,7 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
         const int bcw = __shfl(cl.cw, src), bch = __shfl(cl.ch, src);
         const int bwidth = __shfl(width, src), bheight = __shfl(height, src);
         const uint32_t bkey0 = (uint32_t)__shfl((int)key0, src), bstride = (uint32_t)__shfl((int)stride, src);
-        const int64_t bo = __shfl(off, src);
+        const int64_t bo = base + (int64_t)(uint32_t)__shfl((int)rel, src);
         const int64_t end = bo + bcnt;
         const RowCull rc = row_prep(shfl4(A, src), shfl4(B, src), st);
         const int rows = (int)(barea / (uint32_t)bw);
@@ -1389,27 +1479,49 @@ bool composite_config_supported(const CompositeConfig& c) {
 
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
                              int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
-                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part,
-                             uint64_t* wide_counts) {
+                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part) {
     if (R == 0) return;
     const unsigned nb = blocks_of(R);
     hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, skeys,
                        reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, wide_flag, tmask,
                        reinterpret_cast<float4*>(srec), part);
-    const unsigned sb = (unsigned)std::min<int64_t>(256, ((int64_t)nb + 255) / 256);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(sb), dim3(256), 0, stream, part, (int)nb, wide_counts);
 }
 
-size_t classify_parts_bytes(int64_t R) { return (size_t)blocks_of(R) * 8 + 8; }
+// part: 2 nb + 4 nb u32 counts (per workgroup, per wave), then (8-byte
+// aligned) the list offsets: per wave, per group (3 totals and the offset)
+namespace {
+int64_t waves_of(int64_t R) { return (int64_t)blocks_of(R) * 4; }
+int64_t groups_of(int64_t R) { return (waves_of(R) + LO_GROUP - 1) / LO_GROUP; }
+size_t counts_bytes(int64_t R) { return ((size_t)blocks_of(R) * 24 + 15) / 8 * 8; }
+ListOffsets list_offsets(uint32_t* part, int64_t R) {
+    char* p = reinterpret_cast<char*>(part) + counts_bytes(R);
+    ListOffsets lo;
+    lo.wave_rel = reinterpret_cast<uint64_t*>(p);
+    lo.group_tot = lo.wave_rel + waves_of(R);
+    lo.group_off = lo.group_tot + 3 * groups_of(R);
+    return lo;
+}
+}  // namespace
+
+size_t classify_parts_bytes(int64_t R) { return counts_bytes(R) + (size_t)(waves_of(R) + 4 * groups_of(R)) * 8 + 8; }
+
+void launch_list_offsets(hipStream_t stream, uint32_t* part, int64_t R, uint64_t* total, uint64_t* wide_counts) {
+    const ListOffsets lo = list_offsets(part, R);
+    const int64_t ng = R > 0 ? groups_of(R) : 0;
+    if (ng > 0)
+        hipLaunchKernelGGL(list_offsets_group_kernel, dim3((unsigned)ng), dim3(LO_GROUP), 0, stream, part,
+                           (int64_t)blocks_of(R), waves_of(R), lo);
+    hipLaunchKernelGGL(list_offsets_total_kernel, dim3(1), dim3(LO_GROUP), 0, stream, ng, lo, total, wide_counts);
+}
 
 void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
-                            const uint32_t* wide_flag, const uint64_t* tmask, const uint32_t* offsets, int64_t R,
+                            const uint32_t* wide_flag, const uint64_t* tmask, uint32_t* part, int64_t R,
                             int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
                             int64_t capacity, uint32_t* flags) {
     if (R == 0) return;
     hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
-                       reinterpret_cast<const float4*>(srec), cnt_sorted, wide_flag, tmask, offsets, R, n, views, st,
-                       keys, vals, capacity, flags);
+                       reinterpret_cast<const float4*>(srec), cnt_sorted, wide_flag, tmask, list_offsets(part, R), R,
+                       n, views, st, keys, vals, capacity, flags);
 }
 
 void launch_tile_order(hipStream_t stream, const uint32_t* key, uint32_t tiles, uint32_t* hist_cursor,
