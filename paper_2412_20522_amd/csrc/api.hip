@@ -288,11 +288,12 @@ struct mgs_frame {
     DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, wide_flag, tmask,
         cls_part;
     // order, order_b: the tile orders of the forward and the backward
-    // compositing (most expensive first), tcost: the forward's cost keys
+    // compositing (most expensive first), tcost: the forward's cost keys,
+    // caps: checkpoint totals per workgroup of 256 tiles
     DevBuf keys, vals, keys_alt, vals_alt, ranges, caps, tcost, order, order_b, cur_off, nbatch, cur, cur_stg, stg,
         t_final, last, stats, evals;
     bool have_stats = false;  // the last forward wrote the per-pixel work counters
-    DevBuf d_rec, dm_acc, scan_tmp, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
+    DevBuf d_rec, dm_acc, rsort_tmp, sort_tmp, misc, queue, sum_tmp;  // d_rec, dm_acc: FP64
     DevBuf imp_acc;  // FP64 sums of the importance forward
     // d_rec is all zeros from the forward compositing (which clears it) to
     // the backward that accumulates into it; false after a backward and
@@ -416,7 +417,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
                       &f->caps,     &f->tcost,     &f->order,     &f->order_b,   &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
-                      &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->scan_tmp, &f->rsort_tmp, &f->sort_tmp,
+                      &f->stats,    &f->evals,     &f->d_rec,     &f->dm_acc,    &f->rsort_tmp, &f->sort_tmp,
                       &f->misc,     &f->queue,     &f->sum_tmp,  &f->imp_acc};
     for (DevBuf* b : bufs) release(*b);
     if (f->h_pinned) (void)hipHostFree(f->h_pinned);
@@ -561,7 +562,6 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->cur_off, (size_t)T * 4 + 4)) || (s = grow_nbatch(f, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->t_final, (size_t)P * 4)) || (s = grow(ctx, f->last, (size_t)P * 4)) ||
         (s = grow(ctx, f->stats, (size_t)P * 16)) || (s = grow(ctx, f->evals, (size_t)P * 16)) ||
-        (s = grow(ctx, f->scan_tmp, scan_scratch_bytes(T))) ||
         (s = grow(ctx, f->rsort_tmp, sort_scratch_bytes(R))) || (s = grow(ctx, f->queue, 256)))
         return s;
     launch_fill_u32(stream, f->flags(), 10, 0u);  // flags and the counters up to byte 40
@@ -652,25 +652,25 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
                             (uint32_t*)f->vals_alt.p, f->K, K_dev, 0, 8 * f->sort_passes, f->sort_tmp.p, &in_alt);
     }
     f->sorted_in_alt = in_alt;
+    uint32_t* queue = f->persistent ? (uint32_t*)f->queue.p : nullptr;
     {
         StageTimer t(ctx, stream, MGS_STAGE_RANGES);
-        launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T + NR, (uint32_t*)f->ranges.p);
-        launch_batch_caps(stream, (const uint32_t*)f->ranges.p, f->views, (int)B, (uint32_t*)f->caps.p,
-                          (uint32_t*)f->tcost.p);
+        // one launch clears the ranges, the tile order's histogram and
+        // cursors, the staged-entry counter and the persistent queue
+        const FillSpan zero[4] = {{(uint32_t*)f->ranges.p, 2 * (T + NR), 0u},
+                                  {f->order_hist(), 512, 0u},
+                                  {f->stg_count(), 1, 0u},
+                                  {queue, 1, 0u}};
+        launch_fill_spans(stream, zero, 4);
+        launch_tile_ranges32(stream, f->keys_sorted(), f->K, K_dev, T + NR, (uint32_t*)f->ranges.p, true);
         // the forward takes the most expensive tiles first: by the batches the
         // last forward over the same views took, else by list length
         const bool measured = f->order_valid && std::memcmp(&f->order_views, &f->views, sizeof(ViewSet)) == 0;
-        launch_tile_order(stream, (const uint32_t*)(measured ? f->nbatch.p : f->tcost.p), (uint32_t)T,
-                          f->order_hist(), (uint32_t*)f->order.p);
-        launch_scan_u32(stream, (const uint32_t*)f->caps.p, T, (uint32_t*)f->cur_off.p, f->cur_need(),
-                        f->scan_tmp.p);
+        launch_tile_setup(stream, (const uint32_t*)f->ranges.p, f->views, (int)B,
+                          measured ? (const uint32_t*)f->nbatch.p : nullptr, (uint32_t*)f->tcost.p,
+                          (uint32_t*)f->cur_off.p, f->cur_need(), (uint32_t*)f->caps.p, f->order_hist(),
+                          (uint32_t*)f->order.p);
     }
-    uint32_t* queue = nullptr;
-    if (f->persistent) {
-        queue = (uint32_t*)f->queue.p;
-        launch_fill_u32(stream, queue, 1, 0u);
-    }
-    launch_fill_u32(stream, f->stg_count(), 1, 0u);
     const bool imp = imp_sum != nullptr;
     if (imp) {
         if ((s = grow(ctx, f->imp_acc, (size_t)f->n * 8 + 8))) return s;
@@ -737,10 +737,12 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         launch_fill_u32(stream, (uint32_t*)f->d_rec.p, f->d_rec.bytes / 4, 0u);
     }
     f->drec_zero = false;  // this backward accumulates into it
-    launch_fill_u32(stream, (uint32_t*)f->dm_acc.p, 2 * f->n, 0u);
-    if (f->persistent) {
-        queue = (uint32_t*)f->queue.p;
-        launch_fill_u32(stream, queue, 1, 0u);
+    if (f->persistent) queue = (uint32_t*)f->queue.p;
+    {
+        // one launch clears the FP64 mask gradients, the persistent queue and
+        // the tile order's histogram and cursors
+        const FillSpan zero[3] = {{(uint32_t*)f->dm_acc.p, 2 * f->n, 0u}, {queue, 1, 0u}, {f->order_hist(), 512, 0u}};
+        launch_fill_spans(stream, zero, 3);
     }
     HybridBuffers hb = f->hybrid();
     {
@@ -748,7 +750,7 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         // the backward takes first the tiles where the forward took most
         // batches (the backward replays them)
         const uint32_t T = f->views.total_tiles;
-        launch_tile_order(stream, (const uint32_t*)f->nbatch.p, T, f->order_hist(), (uint32_t*)f->order_b.p);
+        launch_tile_order(stream, (const uint32_t*)f->nbatch.p, T, f->order_hist(), (uint32_t*)f->order_b.p, true);
         hb.order = (const uint32_t*)f->order_b.p;
         launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, hb, f->views, f->st,
                           (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,

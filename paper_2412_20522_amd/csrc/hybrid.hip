@@ -665,22 +665,50 @@ __device__ __forceinline__ uint32_t region_of_tile(int tx, int ty, const DevView
     return views.total_tiles + cam.reg_off + (uint32_t)(ty / REGION) * (uint32_t)cam.reg_w + (uint32_t)(tx / REGION);
 }
 
+// Per tile: the batch checkpoints it may take (a batch either emits `batch`
+// merged entries or exhausts a whole window of one of the two streams), as
+// an exclusive prefix within the workgroup (cur_off) and the workgroup's
+// total (blk); the forward's cost key (cost: the entries of the two lists in
+// units of 8, at most 255); and the workgroup's histogram of the tile-order
+// key (key[t], or the cost key when key is null), added into hist[256].
 __global__ void __launch_bounds__(256) batch_caps_kernel(const uint2* __restrict__ ranges, ViewSet views, int batch,
-                                                          uint32_t* __restrict__ caps, uint32_t* __restrict__ cost) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= views.total_tiles) return;
-    int vi = 0;
-    while (vi + 1 < views.n_views && t >= views.v[vi + 1].tile_off) ++vi;
-    const DevView& cam = views.v[vi];
-    const uint32_t lt = t - cam.tile_off;
-    const int tx = (int)(lt % (uint32_t)cam.grid_w), ty = (int)(lt / (uint32_t)cam.grid_w);
-    const uint2 r2 = ranges[region_of_tile(tx, ty, cam, views)];
-    const uint32_t len1 = ranges[t].y - ranges[t].x;
-    const uint32_t len2 = r2.y - r2.x;
-    caps[t] = 2u * ((len1 + batch - 1) / batch + (len2 + batch - 1) / batch) + 2u;
-    // cost key of the forward's tile order: entries of the two lists, in
-    // units of 8
-    if (cost) cost[t] = min((len1 + len2) >> 3, 255u);
+                                                          const uint32_t* __restrict__ key, uint32_t* __restrict__ cost,
+                                                          uint32_t* __restrict__ cur_off, uint32_t* __restrict__ blk,
+                                                          uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    __shared__ uint32_t s_w[4];
+    const int tid = threadIdx.x, lane = lane_id();
+    h[tid] = 0u;
+    __syncthreads();
+    const uint32_t t = blockIdx.x * 256u + (uint32_t)tid;
+    uint32_t c = 0;
+    if (t < views.total_tiles) {
+        int vi = 0;
+        while (vi + 1 < views.n_views && t >= views.v[vi + 1].tile_off) ++vi;
+        const DevView& cam = views.v[vi];
+        const uint32_t lt = t - cam.tile_off;
+        const int tx = (int)(lt % (uint32_t)cam.grid_w), ty = (int)(lt / (uint32_t)cam.grid_w);
+        const uint2 r2 = ranges[region_of_tile(tx, ty, cam, views)];
+        const uint32_t len1 = ranges[t].y - ranges[t].x;
+        const uint32_t len2 = r2.y - r2.x;
+        c = 2u * ((len1 + batch - 1) / batch + (len2 + batch - 1) / batch) + 2u;
+        const uint32_t ck = min((len1 + len2) >> 3, 255u);
+        if (cost) cost[t] = ck;
+        atomicAdd(&h[255u - min(key ? key[t] : ck, 255u)], 1u);
+    }
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[tid >> 6] = x;
+    __syncthreads();
+    uint32_t wo = 0;
+    for (int v = 0; v < (tid >> 6); ++v) wo += s_w[v];
+    if (t < views.total_tiles) cur_off[t] = wo + x - c;
+    if (tid == 255) blk[blockIdx.x] = wo + x;
+    if (h[tid]) atomicAdd(&hist[tid], h[tid]);
 }
 
 // Queue order of the tiles, most expensive first, so that the last tiles a
@@ -729,6 +757,55 @@ __global__ void __launch_bounds__(256) order_place_kernel(const uint32_t* __rest
     const uint32_t rank = i < n ? atomicAdd(&s_cnt[b], 1u) : 0u;
     __syncthreads();
     // a run of slots per non-empty bin
+    if (s_cnt[t]) s_base[t] = start + atomicAdd(&cursor[t], s_cnt[t]);
+    __syncthreads();
+    if (i < n) order[s_base[b] + rank] = i;
+}
+
+// order_place_kernel for the forward's set-up (the keys: key[t], or cost[t]
+// when key is null), which also completes the checkpoint offsets: cur_off[t]
+// (a prefix within its workgroup of 256 tiles) plus the totals of the
+// earlier workgroups (blk), and *cur_need = the grand total.
+__global__ void __launch_bounds__(256) order_offsets_kernel(const uint32_t* __restrict__ key,
+                                                             const uint32_t* __restrict__ cost, uint32_t n,
+                                                             const uint32_t* __restrict__ hist,
+                                                             uint32_t* __restrict__ cursor,
+                                                             uint32_t* __restrict__ order,
+                                                             uint32_t* __restrict__ cur_off,
+                                                             const uint32_t* __restrict__ blk,
+                                                             uint64_t* __restrict__ cur_need) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_cnt[256];
+    __shared__ uint32_t s_wsum[4];
+    __shared__ uint64_t s_pre[4];
+    const int t = threadIdx.x, lane = lane_id();
+    const uint32_t c = hist[t];
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    // checkpoints of the earlier workgroups
+    uint64_t pre = 0;
+    for (uint32_t b0 = 0; b0 < blockIdx.x; b0 += 256u) {
+        const uint32_t b = b0 + (uint32_t)t;
+        if (b < blockIdx.x) pre += blk[b];
+    }
+    for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
+    if (lane == 63) s_wsum[t >> 6] = x;
+    if (lane == 0) s_pre[t >> 6] = pre;
+    s_cnt[t] = 0u;
+    __syncthreads();
+    uint32_t start = x - c;
+    for (int v = 0; v < (t >> 6); ++v) start += s_wsum[v];
+    const uint64_t before = s_pre[0] + s_pre[1] + s_pre[2] + s_pre[3];
+    const uint32_t i = blockIdx.x * 256u + (uint32_t)t;
+    if (i < n) cur_off[i] += (uint32_t)before;
+    if (blockIdx.x == gridDim.x - 1 && t == 0) *cur_need = before + blk[blockIdx.x];
+    const uint32_t b = i < n ? 255u - min(key ? key[i] : cost[i], 255u) : 0u;
+    const uint32_t rank = i < n ? atomicAdd(&s_cnt[b], 1u) : 0u;
+    __syncthreads();
     if (s_cnt[t]) s_base[t] = start + atomicAdd(&cursor[t], s_cnt[t]);
     __syncthreads();
     if (i < n) order[s_base[b] + rank] = i;
@@ -1525,19 +1602,24 @@ void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_
 }
 
 void launch_tile_order(hipStream_t stream, const uint32_t* key, uint32_t tiles, uint32_t* hist_cursor,
-                       uint32_t* order) {
+                       uint32_t* order, bool cleared) {
     if (tiles == 0) return;
-    launch_fill_u32(stream, hist_cursor, 512, 0u);
+    if (!cleared) launch_fill_u32(stream, hist_cursor, 512, 0u);
     hipLaunchKernelGGL(order_hist_kernel, dim3(blocks_of(tiles)), dim3(256), 0, stream, key, tiles, hist_cursor);
     hipLaunchKernelGGL(order_place_kernel, dim3(blocks_of(tiles)), dim3(256), 0, stream, key, tiles,
                        (const uint32_t*)hist_cursor, hist_cursor + 256, order);
 }
 
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps,
-                       uint32_t* cost) {
-    if (views.total_tiles == 0) return;
-    hipLaunchKernelGGL(batch_caps_kernel, dim3(blocks_of(views.total_tiles)), dim3(256), 0, stream,
-                       reinterpret_cast<const uint2*>(ranges), views, batch, caps, cost);
+void launch_tile_setup(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch,
+                       const uint32_t* key, uint32_t* cost, uint32_t* cur_off, uint64_t* cur_need, uint32_t* blk,
+                       uint32_t* hist_cursor, uint32_t* order) {
+    const uint32_t T = views.total_tiles;
+    if (T == 0) return;
+    hipLaunchKernelGGL(batch_caps_kernel, dim3(blocks_of(T)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint2*>(ranges), views, batch, key, cost, cur_off, blk, hist_cursor);
+    hipLaunchKernelGGL(order_offsets_kernel, dim3(blocks_of(T)), dim3(256), 0, stream, key, (const uint32_t*)cost, T,
+                       (const uint32_t*)hist_cursor, hist_cursor + 256, order, cur_off, (const uint32_t*)blk,
+                       cur_need);
 }
 
 void launch_hybrid_fwd(hipStream_t stream, const CompositeConfig& cfg, const float* srec, const HybridBuffers& bufs,

@@ -60,9 +60,19 @@ void launch_radix_sort32(hipStream_t stream, uint32_t* keys, uint32_t* vals, uin
 // seg_len keys each (at most 16 segments; the last may be shorter).
 void launch_radix_sort_segmented(hipStream_t stream, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                                  uint32_t* vals_alt, int64_t K, int64_t seg_len, void* scratch, bool* out_in_alt);
+// cleared: ranges is already zero (else cleared here)
 void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, const uint64_t* K_dev,
-                          int64_t total_tiles, uint32_t* ranges);
+                          int64_t total_tiles, uint32_t* ranges, bool cleared = false);
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value);
+// Several u32 fills in one launch (at most FILL_SPANS; null or empty spans
+// are skipped).
+constexpr int FILL_SPANS = 4;
+struct FillSpan {
+    uint32_t* p;
+    int64_t n;
+    uint32_t value;
+};
+void launch_fill_spans(hipStream_t stream, const FillSpan* spans, int count);
 void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value);
 // Sum of n int32 values into a device u64 (deterministic).
 void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);
@@ -98,13 +108,18 @@ void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_
                             int64_t capacity, uint32_t* flags);
 // Tile order of a persistent launch: the tiles by descending cost key
 // (key[t] in 0..255, ties in any order), so that the most expensive start
-// first.  hist_cursor: [512] u32 of scratch (cleared here).
+// first.  hist_cursor: [512] u32 of scratch (cleared here unless cleared).
 void launch_tile_order(hipStream_t stream, const uint32_t* key, uint32_t tiles, uint32_t* hist_cursor,
-                       uint32_t* order);
-// cost (optional, [tiles]): the forward's tile-order key, the entries of a
-// tile's two lists in units of 8, at most 255
-void launch_batch_caps(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch, uint32_t* caps,
-                       uint32_t* cost = nullptr);
+                       uint32_t* order, bool cleared = false);
+// The forward's per-tile set-up after the ranges: each tile's first batch
+// checkpoint (cur_off, and the total into the device u64 *cur_need: per tile
+// 2 (ceil(narrow / batch) + ceil(region / batch)) + 2), its cost key (cost:
+// the entries of its two lists in units of 8, at most 255), and the tile
+// order by descending key (key[t], or the cost key when key is null).
+// hist_cursor: [512] u32, zero before; blk: blocks of 256 tiles, u32 scratch.
+void launch_tile_setup(hipStream_t stream, const uint32_t* ranges, const ViewSet& views, int batch,
+                       const uint32_t* key, uint32_t* cost, uint32_t* cur_off, uint64_t* cur_need, uint32_t* blk,
+                       uint32_t* hist_cursor, uint32_t* order);
 struct HybridBuffers {
     const uint32_t* vals;        // list entries (sorted positions), (cell, position) order
     const uint32_t* ranges;      // [tiles + regions, 2]

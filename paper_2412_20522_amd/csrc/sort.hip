@@ -516,6 +516,27 @@ __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p,
     if (i < n) p[i] = v;
 }
 
+// Up to FILL_SPANS u32 spans in one launch: element i of the concatenation
+// belongs to the first span whose end exceeds it.
+struct FillSet {
+    uint32_t* p[FILL_SPANS];
+    int64_t end[FILL_SPANS];  // cumulative element counts
+    uint32_t v[FILL_SPANS];
+    int count;
+};
+
+__global__ void __launch_bounds__(256) fill_set_kernel(FillSet fs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t start = 0;
+    for (int k = 0; k < fs.count; ++k) {
+        if (i < fs.end[k]) {
+            fs.p[k][i - start] = fs.v[k];
+            return;
+        }
+        start = fs.end[k];
+    }
+}
+
 __global__ void __launch_bounds__(256) fill_f32_kernel(float* __restrict__ p, int64_t n, float v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -705,8 +726,8 @@ void launch_tile_ranges(hipStream_t stream, const uint64_t* keys, int64_t K, con
 }
 
 void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, const uint64_t* K_dev,
-                          int64_t total_tiles, uint32_t* ranges) {
-    launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
+                          int64_t total_tiles, uint32_t* ranges, bool cleared) {
+    if (!cleared) launch_fill_u32(stream, ranges, 2 * total_tiles, 0u);
     if (K == 0) return;
     // keys come from the library's own buffers (16-byte aligned)
     hipLaunchKernelGGL(tile_ranges4_kernel, dim3((unsigned)((K + 1023) / 1024)), dim3(256), 0, stream, keys, K, K_dev,
@@ -716,6 +737,21 @@ void launch_tile_ranges32(hipStream_t stream, const uint32_t* keys, int64_t K, c
 void launch_fill_u32(hipStream_t stream, uint32_t* p, int64_t n, uint32_t value) {
     if (n <= 0) return;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n, value);
+}
+
+void launch_fill_spans(hipStream_t stream, const FillSpan* spans, int count) {
+    FillSet fs{};
+    int64_t total = 0;
+    for (int k = 0; k < count && fs.count < FILL_SPANS; ++k) {
+        if (!spans[k].p || spans[k].n <= 0) continue;
+        total += spans[k].n;
+        fs.p[fs.count] = spans[k].p;
+        fs.end[fs.count] = total;
+        fs.v[fs.count] = spans[k].value;
+        ++fs.count;
+    }
+    if (total == 0) return;
+    hipLaunchKernelGGL(fill_set_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, fs);
 }
 
 void launch_round_f64(hipStream_t stream, const double* in, float* out, int64_t n) {
