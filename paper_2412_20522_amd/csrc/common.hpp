@@ -106,6 +106,21 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row operations:
+// shifts by 1, 2, 4 and 8 lanes within each 16-lane row (a lane with no
+// source adds 0), then lane 15's sum into rows 1 and 3 and lane 31's into
+// rows 2 and 3.  Lane 63 ends with the wave's total.
+__device__ __forceinline__ uint32_t wave_add_scan(uint32_t v) {
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr 1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr 2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr 4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr 8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast 15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast 31
+    return (uint32_t)x;
+}
+
 // Sum over the 64 lanes of a wave with DPP row operations (GCN/CDNA row
 // broadcast); the total lands in lane 63 and is returned to every lane.
 __device__ __forceinline__ float wave_sum(float v) {

@@ -322,14 +322,11 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     // wide records and their list entries of the workgroup (no atomics: one
     // address updated by every wave serialises)
     const uint64_t wb = __ballot(live && wide);
-    uint32_t e = live && wide ? cnt : 0u;
-    uint32_t ea = live ? cnt : 0u;
-    for (int off = 32; off > 0; off >>= 1) {
-        e += __shfl_xor(e, off);
-        ea += __shfl_xor(ea, off);
-    }
+    // the wave's totals land in lane 63
+    const uint32_t e = wave_add_scan(live && wide ? cnt : 0u);
+    const uint32_t ea = wave_add_scan(live ? cnt : 0u);
     const int wid = threadIdx.x >> 6;
-    if (lane == 0) {
+    if (lane == 63) {
         s_part[0][wid] = (uint32_t)__popcll(wb);
         s_part[1][wid] = e;
         part[2 * gridDim.x + (blockIdx.x * blockDim.x + threadIdx.x) / 64] = ea;
@@ -554,19 +551,11 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     uint32_t rel;
     {
         // inclusive scans over the wave: all entries (ax), flat slots (x)
-        uint32_t x = flat ? cnt : 0u, ax = cnt;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(x, d), ay = __shfl_up(ax, d);
-            if (lane >= d) {
-                x += y;
-                ax += ay;
-            }
-        }
+        const uint32_t x = wave_add_scan(flat ? cnt : 0u), ax = wave_add_scan(cnt);
         rel = ax - cnt;
         // first slot of each record among the wave's flat slots
         const uint32_t first = x - (flat ? cnt : 0u);
-        const uint32_t total = (uint32_t)__shfl((int)x, 63);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
         s_first[t] = first;
         s_rel[t] = rel;
         s_mask[t] = mask;
