@@ -69,6 +69,24 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sh, T* total) {
     return wo + inc - v;
 }
 
+// The same over a block of NTH threads (a multiple of 64).
+template <typename T, int NTH>
+__device__ __forceinline__ T block_exclusive_scan_n(T v, T* sh, T* total) {
+    const T inc = wave_inclusive_scan(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) sh[w] = inc;
+    __syncthreads();
+    T wo = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NTH / 64; ++i) {
+        if (i < w) wo += sh[i];
+        tot += sh[i];
+    }
+    *total = tot;
+    __syncthreads();
+    return wo + inc - v;
+}
+
 __host__ __device__ inline int64_t nblocks(int64_t n) { return (n + TILE - 1) / TILE; }
 
 // Items per thread of the sort's tiles: 8 for 64-bit keys (with 16, the
@@ -347,19 +365,32 @@ __global__ void __launch_bounds__(NT) radix_rowscan_kernel(const uint32_t* __res
     if (threadIdx.x == 0) row_tot[row] = tot;
 }
 
+// Threads of a scatter workgroup: 512 for 32-bit keys (8 per thread, so
+// that twice the waves of a 256-thread workgroup share the tile's LDS), 256
+// for 64-bit keys.
 template <typename KeyT>
-__global__ void __launch_bounds__(NT) radix_downsweep_kernel(
+constexpr int sort_dt() {
+    return sizeof(KeyT) == 8 ? 256 : 512;
+}
+
+// Threads t < RADIX own digit t in the digit steps; the per-wave digit
+// counts (at most 64 x 8 per wave, prefixes at most the tile) fit 16 bits.
+template <typename KeyT>
+__global__ void __launch_bounds__(sort_dt<KeyT>()) __attribute__((amdgpu_waves_per_eu(sizeof(KeyT) == 8 ? 1 : 6)))
+radix_downsweep_kernel(
     const KeyT* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, KeyT* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out, int64_t Kcap, const uint64_t* __restrict__ K_dev, int shift,
     const uint32_t* __restrict__ row_pre, const uint32_t* __restrict__ row_tot, int64_t nb, int64_t chunk,
     int64_t seg_len, int64_t nbs) {
-    constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
+    constexpr int DT = sort_dt<KeyT>();
+    constexpr int STILE = sort_tile<KeyT>(), SIPT = STILE / DT;
+    static_assert(SIPT * 64 <= 65535 && STILE <= 65535, "16-bit digit counts");
     __shared__ KeyT sk[STILE];
     __shared__ uint32_t sv[STILE];
-    __shared__ uint32_t wcnt[NT / 64][RADIX];
+    __shared__ uint16_t wcnt[DT / 64][RADIX];
     __shared__ uint32_t dstart[RADIX];
     __shared__ uint32_t gstart[RADIX];
-    __shared__ uint32_t scan_sh[NT / 64];
+    __shared__ uint32_t scan_sh[DT / 64];
 
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
@@ -368,15 +399,16 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     if (cbeg >= cend) return;  // uniform over the block
     const int w = threadIdx.x >> 6, lane = lane_id();
     // global start of each digit for this chunk, advanced after every sub-tile
+    const bool dig = threadIdx.x < RADIX;
     {
-        const int64_t row = sg.seg * RADIX + threadIdx.x;
+        const int64_t row = sg.seg * RADIX + (dig ? threadIdx.x : 0);
         uint32_t tot;
-        const uint32_t below = block_exclusive_scan(row_tot[row], scan_sh, &tot);
-        gstart[threadIdx.x] = (uint32_t)(sg.seg * seg_len) + below + row_pre[row * nbs + sg.bl];
+        const uint32_t below = block_exclusive_scan_n<uint32_t, DT>(dig ? row_tot[row] : 0u, scan_sh, &tot);
+        if (dig) gstart[threadIdx.x] = (uint32_t)(sg.seg * seg_len) + below + row_pre[row * nbs + sg.bl];
     }
     for (int64_t base = cbeg; base < cend; base += STILE) {
     const int nvalid = (int)min((int64_t)STILE, cend - base);
-    for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&wcnt[0][0])[i] = 0u;
+    for (int i = threadIdx.x; i < (DT / 64) * RADIX; i += DT) (&wcnt[0][0])[i] = 0u;
     __syncthreads();
 
     // wave w owns the contiguous span [w * 64 SIPT, (w + 1) * 64 SIPT) of the tile;
@@ -384,12 +416,15 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     KeyT key[SIPT];
     uint32_t val[SIPT];
     uint32_t rank[SIPT];
+    // one address per array: the rounds are constant offsets from it
+    const int l0 = w * (SIPT * 64) + lane;
+    const KeyT* kp = keys_in + base + l0;
+    const uint32_t* vp = vals_in + base + l0;
 #pragma unroll
     for (int j = 0; j < SIPT; ++j) {
-        const int li = w * (SIPT * 64) + j * 64 + lane;
-        if (li < nvalid) {
-            key[j] = keys_in[base + li];
-            val[j] = vals_in[base + li];
+        if (l0 + j * 64 < nvalid) {
+            key[j] = kp[j * 64];
+            val[j] = vp[j * 64];
         } else {
             key[j] = ~(KeyT)0;  // digit 255 at every shift, ranked after every valid item
             val[j] = 0u;
@@ -408,22 +443,25 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
         const uint32_t before = wcnt[w][d];
         rank[j] = before + (uint32_t)__popcll(peers & lt);
         const int leader = __ffsll((long long)peers) - 1;
-        if (lane == leader) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+        if (lane == leader) wcnt[w][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
     }
     __syncthreads();
     // per digit: offsets of each wave, block total, then block-wide digit starts
-    uint32_t digit_total;
+    uint32_t digit_total = 0;
     {
         const int d = threadIdx.x;
         uint32_t run = 0;
+        if (dig) {
 #pragma unroll
-        for (int i = 0; i < NT / 64; ++i) {
-            const uint32_t c = wcnt[i][d];
-            wcnt[i][d] = run;
-            run += c;
+            for (int i = 0; i < DT / 64; ++i) {
+                const uint32_t c = wcnt[i][d];
+                wcnt[i][d] = (uint16_t)run;
+                run += c;
+            }
         }
         uint32_t tot;
-        dstart[d] = block_exclusive_scan(run, scan_sh, &tot);
+        const uint32_t ds = block_exclusive_scan_n<uint32_t, DT>(run, scan_sh, &tot);
+        if (dig) dstart[d] = ds;
         digit_total = run;
     }
     __syncthreads();
@@ -435,7 +473,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
         sv[pos] = val[j];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nvalid; i += NT) {
+    for (int i = threadIdx.x; i < nvalid; i += DT) {
         const KeyT k = sk[i];
         const uint32_t d = digit_of(k, shift);
         const uint32_t o = gstart[d] + (uint32_t)i - dstart[d];
@@ -445,7 +483,7 @@ __global__ void __launch_bounds__(NT) radix_downsweep_kernel(
     __syncthreads();
     // padded items all carry digit 255 and sit past nvalid; they are not counted
     const uint32_t pad = (threadIdx.x == RADIX - 1) ? (uint32_t)(STILE - nvalid) : 0u;
-    gstart[threadIdx.x] += digit_total - pad;
+    if (dig) gstart[threadIdx.x] += digit_total - pad;
     __syncthreads();
     }
 }
@@ -631,7 +669,8 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
                            hist, nb, chunk, seg_arg, nbs);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)rows), dim3(NT), 0, stream, (const uint32_t*)hist,
                            nbs, row_pre, row_tot);
-        hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, vin, kout, vout,
+        hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(sort_dt<KeyT>()), 0, stream, kin, vin,
+                           kout, vout,
                            K, K_dev, shift, (const uint32_t*)row_pre, (const uint32_t*)row_tot, nb, chunk, seg_arg,
                            nbs);
         KeyT* tk = kin; kin = kout; kout = tk;
