@@ -445,6 +445,11 @@ radix_downsweep_kernel(
         const int leader = __ffsll((long long)peers) - 1;
         if (lane == leader) wcnt[w][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
     }
+    // the keys pass through an empty asm statement, so that the scatter below
+    // derives each item's digit again instead of keeping its counter address
+    // live (in registers) across the digit scan
+#pragma unroll
+    for (int j = 0; j < SIPT; ++j) asm volatile("" : "+v"(key[j]));
     __syncthreads();
     // per digit: offsets of each wave, block total, then block-wide digit starts
     uint32_t digit_total = 0;
