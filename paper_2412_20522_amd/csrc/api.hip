@@ -285,7 +285,7 @@ struct mgs_frame {
     int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, cur_cap = 0, stg_cap = 0;
     // device buffers: per record, then per list entry (32-bit cell keys), per
     // tile and region, per pixel
-    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, wide_flag, tmask,
+    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, tmask,
         cls_part;
     // order, order_b: the tile orders of the forward and the backward
     // compositing (most expensive first), tcost: the forward's cost keys,
@@ -413,7 +413,7 @@ mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
-                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->wide_flag, &f->tmask, &f->cls_part,
+                      &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->tmask, &f->cls_part,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
                       &f->caps,     &f->tcost,     &f->order,     &f->order_b,   &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
                       &f->t_final,  &f->last,
@@ -554,7 +554,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) ||
-        (s = grow(ctx, f->wide_flag, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
+        (s = grow(ctx, f->tmask, (size_t)R * 8 + 8)) ||
         (s = grow(ctx, f->cls_part, classify_parts_bytes(R))) ||
         (s = grow(ctx, f->ranges, (size_t)(T + NR) * 8)) || (s = grow(ctx, f->caps, (size_t)T * 4 + 4)) ||
         (s = grow(ctx, f->tcost, (size_t)T * 4 + 4)) || (s = grow(ctx, f->order, (size_t)T * 4 + 4)) ||
@@ -586,7 +586,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
                                 (const uint32_t*)(f->order_in_alt ? f->rkeys_alt.p : f->rkeys.p),
                                 (const float*)f->rec.p, R, f->n, f->views, f->st,
                                 (uint32_t*)f->cnt_sorted.p,
-                                (uint32_t*)f->wide_flag.p, (uint64_t*)f->tmask.p, (float*)f->srec.p,
+                                (uint64_t*)f->tmask.p, (float*)f->srec.p,
                                 (uint32_t*)f->cls_part.p);
     }
     {
@@ -638,7 +638,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     {
         StageTimer t(ctx, stream, MGS_STAGE_DUPLICATE);
         launch_duplicate_lists(stream, (const float*)f->srec.p, (const uint32_t*)f->cnt_sorted.p,
-                               (const uint32_t*)f->wide_flag.p, (const uint64_t*)f->tmask.p,
+                               (const uint64_t*)f->tmask.p,
                                (uint32_t*)f->cls_part.p, R, f->n, f->views, f->st, (uint32_t*)f->keys.p,
                                (uint32_t*)f->vals.p, f->K, f->flags());
     }

@@ -249,6 +249,9 @@ constexpr uint32_t CULL_MAX = 64;
 // Key of an emitted slot the duplication could not fill: past every cell,
 // so it sorts last and no range includes it.
 constexpr uint32_t KEY_NONE = 0xffffffffu;
+// Bit of a position's entry count that marks a wide record (listed per
+// region); the count itself is below 2^24.
+constexpr uint32_t CNT_WIDE = 0x80000000u;
 
 __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
     return make_float4(__shfl(v.x, src), __shfl(v.y, src), __shfl(v.z, src), __shfl(v.w, src));
@@ -266,7 +269,7 @@ __device__ __forceinline__ float4 shfl4(const float4& v, int src) {
 __global__ void __launch_bounds__(256) permute_classify_kernel(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ skeys, const float4* __restrict__ rec,
     int64_t R, int64_t n, ViewSet views, DevSettings st, uint32_t* __restrict__ cnt_out,
-    uint32_t* __restrict__ wide_flag, uint64_t* __restrict__ tmask, float4* __restrict__ srec,
+    uint64_t* __restrict__ tmask, float4* __restrict__ srec,
     uint32_t* __restrict__ part) {
     __shared__ uint32_t s_part[2][4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -279,9 +282,7 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
     // both loads of the position in one round trip, then the record
     const uint32_t key = live ? skeys[i] : 0xffffffffu;
     const uint32_t r = live ? order[i] : 0u;
-    if (live && key == 0xffffffffu) {
-        wide_flag[i] = 0u;
-    } else if (live) {
+    if (live && key != 0xffffffffu) {
         // one gather of the record (radius in B.w, tile count in C.w)
         A = rec[3 * (size_t)r];
         B = rec[3 * (size_t)r + 1];
@@ -293,7 +294,6 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
         srec[3 * i] = A;
         srec[3 * i + 1] = B;
         reinterpret_cast<uint4*>(srec)[3 * i + 2] = C;
-        wide_flag[i] = wide ? 1u : 0u;
     }
     Cells cl{0, 0, 1, 0u, st.tile_w, st.tile_h};
     if (live && c > 0) cl = cells_of(A, B, wide, views.v[vi], st);
@@ -316,8 +316,10 @@ __global__ void __launch_bounds__(256) permute_classify_kernel(
         }
     }
     if (live) {
-        cnt_out[i] = cnt;
-        tmask[i] = mask;
+        // the wide flag rides in bit 31 (counts stay below 2^24); the cull
+        // mask is kept only for positions with entries
+        cnt_out[i] = cnt | (wide ? CNT_WIDE : 0u);
+        if (cnt != 0) tmask[i] = mask;
     }
     // wide records and their list entries of the workgroup (no atomics: one
     // address updated by every wave serialises)
@@ -497,7 +499,7 @@ __device__ __forceinline__ int wave_max_scan(int x) {
 // never leave a record's counted slots; a slot the emission does not fill
 // gets KEY_NONE.  No step waits on another wave.
 __global__ void __launch_bounds__(256) duplicate_kernel(
-    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted, const uint32_t* __restrict__ wide_flag,
+    const float4* __restrict__ srec, const uint32_t* __restrict__ cnt_sorted,
     const uint64_t* __restrict__ tmask, ListOffsets lo, int64_t R, int64_t n, ViewSet views, DevSettings st,
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity, uint32_t* __restrict__ flags) {
     __shared__ uint32_t s_first[256];
@@ -519,12 +521,14 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     const bool cull = st.tile_cull != 0;
     if (i < R) {
         // every load of the position at once (one memory round trip); the
-        // copy and the mask of a position without entries are not used
-        cnt = cnt_sorted[i];
-        wide = wide_flag[i] != 0;
+        // copy and the mask of a position without entries (never written)
+        // are not used
+        const uint32_t cw = cnt_sorted[i];
         A = srec[3 * i];
         B = srec[3 * i + 1];
         if (cull) mask = tmask[i];
+        cnt = cw & ~CNT_WIDE;
+        wide = (cw & CNT_WIDE) != 0;
     }
     // the record's view, loaded once: cell (x0 + rx, y0 + ry) has key
     // key0 + ry stride + rx
@@ -1545,11 +1549,11 @@ bool composite_config_supported(const CompositeConfig& c) {
 
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
                              int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
-                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part) {
+                             uint64_t* tmask, float* srec, uint32_t* part) {
     if (R == 0) return;
     const unsigned nb = blocks_of(R);
     hipLaunchKernelGGL(permute_classify_kernel, dim3(nb), dim3(256), 0, stream, order, skeys,
-                       reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, wide_flag, tmask,
+                       reinterpret_cast<const float4*>(rec), R, n, views, st, cnt, tmask,
                        reinterpret_cast<float4*>(srec), part);
 }
 
@@ -1581,12 +1585,12 @@ void launch_list_offsets(hipStream_t stream, uint32_t* part, int64_t R, uint64_t
 }
 
 void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
-                            const uint32_t* wide_flag, const uint64_t* tmask, uint32_t* part, int64_t R,
+                            const uint64_t* tmask, uint32_t* part, int64_t R,
                             int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
                             int64_t capacity, uint32_t* flags) {
     if (R == 0) return;
     hipLaunchKernelGGL(duplicate_kernel, dim3(blocks_of(R)), dim3(256), 0, stream,
-                       reinterpret_cast<const float4*>(srec), cnt_sorted, wide_flag, tmask, list_offsets(part, R), R,
+                       reinterpret_cast<const float4*>(srec), cnt_sorted, tmask, list_offsets(part, R), R,
                        n, views, st, keys, vals, capacity, flags);
 }
 

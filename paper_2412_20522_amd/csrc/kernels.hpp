@@ -97,13 +97,13 @@ bool composite_config_supported(const CompositeConfig& c);
 size_t classify_parts_bytes(int64_t R);
 void launch_permute_classify(hipStream_t stream, const uint32_t* order, const uint32_t* skeys, const float* rec,
                              int64_t R, int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* cnt,
-                             uint32_t* wide_flag, uint64_t* tmask, float* srec, uint32_t* part);
+                             uint64_t* tmask, float* srec, uint32_t* part);
 // From the classification's per-workgroup counts: each workgroup's first list
 // entry, the entry total (device u64 *total) and wide_counts (device u64):
 // [0] = wide records, [2] = their region entries
 void launch_list_offsets(hipStream_t stream, uint32_t* part, int64_t R, uint64_t* total, uint64_t* wide_counts);
 void launch_duplicate_lists(hipStream_t stream, const float* srec, const uint32_t* cnt_sorted,
-                            const uint32_t* wide_flag, const uint64_t* tmask, uint32_t* part, int64_t R,
+                            const uint64_t* tmask, uint32_t* part, int64_t R,
                             int64_t n, const ViewSet& views, const DevSettings& st, uint32_t* keys, uint32_t* vals,
                             int64_t capacity, uint32_t* flags);
 // Tile order of a persistent launch: the tiles by descending cost key
