@@ -91,8 +91,9 @@ def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
     if stage == "depth_sort":
         # 4 passes over 32-bit keys and values (read and written), then the
         # classification: order and key read, one record gathered (48 B),
-        # the sorted copy (48 B), count, wide flag and cull mask written
-        return 16 * R * 4 + R * (8 + 48 + 48 + 4 + 4 + 8), 0
+        # the sorted copy (48 B), the count (wide flag in its top bit) and
+        # the cull mask written
+        return 16 * R * 4 + R * (8 + 48 + 48 + 4 + 8), 0
     if stage == "project":
         # parameters read once; record (48 B), depth, radius, tile count,
         # depth key and order written per record
@@ -102,11 +103,13 @@ def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
         # parameter gradients written
         return n * 4 * (11 + k3) + R * 72 + n * 4 * (10 + k3), 0
     if stage == "duplicate":
-        # per position: count, offset, wide flag, cull mask and the record's
-        # geometry (32 B); per list entry a key and a value written
-        return R * (4 + 4 + 4 + 8 + 32) + K * 8, 0
+        # per position: count, cull mask and the record's geometry (32 B); per
+        # list entry a key and a value written
+        return R * (4 + 8 + 32) + K * 8, 0
     if stage == "scan":
-        return R * 8, 0
+        # the list offsets: one count read and one 8-byte offset written per
+        # wave of 64 positions
+        return (R + 63) // 64 * 12, 0
     if stage == "ranges":
         return K * 4 + 8 * fs["total_tiles"], 0
     if stage == "sample_masks":
