@@ -278,16 +278,20 @@ __device__ __forceinline__ SortSeg sort_seg(int64_t K, int64_t seg_len, int64_t 
 // Each block owns a contiguous chunk of `chunk` keys (a multiple of the sort tile),
 // so a couple of thousand blocks cover any K and the digit-major histogram
 // stays small.
-template <typename KeyT>
+// COPIES histograms per wave (lane mod COPIES picks one), so that lanes of
+// a wave with equal digits rarely hit one LDS counter: 4 for the list
+// entries' cell keys (digits clustered in the second pass), 1 for the
+// depth keys
+template <typename KeyT, int COPIES>
 __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restrict__ keys, int64_t Kcap,
                                                             const uint64_t* __restrict__ K_dev, int shift,
                                                             uint32_t* __restrict__ hist, int64_t nb, int64_t chunk,
                                                             int64_t seg_len, int64_t nbs) {
     constexpr int VEC = 16 / sizeof(KeyT);  // keys per 16-byte load
     constexpr int SIPT = sort_ipt<KeyT>(), STILE = sort_tile<KeyT>();
-    __shared__ uint32_t h[NT / 64][RADIX];
-    const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < (NT / 64) * RADIX; i += NT) (&h[0][0])[i] = 0u;
+    __shared__ uint32_t h[(NT / 64) * COPIES][RADIX];
+    const int w = (threadIdx.x >> 6) * COPIES + (lane_id() & (COPIES - 1));
+    for (int i = threadIdx.x; i < (NT / 64) * COPIES * RADIX; i += NT) (&h[0][0])[i] = 0u;
     __syncthreads();
     const int64_t K = live_count(Kcap, K_dev);
     chunk = sort_chunk<KeyT>(K, K_dev, nb, chunk);
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(NT) radix_upsweep_kernel(const KeyT* __restric
     const int d = threadIdx.x;  // NT == RADIX
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) s += h[i][d];
+    for (int i = 0; i < (NT / 64) * COPIES; ++i) s += h[i][d];
     hist[(sg.seg * RADIX + d) * nbs + sg.bl] = s;
 }
 
@@ -670,8 +674,12 @@ void radix_sort_t(hipStream_t stream, KeyT* keys, uint32_t* vals, KeyT* keys_alt
     KeyT* kout = keys_alt;
     uint32_t* vout = vals_alt;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(radix_upsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev, shift,
-                           hist, nb, chunk, seg_arg, nbs);
+        if (segmented)
+            hipLaunchKernelGGL((radix_upsweep_kernel<KeyT, 1>), dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev,
+                               shift, hist, nb, chunk, seg_arg, nbs);
+        else
+            hipLaunchKernelGGL((radix_upsweep_kernel<KeyT, 4>), dim3((unsigned)nb), dim3(NT), 0, stream, kin, K, K_dev,
+                               shift, hist, nb, chunk, seg_arg, nbs);
         hipLaunchKernelGGL(radix_rowscan_kernel, dim3((unsigned)rows), dim3(NT), 0, stream, (const uint32_t*)hist,
                            nbs, row_pre, row_tot);
         hipLaunchKernelGGL(radix_downsweep_kernel<KeyT>, dim3((unsigned)nb), dim3(sort_dt<KeyT>()), 0, stream, kin, vin,
