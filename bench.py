@@ -95,9 +95,9 @@ def stage_work(stage: str, counts: dict, fs: dict, n: int, sh_deg: int, P: int):
         # the cull mask written
         return 16 * R * 4 + R * (8 + 48 + 48 + 4 + 8), 0
     if stage == "project":
-        # parameters read once; record (48 B), depth, radius, tile count,
-        # depth key and order written per record
-        return n * 4 * (11 + k3 + 1) + R * (48 + 5 * 4), 0
+        # parameters read once; record (48 B), depth, tile count, depth key
+        # and order written per record
+        return n * 4 * (11 + k3 + 1) + R * (48 + 4 * 4), 0
     if stage == "project_bwd":
         # parameters read, the FP64 gradient row (9 doubles) read per record,
         # parameter gradients written

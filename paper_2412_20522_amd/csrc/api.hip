@@ -285,7 +285,7 @@ struct mgs_frame {
     int64_t res_R = 0, res_P = 0, res_T = 0, K_cap = 0, cur_cap = 0, stg_cap = 0;
     // device buffers: per record, then per list entry (32-bit cell keys), per
     // tile and region, per pixel
-    DevBuf rec, srec, depth, radius, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, tmask,
+    DevBuf rec, srec, depth, tiles, rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, tmask,
         cls_part;
     // order, order_b: the tile orders of the forward and the backward
     // compositing (most expensive first), tcost: the forward's cost keys,
@@ -412,7 +412,7 @@ mgs_status mgs_frame_create(mgs_ctx* ctx, mgs_frame** out) {
 mgs_status mgs_frame_destroy(mgs_frame* f) {
     if (!f) return MGS_OK;
     (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->radius,   &f->tiles,     &f->rkeys,    &f->rvals,
+    DevBuf* bufs[] = {&f->rec,      &f->srec,      &f->depth,     &f->tiles,     &f->rkeys,    &f->rvals,
                       &f->rkeys_alt, &f->rvals_alt, &f->cnt_sorted, &f->tmask, &f->cls_part,
                       &f->keys,     &f->vals,      &f->keys_alt, &f->vals_alt,  &f->ranges,
                       &f->caps,     &f->tcost,     &f->order,     &f->order_b,   &f->cur_off,   &f->nbatch,   &f->cur,       &f->cur_stg,   &f->stg,
@@ -550,7 +550,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
                     (long long)f->res_T);
     if ((s = grow(ctx, f->rec, (size_t)R * 48 + 16)) || (s = grow(ctx, f->srec, (size_t)R * 48 + 16)) ||
         (s = grow(ctx, f->depth, (size_t)R * 4 + 4)) ||
-        (s = grow(ctx, f->radius, (size_t)R * 4 + 4)) || (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
+        (s = grow(ctx, f->tiles, (size_t)R * 4 + 4)) ||
         (s = grow(ctx, f->rkeys, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->rkeys_alt, (size_t)R * 8 + 16)) || (s = grow(ctx, f->rvals_alt, (size_t)R * 4 + 16)) ||
         (s = grow(ctx, f->cnt_sorted, (size_t)R * 4 + 4)) ||
@@ -567,7 +567,8 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
     launch_fill_u32(stream, f->flags(), 10, 0u);  // flags and the counters up to byte 40
     {
         StageTimer t(ctx, stream, MGS_STAGE_PROJECT);
-        launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, (float*)f->radius.p,
+        // the radius stays in the records (B.w); the export reads it there
+        launch_project_fwd(stream, *g, f->views, f->st, (float*)f->rec.p, (float*)f->depth.p, nullptr,
                            (uint32_t*)f->tiles.p, f->flags(), (uint32_t*)f->rkeys.p, (uint32_t*)f->rvals.p);
     }
     {
@@ -898,7 +899,13 @@ mgs_status mgs_frame_export(mgs_frame* f, mgs_stream stream, int what, void* dst
     switch (what) {
         case MGS_EXPORT_RECORDS: src = f->rec.p; n = (size_t)f->R * 48; break;
         case MGS_EXPORT_DEPTH: src = f->depth.p; n = (size_t)f->R * 4; break;
-        case MGS_EXPORT_RADIUS: src = f->radius.p; n = (size_t)f->R * 4; break;
+        case MGS_EXPORT_RADIUS:
+            *bytes = (size_t)f->R * 4;
+            if (dst) {
+                launch_record_field((hipStream_t)stream, (const float*)f->rec.p, f->R, 7, (float*)dst);
+                MGS_CHECK_LAUNCH(ctx);
+            }
+            return MGS_OK;
         case MGS_EXPORT_TILES: src = f->tiles.p; n = (size_t)f->R * 4; break;
         case MGS_EXPORT_VALUES: src = f->vals_sorted(); n = (size_t)f->K * 4; break;
         case MGS_EXPORT_RANGES: src = f->ranges.p; n = (size_t)(f->total_tiles + f->views.total_regions) * 8; break;

@@ -9,13 +9,15 @@
 
 namespace mgs {
 
-// projection
+// projection (radius optional: the record's B.w holds it too)
 // rkeys, rvals (optional, both or neither): the keys of the per-view depth
 // order of the records (depth bits, all ones for records without tiles) and
 // the record ids
 void launch_project_fwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         float* rec, float* depth, float* radius, uint32_t* tiles, uint32_t* flags,
                         uint32_t* rkeys = nullptr, uint32_t* rvals = nullptr);
+// out[r] = field `field` (0..11) of record r (the radius is field 7, B.w)
+void launch_record_field(hipStream_t stream, const float* rec, int64_t R, int field, float* out);
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out);
 // Whole path: FP64 per-record gradients (zeroed by the forward compositing

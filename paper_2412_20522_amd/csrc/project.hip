@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
             rec[3 * r + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
             rec[3 * r + 2] = make_float4(0.f, 0.f, 0.f, 0.f);
             depth_out[r] = o.depth;
-            radius_out[r] = 0.f;
+            if (radius_out) radius_out[r] = 0.f;
             tiles_out[r] = 0;
             if (rkeys) {
                 rkeys[r] = 0xffffffffu;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
         rec[3 * r + 1] = make_float4((float)o.gamma, opac, mval, o.radius);
         rec[3 * r + 2] = make_float4(col[0], col[1], col[2], __uint_as_float(count));
         depth_out[r] = o.depth;
-        radius_out[r] = o.radius;
+        if (radius_out) radius_out[r] = o.radius;  // (also in the record, B.w)
         tiles_out[r] = count;
         // keys of the depth order of the records (per view): the depth bits,
         // all ones for a record listed nowhere (sorted last in its view)
@@ -310,6 +310,13 @@ __global__ void __launch_bounds__(256) project_fwd_kernel(
         }
     }
     if (bad) atomicOr(flags, FLAG_NONFINITE);
+}
+
+// out[r] = field f (0..11) of record r: the radius export reads B.w (f = 7)
+__global__ void __launch_bounds__(256) record_field_kernel(const float* __restrict__ rec, int64_t R, int f,
+                                                            float* __restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) out[r] = rec[12 * r + f];
 }
 
 // AccT: type of the per-record 2D gradients (float from the stage entry
@@ -624,6 +631,12 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
 #undef MGS_PBWD_A
 }
 }  // namespace
+
+void launch_record_field(hipStream_t stream, const float* rec, int64_t R, int field, float* out) {
+    if (R <= 0) return;
+    hipLaunchKernelGGL(record_field_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, stream, rec, R, field,
+                       out);
+}
 
 void launch_project_bwd(hipStream_t stream, const mgs_gaussians& g, const ViewSet& views, const DevSettings& st,
                         const float* d_rec, const mgs_gradients& out) {
