@@ -303,6 +303,10 @@ struct mgs_frame {
     // the tiles of the next forward over the same views
     ViewSet order_views{};
     bool order_valid = false;
+    // the last forward ordered its tiles by measured batch counts (those of
+    // the forward before it over the same views); the backward then reuses
+    // that order
+    bool fwd_order_measured = false;
     // misc: flags (u32) at 0, list entry count (u64) at 8, wide record count
     // (u64) at 16, checkpoint count (u64) at 24, region entry count (u64) at
     // 32, staged-entry counter (u32) at 192; the tile orders' histogram and
@@ -667,6 +671,7 @@ mgs_status forward_impl(mgs_frame* f, mgs_stream stream_, const mgs_gaussians* g
         // the forward takes the most expensive tiles first: by the batches the
         // last forward over the same views took, else by list length
         const bool measured = f->order_valid && std::memcmp(&f->order_views, &f->views, sizeof(ViewSet)) == 0;
+        f->fwd_order_measured = measured;
         launch_tile_setup(stream, (const uint32_t*)f->ranges.p, f->views, (int)B,
                           measured ? (const uint32_t*)f->nbatch.p : nullptr, (uint32_t*)f->tcost.p,
                           (uint32_t*)f->cur_off.p, f->cur_need(), (uint32_t*)f->caps.p, f->order_hist(),
@@ -739,10 +744,15 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
     }
     f->drec_zero = false;  // this backward accumulates into it
     if (f->persistent) queue = (uint32_t*)f->queue.p;
+    // the tile order: the forward's when it came from measured batch counts
+    // (a scheduling choice: the order decides no result), else by this
+    // forward's batch counts
+    const bool own_order = !f->fwd_order_measured;
     {
         // one launch clears the FP64 mask gradients, the persistent queue and
         // the tile order's histogram and cursors
-        const FillSpan zero[3] = {{(uint32_t*)f->dm_acc.p, 2 * f->n, 0u}, {queue, 1, 0u}, {f->order_hist(), 512, 0u}};
+        const FillSpan zero[3] = {{(uint32_t*)f->dm_acc.p, 2 * f->n, 0u}, {queue, 1, 0u},
+                                  {own_order ? f->order_hist() : nullptr, 512, 0u}};
         launch_fill_spans(stream, zero, 3);
     }
     HybridBuffers hb = f->hybrid();
@@ -751,8 +761,13 @@ mgs_status mgs_backward(mgs_frame* f, mgs_stream stream_, const float* dl_dimage
         // the backward takes first the tiles where the forward took most
         // batches (the backward replays them)
         const uint32_t T = f->views.total_tiles;
-        launch_tile_order(stream, (const uint32_t*)f->nbatch.p, T, f->order_hist(), (uint32_t*)f->order_b.p, true);
-        hb.order = (const uint32_t*)f->order_b.p;
+        if (own_order) {
+            launch_tile_order(stream, (const uint32_t*)f->nbatch.p, T, f->order_hist(), (uint32_t*)f->order_b.p,
+                              true);
+            hb.order = (const uint32_t*)f->order_b.p;
+        } else {
+            hb.order = (const uint32_t*)f->order.p;
+        }
         launch_hybrid_bwd(stream, f->cfg_bwd, (const float*)f->srec.p, hb, f->views, f->st,
                           (const float*)f->t_final.p, (const int32_t*)f->last.p, dl_dimages, f->n,
                           (double*)f->d_rec.p, (double*)f->dm_acc.p, queue, ctx->num_cus);
