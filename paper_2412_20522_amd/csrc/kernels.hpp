@@ -76,8 +76,6 @@ struct FillSpan {
 };
 void launch_fill_spans(hipStream_t stream, const FillSpan* spans, int count);
 void launch_fill_f32(hipStream_t stream, float* p, int64_t n, float value);
-// Sum of n int32 values into a device u64 (deterministic).
-void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);
 // Column sums of an [n, 4] int32 array into out_dev[4] (u64); scratch holds
 // 4 * scan_scratch_bytes(n) bytes.
 void launch_sum_i32x4(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch);

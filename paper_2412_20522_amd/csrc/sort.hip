@@ -595,25 +595,6 @@ __global__ void __launch_bounds__(256) round_f64_kernel(const double* __restrict
     if (i < n) out[i] = (float)in[i];
 }
 
-__global__ void __launch_bounds__(NT) sum_i32_partial_kernel(const int32_t* __restrict__ in, int64_t n,
-                                                              uint64_t* __restrict__ partial) {
-    __shared__ uint64_t sh[NT / 64];
-    const int64_t base = (int64_t)blockIdx.x * TILE;
-    uint64_t s = 0;
-    for (int j = 0; j < IPT; ++j) {
-        const int64_t i = base + j * NT + threadIdx.x;
-        if (i < n) s += (uint64_t)(int64_t)in[i];
-    }
-    s = wave_inclusive_scan(s);
-    if (lane_id() == 63) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int i = 0; i < NT / 64; ++i) t += sh[i];
-        partial[blockIdx.x] = t;
-    }
-}
-
 __global__ void __launch_bounds__(NT) sum_i32x4_partial_kernel(const int4* __restrict__ in, int64_t n,
                                                                 uint64_t* __restrict__ partial, int64_t nb) {
     __shared__ uint64_t sh[4][NT / 64];
@@ -823,13 +804,6 @@ void launch_sum_i32x4(hipStream_t stream, const int32_t* in, int64_t n, uint64_t
                        reinterpret_cast<const int4*>(in), n, partial, nb);
     for (int c = 0; c < 4; ++c)
         hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial + c * nb, nb, out_dev + c);
-}
-
-void launch_sum_i32(hipStream_t stream, const int32_t* in, int64_t n, uint64_t* out_dev, void* scratch) {
-    const int64_t nb = nblocks(n > 0 ? n : 1);
-    uint64_t* partial = reinterpret_cast<uint64_t*>(scratch);
-    hipLaunchKernelGGL(sum_i32_partial_kernel, dim3((unsigned)nb), dim3(NT), 0, stream, in, n, partial);
-    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(NT), 0, stream, partial, nb, out_dev);
 }
 
 }  // namespace mgs
