@@ -40,6 +40,13 @@ def _scene(kind):
         s["cameras"][1] = scenegen.orbit_camera(4.0, 35.0, 8.0, 50, 72)
         s["cameras"][2] = scenegen.orbit_camera(3.5, -60.0, -12.0, 33, 29)
         return s
+    if kind == "many":
+        # 100,011 records: more than one group of 1024 waves in the list
+        # offsets, and a ragged last workgroup of positions
+        s = scenegen.small_scene(33_337, 160, 120, seed=104, sh_degree=1, log_scale_mean=-3.0, n_views=3)
+        s["cameras"][1] = scenegen.orbit_camera(4.5, 25.0, 10.0, 144, 96)
+        s["cameras"][2] = scenegen.orbit_camera(3.8, -40.0, -8.0, 101, 77)
+        return s
     raise KeyError(kind)
 
 
@@ -212,7 +219,7 @@ def merged_tile_lists(cams, tw, th, vals, ranges, order, depth_bits, mean2d, rad
     return out, region_recs
 
 
-@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview", "many"])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
 @pytest.mark.parametrize("wide_tiles", [-1, 0, 1])
 def test_whole_path_lists_match_oracle_bitwise(ctx, kind, tile, wide_tiles):
@@ -438,7 +445,7 @@ def test_product_compositing_matches_oracle(ctx, kind, shape, cull):
     assert np.count_nonzero(r["d_masks"][masked]) > 0
 
 
-@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview"])
+@pytest.mark.parametrize("kind", ["tiny", "ragged_sh3", "multiview", "many"])
 def test_culled_lists_keep_every_entry_that_can_blend(ctx, kind):
     """With tile culling the whole path lists a record in a tile (or its
     region) only where it can pass the per-pixel filters.  Checked on the
