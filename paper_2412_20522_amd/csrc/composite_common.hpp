@@ -64,13 +64,13 @@ __device__ __forceinline__ bool eval_entry(const float4& A, const float4& B, flo
     e.apt = A.z * e.t;
     e.gdy = B.x * e.dy;
     const float qs = fmaf(e.apt, e.t, e.gdy * e.dy);  // QSCALE Q <= 0
-    if (!(qs >= k.qs_max)) return false;
+    // computed for every pair, so that alpha needs no select on the cut
     e.G = __builtin_amdgcn_exp2f(qs);
     e.oG = B.y * e.G;
     // min(alpha_max, oG) for oG >= 0 in one instruction (a min would first
     // canonicalise its operands)
     e.alpha = __builtin_amdgcn_fmed3f(e.oG, 0.f, k.amax);
-    return e.alpha >= k.amin;
+    return (qs >= k.qs_max) & (e.alpha >= k.amin);
 }
 
 // Persistent launches pop tile ids from a device counter; plain launches

@@ -816,9 +816,9 @@ struct Lds {
     uint32_t* yraw;   // region window (sorted positions), before the tile test
     uint32_t* yk;     // entries of the region window that belong to this tile
     uint8_t* ypass;   // tile test of the region window
-    float4* A;        // staged records of the batch
-    float4* Bv;
-    float4* C;
+    // staged records of the batch, three float4 per entry (A, B, C): one
+    // LDS address per entry, the three reads at fixed offsets
+    float4* E;
     uint32_t* m;      // merged positions of the batch
     uint32_t* wsum;   // per-wave partial counts
 };
@@ -827,9 +827,7 @@ __host__ __device__ constexpr size_t lds_bytes(int batch) { return (size_t)batch
 
 __device__ __forceinline__ Lds carve(char* smem, int batch) {
     Lds L;
-    L.A = reinterpret_cast<float4*>(smem);
-    L.Bv = L.A + batch;
-    L.C = L.Bv + batch;
+    L.E = reinterpret_cast<float4*>(smem);
     L.xk = reinterpret_cast<uint32_t*>(smem);
     L.yraw = L.xk + batch;
     L.yk = L.yraw + batch;
@@ -896,7 +894,7 @@ struct Batch {
 // touch test then only decides which merged entries are staged.
 __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, const float4* __restrict__ srec,
                              int i1, int e1, int i2, int e2, int batch, int tcx, int tcy, const TileBox& tb,
-                             const DevView& cam, const DevSettings& st) {
+                             const DevView& cam, const DevSettings& st, int kbase) {
     const int t = threadIdx.x, NT = blockDim.x;
     const int cX = min(batch, e1 - i1), cY = min(batch, e2 - i2);
     for (int l = t; l < cX; l += NT) L.xk[l] = vals[i1 + l];
@@ -959,16 +957,17 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     // the windows are dead: stage over them, in merged order, the records
     // that can reach a pixel of the tile (a and gamma scaled for
     // eval_entry); B.w (the radius, unused here) carries the entry's index
-    // within the merged batch
+    // in the tile's full list: kbase (the merged entries of the earlier
+    // batches) plus its index within the merged batch
     const int M = nX + nY;
     if (st.tile_cull) {
         for (int j = t; j < M; j += NT) {
             const size_t i = L.m[j];
             float4 B = stage_b(srec[3 * i + 1]);
-            B.w = __int_as_float(j);
-            L.A[j] = stage_a(srec[3 * i]);
-            L.Bv[j] = B;
-            L.C[j] = srec[3 * i + 2];
+            B.w = __int_as_float(kbase + j);
+            L.E[3 * j] = stage_a(srec[3 * i]);
+            L.E[3 * j + 1] = B;
+            L.E[3 * j + 2] = srec[3 * i + 2];
         }
         __syncthreads();
         return Batch{M, M, nX, nYr};
@@ -992,10 +991,10 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
         const int j = t * run + q;
         const size_t i = L.m[j];
         float4 B = stage_b(srec[3 * i + 1]);
-        B.w = __int_as_float(j);
-        L.A[p] = stage_a(srec[3 * i]);
-        L.Bv[p] = B;
-        L.C[p] = srec[3 * i + 2];
+        B.w = __int_as_float(kbase + j);
+        L.E[3 * p] = stage_a(srec[3 * i]);
+        L.E[3 * p + 1] = B;
+        L.E[3 * p + 2] = srec[3 * i + 2];
         ++p;
     }
     __syncthreads();
@@ -1126,9 +1125,11 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         const TileGeom tg = tile_geom(views, tile, TW, TH);
         const DevView& cam = views.v[tg.vi];
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
+        // stopk: the entry at which the pixel stopped, -1 while it runs
+        // (and 0 for a pixel outside the view, which never runs): the
+        // pixel's done flag, tested with one compare per slot and entry and
+        // written only when the pixel stops
         int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT], nev[PPT], nev_last[PPT];
-        // done as a full int (0 / 1): tested with one compare per slot and entry
-        int done[PPT];
         bool inside[PPT];
 #pragma unroll
         for (int i = 0; i < PPT; ++i) {
@@ -1140,9 +1141,8 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
             T[i] = 1.f;
             C0[i] = C1[i] = C2[i] = 0.f;
             last[i] = -1;
-            stopk[i] = -1;
+            stopk[i] = inside[i] ? -1 : 0;
             nblend[i] = nmasked[i] = nev[i] = nev_last[i] = 0;
-            done[i] = inside[i] ? 0 : 1;
         }
         const int tcx = tg.tx0 / TW, tcy = tg.ty0 / TH;
         const uint2 r1 = hl.ranges[tile];
@@ -1155,10 +1155,10 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         while (i1 < e1 || i2 < e2) {
             bool active = false;
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
+            for (int i = 0; i < PPT; ++i) active |= stopk[i] < 0;
             if (!__syncthreads_or(active)) break;
             if (t == 0) cur[b] = make_uint4((uint32_t)i1, (uint32_t)i2, (uint32_t)m, 0u);
-            const Batch bt = merge_batch(L, hl.vals, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, cam, st);
+            const Batch bt = merge_batch(L, hl.vals, srec, i1, e1, i2, e2, batch, tcx, tcy, tb, cam, st, m);
             // room for the staged entries in the list kept for the backward:
             // thread 0 sub-allocates from a chunk the workgroup took from the
             // global counter (one atomic per chunk, not per batch)
@@ -1171,32 +1171,34 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                 my_off = cbase + cused;
                 cused += (uint32_t)bt.M;
             }
-            for (int j = 0; j < bt.M; ++j) {
+            // uniform: a scalar loop bound
+            const int Mb = __builtin_amdgcn_readfirstlane(bt.M);
+            for (int j = 0; j < Mb; ++j) {
                 // the wave leaves the batch once all its pixels are done,
                 // tested every 16 entries (a done pixel's slot costs only
                 // its skip; a test per entry costs more than it saves)
                 if ((j & 15) == 0) {
                     active = false;
 #pragma unroll
-                    for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
+                    for (int i = 0; i < PPT; ++i) active |= stopk[i] < 0;
                     if (!__any(active)) break;
                 }
-                const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
-                const int k = m + __float_as_int(B.w);  // index in the tile's full list
+                const float4 A = L.E[3 * j], B = L.E[3 * j + 1], Cc = L.E[3 * j + 2];
+                const int k = __float_as_int(B.w);  // index in the tile's full list
                 float isum = 0.f, imax = 0.f;
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
-                    if (done[i] != 0) continue;
+                    if (stopk[i] >= 0) continue;
                     if (STATS) ++nev[i];
                     Eval e;
                     if (!eval_entry(A, B, px[i], py[i], ek, e)) continue;
                     const float ma = B.z * e.alpha;
                     const float test = T[i] * (1.f - ma);
-                    if (test < st.t_min) {
-                        done[i] = 1;
-                        stopk[i] = k;
-                        continue;
-                    }
+                    // one select, not a branch with copies on both sides
+                    const bool stop = test < st.t_min;
+                    stopk[i] = stop ? k : stopk[i];
+                    asm volatile("" : "+v"(stopk[i]));  // keeps the select here
+                    if (stop) continue;
                     const float wgt = ma * T[i];
                     C0[i] += wgt * Cc.x;
                     C1[i] += wgt * Cc.y;
@@ -1224,7 +1226,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
             }
             active = false;
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) active |= done[i] == 0;
+            for (int i = 0; i < PPT; ++i) active |= stopk[i] < 0;
             if (hl.stg) {
                 if (t == 0) {
                     const uint32_t off = (uint64_t)my_off + (uint64_t)bt.M <= hl.stg_cap ? my_off : 0xffffffffu;
@@ -1235,7 +1237,7 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
                 const uint32_t off = L.wsum[8];
                 if (off != 0xffffffffu) {
                     for (int p = t; p < bt.M; p += NT) {
-                        const uint32_t jj = __float_as_uint(L.Bv[p].w);
+                        const uint32_t jj = __float_as_uint(L.E[3 * p + 1].w) - (uint32_t)m;
                         hl.stg[off + p] = make_uint2(L.m[jj], jj);
                     }
                 }
@@ -1375,19 +1377,19 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
                     const uint2 e = hl.stg[cs.x + p];
                     const size_t i = e.x;
                     float4 B = stage_b(srec[3 * i + 1]);
-                    B.w = __uint_as_float(e.y);
-                    L.A[p] = stage_a(srec[3 * i]);
-                    L.Bv[p] = B;
-                    L.C[p] = srec[3 * i + 2];
+                    B.w = __int_as_float(m + (int)e.y);
+                    L.E[3 * p] = stage_a(srec[3 * i]);
+                    L.E[3 * p + 1] = B;
+                    L.E[3 * p + 2] = srec[3 * i + 2];
                 }
                 __syncthreads();
             } else {
                 Mb = merge_batch(L, hl.vals, srec, (int)c.x, (int)r1.y, (int)c.y, (int)r2.y, batch, tcx, tcy, tb,
-                                 cam, st).M;
+                                 cam, st, m).M;
             }
             for (int j = Mb - 1; j >= 0; --j) {
-                const float4 A = L.A[j], B = L.Bv[j], Cc = L.C[j];
-                const int k = m + __float_as_int(B.w);  // index in the tile's full list
+                const float4 A = L.E[3 * j], B = L.E[3 * j + 1], Cc = L.E[3 * j + 2];
+                const int k = __float_as_int(B.w);  // index in the tile's full list
                 if (k > top) continue;                  // uniform: past every pixel's last entry
                 const float M = B.z;
                 const float okq = B.y * QSCALE_NINV;
