@@ -1001,13 +1001,14 @@ __device__ Batch merge_batch(const Lds& L, const uint32_t* __restrict__ vals, co
     return Batch{(int)Mc, M, nX, nYr};
 }
 
-// Wave totals of ten per-lane quantities, transposed: on return lane q
-// (q < 10) holds the total of quantity q.  A butterfly within each 16-lane
-// row halves the values a lane carries at every step: the partner lane
-// (lane ^ 1, lane ^ 2 by DPP quad permutes, then the row rotations by 4 and
-// 8) receives one of each pair and keeps the other, so after four steps a
-// lane holds the row total of one quantity (lane & 7) and of quantity
-// 8 + (lane & 1); the four rows are then added by two lane swaps.
+// Wave totals of ten per-lane quantities, each left in the lanes that
+// issue its atomic.  The gfx950 lane swaps halve the data without selects:
+// permlane32_swap trades the upper half of its first operand for the lower
+// half of its second, so the sum of its two results holds the first
+// quantity's total over lanes l, l + 32 in the lower half and the second's in
+// the upper half; permlane16_swap trades rows 1 and 3 of its first operand
+// for rows 0 and 2 of its second, which halves again across the row pairs.
+// Four DPP steps within each 16-lane row then complete the totals.
 __device__ __forceinline__ float dpp_xor1(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
 }
@@ -1020,35 +1021,41 @@ __device__ __forceinline__ float dpp_ror4(float x) {
 __device__ __forceinline__ float dpp_ror8(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
 }
-// x(lane) + x(lane ^ 16) + x(lane ^ 32) + x(lane ^ 48)
-__device__ __forceinline__ float rows_sum(float x) {
-    const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    x = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
-    const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+__device__ __forceinline__ float halves_pair(float a, float b) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+__device__ __forceinline__ float rows_pair(float a, float b) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// total over the 16 lanes of each row, in every lane of the row
+__device__ __forceinline__ float row_total(float x) {
+    x += dpp_ror8(x);
+    x += dpp_ror4(x);
+    x += dpp_xor2(x);
+    return x + dpp_xor1(x);
 }
 
-__device__ __forceinline__ float wave_sum_transposed10(const float (&v)[10], int lane) {
-    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
-    float w[5];
-#pragma unroll
-    for (int p = 0; p < 5; ++p) {
-        // w[p]: quantity 2 p + b0 over lanes {l, l ^ 1}
-        const float keep = b0 ? v[2 * p + 1] : v[2 * p], send = b0 ? v[2 * p] : v[2 * p + 1];
-        w[p] = keep + dpp_xor1(send);
-    }
-    // x0: quantity 2 b1 + b0, x1: 4 + 2 b1 + b0, x2: 8 + b0, over the quad
-    const float x0 = (b1 ? w[1] : w[0]) + dpp_xor2(b1 ? w[0] : w[1]);
-    const float x1 = (b1 ? w[3] : w[2]) + dpp_xor2(b1 ? w[2] : w[3]);
-    const float x2 = w[4] + dpp_xor2(w[4]);
-    // the rotation by 4 pairs every lane with one of opposite b2 and equal
-    // low bits: y0 holds quantity lane & 7 over two quads, y1 quantity 8 + b0
-    const float y0 = (b2 ? x1 : x0) + dpp_ror4(b2 ? x0 : x1);
-    const float y1 = x2 + dpp_ror4(x2);
-    // rotation by 8 = lane ^ 8: row totals
-    const float z0 = rows_sum(y0 + dpp_ror8(y0));
-    const float z1 = rows_sum(y1 + dpp_ror8(y1));
-    return lane < 8 ? z0 : z1;
+// Quantity whose wave total lane holds after wave_sum_swap10 (-1: none).
+// Column 0 of the rows holds quantities 0, 2, 1, 3 (rows 0 to 3), column 1
+// quantities 4, 6, 5, 7, column 2 of rows 0 and 2 quantities 8 and 9.
+__device__ __forceinline__ int swap10_quantity(int lane) {
+    const int row = lane >> 4, c = lane & 15;
+    if (c == 0) return (row & 1) * 2 + (row >> 1);
+    if (c == 1) return 4 + (row & 1) * 2 + (row >> 1);
+    if (c == 2 && (row & 1) == 0) return 8 + (row >> 1);
+    return -1;
+}
+
+__device__ __forceinline__ float wave_sum_swap10(const float (&v)[10], int lane) {
+    const float s0 = halves_pair(v[0], v[1]), s1 = halves_pair(v[2], v[3]), s2 = halves_pair(v[4], v[5]);
+    const float s3 = halves_pair(v[6], v[7]), s4 = halves_pair(v[8], v[9]);
+    const float t0 = row_total(rows_pair(s0, s1));  // rows: quantities 0, 2, 1, 3
+    const float t1 = row_total(rows_pair(s2, s3));  // rows: 4, 6, 5, 7
+    const float t2 = row_total(rows_pair(s4, s4));  // rows: 8, 8, 9, 9
+    const int c = lane & 15;
+    return c == 0 ? t0 : (c == 1 ? t1 : t2);
 }
 
 // Pixel of slot i of thread t: every wave's slot covers one 8x8 block of
@@ -1300,9 +1307,12 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
     const Lds L = carve(smem, batch);
     const float bg0 = st.bg[0], bg1 = st.bg[1], bg2 = st.bg[2];
     const EvalConsts ek = eval_consts(st);
-    // the wave totals of the sums over t^2 and dy^2 (quantities 2 and 4) are
-    // rescaled by QSCALE / 2 to give dL/da and dL/dgamma (see the pixel loop)
-    const float qscale = (lane == 2 || lane == 4) ? 0.5f * QSCALE : 1.f;
+    // the quantity whose wave total this lane adds into the accumulator
+    // (-1: none); the totals of the sums over t^2 and dy^2 (quantities 2
+    // and 4) are rescaled by QSCALE / 2 to give dL/da and dL/dgamma (see the
+    // pixel loop)
+    const int qi = swap10_quantity(lane);
+    const float qscale = (qi == 2 || qi == 4) ? 0.5f * QSCALE : 1.f;
     if (*hl.cur_need > hl.cur_cap) return;  // the forward reported it
     for (;;) {
         const uint32_t q = next_tile(queue, &s_tile, blockIdx.x);
@@ -1434,11 +1444,11 @@ __global__ void __launch_bounds__(TW * TH / PPT, 5) hybrid_bwd_kernel(
                     const uint32_t r = __float_as_uint(Cc.w);
                     const int64_t g = (int64_t)r - rec_base;
                     if (M != 0.f) {
-                        // lane q (< 10) of the wave receives the wave total of quantity q
-                        float v[10] = {gu, gv, ga, gb, gc, go, gr, gg, gbl, gm};
-                        const float x = wave_sum_transposed10(v, lane) * qscale;
-                        if (lane < DREC) atomicAdd(d_rec + (size_t)r * DREC + lane, (double)x);
-                        else if (lane == DREC) atomicAdd(d_masks + g, (double)x);
+                        // ten lanes receive the wave totals, quantity qi each
+                        const float v[10] = {gu, gv, ga, gb, gc, go, gr, gg, gbl, gm};
+                        const float x = wave_sum_swap10(v, lane) * qscale;
+                        if ((unsigned)qi < (unsigned)DREC) atomicAdd(d_rec + (size_t)r * DREC + qi, (double)x);
+                        else if (qi == DREC) atomicAdd(d_masks + g, (double)x);
                     } else {
                         const float sm = wave_sum(gm);
                         if (lane == 0) atomicAdd(d_masks + g, (double)sm);
