@@ -39,10 +39,12 @@ if ROOT not in sys.path:
 
 # VALU lane-slots per Gaussian-pixel evaluation, counted from the formulas
 # (each add, multiply, fused multiply-add, compare or select is one slot; exp
-# and reciprocal are quarter rate and count four).
-SLOTS_FILTER = 16      # dx, dy, Q, cut, exp, o*G, clamp, alpha filter
+# and reciprocal issue at half rate on gfx950 and count two: a loop of
+# independent exp2 + FMA pairs runs at 12.9 T pairs/s, 1 / (1 + 2) of the
+# 39.3 T slot peak).
+SLOTS_FILTER = 14      # dx, dy, Q, cut, exp, o*G, clamp, alpha filter
 SLOTS_BLEND = 9        # M*a, test, stop compare, weight, 3 colour FMAs, T
-SLOTS_BWD_VISIBLE = 44  # T recovery (rcp), X, dL/dM, dL/dc, dL/do, dL/dQ, dL/du,dv, conic, b update
+SLOTS_BWD_VISIBLE = 42  # T recovery (rcp), X, dL/dM, dL/dc, dL/do, dL/dQ, dL/du,dv, conic, b update
 SLOTS_BWD_MASKED = 11   # X with T unchanged, dL/dM
 PEAK_SLOTS = 256 * 64 * 2.4e9   # 256 CUs x 4 SIMD x 16 lanes per clock x 2.4 GHz
 PEAK_HBM = 8.0e12
