@@ -1134,8 +1134,8 @@ __global__ void __launch_bounds__(TW * TH / PPT, PPT >= 4 ? 5 : 7) hybrid_fwd_ke
         float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT];
         // stopk: the entry at which the pixel stopped, -1 while it runs
         // (and 0 for a pixel outside the view, which never runs): the
-        // pixel's done flag, tested with one compare per slot and entry and
-        // written only when the pixel stops
+        // pixel's done flag, tested with one compare per slot and entry; its
+        // value changes only when the pixel stops
         int last[PPT], stopk[PPT], nblend[PPT], nmasked[PPT], nev[PPT], nev_last[PPT];
         bool inside[PPT];
 #pragma unroll
