@@ -173,7 +173,11 @@ struct ViewGeom {
     float radius;
 };
 
-// Per-view geometry of one Gaussian.
+// Per-view geometry of one Gaussian.  FULL = false stops after the 2D
+// covariance and its determinant (the conic, the radius and their finiteness
+// test are left unset): for a record the forward already found valid, whose
+// tests this double computation would repeat bit for bit.
+template <bool FULL = true>
 __device__ __forceinline__ ViewGeom view_geom(const DevView& cam, const DevSettings& st, float px, float py, float pz,
                                               const double* Sig) {
     ViewGeom o;
@@ -217,6 +221,7 @@ __device__ __forceinline__ ViewGeom view_geom(const DevView& cam, const DevSetti
     const double det = o.a * o.c - o.b * o.b;
     if (!(det > 0.0)) { o.valid = false; return o; }
     o.detv = det;
+    if (!FULL) return o;
     o.ca = o.c / det;
     o.beta = -o.b / o.c;
     o.gamma = 1.0 / o.c;
@@ -327,7 +332,9 @@ __global__ void __launch_bounds__(256) record_field_kernel(const float* __restri
 // (only records listed in some tile can have received gradients, and every
 // such row is read here).  tiles (optional): the forward's per-record tile
 // counts; rows of records without tiles are neither read nor cleared.
-template <int DEG, typename AccT, bool ACC>
+// TILES: tiles is given (a listed record then passed the forward's validity
+// tests on the same double values, which are not repeated).
+template <int DEG, typename AccT, bool ACC, bool TILES>
 __global__ void __launch_bounds__(256) project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh, const float* __restrict__ masks,
@@ -372,9 +379,12 @@ __global__ void __launch_bounds__(256) project_bwd_kernel(
             // a record without tiles (every invalid one among them) was listed
             // nowhere: its row was never written and is zero (tiles: the
             // forward's per-record counts); its geometry is not formed
-            const bool listed = !tiles || tiles[r] != 0u;
+            const bool listed = !TILES || tiles[r] != 0u;
+            // with the tile counts, a listed record passed the forward's
+            // validity tests on the same double values: only the geometry
+            // the gradients use is formed again
             ViewGeom o;
-            if (listed) o = view_geom(cam, st, px, py, pz, Sig);
+            if (listed) o = view_geom<!TILES>(cam, st, px, py, pz, Sig);
             if (!listed || !o.valid) {
                 if (d_rec_out) {
 #pragma unroll
@@ -612,15 +622,21 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     const size_t lds = (size_t)views.n_views * 3 * 256 * sizeof(float);  // colour gradients of every view
     float* d_masks = dm_acc ? out.d_masks : nullptr;
     float* rec_out = dm_acc ? out.d_records : nullptr;  // whole path only
-#define MGS_PBWD_A(D, A)                                                                                          \
-    hipLaunchKernelGGL((project_bwd_kernel<D, AccT, A>), grid, dim3(256), lds, stream, g.means, g.log_scales,       \
+#define MGS_PBWD_T(D, A, T)                                                                                       \
+    hipLaunchKernelGGL((project_bwd_kernel<D, AccT, A, T>), grid, dim3(256), lds, stream, g.means, g.log_scales,    \
                        g.quats, g.opacity_logits, g.sh, g.masks, g.n, views, st, d_rec, dm_acc, clear, out.d_means, \
                        out.d_log_scales, out.d_quats, out.d_opacity_logits, out.d_sh, d_masks, rec_out, tiles)
+#define MGS_PBWD_A(D, A)             \
+    if (tiles)                       \
+        MGS_PBWD_T(D, A, true);      \
+    else                             \
+        MGS_PBWD_T(D, A, false)
 #define MGS_PBWD(D)              \
-    if (out.accumulate)          \
+    if (out.accumulate) {        \
         MGS_PBWD_A(D, true);     \
-    else                         \
-        MGS_PBWD_A(D, false)
+    } else {                     \
+        MGS_PBWD_A(D, false);    \
+    }
     switch (st.sh_degree) {
         case 0: MGS_PBWD(0); break;
         case 1: MGS_PBWD(1); break;
@@ -629,6 +645,7 @@ void project_bwd_t(hipStream_t stream, const mgs_gaussians& g, const ViewSet& vi
     }
 #undef MGS_PBWD
 #undef MGS_PBWD_A
+#undef MGS_PBWD_T
 }
 }  // namespace
 
