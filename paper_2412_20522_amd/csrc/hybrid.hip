@@ -520,15 +520,17 @@ __global__ void __launch_bounds__(256) duplicate_kernel(
     float4 A = make_float4(0.f, 0.f, 0.f, 0.f), B = A;
     const bool cull = st.tile_cull != 0;
     if (i < R) {
-        // every load of the position at once (one memory round trip); the
-        // copy and the mask of a position without entries (never written)
-        // are not used
         const uint32_t cw = cnt_sorted[i];
+        cnt = cw & ~CNT_WIDE;
+        wide = (cw & CNT_WIDE) != 0;
+    }
+    // the copy and the mask of a position without entries (never written)
+    // are not used: positions listed nowhere sort last in their view, so
+    // whole waves of them load nothing more
+    if (__any(cnt != 0) && i < R) {
         A = srec[3 * i];
         B = srec[3 * i + 1];
         if (cull) mask = tmask[i];
-        cnt = cw & ~CNT_WIDE;
-        wide = (cw & CNT_WIDE) != 0;
     }
     // the record's view, loaded once: cell (x0 + rx, y0 + ry) has key
     // key0 + ry stride + rx
